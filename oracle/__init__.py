@@ -1,0 +1,195 @@
+"""Python access to the FP64 CPU oracle in ``ref3dgs.c``.
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
+CPU-baseline leg are the only callers. The GPU library never imports this
+package and this package never imports the GPU library.
+
+``build()`` compiles the C file with gcc (OpenMP, no floating-point
+contraction) into ``oracle/libref3dgs.so``; ``lib()`` loads it, building it
+first if it is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ref3dgs.c")
+_SO = os.path.join(_HERE, "libref3dgs.so")
+_lib = None
+
+# per-Gaussian flags
+VISIBLE, AMBIG_RECT, AMBIG_DEPTH, AMBIG_VIS = 1, 2, 4, 8
+# per-pixel flags
+PIX_AMBIG_ALPHA, PIX_AMBIG_STOP, PIX_AMBIG_GAUSS, PIX_POWER_POS = 1, 2, 4, 8
+
+ALPHA_MIN = 1.0 / 255.0
+ALPHA_MAX = 0.99
+T_MIN = 1e-4
+
+
+def build():
+    cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fopenmp", "-ffp-contract=off",
+           "-fno-fast-math", "-shared", "-fPIC", "-Wall", "-o", _SO + ".tmp", _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(_SO + ".tmp", _SO)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+            build()
+        L = ctypes.CDLL(_SO)
+        P = ctypes.c_void_p
+        i64, i32, dbl, flt = ctypes.c_int64, ctypes.c_int, ctypes.c_double, ctypes.c_float
+        L.orc_num_threads.restype = i32
+        L.orc_sh_basis.argtypes = [P, i32, P]
+        L.orc_project.argtypes = [i64, P, P, P, P, P, i32, P, i32, P, P, P, P, P, P, P, P, P]
+        L.orc_render.argtypes = [i64, P, P, P, P, P, P, P, i32, i32, i32, P, i64, P,
+                                 P, P, P, P, P, P, P, P]
+        L.orc_count_entries.argtypes = [i64, P]
+        L.orc_count_entries.restype = i64
+        L.orc_depth_range.argtypes = [i64, P, P, i32, dbl, dbl, flt, flt, flt, P]
+        L.orc_bin_of.argtypes = [flt, flt, flt, i32]
+        L.orc_schedule.argtypes = [i64, P, P, i32, i32, i32, i32, dbl, dbl, flt, flt, flt,
+                                   P, P, P, P, P, P]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def num_threads():
+    return lib().orc_num_threads()
+
+
+def cam_array(cam):
+    """Camera dict (see scenes.py) -> double[20] layout of the C oracle."""
+    return np.concatenate([np.asarray(cam["R"], np.float64).reshape(9),
+                           np.asarray(cam["t"], np.float64).reshape(3),
+                           [cam["fx"], cam["fy"], cam["cx"], cam["cy"],
+                            cam["width"], cam["height"], cam["znear"], cam["zfar"]]]).astype(np.float64)
+
+
+def sh_basis(direction, degree=3):
+    out = np.zeros(16, np.float64)
+    lib().orc_sh_basis(_p(_c(direction, np.float64)), int(degree), _p(out))
+    return out[: (degree + 1) ** 2]
+
+
+def project(g, cam, tile_size=16):
+    """FP64 projection of Gaussians ``g`` (scenes.py layout) through ``cam``."""
+    n = g["means"].shape[0]
+    means = _c(g["means"], np.float32)
+    ls = _c(g["log_scales"], np.float32)
+    qs = _c(g["quats"], np.float32)
+    lg = _c(g["logits"], np.float32)
+    sh = _c(g["sh"], np.float32)
+    out = {
+        "mean2d": np.zeros((n, 2)), "cov2d": np.zeros((n, 3)), "conic": np.zeros((n, 3)),
+        "depth": np.zeros(n), "opacity": np.zeros(n), "rgb": np.zeros((n, 3)),
+        "rect": np.zeros((n, 4), np.int32), "depth_key": np.zeros(n, np.float32),
+        "flags": np.zeros(n, np.uint8),
+    }
+    rc = lib().orc_project(n, _p(means), _p(ls), _p(qs), _p(lg), _p(sh), int(g["sh_degree"]),
+                           _p(cam_array(cam)), int(tile_size), _p(out["mean2d"]), _p(out["cov2d"]),
+                           _p(out["conic"]), _p(out["depth"]), _p(out["opacity"]), _p(out["rgb"]),
+                           _p(out["rect"]), _p(out["depth_key"]), _p(out["flags"]))
+    assert rc == 0, rc
+    return out
+
+
+def render(proj, width, height, tile_size=16, bg=(0.0, 0.0, 0.0), pix=None, mode="tiled"):
+    """Composite projected Gaussians (dict with mean2d, conic, opacity, rgb,
+    depth_key, rect, flags) at every pixel or at the [k, 2] (x, y) ``pix``."""
+    n = proj["mean2d"].shape[0]
+    npix = width * height if pix is None else len(pix)
+    pixa = None if pix is None else _c(pix, np.int32)
+    out = {
+        "rgb": np.zeros((npix, 3)), "alpha": np.zeros(npix), "last_gid": np.zeros(npix, np.int64),
+        "last_pos": np.zeros(npix, np.int64), "ncontrib": np.zeros(npix, np.int32),
+        "nvisit": np.zeros(npix, np.int32), "nsupport": np.zeros(npix, np.int32),
+        "flags": np.zeros(npix, np.uint8),
+    }
+    rect = _c(proj["rect"], np.int32) if mode == "tiled" else None
+    flags = None if proj.get("flags") is None else _c(proj["flags"], np.uint8)
+    rc = lib().orc_render(n, _p(_c(proj["mean2d"], np.float64)), _p(_c(proj["conic"], np.float64)),
+                          _p(_c(proj["opacity"], np.float64)), _p(_c(proj["rgb"], np.float64)),
+                          _p(_c(proj["depth_key"], np.float32)), _p(rect), _p(flags), int(width),
+                          int(height), int(tile_size), _p(_c(bg, np.float64)), npix, _p(pixa),
+                          _p(out["rgb"]), _p(out["alpha"]), _p(out["last_gid"]), _p(out["last_pos"]),
+                          _p(out["ncontrib"]), _p(out["nvisit"]), _p(out["nsupport"]), _p(out["flags"]))
+    assert rc == 0, rc
+    if pix is None:
+        for k in list(out):
+            v = out[k]
+            out[k] = v.reshape((height, width) + v.shape[1:])
+    return out
+
+
+def splats_to_proj(splats, info):
+    """Projected splats in the two-array layout of scenes.random_splats
+    (splats [n, 12] fp32, info [n, 4] uint32) as the float64 record dict
+    that ``render`` takes. The mean is hi + lo, exactly, in float64."""
+    s = np.ascontiguousarray(splats, dtype=np.float32)
+    w = np.ascontiguousarray(info, dtype=np.uint32)
+    rect = np.stack([w[:, 1] & 0xFFFF, w[:, 1] >> 16, w[:, 2] & 0xFFFF, w[:, 2] >> 16], 1)
+    rect = rect.astype(np.int32)
+    vis = (rect[:, 2] > rect[:, 0]) & (rect[:, 3] > rect[:, 1])
+    return {
+        "mean2d": s[:, 0:2].astype(np.float64) + s[:, 2:4].astype(np.float64),
+        "conic": s[:, 4:7].astype(np.float64),
+        "opacity": s[:, 7].astype(np.float64),
+        "rgb": s[:, 8:11].astype(np.float64),
+        "depth_key": np.ascontiguousarray(w[:, 0]).view(np.float32).copy(),
+        "rect": rect,
+        "flags": vis.astype(np.uint8) * VISIBLE,
+    }
+
+
+def count_entries(rect):
+    return int(lib().orc_count_entries(len(rect), _p(_c(rect, np.int32))))
+
+
+def depth_range(depth, rect, S=8192, p_lo=1.0, p_hi=99.0, pad=0.05, znear=0.01, zfar=1e10):
+    zr = np.zeros(2, np.float32)
+    rc = lib().orc_depth_range(len(depth), _p(_c(depth, np.float32)), _p(_c(rect, np.int32)), int(S),
+                               float(p_lo), float(p_hi), float(pad), float(znear), float(zfar), _p(zr))
+    assert rc == 0
+    return zr
+
+
+def bin_of(z, zmin, zmax, K):
+    return int(lib().orc_bin_of(float(z), float(zmin), float(zmax), int(K)))
+
+
+def schedule(depth, rect, tiles_x, tiles_y, K=64, S=8192, p_lo=1.0, p_hi=99.0, pad=0.05,
+             znear=0.01, zfar=1e10):
+    """Integer schedule (keys, vals, tile_offsets, zrange, bin_offsets, stream)."""
+    depth = _c(depth, np.float32)
+    rect = _c(rect, np.int32)
+    n = len(depth)
+    M = count_entries(rect)
+    T = tiles_x * tiles_y
+    out = {
+        "keys": np.zeros(M, np.uint64), "vals": np.zeros(M, np.uint32),
+        "tile_offsets": np.zeros(T + 1, np.uint32), "zrange": np.zeros(2, np.float32),
+        "bin_offsets": np.zeros(T * K + 1, np.uint32), "stream": np.zeros(M, np.uint64),
+    }
+    rc = lib().orc_schedule(n, _p(depth), _p(rect), int(tiles_x), int(tiles_y), int(K), int(S),
+                            float(p_lo), float(p_hi), float(pad), float(znear), float(zfar),
+                            _p(out["keys"]), _p(out["vals"]), _p(out["tile_offsets"]),
+                            _p(out["zrange"]), _p(out["bin_offsets"]), _p(out["stream"]))
+    assert rc == 0, rc
+    out["M"] = M
+    return out

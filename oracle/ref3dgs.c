@@ -1,0 +1,629 @@
+/*
+ * ref3dgs.c -- plain, slow FP64 CPU reference for the 3D Gaussian splatting
+ * forward image, its integer schedule (tile keys, depth bins, offsets) and its
+ * adjoint.
+ *
+ * TEST INFRASTRUCTURE ONLY. Nothing in the product path may link or call this
+ * file; only the test suite, the smoke check and the benchmark's CPU-baseline
+ * leg use it. It shares no code, header, table or constant generator with the
+ * GPU library.
+ *
+ * What it follows:
+ *  - The image model is the unchanged 3DGS one (paper: Introduction and the
+ *    Related-work paragraph on 3DGS/EWA splatting; the method section states
+ *    that projection, splat evaluation and compositing are kept as in the
+ *    baseline). The equations are the standard EWA-splatting / 3DGS ones:
+ *    Sigma = R S^2 R^T, Sigma' = J W Sigma W^T J^T + 0.3 I, conic = Sigma'^-1,
+ *    alpha = min(0.99, o exp(-q/2)), skip alpha < 1/255, stop before the
+ *    Gaussian that would take T below 1e-4, C += T alpha c.
+ *  - The baseline ordering is "first by tile, then by depth" (section
+ *    "Baseline 3DGS rasterization"); ties are broken by Gaussian id.
+ *  - Depth range: supplement, Algorithm "Robust depth-range estimation".
+ *  - Tile-local bins, count / exclusive scan / scatter: supplement,
+ *    Algorithm "Tile-local bin construction" and the log-depth-bin equation.
+ *  - Repair selection rules and budget: Table "Exact-repair selection rules"
+ *    and supplement Algorithm "Selective repair selection and local exact
+ *    sorting".
+ *
+ * Everything is computed in double precision except where a floating-point
+ * value decides an integer the GPU path also decides (the depth used as the
+ * ordering key, the depth range and the bin index): there the computation is
+ * done in the precision the GPU path uses (IEEE binary32, no contraction),
+ * and ambiguous cases are reported through flag bits instead of guessed.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_EXPORT __attribute__((visibility("default")))
+
+/* Fixed thresholds of the 3DGS image model. */
+static const double ALPHA_MIN = 1.0 / 255.0;
+static const double ALPHA_MAX = 0.99;
+static const double T_MIN = 1e-4;
+static const double DILATION = 0.3;  /* px^2 added to the screen covariance */
+static const double GUARD = 0.3;     /* frustum guard: 30 % beyond the image */
+
+/* Per-Gaussian flag bits written by orc_project. */
+enum {
+    ORC_VISIBLE = 1,
+    ORC_AMBIG_RECT = 2,   /* a footprint edge sits on a tile boundary */
+    ORC_AMBIG_DEPTH = 4,  /* reserved */
+    ORC_AMBIG_VIS = 8     /* a visibility test is within rounding of its edge */
+};
+
+/* Per-pixel flag bits written by orc_render. */
+enum {
+    PIX_AMBIG_ALPHA = 1,  /* some alpha within rounding of 1/255 */
+    PIX_AMBIG_STOP = 2,   /* the stopping test within rounding of 1e-4 */
+    PIX_AMBIG_GAUSS = 4,  /* a Gaussian with an ambiguity flag is involved */
+    PIX_POWER_POS = 8     /* -q/2 > 0 was seen (cannot happen in exact math) */
+};
+
+ORC_EXPORT int orc_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------------ */
+/* Real spherical harmonics from associated Legendre functions.             */
+/* ------------------------------------------------------------------------ */
+
+static double factorial(int k) {
+    double f = 1.0;
+    for (int i = 2; i <= k; ++i) f *= i;
+    return f;
+}
+
+/* Associated Legendre P_l^m(x), m >= 0, with the Condon-Shortley phase. */
+static double legendre(int l, int m, double x) {
+    double pmm = 1.0;
+    double s = sqrt(fmax(0.0, 1.0 - x * x));
+    for (int i = 1; i <= m; ++i) pmm *= -(2.0 * i - 1.0) * s;
+    if (l == m) return pmm;
+    double pm1 = x * (2.0 * m + 1.0) * pmm;
+    if (l == m + 1) return pm1;
+    double pl = 0.0;
+    for (int ll = m + 2; ll <= l; ++ll) {
+        pl = ((2.0 * ll - 1.0) * x * pm1 - (ll + m - 1.0) * pmm) / (ll - m);
+        pmm = pm1;
+        pm1 = pl;
+    }
+    return pl;
+}
+
+/* Y_lm(dir) for l <= degree into out[l*l + l + m]; dir need not be unit. */
+ORC_EXPORT void orc_sh_basis(const double* dir, int degree, double* out) {
+    double n = sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
+    double x = dir[0] / n, y = dir[1] / n, z = dir[2] / n;
+    double phi = atan2(y, x);
+    for (int l = 0; l <= degree; ++l) {
+        for (int m = -l; m <= l; ++m) {
+            int am = m < 0 ? -m : m;
+            double norm = sqrt((2.0 * l + 1.0) / (4.0 * M_PI) * factorial(l - am) / factorial(l + am));
+            double p = legendre(l, am, z);
+            double v;
+            if (m > 0)
+                v = sqrt(2.0) * norm * p * cos(am * phi);
+            else if (m < 0)
+                v = sqrt(2.0) * norm * p * sin(am * phi);
+            else
+                v = norm * p;
+            out[l * l + l + m] = v;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Projection of one Gaussian (EWA splatting, 3DGS conventions).            */
+/* camera: double[20] = R[9] (row-major world->camera), t[3], fx, fy, cx,   */
+/* cy, width, height, znear, zfar.                                          */
+/* ------------------------------------------------------------------------ */
+
+static int near_integer(double v, double tol) {
+    return fabs(v - floor(v + 0.5)) < tol;
+}
+
+ORC_EXPORT int orc_project(int64_t n, const float* means, const float* log_scales,
+                           const float* quats, const float* logits, const float* sh,
+                           int sh_degree, const double* cam, int tile_size,
+                           double* mean2d, double* cov2d, double* conic, double* depth,
+                           double* opacity, double* rgb, int32_t* rect, float* depth_key,
+                           uint8_t* flags) {
+    if (n < 0 || sh_degree < 0 || sh_degree > 3 || tile_size <= 0) return 1;
+    const double* R = cam;
+    const double* t = cam + 9;
+    const double fx = cam[12], fy = cam[13], cx = cam[14], cy = cam[15];
+    const int W = (int)cam[16], H = (int)cam[17];
+    const double znear = cam[18], zfar = cam[19];
+    const int tiles_x = (W + tile_size - 1) / tile_size;
+    const int tiles_y = (H + tile_size - 1) / tile_size;
+    const int nsh = (sh_degree + 1) * (sh_degree + 1);
+    /* camera centre c = -R^T t */
+    double campos[3];
+    for (int i = 0; i < 3; ++i) campos[i] = -(R[0 * 3 + i] * t[0] + R[1 * 3 + i] * t[1] + R[2 * 3 + i] * t[2]);
+
+#pragma omp parallel for schedule(static)
+    for (int64_t g = 0; g < n; ++g) {
+        uint8_t fl = 0;
+        mean2d[2 * g] = mean2d[2 * g + 1] = 0.0;
+        for (int k = 0; k < 3; ++k) { cov2d[3 * g + k] = 0.0; conic[3 * g + k] = 0.0; rgb[3 * g + k] = 0.0; }
+        depth[g] = 0.0;
+        opacity[g] = 0.0;
+        depth_key[g] = 0.0f;
+        rect[4 * g] = rect[4 * g + 1] = rect[4 * g + 2] = rect[4 * g + 3] = 0;
+
+        double mu[3] = {means[3 * g], means[3 * g + 1], means[3 * g + 2]};
+        double pc[3];
+        for (int i = 0; i < 3; ++i) pc[i] = R[3 * i] * mu[0] + R[3 * i + 1] * mu[1] + R[3 * i + 2] * mu[2] + t[i];
+        double z = pc[2];
+        if (!(z > znear && z < zfar)) {
+            if (fabs(z - znear) <= 1e-12 * fabs(znear) + 1e-300) fl |= ORC_AMBIG_VIS;
+            flags[g] = fl;
+            continue;
+        }
+        if (fabs(z - znear) <= 1e-12 * znear) fl |= ORC_AMBIG_VIS;
+        /* The ordering key is the binary32 rounding of this binary64 depth,
+           evaluated as ((R20 x + R21 y) + R22 z) + t2 without contraction, so
+           any implementation that performs the same IEEE operations in the
+           same order obtains the same key bits. */
+        depth[g] = z;
+        depth_key[g] = (float)z;
+
+        /* rotation from the normalised quaternion (w, x, y, z) */
+        double qw = quats[4 * g], qx = quats[4 * g + 1], qy = quats[4 * g + 2], qz = quats[4 * g + 3];
+        double qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+        if (!(qn > 0.0) || !isfinite(qn)) { flags[g] = fl; continue; }
+        qw /= qn; qx /= qn; qy /= qn; qz /= qn;
+        double Rq[9] = {
+            1.0 - 2.0 * (qy * qy + qz * qz), 2.0 * (qx * qy - qw * qz), 2.0 * (qx * qz + qw * qy),
+            2.0 * (qx * qy + qw * qz), 1.0 - 2.0 * (qx * qx + qz * qz), 2.0 * (qy * qz - qw * qx),
+            2.0 * (qx * qz - qw * qy), 2.0 * (qy * qz + qw * qx), 1.0 - 2.0 * (qx * qx + qy * qy)};
+        double s2[3];
+        for (int k = 0; k < 3; ++k) { double s = exp((double)log_scales[3 * g + k]); s2[k] = s * s; }
+        /* world covariance Sigma = Rq diag(s^2) Rq^T */
+        double Sw[9];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                double acc = 0.0;
+                for (int k = 0; k < 3; ++k) acc += Rq[3 * i + k] * s2[k] * Rq[3 * j + k];
+                Sw[3 * i + j] = acc;
+            }
+        /* camera covariance R Sigma R^T */
+        double RS[9], Sc[9];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                double acc = 0.0;
+                for (int k = 0; k < 3; ++k) acc += R[3 * i + k] * Sw[3 * k + j];
+                RS[3 * i + j] = acc;
+            }
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                double acc = 0.0;
+                for (int k = 0; k < 3; ++k) acc += RS[3 * i + k] * R[3 * j + k];
+                Sc[3 * i + j] = acc;
+            }
+        /* Jacobian of the perspective map at the (guarded) centre */
+        double lim_xp = (W - cx) / fx + GUARD * W / fx, lim_xn = cx / fx + GUARD * W / fx;
+        double lim_yp = (H - cy) / fy + GUARD * H / fy, lim_yn = cy / fy + GUARD * H / fy;
+        double txz = pc[0] / z, tyz = pc[1] / z;
+        double tx = z * fmin(lim_xp, fmax(-lim_xn, txz));
+        double ty = z * fmin(lim_yp, fmax(-lim_yn, tyz));
+        double J[6] = {fx / z, 0.0, -fx * tx / (z * z), 0.0, fy / z, -fy * ty / (z * z)};
+        double JS[6];
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 3; ++j) {
+                double acc = 0.0;
+                for (int k = 0; k < 3; ++k) acc += J[3 * i + k] * Sc[3 * k + j];
+                JS[3 * i + j] = acc;
+            }
+        double C2[4];
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j) {
+                double acc = 0.0;
+                for (int k = 0; k < 3; ++k) acc += JS[3 * i + k] * J[3 * j + k];
+                C2[2 * i + j] = acc;
+            }
+        double c00 = C2[0] + DILATION, c01 = 0.5 * (C2[1] + C2[2]), c11 = C2[3] + DILATION;
+        cov2d[3 * g] = c00; cov2d[3 * g + 1] = c01; cov2d[3 * g + 2] = c11;
+        double det = c00 * c11 - c01 * c01;
+        if (!(det > 0.0) || !isfinite(det)) { flags[g] = fl; continue; }
+        conic[3 * g] = c11 / det;
+        conic[3 * g + 1] = -c01 / det;
+        conic[3 * g + 2] = c00 / det;
+        double mx = fx * pc[0] / z + cx, my = fy * pc[1] / z + cy;
+        mean2d[2 * g] = mx;
+        mean2d[2 * g + 1] = my;
+
+        double o = 1.0 / (1.0 + exp(-(double)logits[g]));
+        opacity[g] = o;
+
+        /* colour: 0.5 + sum_lm sh_lm Y_lm(dir), clamped below at 0 */
+        double dir[3] = {mu[0] - campos[0], mu[1] - campos[1], mu[2] - campos[2]};
+        double Y[16];
+        orc_sh_basis(dir, sh_degree, Y);
+        for (int ch = 0; ch < 3; ++ch) {
+            double acc = 0.0;
+            for (int k = 0; k < nsh; ++k) acc += (double)sh[((int64_t)g * nsh + k) * 3 + ch] * Y[k];
+            rgb[3 * g + ch] = fmax(0.0, 0.5 + acc);
+        }
+
+        /* opacity-aware footprint: alpha >= 1/255 needs q <= 2 ln(255 o) */
+        if (fabs(o * 255.0 - 1.0) < 1e-12) fl |= ORC_AMBIG_VIS;
+        if (!(o >= ALPHA_MIN)) { flags[g] = fl; continue; }
+        double tau = 2.0 * log(255.0 * o);
+        double hx = sqrt(tau * c00), hy = sqrt(tau * c11);
+        double ex = hx * (1.0 + 1e-4) + 1e-3, ey = hy * (1.0 + 1e-4) + 1e-3;
+        double fx0 = (mx - ex) / tile_size, fx1 = (mx + ex) / tile_size;
+        double fy0 = (my - ey) / tile_size, fy1 = (my + ey) / tile_size;
+        if (near_integer(fx0, 1e-9) || near_integer(fx1, 1e-9) || near_integer(fy0, 1e-9) || near_integer(fy1, 1e-9))
+            fl |= ORC_AMBIG_RECT;
+        double x0 = floor(fx0), x1 = floor(fx1) + 1.0, y0 = floor(fy0), y1 = floor(fy1) + 1.0;
+        x0 = fmin(fmax(x0, 0.0), tiles_x); x1 = fmin(fmax(x1, 0.0), tiles_x);
+        y0 = fmin(fmax(y0, 0.0), tiles_y); y1 = fmin(fmax(y1, 0.0), tiles_y);
+        if (!(x1 > x0 && y1 > y0)) { flags[g] = fl; continue; }
+        rect[4 * g] = (int32_t)x0; rect[4 * g + 1] = (int32_t)y0;
+        rect[4 * g + 2] = (int32_t)x1; rect[4 * g + 3] = (int32_t)y1;
+        fl |= ORC_VISIBLE;
+        flags[g] = fl;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Compositing: the per-pixel definition.                                   */
+/* ------------------------------------------------------------------------ */
+
+typedef struct { float key; uint32_t gid; } ord_t;
+
+static int ord_cmp(const void* a, const void* b) {
+    const ord_t* x = (const ord_t*)a;
+    const ord_t* y = (const ord_t*)b;
+    if (x->key < y->key) return -1;
+    if (x->key > y->key) return 1;
+    return (x->gid > y->gid) - (x->gid < y->gid);
+}
+
+/* Traverse one pixel over an ordered candidate list (front to back). */
+static void composite_pixel(const ord_t* list, int64_t len, int64_t pos_base, double px, double py,
+                            const double* mean2d, const double* conic, const double* opacity,
+                            const double* rgb, const uint8_t* gflags, const double* bg,
+                            double* out_rgb, double* out_alpha, int64_t* out_last_gid,
+                            int64_t* out_last_pos, int32_t* out_ncontrib, int32_t* out_nvisit,
+                            int32_t* out_nsupport, uint8_t* out_flags) {
+    double T = 1.0, C[3] = {0.0, 0.0, 0.0};
+    int64_t last_gid = -1, last_pos = -1;
+    int32_t ncontrib = 0, nvisit = 0, nsupport = 0;
+    uint8_t pf = 0;
+    for (int64_t i = 0; i < len; ++i) {
+        uint32_t g = list[i].gid;
+        nvisit++;
+        double dx = mean2d[2 * g] - px, dy = mean2d[2 * g + 1] - py;
+        double a = conic[3 * g], b = conic[3 * g + 1], c = conic[3 * g + 2];
+        double q = a * dx * dx + 2.0 * b * dx * dy + c * dy * dy;
+        double power = -0.5 * q;
+        if (power > 0.0) { pf |= PIX_POWER_POS; continue; }
+        double araw = opacity[g] * exp(power);
+        /* rounding bound of a binary32 evaluation of q, in q units */
+        double qerr = 2e-6 * (fabs(a) * dx * dx + 2.0 * fabs(b * dx * dy) + fabs(c) * dy * dy) + 2e-6;
+        double margin = log(araw * 255.0);
+        if (fabs(margin) < 0.5 * qerr + 2e-5) {
+            pf |= PIX_AMBIG_ALPHA;
+            if (gflags && (gflags[g] & (ORC_AMBIG_RECT | ORC_AMBIG_DEPTH | ORC_AMBIG_VIS))) pf |= PIX_AMBIG_GAUSS;
+        }
+        if (araw < ALPHA_MIN) continue;
+        if (gflags && (gflags[g] & (ORC_AMBIG_RECT | ORC_AMBIG_DEPTH | ORC_AMBIG_VIS))) pf |= PIX_AMBIG_GAUSS;
+        double alpha = fmin(ALPHA_MAX, araw);
+        nsupport++;
+        double test = T * (1.0 - alpha);
+        if (fabs(test / T_MIN - 1.0) < 2e-4) pf |= PIX_AMBIG_STOP;
+        if (test < T_MIN) break;
+        for (int ch = 0; ch < 3; ++ch) C[ch] += T * alpha * rgb[3 * g + ch];
+        T = test;
+        last_gid = g;
+        last_pos = pos_base + i;
+        ncontrib++;
+    }
+    for (int ch = 0; ch < 3; ++ch) out_rgb[ch] = C[ch] + T * bg[ch];
+    *out_alpha = 1.0 - T;
+    *out_last_gid = last_gid;
+    *out_last_pos = last_pos;
+    *out_ncontrib = ncontrib;
+    *out_nvisit = nvisit;
+    *out_nsupport = nsupport;
+    *out_flags = pf;
+}
+
+/*
+ * Render the pixels listed in pix ([npix][2] as x, y; NULL = every pixel,
+ * row-major). With rect != NULL ("tiled"), each pixel walks the ordered list
+ * of its tile (Gaussians whose half-open tile rect contains the tile), and
+ * last_pos is the position in the concatenation of the tile lists in
+ * row-major tile order. With rect == NULL ("brute"), each pixel considers
+ * every Gaussian with ORC_VISIBLE set; nvisit and last_pos are -1 there.
+ * Every Gaussian is assumed valid when gflags is NULL.
+ */
+ORC_EXPORT int orc_render(int64_t n, const double* mean2d, const double* conic, const double* opacity,
+                          const double* rgb, const float* depth_key, const int32_t* rect,
+                          const uint8_t* gflags, int width, int height, int tile_size,
+                          const double* bg, int64_t npix, const int32_t* pix, double* out_rgb,
+                          double* out_alpha, int64_t* out_last_gid, int64_t* out_last_pos,
+                          int32_t* out_ncontrib, int32_t* out_nvisit, int32_t* out_nsupport,
+                          uint8_t* out_flags) {
+    if (n < 0 || width <= 0 || height <= 0 || tile_size <= 0) return 1;
+    const int64_t P = pix ? npix : (int64_t)width * height;
+    const int tiles_x = (width + tile_size - 1) / tile_size;
+    const int tiles_y = (height + tile_size - 1) / tile_size;
+    const int64_t T = (int64_t)tiles_x * tiles_y;
+
+    if (rect) {
+        /* tile lists in CSR form */
+        int64_t* off = (int64_t*)calloc((size_t)T + 1, sizeof(int64_t));
+        if (!off) return 2;
+        for (int64_t g = 0; g < n; ++g) {
+            if (gflags && !(gflags[g] & ORC_VISIBLE)) continue;
+            for (int y = rect[4 * g + 1]; y < rect[4 * g + 3]; ++y)
+                for (int x = rect[4 * g]; x < rect[4 * g + 2]; ++x) off[(int64_t)y * tiles_x + x + 1]++;
+        }
+        for (int64_t t = 0; t < T; ++t) off[t + 1] += off[t];
+        int64_t M = off[T];
+        ord_t* lists = (ord_t*)malloc((size_t)(M > 0 ? M : 1) * sizeof(ord_t));
+        int64_t* cur = (int64_t*)malloc((size_t)(T > 0 ? T : 1) * sizeof(int64_t));
+        if (!lists || !cur) { free(off); free(lists); free(cur); return 2; }
+        memcpy(cur, off, (size_t)T * sizeof(int64_t));
+        for (int64_t g = 0; g < n; ++g) {
+            if (gflags && !(gflags[g] & ORC_VISIBLE)) continue;
+            for (int y = rect[4 * g + 1]; y < rect[4 * g + 3]; ++y)
+                for (int x = rect[4 * g]; x < rect[4 * g + 2]; ++x) {
+                    int64_t t = (int64_t)y * tiles_x + x;
+                    lists[cur[t]].key = depth_key[g];
+                    lists[cur[t]].gid = (uint32_t)g;
+                    cur[t]++;
+                }
+        }
+#pragma omp parallel for schedule(dynamic, 16)
+        for (int64_t t = 0; t < T; ++t)
+            qsort(lists + off[t], (size_t)(off[t + 1] - off[t]), sizeof(ord_t), ord_cmp);
+#pragma omp parallel for schedule(dynamic, 256)
+        for (int64_t p = 0; p < P; ++p) {
+            int x = pix ? pix[2 * p] : (int)(p % width);
+            int y = pix ? pix[2 * p + 1] : (int)(p / width);
+            int64_t t = (int64_t)(y / tile_size) * tiles_x + x / tile_size;
+            composite_pixel(lists + off[t], off[t + 1] - off[t], off[t], x + 0.5, y + 0.5, mean2d, conic,
+                            opacity, rgb, gflags, bg, out_rgb + 3 * p, out_alpha + p, out_last_gid + p,
+                            out_last_pos + p, out_ncontrib + p, out_nvisit + p, out_nsupport + p,
+                            out_flags + p);
+        }
+        free(off);
+        free(lists);
+        free(cur);
+        return 0;
+    }
+
+    /* brute force: every visible Gaussian, sorted per pixel */
+    int err = 0;
+#pragma omp parallel
+    {
+        ord_t* list = (ord_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(ord_t));
+        if (!list) {
+#pragma omp atomic write
+            err = 2;
+        }
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t p = 0; p < P; ++p) {
+            if (!list) continue;
+            int x = pix ? pix[2 * p] : (int)(p % width);
+            int y = pix ? pix[2 * p + 1] : (int)(p / width);
+            double px = x + 0.5, py = y + 0.5;
+            int64_t len = 0;
+            for (int64_t g = 0; g < n; ++g) {
+                if (gflags && !(gflags[g] & ORC_VISIBLE)) continue;
+                double dx = mean2d[2 * g] - px, dy = mean2d[2 * g + 1] - py;
+                double q = conic[3 * g] * dx * dx + 2.0 * conic[3 * g + 1] * dx * dy + conic[3 * g + 2] * dy * dy;
+                /* keep a slightly larger set than the alpha support so that the
+                   near-threshold flags are raised exactly as in tiled mode */
+                if (opacity[g] * exp(-0.5 * q) < ALPHA_MIN * 0.999) continue;
+                list[len].key = depth_key[g];
+                list[len].gid = (uint32_t)g;
+                len++;
+            }
+            qsort(list, (size_t)len, sizeof(ord_t), ord_cmp);
+            composite_pixel(list, len, 0, px, py, mean2d, conic, opacity, rgb, gflags, bg,
+                            out_rgb + 3 * p, out_alpha + p, out_last_gid + p, out_last_pos + p,
+                            out_ncontrib + p, out_nvisit + p, out_nsupport + p, out_flags + p);
+            out_nvisit[p] = -1;
+            out_last_pos[p] = -1;
+        }
+        free(list);
+    }
+    return err;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Integer schedule: keys, global order, depth range, bins, offsets.        */
+/* ------------------------------------------------------------------------ */
+
+static uint32_t f32_bits(float f) {
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    return u;
+}
+
+/* Number of (Gaussian, tile) entries: the sum of the rect areas. */
+ORC_EXPORT int64_t orc_count_entries(int64_t n, const int32_t* rect) {
+    int64_t M = 0;
+    for (int64_t g = 0; g < n; ++g) {
+        int64_t w = rect[4 * g + 2] - rect[4 * g], h = rect[4 * g + 3] - rect[4 * g + 1];
+        if (w > 0 && h > 0) M += w * h;
+    }
+    return M;
+}
+
+typedef struct { uint64_t key; uint32_t gid; } kv_t;
+
+static int kv_cmp(const void* a, const void* b) {
+    const kv_t* x = (const kv_t*)a;
+    const kv_t* y = (const kv_t*)b;
+    if (x->key != y->key) return x->key < y->key ? -1 : 1;
+    return (x->gid > y->gid) - (x->gid < y->gid);
+}
+
+static int u32_cmp(const void* a, const void* b) {
+    uint32_t x = *(const uint32_t*)a, y = *(const uint32_t*)b;
+    return (x > y) - (x < y);
+}
+
+static int u64_cmp(const void* a, const void* b) {
+    uint64_t x = *(const uint64_t*)a, y = *(const uint64_t*)b;
+    return (x > y) - (x < y);
+}
+
+/*
+ * Robust depth range (supplement, Algorithm "Robust depth-range estimation"),
+ * without the near-depth shift: sample the depths of the visible Gaussians
+ * (non-empty rect), take the exact order statistics at the p_lo / p_hi
+ * percentiles, pad by pad * span and clamp to [znear, zfar].
+ * Readings: with V visible Gaussians and S samples, all are taken when
+ * V <= S, otherwise the visible Gaussians at ranks floor(i V / S) of the
+ * ascending id list; the order statistics are the 0-based ranks
+ * floor(p_lo/100 (n-1)) and ceil(p_hi/100 (n-1)); the arithmetic after the
+ * selection is binary32 without contraction.
+ */
+ORC_EXPORT int orc_depth_range(int64_t n, const float* depth, const int32_t* rect, int S, double p_lo,
+                               double p_hi, float pad, float znear, float zfar, float* zrange) {
+    int64_t V = 0;
+    for (int64_t g = 0; g < n; ++g)
+        if (rect[4 * g + 2] > rect[4 * g] && rect[4 * g + 3] > rect[4 * g + 1]) V++;
+    if (V == 0) { zrange[0] = znear; zrange[1] = zfar; return 0; }
+    int64_t* vis = (int64_t*)malloc((size_t)V * sizeof(int64_t));
+    if (!vis) return 2;
+    int64_t k = 0;
+    for (int64_t g = 0; g < n; ++g)
+        if (rect[4 * g + 2] > rect[4 * g] && rect[4 * g + 3] > rect[4 * g + 1]) vis[k++] = g;
+    int64_t ns = V <= S ? V : S;
+    uint32_t* sample = (uint32_t*)malloc((size_t)ns * sizeof(uint32_t));
+    if (!sample) { free(vis); return 2; }
+    for (int64_t i = 0; i < ns; ++i) {
+        int64_t r = V <= S ? i : (i * V) / S;
+        sample[i] = f32_bits(depth[vis[r]]);
+    }
+    qsort(sample, (size_t)ns, sizeof(uint32_t), u32_cmp);
+    int64_t klo = (int64_t)floor(p_lo / 100.0 * (double)(ns - 1));
+    int64_t khi = (int64_t)ceil(p_hi / 100.0 * (double)(ns - 1));
+    if (klo < 0) klo = 0;
+    if (khi > ns - 1) khi = ns - 1;
+    float zlo, zhi;
+    memcpy(&zlo, &sample[klo], 4);
+    memcpy(&zhi, &sample[khi], 4);
+    volatile float diff = zhi - zlo;
+    float span = diff > 1e-6f ? diff : 1e-6f;
+    volatile float padv = pad * span;
+    volatile float lo = zlo - padv;
+    volatile float hi = zhi + padv;
+    zrange[0] = lo > znear ? lo : znear;
+    zrange[1] = hi < zfar ? hi : zfar;
+    free(sample);
+    free(vis);
+    return 0;
+}
+
+/*
+ * Log-depth bin of a binary32 depth: the paper's clamped log-space map
+ * floor(K u), u = (log z - log zmin) / (log zmax - log zmin), realised with
+ * the IEEE-754 bit pattern as the logarithm (a monotone piecewise-linear
+ * log2), evaluated exactly in integers.
+ */
+static int bin_of(float z, float zmin, float zmax, int K) {
+    int64_t L = f32_bits(z), Lmin = f32_bits(zmin), Lmax = f32_bits(zmax);
+    if (Lmax <= Lmin || L <= Lmin) return 0;
+    if (L >= Lmax) return K - 1;
+    int64_t b = ((int64_t)K * (L - Lmin)) / (Lmax - Lmin);
+    return b > K - 1 ? K - 1 : (int)b;
+}
+
+ORC_EXPORT int orc_bin_of(float z, float zmin, float zmax, int K) { return bin_of(z, zmin, zmax, K); }
+
+/*
+ * The whole integer schedule for binary32 depths and tile rects.
+ * keys/vals: the global list, sorted by (tile << 32 | depth bits, id).
+ * tile_offsets[T+1]: each tile's range in it.
+ * zrange[2]: the depth range; bin_offsets[T*K+1]: exclusive scan of the
+ * (tile, bin) counts in tile-major, bin-minor order (supplement, Algorithm
+ * "Tile-local bin construction").
+ * stream[M]: the tile-bin-major stream with every (tile, bin) segment sorted
+ * by (depth bits << 32 | id), the exact-repair order.
+ * Any output pointer may be NULL.
+ */
+ORC_EXPORT int orc_schedule(int64_t n, const float* depth, const int32_t* rect, int tiles_x, int tiles_y,
+                            int K, int S, double p_lo, double p_hi, float pad, float znear, float zfar,
+                            uint64_t* keys, uint32_t* vals, uint32_t* tile_offsets, float* zrange,
+                            uint32_t* bin_offsets, uint64_t* stream) {
+    const int64_t T = (int64_t)tiles_x * tiles_y;
+    const int64_t M = orc_count_entries(n, rect);
+    kv_t* e = (kv_t*)malloc((size_t)(M > 0 ? M : 1) * sizeof(kv_t));
+    if (!e) return 2;
+    int64_t m = 0;
+    for (int64_t g = 0; g < n; ++g)
+        for (int y = rect[4 * g + 1]; y < rect[4 * g + 3]; ++y)
+            for (int x = rect[4 * g]; x < rect[4 * g + 2]; ++x) {
+                uint64_t t = (uint64_t)y * tiles_x + x;
+                e[m].key = (t << 32) | f32_bits(depth[g]);
+                e[m].gid = (uint32_t)g;
+                m++;
+            }
+    qsort(e, (size_t)M, sizeof(kv_t), kv_cmp);
+    if (keys)
+        for (int64_t i = 0; i < M; ++i) keys[i] = e[i].key;
+    if (vals)
+        for (int64_t i = 0; i < M; ++i) vals[i] = e[i].gid;
+    if (tile_offsets) {
+        int64_t i = 0;
+        for (int64_t t = 0; t <= T; ++t) {
+            while (i < M && (int64_t)(e[i].key >> 32) < t) i++;
+            tile_offsets[t] = (uint32_t)i;
+        }
+    }
+    float zr[2];
+    int rc = orc_depth_range(n, depth, rect, S, p_lo, p_hi, pad, znear, zfar, zr);
+    if (rc) { free(e); return rc; }
+    if (zrange) { zrange[0] = zr[0]; zrange[1] = zr[1]; }
+    if (bin_offsets || stream) {
+        const int64_t NS = T * K;
+        uint32_t* cnt = (uint32_t*)calloc((size_t)NS + 1, sizeof(uint32_t));
+        uint32_t* off = (uint32_t*)malloc(((size_t)NS + 1) * sizeof(uint32_t));
+        uint32_t* cur = (uint32_t*)malloc(((size_t)NS + 1) * sizeof(uint32_t));
+        uint64_t* st = (uint64_t*)malloc((size_t)(M > 0 ? M : 1) * sizeof(uint64_t));
+        if (!cnt || !off || !cur || !st) { free(cnt); free(off); free(cur); free(st); free(e); return 2; }
+        /* count in emission order (the order is irrelevant for counts) */
+        for (int64_t g = 0; g < n; ++g) {
+            int b = bin_of(depth[g], zr[0], zr[1], K);
+            for (int y = rect[4 * g + 1]; y < rect[4 * g + 3]; ++y)
+                for (int x = rect[4 * g]; x < rect[4 * g + 2]; ++x) cnt[((int64_t)y * tiles_x + x) * K + b]++;
+        }
+        off[0] = 0;
+        for (int64_t s = 0; s < NS; ++s) off[s + 1] = off[s] + cnt[s];
+        memcpy(cur, off, ((size_t)NS + 1) * sizeof(uint32_t));
+        for (int64_t g = 0; g < n; ++g) {
+            int b = bin_of(depth[g], zr[0], zr[1], K);
+            for (int y = rect[4 * g + 1]; y < rect[4 * g + 3]; ++y)
+                for (int x = rect[4 * g]; x < rect[4 * g + 2]; ++x) {
+                    int64_t s = ((int64_t)y * tiles_x + x) * K + b;
+                    st[cur[s]++] = ((uint64_t)f32_bits(depth[g]) << 32) | (uint64_t)g;
+                }
+        }
+        for (int64_t s = 0; s < NS; ++s)
+            qsort(st + off[s], (size_t)(off[s + 1] - off[s]), sizeof(uint64_t), u64_cmp);
+        if (bin_offsets) memcpy(bin_offsets, off, ((size_t)NS + 1) * sizeof(uint32_t));
+        if (stream) memcpy(stream, st, (size_t)M * sizeof(uint64_t));
+        free(cnt); free(off); free(cur); free(st);
+    }
+    free(e);
+    return 0;
+}

@@ -1,0 +1,238 @@
+"""Pins of the oracle's projection and colour (EWA splatting / 3DGS image model).
+
+Each test checks the oracle against something other than its own formulas:
+closed forms of special cases, a numerical Jacobian, scipy's spherical
+harmonics, quadrature orthonormality and exact invariances.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import scenes
+
+
+def one_gaussian(mean, log_scales, quat=(1.0, 0.0, 0.0, 0.0), logit=0.0, sh=None, degree=0):
+    if sh is None:
+        sh = np.zeros(((degree + 1) ** 2, 3))
+    return {
+        "means": np.array([mean], np.float32), "log_scales": np.array([log_scales], np.float32),
+        "quats": np.array([quat], np.float32), "logits": np.array([logit], np.float32),
+        "sh": np.array([sh], np.float32), "sh_degree": degree,
+    }
+
+
+def ident_cam(f=100.0, w=64, h=64):
+    return scenes.camera(np.eye(3), np.zeros(3), f, f, w / 2.0, h / 2.0, w, h)
+
+
+def test_isotropic_on_axis_closed_form():
+    # mu = (0, 0, z) on the optical axis: J has a zero third column on the
+    # axis, so Sigma' = (f sigma / z)^2 I + 0.3 I exactly.
+    s, z, f = 0.05, 3.0, 100.0
+    g = one_gaussian((0.0, 0.0, z), [math.log(s)] * 3)
+    p = oracle.project(g, ident_cam(f))
+    s32 = float(np.float32(math.log(s)))
+    sig = f * math.exp(s32) / z
+    expect = sig * sig + 0.3
+    np.testing.assert_allclose(p["cov2d"][0], [expect, 0.0, expect], rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(p["conic"][0], [1 / expect, 0.0, 1 / expect], rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(p["mean2d"][0], [32.0, 32.0], rtol=0, atol=1e-12)
+    assert p["depth"][0] == pytest.approx(3.0)
+    assert p["opacity"][0] == pytest.approx(0.5)
+
+
+@pytest.mark.parametrize("theta", [0.0, 0.3, 1.1, 2.5])
+def test_anisotropic_rotation_about_optical_axis(theta):
+    # A rotation by theta about the optical axis rotates the 2D covariance by
+    # theta: Sigma' = (f/z)^2 R(theta) diag(s1^2, s2^2) R(theta)^T + 0.3 I.
+    s1, s2, s3, z, f = 0.08, 0.02, 0.5, 4.0, 120.0
+    q = (math.cos(theta / 2), 0.0, 0.0, math.sin(theta / 2))
+    g = one_gaussian((0.0, 0.0, z), [math.log(s1), math.log(s2), math.log(s3)], quat=q)
+    p = oracle.project(g, ident_cam(f))
+    q32 = np.array(q, np.float32).astype(np.float64)
+    th = 2.0 * math.atan2(q32[3], q32[0])
+    ls = np.array([math.log(s1), math.log(s2)], np.float32).astype(np.float64)
+    a1, a2 = np.exp(ls) * f / z
+    c, sn = math.cos(th), math.sin(th)
+    Rt = np.array([[c, -sn], [sn, c]])
+    S = Rt @ np.diag([a1 * a1, a2 * a2]) @ Rt.T + 0.3 * np.eye(2)
+    np.testing.assert_allclose(p["cov2d"][0], [S[0, 0], S[0, 1], S[1, 1]], rtol=1e-10, atol=1e-12)
+
+
+def test_jacobian_against_numerical_derivative():
+    # For an isotropic Gaussian Sigma_cam = s^2 I, so Sigma' - 0.3 I = s^2 J J^T
+    # where J is the derivative of the pinhole map (fx x/z + cx, fy y/z + cy).
+    rng = np.random.default_rng(3)
+    fx, fy, W, H = 150.0, 130.0, 96, 80
+    cam = scenes.camera(np.eye(3), np.zeros(3), fx, fy, 41.0, 37.0, W, H)
+    for _ in range(10):
+        mu = np.array([rng.uniform(-0.5, 0.5), rng.uniform(-0.5, 0.5), rng.uniform(1.5, 4)], np.float32)
+        s = 0.03
+        p = oracle.project(one_gaussian(mu, [math.log(s)] * 3), cam)
+        m = mu.astype(np.float64)
+
+        def pin(v):
+            return np.array([fx * v[0] / v[2] + 41.0, fy * v[1] / v[2] + 37.0])
+        h = 1e-6
+        J = np.stack([(pin(m + h * e) - pin(m - h * e)) / (2 * h) for e in np.eye(3)], axis=1)
+        s64 = math.exp(float(np.float32(math.log(s))))
+        S = s64 * s64 * J @ J.T + 0.3 * np.eye(2)
+        np.testing.assert_allclose(p["cov2d"][0], [S[0, 0], S[0, 1], S[1, 1]], rtol=1e-7)
+        np.testing.assert_allclose(p["mean2d"][0], pin(m), rtol=1e-12)
+
+
+def test_world_scale_invariance():
+    # Scaling the means, the scales and the camera translation by k leaves the
+    # screen-space projection unchanged (and the depth scaled by k).
+    g, cam = scenes.small_forward(seed=4, n=300)
+    cam["t"] = np.array([0.1, -0.2, 0.5])
+    k = 2.0  # a power of two keeps the fp32 inputs exact
+    g2 = dict(g)
+    g2["means"] = (g["means"] * k).astype(np.float32)
+    g2["log_scales"] = (g["log_scales"] + np.float32(math.log(k))).astype(np.float32)
+    cam2 = dict(cam)
+    cam2["t"] = cam["t"] * k
+    a, b = oracle.project(g, cam), oracle.project(g2, cam2)
+    vis = (a["flags"] & 1) > 0
+    np.testing.assert_array_equal(vis, (b["flags"] & 1) > 0)
+    np.testing.assert_allclose(a["mean2d"][vis], b["mean2d"][vis], rtol=1e-12, atol=1e-9)
+    np.testing.assert_allclose(a["cov2d"][vis], b["cov2d"][vis], rtol=1e-5)
+    np.testing.assert_allclose(a["depth"][vis] * k, b["depth"][vis], rtol=1e-14)
+
+
+def test_rigid_motion_invariance():
+    # Moving the world by a rotation Q and translation d and the camera with it
+    # (R' = R Q^T, t' = t - R' d) leaves the projection unchanged (degree 0, so
+    # the colour does not depend on the view direction).
+    g, cam = scenes.small_forward(seed=5, n=200)
+    rng = np.random.default_rng(0)
+    A = rng.normal(size=(3, 3))
+    Q, _ = np.linalg.qr(A)
+    if np.linalg.det(Q) < 0:
+        Q[:, 0] *= -1
+    d = np.array([0.25, -0.5, 1.0])
+    g2 = dict(g)
+    g2["means"] = (g["means"].astype(np.float64) @ Q.T + d).astype(np.float32)
+    qw = g["quats"].astype(np.float64)
+    # compose the rotation of each Gaussian with Q (quaternion of Q times q)
+    from scipy.spatial.transform import Rotation
+    rq = Rotation.from_quat(np.concatenate([qw[:, 1:], qw[:, :1]], 1))
+    rq2 = Rotation.from_matrix(Q) * rq
+    x = rq2.as_quat()
+    g2["quats"] = np.concatenate([x[:, 3:], x[:, :3]], 1).astype(np.float32)
+    R2 = cam["R"] @ Q.T
+    cam2 = dict(cam)
+    cam2["R"] = R2
+    cam2["t"] = cam["t"] - R2 @ d
+    a, b = oracle.project(g, cam), oracle.project(g2, cam2)
+    vis = ((a["flags"] & 1) > 0) & ((b["flags"] & 1) > 0)
+    assert vis.sum() > 150
+    # fp32 rounding of the moved means limits the agreement
+    np.testing.assert_allclose(a["mean2d"][vis], b["mean2d"][vis], rtol=0, atol=2e-4)
+    np.testing.assert_allclose(a["cov2d"][vis], b["cov2d"][vis], rtol=2e-4, atol=1e-5)
+    np.testing.assert_allclose(a["rgb"][vis], b["rgb"][vis], rtol=1e-12)
+
+
+def test_sh_low_order_closed_forms():
+    rng = np.random.default_rng(1)
+    for _ in range(20):
+        d = rng.normal(size=3)
+        x, y, z = d / np.linalg.norm(d)
+        Y = oracle.sh_basis(d, 1)
+        c1 = math.sqrt(3 / (4 * math.pi))
+        np.testing.assert_allclose(Y, [1 / (2 * math.sqrt(math.pi)), -c1 * y, c1 * z, -c1 * x], rtol=1e-13)
+
+
+def test_sh_against_scipy():
+    # Real harmonics from scipy's complex ones (which carry the Condon-Shortley
+    # phase): sqrt(2) Re Y_l^m for m > 0, sqrt(2) Im Y_l^|m| for m < 0.
+    from scipy.special import sph_harm_y
+    rng = np.random.default_rng(2)
+    for _ in range(25):
+        d = rng.normal(size=3)
+        u = d / np.linalg.norm(d)
+        polar, azim = math.acos(u[2]), math.atan2(u[1], u[0])
+        Y = oracle.sh_basis(d, 3)
+        for l in range(4):
+            for m in range(-l, l + 1):
+                c = sph_harm_y(l, abs(m), polar, azim)
+                if m > 0:
+                    ref = math.sqrt(2) * c.real
+                elif m < 0:
+                    ref = math.sqrt(2) * c.imag
+                else:
+                    ref = c.real
+                assert Y[l * l + l + m] == pytest.approx(ref, abs=1e-12), (l, m)
+
+
+def test_sh_orthonormal_by_quadrature():
+    # Gauss-Legendre in cos(theta) times a uniform rule in phi integrates
+    # products of degree <= 6 exactly: the Gram matrix must be the identity.
+    nt, nphi = 12, 16
+    xs, ws = np.polynomial.legendre.leggauss(nt)
+    G = np.zeros((16, 16))
+    for ct, w in zip(xs, ws):
+        st = math.sqrt(1 - ct * ct)
+        for k in range(nphi):
+            ph = 2 * math.pi * k / nphi
+            Y = oracle.sh_basis(np.array([st * math.cos(ph), st * math.sin(ph), ct]), 3)
+            G += w * (2 * math.pi / nphi) * np.outer(Y, Y)
+    np.testing.assert_allclose(G, np.eye(16), atol=1e-12)
+
+
+def test_sh_degree0_colour_and_degree3_reduction():
+    rng = np.random.default_rng(3)
+    dc = rng.normal(size=3)
+    g0 = one_gaussian((0.1, -0.2, 3.0), [-3.0] * 3, sh=[dc], degree=0)
+    sh3 = np.zeros((16, 3))
+    sh3[0] = dc
+    g3 = one_gaussian((0.1, -0.2, 3.0), [-3.0] * 3, sh=sh3, degree=3)
+    cam = ident_cam()
+    a, b = oracle.project(g0, cam), oracle.project(g3, cam)
+    dc32 = np.float32(dc).astype(np.float64)
+    np.testing.assert_allclose(a["rgb"][0], np.maximum(0, 0.5 + dc32 / (2 * math.sqrt(math.pi))), rtol=1e-14)
+    np.testing.assert_allclose(a["rgb"][0], b["rgb"][0], rtol=1e-14)
+
+
+def test_sh_colour_uses_view_direction_and_clamps():
+    # Degree 1 with only the z coefficient: colour = max(0, 0.5 + c * Y_10(d)).
+    sh = np.zeros((4, 3))
+    sh[2] = [1.0, -1.0, 3.0]
+    g = one_gaussian((0.0, 0.0, 2.0), [-3.0] * 3, sh=sh, degree=1)
+    p = oracle.project(g, ident_cam())
+    c1 = math.sqrt(3 / (4 * math.pi))
+    np.testing.assert_allclose(p["rgb"][0], [0.5 + c1, max(0.0, 0.5 - c1), 0.5 + 3 * c1], rtol=1e-7)
+
+
+def test_visibility_rules():
+    cam = ident_cam()
+    assert oracle.project(one_gaussian((0, 0, 0.005), [-3] * 3), cam)["flags"][0] & 1 == 0  # before znear
+    assert oracle.project(one_gaussian((0, 0, -1.0), [-3] * 3), cam)["flags"][0] & 1 == 0   # behind
+    assert oracle.project(one_gaussian((0, 0, 2), [-3] * 3, quat=(0, 0, 0, 0)), cam)["flags"][0] & 1 == 0
+    assert oracle.project(one_gaussian((np.nan, 0, 2), [-3] * 3), cam)["flags"][0] & 1 == 0
+    # opacity below 1/255 can never pass the alpha test
+    assert oracle.project(one_gaussian((0, 0, 2), [-3] * 3, logit=-5.6), cam)["flags"][0] & 1 == 0
+    assert oracle.project(one_gaussian((0, 0, 2), [-3] * 3, logit=-5.5), cam)["flags"][0] & 1 == 1
+    # far outside the image
+    assert oracle.project(one_gaussian((5.0, 0, 2), [-3] * 3), cam)["flags"][0] & 1 == 0
+
+
+def test_footprint_covers_alpha_support():
+    # The opacity-aware rect must contain every pixel where alpha >= 1/255:
+    # for a large splat, check the tiles of all such pixels (evaluated from the
+    # closed-form isotropic image) lie inside the rect.
+    s, z, f = 0.2, 3.0, 100.0
+    g = one_gaussian((0.11, -0.07, z), [math.log(s)] * 3, logit=2.0)
+    p = oracle.project(g, ident_cam(f, 128, 128))
+    sig2 = (f * math.exp(float(np.float32(math.log(s)))) / z) ** 2 + 0.3
+    o = 1 / (1 + math.exp(-2.0))
+    mx, my = p["mean2d"][0]
+    x0, y0, x1, y1 = p["rect"][0]
+    ys, xs = np.mgrid[0:128, 0:128] + 0.5
+    a = o * np.exp(-0.5 * ((xs - mx) ** 2 + (ys - my) ** 2) / sig2)
+    yy, xx = np.nonzero(a >= 1 / 255)
+    assert len(xx) > 100
+    assert (xx // 16).min() >= x0 and (xx // 16).max() < x1
+    assert (yy // 16).min() >= y0 and (yy // 16).max() < y1
