@@ -1,0 +1,193 @@
+/*
+ * tilegs.h -- C ABI of the MI355X (gfx950) tile-local depth-binned 3D Gaussian
+ * splatting rasterizer.
+ *
+ * The library implements the forward path of "TileGS: Tile-Local Depth
+ * Binning for Gaussian Splatting Rasterization" and the globally sorted
+ * comparator it is measured against:
+ *
+ *   tgs_project    3DGS projection + spherical-harmonic colour (the paper keeps
+ *                  the baseline projection unchanged; method section,
+ *                  "Baseline 3DGS rasterization").
+ *   tgs_bin        GLOBAL: one (tile, depth) key per Gaussian-tile entry and a
+ *                  device radix sort (the baseline's globally sorted stream);
+ *                  BINNED: robust depth range (supplement, Algorithm
+ *                  "Robust depth-range estimation"), tile-local log-depth bins
+ *                  by count / exclusive scan / scatter (Algorithm "Tile-local
+ *                  bin construction") and exact repair of the (tile, bin)
+ *                  segments (section "Repair for correctness", Algorithm
+ *                  "Selective repair selection and local exact sorting").
+ *   tgs_rasterize  front-to-back alpha compositing of each tile's one
+ *                  contiguous range (Algorithm "Binned raster traversal after
+ *                  repair").
+ *
+ * Conventions
+ *  - Pointers named *_dev are device pointers (hipMalloc'd or torch CUDA
+ *    tensors); everything else is host memory. The caller owns every buffer,
+ *    including the workspace; the library never allocates or frees device
+ *    memory.
+ *  - Every call enqueues on `stream` (a hipStream_t, NULL = default stream)
+ *    and returns without waiting, except tgs_bin with a non-NULL
+ *    num_entries_host, which waits for the entry count.
+ *  - Arguments are validated on the host before anything is launched; on an
+ *    error nothing is enqueued and outputs are untouched. tgs_last_error()
+ *    returns a message for the last failing call on the calling thread.
+ *  - Per-Gaussian invalid data (non-finite values, a zero quaternion, depth
+ *    outside (znear, zfar), a singular screen covariance, opacity < 1/255) is
+ *    not an error: that Gaussian is invisible (empty rect).
+ *  - Limits: 0 <= n < 2^31, sh_degree 0..3, width and height 1..16384,
+ *    tile_size 16, 1 <= num_bins <= 1024, 0 < znear < zfar, entries < 2^32.
+ */
+#ifndef TILEGS_H
+#define TILEGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TGS_API __attribute__((visibility("default")))
+
+typedef enum {
+    TGS_OK = 0,
+    TGS_ERR_INVALID_ARG = 1,
+    TGS_ERR_CAPACITY = 2,    /* more entries than the binned buffers hold */
+    TGS_ERR_HIP = 3,         /* a HIP runtime call or launch failed */
+    TGS_ERR_UNSUPPORTED = 4, /* a valid but unimplemented option */
+    TGS_ERR_WORKSPACE = 5    /* workspace missing or smaller than required */
+} tgs_status;
+
+/* Orders of the entry stream. */
+enum { TGS_ORDER_GLOBAL = 0, TGS_ORDER_BINNED = 1 };
+/* Raster kernels. PLAIN: one 256-lane workgroup per tile walks shared
+   batches gathered by Gaussian id (the baseline's kernel structure). WAVE:
+   each 64-lane wavefront owns an 8x8 pixel block, streams the tile's range,
+   drops entries that provably cannot reach alpha 1/255 anywhere in its block
+   and exits on its own. Both produce bit-identical images. */
+enum { TGS_RASTER_PLAIN = 0, TGS_RASTER_WAVE = 1 };
+
+/* Pinhole camera, host struct. p_cam = R p_world + t, R row-major, image x
+   right, y down, z forward; pixel (i, j) is sampled at (i + 0.5, j + 0.5). */
+typedef struct {
+    double R[9];
+    double t[3];
+    double fx, fy, cx, cy;
+    int32_t width, height;
+    double znear, zfar;
+} tgs_camera;
+
+/* Gaussians, device pointers, fp32:
+   means [n][3]; log_scales [n][3]; quats [n][4] as (w, x, y, z), need not be
+   normalised; logits [n] (opacity = sigmoid(logit)); sh [n][(D+1)^2][3] real
+   SH coefficients in the order l*l + l + m, m = -l..l. */
+typedef struct {
+    const float* means_dev;
+    const float* log_scales_dev;
+    const float* quats_dev;
+    const float* logits_dev;
+    const float* sh_dev;
+    int64_t n;
+    int32_t sh_degree;
+} tgs_gaussians;
+
+/* Projected Gaussians, device pointers (written by tgs_project, read by
+   tgs_bin and tgs_rasterize; callers may also fill them directly):
+   splats [n][12] fp32: mean_x, mean_y (binary32 rounding of the pixel-space
+       mean), mean_x_lo, mean_y_lo (the remainders, so hi + lo is the mean to
+       about 1e-11 px), conic_a, conic_b, conic_c (inverse screen covariance,
+       q = a dx^2 + 2 b dx dy + c dy^2), opacity, r, g, b, 0.
+   info [n][4] uint32: depth (binary32 bits of the camera-space z, the
+       ordering key), x0 | y0 << 16, x1 | y1 << 16 (half-open tile rect),
+       number of tiles (x1 - x0) * (y1 - y0); an empty rect = invisible. */
+typedef struct {
+    float* splats_dev;
+    uint32_t* info_dev;
+    int64_t n;
+} tgs_projected;
+
+/* Ordering and raster options (tgs_default_params fills the paper's values). */
+typedef struct {
+    int32_t tile_size;    /* 16 */
+    int32_t num_bins;     /* K, 64 */
+    int32_t sample_count; /* depth-range samples, 8192 */
+    float p_lo, p_hi;     /* depth-range percentiles, 1 and 99 */
+    float pad;            /* depth-range padding fraction, 0.05 */
+    int32_t raster;       /* TGS_RASTER_* */
+    int32_t packed;       /* 1: BINNED order also writes per-entry records and
+                             the raster reads them instead of gathering */
+} tgs_params;
+
+/* Entry buffers written by tgs_bin and read by tgs_rasterize. All device
+   pointers; sized for `capacity` entries, T = tiles_x * tiles_y tiles.
+   GLOBAL order: keys [capacity] (tile << 32 | depth bits, sorted),
+       vals [capacity] (Gaussian ids in that order), offsets [T + 1].
+   BINNED order: pairs [capacity] (depth bits << 32 | id in tile-bin-major
+       order, every (tile, bin) segment sorted), offsets [T * K + 1] (bin
+       offsets, tile-major), records [capacity][12] when params.packed (the
+       splat of each entry with its mean relative to the entry's tile
+       origin: mx - 16 tx, my - 16 ty, a, b, c, opacity, r, g, b, id bits,
+       0, 0), zrange [2] (the depth range).
+   counters [4] int64: entries M, visible Gaussians V, overflow flag (1 when
+       M > capacity: the stream was truncated and tgs_rasterize writes NaN),
+       reserved. */
+typedef struct {
+    int64_t capacity;
+    uint64_t* keys_dev;
+    uint32_t* vals_dev;
+    uint64_t* pairs_dev;
+    uint32_t* offsets_dev;
+    float* records_dev;
+    float* zrange_dev;
+    int64_t* counters_dev;
+} tgs_binned;
+
+/* Fills the paper's defaults (16 px tiles, K = 64, S = 8192, 1st / 99th
+   percentiles, 5 % pad), the WAVE raster and packed records. */
+TGS_API void tgs_default_params(tgs_params* params);
+
+/* Projection + SH colour + opacity-aware tile rect for every Gaussian. The
+   geometry is evaluated in binary64 and rounded once to the fp32 outputs;
+   the depth key is the binary32 rounding of ((R20 x + R21 y) + R22 z) + t2
+   evaluated in binary64 without contraction. */
+TGS_API tgs_status tgs_project(const tgs_gaussians* gaussians, const tgs_camera* camera,
+                       const tgs_params* params, tgs_projected* out, void* stream);
+
+/* Workspace bytes tgs_bin needs for n Gaussians, `capacity` entries, this
+   camera, params and order. */
+TGS_API size_t tgs_bin_workspace_size(int64_t n, int64_t capacity, const tgs_camera* camera,
+                              const tgs_params* params, int32_t order);
+
+/* Builds the entry stream of `order`. num_entries_host: NULL = no host
+   synchronisation (an overflow is only reported through counters[2]);
+   non-NULL = wait for the entry count, store it there, and return
+   TGS_ERR_CAPACITY without building the stream when it exceeds capacity.
+   The GLOBAL order always synchronises (the radix sort needs the count). */
+TGS_API tgs_status tgs_bin(const tgs_projected* projected, const tgs_camera* camera,
+                   const tgs_params* params, int32_t order, void* workspace_dev,
+                   size_t workspace_bytes, tgs_binned* out, int64_t* num_entries_host,
+                   void* stream);
+
+/* Composites every pixel front to back over its tile's range. bg: host
+   float[3]. Outputs (device): rgb [H][W][3], alpha [H][W] (= 1 - final
+   transmittance), last [H][W] int32 stream position of the last composited
+   entry or -1. Optional counters (NULL to skip; any non-NULL selects the
+   instrumented kernel instance): n_contrib [H][W] composited entries,
+   n_visit [H][W] entries the pixel evaluated before it stopped, n_support
+   [H][W] evaluated entries with alpha >= 1/255 (including the one that
+   stopped the pixel). */
+TGS_API tgs_status tgs_rasterize(const tgs_projected* projected, const tgs_binned* binned,
+                         const tgs_camera* camera, const tgs_params* params, int32_t order,
+                         const float* bg, float* rgb_dev, float* alpha_dev, int32_t* last_dev,
+                         int32_t* n_contrib_dev, int32_t* n_visit_dev, int32_t* n_support_dev,
+                         void* stream);
+
+/* Message for the last failing call on this thread ("" if none). */
+TGS_API const char* tgs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TILEGS_H */

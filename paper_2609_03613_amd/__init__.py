@@ -1,0 +1,8 @@
+"""MI355X (gfx950) tile-local depth-binned 3D Gaussian splatting rasterizer.
+
+The compute path is the HIP library ``libtilegs.so`` behind the C ABI in
+``include/tilegs.h``; this package only marshals arguments to it.
+"""
+from ._lib import (ORDER_BINNED, ORDER_GLOBAL, RASTER_PLAIN, RASTER_WAVE, TileGSError,  # noqa: F401
+                   LIB_PATH, EXPORTS, lib)
+from .api import Binned, Params, Renderer, camera_struct, project, render, to_device  # noqa: F401

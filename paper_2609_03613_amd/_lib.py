@@ -1,0 +1,90 @@
+"""ctypes binding of ``libtilegs.so`` (argument marshalling only).
+
+The structs mirror ``include/tilegs.h`` field by field. The library is loaded
+from this package directory; if it is missing the import of the library
+fails loudly (there is no fallback path).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtilegs.so")
+
+TGS_OK, TGS_ERR_INVALID_ARG, TGS_ERR_CAPACITY, TGS_ERR_HIP, TGS_ERR_UNSUPPORTED, TGS_ERR_WORKSPACE = range(6)
+ORDER_GLOBAL, ORDER_BINNED = 0, 1
+RASTER_PLAIN, RASTER_WAVE = 0, 1
+
+EXPORTS = ("tgs_default_params", "tgs_project", "tgs_bin_workspace_size", "tgs_bin", "tgs_rasterize",
+           "tgs_last_error")
+
+_c_p = ctypes.c_void_p
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_double * 9), ("t", ctypes.c_double * 3), ("fx", ctypes.c_double),
+                ("fy", ctypes.c_double), ("cx", ctypes.c_double), ("cy", ctypes.c_double),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32), ("znear", ctypes.c_double),
+                ("zfar", ctypes.c_double)]
+
+
+class Gaussians(ctypes.Structure):
+    _fields_ = [("means", _c_p), ("log_scales", _c_p), ("quats", _c_p), ("logits", _c_p), ("sh", _c_p),
+                ("n", ctypes.c_int64), ("sh_degree", ctypes.c_int32)]
+
+
+class Projected(ctypes.Structure):
+    _fields_ = [("splats", _c_p), ("info", _c_p), ("n", ctypes.c_int64)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("tile_size", ctypes.c_int32), ("num_bins", ctypes.c_int32), ("sample_count", ctypes.c_int32),
+                ("p_lo", ctypes.c_float), ("p_hi", ctypes.c_float), ("pad", ctypes.c_float),
+                ("raster", ctypes.c_int32), ("packed", ctypes.c_int32)]
+
+
+class Binned(ctypes.Structure):
+    _fields_ = [("capacity", ctypes.c_int64), ("keys", _c_p), ("vals", _c_p), ("pairs", _c_p),
+                ("offsets", _c_p), ("records", _c_p), ("zrange", _c_p), ("counters", _c_p)]
+
+
+class TileGSError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"tilegs status {status}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
+                              f"python -m paper_2609_03613_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER
+        L.tgs_default_params.argtypes = [P(Params)]
+        L.tgs_default_params.restype = None
+        L.tgs_project.argtypes = [P(Gaussians), P(Camera), P(Params), P(Projected), _c_p]
+        L.tgs_project.restype = ctypes.c_int
+        L.tgs_bin_workspace_size.argtypes = [ctypes.c_int64, ctypes.c_int64, P(Camera), P(Params), ctypes.c_int32]
+        L.tgs_bin_workspace_size.restype = ctypes.c_size_t
+        L.tgs_bin.argtypes = [P(Projected), P(Camera), P(Params), ctypes.c_int32, _c_p, ctypes.c_size_t, P(Binned),
+                              P(ctypes.c_int64), _c_p]
+        L.tgs_bin.restype = ctypes.c_int
+        L.tgs_rasterize.argtypes = [P(Projected), P(Binned), P(Camera), P(Params), ctypes.c_int32,
+                                    P(ctypes.c_float), _c_p, _c_p, _c_p, _c_p, _c_p, _c_p, _c_p]
+        L.tgs_rasterize.restype = ctypes.c_int
+        L.tgs_last_error.argtypes = []
+        L.tgs_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def check(status):
+    if status != TGS_OK:
+        raise TileGSError(status, lib().tgs_last_error().decode())
+    return status

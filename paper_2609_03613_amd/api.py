@@ -1,0 +1,197 @@
+"""Python entry points over the C ABI. PyTorch provides device memory and the
+current HIP stream; every step of the path runs in the library's kernels.
+
+Typical use::
+
+    r = Renderer(camera_dict, params)
+    out = r.render(gaussians, order="binned")   # dict of device tensors
+
+``gaussians`` is a dict of CUDA tensors (means, log_scales, quats, logits, sh)
+plus ``sh_degree``, in the layout of ``include/tilegs.h``.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as L
+
+ORDERS = {"global": L.ORDER_GLOBAL, "binned": L.ORDER_BINNED}
+RASTERS = {"plain": L.RASTER_PLAIN, "wave": L.RASTER_WAVE}
+
+
+@dataclass
+class Params:
+    """Ordering / raster options; defaults are the paper's (K = 64, 8192
+    samples, 1st / 99th percentiles, 5 % pad) with the wave raster and packed
+    records."""
+    tile_size: int = 16
+    num_bins: int = 64
+    sample_count: int = 8192
+    p_lo: float = 1.0
+    p_hi: float = 99.0
+    pad: float = 0.05
+    raster: str = "wave"
+    packed: bool = True
+
+    def c(self):
+        return L.Params(self.tile_size, self.num_bins, self.sample_count, self.p_lo, self.p_hi, self.pad,
+                        RASTERS[self.raster], int(bool(self.packed)))
+
+
+def camera_struct(cam):
+    c = L.Camera()
+    R = [float(v) for v in torch.as_tensor(cam["R"], dtype=torch.float64).reshape(9).tolist()]
+    t = [float(v) for v in torch.as_tensor(cam["t"], dtype=torch.float64).reshape(3).tolist()]
+    c.R = (ctypes.c_double * 9)(*R)
+    c.t = (ctypes.c_double * 3)(*t)
+    c.fx, c.fy, c.cx, c.cy = float(cam["fx"]), float(cam["fy"]), float(cam["cx"]), float(cam["cy"])
+    c.width, c.height = int(cam["width"]), int(cam["height"])
+    c.znear, c.zfar = float(cam.get("znear", 0.01)), float(cam.get("zfar", 1e10))
+    return c
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def to_device(g, device="cuda"):
+    """numpy scene dict (scenes.py) -> dict of contiguous CUDA tensors."""
+    out = {k: torch.as_tensor(v).to(device).contiguous() for k, v in g.items() if k != "sh_degree"}
+    out["sh_degree"] = int(g["sh_degree"])
+    return out
+
+
+def project(g, cam, params=None):
+    """tgs_project: returns (splats [n, 12] float32, info [n, 4] int32)."""
+    params = params or Params()
+    n = int(g["means"].shape[0])
+    dev = g["means"].device
+    splats = torch.empty((n, 12), dtype=torch.float32, device=dev)
+    info = torch.empty((n, 4), dtype=torch.int32, device=dev)
+    gs = L.Gaussians(_ptr(g["means"]).value, _ptr(g["log_scales"]).value, _ptr(g["quats"]).value,
+                     _ptr(g["logits"]).value, _ptr(g["sh"]).value, n, int(g["sh_degree"]))
+    pr = L.Projected(_ptr(splats).value, _ptr(info).value, n)
+    L.check(L.lib().tgs_project(ctypes.byref(gs), ctypes.byref(camera_struct(cam)), ctypes.byref(params.c()),
+                                ctypes.byref(pr), _stream()))
+    return splats, info
+
+
+class Binned:
+    """Device buffers of one entry stream (see tgs_binned)."""
+
+    def __init__(self, order, capacity, tiles, num_bins, packed, device):
+        self.order = ORDERS[order] if isinstance(order, str) else order
+        self.capacity = int(capacity)
+        cap = max(self.capacity, 1)
+        kw = dict(device=device)
+        self.counters = torch.zeros(4, dtype=torch.int64, **kw)
+        self.zrange = torch.zeros(2, dtype=torch.float32, **kw)
+        self.keys = self.vals = self.pairs = self.records = None
+        if self.order == L.ORDER_GLOBAL:
+            self.keys = torch.empty(cap, dtype=torch.int64, **kw)
+            self.vals = torch.empty(cap, dtype=torch.int32, **kw)
+            self.offsets = torch.empty(tiles + 1, dtype=torch.int32, **kw)
+        else:
+            self.pairs = torch.empty(cap, dtype=torch.int64, **kw)
+            self.offsets = torch.empty(tiles * num_bins + 1, dtype=torch.int32, **kw)
+            if packed:
+                self.records = torch.empty((cap, 12), dtype=torch.float32, **kw)
+        self.num_entries = None
+
+    def c(self):
+        return L.Binned(self.capacity, _ptr(self.keys).value, _ptr(self.vals).value, _ptr(self.pairs).value,
+                        _ptr(self.offsets).value, _ptr(self.records).value, _ptr(self.zrange).value,
+                        _ptr(self.counters).value)
+
+
+class Renderer:
+    """Holds a camera, options, workspace and entry buffers (grown on demand)."""
+
+    def __init__(self, cam, params=None, device="cuda"):
+        self.cam = cam
+        self.params = params or Params()
+        self.ccam = camera_struct(cam)
+        self.cparams = self.params.c()
+        self.device = device
+        self.tiles_x = (int(cam["width"]) + 15) // 16
+        self.tiles_y = (int(cam["height"]) + 15) // 16
+        self.tiles = self.tiles_x * self.tiles_y
+        self._binned = {}
+        self._ws = {}
+
+    def _workspace(self, order, n, capacity):
+        need = L.lib().tgs_bin_workspace_size(n, capacity, ctypes.byref(self.ccam), ctypes.byref(self.cparams),
+                                              order)
+        ws = self._ws.get(order)
+        if ws is None or ws.numel() < need:
+            ws = torch.empty(max(need, 256), dtype=torch.uint8, device=self.device)
+            self._ws[order] = ws
+        return ws
+
+    def bin(self, splats, info, order="binned", capacity=None, sync=True):
+        """tgs_bin. With sync, the entry count is read back and the buffers are
+        grown (and the call repeated) when it exceeds their capacity."""
+        o = ORDERS[order] if isinstance(order, str) else order
+        n = int(splats.shape[0])
+        pr = L.Projected(_ptr(splats).value, _ptr(info).value, n)
+        b = self._binned.get(o)
+        if b is None or (capacity is not None and b.capacity < capacity):
+            b = Binned(o, capacity if capacity is not None else max(1024, 4 * n), self.tiles,
+                       self.params.num_bins, self.params.packed, self.device)
+            self._binned[o] = b
+        for _ in range(2):
+            ws = self._workspace(o, n, b.capacity)
+            m = ctypes.c_int64(-1)
+            st = L.lib().tgs_bin(ctypes.byref(pr), ctypes.byref(self.ccam), ctypes.byref(self.cparams), o,
+                                 _ptr(ws), ws.numel(), ctypes.byref(b.c()),
+                                 ctypes.byref(m) if sync else None, _stream())
+            if st == L.TGS_ERR_CAPACITY:
+                b = Binned(o, int(m.value * 1.1) + 1024, self.tiles, self.params.num_bins, self.params.packed,
+                           self.device)
+                self._binned[o] = b
+                continue
+            L.check(st)
+            b.num_entries = int(m.value) if sync else None
+            return b
+        raise L.TileGSError(L.TGS_ERR_CAPACITY, "capacity still exceeded after growing")
+
+    def rasterize(self, splats, info, binned, bg=(0.0, 0.0, 0.0), counts=False, out=None):
+        """tgs_rasterize: dict with rgb [H, W, 3], alpha [H, W], last [H, W]
+        (and n_contrib, n_visit, n_support when counts)."""
+        H, W = int(self.cam["height"]), int(self.cam["width"])
+        if out is None:
+            out = {
+                "rgb": torch.empty((H, W, 3), dtype=torch.float32, device=self.device),
+                "alpha": torch.empty((H, W), dtype=torch.float32, device=self.device),
+                "last": torch.empty((H, W), dtype=torch.int32, device=self.device),
+            }
+            if counts:
+                out["n_contrib"] = torch.empty((H, W), dtype=torch.int32, device=self.device)
+                out["n_visit"] = torch.empty((H, W), dtype=torch.int32, device=self.device)
+                out["n_support"] = torch.empty((H, W), dtype=torch.int32, device=self.device)
+        n = int(splats.shape[0])
+        pr = L.Projected(_ptr(splats).value, _ptr(info).value, n)
+        bgc = (ctypes.c_float * 3)(*[float(v) for v in bg])
+        L.check(L.lib().tgs_rasterize(ctypes.byref(pr), ctypes.byref(binned.c()), ctypes.byref(self.ccam),
+                                      ctypes.byref(self.cparams), binned.order, bgc, _ptr(out["rgb"]),
+                                      _ptr(out["alpha"]), _ptr(out["last"]), _ptr(out.get("n_contrib")),
+                                      _ptr(out.get("n_visit")), _ptr(out.get("n_support")), _stream()))
+        return out
+
+    def render(self, g, order="binned", bg=(0.0, 0.0, 0.0), counts=False):
+        splats, info = project(g, self.cam, self.params)
+        b = self.bin(splats, info, order)
+        out = self.rasterize(splats, info, b, bg=bg, counts=counts)
+        out["splats"], out["info"], out["binned"] = splats, info, b
+        return out
+
+
+def render(g, cam, params=None, order="binned", bg=(0.0, 0.0, 0.0), counts=False):
+    return Renderer(cam, params, device=g["means"].device).render(g, order=order, bg=bg, counts=counts)

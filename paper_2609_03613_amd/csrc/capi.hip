@@ -1,0 +1,283 @@
+// C ABI: argument validation, workspace layout and the launch sequences of
+// tgs_project / tgs_bin / tgs_rasterize.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+
+#include "common.hpp"
+
+using namespace tgs;
+
+namespace {
+
+thread_local std::string g_err;
+
+tgs_status fail(tgs_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+tgs_status fail(tgs_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+tgs_status hip_fail(hipError_t e, const char* where) {
+    return fail(TGS_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+#define TGS_HIP(call, where)                      \
+    do {                                          \
+        hipError_t e_ = (call);                   \
+        if (e_ != hipSuccess) return hip_fail(e_, where); \
+    } while (0)
+
+tgs_status check_camera(const tgs_camera* c) {
+    if (!c) return fail(TGS_ERR_INVALID_ARG, "camera is NULL");
+    if (c->width < 1 || c->width > 16384 || c->height < 1 || c->height > 16384)
+        return fail(TGS_ERR_INVALID_ARG, "image size %dx%d outside 1..16384", c->width, c->height);
+    if (!(c->znear > 0.0) || !(c->zfar > c->znear) || !isfinite(c->znear))
+        return fail(TGS_ERR_INVALID_ARG, "need 0 < znear < zfar (got %g, %g)", c->znear, c->zfar);
+    if (!(c->fx > 0.0) || !(c->fy > 0.0) || !isfinite(c->fx) || !isfinite(c->fy))
+        return fail(TGS_ERR_INVALID_ARG, "focal lengths must be positive and finite");
+    for (int i = 0; i < 9; ++i)
+        if (!isfinite(c->R[i])) return fail(TGS_ERR_INVALID_ARG, "camera rotation is not finite");
+    for (int i = 0; i < 3; ++i)
+        if (!isfinite(c->t[i])) return fail(TGS_ERR_INVALID_ARG, "camera translation is not finite");
+    if (!isfinite(c->cx) || !isfinite(c->cy)) return fail(TGS_ERR_INVALID_ARG, "principal point is not finite");
+    return TGS_OK;
+}
+
+tgs_status check_params(const tgs_params* p) {
+    if (!p) return fail(TGS_ERR_INVALID_ARG, "params is NULL");
+    if (p->tile_size != kTile) return fail(TGS_ERR_UNSUPPORTED, "tile_size %d (only 16 is implemented)", p->tile_size);
+    if (p->num_bins < 1 || p->num_bins > 1024) return fail(TGS_ERR_INVALID_ARG, "num_bins %d outside 1..1024", p->num_bins);
+    if (p->sample_count < 1 || p->sample_count > 8192)
+        return fail(TGS_ERR_INVALID_ARG, "sample_count %d outside 1..8192", p->sample_count);
+    if (!(p->p_lo >= 0.f && p->p_lo <= p->p_hi && p->p_hi <= 100.f))
+        return fail(TGS_ERR_INVALID_ARG, "need 0 <= p_lo <= p_hi <= 100");
+    if (!(p->pad >= 0.f) || !isfinite(p->pad)) return fail(TGS_ERR_INVALID_ARG, "pad must be >= 0");
+    if (p->raster != TGS_RASTER_PLAIN && p->raster != TGS_RASTER_WAVE)
+        return fail(TGS_ERR_INVALID_ARG, "unknown raster %d", p->raster);
+    return TGS_OK;
+}
+
+tgs_status check_projected(const tgs_projected* pr) {
+    if (!pr) return fail(TGS_ERR_INVALID_ARG, "projected is NULL");
+    if (pr->n < 0 || pr->n >= (int64_t)1 << 31) return fail(TGS_ERR_INVALID_ARG, "n = %lld outside 0..2^31-1", (long long)pr->n);
+    if (pr->n > 0 && (!pr->splats_dev || !pr->info_dev)) return fail(TGS_ERR_INVALID_ARG, "projected buffers are NULL");
+    return TGS_OK;
+}
+
+inline size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct Layout {
+    size_t emit_off, scan_tmp, sample, count, entry_rank, seg_lists, bucket_count, keys_in, vals_in, sort_tmp,
+        sort_tmp_bytes, total;
+};
+
+int end_bit_for(int64_t T) {
+    int b = 0;
+    while (((int64_t)1 << b) < T) ++b;
+    return 32 + (b > 0 ? b : 1);
+}
+
+Layout layout(int64_t n, int64_t capacity, int64_t T, int K, int order) {
+    Layout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off = align_up(off + bytes);
+        return at;
+    };
+    const int64_t nseg = T * K;
+    const int64_t scan_n = n > nseg ? n : nseg;
+    L.emit_off = take(sizeof(uint32_t) * (size_t)(n + 1));
+    L.scan_tmp = take(sizeof(uint32_t) * scan_tmp_words(scan_n));
+    L.sample = take(sizeof(uint32_t) * 8192);
+    if (order == TGS_ORDER_BINNED) {
+        L.count = take(sizeof(uint32_t) * (size_t)nseg);
+        L.entry_rank = take(sizeof(uint32_t) * (size_t)capacity);
+        L.seg_lists = take(sizeof(uint32_t) * (size_t)kBuckets * (size_t)nseg);
+        L.bucket_count = take(sizeof(uint32_t) * 64);
+    } else {
+        L.keys_in = take(sizeof(uint64_t) * (size_t)capacity);
+        L.vals_in = take(sizeof(uint32_t) * (size_t)capacity);
+        L.sort_tmp_bytes = global_sort_tmp_bytes(capacity, end_bit_for(T)) + 1024;
+        L.sort_tmp = take(L.sort_tmp_bytes);
+    }
+    L.total = off;
+    return L;
+}
+
+int64_t tiles_of(const tgs_camera* c) {
+    return (int64_t)div_up(c->width, kTile) * div_up(c->height, kTile);
+}
+
+}  // namespace
+
+extern "C" {
+
+void tgs_default_params(tgs_params* p) {
+    if (!p) return;
+    p->tile_size = 16;
+    p->num_bins = 64;
+    p->sample_count = 8192;
+    p->p_lo = 1.0f;
+    p->p_hi = 99.0f;
+    p->pad = 0.05f;
+    p->raster = TGS_RASTER_WAVE;
+    p->packed = 1;
+}
+
+const char* tgs_last_error(void) { return g_err.c_str(); }
+
+tgs_status tgs_project(const tgs_gaussians* g, const tgs_camera* cam, const tgs_params* params, tgs_projected* out,
+                       void* stream) {
+    g_err.clear();
+    if (!g) return fail(TGS_ERR_INVALID_ARG, "gaussians is NULL");
+    if (g->n < 0 || g->n >= (int64_t)1 << 31) return fail(TGS_ERR_INVALID_ARG, "n = %lld outside 0..2^31-1", (long long)g->n);
+    if (g->sh_degree < 0 || g->sh_degree > 3) return fail(TGS_ERR_INVALID_ARG, "sh_degree %d outside 0..3", g->sh_degree);
+    if (g->n > 0 && (!g->means_dev || !g->log_scales_dev || !g->quats_dev || !g->logits_dev || !g->sh_dev))
+        return fail(TGS_ERR_INVALID_ARG, "a Gaussian attribute pointer is NULL");
+    tgs_status st = check_camera(cam);
+    if (st) return st;
+    if ((st = check_params(params))) return st;
+    if (!out || out->n != g->n) return fail(TGS_ERR_INVALID_ARG, "projected output missing or n mismatch");
+    if (g->n > 0 && (!out->splats_dev || !out->info_dev)) return fail(TGS_ERR_INVALID_ARG, "projected buffers are NULL");
+    TGS_HIP(launch_project(*g, make_cam(*cam), out->splats_dev, out->info_dev, (hipStream_t)stream), "project");
+    return TGS_OK;
+}
+
+size_t tgs_bin_workspace_size(int64_t n, int64_t capacity, const tgs_camera* cam, const tgs_params* params,
+                              int32_t order) {
+    if (!cam || !params || n < 0 || capacity < 0) return 0;
+    if (cam->width < 1 || cam->height < 1 || params->num_bins < 1) return 0;
+    return layout(n, capacity, tiles_of(cam), params->num_bins, order).total;
+}
+
+tgs_status tgs_bin(const tgs_projected* pr, const tgs_camera* cam, const tgs_params* params, int32_t order, void* ws,
+                   size_t ws_bytes, tgs_binned* out, int64_t* num_entries_host, void* stream) {
+    g_err.clear();
+    tgs_status st = check_projected(pr);
+    if (st) return st;
+    if ((st = check_camera(cam))) return st;
+    if ((st = check_params(params))) return st;
+    if (order != TGS_ORDER_GLOBAL && order != TGS_ORDER_BINNED) return fail(TGS_ERR_INVALID_ARG, "unknown order %d", order);
+    if (!out) return fail(TGS_ERR_INVALID_ARG, "binned output is NULL");
+    if (out->capacity < 0 || out->capacity >= ((int64_t)1 << 32)) return fail(TGS_ERR_INVALID_ARG, "capacity outside 0..2^32-1");
+    if (!out->counters_dev || !out->offsets_dev) return fail(TGS_ERR_INVALID_ARG, "counters or offsets is NULL");
+    const int64_t n = pr->n, cap = out->capacity, T = tiles_of(cam);
+    const int K = params->num_bins;
+    if (order == TGS_ORDER_BINNED) {
+        if (!out->zrange_dev || (cap > 0 && !out->pairs_dev)) return fail(TGS_ERR_INVALID_ARG, "pairs or zrange is NULL");
+        if (params->packed && cap > 0 && !out->records_dev) return fail(TGS_ERR_INVALID_ARG, "records is NULL with packed=1");
+        if (T * K >= ((int64_t)1 << 31)) return fail(TGS_ERR_INVALID_ARG, "tiles * bins too large");
+    } else if (cap > 0 && (!out->keys_dev || !out->vals_dev)) {
+        return fail(TGS_ERR_INVALID_ARG, "keys or vals is NULL");
+    }
+    const Layout L = layout(n, cap, T, K, order);
+    if (!ws || ws_bytes < L.total)
+        return fail(TGS_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
+    hipStream_t s = (hipStream_t)stream;
+    char* w = (char*)ws;
+    uint32_t* emit_off = (uint32_t*)(w + L.emit_off);
+    uint32_t* tmp = (uint32_t*)(w + L.scan_tmp);
+    uint32_t* sample = (uint32_t*)(w + L.sample);
+    const int S = params->sample_count;
+
+    const int tiles_x = div_up(cam->width, kTile), tiles_y = div_up(cam->height, kTile);
+    TGS_HIP(launch_emit_scan(pr->info_dev, n, tiles_x, tiles_y, emit_off, tmp, out->counters_dev, cap, sample, S, s),
+            "emit scan");
+    int64_t M = -1;
+    if (num_entries_host || order == TGS_ORDER_GLOBAL) {
+        TGS_HIP(hipMemcpyAsync(&M, out->counters_dev, sizeof(int64_t), hipMemcpyDeviceToHost, s), "read entry count");
+        TGS_HIP(hipStreamSynchronize(s), "read entry count");
+        if (num_entries_host) *num_entries_host = M;
+        if (M > cap) return fail(TGS_ERR_CAPACITY, "%lld entries exceed the capacity %lld", (long long)M, (long long)cap);
+    }
+    if (order == TGS_ORDER_GLOBAL) {
+        uint64_t* keys_in = (uint64_t*)(w + L.keys_in);
+        uint32_t* vals_in = (uint32_t*)(w + L.vals_in);
+        TGS_HIP(launch_emit_keys(pr->info_dev, n, emit_off, tiles_x, tiles_y, keys_in, vals_in, cap, s), "emit keys");
+        TGS_HIP(launch_global_sort(w + L.sort_tmp, L.sort_tmp_bytes, keys_in, out->keys_dev, vals_in, out->vals_dev, M,
+                                   end_bit_for(T), s),
+                "radix sort");
+        TGS_HIP(launch_tile_ranges(out->keys_dev, M, T, out->offsets_dev, s), "tile ranges");
+        return TGS_OK;
+    }
+    uint32_t* count = (uint32_t*)(w + L.count);
+    uint32_t* entry_rank = (uint32_t*)(w + L.entry_rank);
+    uint32_t* seg_lists = (uint32_t*)(w + L.seg_lists);
+    uint32_t* bucket_count = (uint32_t*)(w + L.bucket_count);
+    const int64_t nseg = T * K;
+    TGS_HIP(launch_depth_range(sample, out->counters_dev, S, params->p_lo, params->p_hi, params->pad, (float)cam->znear,
+                               (float)cam->zfar, out->zrange_dev, s),
+            "depth range");
+    TGS_HIP(launch_fill_u32(count, 0u, nseg, s), "clear counts");
+    TGS_HIP(launch_bin_count(pr->info_dev, n, emit_off, out->zrange_dev, K, tiles_x, tiles_y, count, entry_rank, cap, s),
+            "bin count");
+    TGS_HIP(launch_scan_u32(count, out->offsets_dev, nseg, tmp, out->offsets_dev + nseg, s), "bin offsets");
+    TGS_HIP(launch_bin_scatter(pr->info_dev, n, emit_off, out->zrange_dev, K, tiles_x, tiles_y, out->offsets_dev,
+                               entry_rank, out->pairs_dev, cap, s),
+            "bin scatter");
+    TGS_HIP(launch_repair(out->offsets_dev, nseg, out->pairs_dev, seg_lists, bucket_count, out->counters_dev, s),
+            "repair");
+    if (params->packed)
+        TGS_HIP(launch_pack(out->pairs_dev, out->offsets_dev, K, tiles_x, T, pr->splats_dev, out->records_dev,
+                            out->counters_dev, cap, s),
+                "pack");
+    return TGS_OK;
+}
+
+tgs_status tgs_rasterize(const tgs_projected* pr, const tgs_binned* b, const tgs_camera* cam, const tgs_params* params,
+                         int32_t order, const float* bg, float* rgb, float* alpha, int32_t* last, int32_t* n_contrib,
+                         int32_t* n_visit, int32_t* n_support, void* stream) {
+    g_err.clear();
+    tgs_status st = check_projected(pr);
+    if (st) return st;
+    if ((st = check_camera(cam))) return st;
+    if ((st = check_params(params))) return st;
+    if (order != TGS_ORDER_GLOBAL && order != TGS_ORDER_BINNED) return fail(TGS_ERR_INVALID_ARG, "unknown order %d", order);
+    if (!b || !b->offsets_dev || !b->counters_dev) return fail(TGS_ERR_INVALID_ARG, "binned buffers are NULL");
+    if (!bg || !rgb || !alpha || !last) return fail(TGS_ERR_INVALID_ARG, "an output pointer is NULL");
+    RasterArgs a{};
+    a.splats = pr->splats_dev;
+    a.offsets = b->offsets_dev;
+    a.counters = b->counters_dev;
+    if (order == TGS_ORDER_GLOBAL) {
+        a.stride = 1;
+        a.vals = b->vals_dev;
+        if (!a.vals && b->capacity > 0) return fail(TGS_ERR_INVALID_ARG, "vals is NULL");
+    } else {
+        a.stride = params->num_bins;
+        a.pairs = b->pairs_dev;
+        a.records = params->packed ? b->records_dev : nullptr;
+        if (b->capacity > 0 && !a.pairs) return fail(TGS_ERR_INVALID_ARG, "pairs is NULL");
+        if (params->packed && b->capacity > 0 && !a.records) return fail(TGS_ERR_INVALID_ARG, "records is NULL");
+    }
+    if (pr->n > 0 && !a.splats && !a.records) return fail(TGS_ERR_INVALID_ARG, "splats is NULL");
+    a.width = cam->width;
+    a.height = cam->height;
+    a.tiles_x = div_up(cam->width, kTile);
+    a.tiles_y = div_up(cam->height, kTile);
+    for (int i = 0; i < 3; ++i) a.bg[i] = bg[i];
+    a.rgb = rgb;
+    a.alpha = alpha;
+    a.last = last;
+    a.n_contrib = n_contrib;
+    a.n_visit = n_visit;
+    a.n_support = n_support;
+    hipStream_t s = (hipStream_t)stream;
+    if (params->raster == TGS_RASTER_PLAIN)
+        TGS_HIP(launch_raster_plain(a, s), "raster");
+    else
+        TGS_HIP(launch_raster_wave(a, s), "raster");
+    return TGS_OK;
+}
+
+}  // extern "C"

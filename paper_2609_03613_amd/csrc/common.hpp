@@ -1,0 +1,153 @@
+// Shared device helpers and the internal host interface of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tilegs.h"
+
+namespace tgs {
+
+constexpr int kWave = 64;
+constexpr int kTile = 16;          // tile edge in pixels
+constexpr int kSplatWords = 12;    // fp32 words per splat / packed record
+constexpr int kInfoWords = 4;
+
+// Fixed thresholds of the 3DGS image model.
+constexpr float kAlphaMin = 1.0f / 255.0f;
+constexpr float kAlphaMax = 0.99f;
+constexpr float kTMin = 1e-4f;
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+__device__ __forceinline__ int lane() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0)); }
+
+// Number of set bits of `mask` below the calling lane.
+__device__ __forceinline__ uint32_t rank_in(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));
+}
+
+__device__ __forceinline__ uint32_t shfl_up_u32(uint32_t v, int d) { return (uint32_t)__shfl_up((int)v, d, kWave); }
+__device__ __forceinline__ uint32_t shfl_u32(uint32_t v, int src) { return (uint32_t)__shfl((int)v, src, kWave); }
+__device__ __forceinline__ uint32_t shfl_xor_u32(uint32_t v, int m) { return (uint32_t)__shfl_xor((int)v, m, kWave); }
+
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
+    uint32_t lo = shfl_xor_u32((uint32_t)v, m);
+    uint32_t hi = shfl_xor_u32((uint32_t)(v >> 32), m);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Inclusive prefix sum across the 64 lanes of a wavefront.
+__device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t v) {
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        uint32_t o = shfl_up_u32(v, d);
+        if (lane() >= d) v += o;
+    }
+    return v;
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2). Give each XCD a contiguous run of work items so that neighbouring
+// tiles, which share Gaussians, meet in the same L2.
+__device__ __forceinline__ int xcd_remap(int b, int nblocks) {
+    constexpr int X = 8;
+    int per = nblocks / X, rem = nblocks % X;
+    int x = b % X, k = b / X;
+    return x * per + (x < rem ? x : rem) + k;
+}
+
+__host__ __device__ __forceinline__ int div_up(int a, int b) { return (a + b - 1) / b; }
+
+// Tile rect of an info record, clipped to the tile grid; returns the number
+// of tiles (0 = invisible). Every stage derives the entries of a Gaussian
+// from this, so a caller-filled rect can never address outside the grid.
+__device__ __forceinline__ int rect_of(const uint4& in, int tiles_x, int tiles_y, int& x0, int& y0, int& x1,
+                                       int& y1) {
+    x0 = min((int)(in.y & 0xFFFFu), tiles_x);
+    y0 = min((int)(in.y >> 16), tiles_y);
+    x1 = min((int)(in.z & 0xFFFFu), tiles_x);
+    y1 = min((int)(in.z >> 16), tiles_y);
+    if (x1 <= x0 || y1 <= y0) return 0;
+    return (x1 - x0) * (y1 - y0);
+}
+
+struct Cam {
+    double R[9], t[3];
+    double fx, fy, cx, cy;
+    double znear, zfar;
+    double campos[3];
+    double lim_xp, lim_xn, lim_yp, lim_yn;
+    int width, height, tiles_x, tiles_y;
+};
+
+Cam make_cam(const tgs_camera& c);
+
+// Launch helpers (host), implemented next to their kernels.
+hipError_t launch_project(const tgs_gaussians& g, const Cam& cam, float* splats, uint32_t* info,
+                          hipStream_t s);
+
+// Exclusive scan of n uint32 values (in may equal out). `total` (device, may
+// be null) receives the sum. tmp needs scan_tmp_words(n) uint32 words.
+size_t scan_tmp_words(int64_t n);
+hipError_t launch_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* tmp, uint32_t* total,
+                           hipStream_t s);
+
+// Entry emission scan over the info array: emit_off[g] = sum of n_tiles
+// before g; counters[0] = M, counters[1] = V (visible); the depth samples
+// for the range estimate are written to sample[] (see the kernel).
+// counters[2] is set to 1 when M exceeds `capacity`; every later stage
+// then skips its writes beyond the buffers.
+hipError_t launch_emit_scan(const uint32_t* info, int64_t n, int tiles_x, int tiles_y, uint32_t* emit_off,
+                            uint32_t* tmp, int64_t* counters, int64_t capacity, uint32_t* sample, int S,
+                            hipStream_t s);
+
+hipError_t launch_depth_range(const uint32_t* sample, const int64_t* counters, int S, float p_lo,
+                              float p_hi, float pad, float znear, float zfar, float* zrange,
+                              hipStream_t s);
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
+
+hipError_t launch_bin_count(const uint32_t* info, int64_t n, const uint32_t* emit_off, const float* zrange,
+                            int K, int tiles_x, int tiles_y, uint32_t* count, uint32_t* entry_rank,
+                            int64_t capacity, hipStream_t s);
+hipError_t launch_bin_scatter(const uint32_t* info, int64_t n, const uint32_t* emit_off, const float* zrange,
+                              int K, int tiles_x, int tiles_y, const uint32_t* bin_off,
+                              const uint32_t* entry_rank, uint64_t* pairs, int64_t capacity, hipStream_t s);
+
+constexpr int kBuckets = 5;
+hipError_t launch_repair(const uint32_t* bin_off, int64_t nseg, uint64_t* pairs, uint32_t* seg_lists,
+                         uint32_t* bucket_count, const int64_t* counters, hipStream_t s);
+
+hipError_t launch_pack(const uint64_t* pairs, const uint32_t* bin_off, int K, int tiles_x, int64_t T,
+                       const float* splats, float* records, const int64_t* counters, int64_t capacity,
+                       hipStream_t s);
+
+hipError_t launch_emit_keys(const uint32_t* info, int64_t n, const uint32_t* emit_off, int tiles_x, int tiles_y,
+                            uint64_t* keys, uint32_t* vals, int64_t capacity, hipStream_t s);
+size_t global_sort_tmp_bytes(int64_t capacity, int end_bit);
+hipError_t launch_global_sort(void* tmp, size_t tmp_bytes, uint64_t* keys_in, uint64_t* keys_out,
+                              uint32_t* vals_in, uint32_t* vals_out, int64_t m, int end_bit, hipStream_t s);
+hipError_t launch_tile_ranges(const uint64_t* keys, int64_t m, int64_t T, uint32_t* tile_off, hipStream_t s);
+
+struct RasterArgs {
+    const float* splats;    // [n][12]
+    const uint32_t* offsets;
+    int stride;             // offsets index step per tile (1 for GLOBAL, K for BINNED)
+    const uint32_t* vals;   // GLOBAL ids
+    const uint64_t* pairs;  // BINNED pairs
+    const float* records;   // BINNED packed records or null
+    const int64_t* counters;
+    int width, height, tiles_x, tiles_y;
+    float bg[3];
+    float* rgb;
+    float* alpha;
+    int32_t* last;
+    int32_t* n_contrib;
+    int32_t* n_visit;
+    int32_t* n_support;
+};
+hipError_t launch_raster_plain(const RasterArgs& a, hipStream_t s);
+hipError_t launch_raster_wave(const RasterArgs& a, hipStream_t s);
+
+}  // namespace tgs

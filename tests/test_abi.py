@@ -1,0 +1,112 @@
+"""The C ABI on the host: the library loads, exports every symbol the header
+declares, and rejects bad arguments before launching anything (these calls
+never reach the GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2609_03613_amd as tg
+from paper_2609_03613_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "tilegs.h")).read()
+    return sorted(set(re.findall(r"TGS_API\s+[\w\s\*]+?\b(tgs_\w+)\s*\(", text)))
+
+
+def test_exports_match_header():
+    names = header_functions()
+    assert names == sorted(L.EXPORTS)
+    lib = ctypes.CDLL(L.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_default_params():
+    p = L.Params()
+    L.lib().tgs_default_params(ctypes.byref(p))
+    assert (p.tile_size, p.num_bins, p.sample_count) == (16, 64, 8192)
+    assert (p.p_lo, p.p_hi) == (1.0, 99.0) and abs(p.pad - 0.05) < 1e-7
+    assert p.raster == L.RASTER_WAVE and p.packed == 1
+
+
+def cam(w=64, h=48):
+    return tg.camera_struct({"R": [1, 0, 0, 0, 1, 0, 0, 0, 1], "t": [0, 0, 0], "fx": 50.0, "fy": 50.0,
+                             "cx": w / 2, "cy": h / 2, "width": w, "height": h})
+
+
+def status_of(fn, *args):
+    return fn(*args), L.lib().tgs_last_error().decode()
+
+
+def test_project_argument_errors():
+    lib = L.lib()
+    p = tg.Params().c()
+    out = L.Projected(None, None, 0)
+    g = L.Gaussians(None, None, None, None, None, 0, 5)
+    st, msg = status_of(lib.tgs_project, ctypes.byref(g), ctypes.byref(cam()), ctypes.byref(p), ctypes.byref(out), None)
+    assert st == L.TGS_ERR_INVALID_ARG and "sh_degree" in msg
+    g = L.Gaussians(None, None, None, None, None, 10, 0)
+    st, msg = status_of(lib.tgs_project, ctypes.byref(g), ctypes.byref(cam()), ctypes.byref(p), ctypes.byref(out), None)
+    assert st == L.TGS_ERR_INVALID_ARG and "NULL" in msg
+    bad = cam(0, 10)
+    g = L.Gaussians(None, None, None, None, None, 0, 0)
+    st, msg = status_of(lib.tgs_project, ctypes.byref(g), ctypes.byref(bad), ctypes.byref(p), ctypes.byref(out), None)
+    assert st == L.TGS_ERR_INVALID_ARG and "image size" in msg
+    c = cam()
+    c.znear = 2.0
+    c.zfar = 1.0
+    st, msg = status_of(lib.tgs_project, ctypes.byref(g), ctypes.byref(c), ctypes.byref(p), ctypes.byref(out), None)
+    assert st == L.TGS_ERR_INVALID_ARG and "znear" in msg
+    p8 = tg.Params(tile_size=8).c()
+    st, msg = status_of(lib.tgs_project, ctypes.byref(g), ctypes.byref(cam()), ctypes.byref(p8), ctypes.byref(out), None)
+    assert st == L.TGS_ERR_UNSUPPORTED
+
+
+def test_bin_workspace_and_argument_errors():
+    lib = L.lib()
+    c = cam()
+    p = tg.Params().c()
+    need = lib.tgs_bin_workspace_size(1000, 5000, ctypes.byref(c), ctypes.byref(p), L.ORDER_BINNED)
+    assert need >= 5000 * 4 + 12 * 64 * 4
+    need_g = lib.tgs_bin_workspace_size(1000, 5000, ctypes.byref(c), ctypes.byref(p), L.ORDER_GLOBAL)
+    assert need_g >= 5000 * 12
+    pr = L.Projected(None, None, 0)
+    need = lib.tgs_bin_workspace_size(0, 5000, ctypes.byref(c), ctypes.byref(p), L.ORDER_BINNED)
+    fake = ctypes.c_void_p(0x1000)
+    b = L.Binned(5000, None, None, fake.value, fake.value, fake.value, fake.value, fake.value)
+    st, msg = status_of(lib.tgs_bin, ctypes.byref(pr), ctypes.byref(c), ctypes.byref(p), L.ORDER_BINNED, fake,
+                        need - 1, ctypes.byref(b), None, None)
+    assert st == L.TGS_ERR_WORKSPACE and "workspace" in msg
+    st, _ = status_of(lib.tgs_bin, ctypes.byref(pr), ctypes.byref(c), ctypes.byref(p), 7, fake, need,
+                      ctypes.byref(b), None, None)
+    assert st == L.TGS_ERR_INVALID_ARG
+    pk = tg.Params(num_bins=0).c()
+    st, _ = status_of(lib.tgs_bin, ctypes.byref(pr), ctypes.byref(c), ctypes.byref(pk), L.ORDER_BINNED, fake, need,
+                      ctypes.byref(b), None, None)
+    assert st == L.TGS_ERR_INVALID_ARG
+    b.records = None
+    st, msg = status_of(lib.tgs_bin, ctypes.byref(pr), ctypes.byref(c), ctypes.byref(p), L.ORDER_BINNED, fake, need,
+                        ctypes.byref(b), None, None)
+    assert st == L.TGS_ERR_INVALID_ARG and "records" in msg
+
+
+def test_rasterize_argument_errors():
+    lib = L.lib()
+    c = cam()
+    p = tg.Params().c()
+    pr = L.Projected(None, None, 0)
+    b = L.Binned(0, None, None, None, None, None, None, None)
+    bg = (ctypes.c_float * 3)(0, 0, 0)
+    st, msg = status_of(lib.tgs_rasterize, ctypes.byref(pr), ctypes.byref(b), ctypes.byref(c), ctypes.byref(p),
+                        L.ORDER_BINNED, bg, None, None, None, None, None, None, None)
+    assert st == L.TGS_ERR_INVALID_ARG
+
+
+def test_error_type():
+    with pytest.raises(tg.TileGSError):
+        L.check(L.TGS_ERR_INVALID_ARG)

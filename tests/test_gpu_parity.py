@@ -1,0 +1,265 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Bars: integer and index results (entry keys, global order, tile ranges, depth
+range, bin offsets, the repaired stream) bit-exact; images within 1e-4 per
+channel of the FP64 oracle on every pixel the oracle did not flag as
+threshold-ambiguous; the binned and globally sorted paths, and every raster
+variant, bitwise identical to each other.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import scenes
+from helpers import decode_info, image_compare, to_np
+
+pytestmark = pytest.mark.gpu
+
+tg = pytest.importorskip("paper_2609_03613_amd")
+
+TOL = 1e-4
+
+
+def dev():
+    return torch.device("cuda:0")
+
+
+def run_bin(splats_np, info_np, cam, order, params=None, capacity=None):
+    r = tg.Renderer(cam, params or tg.Params(), device=dev())
+    s = torch.as_tensor(splats_np).to(dev())
+    i = torch.as_tensor(np.ascontiguousarray(info_np).view(np.int32)).to(dev())
+    b = r.bin(s, i, order, capacity=capacity)
+    torch.cuda.synchronize()
+    return r, s, i, b
+
+
+def cam_for(W, H, f=100.0):
+    return scenes.camera(np.eye(3), np.zeros(3), f, f, W / 2, H / 2, W, H)
+
+
+# ---------------------------------------------------------------------------
+# projection
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("case", ["small", "training_d3", "surface_d3"])
+def test_project_matches_oracle(case):
+    if case == "small":
+        g, cam = scenes.small_forward(seed=0)
+    elif case == "training_d3":
+        g, cam = scenes.training_scene(seed=0, n=20000)
+    else:
+        g, cam = scenes.scene_1080p(seed=0, n=50000)
+    ref = oracle.project(g, cam)
+    splats, info = tg.project(tg.to_device(g, dev()), cam)
+    torch.cuda.synchronize()
+    s = to_np(splats).astype(np.float64)
+    depth, rect = decode_info(to_np(info))
+    vis_ref = (ref["flags"] & oracle.VISIBLE) > 0
+    vis = (rect[:, 2] > rect[:, 0]) & (rect[:, 3] > rect[:, 1])
+    amb = (ref["flags"] & (oracle.AMBIG_RECT | oracle.AMBIG_VIS)) > 0
+    assert np.array_equal(vis[~amb], vis_ref[~amb])
+    v = vis & vis_ref
+    assert v.sum() > 0.5 * len(v)
+    # depth key: bit-exact (same IEEE binary64 operations, one rounding)
+    assert np.array_equal(depth[v].view(np.uint32), ref["depth_key"][v].view(np.uint32))
+    ok = v & ~amb
+    assert np.array_equal(rect[ok], ref["rect"][ok].astype(np.int64))
+    mean = s[:, 0:2] + s[:, 2:4]
+    np.testing.assert_allclose(mean[v], ref["mean2d"][v], rtol=1e-12, atol=1e-9)
+    np.testing.assert_allclose(s[v, 4:7], ref["conic"][v], rtol=2e-7, atol=1e-12 * np.abs(ref["conic"][v]).max())
+    np.testing.assert_allclose(s[v, 7], ref["opacity"][v], rtol=2e-7)
+    np.testing.assert_allclose(s[v, 8:11], ref["rgb"][v], rtol=2e-7, atol=1e-7)
+
+
+# ---------------------------------------------------------------------------
+# ordering: bit-exact against the oracle's integer schedule
+# ---------------------------------------------------------------------------
+
+SCHED_CASES = [
+    # (n, W, H, K, seed, tie_fraction, hidden_fraction, max_sigma)
+    (3000, 128, 96, 64, 0, 0.0, 0.0, 12.0),
+    (5000, 200, 120, 8, 1, 0.2, 0.1, 20.0),   # ragged image, ties, hidden splats
+    (20000, 512, 384, 64, 2, 0.05, 0.05, 8.0),  # V > S: sampled depth range
+    (4000, 64, 64, 1, 3, 0.1, 0.0, 40.0),     # K = 1: segments are whole tiles
+    (1, 16, 16, 64, 4, 0.0, 0.0, 2.0),        # one splat
+]
+
+
+@pytest.mark.parametrize("case", SCHED_CASES)
+def test_schedule_bit_exact(case):
+    n, W, H, K, seed, ties, hidden, sig = case
+    splats, info = scenes.random_splats(n, W, H, seed=seed, tie_fraction=ties, hidden_fraction=hidden,
+                                        max_sigma_px=sig)
+    cam = cam_for(W, H)
+    depth, rect = scenes.info_depth(info), scenes.info_rects(info)
+    tx, ty = (W + 15) // 16, (H + 15) // 16
+    ref = oracle.schedule(depth, rect, tx, ty, K=K, znear=cam["znear"], zfar=cam["zfar"])
+    p = tg.Params(num_bins=K)
+    _, _, _, bg = run_bin(splats, info, cam, "global", p)
+    assert bg.num_entries == ref["M"]
+    M = ref["M"]
+    assert np.array_equal(to_np(bg.keys)[:M].view(np.uint64), ref["keys"])
+    assert np.array_equal(to_np(bg.vals)[:M].view(np.uint32), ref["vals"])
+    assert np.array_equal(to_np(bg.offsets).view(np.uint32), ref["tile_offsets"])
+    _, _, _, bb = run_bin(splats, info, cam, "binned", p)
+    assert bb.num_entries == M
+    assert np.array_equal(to_np(bb.zrange).view(np.uint32), ref["zrange"].view(np.uint32))
+    assert np.array_equal(to_np(bb.offsets).view(np.uint32), ref["bin_offsets"])
+    assert np.array_equal(to_np(bb.pairs)[:M].view(np.uint64), ref["stream"])
+    c = to_np(bb.counters)
+    assert c[0] == M and c[2] == 0
+
+
+def test_tail_segments_bit_exact():
+    # one 16x16 tile covered by 20k splats with K = 1: a single segment of
+    # more than 8192 entries goes through the global-memory tail sort, and a
+    # second tile gets a 2049..8192 segment
+    n = 26000
+    rng = np.random.default_rng(9)
+    splats, info = scenes.random_splats(n, 32, 16, seed=9, tie_fraction=0.3, max_sigma_px=1.0)
+    rect = np.zeros((n, 4), np.int64)
+    rect[:, 2] = 1
+    rect[:, 3] = 1
+    rect[20000:, 0] = 1
+    rect[20000:, 2] = 2
+    info = scenes.make_info(scenes.info_depth(info), rect)
+    cam = cam_for(32, 16)
+    ref = oracle.schedule(scenes.info_depth(info), rect, 2, 1, K=1)
+    _, _, _, bb = run_bin(splats, info, cam, "binned", tg.Params(num_bins=1))
+    assert np.array_equal(to_np(bb.pairs)[:n].view(np.uint64), ref["stream"])
+    assert np.array_equal(to_np(bb.offsets).view(np.uint32), ref["bin_offsets"])
+    del rng
+
+
+def test_empty_and_invisible():
+    cam = cam_for(40, 24)
+    for n in (0, 5):
+        splats, info = scenes.random_splats(n, 40, 24, seed=1, hidden_fraction=1.0)
+        for order in ("global", "binned"):
+            r, s, i, b = run_bin(splats, info, cam, order)
+            assert b.num_entries == 0
+            out = r.rasterize(s, i, b, bg=(0.25, 0.5, 0.75))
+            torch.cuda.synchronize()
+            assert np.all(to_np(out["rgb"]) == np.array([0.25, 0.5, 0.75], np.float32))
+            assert np.all(to_np(out["alpha"]) == 0) and np.all(to_np(out["last"]) == -1)
+
+
+# ---------------------------------------------------------------------------
+# raster: images against the FP64 oracle; all variants bitwise equal
+# ---------------------------------------------------------------------------
+
+VARIANTS = [("global", "plain", False), ("global", "wave", False), ("binned", "plain", False),
+            ("binned", "wave", False), ("binned", "plain", True), ("binned", "wave", True)]
+
+
+def render_variant(g_splats, g_info, cam, order, raster, packed, K=64, bg=(0.0, 0.0, 0.0)):
+    p = tg.Params(num_bins=K, raster=raster, packed=packed)
+    r = tg.Renderer(cam, p, device=dev())
+    b = r.bin(g_splats, g_info, order)
+    out = r.rasterize(g_splats, g_info, b, bg=bg, counts=True)
+    torch.cuda.synchronize()
+    return {k: to_np(v) for k, v in out.items()}, b
+
+
+@pytest.mark.parametrize("seed,W,H", [(0, 128, 96), (1, 203, 77), (2, 16, 16), (3, 1, 1)])
+def test_raster_synthetic_splats(seed, W, H):
+    n = max(1, (W * H) // 8)
+    splats, info = scenes.random_splats(n, W, H, seed=seed, tie_fraction=0.05, hidden_fraction=0.05)
+    cam = cam_for(W, H)
+    ref = oracle.render(oracle.splats_to_proj(splats, info), W, H, bg=(0.1, 0.2, 0.3))
+    s = torch.as_tensor(splats).to(dev())
+    i = torch.as_tensor(info.view(np.int32)).to(dev())
+    outs = {}
+    for order, raster, packed in VARIANTS:
+        out, b = render_variant(s, i, cam, order, raster, packed, bg=(0.1, 0.2, 0.3))
+        outs[(order, raster, packed)] = out
+        e_rgb, e_a, nflag = image_compare(out["rgb"], out["alpha"], ref)
+        assert e_rgb <= TOL and e_a <= TOL, (order, raster, packed, e_rgb, e_a, nflag)
+        mask = ref["flags"] == 0
+        assert np.array_equal(out["n_contrib"][mask], ref["ncontrib"][mask])
+        # last: the stream position of the oracle's list (same global order)
+        assert np.array_equal(out["last"][mask], ref["last_pos"][mask])
+        assert np.array_equal(out["n_support"][mask], ref["nsupport"][mask])
+        if raster == "plain":
+            assert np.array_equal(out["n_visit"][mask], ref["nvisit"][mask])
+        else:
+            assert np.all(out["n_visit"][mask] <= ref["nvisit"][mask])
+            assert np.all(out["n_visit"][mask] >= ref["nsupport"][mask])
+    base = outs[VARIANTS[0]]
+    for k, out in outs.items():
+        for key in ("rgb", "alpha", "last", "n_contrib"):
+            assert np.array_equal(out[key], base[key]), (k, key)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_end_to_end_small_forward(seed):
+    g, cam = scenes.small_forward(seed=seed)
+    ref = oracle.render(oracle.project(g, cam), 128, 128)
+    gd = tg.to_device(g, dev())
+    imgs = {}
+    for order in ("global", "binned"):
+        out = tg.render(gd, cam, order=order, counts=True)
+        torch.cuda.synchronize()
+        e_rgb, e_a, nflag = image_compare(to_np(out["rgb"]), to_np(out["alpha"]), ref)
+        assert e_rgb <= TOL and e_a <= TOL, (order, e_rgb, e_a)
+        assert nflag <= 20
+        mask = ref["flags"] == 0
+        assert np.array_equal(to_np(out["n_contrib"])[mask], ref["ncontrib"][mask])
+        imgs[order] = to_np(out["rgb"])
+    assert np.array_equal(imgs["global"], imgs["binned"])
+
+
+def test_end_to_end_large_splats_terminate():
+    # larger, denser splats so that pixels reach the transmittance stop
+    g, cam = scenes.small_forward(seed=2, n=3000)
+    g["log_scales"] = (g["log_scales"] + 2.0).astype(np.float32)
+    g["logits"] = (g["logits"] + 2.0).astype(np.float32)
+    ref = oracle.render(oracle.project(g, cam), 128, 128)
+    assert (ref["alpha"] > 1 - 2e-4).mean() > 0.05
+    out = tg.render(tg.to_device(g, dev()), cam, order="binned", counts=True)
+    torch.cuda.synchronize()
+    e_rgb, e_a, nflag = image_compare(to_np(out["rgb"]), to_np(out["alpha"]), ref)
+    assert e_rgb <= TOL and e_a <= TOL, (e_rgb, e_a, nflag)
+
+
+def test_determinism():
+    g, cam = scenes.training_scene(seed=3, n=30000, width=300, height=200)
+    gd = tg.to_device(g, dev())
+    r = tg.Renderer(cam, device=dev())
+    a = r.render(gd, "binned")
+    pa = to_np(a["binned"].pairs).copy()
+    ia = to_np(a["rgb"]).copy()
+    b = r.render(gd, "binned")
+    assert np.array_equal(pa, to_np(b["binned"].pairs))
+    assert np.array_equal(ia, to_np(b["rgb"]))
+
+
+def test_capacity_overflow():
+    splats, info = scenes.random_splats(2000, 128, 128, seed=5)
+    cam = cam_for(128, 128)
+    M = oracle.count_entries(scenes.info_rects(info))
+    p = tg.Params()
+    r = tg.Renderer(cam, p, device=dev())
+    s = torch.as_tensor(splats).to(dev())
+    i = torch.as_tensor(info.view(np.int32)).to(dev())
+    # without synchronisation: counters[2] is raised and the raster writes NaN
+    b = tg.Binned("binned", M // 2, r.tiles, p.num_bins, p.packed, dev())
+    r._binned[1] = b
+    b2 = r.bin(s, i, "binned", sync=False)
+    out = r.rasterize(s, i, b2)
+    torch.cuda.synchronize()
+    c = to_np(b2.counters)
+    assert c[0] == M and c[2] == 1
+    assert np.all(np.isnan(to_np(out["rgb"])))
+    # with synchronisation the wrapper grows the buffers and succeeds
+    b3 = r.bin(s, i, "binned", sync=True)
+    assert b3.num_entries == M and b3.capacity >= M
+
+
+def test_invalid_arguments_raise():
+    cam = cam_for(32, 32)
+    splats, info = scenes.random_splats(10, 32, 32, seed=0)
+    with pytest.raises(tg.TileGSError):
+        tg.Renderer(cam, tg.Params(tile_size=8), device=dev()).bin(
+            torch.as_tensor(splats).to(dev()), torch.as_tensor(info.view(np.int32)).to(dev()))
