@@ -43,7 +43,39 @@ def parse():
     ap.add_argument("--config", default="1080p", choices=["1080p", "small"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--mode", default="frame", choices=["frame", "kernels"],
+                    help="kernels: only launch the product and comparator raster kernels and a "
+                         "256 MiB device copy (for profiler counter runs)")
     return ap.parse_args()
+
+
+def kernels_only(args):
+    """Launches, after one binned and one global frame, the product raster
+    (binned, wave, packed) and the comparator raster (global, plain) `steps`
+    times each, then a 256 MiB device-to-device copy used to calibrate the
+    profiler's HBM byte counters."""
+    import torch
+    import paper_2609_03613_amd as tg
+    dev = torch.device("cuda:0")
+    g, cam, desc = workload(args.config)
+    gd = tg.to_device(g, dev)
+    rb = tg.Renderer(cam, tg.Params(raster="wave", packed=True), device=dev)
+    rg = tg.Renderer(cam, tg.Params(raster="plain", packed=False, tile_order=False), device=dev)
+    splats, info = tg.project(gd, cam)
+    bb = rb.bin(splats, info, "binned", sync=True)
+    bgl = rg.bin(splats, info, "global", sync=True)
+    torch.cuda.synchronize()
+    for _ in range(args.steps):
+        rb.rasterize(splats, info, bb)
+    for _ in range(args.steps):
+        rg.rasterize(splats, info, bgl)
+    src = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"mode": "kernels", "entries": bb.num_entries, "steps": args.steps,
+                      "copy_bytes": src.numel()}), flush=True)
 
 
 def workload(name):
@@ -82,6 +114,8 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path shards by screen tiles "
               f"but multi-GPU runs are not part of this build", file=sys.stderr)
         sys.exit(2)
+    if args.mode == "kernels":
+        return kernels_only(args)
     import torch
     import paper_2609_03613_amd as tg
 
@@ -92,7 +126,9 @@ def main():
     stream = torch.cuda.current_stream()
 
     rb = tg.Renderer(cam, tg.Params(raster="wave", packed=True), device=dev)
-    rg = tg.Renderer(cam, tg.Params(raster="plain", packed=False), device=dev)
+    # the comparator: globally sorted stream, one workgroup per tile gathering
+    # batches by id, tiles in raster order
+    rg = tg.Renderer(cam, tg.Params(raster="plain", packed=False, tile_order=False), device=dev)
 
     # first frames: size the entry buffers (host reads the entry count once)
     splats, info = tg.project(gd, cam)
@@ -167,6 +203,21 @@ def main():
     ras_b = raster_only(rb, bb, out_b)
     ras_g = raster_only(rg, bgl, out_g)
 
+    # ablation: the same two streams through the other kernels and layouts
+    import copy
+    bb_noorder = copy.copy(bb)
+    bb_noorder.tile_order = None
+    r_wave_gather = tg.Renderer(cam, tg.Params(raster="wave", packed=False), device=dev)
+    r_plain_packed = tg.Renderer(cam, tg.Params(raster="plain", packed=True), device=dev)
+    ablation = {
+        "binned wave packed (product)": float(np.median(ras_b)),
+        "binned wave packed, raster-order tiles": float(np.median(raster_only(rb, bb_noorder, out_b))),
+        "binned wave gather-by-id": float(np.median(raster_only(r_wave_gather, bb, out_b))),
+        "binned plain packed": float(np.median(raster_only(r_plain_packed, bb, out_b))),
+        "global wave gather-by-id": float(np.median(raster_only(r_wave_gather, bgl, out_g))),
+        "global plain gather-by-id (comparator)": float(np.median(ras_g)),
+    }
+
     # instrumented launches (outside the timed region): algorithmic work
     cb = rb.rasterize(splats, info, bb, counts=True)
     cg = rg.rasterize(splats, info, bgl, counts=True)
@@ -210,6 +261,7 @@ def main():
         "tests_per_pixel": {"support": n_support / (W * H), "visit_binned": n_visit_b / (W * H),
                             "visit_global": n_visit_g / (W * H)},
         "images_bitwise_equal": same,
+        "raster_ablation_ms": ablation,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_LANE_OPS, "unit": "lane-op/s",
                      "frac": achieved / PEAK_LANE_OPS, "traffic": None,
                      "kernel": "raster_wave_kernel (binned, packed records)",

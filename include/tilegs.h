@@ -131,7 +131,11 @@ typedef struct {
        0, 0), zrange [2] (the depth range).
    counters [4] int64: entries M, visible Gaussians V, overflow flag (1 when
        M > capacity: the stream was truncated and tgs_rasterize writes NaN),
-       reserved. */
+       reserved.
+   tile_order [T] (optional, NULL = none): tgs_bin writes the tiles in
+       descending order of their entry count (grouped by the bit length of
+       the count) and the WAVE raster dispatches tiles in that order, so the
+       longest tiles start first. */
 typedef struct {
     int64_t capacity;
     uint64_t* keys_dev;
@@ -141,6 +145,7 @@ typedef struct {
     float* records_dev;
     float* zrange_dev;
     int64_t* counters_dev;
+    uint32_t* tile_order_dev;
 } tgs_binned;
 
 /* Fills the paper's defaults (16 px tiles, K = 64, S = 8192, 1st / 99th

@@ -35,6 +35,7 @@ class Params:
     pad: float = 0.05
     raster: str = "wave"
     packed: bool = True
+    tile_order: bool = True
 
     def c(self):
         return L.Params(self.tile_size, self.num_bins, self.sample_count, self.p_lo, self.p_hi, self.pad,
@@ -86,7 +87,7 @@ def project(g, cam, params=None):
 class Binned:
     """Device buffers of one entry stream (see tgs_binned)."""
 
-    def __init__(self, order, capacity, tiles, num_bins, packed, device):
+    def __init__(self, order, capacity, tiles, num_bins, packed, device, tile_order=True):
         self.order = ORDERS[order] if isinstance(order, str) else order
         self.capacity = int(capacity)
         cap = max(self.capacity, 1)
@@ -103,12 +104,13 @@ class Binned:
             self.offsets = torch.empty(tiles * num_bins + 1, dtype=torch.int32, **kw)
             if packed:
                 self.records = torch.empty((cap, 12), dtype=torch.float32, **kw)
+        self.tile_order = torch.empty(max(tiles, 1), dtype=torch.int32, **kw) if tile_order else None
         self.num_entries = None
 
     def c(self):
         return L.Binned(self.capacity, _ptr(self.keys).value, _ptr(self.vals).value, _ptr(self.pairs).value,
                         _ptr(self.offsets).value, _ptr(self.records).value, _ptr(self.zrange).value,
-                        _ptr(self.counters).value)
+                        _ptr(self.counters).value, _ptr(self.tile_order).value)
 
 
 class Renderer:
@@ -144,7 +146,7 @@ class Renderer:
         b = self._binned.get(o)
         if b is None or (capacity is not None and b.capacity < capacity):
             b = Binned(o, capacity if capacity is not None else max(1024, 4 * n), self.tiles,
-                       self.params.num_bins, self.params.packed, self.device)
+                       self.params.num_bins, self.params.packed, self.device, self.params.tile_order)
             self._binned[o] = b
         for _ in range(2):
             ws = self._workspace(o, n, b.capacity)
@@ -154,7 +156,7 @@ class Renderer:
                                  ctypes.byref(m) if sync else None, _stream())
             if st == L.TGS_ERR_CAPACITY:
                 b = Binned(o, int(m.value * 1.1) + 1024, self.tiles, self.params.num_bins, self.params.packed,
-                           self.device)
+                           self.device, self.params.tile_order)
                 self._binned[o] = b
                 continue
             L.check(st)

@@ -100,7 +100,7 @@ Layout layout(int64_t n, int64_t capacity, int64_t T, int K, int order) {
     L.scan_tmp = take(sizeof(uint32_t) * scan_tmp_words(scan_n));
     L.sample = take(sizeof(uint32_t) * 8192);
     if (order == TGS_ORDER_BINNED) {
-        L.count = take(sizeof(uint32_t) * (size_t)nseg);
+        L.count = take(sizeof(uint32_t) * (size_t)kXcc * (size_t)nseg);
         L.entry_rank = take(sizeof(uint32_t) * (size_t)capacity);
         L.seg_lists = take(sizeof(uint32_t) * (size_t)kBuckets * (size_t)nseg);
         L.bucket_count = take(sizeof(uint32_t) * 64);
@@ -208,6 +208,7 @@ tgs_status tgs_bin(const tgs_projected* pr, const tgs_camera* cam, const tgs_par
                                    end_bit_for(T), s),
                 "radix sort");
         TGS_HIP(launch_tile_ranges(out->keys_dev, M, T, out->offsets_dev, s), "tile ranges");
+        if (out->tile_order_dev) TGS_HIP(launch_tile_order(out->offsets_dev, 1, T, out->tile_order_dev, s), "tile order");
         return TGS_OK;
     }
     uint32_t* count = (uint32_t*)(w + L.count);
@@ -215,22 +216,22 @@ tgs_status tgs_bin(const tgs_projected* pr, const tgs_camera* cam, const tgs_par
     uint32_t* seg_lists = (uint32_t*)(w + L.seg_lists);
     uint32_t* bucket_count = (uint32_t*)(w + L.bucket_count);
     const int64_t nseg = T * K;
+    RecordSink rs{reinterpret_cast<const float4*>(pr->splats_dev),
+                  params->packed ? reinterpret_cast<float4*>(out->records_dev) : nullptr, K, tiles_x};
     TGS_HIP(launch_depth_range(sample, out->counters_dev, S, params->p_lo, params->p_hi, params->pad, (float)cam->znear,
                                (float)cam->zfar, out->zrange_dev, s),
             "depth range");
-    TGS_HIP(launch_fill_u32(count, 0u, nseg, s), "clear counts");
-    TGS_HIP(launch_bin_count(pr->info_dev, n, emit_off, out->zrange_dev, K, tiles_x, tiles_y, count, entry_rank, cap, s),
+    TGS_HIP(launch_fill_u32(count, 0u, (int64_t)kXcc * nseg, s), "clear counts");
+    TGS_HIP(launch_bin_count(pr->info_dev, n, emit_off, out->zrange_dev, K, tiles_x, tiles_y, count, nseg, entry_rank,
+                             cap, s),
             "bin count");
-    TGS_HIP(launch_scan_u32(count, out->offsets_dev, nseg, tmp, out->offsets_dev + nseg, s), "bin offsets");
-    TGS_HIP(launch_bin_scatter(pr->info_dev, n, emit_off, out->zrange_dev, K, tiles_x, tiles_y, out->offsets_dev,
-                               entry_rank, out->pairs_dev, cap, s),
+    TGS_HIP(launch_bin_offsets(count, nseg, out->offsets_dev, tmp, s), "bin offsets");
+    TGS_HIP(launch_bin_scatter(pr->info_dev, n, emit_off, out->zrange_dev, K, tiles_x, tiles_y, out->offsets_dev, count,
+                               nseg, entry_rank, out->pairs_dev, cap, rs, s),
             "bin scatter");
-    TGS_HIP(launch_repair(out->offsets_dev, nseg, out->pairs_dev, seg_lists, bucket_count, out->counters_dev, s),
+    TGS_HIP(launch_repair(out->offsets_dev, nseg, out->pairs_dev, seg_lists, bucket_count, out->counters_dev, rs, s),
             "repair");
-    if (params->packed)
-        TGS_HIP(launch_pack(out->pairs_dev, out->offsets_dev, K, tiles_x, T, pr->splats_dev, out->records_dev,
-                            out->counters_dev, cap, s),
-                "pack");
+    if (out->tile_order_dev) TGS_HIP(launch_tile_order(out->offsets_dev, K, T, out->tile_order_dev, s), "tile order");
     return TGS_OK;
 }
 
@@ -249,6 +250,7 @@ tgs_status tgs_rasterize(const tgs_projected* pr, const tgs_binned* b, const tgs
     a.splats = pr->splats_dev;
     a.offsets = b->offsets_dev;
     a.counters = b->counters_dev;
+    a.order = b->tile_order_dev;
     if (order == TGS_ORDER_GLOBAL) {
         a.stride = 1;
         a.vals = b->vals_dev;

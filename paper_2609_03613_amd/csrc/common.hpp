@@ -72,6 +72,38 @@ __device__ __forceinline__ int rect_of(const uint4& in, int tiles_x, int tiles_y
     return (x1 - x0) * (y1 - y0);
 }
 
+// XCD (accelerator complex die) executing the calling wave, 0..7.
+__device__ __forceinline__ int xcc_id() {
+    return (int)(__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 7u);
+}
+constexpr int kXcc = 8;
+
+// Per-entry packed record: the splat of the entry's Gaussian with its mean
+// made relative to the entry's tile origin as (hi - origin) + lo, followed
+// by the id. The raster stages splats the same way, so both routes give the
+// same bits.
+__device__ __forceinline__ void write_record(float4* __restrict__ rec, const float4* __restrict__ splats, uint32_t gid,
+                                             float ox, float oy) {
+#pragma clang fp contract(off)
+    const float4 a = splats[3 * (int64_t)gid], b = splats[3 * (int64_t)gid + 1], c = splats[3 * (int64_t)gid + 2];
+    rec[0] = make_float4((a.x - ox) + a.z, (a.y - oy) + a.w, b.x, b.y);
+    rec[1] = make_float4(b.z, b.w, c.x, c.y);
+    rec[2] = make_float4(c.z, __uint_as_float(gid), 0.f, 0.f);
+}
+
+// Where the repair kernels put packed records (records == null: none).
+struct RecordSink {
+    const float4* splats;
+    float4* records;
+    int K, tiles_x;
+    __device__ __forceinline__ void put(uint32_t seg, uint32_t pos, uint64_t pair) const {
+        if (!records) return;
+        const uint32_t t = seg / (uint32_t)K;
+        const float ox = (float)((t % (uint32_t)tiles_x) * kTile), oy = (float)((t / (uint32_t)tiles_x) * kTile);
+        write_record(records + 3 * (int64_t)pos, splats, (uint32_t)pair, ox, oy);
+    }
+};
+
 struct Cam {
     double R[9], t[3];
     double fx, fy, cx, cy;
@@ -108,20 +140,28 @@ hipError_t launch_depth_range(const uint32_t* sample, const int64_t* counters, i
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 
+// (tile, bin) counting with one count copy per XCD: count [kXcc][nseg]. The
+// rank of each entry in its copy, with the copy index in the top three bits,
+// goes to entry_rank.
 hipError_t launch_bin_count(const uint32_t* info, int64_t n, const uint32_t* emit_off, const float* zrange,
-                            int K, int tiles_x, int tiles_y, uint32_t* count, uint32_t* entry_rank,
+                            int K, int tiles_x, int tiles_y, uint32_t* count, int64_t nseg, uint32_t* entry_rank,
                             int64_t capacity, hipStream_t s);
+// bin_off[s] = exclusive scan of the summed copies; count[x][s] becomes the
+// base position of copy x inside segment s; bin_off[nseg] = M.
+size_t bin_offsets_tmp_words(int64_t nseg);
+hipError_t launch_bin_offsets(uint32_t* count, int64_t nseg, uint32_t* bin_off, uint32_t* tmp, hipStream_t s);
 hipError_t launch_bin_scatter(const uint32_t* info, int64_t n, const uint32_t* emit_off, const float* zrange,
-                              int K, int tiles_x, int tiles_y, const uint32_t* bin_off,
-                              const uint32_t* entry_rank, uint64_t* pairs, int64_t capacity, hipStream_t s);
+                              int K, int tiles_x, int tiles_y, const uint32_t* bin_off, const uint32_t* base,
+                              int64_t nseg, const uint32_t* entry_rank, uint64_t* pairs, int64_t capacity,
+                              RecordSink rs, hipStream_t s);
 
-constexpr int kBuckets = 5;
+constexpr int kBuckets = 7;
 hipError_t launch_repair(const uint32_t* bin_off, int64_t nseg, uint64_t* pairs, uint32_t* seg_lists,
-                         uint32_t* bucket_count, const int64_t* counters, hipStream_t s);
+                         uint32_t* bucket_count, const int64_t* counters, RecordSink rs, hipStream_t s);
 
-hipError_t launch_pack(const uint64_t* pairs, const uint32_t* bin_off, int K, int tiles_x, int64_t T,
-                       const float* splats, float* records, const int64_t* counters, int64_t capacity,
-                       hipStream_t s);
+// Tiles in descending order of their entry count (coarse: by bit length of
+// the count), so the heaviest tiles are dispatched first.
+hipError_t launch_tile_order(const uint32_t* offsets, int stride, int64_t T, uint32_t* order, hipStream_t s);
 
 hipError_t launch_emit_keys(const uint32_t* info, int64_t n, const uint32_t* emit_off, int tiles_x, int tiles_y,
                             uint64_t* keys, uint32_t* vals, int64_t capacity, hipStream_t s);
@@ -138,6 +178,7 @@ struct RasterArgs {
     const uint64_t* pairs;  // BINNED pairs
     const float* records;   // BINNED packed records or null
     const int64_t* counters;
+    const uint32_t* order;  // tile dispatch order or null
     int width, height, tiles_x, tiles_y;
     float bg[3];
     float* rgb;

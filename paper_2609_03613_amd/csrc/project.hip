@@ -57,7 +57,10 @@ __device__ __forceinline__ void sh_basis(double x, double y, double z, int degre
     Y[15] = -0.5900435899266435 * x * (xx - 3.0 * yy);
 }
 
-__global__ void __launch_bounds__(256) project_kernel(const float* __restrict__ means,
+constexpr int kProjThreads = 128;
+constexpr int kMaxShFloats = 16 * 3;
+
+__global__ void __launch_bounds__(kProjThreads) project_kernel(const float* __restrict__ means,
                                                       const float* __restrict__ log_scales,
                                                       const float* __restrict__ quats,
                                                       const float* __restrict__ logits,
@@ -65,7 +68,26 @@ __global__ void __launch_bounds__(256) project_kernel(const float* __restrict__ 
                                                       Cam cam, float4* __restrict__ splats,
                                                       uint4* __restrict__ info) {
 #pragma clang fp contract(off)
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // The SH coefficients of the workgroup's Gaussians are one contiguous
+    // block; stage it through LDS with coalesced 16-byte loads.
+    __shared__ float4 sh_lds[kProjThreads * kMaxShFloats / 4];
+    const int nsh = (degree + 1) * (degree + 1);
+    const int64_t g0 = (int64_t)blockIdx.x * kProjThreads;
+    {
+        const int64_t cnt = min((int64_t)kProjThreads, n - g0) * nsh * 3;  // floats
+        const float* src = sh + g0 * nsh * 3;
+        if ((reinterpret_cast<uintptr_t>(src) & 15) == 0) {
+            const float4* s4 = reinterpret_cast<const float4*>(src);
+            for (int64_t i = threadIdx.x; i < cnt / 4; i += kProjThreads) sh_lds[i] = s4[i];
+            float* f = reinterpret_cast<float*>(sh_lds);
+            for (int64_t i = (cnt / 4) * 4 + threadIdx.x; i < cnt; i += kProjThreads) f[i] = src[i];
+        } else {
+            float* f = reinterpret_cast<float*>(sh_lds);
+            for (int64_t i = threadIdx.x; i < cnt; i += kProjThreads) f[i] = src[i];
+        }
+    }
+    __syncthreads();
+    const int64_t g = g0 + threadIdx.x;
     if (g >= n) return;
     float4* out = splats + 3 * g;
     const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -144,14 +166,13 @@ __global__ void __launch_bounds__(256) project_kernel(const float* __restrict__ 
         return;
     }
     // colour: 0.5 + sum sh_lm Y_lm(dir), dir from the camera centre, >= 0
-    const int nsh = (degree + 1) * (degree + 1);
     double dx = mx3 - cam.campos[0], dy = my3 - cam.campos[1], dz = mz3 - cam.campos[2];
     const double dn = sqrt(dx * dx + dy * dy + dz * dz);
     dx /= dn; dy /= dn; dz /= dn;
     double Y[16];
     sh_basis(dx, dy, dz, degree, Y);
     double col[3] = {0.0, 0.0, 0.0};
-    const float* shg = sh + (int64_t)g * nsh * 3;
+    const float* shg = reinterpret_cast<const float*>(sh_lds) + threadIdx.x * nsh * 3;
     for (int k = 0; k < nsh; ++k) {
         col[0] += (double)shg[3 * k] * Y[k];
         col[1] += (double)shg[3 * k + 1] * Y[k];
@@ -172,7 +193,7 @@ __global__ void __launch_bounds__(256) project_kernel(const float* __restrict__ 
 
 hipError_t launch_project(const tgs_gaussians& g, const Cam& cam, float* splats, uint32_t* info, hipStream_t s) {
     if (g.n == 0) return hipSuccess;
-    const int block = 256;
+    const int block = kProjThreads;
     const int64_t grid = (g.n + block - 1) / block;
     hipLaunchKernelGGL(project_kernel, dim3((unsigned)grid), dim3(block), 0, s, g.means_dev, g.log_scales_dev,
                        g.quats_dev, g.logits_dev, g.sh_dev, g.n, g.sh_degree, cam,

@@ -145,7 +145,7 @@ __global__ void __launch_bounds__(256) raster_plain_kernel(RasterArgs A) {
     __shared__ float4 sb[256];
     __shared__ float2 sc[256];
     const int T = A.tiles_x * A.tiles_y;
-    const int t = xcd_remap(blockIdx.x, T);
+    const int t = A.order ? (int)A.order[blockIdx.x] : xcd_remap(blockIdx.x, T);
     const int tx = t % A.tiles_x, ty = t / A.tiles_x;
     const int lx = threadIdx.x & 15, ly = threadIdx.x >> 4;
     const int x = tx * kTile + lx, y = ty * kTile + ly;
@@ -217,11 +217,29 @@ __device__ __forceinline__ bool block_may_touch(float mx, float my, float a, flo
     return qmin <= tau + 1e-3f + 4e-6f * mag;
 }
 
+// Loads the raw 12-word record or splat of entry e for the cull test and
+// staging.
+template <int SRC>
+__device__ __forceinline__ void fetch_entry(const RasterArgs& A, uint32_t e, float4& r0, float4& r1, float4& r2) {
+    if (SRC == SRC_PACKED) {
+        const float4* r = reinterpret_cast<const float4*>(A.records) + 3 * (int64_t)e;
+        r0 = r[0];
+        r1 = r[1];
+        r2 = r[2];
+    } else {
+        const uint32_t g = id_at<SRC>(A, e);
+        const float4* q = reinterpret_cast<const float4*>(A.splats) + 3 * (int64_t)g;
+        r0 = q[0];
+        r1 = q[1];
+        r2 = q[2];
+    }
+}
+
 template <int SRC, bool COUNT, bool CULL>
 __global__ void __launch_bounds__(256) raster_wave_kernel(RasterArgs A) {
     __shared__ Staged stage[4][kWave];
     const int T = A.tiles_x * A.tiles_y;
-    const int t = xcd_remap(blockIdx.x, T);
+    const int t = A.order ? (int)A.order[blockIdx.x] : xcd_remap(blockIdx.x, T);
     const int tx = t % A.tiles_x, ty = t / A.tiles_x;
     const int w = threadIdx.x / kWave, l = lane();
     const int bx = (w & 1) * 8, by = (w >> 1) * 8;
@@ -239,24 +257,23 @@ __global__ void __launch_bounds__(256) raster_wave_kernel(RasterArgs A) {
     const uint32_t begin = A.offsets[(int64_t)t * A.stride];
     const uint32_t end = bad ? begin : A.offsets[(int64_t)(t + 1) * A.stride];
     Staged* st = stage[w];
+    // software pipeline: the next 64 entries are in flight while the current
+    // ones are culled and composited
+    float4 n0 = make_float4(0.f, 0.f, 0.f, 0.f), n1 = n0, n2 = n0;
+    if (begin + l < end) fetch_entry<SRC>(A, begin + l, n0, n1, n2);
     for (uint32_t base = begin; base < end; base += kWave) {
         if (ballot(!p.done) == 0) break;
         const uint32_t e = base + l;
+        const float4 r0 = n0, r1 = n1, r2 = n2;
+        if (e + kWave < end) fetch_entry<SRC>(A, e + kWave, n0, n1, n2);
         bool keep = e < end;
         Staged s;
-        if (keep) {
-            if (SRC == SRC_PACKED) {
-                const float4* r = reinterpret_cast<const float4*>(A.records) + 3 * (int64_t)e;
-                const float4 r0 = r[0], r1 = r[1], r2 = r[2];
-                if (CULL) keep = block_may_touch(r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, xa, xb, ya, yb);
-                s = stage_record(r0, r1, r2, (int32_t)e);
-            } else {
-                const uint32_t g = id_at<SRC>(A, e);
-                const float4* q = reinterpret_cast<const float4*>(A.splats) + 3 * (int64_t)g;
-                const float4 q0 = q[0], q1 = q[1], q2 = q[2];
-                s = stage_splat(q0, q1, q2, ox, oy, (int32_t)e);
-                if (CULL) keep = block_may_touch(s.a.x, s.a.y, q1.x, q1.y, q1.z, q1.w, xa, xb, ya, yb);
-            }
+        if (SRC == SRC_PACKED) {
+            if (CULL && keep) keep = block_may_touch(r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, xa, xb, ya, yb);
+            s = stage_record(r0, r1, r2, (int32_t)e);
+        } else {
+            s = stage_splat(r0, r1, r2, ox, oy, (int32_t)e);
+            if (CULL && keep) keep = block_may_touch(s.a.x, s.a.y, r1.x, r1.y, r1.z, r1.w, xa, xb, ya, yb);
         }
         const uint64_t m = ballot(keep);
         if (keep) st[rank_in(m)] = s;

@@ -213,6 +213,61 @@ __global__ void __launch_bounds__(kThreads) emit_apply(const uint32_t* __restric
     }
 }
 
+// ---- bin offsets from the per-XCD count copies ---------------------------
+
+__global__ void __launch_bounds__(kThreads) bo_reduce(const uint32_t* __restrict__ count, int64_t nseg,
+                                                      uint32_t* __restrict__ block_sums) {
+    __shared__ uint32_t lds[kThreads / kWave + 1];
+    const int64_t base = (int64_t)blockIdx.x * kPerBlock + (int64_t)threadIdx.x * kItems;
+    uint32_t s = 0;
+    for (int x = 0; x < kXcc; ++x) {
+        const uint32_t* c = count + (int64_t)x * nseg;
+#pragma unroll
+        for (int k = 0; k < kItems; ++k)
+            if (base + k < nseg) s += c[base + k];
+    }
+    uint32_t total;
+    (void)block_excl<uint32_t, kThreads>(s, lds, &total);
+    if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
+}
+
+// bin_off[s] = exclusive prefix of the summed copies; count[x][s] is then
+// replaced by bin_off[s] + the counts of copies 0..x-1 in segment s.
+__global__ void __launch_bounds__(kThreads) bo_apply(uint32_t* __restrict__ count, int64_t nseg,
+                                                     uint32_t* __restrict__ bin_off,
+                                                     const uint32_t* __restrict__ block_off) {
+    __shared__ uint32_t lds[kThreads / kWave + 1];
+    const int64_t base = (int64_t)blockIdx.x * kPerBlock + (int64_t)threadIdx.x * kItems;
+    uint32_t tot[kItems];
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) tot[k] = 0;
+    for (int x = 0; x < kXcc; ++x) {
+        const uint32_t* c = count + (int64_t)x * nseg;
+#pragma unroll
+        for (int k = 0; k < kItems; ++k)
+            if (base + k < nseg) tot[k] += c[base + k];
+    }
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) s += tot[k];
+    uint32_t total;
+    uint32_t run = block_off[blockIdx.x] + block_excl<uint32_t, kThreads>(s, lds, &total);
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        if (base + k < nseg) {
+            bin_off[base + k] = run;
+            uint32_t r = run;
+            for (int x = 0; x < kXcc; ++x) {
+                uint32_t* c = count + (int64_t)x * nseg + base + k;
+                const uint32_t v = *c;
+                *c = r;
+                r += v;
+            }
+        }
+        run += tot[k];
+    }
+}
+
 __global__ void fill_u32_kernel(uint32_t* p, uint32_t v, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = v;
@@ -246,6 +301,17 @@ hipError_t launch_emit_scan(const uint32_t* info, int64_t n, int tiles_x, int ti
     if (nb > 0)
         hipLaunchKernelGGL(emit_apply, dim3((unsigned)nb), dim3(kThreads), 0, s, info, n, tiles_x, tiles_y, emit_off,
                            bs, counters, sample, S);
+    return hipGetLastError();
+}
+
+size_t bin_offsets_tmp_words(int64_t nseg) { return (size_t)((nseg + kPerBlock - 1) / kPerBlock + 16); }
+
+hipError_t launch_bin_offsets(uint32_t* count, int64_t nseg, uint32_t* bin_off, uint32_t* tmp, hipStream_t s) {
+    if (nseg <= 0) return launch_fill_u32(bin_off, 0u, 1, s);
+    const int64_t nb = (nseg + kPerBlock - 1) / kPerBlock;
+    hipLaunchKernelGGL(bo_reduce, dim3((unsigned)nb), dim3(kThreads), 0, s, count, nseg, tmp);
+    hipLaunchKernelGGL(u32_top, dim3(1), dim3(kTopThreads), 0, s, tmp, nb, bin_off + nseg);
+    hipLaunchKernelGGL(bo_apply, dim3((unsigned)nb), dim3(kThreads), 0, s, count, nseg, bin_off, tmp);
     return hipGetLastError();
 }
 

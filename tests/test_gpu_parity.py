@@ -263,3 +263,42 @@ def test_invalid_arguments_raise():
     with pytest.raises(tg.TileGSError):
         tg.Renderer(cam, tg.Params(tile_size=8), device=dev()).bin(
             torch.as_tensor(splats).to(dev()), torch.as_tensor(info.view(np.int32)).to(dev()))
+
+
+BUCKET_EDGES = [2, 3, 63, 64, 65, 127, 128, 129, 255, 256, 257, 511, 512, 513, 4096, 4097, 8192, 8193]
+
+
+def test_repair_bucket_edges_and_records():
+    # one tile per segment length at every bucket boundary of the repair
+    # sorts (K = 1, so a segment is a whole tile); random depths with ties
+    lens = BUCKET_EDGES
+    W = 16 * len(lens)
+    n = sum(lens)
+    splats, info = scenes.random_splats(n, W, 16, seed=11, tie_fraction=0.3, max_sigma_px=1.0)
+    rect = np.zeros((n, 4), np.int64)
+    tile = np.repeat(np.arange(len(lens)), lens)
+    rng = np.random.default_rng(1)
+    perm = rng.permutation(n)  # interleave the tiles in id order
+    rect[perm, 0] = tile
+    rect[perm, 2] = tile + 1
+    rect[:, 3] = 1
+    info = scenes.make_info(scenes.info_depth(info), rect)
+    cam = cam_for(W, 16)
+    for K in (1, 4):
+        ref = oracle.schedule(scenes.info_depth(info), rect, len(lens), 1, K=K)
+        _, _, _, bb = run_bin(splats, info, cam, "binned", tg.Params(num_bins=K))
+        pairs = to_np(bb.pairs)[:n].view(np.uint64)
+        assert np.array_equal(pairs, ref["stream"]), K
+        assert np.array_equal(to_np(bb.offsets).view(np.uint32), ref["bin_offsets"])
+        # packed records: the entry's splat with the mean relative to its tile
+        rec = to_np(bb.records)[:n]
+        gid = (pairs & np.uint64(0xFFFFFFFF)).astype(np.int64)
+        t_of = np.repeat(np.arange(len(lens)), np.diff(ref["bin_offsets"][::K].astype(np.int64)))
+        ox = (t_of * 16).astype(np.float32)
+        sp = splats[gid]
+        exp_mx = (sp[:, 0] - ox) + sp[:, 2]
+        exp_my = (sp[:, 1] - np.float32(0.0)) + sp[:, 3]
+        assert np.array_equal(rec[:, 0], exp_mx.astype(np.float32))
+        assert np.array_equal(rec[:, 1], exp_my.astype(np.float32))
+        assert np.array_equal(rec[:, 2:9], sp[:, 4:11])
+        assert np.array_equal(rec[:, 9].view(np.uint32), gid.astype(np.uint32))
