@@ -158,6 +158,66 @@ __device__ __forceinline__ int bin_of(uint32_t L, uint32_t Lmin, uint32_t Lmax, 
     return b > (uint64_t)(K - 1) ? K - 1 : (int)b;
 }
 
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Per-wavefront LDS view of its 64 Gaussians for the entry expansion.
+struct WaveGauss {
+    uint32_t excl[kWave];  // first entry of each Gaussian, relative to the wavefront
+    uint32_t rect[kWave];  // x0 | y0 << 16
+    uint32_t width[kWave];
+    uint32_t key[kWave];   // depth bits
+    uint32_t bin[kWave];
+};
+
+// Load-balanced expansion of the (Gaussian, tile) entries of a wavefront's
+// 64 consecutive Gaussians: the entries are enumerated 64 at a time, one per
+// lane, and each lane finds its Gaussian by binary search over the
+// wavefront's exclusive entry counts. Entries of consecutive Gaussians are
+// consecutive in the global entry order, so entry e = emit_off[first] + k.
+// f(gid, tile_x, tile_y, e, depth_bits, bin) is called once per entry.
+template <bool WITH_BIN, class F>
+__device__ __forceinline__ void for_wave_entries(const uint4* __restrict__ info, int64_t n,
+                                                 const uint32_t* __restrict__ emit_off, int tiles_x, int tiles_y,
+                                                 const float* __restrict__ zrange, int K, WaveGauss* W, F&& f) {
+    const int l = lane();
+    const int64_t g0 = ((int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~(kWave - 1)));
+    if (g0 >= n) return;
+    const int64_t g = g0 + l;
+    int cnt = 0, x0 = 0, y0 = 0, x1 = 0, y1 = 0;
+    uint32_t key = 0;
+    if (g < n) {
+        const uint4 in = info[g];
+        cnt = rect_of(in, tiles_x, tiles_y, x0, y0, x1, y1);
+        key = in.x;
+    }
+    const uint32_t incl = wave_inclusive_sum((uint32_t)cnt);
+    const uint32_t total = shfl_u32(incl, kWave - 1);
+    if (total == 0) return;
+    W->excl[l] = incl - (uint32_t)cnt;
+    W->rect[l] = (uint32_t)x0 | ((uint32_t)y0 << 16);
+    W->width[l] = (uint32_t)(x1 - x0);
+    W->key[l] = key;
+    if (WITH_BIN) W->bin[l] = cnt ? (uint32_t)bin_of(key, __float_as_uint(zrange[0]), __float_as_uint(zrange[1]), K) : 0u;
+    const int64_t ebase = emit_off[g0];
+    wave_sync();
+    for (uint32_t base = 0; base < total; base += kWave) {
+        const uint32_t k = base + (uint32_t)l;
+        if (k < total) {
+            int lo = 0;
+#pragma unroll
+            for (int step = kWave / 2; step > 0; step >>= 1)
+                if (W->excl[lo + step] <= k) lo += step;
+            const uint32_t j = k - W->excl[lo], w = W->width[lo], r = W->rect[lo];
+            const int tx = (int)(r & 0xFFFFu) + (int)(j % w), ty = (int)(r >> 16) + (int)(j / w);
+            f(g0 + lo, tx, ty, ebase + k, W->key[lo], WITH_BIN ? W->bin[lo] : 0u);
+        }
+    }
+}
+
 // Atomic count per (tile, bin) into the calling XCD's copy of the counts.
 // All atomics on copy x come from XCD x, so they are carried out in that
 // XCD's L2 (workgroup scope) instead of at the memory side; the returned old
@@ -167,21 +227,15 @@ __global__ void __launch_bounds__(256) bin_count_kernel(const uint4* __restrict_
                                                         const float* __restrict__ zrange, int K, int tiles_x,
                                                         int tiles_y, uint32_t* __restrict__ count, int64_t nseg,
                                                         uint32_t* __restrict__ entry_rank, int64_t capacity) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= n) return;
-    const uint4 in = info[g];
-    int x0, y0, x1, y1;
-    if (rect_of(in, tiles_x, tiles_y, x0, y0, x1, y1) == 0) return;
-    const int b = bin_of(in.x, __float_as_uint(zrange[0]), __float_as_uint(zrange[1]), K);
+    __shared__ WaveGauss wg[4];
     const uint32_t x = (uint32_t)xcc_id();
     uint32_t* cnt = count + (int64_t)x * nseg;
-    int64_t e = emit_off[g];
-    for (int y = y0; y < y1; ++y)
-        for (int xx = x0; xx < x1; ++xx, ++e) {
-            const uint32_t r = __hip_atomic_fetch_add(&cnt[(int64_t)(y * tiles_x + xx) * K + b], 1u,
-                                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (e < capacity) entry_rank[e] = (r & 0x1FFFFFFFu) | (x << 29);
-        }
+    for_wave_entries<true>(info, n, emit_off, tiles_x, tiles_y, zrange, K, &wg[threadIdx.x / kWave],
+                           [&](int64_t, int tx, int ty, int64_t e, uint32_t, uint32_t b) {
+                               const uint32_t r = __hip_atomic_fetch_add(&cnt[(int64_t)(ty * tiles_x + tx) * K + b], 1u,
+                                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                               if (e < capacity) entry_rank[e] = (r & 0x1FFFFFFFu) | (x << 29);
+                           });
 }
 
 // pair = depth bits << 32 | id at base[copy][segment] + rank. An entry that
@@ -195,201 +249,166 @@ __global__ void __launch_bounds__(256) bin_scatter_kernel(const uint4* __restric
                                                           const uint32_t* __restrict__ entry_rank,
                                                           uint64_t* __restrict__ pairs, int64_t capacity,
                                                           RecordSink rs) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= n) return;
-    const uint4 in = info[g];
-    int x0, y0, x1, y1;
-    if (rect_of(in, tiles_x, tiles_y, x0, y0, x1, y1) == 0) return;
-    const int b = bin_of(in.x, __float_as_uint(zrange[0]), __float_as_uint(zrange[1]), K);
-    const uint64_t pair = ((uint64_t)in.x << 32) | (uint64_t)g;
-    int64_t e = emit_off[g];
-    for (int y = y0; y < y1; ++y)
-        for (int xx = x0; xx < x1; ++xx, ++e) {
-            if (e >= capacity) return;
-            const uint32_t rk = entry_rank[e];
-            const int64_t sg = (int64_t)(y * tiles_x + xx) * K + b;
-            const int64_t p = (int64_t)base[(int64_t)(rk >> 29) * nseg + sg] + (rk & 0x1FFFFFFFu);
-            if (p >= capacity) continue;
-            pairs[p] = pair;
-            if (rs.records && bin_off[sg + 1] - bin_off[sg] == 1) rs.put((uint32_t)sg, (uint32_t)p, pair);
-        }
+    __shared__ WaveGauss wg[4];
+    for_wave_entries<true>(info, n, emit_off, tiles_x, tiles_y, zrange, K, &wg[threadIdx.x / kWave],
+                           [&](int64_t gid, int tx, int ty, int64_t e, uint32_t key, uint32_t b) {
+                               if (e >= capacity) return;
+                               const uint32_t rk = entry_rank[e];
+                               const int64_t sg = (int64_t)(ty * tiles_x + tx) * K + b;
+                               const int64_t p = (int64_t)base[(int64_t)(rk >> 29) * nseg + sg] + (rk & 0x1FFFFFFFu);
+                               if (p >= capacity) return;
+                               const uint64_t pair = ((uint64_t)key << 32) | (uint64_t)gid;
+                               pairs[p] = pair;
+                               if (rs.records && bin_off[sg + 1] - bin_off[sg] == 1)
+                                   rs.put((uint32_t)sg, (uint32_t)p, pair);
+                           });
 }
 
 // ---------------------------------------------------------------------------
 // exact repair
 // ---------------------------------------------------------------------------
 
-// Length buckets: 2..64, 65..128, 129..256, 257..512 (one wavefront, 1, 2,
-// 4 or 8 keys per lane in registers), 513..4096, 4097..8192 (one workgroup,
-// LDS), > 8192 (one workgroup, in place in global memory).
-__device__ __forceinline__ int bucket_of(uint32_t len) {
-    if (len <= 1) return -1;
-    if (len <= 64) return 0;
-    if (len <= 128) return 1;
-    if (len <= 256) return 2;
-    if (len <= 512) return 3;
-    if (len <= 4096) return 4;
-    if (len <= 8192) return 5;
-    return 6;
-}
-
-constexpr int kClassifyItems = 8;
-
-// Appends every segment of two or more entries to its bucket list. Counts
-// are aggregated per wavefront (ballot) and per workgroup (LDS) so that each
-// workgroup issues one global atomic per bucket. Nothing is queued when the
-// stream overflowed its buffers (counters[2]).
-__global__ void __launch_bounds__(256) classify_kernel(const uint32_t* __restrict__ bin_off, int64_t nseg,
-                                                       uint32_t* __restrict__ lists,
-                                                       uint32_t* __restrict__ bucket_count,
-                                                       const int64_t* __restrict__ counters) {
-    __shared__ uint32_t lcount[kBuckets], lbase[kBuckets];
-    if (counters[2]) return;
-    if (threadIdx.x < kBuckets) lcount[threadIdx.x] = 0;
-    __syncthreads();
-    const int64_t first = (int64_t)blockIdx.x * 256 * kClassifyItems;
-    int bk[kClassifyItems];
-    uint32_t slot[kClassifyItems];
+// Bitonic network over groups of G lanes, one key per lane (the partner at
+// distance j < G is lane l ^ j, inside the group).
+template <int G>
+__device__ __forceinline__ uint64_t group_bitonic(uint64_t v, int li) {
 #pragma unroll
-    for (int i = 0; i < kClassifyItems; ++i) {
-        const int64_t s = first + (int64_t)i * 256 + threadIdx.x;
-        bk[i] = s < nseg ? bucket_of(bin_off[s + 1] - bin_off[s]) : -1;
-        slot[i] = 0;
-        if (ballot(bk[i] >= 0) == 0) continue;
+    for (int k = 2; k <= G; k <<= 1) {
 #pragma unroll
-        for (int k = 0; k < kBuckets; ++k) {
-            const uint64_t m = ballot(bk[i] == k);
-            if (m == 0) continue;
-            const int leader = __builtin_ctzll(m);
-            uint32_t b0 = 0;
-            if (lane() == leader) b0 = atomicAdd(&lcount[k], (uint32_t)__builtin_popcountll(m));
-            b0 = shfl_u32(b0, leader);
-            if (bk[i] == k) slot[i] = b0 + rank_in(m);
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const uint64_t o = shfl_xor_u64(v, j);
+            const bool up = (li & k) == 0, lower = (li & j) == 0;
+            const uint64_t mn = v < o ? v : o, mx = v < o ? o : v;
+            v = (lower == up) ? mn : mx;
         }
     }
-    __syncthreads();
-    if (threadIdx.x < kBuckets)
-        lbase[threadIdx.x] = lcount[threadIdx.x] ? atomicAdd(&bucket_count[threadIdx.x], lcount[threadIdx.x]) : 0u;
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < kClassifyItems; ++i) {
-        if (bk[i] < 0) continue;
-        const int64_t s = first + (int64_t)i * 256 + threadIdx.x;
-        lists[(int64_t)bk[i] * nseg + lbase[bk[i]] + slot[i]] = (uint32_t)s;
+    return v;
+}
+
+// Segments of 2..64 keys: 64 / G segments per wavefront, G lanes each.
+template <int G>
+__device__ __forceinline__ void sort_groups(const uint32_t* __restrict__ bin_off, const uint32_t* __restrict__ list,
+                                            uint32_t cnt, int wid, int waves, uint64_t* __restrict__ pairs,
+                                            const RecordSink& rs) {
+    constexpr int SPW = kWave / G;
+    const int l = lane(), gi = l / G, li = l % G;
+    for (uint32_t i0 = (uint32_t)wid * SPW; i0 < cnt; i0 += (uint32_t)waves * SPW) {
+        const uint32_t i = i0 + gi;
+        uint32_t s = 0, begin = 0, len = 0;
+        if (i < cnt) {
+            s = list[i];
+            begin = bin_off[s];
+            len = bin_off[s + 1] - begin;
+        }
+        uint64_t v = (uint32_t)li < len ? pairs[begin + li] : ~0ull;
+        v = group_bitonic<G>(v, li);
+        if ((uint32_t)li < len) {
+            pairs[begin + li] = v;
+            rs.put(s, begin + li, v);
+        }
     }
 }
 
-// One wavefront per segment of at most 64 E keys; lane l holds keys
-// l E .. l E + E - 1 in registers. Bitonic network: partners at distance
-// j >= E are in lane l ^ (j / E) (lane shuffle), closer ones in the same lane.
-template <int E>
-__global__ void __launch_bounds__(256) sort_wave_kernel(const uint32_t* __restrict__ bin_off,
-                                                        const uint32_t* __restrict__ list,
-                                                        const uint32_t* __restrict__ bucket_count, int bucket,
-                                                        uint64_t* __restrict__ pairs, RecordSink rs) {
-    constexpr int N = kWave * E;
-    const int waves = gridDim.x * (blockDim.x / kWave);
-    const int wid = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-    const uint32_t cnt = bucket_count[bucket];
+// Segments of 65..512 keys: one wavefront, bitonic network in its own LDS
+// region (no workgroup barriers; LDS operations of a wavefront complete in
+// order).
+__device__ __forceinline__ void sort_wave_lds(const uint32_t* __restrict__ bin_off, const uint32_t* __restrict__ list,
+                                              uint32_t cnt, int wid, int waves, uint64_t* __restrict__ pairs,
+                                              uint64_t* buf, const RecordSink& rs) {
     const int l = lane();
-    for (uint32_t i = wid; i < cnt; i += waves) {
-        const uint32_t s = list[i];
-        const uint32_t begin = bin_off[s], len = bin_off[s + 1] - begin;
-        uint64_t v[E];
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const uint32_t idx = (uint32_t)(l * E + e);
-            v[e] = idx < len ? pairs[begin + idx] : ~0ull;
-        }
-#pragma unroll
-        for (int k = 2; k <= N; k <<= 1) {
-#pragma unroll
-            for (int j = k >> 1; j > 0; j >>= 1) {
-                if (j >= E) {
-#pragma unroll
-                    for (int e = 0; e < E; ++e) {
-                        const int idx = l * E + e;
-                        const uint64_t o = shfl_xor_u64(v[e], j / E);
-                        const bool up = (idx & k) == 0, lower = (idx & j) == 0;
-                        const uint64_t mn = v[e] < o ? v[e] : o, mx = v[e] < o ? o : v[e];
-                        v[e] = (lower == up) ? mn : mx;
-                    }
-                } else {
-#pragma unroll
-                    for (int e = 0; e < E; ++e) {
-                        if (e & j) continue;
-                        const int idx = l * E + e;
-                        const bool up = (idx & k) == 0;
-                        const uint64_t a = v[e], b = v[e ^ j];
-                        if ((a > b) == up) {
-                            v[e] = b;
-                            v[e ^ j] = a;
-                        }
-                    }
-                }
-            }
-        }
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const uint32_t idx = (uint32_t)(l * E + e);
-            if (idx < len) {
-                pairs[begin + idx] = v[e];
-                rs.put(s, begin + idx, v[e]);
-            }
-        }
-    }
-}
-
-// Segments up to CAP keys: one workgroup per segment, bitonic network in
-// LDS over the next power of two, padded with the maximum key.
-template <int NT, int CAP>
-__global__ void __launch_bounds__(NT) sort_lds_kernel(const uint32_t* __restrict__ bin_off,
-                                                      const uint32_t* __restrict__ list,
-                                                      const uint32_t* __restrict__ bucket_count, int bucket,
-                                                      uint64_t* __restrict__ pairs, RecordSink rs) {
-    __shared__ uint64_t buf[CAP];
-    const uint32_t cnt = bucket_count[bucket];
-    for (uint32_t i = blockIdx.x; i < cnt; i += gridDim.x) {
+    for (uint32_t i = (uint32_t)wid; i < cnt; i += (uint32_t)waves) {
         const uint32_t s = list[i];
         const uint32_t begin = bin_off[s], len = bin_off[s + 1] - begin;
         uint32_t P = 1;
         while (P < len) P <<= 1;
-        for (uint32_t e = threadIdx.x; e < P; e += NT) buf[e] = e < len ? pairs[begin + e] : ~0ull;
-        __syncthreads();
+        for (uint32_t e = l; e < P; e += kWave) buf[e] = e < len ? pairs[begin + e] : ~0ull;
+        wave_sync();
         for (uint32_t k = 2; k <= P; k <<= 1) {
             for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-                for (uint32_t e = threadIdx.x; e < P; e += NT) {
-                    const uint32_t p = e ^ j;
-                    if (p > e) {
-                        const uint64_t a = buf[e], b = buf[p];
-                        const bool up = (e & k) == 0;
-                        if ((a > b) == up) {
-                            buf[e] = b;
-                            buf[p] = a;
-                        }
+                for (uint32_t t = l; t < P / 2; t += kWave) {
+                    const uint32_t lo = (t / j) * 2 * j + (t % j), hi = lo + j;
+                    const uint64_t a = buf[lo], b = buf[hi];
+                    const bool up = (lo & k) == 0;
+                    if ((a > b) == up) {
+                        buf[lo] = b;
+                        buf[hi] = a;
                     }
                 }
-                __syncthreads();
+                wave_sync();
             }
         }
-        for (uint32_t e = threadIdx.x; e < len; e += NT) {
-            pairs[begin + e] = buf[e];
-            rs.put(s, begin + e, buf[e]);
+        for (uint32_t e = l; e < len; e += kWave) {
+            const uint64_t v = buf[e];
+            pairs[begin + e] = v;
+            rs.put(s, begin + e, v);
         }
-        __syncthreads();
+        wave_sync();
     }
 }
 
-// Segments above 8192 keys: one workgroup sorts the segment in place in
-// global memory. Bitonic network in the form whose every comparator puts
-// the smaller key at the lower index (each merge starts by comparing
-// mirrored positions), so positions at or beyond the segment length act as
-// +infinity and are never touched.
-__global__ void __launch_bounds__(1024) sort_tail_kernel(const uint32_t* __restrict__ bin_off,
-                                                         const uint32_t* __restrict__ list,
-                                                         const uint32_t* __restrict__ bucket_count, int bucket,
-                                                         uint64_t* pairs, RecordSink rs) {
-    const uint32_t cnt = bucket_count[bucket];
+// Buckets 0..4 in one launch: every wavefront walks every bucket with a
+// static stride (no shared work counter).
+__global__ void __launch_bounds__(256) sort_small_kernel(const uint32_t* __restrict__ bin_off,
+                                                         const uint32_t* __restrict__ lists, int64_t nseg,
+                                                         const uint32_t* __restrict__ bucket_count,
+                                                         uint64_t* __restrict__ pairs, RecordSink rs) {
+    __shared__ uint64_t buf[4][512];
+    const int waves = gridDim.x * (blockDim.x / kWave);
+    const int wid = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    sort_groups<8>(bin_off, lists + 0 * nseg, bucket_count[0], wid, waves, pairs, rs);
+    sort_groups<16>(bin_off, lists + 1 * nseg, bucket_count[1], wid, waves, pairs, rs);
+    sort_groups<32>(bin_off, lists + 2 * nseg, bucket_count[2], wid, waves, pairs, rs);
+    sort_groups<64>(bin_off, lists + 3 * nseg, bucket_count[3], wid, waves, pairs, rs);
+    sort_wave_lds(bin_off, lists + 4 * nseg, bucket_count[4], wid, waves, pairs, buf[threadIdx.x / kWave], rs);
+}
+
+// Buckets 5..7: one workgroup per segment. 513..8192 keys: bitonic network
+// in LDS over the next power of two, padded with the maximum key. Above
+// 8192: in place in global memory, with the network in the form whose every
+// comparator puts the smaller key at the lower index (each merge starts by
+// comparing mirrored positions), so positions at or beyond the segment
+// length act as +infinity and are never touched.
+constexpr int kLargeThreads = 512;
+constexpr int kLargeCap = 8192;
+
+__global__ void __launch_bounds__(kLargeThreads) sort_large_kernel(const uint32_t* __restrict__ bin_off,
+                                                                   const uint32_t* __restrict__ lists, int64_t nseg,
+                                                                   const uint32_t* __restrict__ bucket_count,
+                                                                   uint64_t* pairs, RecordSink rs) {
+    __shared__ uint64_t buf[kLargeCap];
+    for (int bucket = 5; bucket <= 6; ++bucket) {
+        const uint32_t cnt = bucket_count[bucket];
+        const uint32_t* list = lists + (int64_t)bucket * nseg;
+        for (uint32_t i = blockIdx.x; i < cnt; i += gridDim.x) {
+            const uint32_t s = list[i];
+            const uint32_t begin = bin_off[s], len = bin_off[s + 1] - begin;
+            uint32_t P = 1;
+            while (P < len) P <<= 1;
+            for (uint32_t e = threadIdx.x; e < P; e += kLargeThreads) buf[e] = e < len ? pairs[begin + e] : ~0ull;
+            __syncthreads();
+            for (uint32_t k = 2; k <= P; k <<= 1) {
+                for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+                    for (uint32_t t = threadIdx.x; t < P / 2; t += kLargeThreads) {
+                        const uint32_t lo = (t / j) * 2 * j + (t % j), hi = lo + j;
+                        const uint64_t a = buf[lo], b = buf[hi];
+                        const bool up = (lo & k) == 0;
+                        if ((a > b) == up) {
+                            buf[lo] = b;
+                            buf[hi] = a;
+                        }
+                    }
+                    __syncthreads();
+                }
+            }
+            for (uint32_t e = threadIdx.x; e < len; e += kLargeThreads) {
+                pairs[begin + e] = buf[e];
+                rs.put(s, begin + e, buf[e]);
+            }
+            __syncthreads();
+        }
+    }
+    const uint32_t cnt = bucket_count[7];
+    const uint32_t* list = lists + 7 * nseg;
     for (uint32_t i = blockIdx.x; i < cnt; i += gridDim.x) {
         const uint32_t s = list[i];
         const uint32_t begin = bin_off[s], len = bin_off[s + 1] - begin;
@@ -398,7 +417,7 @@ __global__ void __launch_bounds__(1024) sort_tail_kernel(const uint32_t* __restr
         while (P < len) P <<= 1;
         for (uint32_t k = 2; k <= P; k <<= 1) {
             const uint32_t h = k >> 1;
-            for (uint32_t t = threadIdx.x; t < P / 2; t += blockDim.x) {
+            for (uint32_t t = threadIdx.x; t < P / 2; t += kLargeThreads) {
                 const uint32_t blk = t / h, off = t % h;
                 const uint32_t lo = blk * k + off, hi = blk * k + k - 1 - off;
                 if (hi < len) {
@@ -411,7 +430,7 @@ __global__ void __launch_bounds__(1024) sort_tail_kernel(const uint32_t* __restr
             }
             __syncthreads();
             for (uint32_t j = k >> 2; j > 0; j >>= 1) {
-                for (uint32_t t = threadIdx.x; t < P / 2; t += blockDim.x) {
+                for (uint32_t t = threadIdx.x; t < P / 2; t += kLargeThreads) {
                     const uint32_t lo = (t / j) * 2 * j + (t % j), hi = lo + j;
                     if (hi < len) {
                         const uint64_t x = a[lo], y = a[hi];
@@ -424,7 +443,7 @@ __global__ void __launch_bounds__(1024) sort_tail_kernel(const uint32_t* __restr
                 __syncthreads();
             }
         }
-        for (uint32_t e = threadIdx.x; e < len; e += blockDim.x) rs.put(s, begin + e, a[e]);
+        for (uint32_t e = threadIdx.x; e < len; e += kLargeThreads) rs.put(s, begin + e, a[e]);
         __syncthreads();
     }
 }
@@ -435,15 +454,37 @@ __global__ void __launch_bounds__(1024) sort_tail_kernel(const uint32_t* __restr
 
 constexpr int kOrderBuckets = 33;
 
+__device__ __forceinline__ int order_bucket(uint32_t c) { return c ? __builtin_clz(c) : 32; }
+
+// Counts per bucket are aggregated per wavefront (one LDS atomic per
+// distinct bucket value in the wavefront) before the LDS atomics.
+__device__ __forceinline__ uint32_t wave_aggregated_add(uint32_t* ctr, int b, bool active) {
+    uint32_t slot = 0;
+    uint64_t pending = ballot(active);
+    while (pending) {
+        const int leader = __builtin_ctzll(pending);
+        const int lb = (int)shfl_u32((uint32_t)b, leader);
+        const uint64_t m = ballot(active && b == lb);
+        uint32_t base = 0;
+        if (lane() == leader) base = atomicAdd(&ctr[lb], (uint32_t)__builtin_popcountll(m));
+        base = shfl_u32(base, leader);
+        if (active && b == lb) slot = base + rank_in(m);
+        pending &= ~m;
+    }
+    return slot;
+}
+
 __global__ void __launch_bounds__(1024) tile_order_kernel(const uint32_t* __restrict__ offsets, int stride,
                                                           int64_t T, uint32_t* __restrict__ order) {
     __shared__ uint32_t hist[kOrderBuckets], cur[kOrderBuckets];
     if (threadIdx.x < kOrderBuckets) hist[threadIdx.x] = 0;
     __syncthreads();
-    for (int64_t t = threadIdx.x; t < T; t += blockDim.x) {
-        const uint32_t c = offsets[(t + 1) * stride] - offsets[t * stride];
-        const int b = 32 - (c ? 32 - __builtin_clz(c) : 0);
-        atomicAdd(&hist[b], 1u);
+    const int64_t rounds = (T + blockDim.x - 1) / blockDim.x;
+    for (int64_t r = 0; r < rounds; ++r) {
+        const int64_t t = r * blockDim.x + threadIdx.x;
+        const bool act = t < T;
+        const int b = act ? order_bucket(offsets[(t + 1) * stride] - offsets[t * stride]) : 0;
+        (void)wave_aggregated_add(hist, b, act);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -454,10 +495,12 @@ __global__ void __launch_bounds__(1024) tile_order_kernel(const uint32_t* __rest
         }
     }
     __syncthreads();
-    for (int64_t t = threadIdx.x; t < T; t += blockDim.x) {
-        const uint32_t c = offsets[(t + 1) * stride] - offsets[t * stride];
-        const int b = 32 - (c ? 32 - __builtin_clz(c) : 0);
-        order[atomicAdd(&cur[b], 1u)] = (uint32_t)t;
+    for (int64_t r = 0; r < rounds; ++r) {
+        const int64_t t = r * blockDim.x + threadIdx.x;
+        const bool act = t < T;
+        const int b = act ? order_bucket(offsets[(t + 1) * stride] - offsets[t * stride]) : 0;
+        const uint32_t pos = wave_aggregated_add(cur, b, act);
+        if (act) order[pos] = (uint32_t)t;
     }
 }
 
@@ -469,18 +512,13 @@ __global__ void __launch_bounds__(256) emit_keys_kernel(const uint4* __restrict_
                                                         const uint32_t* __restrict__ emit_off, int tiles_x,
                                                         int tiles_y, uint64_t* __restrict__ keys,
                                                         uint32_t* __restrict__ vals, int64_t capacity) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= n) return;
-    const uint4 in = info[g];
-    int x0, y0, x1, y1;
-    if (rect_of(in, tiles_x, tiles_y, x0, y0, x1, y1) == 0) return;
-    int64_t e = emit_off[g];
-    for (int y = y0; y < y1; ++y)
-        for (int x = x0; x < x1; ++x, ++e) {
-            if (e >= capacity) return;
-            keys[e] = ((uint64_t)(y * tiles_x + x) << 32) | in.x;
-            vals[e] = (uint32_t)g;
-        }
+    __shared__ WaveGauss wg[4];
+    for_wave_entries<false>(info, n, emit_off, tiles_x, tiles_y, nullptr, 1, &wg[threadIdx.x / kWave],
+                            [&](int64_t gid, int tx, int ty, int64_t e, uint32_t key, uint32_t) {
+                                if (e >= capacity) return;
+                                keys[e] = ((uint64_t)(ty * tiles_x + tx) << 32) | key;
+                                vals[e] = (uint32_t)gid;
+                            });
 }
 
 // tile_off[t] = first position whose tile is >= t (t = 0..T).
@@ -531,27 +569,13 @@ hipError_t launch_bin_scatter(const uint32_t* info, int64_t n, const uint32_t* e
     return hipGetLastError();
 }
 
-hipError_t launch_repair(const uint32_t* bin_off, int64_t nseg, uint64_t* pairs, uint32_t* seg_lists,
-                         uint32_t* bucket_count, const int64_t* counters, RecordSink rs, hipStream_t s) {
+hipError_t launch_repair(const uint32_t* bin_off, int64_t nseg, uint64_t* pairs, const uint32_t* seg_lists,
+                         const uint32_t* bucket_count, RecordSink rs, hipStream_t s) {
     if (nseg == 0) return hipSuccess;
-    hipError_t e = launch_fill_u32(bucket_count, 0u, kBuckets, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(classify_kernel, dim3(grid_for(nseg, 256 * kClassifyItems)), dim3(256), 0, s, bin_off, nseg,
-                       seg_lists, bucket_count, counters);
-    const unsigned wave_blocks = (unsigned)std::min<int64_t>(std::max<int64_t>((nseg + 3) / 4, 1), 8192);
-    hipLaunchKernelGGL((sort_wave_kernel<1>), dim3(wave_blocks), dim3(256), 0, s, bin_off, seg_lists, bucket_count, 0,
+    const unsigned small_blocks = (unsigned)std::min<int64_t>(std::max<int64_t>((nseg + 31) / 32, 1), 4096);
+    hipLaunchKernelGGL(sort_small_kernel, dim3(small_blocks), dim3(256), 0, s, bin_off, seg_lists, nseg, bucket_count,
                        pairs, rs);
-    hipLaunchKernelGGL((sort_wave_kernel<2>), dim3(std::min(wave_blocks, 4096u)), dim3(256), 0, s, bin_off,
-                       seg_lists + nseg, bucket_count, 1, pairs, rs);
-    hipLaunchKernelGGL((sort_wave_kernel<4>), dim3(std::min(wave_blocks, 2048u)), dim3(256), 0, s, bin_off,
-                       seg_lists + 2 * nseg, bucket_count, 2, pairs, rs);
-    hipLaunchKernelGGL((sort_wave_kernel<8>), dim3(std::min(wave_blocks, 2048u)), dim3(256), 0, s, bin_off,
-                       seg_lists + 3 * nseg, bucket_count, 3, pairs, rs);
-    hipLaunchKernelGGL((sort_lds_kernel<1024, 4096>), dim3(512), dim3(1024), 0, s, bin_off, seg_lists + 4 * nseg,
-                       bucket_count, 4, pairs, rs);
-    hipLaunchKernelGGL((sort_lds_kernel<1024, 8192>), dim3(256), dim3(1024), 0, s, bin_off, seg_lists + 5 * nseg,
-                       bucket_count, 5, pairs, rs);
-    hipLaunchKernelGGL(sort_tail_kernel, dim3(64), dim3(1024), 0, s, bin_off, seg_lists + 6 * nseg, bucket_count, 6,
+    hipLaunchKernelGGL(sort_large_kernel, dim3(512), dim3(kLargeThreads), 0, s, bin_off, seg_lists, nseg, bucket_count,
                        pairs, rs);
     return hipGetLastError();
 }

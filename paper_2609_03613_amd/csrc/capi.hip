@@ -76,9 +76,15 @@ tgs_status check_projected(const tgs_projected* pr) {
 inline size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t emit_off, scan_tmp, sample, count, entry_rank, seg_lists, bucket_count, keys_in, vals_in, sort_tmp,
+    size_t emit_off, scan_tmp, sample, zero, zero_words, entry_rank, seg_lists, keys_in, vals_in, sort_tmp,
         sort_tmp_bytes, total;
 };
+
+// Control words at the start of the zeroed region (uint32 offsets).
+constexpr int kDoneEmit = 0;
+constexpr int kDoneBins = 1;
+constexpr int kBucketCount = 16;
+constexpr int kControlWords = 64;
 
 int end_bit_for(int64_t T) {
     int b = 0;
@@ -86,6 +92,10 @@ int end_bit_for(int64_t T) {
     return 32 + (b > 0 ? b : 1);
 }
 
+// Workspace: [emit offsets][scan partials][depth samples][zeroed region:
+// control words, per-XCD counts][entry ranks][repair lists] (BINNED) or
+// [...][zeroed control words][unsorted keys][unsorted ids][sort scratch]
+// (GLOBAL).
 Layout layout(int64_t n, int64_t capacity, int64_t T, int K, int order) {
     Layout L{};
     size_t off = 0;
@@ -100,11 +110,13 @@ Layout layout(int64_t n, int64_t capacity, int64_t T, int K, int order) {
     L.scan_tmp = take(sizeof(uint32_t) * scan_tmp_words(scan_n));
     L.sample = take(sizeof(uint32_t) * 8192);
     if (order == TGS_ORDER_BINNED) {
-        L.count = take(sizeof(uint32_t) * (size_t)kXcc * (size_t)nseg);
+        L.zero_words = (size_t)kControlWords + (size_t)kXcc * (size_t)nseg;
+        L.zero = take(sizeof(uint32_t) * L.zero_words);
         L.entry_rank = take(sizeof(uint32_t) * (size_t)capacity);
         L.seg_lists = take(sizeof(uint32_t) * (size_t)kBuckets * (size_t)nseg);
-        L.bucket_count = take(sizeof(uint32_t) * 64);
     } else {
+        L.zero_words = (size_t)kControlWords;
+        L.zero = take(sizeof(uint32_t) * L.zero_words);
         L.keys_in = take(sizeof(uint64_t) * (size_t)capacity);
         L.vals_in = take(sizeof(uint32_t) * (size_t)capacity);
         L.sort_tmp_bytes = global_sort_tmp_bytes(capacity, end_bit_for(T)) + 1024;
@@ -188,10 +200,13 @@ tgs_status tgs_bin(const tgs_projected* pr, const tgs_camera* cam, const tgs_par
     uint32_t* emit_off = (uint32_t*)(w + L.emit_off);
     uint32_t* tmp = (uint32_t*)(w + L.scan_tmp);
     uint32_t* sample = (uint32_t*)(w + L.sample);
+    uint32_t* zero = (uint32_t*)(w + L.zero);
     const int S = params->sample_count;
-
     const int tiles_x = div_up(cam->width, kTile), tiles_y = div_up(cam->height, kTile);
-    TGS_HIP(launch_emit_scan(pr->info_dev, n, tiles_x, tiles_y, emit_off, tmp, out->counters_dev, cap, sample, S, s),
+
+    TGS_HIP(launch_fill_u32(zero, 0u, (int64_t)L.zero_words, s), "clear control words");
+    TGS_HIP(launch_emit_scan(pr->info_dev, n, tiles_x, tiles_y, emit_off, tmp, zero + kDoneEmit, out->counters_dev, cap,
+                             sample, S, nullptr, 0, s),
             "emit scan");
     int64_t M = -1;
     if (num_entries_host || order == TGS_ORDER_GLOBAL) {
@@ -211,26 +226,26 @@ tgs_status tgs_bin(const tgs_projected* pr, const tgs_camera* cam, const tgs_par
         if (out->tile_order_dev) TGS_HIP(launch_tile_order(out->offsets_dev, 1, T, out->tile_order_dev, s), "tile order");
         return TGS_OK;
     }
-    uint32_t* count = (uint32_t*)(w + L.count);
+    uint32_t* count = zero + kControlWords;
     uint32_t* entry_rank = (uint32_t*)(w + L.entry_rank);
     uint32_t* seg_lists = (uint32_t*)(w + L.seg_lists);
-    uint32_t* bucket_count = (uint32_t*)(w + L.bucket_count);
+    uint32_t* bucket_count = zero + kBucketCount;
     const int64_t nseg = T * K;
     RecordSink rs{reinterpret_cast<const float4*>(pr->splats_dev),
                   params->packed ? reinterpret_cast<float4*>(out->records_dev) : nullptr, K, tiles_x};
     TGS_HIP(launch_depth_range(sample, out->counters_dev, S, params->p_lo, params->p_hi, params->pad, (float)cam->znear,
                                (float)cam->zfar, out->zrange_dev, s),
             "depth range");
-    TGS_HIP(launch_fill_u32(count, 0u, (int64_t)kXcc * nseg, s), "clear counts");
     TGS_HIP(launch_bin_count(pr->info_dev, n, emit_off, out->zrange_dev, K, tiles_x, tiles_y, count, nseg, entry_rank,
                              cap, s),
             "bin count");
-    TGS_HIP(launch_bin_offsets(count, nseg, out->offsets_dev, tmp, s), "bin offsets");
+    TGS_HIP(launch_bin_offsets(count, nseg, out->offsets_dev, tmp, zero + kDoneBins, seg_lists, bucket_count,
+                               out->counters_dev, s),
+            "bin offsets");
     TGS_HIP(launch_bin_scatter(pr->info_dev, n, emit_off, out->zrange_dev, K, tiles_x, tiles_y, out->offsets_dev, count,
                                nseg, entry_rank, out->pairs_dev, cap, rs, s),
             "bin scatter");
-    TGS_HIP(launch_repair(out->offsets_dev, nseg, out->pairs_dev, seg_lists, bucket_count, out->counters_dev, rs, s),
-            "repair");
+    TGS_HIP(launch_repair(out->offsets_dev, nseg, out->pairs_dev, seg_lists, bucket_count, rs, s), "repair");
     if (out->tile_order_dev) TGS_HIP(launch_tile_order(out->offsets_dev, K, T, out->tile_order_dev, s), "tile order");
     return TGS_OK;
 }

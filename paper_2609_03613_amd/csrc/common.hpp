@@ -119,20 +119,17 @@ Cam make_cam(const tgs_camera& c);
 hipError_t launch_project(const tgs_gaussians& g, const Cam& cam, float* splats, uint32_t* info,
                           hipStream_t s);
 
-// Exclusive scan of n uint32 values (in may equal out). `total` (device, may
-// be null) receives the sum. tmp needs scan_tmp_words(n) uint32 words.
+// Scratch words for the scans' partial sums.
 size_t scan_tmp_words(int64_t n);
-hipError_t launch_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* tmp, uint32_t* total,
-                           hipStream_t s);
 
-// Entry emission scan over the info array: emit_off[g] = sum of n_tiles
-// before g; counters[0] = M, counters[1] = V (visible); the depth samples
-// for the range estimate are written to sample[] (see the kernel).
-// counters[2] is set to 1 when M exceeds `capacity`; every later stage
-// then skips its writes beyond the buffers.
+// Entry emission scan over the info array: emit_off[g] = number of entries
+// of the Gaussians before g; counters[0] = M, counters[1] = V (visible),
+// counters[2] = 1 when M exceeds `capacity` (every later stage then skips
+// its writes beyond the buffers); the depth samples for the range estimate
+// are written to sample[]. `done` must be zero (it is left zero).
 hipError_t launch_emit_scan(const uint32_t* info, int64_t n, int tiles_x, int tiles_y, uint32_t* emit_off,
-                            uint32_t* tmp, int64_t* counters, int64_t capacity, uint32_t* sample, int S,
-                            hipStream_t s);
+                            uint32_t* tmp, uint32_t* done, int64_t* counters, int64_t capacity, uint32_t* sample,
+                            int S, uint32_t* zero, int64_t zero_words, hipStream_t s);
 
 hipError_t launch_depth_range(const uint32_t* sample, const int64_t* counters, int S, float p_lo,
                               float p_hi, float pad, float znear, float zfar, float* zrange,
@@ -146,18 +143,37 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_bin_count(const uint32_t* info, int64_t n, const uint32_t* emit_off, const float* zrange,
                             int K, int tiles_x, int tiles_y, uint32_t* count, int64_t nseg, uint32_t* entry_rank,
                             int64_t capacity, hipStream_t s);
-// bin_off[s] = exclusive scan of the summed copies; count[x][s] becomes the
-// base position of copy x inside segment s; bin_off[nseg] = M.
-size_t bin_offsets_tmp_words(int64_t nseg);
-hipError_t launch_bin_offsets(uint32_t* count, int64_t nseg, uint32_t* bin_off, uint32_t* tmp, hipStream_t s);
+// Repair length buckets: 2..8, 9..16, 17..32, 33..64 (lane groups of one
+// wavefront, registers), 65..512 (one wavefront, LDS), 513..4096 and
+// 4097..8192 (one workgroup, LDS), above 8192 (one workgroup, global memory).
+constexpr int kBuckets = 8;
+__host__ __device__ __forceinline__ int bucket_of(uint32_t len) {
+    if (len <= 1) return -1;
+    if (len <= 8) return 0;
+    if (len <= 16) return 1;
+    if (len <= 32) return 2;
+    if (len <= 64) return 3;
+    if (len <= 512) return 4;
+    if (len <= 4096) return 5;
+    if (len <= 8192) return 6;
+    return 7;
+}
+
+// bin_off[s] = exclusive scan of the summed copies (bin_off[nseg] = M);
+// count[x][s] becomes the base position of copy x inside segment s; every
+// segment of two or more entries is appended to lists[bucket][...] with
+// bucket_count[bucket] entries (not when counters[2] flags an overflow).
+// `done` and bucket_count must be zero.
+hipError_t launch_bin_offsets(uint32_t* count, int64_t nseg, uint32_t* bin_off, uint32_t* tmp, uint32_t* done,
+                              uint32_t* lists, uint32_t* bucket_count, const int64_t* counters, hipStream_t s);
 hipError_t launch_bin_scatter(const uint32_t* info, int64_t n, const uint32_t* emit_off, const float* zrange,
                               int K, int tiles_x, int tiles_y, const uint32_t* bin_off, const uint32_t* base,
                               int64_t nseg, const uint32_t* entry_rank, uint64_t* pairs, int64_t capacity,
                               RecordSink rs, hipStream_t s);
 
-constexpr int kBuckets = 7;
-hipError_t launch_repair(const uint32_t* bin_off, int64_t nseg, uint64_t* pairs, uint32_t* seg_lists,
-                         uint32_t* bucket_count, const int64_t* counters, RecordSink rs, hipStream_t s);
+// Sorts every queued segment by its 64-bit pairs and writes its records.
+hipError_t launch_repair(const uint32_t* bin_off, int64_t nseg, uint64_t* pairs, const uint32_t* seg_lists,
+                         const uint32_t* bucket_count, RecordSink rs, hipStream_t s);
 
 // Tiles in descending order of their entry count (coarse: by bit length of
 // the count), so the heaviest tiles are dispatched first.

@@ -1,7 +1,9 @@
-// Exclusive prefix sums: reduce -> scan of block sums -> apply, with
-// wavefront shuffles inside a workgroup. Used for the per-Gaussian entry
-// offsets (fused with the visible-Gaussian ranks and the depth-range
-// sampling) and for the (tile, bin) counts -> bin offsets.
+// Exclusive prefix sums, two launches each: (1) per-block partial sums, the
+// last block to finish scanning the partials; (2) per-block apply. Items are
+// read in coalesced rounds of 256 per workgroup. Used for the per-Gaussian
+// entry offsets (fused with the visible-Gaussian ranks and the depth-range
+// sampling) and for the (tile, bin) counts -> bin offsets (fused with the
+// per-XCD bases and the repair-bucket classification).
 #include "common.hpp"
 
 namespace tgs {
@@ -9,9 +11,8 @@ namespace tgs {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kItems = 16;
-constexpr int kPerBlock = kThreads * kItems;
-constexpr int kTopThreads = 1024;
+constexpr int kRounds = 16;
+constexpr int kPerBlock = kThreads * kRounds;
 
 struct U64x2 {
     uint64_t x, y;
@@ -66,105 +67,75 @@ __device__ __forceinline__ V block_excl(V v, V* lds, V* total) {
     return r;
 }
 
-// ---- generic uint32 scan -------------------------------------------------
-
-__global__ void __launch_bounds__(kThreads) u32_reduce(const uint32_t* __restrict__ in, int64_t n,
-                                                       uint32_t* __restrict__ block_sums) {
-    __shared__ uint32_t lds[kThreads / kWave + 1];
-    const int64_t base = (int64_t)blockIdx.x * kPerBlock + (int64_t)threadIdx.x * kItems;
-    uint32_t s = 0;
-#pragma unroll
-    for (int k = 0; k < kItems; ++k)
-        if (base + k < n) s += in[base + k];
-    uint32_t total;
-    (void)block_excl<uint32_t, kThreads>(s, lds, &total);
-    if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
-}
-
-// Single workgroup: exclusive scan of the block sums in place; *total = sum.
-__global__ void __launch_bounds__(kTopThreads) u32_top(uint32_t* __restrict__ block_sums, int64_t nb,
-                                                       uint32_t* __restrict__ total_out) {
-    __shared__ uint32_t lds[kTopThreads / kWave + 1];
-    uint32_t carry = 0;
-    for (int64_t base = 0; base < nb; base += kTopThreads) {
+// Called by every block after writing its partial: the block that finishes
+// last replaces the partials by their exclusive scan, writes the total and
+// resets the done counter for the next launch. The device-scope fences make
+// the partials of all XCDs visible to it.
+template <typename V>
+__device__ __forceinline__ bool last_block_scan(V* partials, int64_t nb, uint32_t* done, V* lds, V* total_out) {
+    __shared__ int is_last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) is_last = atomicAdd(done, 1u) == (uint32_t)(nb - 1);
+    __syncthreads();
+    if (!is_last) return false;
+    __threadfence();
+    V carry;
+    set_zero(carry);
+    for (int64_t base = 0; base < nb; base += kThreads) {
         const int64_t i = base + threadIdx.x;
-        const uint32_t v = i < nb ? block_sums[i] : 0u;
-        uint32_t tot;
-        const uint32_t ex = block_excl<uint32_t, kTopThreads>(v, lds, &tot);
-        if (i < nb) block_sums[i] = carry + ex;
-        carry += tot;
+        V v;
+        set_zero(v);
+        if (i < nb) v = partials[i];
+        V tot;
+        const V ex = block_excl<V, kThreads>(v, lds, &tot);
+        if (i < nb) partials[i] = carry + ex;
+        carry = carry + tot;
     }
-    if (threadIdx.x == 0 && total_out) *total_out = carry;
-}
-
-__global__ void __launch_bounds__(kThreads) u32_apply(const uint32_t* in, uint32_t* out, int64_t n,
-                                                      const uint32_t* __restrict__ block_off) {
-    __shared__ uint32_t lds[kThreads / kWave + 1];
-    const int64_t base = (int64_t)blockIdx.x * kPerBlock + (int64_t)threadIdx.x * kItems;
-    uint32_t v[kItems];
-    uint32_t s = 0;
-#pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-        v[k] = base + k < n ? in[base + k] : 0u;
-        s += v[k];
+    if (threadIdx.x == 0) {
+        *total_out = carry;
+        *done = 0;
     }
-    uint32_t total;
-    uint32_t run = block_off[blockIdx.x] + block_excl<uint32_t, kThreads>(s, lds, &total);
-#pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-        if (base + k < n) out[base + k] = run;
-        run += v[k];
-    }
+    return true;
 }
 
 // ---- entry-emission scan over the info array --------------------------------
 // x: number of tiles (entries) per Gaussian, y: 1 if visible.
 
-__device__ __forceinline__ U64x2 emit_val(const uint32_t* info, int64_t g, int64_t n, int tiles_x, int tiles_y) {
+__device__ __forceinline__ U64x2 emit_val(const uint4* info, int64_t g, int64_t n, int tiles_x, int tiles_y) {
     U64x2 r;
     set_zero(r);
     if (g < n) {
-        const uint4 in = reinterpret_cast<const uint4*>(info)[g];
         int x0, y0, x1, y1;
-        const int nt = rect_of(in, tiles_x, tiles_y, x0, y0, x1, y1);
+        const int nt = rect_of(info[g], tiles_x, tiles_y, x0, y0, x1, y1);
         r.x = (uint64_t)nt;
         r.y = nt > 0 ? 1ull : 0ull;
     }
     return r;
 }
 
-__global__ void __launch_bounds__(kThreads) emit_reduce(const uint32_t* __restrict__ info, int64_t n, int tiles_x,
-                                                        int tiles_y, U64x2* __restrict__ block_sums) {
+// Also clears the `zero_words` control words (count copies, repair queues)
+// that later kernels of the same tgs_bin call accumulate into.
+__global__ void __launch_bounds__(kThreads) emit_reduce(const uint4* __restrict__ info, int64_t n, int tiles_x,
+                                                        int tiles_y, U64x2* __restrict__ partials, uint32_t* done,
+                                                        int64_t* __restrict__ counters, int64_t capacity,
+                                                        uint32_t* __restrict__ zero, int64_t zero_words) {
     __shared__ U64x2 lds[kThreads / kWave + 1];
-    const int64_t base = (int64_t)blockIdx.x * kPerBlock + (int64_t)threadIdx.x * kItems;
+    const int64_t nb = gridDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < zero_words; i += (int64_t)gridDim.x * kThreads)
+        zero[i] = 0u;
     U64x2 s;
     set_zero(s);
-#pragma unroll
-    for (int k = 0; k < kItems; ++k) s = s + emit_val(info, base + k, n, tiles_x, tiles_y);
+    const int64_t base = (int64_t)blockIdx.x * kPerBlock;
+    for (int r = 0; r < kRounds; ++r) s = s + emit_val(info, base + r * kThreads + threadIdx.x, n, tiles_x, tiles_y);
     U64x2 total;
     (void)block_excl<U64x2, kThreads>(s, lds, &total);
-    if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
-}
-
-__global__ void __launch_bounds__(kTopThreads) emit_top(U64x2* __restrict__ block_sums, int64_t nb,
-                                                        int64_t* __restrict__ counters, int64_t capacity) {
-    __shared__ U64x2 lds[kTopThreads / kWave + 1];
-    U64x2 carry;
-    set_zero(carry);
-    for (int64_t base = 0; base < nb; base += kTopThreads) {
-        const int64_t i = base + threadIdx.x;
-        U64x2 v;
-        set_zero(v);
-        if (i < nb) v = block_sums[i];
-        U64x2 tot;
-        const U64x2 ex = block_excl<U64x2, kTopThreads>(v, lds, &tot);
-        if (i < nb) block_sums[i] = carry + ex;
-        carry = carry + tot;
-    }
-    if (threadIdx.x == 0) {
-        counters[0] = (int64_t)carry.x;
-        counters[1] = (int64_t)carry.y;
-        counters[2] = (int64_t)carry.x > capacity ? 1 : 0;
+    if (threadIdx.x == 0) partials[blockIdx.x] = total;
+    U64x2 all;
+    if (last_block_scan(partials, nb, done, lds, &all) && threadIdx.x == 0) {
+        counters[0] = (int64_t)all.x;
+        counters[1] = (int64_t)all.y;
+        counters[2] = (int64_t)all.x > capacity ? 1 : 0;
         counters[3] = 0;
     }
 }
@@ -174,97 +145,122 @@ __global__ void __launch_bounds__(kTopThreads) emit_top(U64x2* __restrict__ bloc
 // otherwise the visible Gaussians at ranks floor(i V / S), i < S, each
 // stored at its i. A rank r is such a rank iff i = ceil(r S / V) < S and
 // floor(i V / S) == r.
-__global__ void __launch_bounds__(kThreads) emit_apply(const uint32_t* __restrict__ info, int64_t n, int tiles_x,
+__global__ void __launch_bounds__(kThreads) emit_apply(const uint4* __restrict__ info, int64_t n, int tiles_x,
                                                        int tiles_y, uint32_t* __restrict__ emit_off,
                                                        const U64x2* __restrict__ block_off,
                                                        const int64_t* __restrict__ counters,
                                                        uint32_t* __restrict__ sample, int S) {
     __shared__ U64x2 lds[kThreads / kWave + 1];
-    const int64_t base = (int64_t)blockIdx.x * kPerBlock + (int64_t)threadIdx.x * kItems;
-    U64x2 v[kItems];
-    U64x2 s;
-    set_zero(s);
-#pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-        v[k] = emit_val(info, base + k, n, tiles_x, tiles_y);
-        s = s + v[k];
-    }
-    U64x2 total;
-    U64x2 run = block_off[blockIdx.x] + block_excl<U64x2, kThreads>(s, lds, &total);
     const int64_t V = counters[1];
-#pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-        const int64_t g = base + k;
+    U64x2 carry = block_off[blockIdx.x];
+    const int64_t base = (int64_t)blockIdx.x * kPerBlock;
+    for (int r = 0; r < kRounds; ++r) {
+        if (base + (int64_t)r * kThreads >= n) break;  // uniform across the workgroup
+        const int64_t g = base + r * kThreads + threadIdx.x;
+        const U64x2 v = emit_val(info, g, n, tiles_x, tiles_y);
+        U64x2 tot;
+        const U64x2 run = carry + block_excl<U64x2, kThreads>(v, lds, &tot);
+        carry = carry + tot;
         if (g < n) {
             emit_off[g] = (uint32_t)run.x;
-            if (v[k].y) {
-                const int64_t r = (int64_t)run.y;
+            if (v.y) {
+                const int64_t rk = (int64_t)run.y;
                 int64_t i = -1;
                 if (V <= S) {
-                    i = r;
+                    i = rk;
                 } else {
-                    const int64_t c = (r * S + V - 1) / V;
-                    if (c < S && (c * V) / S == r) i = c;
+                    const int64_t c = (rk * S + V - 1) / V;
+                    if (c < S && (c * V) / S == rk) i = c;
                 }
-                if (i >= 0) sample[i] = info[4 * g];
+                if (i >= 0) sample[i] = info[g].x;
             }
         }
-        run = run + v[k];
     }
 }
 
 // ---- bin offsets from the per-XCD count copies ---------------------------
 
-__global__ void __launch_bounds__(kThreads) bo_reduce(const uint32_t* __restrict__ count, int64_t nseg,
-                                                      uint32_t* __restrict__ block_sums) {
-    __shared__ uint32_t lds[kThreads / kWave + 1];
-    const int64_t base = (int64_t)blockIdx.x * kPerBlock + (int64_t)threadIdx.x * kItems;
-    uint32_t s = 0;
-    for (int x = 0; x < kXcc; ++x) {
-        const uint32_t* c = count + (int64_t)x * nseg;
+__device__ __forceinline__ uint32_t seg_total(const uint32_t* __restrict__ count, int64_t nseg, int64_t s) {
+    uint32_t t = 0;
+    if (s < nseg)
 #pragma unroll
-        for (int k = 0; k < kItems; ++k)
-            if (base + k < nseg) s += c[base + k];
-    }
-    uint32_t total;
-    (void)block_excl<uint32_t, kThreads>(s, lds, &total);
-    if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
+        for (int x = 0; x < kXcc; ++x) t += count[(int64_t)x * nseg + s];
+    return t;
 }
 
-// bin_off[s] = exclusive prefix of the summed copies; count[x][s] is then
-// replaced by bin_off[s] + the counts of copies 0..x-1 in segment s.
+__global__ void __launch_bounds__(kThreads) bo_reduce(const uint32_t* __restrict__ count, int64_t nseg,
+                                                      uint32_t* __restrict__ partials, uint32_t* done,
+                                                      uint32_t* __restrict__ total_out) {
+    __shared__ uint32_t lds[kThreads / kWave + 1];
+    const int64_t nb = gridDim.x;
+    const int64_t base = (int64_t)blockIdx.x * kPerBlock;
+    uint32_t s = 0;
+    for (int r = 0; r < kRounds; ++r) s += seg_total(count, nseg, base + r * kThreads + threadIdx.x);
+    uint32_t total;
+    (void)block_excl<uint32_t, kThreads>(s, lds, &total);
+    if (threadIdx.x == 0) partials[blockIdx.x] = total;
+    (void)last_block_scan(partials, nb, done, lds, total_out);
+}
+
+// bin_off[s] = exclusive prefix of the summed copies; count[x][s] becomes
+// bin_off[s] + the counts of copies 0..x-1 in segment s. Every segment with
+// two or more entries is appended to the list of its repair bucket
+// (aggregated per wavefront and per workgroup: one global atomic per bucket
+// and workgroup). Nothing is queued when the stream overflowed (counters[2]).
 __global__ void __launch_bounds__(kThreads) bo_apply(uint32_t* __restrict__ count, int64_t nseg,
                                                      uint32_t* __restrict__ bin_off,
-                                                     const uint32_t* __restrict__ block_off) {
+                                                     const uint32_t* __restrict__ block_off,
+                                                     uint32_t* __restrict__ lists, uint32_t* __restrict__ bucket_count,
+                                                     const int64_t* __restrict__ counters) {
     __shared__ uint32_t lds[kThreads / kWave + 1];
-    const int64_t base = (int64_t)blockIdx.x * kPerBlock + (int64_t)threadIdx.x * kItems;
-    uint32_t tot[kItems];
+    __shared__ uint32_t lcount[kBuckets], lbase[kBuckets];
+    if (threadIdx.x < kBuckets) lcount[threadIdx.x] = 0;
+    const bool queue = counters[2] == 0;
+    uint32_t carry = block_off[blockIdx.x];
+    const int64_t base = (int64_t)blockIdx.x * kPerBlock;
+    int bk[kRounds];
+    uint32_t slot[kRounds];
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) tot[k] = 0;
-    for (int x = 0; x < kXcc; ++x) {
-        const uint32_t* c = count + (int64_t)x * nseg;
+    for (int r = 0; r < kRounds; ++r) {
+        const int64_t s = base + r * kThreads + threadIdx.x;
+        const uint32_t v = seg_total(count, nseg, s);
+        uint32_t tot;
+        uint32_t run = carry + block_excl<uint32_t, kThreads>(v, lds, &tot);
+        carry += tot;
+        bk[r] = -1;
+        slot[r] = 0;
+        if (s < nseg) {
+            bin_off[s] = run;
 #pragma unroll
-        for (int k = 0; k < kItems; ++k)
-            if (base + k < nseg) tot[k] += c[base + k];
-    }
-    uint32_t s = 0;
-#pragma unroll
-    for (int k = 0; k < kItems; ++k) s += tot[k];
-    uint32_t total;
-    uint32_t run = block_off[blockIdx.x] + block_excl<uint32_t, kThreads>(s, lds, &total);
-#pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-        if (base + k < nseg) {
-            bin_off[base + k] = run;
-            uint32_t r = run;
             for (int x = 0; x < kXcc; ++x) {
-                uint32_t* c = count + (int64_t)x * nseg + base + k;
-                const uint32_t v = *c;
-                *c = r;
-                r += v;
+                uint32_t* c = count + (int64_t)x * nseg + s;
+                const uint32_t cv = *c;
+                *c = run;
+                run += cv;
             }
+            if (queue) bk[r] = bucket_of(v);
         }
-        run += tot[k];
+        if (ballot(bk[r] >= 0) == 0) continue;
+#pragma unroll
+        for (int k = 0; k < kBuckets; ++k) {
+            const uint64_t m = ballot(bk[r] == k);
+            if (m == 0) continue;
+            const int leader = __builtin_ctzll(m);
+            uint32_t b0 = 0;
+            if (lane() == leader) b0 = atomicAdd(&lcount[k], (uint32_t)__builtin_popcountll(m));
+            b0 = shfl_u32(b0, leader);
+            if (bk[r] == k) slot[r] = b0 + rank_in(m);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < kBuckets)
+        lbase[threadIdx.x] = lcount[threadIdx.x] ? atomicAdd(&bucket_count[threadIdx.x], lcount[threadIdx.x]) : 0u;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+        if (bk[r] < 0) continue;
+        const int64_t s = base + r * kThreads + threadIdx.x;
+        lists[(int64_t)bk[r] * nseg + lbase[bk[r]] + slot[r]] = (uint32_t)s;
     }
 }
 
@@ -277,41 +273,28 @@ __global__ void fill_u32_kernel(uint32_t* p, uint32_t v, int64_t n) {
 
 size_t scan_tmp_words(int64_t n) {
     const int64_t nb = (n + kPerBlock - 1) / kPerBlock;
-    // room for U64x2 block sums (4 words each) plus alignment
-    return (size_t)(4 * (nb + 1) + 16);
-}
-
-hipError_t launch_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* tmp, uint32_t* total,
-                           hipStream_t s) {
-    if (n <= 0) return total ? launch_fill_u32(total, 0u, 1, s) : hipSuccess;
-    const int64_t nb = (n + kPerBlock - 1) / kPerBlock;
-    hipLaunchKernelGGL(u32_reduce, dim3((unsigned)nb), dim3(kThreads), 0, s, in, n, tmp);
-    hipLaunchKernelGGL(u32_top, dim3(1), dim3(kTopThreads), 0, s, tmp, nb, total);
-    hipLaunchKernelGGL(u32_apply, dim3((unsigned)nb), dim3(kThreads), 0, s, in, out, n, tmp);
-    return hipGetLastError();
+    return (size_t)(4 * (nb + 1) + 64);  // U64x2 partials
 }
 
 hipError_t launch_emit_scan(const uint32_t* info, int64_t n, int tiles_x, int tiles_y, uint32_t* emit_off,
-                            uint32_t* tmp, int64_t* counters, int64_t capacity, uint32_t* sample, int S,
-                            hipStream_t s) {
-    const int64_t nb = n > 0 ? (n + kPerBlock - 1) / kPerBlock : 0;
-    U64x2* bs = reinterpret_cast<U64x2*>(tmp);
-    if (nb > 0) hipLaunchKernelGGL(emit_reduce, dim3((unsigned)nb), dim3(kThreads), 0, s, info, n, tiles_x, tiles_y, bs);
-    hipLaunchKernelGGL(emit_top, dim3(1), dim3(kTopThreads), 0, s, bs, nb, counters, capacity);
-    if (nb > 0)
-        hipLaunchKernelGGL(emit_apply, dim3((unsigned)nb), dim3(kThreads), 0, s, info, n, tiles_x, tiles_y, emit_off,
-                           bs, counters, sample, S);
+                            uint32_t* tmp, uint32_t* done, int64_t* counters, int64_t capacity, uint32_t* sample, int S,
+                            uint32_t* zero, int64_t zero_words, hipStream_t s) {
+    const int64_t nb = n > 0 ? (n + kPerBlock - 1) / kPerBlock : 1;
+    U64x2* partials = reinterpret_cast<U64x2*>(tmp);
+    hipLaunchKernelGGL(emit_reduce, dim3((unsigned)nb), dim3(kThreads), 0, s, reinterpret_cast<const uint4*>(info), n,
+                       tiles_x, tiles_y, partials, done, counters, capacity, zero, zero_words);
+    if (n > 0)
+        hipLaunchKernelGGL(emit_apply, dim3((unsigned)nb), dim3(kThreads), 0, s, reinterpret_cast<const uint4*>(info),
+                           n, tiles_x, tiles_y, emit_off, partials, counters, sample, S);
     return hipGetLastError();
 }
 
-size_t bin_offsets_tmp_words(int64_t nseg) { return (size_t)((nseg + kPerBlock - 1) / kPerBlock + 16); }
-
-hipError_t launch_bin_offsets(uint32_t* count, int64_t nseg, uint32_t* bin_off, uint32_t* tmp, hipStream_t s) {
-    if (nseg <= 0) return launch_fill_u32(bin_off, 0u, 1, s);
-    const int64_t nb = (nseg + kPerBlock - 1) / kPerBlock;
-    hipLaunchKernelGGL(bo_reduce, dim3((unsigned)nb), dim3(kThreads), 0, s, count, nseg, tmp);
-    hipLaunchKernelGGL(u32_top, dim3(1), dim3(kTopThreads), 0, s, tmp, nb, bin_off + nseg);
-    hipLaunchKernelGGL(bo_apply, dim3((unsigned)nb), dim3(kThreads), 0, s, count, nseg, bin_off, tmp);
+hipError_t launch_bin_offsets(uint32_t* count, int64_t nseg, uint32_t* bin_off, uint32_t* tmp, uint32_t* done,
+                              uint32_t* lists, uint32_t* bucket_count, const int64_t* counters, hipStream_t s) {
+    const int64_t nb = nseg > 0 ? (nseg + kPerBlock - 1) / kPerBlock : 1;
+    hipLaunchKernelGGL(bo_reduce, dim3((unsigned)nb), dim3(kThreads), 0, s, count, nseg, tmp, done, bin_off + nseg);
+    hipLaunchKernelGGL(bo_apply, dim3((unsigned)nb), dim3(kThreads), 0, s, count, nseg, bin_off, tmp, lists,
+                       bucket_count, counters);
     return hipGetLastError();
 }
 
