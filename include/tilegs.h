@@ -143,6 +143,7 @@ typedef struct {
     uint64_t* pairs_dev;
     uint32_t* offsets_dev;
     float* records_dev;
+    uint8_t* masks_dev;
     float* zrange_dev;
     int64_t* counters_dev;
     uint32_t* tile_order_dev;

@@ -46,7 +46,7 @@ class Params(ctypes.Structure):
 
 class Binned(ctypes.Structure):
     _fields_ = [("capacity", ctypes.c_int64), ("keys", _c_p), ("vals", _c_p), ("pairs", _c_p),
-                ("offsets", _c_p), ("records", _c_p), ("zrange", _c_p), ("counters", _c_p),
+                ("offsets", _c_p), ("records", _c_p), ("masks", _c_p), ("zrange", _c_p), ("counters", _c_p),
                 ("tile_order", _c_p)]
 
 

@@ -94,7 +94,7 @@ class Binned:
         kw = dict(device=device)
         self.counters = torch.zeros(4, dtype=torch.int64, **kw)
         self.zrange = torch.zeros(2, dtype=torch.float32, **kw)
-        self.keys = self.vals = self.pairs = self.records = None
+        self.keys = self.vals = self.pairs = self.records = self.masks = None
         if self.order == L.ORDER_GLOBAL:
             self.keys = torch.empty(cap, dtype=torch.int64, **kw)
             self.vals = torch.empty(cap, dtype=torch.int32, **kw)
@@ -104,12 +104,14 @@ class Binned:
             self.offsets = torch.empty(tiles * num_bins + 1, dtype=torch.int32, **kw)
             if packed:
                 self.records = torch.empty((cap, 12), dtype=torch.float32, **kw)
+                self.masks = torch.empty(cap, dtype=torch.uint8, **kw)
         self.tile_order = torch.empty(max(tiles, 1), dtype=torch.int32, **kw) if tile_order else None
         self.num_entries = None
 
     def c(self):
         return L.Binned(self.capacity, _ptr(self.keys).value, _ptr(self.vals).value, _ptr(self.pairs).value,
-                        _ptr(self.offsets).value, _ptr(self.records).value, _ptr(self.zrange).value,
+                        _ptr(self.offsets).value, _ptr(self.records).value, _ptr(self.masks).value,
+                        _ptr(self.zrange).value,
                         _ptr(self.counters).value, _ptr(self.tile_order).value)
 
 

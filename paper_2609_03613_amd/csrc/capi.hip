@@ -187,7 +187,8 @@ tgs_status tgs_bin(const tgs_projected* pr, const tgs_camera* cam, const tgs_par
     const int K = params->num_bins;
     if (order == TGS_ORDER_BINNED) {
         if (!out->zrange_dev || (cap > 0 && !out->pairs_dev)) return fail(TGS_ERR_INVALID_ARG, "pairs or zrange is NULL");
-        if (params->packed && cap > 0 && !out->records_dev) return fail(TGS_ERR_INVALID_ARG, "records is NULL with packed=1");
+        if (params->packed && cap > 0 && (!out->records_dev || !out->masks_dev))
+            return fail(TGS_ERR_INVALID_ARG, "records or masks is NULL with packed=1");
         if (T * K >= ((int64_t)1 << 31)) return fail(TGS_ERR_INVALID_ARG, "tiles * bins too large");
     } else if (cap > 0 && (!out->keys_dev || !out->vals_dev)) {
         return fail(TGS_ERR_INVALID_ARG, "keys or vals is NULL");
@@ -232,7 +233,8 @@ tgs_status tgs_bin(const tgs_projected* pr, const tgs_camera* cam, const tgs_par
     uint32_t* bucket_count = zero + kBucketCount;
     const int64_t nseg = T * K;
     RecordSink rs{reinterpret_cast<const float4*>(pr->splats_dev),
-                  params->packed ? reinterpret_cast<float4*>(out->records_dev) : nullptr, K, tiles_x};
+                  params->packed ? reinterpret_cast<float4*>(out->records_dev) : nullptr,
+                  params->packed ? out->masks_dev : nullptr, K, tiles_x, cam->width, cam->height};
     TGS_HIP(launch_depth_range(sample, out->counters_dev, S, params->p_lo, params->p_hi, params->pad, (float)cam->znear,
                                (float)cam->zfar, out->zrange_dev, s),
             "depth range");
@@ -274,8 +276,10 @@ tgs_status tgs_rasterize(const tgs_projected* pr, const tgs_binned* b, const tgs
         a.stride = params->num_bins;
         a.pairs = b->pairs_dev;
         a.records = params->packed ? b->records_dev : nullptr;
+        a.masks = params->packed ? b->masks_dev : nullptr;
         if (b->capacity > 0 && !a.pairs) return fail(TGS_ERR_INVALID_ARG, "pairs is NULL");
-        if (params->packed && b->capacity > 0 && !a.records) return fail(TGS_ERR_INVALID_ARG, "records is NULL");
+        if (params->packed && b->capacity > 0 && (!a.records || !a.masks))
+            return fail(TGS_ERR_INVALID_ARG, "records or masks is NULL");
     }
     if (pr->n > 0 && !a.splats && !a.records) return fail(TGS_ERR_INVALID_ARG, "splats is NULL");
     a.width = cam->width;

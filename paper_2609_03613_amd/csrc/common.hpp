@@ -78,29 +78,105 @@ __device__ __forceinline__ int xcc_id() {
 }
 constexpr int kXcc = 8;
 
-// Per-entry packed record: the splat of the entry's Gaussian with its mean
-// made relative to the entry's tile origin as (hi - origin) + lo, followed
-// by the id. The raster stages splats the same way, so both routes give the
-// same bits.
-__device__ __forceinline__ void write_record(float4* __restrict__ rec, const float4* __restrict__ splats, uint32_t gid,
-                                             float ox, float oy) {
+// -0.5 / ln 2: with the conic scaled by it, exp(-q / 2) = exp2(q').
+constexpr float kHalfLog2e = -0.72134752044448170f;
+
+// Staged form of a splat for one tile, as the raster consumes it: mean
+// relative to the tile origin computed as (hi - origin) + lo, conic scaled
+// by kHalfLog2e (off-diagonal doubled), opacity, colour. Both rasters and
+// the packed records use this one function, so every route gives the same
+// bits.
+__device__ __forceinline__ void stage_splat(const float4& a, const float4& b, const float4& c, float ox, float oy,
+                                            float4& s0, float4& s1, float& s2) {
 #pragma clang fp contract(off)
-    const float4 a = splats[3 * (int64_t)gid], b = splats[3 * (int64_t)gid + 1], c = splats[3 * (int64_t)gid + 2];
-    rec[0] = make_float4((a.x - ox) + a.z, (a.y - oy) + a.w, b.x, b.y);
-    rec[1] = make_float4(b.z, b.w, c.x, c.y);
-    rec[2] = make_float4(c.z, __uint_as_float(gid), 0.f, 0.f);
+    s0 = make_float4((a.x - ox) + a.z, (a.y - oy) + a.w, kHalfLog2e * b.x, (2.0f * kHalfLog2e) * b.y);
+    s1 = make_float4(kHalfLog2e * b.z, b.w, c.x, c.y);
+    s2 = c.z;
 }
 
-// Where the repair kernels put packed records (records == null: none).
+// Conservative block test: can q = a dx^2 + 2 b dx dy + c dy^2 (unscaled
+// conic, mean mx, my) reach 2 ln(255 o) at some pixel centre of the box
+// [xa, xb] x [ya, yb]? The minimum of the convex q over the box is 0 when
+// the mean is inside, otherwise the smallest of the four edge minima. The
+// margin exceeds the binary32 error of both this bound and the per-pixel
+// evaluation, so a block that fails the test fails the alpha >= 1/255 test
+// at every one of its pixels.
+__device__ __forceinline__ bool block_may_touch(float mx, float my, float a, float b, float c, float o, float xa,
+                                                float xb, float ya, float yb) {
+    const float dxl = mx - xb, dxh = mx - xa, dyl = my - yb, dyh = my - ya;
+    float qmin = 0.0f;
+    if (!(dxl <= 0.0f && dxh >= 0.0f && dyl <= 0.0f && dyh >= 0.0f)) {
+        const float ic = 1.0f / c, ia = 1.0f / a;
+        qmin = INFINITY;
+        {
+            const float d = dxl, e = fminf(fmaxf(-b * d * ic, dyl), dyh);
+            qmin = fminf(qmin, a * d * d + 2.0f * b * d * e + c * e * e);
+        }
+        {
+            const float d = dxh, e = fminf(fmaxf(-b * d * ic, dyl), dyh);
+            qmin = fminf(qmin, a * d * d + 2.0f * b * d * e + c * e * e);
+        }
+        {
+            const float e = dyl, d = fminf(fmaxf(-b * e * ia, dxl), dxh);
+            qmin = fminf(qmin, a * d * d + 2.0f * b * d * e + c * e * e);
+        }
+        {
+            const float e = dyh, d = fminf(fmaxf(-b * e * ia, dxl), dxh);
+            qmin = fminf(qmin, a * d * d + 2.0f * b * d * e + c * e * e);
+        }
+    }
+    const float mxd = fmaxf(fabsf(dxl), fabsf(dxh)), myd = fmaxf(fabsf(dyl), fabsf(dyh));
+    const float mag = a * mxd * mxd + c * myd * myd + 2.0f * fabsf(b) * mxd * myd;
+    const float tau = 2.0f * __logf(255.0f * o);
+    return qmin <= tau + 1e-3f + 4e-6f * mag;
+}
+
+// Pixel-centre box (tile-local) of the in-image pixels of 8x8 block w of
+// tile (tx, ty); false when the block lies outside the image.
+__device__ __forceinline__ bool block_box(int w, int tx, int ty, int width, int height, float& xa, float& xb,
+                                          float& ya, float& yb) {
+    const int bx = (w & 1) * 8, by = (w >> 1) * 8;
+    const int nx = min(8, width - (tx * kTile + bx)), ny = min(8, height - (ty * kTile + by));
+    if (nx <= 0 || ny <= 0) return false;
+    xa = bx + 0.5f;
+    xb = bx + nx - 0.5f;
+    ya = by + 0.5f;
+    yb = by + ny - 0.5f;
+    return true;
+}
+
+// Where the entry-placing kernels put packed records (records == null:
+// none): record p = staged splat of the entry's Gaussian for its tile
+// ({mx, my, a', 2b'}, {c', opacity, r, g}, {b, id, 0, 0}) and mask p = bit w
+// set when 8x8 block w of the tile may see the splat.
 struct RecordSink {
     const float4* splats;
     float4* records;
-    int K, tiles_x;
+    uint8_t* masks;
+    int K, tiles_x, width, height;
     __device__ __forceinline__ void put(uint32_t seg, uint32_t pos, uint64_t pair) const {
         if (!records) return;
         const uint32_t t = seg / (uint32_t)K;
-        const float ox = (float)((t % (uint32_t)tiles_x) * kTile), oy = (float)((t / (uint32_t)tiles_x) * kTile);
-        write_record(records + 3 * (int64_t)pos, splats, (uint32_t)pair, ox, oy);
+        const int tx = (int)(t % (uint32_t)tiles_x), ty = (int)(t / (uint32_t)tiles_x);
+        const float ox = (float)(tx * kTile), oy = (float)(ty * kTile);
+        const uint32_t gid = (uint32_t)pair;
+        const float4 a = splats[3 * (int64_t)gid], b = splats[3 * (int64_t)gid + 1], c = splats[3 * (int64_t)gid + 2];
+        float4 s0, s1;
+        float s2;
+        stage_splat(a, b, c, ox, oy, s0, s1, s2);
+        float4* rec = records + 3 * (int64_t)pos;
+        rec[0] = s0;
+        rec[1] = s1;
+        rec[2] = make_float4(s2, __uint_as_float(gid), 0.f, 0.f);
+        uint32_t m = 0;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            float xa, xb, ya, yb;
+            if (block_box(w, tx, ty, width, height, xa, xb, ya, yb) &&
+                block_may_touch(s0.x, s0.y, b.x, b.y, b.z, b.w, xa, xb, ya, yb))
+                m |= 1u << w;
+        }
+        masks[pos] = (uint8_t)m;
     }
 };
 
@@ -193,6 +269,7 @@ struct RasterArgs {
     const uint32_t* vals;   // GLOBAL ids
     const uint64_t* pairs;  // BINNED pairs
     const float* records;   // BINNED packed records or null
+    const uint8_t* masks;   // block masks of the packed records
     const int64_t* counters;
     const uint32_t* order;  // tile dispatch order or null
     int width, height, tiles_x, tiles_y;

@@ -11,17 +11,19 @@
 //
 // raster_wave   The binned path's kernel. Each 64-lane wavefront owns one
 //               8x8 pixel block of the tile and walks the tile range on its
-//               own, 64 entries at a time: every lane loads one entry (a
-//               coalesced packed record, or a gather by id), tests with a
-//               conservative bound whether the splat can reach alpha 1/255
-//               at any pixel centre of the block (the tile alpha cull of the
-//               paper's binned kernel, at block granularity), the survivors
-//               are compacted into wavefront-private LDS by ballot + prefix
-//               count (colour staging), and the lanes composite them. A
-//               wavefront exits when all its pixels have terminated, without
-//               workgroup barriers. Culled entries are exactly those whose
-//               alpha test would fail at every pixel of the block, so images,
-//               last ids and contribution counts are unchanged.
+//               own, 64 entries at a time. An entry survives for the block
+//               when a conservative bound says its splat can reach alpha
+//               1/255 at some pixel centre of the block (the tile alpha cull
+//               of the paper's binned kernel, at block granularity): with
+//               packed records the bound was evaluated once per entry when
+//               the record was written (a 4-bit block mask), otherwise each
+//               wavefront evaluates it on the gathered splat. Survivors are
+//               compacted into wavefront-private LDS by ballot + prefix count
+//               (colour staging) and composited by all lanes; a wavefront
+//               exits when all its pixels have terminated, without workgroup
+//               barriers. Culled entries are exactly those whose alpha test
+//               fails at every pixel of the block, so images, last ids and
+//               contribution counts are unchanged.
 #include <math.h>
 
 #include "common.hpp"
@@ -30,14 +32,10 @@ namespace tgs {
 
 namespace {
 
-// -0.5 / ln 2: q' = k q lets exp(-q/2) be evaluated as exp2(q').
-constexpr float kHalfLog2e = -0.72134752044448170f;
-
-// One staged entry: mean relative to the tile origin, conic scaled by
-// kHalfLog2e (b doubled), opacity, colour, stream position.
+// One staged entry (see stage_splat) and its stream position.
 struct Staged {
-    float4 a;  // mx, my, ca', cb2'
-    float4 b;  // cc', opacity, r, g
+    float4 a;  // mx, my, a', 2b'
+    float4 b;  // c', opacity, r, g
     float2 c;  // b, position bits
 };
 
@@ -47,8 +45,11 @@ struct Pix {
     bool done;
 };
 
-// The per-pixel step shared by both kernels (explicit operation order, no
-// implicit contraction, so both produce identical bits).
+// The per-pixel step shared by both kernels, without branches (explicit
+// operation order, no implicit contraction, so both produce identical bits):
+// skip when q < 0 (rounding only) or alpha < 1/255; stop, without
+// compositing, when T (1 - alpha) < 1e-4; otherwise C += alpha T c and
+// T *= 1 - alpha.
 template <bool COUNT>
 __device__ __forceinline__ void blend(Pix& p, float px, float py, const Staged& s) {
 #pragma clang fp contract(off)
@@ -56,44 +57,24 @@ __device__ __forceinline__ void blend(Pix& p, float px, float py, const Staged& 
     const float dy = s.a.y - py;
     const float w = fmaf(s.a.z, dx, s.a.w * dy);
     const float q2 = fmaf(dx, w, (s.b.x * dy) * dy);  // = -q / (2 ln 2)
-    if (q2 > 0.0f) return;                              // q < 0: rounding only
     const float araw = s.b.y * __builtin_amdgcn_exp2f(q2);
-    if (araw < kAlphaMin) return;
-    if (COUNT) p.nsup++;
+    const bool live = !p.done;
+    const bool sup = live && (q2 <= 0.0f) && (araw >= kAlphaMin);
     const float alpha = fminf(kAlphaMax, araw);
     const float test = p.T * (1.0f - alpha);
-    if (test < kTMin) {
-        p.done = true;
-        return;
+    const bool comp = sup && (test >= kTMin);
+    if (COUNT) {
+        p.nvis += live ? 1 : 0;
+        p.nsup += sup ? 1 : 0;
+        p.ncon += comp ? 1 : 0;
     }
-    const float wt = alpha * p.T;
+    p.done = p.done || (sup && !comp);
+    const float wt = comp ? alpha * p.T : 0.0f;
     p.r = fmaf(wt, s.b.z, p.r);
     p.g = fmaf(wt, s.b.w, p.g);
     p.b = fmaf(wt, s.c.x, p.b);
-    p.T = test;
-    p.last = __float_as_int(s.c.y);
-    p.ncon++;
-}
-
-// Stage a splat (12-word layout) for tile origin (ox, oy).
-__device__ __forceinline__ Staged stage_splat(const float4& a, const float4& b, const float4& c, float ox, float oy,
-                                              int32_t pos) {
-#pragma clang fp contract(off)
-    Staged s;
-    s.a = make_float4((a.x - ox) + a.z, (a.y - oy) + a.w, kHalfLog2e * b.x, (2.0f * kHalfLog2e) * b.y);
-    s.b = make_float4(kHalfLog2e * b.z, b.w, c.x, c.y);
-    s.c = make_float2(c.z, __int_as_float(pos));
-    return s;
-}
-
-// Stage a packed record (mean already relative to the tile origin).
-__device__ __forceinline__ Staged stage_record(const float4& a, const float4& b, const float4& c, int32_t pos) {
-#pragma clang fp contract(off)
-    Staged s;
-    s.a = make_float4(a.x, a.y, kHalfLog2e * a.z, (2.0f * kHalfLog2e) * a.w);
-    s.b = make_float4(kHalfLog2e * b.x, b.y, b.z, b.w);
-    s.c = make_float2(c.x, __int_as_float(pos));
-    return s;
+    p.T = comp ? test : p.T;
+    p.last = comp ? __float_as_int(s.c.y) : p.last;
 }
 
 __device__ __forceinline__ void write_pixel(const RasterArgs& A, int x, int y, const Pix& p, bool bad) {
@@ -126,15 +107,28 @@ __device__ __forceinline__ uint32_t id_at(const RasterArgs& A, uint32_t p) {
     return (uint32_t)A.pairs[p];
 }
 
+// The staged entry at stream position p (packed records are already staged).
 template <int SRC>
 __device__ __forceinline__ Staged load_entry(const RasterArgs& A, uint32_t p, float ox, float oy) {
+    Staged s;
     if (SRC == SRC_PACKED) {
         const float4* r = reinterpret_cast<const float4*>(A.records) + 3 * (int64_t)p;
-        return stage_record(r[0], r[1], r[2], (int32_t)p);
+        s.a = r[0];
+        s.b = r[1];
+        s.c = make_float2(r[2].x, __int_as_float((int32_t)p));
+        return s;
     }
     const uint32_t g = id_at<SRC>(A, p);
-    const float4* s = reinterpret_cast<const float4*>(A.splats) + 3 * (int64_t)g;
-    return stage_splat(s[0], s[1], s[2], ox, oy, (int32_t)p);
+    const float4* q = reinterpret_cast<const float4*>(A.splats) + 3 * (int64_t)g;
+    float s2;
+    stage_splat(q[0], q[1], q[2], ox, oy, s.a, s.b, s2);
+    s.c = make_float2(s2, __int_as_float((int32_t)p));
+    return s;
+}
+
+__device__ __forceinline__ int tile_of_block(const RasterArgs& A) {
+    const int T = A.tiles_x * A.tiles_y;
+    return A.order ? (int)A.order[blockIdx.x] : xcd_remap(blockIdx.x, T);
 }
 
 // ---------------------------------------------------------------------------
@@ -144,8 +138,7 @@ __global__ void __launch_bounds__(256) raster_plain_kernel(RasterArgs A) {
     __shared__ float4 sa[256];
     __shared__ float4 sb[256];
     __shared__ float2 sc[256];
-    const int T = A.tiles_x * A.tiles_y;
-    const int t = A.order ? (int)A.order[blockIdx.x] : xcd_remap(blockIdx.x, T);
+    const int t = tile_of_block(A);
     const int tx = t % A.tiles_x, ty = t / A.tiles_x;
     const int lx = threadIdx.x & 15, ly = threadIdx.x >> 4;
     const int x = tx * kTile + lx, y = ty * kTile + ly;
@@ -173,7 +166,6 @@ __global__ void __launch_bounds__(256) raster_plain_kernel(RasterArgs A) {
             s.a = sa[j];
             s.b = sb[j];
             s.c = sc[j];
-            if (COUNT) p.nvis++;
             blend<COUNT>(p, px, py, s);
         }
     }
@@ -182,114 +174,69 @@ __global__ void __launch_bounds__(256) raster_plain_kernel(RasterArgs A) {
 
 // ---------------------------------------------------------------------------
 
-// Conservative block test: can q = a dx^2 + 2 b dx dy + c dy^2 reach
-// 2 ln(255 o) at some pixel centre of the block? The minimum of the convex
-// q over the box of centres [xa, xb] x [ya, yb] is 0 when the mean is inside,
-// otherwise the smallest of the four edge minima. The margin exceeds the
-// binary32 error of both this bound and the per-pixel evaluation.
-__device__ __forceinline__ bool block_may_touch(float mx, float my, float a, float b, float c, float o, float xa,
-                                                float xb, float ya, float yb) {
-    const float dxl = mx - xb, dxh = mx - xa, dyl = my - yb, dyh = my - ya;
-    float qmin = 0.0f;
-    if (!(dxl <= 0.0f && dxh >= 0.0f && dyl <= 0.0f && dyh >= 0.0f)) {
-        const float ic = 1.0f / c, ia = 1.0f / a;
-        qmin = INFINITY;
-        {
-            const float d = dxl, e = fminf(fmaxf(-b * d * ic, dyl), dyh);
-            qmin = fminf(qmin, a * d * d + 2.0f * b * d * e + c * e * e);
-        }
-        {
-            const float d = dxh, e = fminf(fmaxf(-b * d * ic, dyl), dyh);
-            qmin = fminf(qmin, a * d * d + 2.0f * b * d * e + c * e * e);
-        }
-        {
-            const float e = dyl, d = fminf(fmaxf(-b * e * ia, dxl), dxh);
-            qmin = fminf(qmin, a * d * d + 2.0f * b * d * e + c * e * e);
-        }
-        {
-            const float e = dyh, d = fminf(fmaxf(-b * e * ia, dxl), dxh);
-            qmin = fminf(qmin, a * d * d + 2.0f * b * d * e + c * e * e);
-        }
-    }
-    const float mxd = fmaxf(fabsf(dxl), fabsf(dxh)), myd = fmaxf(fabsf(dyl), fabsf(dyh));
-    const float mag = a * mxd * mxd + c * myd * myd + 2.0f * fabsf(b) * mxd * myd;
-    const float tau = 2.0f * __logf(255.0f * o);
-    return qmin <= tau + 1e-3f + 4e-6f * mag;
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Loads the raw 12-word record or splat of entry e for the cull test and
-// staging.
-template <int SRC>
-__device__ __forceinline__ void fetch_entry(const RasterArgs& A, uint32_t e, float4& r0, float4& r1, float4& r2) {
-    if (SRC == SRC_PACKED) {
-        const float4* r = reinterpret_cast<const float4*>(A.records) + 3 * (int64_t)e;
-        r0 = r[0];
-        r1 = r[1];
-        r2 = r[2];
-    } else {
-        const uint32_t g = id_at<SRC>(A, e);
-        const float4* q = reinterpret_cast<const float4*>(A.splats) + 3 * (int64_t)g;
-        r0 = q[0];
-        r1 = q[1];
-        r2 = q[2];
+// Composites the cnt staged survivors of st[], reading the next one from LDS
+// while the current one is evaluated.
+template <bool COUNT>
+__device__ __forceinline__ void composite_staged(Pix& p, float px, float py, const Staged* st, int cnt) {
+    if (cnt == 0) return;
+    Staged cur = st[0];
+    for (int j = 1; j < cnt; ++j) {
+        const Staged nxt = st[j];
+        blend<COUNT>(p, px, py, cur);
+        cur = nxt;
     }
+    blend<COUNT>(p, px, py, cur);
 }
 
-template <int SRC, bool COUNT, bool CULL>
+template <int SRC, bool COUNT>
 __global__ void __launch_bounds__(256) raster_wave_kernel(RasterArgs A) {
     __shared__ Staged stage[4][kWave];
-    const int T = A.tiles_x * A.tiles_y;
-    const int t = A.order ? (int)A.order[blockIdx.x] : xcd_remap(blockIdx.x, T);
+    const int t = tile_of_block(A);
     const int tx = t % A.tiles_x, ty = t / A.tiles_x;
     const int w = threadIdx.x / kWave, l = lane();
-    const int bx = (w & 1) * 8, by = (w >> 1) * 8;
-    const int lx = bx + (l & 7), ly = by + (l >> 3);
+    float xa, xb, ya, yb;
+    if (!block_box(w, tx, ty, A.width, A.height, xa, xb, ya, yb)) return;  // block outside the image
+    const int lx = (w & 1) * 8 + (l & 7), ly = (w >> 1) * 8 + (l >> 3);
     const int x = tx * kTile + lx, y = ty * kTile + ly;
     const bool inside = x < A.width && y < A.height;
     const bool bad = A.counters[2] != 0;
-    // pixel-centre box of the block's in-image pixels (tile-local)
-    const int nx = min(8, A.width - (tx * kTile + bx)), ny = min(8, A.height - (ty * kTile + by));
-    if (nx <= 0 || ny <= 0) return;  // whole wavefront outside the image
-    const float xa = bx + 0.5f, xb = bx + nx - 0.5f, ya = by + 0.5f, yb = by + ny - 0.5f;
     const float ox = (float)(tx * kTile), oy = (float)(ty * kTile);
     const float px = (float)lx + 0.5f, py = (float)ly + 0.5f;
     Pix p{1.0f, 0.f, 0.f, 0.f, -1, 0, 0, 0, !inside || bad};
     const uint32_t begin = A.offsets[(int64_t)t * A.stride];
     const uint32_t end = bad ? begin : A.offsets[(int64_t)(t + 1) * A.stride];
     Staged* st = stage[w];
-    // software pipeline: the next 64 entries are in flight while the current
-    // ones are culled and composited
-    float4 n0 = make_float4(0.f, 0.f, 0.f, 0.f), n1 = n0, n2 = n0;
-    if (begin + l < end) fetch_entry<SRC>(A, begin + l, n0, n1, n2);
+    const uint32_t bit = 1u << w;
     for (uint32_t base = begin; base < end; base += kWave) {
         if (ballot(!p.done) == 0) break;
         const uint32_t e = base + l;
-        const float4 r0 = n0, r1 = n1, r2 = n2;
-        if (e + kWave < end) fetch_entry<SRC>(A, e + kWave, n0, n1, n2);
         bool keep = e < end;
         Staged s;
         if (SRC == SRC_PACKED) {
-            if (CULL && keep) keep = block_may_touch(r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, xa, xb, ya, yb);
-            s = stage_record(r0, r1, r2, (int32_t)e);
-        } else {
-            s = stage_splat(r0, r1, r2, ox, oy, (int32_t)e);
-            if (CULL && keep) keep = block_may_touch(s.a.x, s.a.y, r1.x, r1.y, r1.z, r1.w, xa, xb, ya, yb);
+            // the block mask decides; only survivors fetch their record
+            if (keep) keep = (A.masks[e] & bit) != 0;
+            if (keep) s = load_entry<SRC>(A, e, ox, oy);
+        } else if (keep) {
+            const uint32_t g = id_at<SRC>(A, e);
+            const float4* q = reinterpret_cast<const float4*>(A.splats) + 3 * (int64_t)g;
+            const float4 q0 = q[0], q1 = q[1], q2 = q[2];
+            float s2;
+            stage_splat(q0, q1, q2, ox, oy, s.a, s.b, s2);
+            s.c = make_float2(s2, __int_as_float((int32_t)e));
+            keep = block_may_touch(s.a.x, s.a.y, q1.x, q1.y, q1.z, q1.w, xa, xb, ya, yb);
         }
         const uint64_t m = ballot(keep);
+        if (m == 0) continue;
         if (keep) st[rank_in(m)] = s;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const int cnt = __builtin_popcountll(m);
-        for (int j = 0; j < cnt; ++j) {
-            if (!p.done) {
-                if (COUNT) p.nvis++;
-                blend<COUNT>(p, px, py, st[j]);
-            }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        wave_sync();
+        composite_staged<COUNT>(p, px, py, st, __builtin_popcountll(m));
+        wave_sync();
     }
     if (inside) write_pixel(A, x, y, p, bad);
 }
@@ -308,9 +255,9 @@ template <int SRC>
 hipError_t wave_dispatch(const RasterArgs& a, hipStream_t s) {
     const int T = a.tiles_x * a.tiles_y;
     if (a.n_visit || a.n_support || a.n_contrib)
-        hipLaunchKernelGGL((raster_wave_kernel<SRC, true, true>), dim3(T), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((raster_wave_kernel<SRC, true>), dim3(T), dim3(256), 0, s, a);
     else
-        hipLaunchKernelGGL((raster_wave_kernel<SRC, false, true>), dim3(T), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((raster_wave_kernel<SRC, false>), dim3(T), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -78,7 +78,7 @@ def test_bin_workspace_and_argument_errors():
     pr = L.Projected(None, None, 0)
     need = lib.tgs_bin_workspace_size(0, 5000, ctypes.byref(c), ctypes.byref(p), L.ORDER_BINNED)
     fake = ctypes.c_void_p(0x1000)
-    b = L.Binned(5000, None, None, fake.value, fake.value, fake.value, fake.value, fake.value)
+    b = L.Binned(5000, None, None, fake.value, fake.value, fake.value, fake.value, fake.value, fake.value)
     st, msg = status_of(lib.tgs_bin, ctypes.byref(pr), ctypes.byref(c), ctypes.byref(p), L.ORDER_BINNED, fake,
                         need - 1, ctypes.byref(b), None, None)
     assert st == L.TGS_ERR_WORKSPACE and "workspace" in msg
@@ -92,7 +92,7 @@ def test_bin_workspace_and_argument_errors():
     b.records = None
     st, msg = status_of(lib.tgs_bin, ctypes.byref(pr), ctypes.byref(c), ctypes.byref(p), L.ORDER_BINNED, fake, need,
                         ctypes.byref(b), None, None)
-    assert st == L.TGS_ERR_INVALID_ARG and "records" in msg
+    assert st == L.TGS_ERR_INVALID_ARG and "records or masks" in msg
 
 
 def test_rasterize_argument_errors():
@@ -100,7 +100,7 @@ def test_rasterize_argument_errors():
     c = cam()
     p = tg.Params().c()
     pr = L.Projected(None, None, 0)
-    b = L.Binned(0, None, None, None, None, None, None, None)
+    b = L.Binned(0, None, None, None, None, None, None, None, None)
     bg = (ctypes.c_float * 3)(0, 0, 0)
     st, msg = status_of(lib.tgs_rasterize, ctypes.byref(pr), ctypes.byref(b), ctypes.byref(c), ctypes.byref(p),
                         L.ORDER_BINNED, bg, None, None, None, None, None, None, None)

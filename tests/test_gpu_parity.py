@@ -290,15 +290,43 @@ def test_repair_bucket_edges_and_records():
         pairs = to_np(bb.pairs)[:n].view(np.uint64)
         assert np.array_equal(pairs, ref["stream"]), K
         assert np.array_equal(to_np(bb.offsets).view(np.uint32), ref["bin_offsets"])
-        # packed records: the entry's splat with the mean relative to its tile
+        # packed records: the entry's splat staged for its tile
         rec = to_np(bb.records)[:n]
         gid = (pairs & np.uint64(0xFFFFFFFF)).astype(np.int64)
         t_of = np.repeat(np.arange(len(lens)), np.diff(ref["bin_offsets"][::K].astype(np.int64)))
         ox = (t_of * 16).astype(np.float32)
         sp = splats[gid]
-        exp_mx = (sp[:, 0] - ox) + sp[:, 2]
-        exp_my = (sp[:, 1] - np.float32(0.0)) + sp[:, 3]
-        assert np.array_equal(rec[:, 0], exp_mx.astype(np.float32))
-        assert np.array_equal(rec[:, 1], exp_my.astype(np.float32))
-        assert np.array_equal(rec[:, 2:9], sp[:, 4:11])
+        k = np.float32(-0.72134752044448170)
+        assert np.array_equal(rec[:, 0], (sp[:, 0] - ox) + sp[:, 2])
+        assert np.array_equal(rec[:, 1], (sp[:, 1] - np.float32(0.0)) + sp[:, 3])
+        assert np.array_equal(rec[:, 2], k * sp[:, 4])
+        assert np.array_equal(rec[:, 3], np.float32(2.0 * k) * sp[:, 5])
+        assert np.array_equal(rec[:, 4], k * sp[:, 6])
+        assert np.array_equal(rec[:, 5:9], sp[:, 7:11])
         assert np.array_equal(rec[:, 9].view(np.uint32), gid.astype(np.uint32))
+        check_block_masks(to_np(bb.masks)[:n], sp, t_of, W, 16)
+
+
+def check_block_masks(masks, sp, tiles, W, H, tiles_x=None):
+    """Bit w of an entry's mask must be set whenever some pixel of 8x8 block w
+    of its tile reaches alpha >= 1/255 (safety of the cull, float64), and is
+    clear for blocks outside the image."""
+    tiles_x = tiles_x or (W + 15) // 16
+    ly, lx = np.mgrid[0:16, 0:16]
+    for i in range(len(masks)):
+        t = int(tiles[i])
+        tx, ty = t % tiles_x, t // tiles_x
+        mx = float(sp[i, 0]) + float(sp[i, 2]) - 16 * tx
+        my = float(sp[i, 1]) + float(sp[i, 3]) - 16 * ty
+        a, b, c, o = (float(v) for v in sp[i, 4:8])
+        dx, dy = mx - (lx + 0.5), my - (ly + 0.5)
+        q = a * dx * dx + 2 * b * dx * dy + c * dy * dy
+        inimg = (16 * tx + lx < W) & (16 * ty + ly < H)
+        tau = 2 * np.log(255 * o)
+        for w in range(4):
+            blk = (lx // 8 == (w & 1)) & (ly // 8 == (w >> 1)) & inimg
+            bit = (int(masks[i]) >> w) & 1
+            if blk.any() and (q[blk] <= tau).any():
+                assert bit == 1, (i, w)
+            if not blk.any():
+                assert bit == 0, (i, w)
