@@ -52,7 +52,7 @@ def parse():
 def kernels_only(args):
     """Launches, after one binned and one global frame, the product raster
     (binned, wave, packed) and the comparator raster (global, plain) `steps`
-    times each, then a 256 MiB device-to-device copy used to calibrate the
+    times each, then a 256 MiB elementwise copy used to calibrate the
     profiler's HBM byte counters."""
     import torch
     import paper_2609_03613_amd as tg
@@ -69,13 +69,14 @@ def kernels_only(args):
         rb.rasterize(splats, info, bb)
     for _ in range(args.steps):
         rg.rasterize(splats, info, bgl)
-    src = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
+    # plain copy of 256 MiB through an elementwise kernel: reads 256 MiB,
+    # writes 256 MiB
+    src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
     dst = torch.empty_like(src)
-    src.fill_(1)
-    dst.copy_(src)
+    torch.add(src, 1.0, out=dst)
     torch.cuda.synchronize()
     print(json.dumps({"mode": "kernels", "entries": bb.num_entries, "steps": args.steps,
-                      "copy_bytes": src.numel()}), flush=True)
+                      "copy_bytes": src.numel() * 4}), flush=True)
 
 
 def workload(name):

@@ -94,10 +94,11 @@ typedef struct {
 
 /* Projected Gaussians, device pointers (written by tgs_project, read by
    tgs_bin and tgs_rasterize; callers may also fill them directly):
-   splats [n][12] fp32: mean_x, mean_y (binary32 rounding of the pixel-space
-       mean), mean_x_lo, mean_y_lo (the remainders, so hi + lo is the mean to
-       about 1e-11 px), conic_a, conic_b, conic_c (inverse screen covariance,
-       q = a dx^2 + 2 b dx dy + c dy^2), opacity, r, g, b, 0.
+   splats [n][16] fp32 (one 64-byte line per Gaussian): mean_x, mean_y
+       (binary32 rounding of the pixel-space mean), mean_x_lo, mean_y_lo (the
+       remainders, so hi + lo is the mean to about 1e-11 px), conic_a,
+       conic_b, conic_c (inverse screen covariance, q = a dx^2 + 2 b dx dy +
+       c dy^2), opacity, r, g, b, then five zero words.
    info [n][4] uint32: depth (binary32 bits of the camera-space z, the
        ordering key), x0 | y0 << 16, x1 | y1 << 16 (half-open tile rect),
        number of tiles (x1 - x0) * (y1 - y0); an empty rect = invisible. */

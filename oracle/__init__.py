@@ -139,7 +139,7 @@ def render(proj, width, height, tile_size=16, bg=(0.0, 0.0, 0.0), pix=None, mode
 
 def splats_to_proj(splats, info):
     """Projected splats in the two-array layout of scenes.random_splats
-    (splats [n, 12] fp32, info [n, 4] uint32) as the float64 record dict
+    (splats [n, 16] fp32, info [n, 4] uint32) as the float64 record dict
     that ``render`` takes. The mean is hi + lo, exactly, in float64."""
     s = np.ascontiguousarray(splats, dtype=np.float32)
     w = np.ascontiguousarray(info, dtype=np.uint32)

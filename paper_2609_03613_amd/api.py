@@ -70,11 +70,11 @@ def to_device(g, device="cuda"):
 
 
 def project(g, cam, params=None):
-    """tgs_project: returns (splats [n, 12] float32, info [n, 4] int32)."""
+    """tgs_project: returns (splats [n, 16] float32, info [n, 4] int32)."""
     params = params or Params()
     n = int(g["means"].shape[0])
     dev = g["means"].device
-    splats = torch.empty((n, 12), dtype=torch.float32, device=dev)
+    splats = torch.empty((n, 16), dtype=torch.float32, device=dev)
     info = torch.empty((n, 4), dtype=torch.int32, device=dev)
     gs = L.Gaussians(_ptr(g["means"]).value, _ptr(g["log_scales"]).value, _ptr(g["quats"]).value,
                      _ptr(g["logits"]).value, _ptr(g["sh"]).value, n, int(g["sh_degree"]))

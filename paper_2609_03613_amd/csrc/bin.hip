@@ -51,7 +51,8 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
 // positive so the bit order is the value order). Both ranks are selected
 // together by radix passes of 11 bits over key - min(key), which spreads the
 // histogram even when all depths share their top bits.
-__global__ void __launch_bounds__(kRangeThreads) depth_range_kernel(const uint32_t* __restrict__ sample,
+__global__ void __launch_bounds__(kRangeThreads) depth_range_kernel(const uint4* __restrict__ info,
+                                                                   const uint32_t* __restrict__ vis_ids,
                                                                    const int64_t* __restrict__ counters, int S,
                                                                    float p_lo, float p_hi, float pad, float znear,
                                                                    float zfar, float* __restrict__ zrange) {
@@ -71,7 +72,8 @@ __global__ void __launch_bounds__(kRangeThreads) depth_range_kernel(const uint32
     }
     uint32_t lo = 0xFFFFFFFFu, hi = 0u;
     for (int i = threadIdx.x; i < n; i += kRangeThreads) {
-        const uint32_t k = sample[i];
+        const int64_t r = V <= S ? (int64_t)i : ((int64_t)i * V) / S;
+        const uint32_t k = info[vis_ids[r]].x;
         keys[i] = k;
         lo = min(lo, k);
         hi = max(hi, k);
@@ -474,33 +476,43 @@ __device__ __forceinline__ uint32_t wave_aggregated_add(uint32_t* ctr, int b, bo
     return slot;
 }
 
+// One workgroup; the tile counts of a pass are all loaded before they are
+// used (8 per lane in flight).
+constexpr int kOrderItems = 8;
+
 __global__ void __launch_bounds__(1024) tile_order_kernel(const uint32_t* __restrict__ offsets, int stride,
                                                           int64_t T, uint32_t* __restrict__ order) {
     __shared__ uint32_t hist[kOrderBuckets], cur[kOrderBuckets];
     if (threadIdx.x < kOrderBuckets) hist[threadIdx.x] = 0;
     __syncthreads();
-    const int64_t rounds = (T + blockDim.x - 1) / blockDim.x;
-    for (int64_t r = 0; r < rounds; ++r) {
-        const int64_t t = r * blockDim.x + threadIdx.x;
-        const bool act = t < T;
-        const int b = act ? order_bucket(offsets[(t + 1) * stride] - offsets[t * stride]) : 0;
-        (void)wave_aggregated_add(hist, b, act);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t acc = 0;
-        for (int b = 0; b < kOrderBuckets; ++b) {
-            cur[b] = acc;
-            acc += hist[b];
+    const int64_t chunk = (int64_t)blockDim.x * kOrderItems;
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int64_t base = 0; base < T; base += chunk) {
+            int b[kOrderItems];
+#pragma unroll
+            for (int k = 0; k < kOrderItems; ++k) {
+                const int64_t t = base + (int64_t)k * blockDim.x + threadIdx.x;
+                b[k] = t < T ? order_bucket(offsets[(t + 1) * stride] - offsets[t * stride]) : 0;
+            }
+#pragma unroll
+            for (int k = 0; k < kOrderItems; ++k) {
+                const int64_t t = base + (int64_t)k * blockDim.x + threadIdx.x;
+                const bool act = t < T;
+                const uint32_t pos = wave_aggregated_add(pass == 0 ? hist : cur, b[k], act);
+                if (pass == 1 && act) order[pos] = (uint32_t)t;
+            }
         }
-    }
-    __syncthreads();
-    for (int64_t r = 0; r < rounds; ++r) {
-        const int64_t t = r * blockDim.x + threadIdx.x;
-        const bool act = t < T;
-        const int b = act ? order_bucket(offsets[(t + 1) * stride] - offsets[t * stride]) : 0;
-        const uint32_t pos = wave_aggregated_add(cur, b, act);
-        if (act) order[pos] = (uint32_t)t;
+        __syncthreads();
+        if (pass == 0) {
+            if (threadIdx.x == 0) {
+                uint32_t acc = 0;
+                for (int k = 0; k < kOrderBuckets; ++k) {
+                    cur[k] = acc;
+                    acc += hist[k];
+                }
+            }
+            __syncthreads();
+        }
     }
 }
 
@@ -541,10 +553,10 @@ inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 
 
 }  // namespace
 
-hipError_t launch_depth_range(const uint32_t* sample, const int64_t* counters, int S, float p_lo, float p_hi,
-                              float pad, float znear, float zfar, float* zrange, hipStream_t s) {
-    hipLaunchKernelGGL(depth_range_kernel, dim3(1), dim3(kRangeThreads), 0, s, sample, counters, S, p_lo, p_hi, pad,
-                       znear, zfar, zrange);
+hipError_t launch_depth_range(const uint32_t* info, const uint32_t* vis_ids, const int64_t* counters, int S,
+                              float p_lo, float p_hi, float pad, float znear, float zfar, float* zrange, hipStream_t s) {
+    hipLaunchKernelGGL(depth_range_kernel, dim3(1), dim3(kRangeThreads), 0, s, reinterpret_cast<const uint4*>(info),
+                       vis_ids, counters, S, p_lo, p_hi, pad, znear, zfar, zrange);
     return hipGetLastError();
 }
 

@@ -76,13 +76,13 @@ tgs_status check_projected(const tgs_projected* pr) {
 inline size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t emit_off, scan_tmp, sample, zero, zero_words, entry_rank, seg_lists, keys_in, vals_in, sort_tmp,
-        sort_tmp_bytes, total;
+    size_t emit_off, vis_ids, zero, zero_words, status_emit_x, status_emit_y, status_bins, count, entry_rank,
+        seg_lists, keys_in, vals_in, sort_tmp, sort_tmp_bytes, total;
 };
 
 // Control words at the start of the zeroed region (uint32 offsets).
-constexpr int kDoneEmit = 0;
-constexpr int kDoneBins = 1;
+constexpr int kTicketEmit = 0;
+constexpr int kTicketBins = 1;
 constexpr int kBucketCount = 16;
 constexpr int kControlWords = 64;
 
@@ -92,10 +92,10 @@ int end_bit_for(int64_t T) {
     return 32 + (b > 0 ? b : 1);
 }
 
-// Workspace: [emit offsets][scan partials][depth samples][zeroed region:
-// control words, per-XCD counts][entry ranks][repair lists] (BINNED) or
-// [...][zeroed control words][unsorted keys][unsorted ids][sort scratch]
-// (GLOBAL).
+// Workspace: [emit offsets][visible ids][zeroed region: control words,
+// scan status words, per-XCD counts (BINNED)][entry ranks][repair lists]
+// (BINNED) or [...][unsorted keys][unsorted ids][sort scratch] (GLOBAL).
+// The zeroed region is cleared by one fill at the start of each tgs_bin.
 Layout layout(int64_t n, int64_t capacity, int64_t T, int K, int order) {
     Layout L{};
     size_t off = 0;
@@ -105,18 +105,28 @@ Layout layout(int64_t n, int64_t capacity, int64_t T, int K, int order) {
         return at;
     };
     const int64_t nseg = T * K;
-    const int64_t scan_n = n > nseg ? n : nseg;
     L.emit_off = take(sizeof(uint32_t) * (size_t)(n + 1));
-    L.scan_tmp = take(sizeof(uint32_t) * scan_tmp_words(scan_n));
-    L.sample = take(sizeof(uint32_t) * 8192);
+    L.vis_ids = take(sizeof(uint32_t) * (size_t)(n + 1));
+    // zeroed region, in uint32 words from L.zero
+    size_t z = kControlWords;
+    const size_t nbe = (size_t)scan_blocks(n), nbb = (size_t)scan_blocks(nseg);
+    L.status_emit_x = z;
+    z += 2 * nbe;
+    L.status_emit_y = z;
+    z += 2 * nbe;
+    L.status_bins = z;
+    z += 2 * nbb;
     if (order == TGS_ORDER_BINNED) {
-        L.zero_words = (size_t)kControlWords + (size_t)kXcc * (size_t)nseg;
-        L.zero = take(sizeof(uint32_t) * L.zero_words);
+        z = (z + 63) & ~(size_t)63;
+        L.count = z;
+        z += (size_t)kXcc * (size_t)nseg;
+    }
+    L.zero_words = z;
+    L.zero = take(sizeof(uint32_t) * z);
+    if (order == TGS_ORDER_BINNED) {
         L.entry_rank = take(sizeof(uint32_t) * (size_t)capacity);
         L.seg_lists = take(sizeof(uint32_t) * (size_t)kBuckets * (size_t)nseg);
     } else {
-        L.zero_words = (size_t)kControlWords;
-        L.zero = take(sizeof(uint32_t) * L.zero_words);
         L.keys_in = take(sizeof(uint64_t) * (size_t)capacity);
         L.vals_in = take(sizeof(uint32_t) * (size_t)capacity);
         L.sort_tmp_bytes = global_sort_tmp_bytes(capacity, end_bit_for(T)) + 1024;
@@ -199,15 +209,15 @@ tgs_status tgs_bin(const tgs_projected* pr, const tgs_camera* cam, const tgs_par
     hipStream_t s = (hipStream_t)stream;
     char* w = (char*)ws;
     uint32_t* emit_off = (uint32_t*)(w + L.emit_off);
-    uint32_t* tmp = (uint32_t*)(w + L.scan_tmp);
-    uint32_t* sample = (uint32_t*)(w + L.sample);
+    uint32_t* vis_ids = (uint32_t*)(w + L.vis_ids);
     uint32_t* zero = (uint32_t*)(w + L.zero);
     const int S = params->sample_count;
     const int tiles_x = div_up(cam->width, kTile), tiles_y = div_up(cam->height, kTile);
 
     TGS_HIP(launch_fill_u32(zero, 0u, (int64_t)L.zero_words, s), "clear control words");
-    TGS_HIP(launch_emit_scan(pr->info_dev, n, tiles_x, tiles_y, emit_off, tmp, zero + kDoneEmit, out->counters_dev, cap,
-                             sample, S, nullptr, 0, s),
+    TGS_HIP(launch_emit_scan(pr->info_dev, n, tiles_x, tiles_y, emit_off, vis_ids, zero + kTicketEmit,
+                             (uint64_t*)(zero + L.status_emit_x), (uint64_t*)(zero + L.status_emit_y),
+                             out->counters_dev, cap, s),
             "emit scan");
     int64_t M = -1;
     if (num_entries_host || order == TGS_ORDER_GLOBAL) {
@@ -227,7 +237,7 @@ tgs_status tgs_bin(const tgs_projected* pr, const tgs_camera* cam, const tgs_par
         if (out->tile_order_dev) TGS_HIP(launch_tile_order(out->offsets_dev, 1, T, out->tile_order_dev, s), "tile order");
         return TGS_OK;
     }
-    uint32_t* count = zero + kControlWords;
+    uint32_t* count = zero + L.count;
     uint32_t* entry_rank = (uint32_t*)(w + L.entry_rank);
     uint32_t* seg_lists = (uint32_t*)(w + L.seg_lists);
     uint32_t* bucket_count = zero + kBucketCount;
@@ -235,14 +245,14 @@ tgs_status tgs_bin(const tgs_projected* pr, const tgs_camera* cam, const tgs_par
     RecordSink rs{reinterpret_cast<const float4*>(pr->splats_dev),
                   params->packed ? reinterpret_cast<float4*>(out->records_dev) : nullptr,
                   params->packed ? out->masks_dev : nullptr, K, tiles_x, cam->width, cam->height};
-    TGS_HIP(launch_depth_range(sample, out->counters_dev, S, params->p_lo, params->p_hi, params->pad, (float)cam->znear,
-                               (float)cam->zfar, out->zrange_dev, s),
+    TGS_HIP(launch_depth_range(pr->info_dev, vis_ids, out->counters_dev, S, params->p_lo, params->p_hi, params->pad,
+                               (float)cam->znear, (float)cam->zfar, out->zrange_dev, s),
             "depth range");
     TGS_HIP(launch_bin_count(pr->info_dev, n, emit_off, out->zrange_dev, K, tiles_x, tiles_y, count, nseg, entry_rank,
                              cap, s),
             "bin count");
-    TGS_HIP(launch_bin_offsets(count, nseg, out->offsets_dev, tmp, zero + kDoneBins, seg_lists, bucket_count,
-                               out->counters_dev, s),
+    TGS_HIP(launch_bin_offsets(count, nseg, out->offsets_dev, zero + kTicketBins, (uint64_t*)(zero + L.status_bins),
+                               seg_lists, bucket_count, out->counters_dev, s),
             "bin offsets");
     TGS_HIP(launch_bin_scatter(pr->info_dev, n, emit_off, out->zrange_dev, K, tiles_x, tiles_y, out->offsets_dev, count,
                                nseg, entry_rank, out->pairs_dev, cap, rs, s),

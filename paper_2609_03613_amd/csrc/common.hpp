@@ -10,7 +10,8 @@ namespace tgs {
 
 constexpr int kWave = 64;
 constexpr int kTile = 16;          // tile edge in pixels
-constexpr int kSplatWords = 12;    // fp32 words per splat / packed record
+constexpr int kSplatVec = 4;       // float4s per splat (64 bytes)
+constexpr int kRecordVec = 3;      // float4s per packed record (48 bytes)
 constexpr int kInfoWords = 4;
 
 // Fixed thresholds of the 3DGS image model.
@@ -160,11 +161,12 @@ struct RecordSink {
         const int tx = (int)(t % (uint32_t)tiles_x), ty = (int)(t / (uint32_t)tiles_x);
         const float ox = (float)(tx * kTile), oy = (float)(ty * kTile);
         const uint32_t gid = (uint32_t)pair;
-        const float4 a = splats[3 * (int64_t)gid], b = splats[3 * (int64_t)gid + 1], c = splats[3 * (int64_t)gid + 2];
+        const float4* sp = splats + kSplatVec * (int64_t)gid;
+        const float4 a = sp[0], b = sp[1], c = sp[2];
         float4 s0, s1;
         float s2;
         stage_splat(a, b, c, ox, oy, s0, s1, s2);
-        float4* rec = records + 3 * (int64_t)pos;
+        float4* rec = records + kRecordVec * (int64_t)pos;
         rec[0] = s0;
         rec[1] = s1;
         rec[2] = make_float4(s2, __uint_as_float(gid), 0.f, 0.f);
@@ -195,20 +197,22 @@ Cam make_cam(const tgs_camera& c);
 hipError_t launch_project(const tgs_gaussians& g, const Cam& cam, float* splats, uint32_t* info,
                           hipStream_t s);
 
-// Scratch words for the scans' partial sums.
-size_t scan_tmp_words(int64_t n);
+// Workgroups of the single-pass scans for n items (at least one).
+int64_t scan_blocks(int64_t n);
 
 // Entry emission scan over the info array: emit_off[g] = number of entries
-// of the Gaussians before g; counters[0] = M, counters[1] = V (visible),
-// counters[2] = 1 when M exceeds `capacity` (every later stage then skips
-// its writes beyond the buffers); the depth samples for the range estimate
-// are written to sample[]. `done` must be zero (it is left zero).
+// of the Gaussians before g, vis_ids[rank] = g for every visible Gaussian;
+// counters[0] = M, counters[1] = V (visible), counters[2] = 1 when M
+// exceeds `capacity` (every later stage then skips its writes beyond the
+// buffers). ticket and status_x / status_y [scan_blocks(n)] must be zero.
 hipError_t launch_emit_scan(const uint32_t* info, int64_t n, int tiles_x, int tiles_y, uint32_t* emit_off,
-                            uint32_t* tmp, uint32_t* done, int64_t* counters, int64_t capacity, uint32_t* sample,
-                            int S, uint32_t* zero, int64_t zero_words, hipStream_t s);
+                            uint32_t* vis_ids, uint32_t* ticket, uint64_t* status_x, uint64_t* status_y,
+                            int64_t* counters, int64_t capacity, hipStream_t s);
 
-hipError_t launch_depth_range(const uint32_t* sample, const int64_t* counters, int S, float p_lo,
-                              float p_hi, float pad, float znear, float zfar, float* zrange,
+// Depth samples: the visible Gaussians at ranks floor(i V / S), i < S (all
+// of them when V <= S), read through vis_ids.
+hipError_t launch_depth_range(const uint32_t* info, const uint32_t* vis_ids, const int64_t* counters, int S,
+                              float p_lo, float p_hi, float pad, float znear, float zfar, float* zrange,
                               hipStream_t s);
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
@@ -239,8 +243,8 @@ __host__ __device__ __forceinline__ int bucket_of(uint32_t len) {
 // count[x][s] becomes the base position of copy x inside segment s; every
 // segment of two or more entries is appended to lists[bucket][...] with
 // bucket_count[bucket] entries (not when counters[2] flags an overflow).
-// `done` and bucket_count must be zero.
-hipError_t launch_bin_offsets(uint32_t* count, int64_t nseg, uint32_t* bin_off, uint32_t* tmp, uint32_t* done,
+// ticket, status [scan_blocks(nseg)] and bucket_count must be zero.
+hipError_t launch_bin_offsets(uint32_t* count, int64_t nseg, uint32_t* bin_off, uint32_t* ticket, uint64_t* status,
                               uint32_t* lists, uint32_t* bucket_count, const int64_t* counters, hipStream_t s);
 hipError_t launch_bin_scatter(const uint32_t* info, int64_t n, const uint32_t* emit_off, const float* zrange,
                               int K, int tiles_x, int tiles_y, const uint32_t* bin_off, const uint32_t* base,
@@ -263,7 +267,7 @@ hipError_t launch_global_sort(void* tmp, size_t tmp_bytes, uint64_t* keys_in, ui
 hipError_t launch_tile_ranges(const uint64_t* keys, int64_t m, int64_t T, uint32_t* tile_off, hipStream_t s);
 
 struct RasterArgs {
-    const float* splats;    // [n][12]
+    const float* splats;    // [n][16]
     const uint32_t* offsets;
     int stride;             // offsets index step per tile (1 for GLOBAL, K for BINNED)
     const uint32_t* vals;   // GLOBAL ids

@@ -89,7 +89,7 @@ __global__ void __launch_bounds__(kProjThreads) project_kernel(const float* __re
     __syncthreads();
     const int64_t g = g0 + threadIdx.x;
     if (g >= n) return;
-    float4* out = splats + 3 * g;
+    float4* out = splats + kSplatVec * g;
     const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
     uint4 inf = make_uint4(0u, 0u, 0u, 0u);
 
@@ -161,7 +161,7 @@ __global__ void __launch_bounds__(kProjThreads) project_kernel(const float* __re
         ok = (x1 > x0) && (y1 > y0);
     }
     if (!ok) {
-        out[0] = zero4; out[1] = zero4; out[2] = zero4;
+        out[0] = zero4; out[1] = zero4; out[2] = zero4; out[3] = zero4;
         info[g] = inf;
         return;
     }
@@ -183,6 +183,7 @@ __global__ void __launch_bounds__(kProjThreads) project_kernel(const float* __re
     out[1] = make_float4((float)(c11 / det), (float)(-c01 / det), (float)(c00 / det), (float)o);
     out[2] = make_float4((float)fmax(0.0, 0.5 + col[0]), (float)fmax(0.0, 0.5 + col[1]),
                          (float)fmax(0.0, 0.5 + col[2]), 0.f);
+    out[3] = zero4;
     const float zf = (float)z;
     inf.x = __float_as_uint(zf);
     inf.y = (uint32_t)x0 | ((uint32_t)y0 << 16);

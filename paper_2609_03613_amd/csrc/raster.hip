@@ -112,14 +112,14 @@ template <int SRC>
 __device__ __forceinline__ Staged load_entry(const RasterArgs& A, uint32_t p, float ox, float oy) {
     Staged s;
     if (SRC == SRC_PACKED) {
-        const float4* r = reinterpret_cast<const float4*>(A.records) + 3 * (int64_t)p;
+        const float4* r = reinterpret_cast<const float4*>(A.records) + kRecordVec * (int64_t)p;
         s.a = r[0];
         s.b = r[1];
         s.c = make_float2(r[2].x, __int_as_float((int32_t)p));
         return s;
     }
     const uint32_t g = id_at<SRC>(A, p);
-    const float4* q = reinterpret_cast<const float4*>(A.splats) + 3 * (int64_t)g;
+    const float4* q = reinterpret_cast<const float4*>(A.splats) + kSplatVec * (int64_t)g;
     float s2;
     stage_splat(q[0], q[1], q[2], ox, oy, s.a, s.b, s2);
     s.c = make_float2(s2, __int_as_float((int32_t)p));
@@ -224,7 +224,7 @@ __global__ void __launch_bounds__(256) raster_wave_kernel(RasterArgs A) {
             if (keep) s = load_entry<SRC>(A, e, ox, oy);
         } else if (keep) {
             const uint32_t g = id_at<SRC>(A, e);
-            const float4* q = reinterpret_cast<const float4*>(A.splats) + 3 * (int64_t)g;
+            const float4* q = reinterpret_cast<const float4*>(A.splats) + kSplatVec * (int64_t)g;
             const float4 q0 = q[0], q1 = q[1], q2 = q[2];
             float s2;
             stage_splat(q0, q1, q2, ox, oy, s.a, s.b, s2);

@@ -241,9 +241,9 @@ def subset(g, idx):
 # ---------------------------------------------------------------------------
 # Synthetic projected splats, for exercising the ordering and raster stages
 # on their own. Two arrays per splat set:
-#   splats [n, 12] fp32: mean_x, mean_y (binary32 parts), mean_x_lo, mean_y_lo
+#   splats [n, 16] fp32: mean_x, mean_y (binary32 parts), mean_x_lo, mean_y_lo
 #       (the remainders, so that hi + lo carries the mean to ~1e-11 px),
-#       conic_a, conic_b, conic_c, opacity, r, g, b, 0.
+#       conic_a, conic_b, conic_c, opacity, r, g, b, five zeros.
 #   info [n, 4] uint32: depth (binary32 bits), rect word 0 (x0 | y0 << 16),
 #       rect word 1 (x1 | y1 << 16), number of tiles; the rect is half-open
 #       in tile units.
@@ -281,7 +281,7 @@ def random_splats(n, width, height, tile_size=16, seed=0, depth_lo=1.0, depth_hi
     hidden = rng.random(n) < hidden_fraction
     cxx, cyy, cxy = sx * sx, sy * sy, rho * sx * sy
     det = cxx * cyy - cxy * cxy
-    splats = np.zeros((n, 12), dtype=np.float32)
+    splats = np.zeros((n, 16), dtype=np.float32)
     mxh, myh = mx.astype(np.float32), my.astype(np.float32)
     splats[:, 0], splats[:, 1] = mxh, myh
     splats[:, 2] = (mx - mxh.astype(np.float64)).astype(np.float32)
