@@ -59,8 +59,8 @@ def kernels_only(args):
     dev = torch.device("cuda:0")
     g, cam, desc = workload(args.config)
     gd = tg.to_device(g, dev)
-    rb = tg.Renderer(cam, tg.Params(raster="wave", packed=True), device=dev)
-    rg = tg.Renderer(cam, tg.Params(raster="plain", packed=False, tile_order=False), device=dev)
+    rb = tg.Renderer(cam, tg.Params(raster="wave", packed=2), device=dev)
+    rg = tg.Renderer(cam, tg.Params(raster="plain", packed=0, tile_order=False), device=dev)
     splats, info = tg.project(gd, cam)
     bb = rb.bin(splats, info, "binned", sync=True)
     bgl = rg.bin(splats, info, "global", sync=True)
@@ -126,10 +126,11 @@ def main():
     gd = tg.to_device(g, dev)
     stream = torch.cuda.current_stream()
 
-    rb = tg.Renderer(cam, tg.Params(raster="wave", packed=True), device=dev)
+    # the product: binned stream, wave raster with per-entry block masks
+    rb = tg.Renderer(cam, tg.Params(raster="wave", packed=2), device=dev)
     # the comparator: globally sorted stream, one workgroup per tile gathering
     # batches by id, tiles in raster order
-    rg = tg.Renderer(cam, tg.Params(raster="plain", packed=False, tile_order=False), device=dev)
+    rg = tg.Renderer(cam, tg.Params(raster="plain", packed=0, tile_order=False), device=dev)
 
     # first frames: size the entry buffers (host reads the entry count once)
     splats, info = tg.project(gd, cam)
@@ -204,20 +205,31 @@ def main():
     ras_b = raster_only(rb, bb, out_b)
     ras_g = raster_only(rg, bgl, out_g)
 
-    # ablation: the same two streams through the other kernels and layouts
+    # ablation: the same streams through the other kernels and layouts; each
+    # binned variant re-bins with its own options, timed separately
     import copy
     bb_noorder = copy.copy(bb)
     bb_noorder.tile_order = None
-    r_wave_gather = tg.Renderer(cam, tg.Params(raster="wave", packed=False), device=dev)
-    r_plain_packed = tg.Renderer(cam, tg.Params(raster="plain", packed=True), device=dev)
-    ablation = {
-        "binned wave packed (product)": float(np.median(ras_b)),
-        "binned wave packed, raster-order tiles": float(np.median(raster_only(rb, bb_noorder, out_b))),
-        "binned wave gather-by-id": float(np.median(raster_only(r_wave_gather, bb, out_b))),
-        "binned plain packed": float(np.median(raster_only(r_plain_packed, bb, out_b))),
-        "global wave gather-by-id": float(np.median(raster_only(r_wave_gather, bgl, out_g))),
-        "global plain gather-by-id (comparator)": float(np.median(ras_g)),
-    }
+    ablation = {"binned wave masks (product)": float(np.median(ras_b)),
+                "binned wave masks, raster-order tiles": float(np.median(raster_only(rb, bb_noorder, out_b)))}
+    bin_ms = {}
+    for name, prm in [("binned wave records+masks", tg.Params(raster="wave", packed=1)),
+                      ("binned wave cull-in-raster", tg.Params(raster="wave", packed=0)),
+                      ("binned plain gather-by-id", tg.Params(raster="plain", packed=0))]:
+        rv = tg.Renderer(cam, prm, device=dev)
+        bv = rv.bin(splats, info, "binned", sync=True)
+        e0, e1 = ev(), ev()
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(args.steps):
+            rv.bin(splats, info, "binned", sync=False)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        bin_ms[name] = e0.elapsed_time(e1) / args.steps
+        ablation[name] = float(np.median(raster_only(rv, bv, out_b)))
+    r_wave_gather = tg.Renderer(cam, tg.Params(raster="wave", packed=0), device=dev)
+    ablation["global wave cull-in-raster"] = float(np.median(raster_only(r_wave_gather, bgl, out_g)))
+    ablation["global plain gather-by-id (comparator)"] = float(np.median(ras_g))
 
     # instrumented launches (outside the timed region): algorithmic work
     cb = rb.rasterize(splats, info, bb, counts=True)
@@ -263,9 +275,10 @@ def main():
                             "visit_global": n_visit_g / (W * H)},
         "images_bitwise_equal": same,
         "raster_ablation_ms": ablation,
+        "bin_stage_ms_by_variant": bin_ms,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_LANE_OPS, "unit": "lane-op/s",
                      "frac": achieved / PEAK_LANE_OPS, "traffic": None,
-                     "kernel": "raster_wave_kernel (binned, packed records)",
+                     "kernel": "raster_wave_kernel (binned, block masks)",
                      "work": f"{n_support} alpha-supported pixel tests x {OPS_PER_TEST} lane-op slots"},
     }
     if not args.no_cpu_baseline:

@@ -116,8 +116,13 @@ typedef struct {
     float p_lo, p_hi;     /* depth-range percentiles, 1 and 99 */
     float pad;            /* depth-range padding fraction, 0.05 */
     int32_t raster;       /* TGS_RASTER_* */
-    int32_t packed;       /* 1: BINNED order also writes per-entry records and
-                             the raster reads them instead of gathering */
+    int32_t packed;       /* BINNED order only. 0: the WAVE raster gathers each
+                             entry's splat by id and tests it against its
+                             block; 1: tgs_bin also writes per-entry staged
+                             records and block masks, the raster reads the
+                             records of the entries its block's mask keeps;
+                             2: block masks only, the raster gathers the kept
+                             entries by id */
 } tgs_params;
 
 /* Entry buffers written by tgs_bin and read by tgs_rasterize. All device
@@ -151,7 +156,7 @@ typedef struct {
 } tgs_binned;
 
 /* Fills the paper's defaults (16 px tiles, K = 64, S = 8192, 1st / 99th
-   percentiles, 5 % pad), the WAVE raster and packed records. */
+   percentiles, 5 % pad), the WAVE raster and block masks (packed = 2). */
 TGS_API void tgs_default_params(tgs_params* params);
 
 /* Projection + SH colour + opacity-aware tile rect for every Gaussian. The

@@ -34,12 +34,12 @@ class Params:
     p_hi: float = 99.0
     pad: float = 0.05
     raster: str = "wave"
-    packed: bool = True
+    packed: int = 2          # 0: gather + cull in the raster, 1: records + masks, 2: masks only
     tile_order: bool = True
 
     def c(self):
         return L.Params(self.tile_size, self.num_bins, self.sample_count, self.p_lo, self.p_hi, self.pad,
-                        RASTERS[self.raster], int(bool(self.packed)))
+                        RASTERS[self.raster], int(self.packed))
 
 
 def camera_struct(cam):
@@ -103,8 +103,9 @@ class Binned:
             self.pairs = torch.empty(cap, dtype=torch.int64, **kw)
             self.offsets = torch.empty(tiles * num_bins + 1, dtype=torch.int32, **kw)
             if packed:
-                self.records = torch.empty((cap, 12), dtype=torch.float32, **kw)
                 self.masks = torch.empty(cap, dtype=torch.uint8, **kw)
+            if packed == 1:
+                self.records = torch.empty((cap, 12), dtype=torch.float32, **kw)
         self.tile_order = torch.empty(max(tiles, 1), dtype=torch.int32, **kw) if tile_order else None
         self.num_entries = None
 

@@ -71,12 +71,24 @@ __global__ void __launch_bounds__(kRangeThreads) depth_range_kernel(const uint4*
         return;
     }
     uint32_t lo = 0xFFFFFFFFu, hi = 0u;
-    for (int i = threadIdx.x; i < n; i += kRangeThreads) {
+    constexpr int kPer = kMaxSamples / kRangeThreads;
+    uint32_t gid[kPer], key[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int i = j * kRangeThreads + threadIdx.x;
         const int64_t r = V <= S ? (int64_t)i : ((int64_t)i * V) / S;
-        const uint32_t k = info[vis_ids[r]].x;
-        keys[i] = k;
-        lo = min(lo, k);
-        hi = max(hi, k);
+        gid[j] = i < n ? vis_ids[r] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) key[j] = (j * kRangeThreads + (int)threadIdx.x) < n ? info[gid[j]].x : 0u;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int i = j * kRangeThreads + threadIdx.x;
+        if (i < n) {
+            keys[i] = key[j];
+            lo = min(lo, key[j]);
+            hi = max(hi, key[j]);
+        }
     }
     lo = wave_min_u32(lo);
     hi = wave_max_u32(hi);
@@ -476,44 +488,44 @@ __device__ __forceinline__ uint32_t wave_aggregated_add(uint32_t* ctr, int b, bo
     return slot;
 }
 
-// One workgroup; the tile counts of a pass are all loaded before they are
-// used (8 per lane in flight).
-constexpr int kOrderItems = 8;
+// Two launches over all tiles: (1) bucket histogram (per-workgroup LDS,
+// then one global atomic per bucket and workgroup), (2) placement: every
+// workgroup scans the global histogram and reserves its slots per bucket
+// with one global atomic per bucket. Order inside a bucket is arbitrary.
+__device__ __forceinline__ uint32_t tile_count(const uint32_t* offsets, int stride, int64_t t) {
+    return offsets[(t + 1) * stride] - offsets[t * stride];
+}
 
-__global__ void __launch_bounds__(1024) tile_order_kernel(const uint32_t* __restrict__ offsets, int stride,
-                                                          int64_t T, uint32_t* __restrict__ order) {
-    __shared__ uint32_t hist[kOrderBuckets], cur[kOrderBuckets];
-    if (threadIdx.x < kOrderBuckets) hist[threadIdx.x] = 0;
+__global__ void __launch_bounds__(256) tile_hist_kernel(const uint32_t* __restrict__ offsets, int stride, int64_t T,
+                                                        uint32_t* __restrict__ hist) {
+    __shared__ uint32_t h[kOrderBuckets];
+    if (threadIdx.x < kOrderBuckets) h[threadIdx.x] = 0;
     __syncthreads();
-    const int64_t chunk = (int64_t)blockDim.x * kOrderItems;
-    for (int pass = 0; pass < 2; ++pass) {
-        for (int64_t base = 0; base < T; base += chunk) {
-            int b[kOrderItems];
-#pragma unroll
-            for (int k = 0; k < kOrderItems; ++k) {
-                const int64_t t = base + (int64_t)k * blockDim.x + threadIdx.x;
-                b[k] = t < T ? order_bucket(offsets[(t + 1) * stride] - offsets[t * stride]) : 0;
-            }
-#pragma unroll
-            for (int k = 0; k < kOrderItems; ++k) {
-                const int64_t t = base + (int64_t)k * blockDim.x + threadIdx.x;
-                const bool act = t < T;
-                const uint32_t pos = wave_aggregated_add(pass == 0 ? hist : cur, b[k], act);
-                if (pass == 1 && act) order[pos] = (uint32_t)t;
-            }
-        }
-        __syncthreads();
-        if (pass == 0) {
-            if (threadIdx.x == 0) {
-                uint32_t acc = 0;
-                for (int k = 0; k < kOrderBuckets; ++k) {
-                    cur[k] = acc;
-                    acc += hist[k];
-                }
-            }
-            __syncthreads();
-        }
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool act = t < T;
+    (void)wave_aggregated_add(h, act ? order_bucket(tile_count(offsets, stride, t)) : 0, act);
+    __syncthreads();
+    if (threadIdx.x < kOrderBuckets && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+}
+
+__global__ void __launch_bounds__(256) tile_place_kernel(const uint32_t* __restrict__ offsets, int stride, int64_t T,
+                                                         const uint32_t* __restrict__ hist, uint32_t* __restrict__ cursor,
+                                                         uint32_t* __restrict__ order) {
+    __shared__ uint32_t h[kOrderBuckets], base[kOrderBuckets];
+    if (threadIdx.x < kOrderBuckets) h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool act = t < T;
+    const int b = act ? order_bucket(tile_count(offsets, stride, t)) : 0;
+    const uint32_t slot = wave_aggregated_add(h, b, act);
+    __syncthreads();
+    if (threadIdx.x < kOrderBuckets) {
+        uint32_t start = 0;
+        for (int k = 0; k < (int)threadIdx.x; ++k) start += hist[k];
+        base[threadIdx.x] = h[threadIdx.x] ? start + atomicAdd(&cursor[threadIdx.x], h[threadIdx.x]) : 0u;
     }
+    __syncthreads();
+    if (act) order[base[b] + slot] = (uint32_t)t;
 }
 
 // ---------------------------------------------------------------------------
@@ -592,9 +604,12 @@ hipError_t launch_repair(const uint32_t* bin_off, int64_t nseg, uint64_t* pairs,
     return hipGetLastError();
 }
 
-hipError_t launch_tile_order(const uint32_t* offsets, int stride, int64_t T, uint32_t* order, hipStream_t s) {
+hipError_t launch_tile_order(const uint32_t* offsets, int stride, int64_t T, uint32_t* hist, uint32_t* order,
+                             hipStream_t s) {
     if (T == 0) return hipSuccess;
-    hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(1024), 0, s, offsets, stride, T, order);
+    hipLaunchKernelGGL(tile_hist_kernel, dim3(grid_for(T, 256)), dim3(256), 0, s, offsets, stride, T, hist);
+    hipLaunchKernelGGL(tile_place_kernel, dim3(grid_for(T, 256)), dim3(256), 0, s, offsets, stride, T, hist,
+                       hist + kOrderBuckets, order);
     return hipGetLastError();
 }
 

@@ -61,6 +61,7 @@ tgs_status check_params(const tgs_params* p) {
     if (!(p->p_lo >= 0.f && p->p_lo <= p->p_hi && p->p_hi <= 100.f))
         return fail(TGS_ERR_INVALID_ARG, "need 0 <= p_lo <= p_hi <= 100");
     if (!(p->pad >= 0.f) || !isfinite(p->pad)) return fail(TGS_ERR_INVALID_ARG, "pad must be >= 0");
+    if (p->packed < 0 || p->packed > 2) return fail(TGS_ERR_INVALID_ARG, "packed must be 0, 1 or 2");
     if (p->raster != TGS_RASTER_PLAIN && p->raster != TGS_RASTER_WAVE)
         return fail(TGS_ERR_INVALID_ARG, "unknown raster %d", p->raster);
     return TGS_OK;
@@ -84,7 +85,8 @@ struct Layout {
 constexpr int kTicketEmit = 0;
 constexpr int kTicketBins = 1;
 constexpr int kBucketCount = 16;
-constexpr int kControlWords = 64;
+constexpr int kTileHist = 32;  // 66 words: histogram and cursors of the tile order
+constexpr int kControlWords = 128;
 
 int end_bit_for(int64_t T) {
     int b = 0;
@@ -153,7 +155,7 @@ void tgs_default_params(tgs_params* p) {
     p->p_hi = 99.0f;
     p->pad = 0.05f;
     p->raster = TGS_RASTER_WAVE;
-    p->packed = 1;
+    p->packed = 2;
 }
 
 const char* tgs_last_error(void) { return g_err.c_str(); }
@@ -197,8 +199,10 @@ tgs_status tgs_bin(const tgs_projected* pr, const tgs_camera* cam, const tgs_par
     const int K = params->num_bins;
     if (order == TGS_ORDER_BINNED) {
         if (!out->zrange_dev || (cap > 0 && !out->pairs_dev)) return fail(TGS_ERR_INVALID_ARG, "pairs or zrange is NULL");
-        if (params->packed && cap > 0 && (!out->records_dev || !out->masks_dev))
+        if (params->packed == 1 && cap > 0 && (!out->records_dev || !out->masks_dev))
             return fail(TGS_ERR_INVALID_ARG, "records or masks is NULL with packed=1");
+        if (params->packed == 2 && cap > 0 && !out->masks_dev)
+            return fail(TGS_ERR_INVALID_ARG, "masks is NULL with packed=2");
         if (T * K >= ((int64_t)1 << 31)) return fail(TGS_ERR_INVALID_ARG, "tiles * bins too large");
     } else if (cap > 0 && (!out->keys_dev || !out->vals_dev)) {
         return fail(TGS_ERR_INVALID_ARG, "keys or vals is NULL");
@@ -234,7 +238,8 @@ tgs_status tgs_bin(const tgs_projected* pr, const tgs_camera* cam, const tgs_par
                                    end_bit_for(T), s),
                 "radix sort");
         TGS_HIP(launch_tile_ranges(out->keys_dev, M, T, out->offsets_dev, s), "tile ranges");
-        if (out->tile_order_dev) TGS_HIP(launch_tile_order(out->offsets_dev, 1, T, out->tile_order_dev, s), "tile order");
+        if (out->tile_order_dev)
+            TGS_HIP(launch_tile_order(out->offsets_dev, 1, T, zero + kTileHist, out->tile_order_dev, s), "tile order");
         return TGS_OK;
     }
     uint32_t* count = zero + L.count;
@@ -243,7 +248,7 @@ tgs_status tgs_bin(const tgs_projected* pr, const tgs_camera* cam, const tgs_par
     uint32_t* bucket_count = zero + kBucketCount;
     const int64_t nseg = T * K;
     RecordSink rs{reinterpret_cast<const float4*>(pr->splats_dev),
-                  params->packed ? reinterpret_cast<float4*>(out->records_dev) : nullptr,
+                  params->packed == 1 ? reinterpret_cast<float4*>(out->records_dev) : nullptr,
                   params->packed ? out->masks_dev : nullptr, K, tiles_x, cam->width, cam->height};
     TGS_HIP(launch_depth_range(pr->info_dev, vis_ids, out->counters_dev, S, params->p_lo, params->p_hi, params->pad,
                                (float)cam->znear, (float)cam->zfar, out->zrange_dev, s),
@@ -258,7 +263,8 @@ tgs_status tgs_bin(const tgs_projected* pr, const tgs_camera* cam, const tgs_par
                                nseg, entry_rank, out->pairs_dev, cap, rs, s),
             "bin scatter");
     TGS_HIP(launch_repair(out->offsets_dev, nseg, out->pairs_dev, seg_lists, bucket_count, rs, s), "repair");
-    if (out->tile_order_dev) TGS_HIP(launch_tile_order(out->offsets_dev, K, T, out->tile_order_dev, s), "tile order");
+    if (out->tile_order_dev)
+        TGS_HIP(launch_tile_order(out->offsets_dev, K, T, zero + kTileHist, out->tile_order_dev, s), "tile order");
     return TGS_OK;
 }
 
@@ -285,11 +291,12 @@ tgs_status tgs_rasterize(const tgs_projected* pr, const tgs_binned* b, const tgs
     } else {
         a.stride = params->num_bins;
         a.pairs = b->pairs_dev;
-        a.records = params->packed ? b->records_dev : nullptr;
+        a.records = params->packed == 1 ? b->records_dev : nullptr;
         a.masks = params->packed ? b->masks_dev : nullptr;
         if (b->capacity > 0 && !a.pairs) return fail(TGS_ERR_INVALID_ARG, "pairs is NULL");
-        if (params->packed && b->capacity > 0 && (!a.records || !a.masks))
+        if (params->packed == 1 && b->capacity > 0 && !a.records)
             return fail(TGS_ERR_INVALID_ARG, "records or masks is NULL");
+        if (params->packed && b->capacity > 0 && !a.masks) return fail(TGS_ERR_INVALID_ARG, "records or masks is NULL");
     }
     if (pr->n > 0 && !a.splats && !a.records) return fail(TGS_ERR_INVALID_ARG, "splats is NULL");
     a.width = cam->width;

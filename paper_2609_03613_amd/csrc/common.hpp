@@ -146,17 +146,18 @@ __device__ __forceinline__ bool block_box(int w, int tx, int ty, int width, int 
     return true;
 }
 
-// Where the entry-placing kernels put packed records (records == null:
-// none): record p = staged splat of the entry's Gaussian for its tile
-// ({mx, my, a', 2b'}, {c', opacity, r, g}, {b, id, 0, 0}) and mask p = bit w
-// set when 8x8 block w of the tile may see the splat.
+// Where the entry-placing kernels put the per-entry raster data. masks ==
+// null: nothing. Otherwise mask p gets bit w set when 8x8 block w of the
+// entry's tile may see the splat, and, when records != null, record p the
+// staged splat of the entry's Gaussian for its tile ({mx, my, a', 2b'},
+// {c', opacity, r, g}, {b, id, 0, 0}).
 struct RecordSink {
     const float4* splats;
     float4* records;
     uint8_t* masks;
     int K, tiles_x, width, height;
     __device__ __forceinline__ void put(uint32_t seg, uint32_t pos, uint64_t pair) const {
-        if (!records) return;
+        if (!masks) return;
         const uint32_t t = seg / (uint32_t)K;
         const int tx = (int)(t % (uint32_t)tiles_x), ty = (int)(t / (uint32_t)tiles_x);
         const float ox = (float)(tx * kTile), oy = (float)(ty * kTile);
@@ -166,10 +167,12 @@ struct RecordSink {
         float4 s0, s1;
         float s2;
         stage_splat(a, b, c, ox, oy, s0, s1, s2);
-        float4* rec = records + kRecordVec * (int64_t)pos;
-        rec[0] = s0;
-        rec[1] = s1;
-        rec[2] = make_float4(s2, __uint_as_float(gid), 0.f, 0.f);
+        if (records) {
+            float4* rec = records + kRecordVec * (int64_t)pos;
+            rec[0] = s0;
+            rec[1] = s1;
+            rec[2] = make_float4(s2, __uint_as_float(gid), 0.f, 0.f);
+        }
         uint32_t m = 0;
 #pragma unroll
         for (int w = 0; w < 4; ++w) {
@@ -256,8 +259,10 @@ hipError_t launch_repair(const uint32_t* bin_off, int64_t nseg, uint64_t* pairs,
                          const uint32_t* bucket_count, RecordSink rs, hipStream_t s);
 
 // Tiles in descending order of their entry count (coarse: by bit length of
-// the count), so the heaviest tiles are dispatched first.
-hipError_t launch_tile_order(const uint32_t* offsets, int stride, int64_t T, uint32_t* order, hipStream_t s);
+// the count), so the heaviest tiles are dispatched first. hist [66] must be
+// zero.
+hipError_t launch_tile_order(const uint32_t* offsets, int stride, int64_t T, uint32_t* hist, uint32_t* order,
+                             hipStream_t s);
 
 hipError_t launch_emit_keys(const uint32_t* info, int64_t n, const uint32_t* emit_off, int tiles_x, int tiles_y,
                             uint64_t* keys, uint32_t* vals, int64_t capacity, hipStream_t s);

@@ -218,8 +218,8 @@ __global__ void __launch_bounds__(256) raster_wave_kernel(RasterArgs A) {
         const uint32_t e = base + l;
         bool keep = e < end;
         Staged s;
-        if (SRC == SRC_PACKED) {
-            // the block mask decides; only survivors fetch their record
+        if (A.masks) {
+            // the block mask decides; only survivors fetch their entry
             if (keep) keep = (A.masks[e] & bit) != 0;
             if (keep) s = load_entry<SRC>(A, e, ox, oy);
         } else if (keep) {

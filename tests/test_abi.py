@@ -31,7 +31,7 @@ def test_default_params():
     L.lib().tgs_default_params(ctypes.byref(p))
     assert (p.tile_size, p.num_bins, p.sample_count) == (16, 64, 8192)
     assert (p.p_lo, p.p_hi) == (1.0, 99.0) and abs(p.pad - 0.05) < 1e-7
-    assert p.raster == L.RASTER_WAVE and p.packed == 1
+    assert p.raster == L.RASTER_WAVE and p.packed == 2
 
 
 def cam(w=64, h=48):
@@ -82,17 +82,29 @@ def test_bin_workspace_and_argument_errors():
     st, msg = status_of(lib.tgs_bin, ctypes.byref(pr), ctypes.byref(c), ctypes.byref(p), L.ORDER_BINNED, fake,
                         need - 1, ctypes.byref(b), None, None)
     assert st == L.TGS_ERR_WORKSPACE and "workspace" in msg
-    st, _ = status_of(lib.tgs_bin, ctypes.byref(pr), ctypes.byref(c), ctypes.byref(p), 7, fake, need,
+    # the remaining cases pass no workspace, so that even a validation bug
+    # stops at the workspace check instead of launching anything
+    st, _ = status_of(lib.tgs_bin, ctypes.byref(pr), ctypes.byref(c), ctypes.byref(p), 7, None, 0,
                       ctypes.byref(b), None, None)
     assert st == L.TGS_ERR_INVALID_ARG
     pk = tg.Params(num_bins=0).c()
-    st, _ = status_of(lib.tgs_bin, ctypes.byref(pr), ctypes.byref(c), ctypes.byref(pk), L.ORDER_BINNED, fake, need,
+    st, _ = status_of(lib.tgs_bin, ctypes.byref(pr), ctypes.byref(c), ctypes.byref(pk), L.ORDER_BINNED, None, 0,
                       ctypes.byref(b), None, None)
     assert st == L.TGS_ERR_INVALID_ARG
-    b.records = None
-    st, msg = status_of(lib.tgs_bin, ctypes.byref(pr), ctypes.byref(c), ctypes.byref(p), L.ORDER_BINNED, fake, need,
+    b.masks = None
+    st, msg = status_of(lib.tgs_bin, ctypes.byref(pr), ctypes.byref(c), ctypes.byref(p), L.ORDER_BINNED, None, 0,
                         ctypes.byref(b), None, None)
-    assert st == L.TGS_ERR_INVALID_ARG and "records or masks" in msg
+    assert st == L.TGS_ERR_INVALID_ARG and "masks" in msg
+    p1 = tg.Params(packed=1).c()
+    b.masks = fake.value
+    b.records = None
+    st, msg = status_of(lib.tgs_bin, ctypes.byref(pr), ctypes.byref(c), ctypes.byref(p1), L.ORDER_BINNED, None, 0,
+                        ctypes.byref(b), None, None)
+    assert st == L.TGS_ERR_INVALID_ARG and "records" in msg
+    p3 = tg.Params(packed=3).c()
+    st, msg = status_of(lib.tgs_bin, ctypes.byref(pr), ctypes.byref(c), ctypes.byref(p3), L.ORDER_BINNED, None, 0,
+                        ctypes.byref(b), None, None)
+    assert st == L.TGS_ERR_INVALID_ARG and "packed" in msg
 
 
 def test_rasterize_argument_errors():

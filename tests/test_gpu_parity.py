@@ -149,8 +149,8 @@ def test_empty_and_invisible():
 # raster: images against the FP64 oracle; all variants bitwise equal
 # ---------------------------------------------------------------------------
 
-VARIANTS = [("global", "plain", False), ("global", "wave", False), ("binned", "plain", False),
-            ("binned", "wave", False), ("binned", "plain", True), ("binned", "wave", True)]
+VARIANTS = [("global", "plain", 0), ("global", "wave", 0), ("binned", "plain", 0), ("binned", "wave", 0),
+            ("binned", "plain", 1), ("binned", "wave", 1), ("binned", "plain", 2), ("binned", "wave", 2)]
 
 
 def render_variant(g_splats, g_info, cam, order, raster, packed, K=64, bg=(0.0, 0.0, 0.0)):
@@ -286,7 +286,7 @@ def test_repair_bucket_edges_and_records():
     cam = cam_for(W, 16)
     for K in (1, 4):
         ref = oracle.schedule(scenes.info_depth(info), rect, len(lens), 1, K=K)
-        _, _, _, bb = run_bin(splats, info, cam, "binned", tg.Params(num_bins=K))
+        _, _, _, bb = run_bin(splats, info, cam, "binned", tg.Params(num_bins=K, packed=1))
         pairs = to_np(bb.pairs)[:n].view(np.uint64)
         assert np.array_equal(pairs, ref["stream"]), K
         assert np.array_equal(to_np(bb.offsets).view(np.uint32), ref["bin_offsets"])
