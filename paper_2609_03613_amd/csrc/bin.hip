@@ -273,7 +273,7 @@ __global__ void __launch_bounds__(256) bin_scatter_kernel(const uint4* __restric
                                if (p >= capacity) return;
                                const uint64_t pair = ((uint64_t)key << 32) | (uint64_t)gid;
                                pairs[p] = pair;
-                               if (rs.records && bin_off[sg + 1] - bin_off[sg] == 1)
+                               if (rs.masks && bin_off[sg + 1] - bin_off[sg] == 1)
                                    rs.put((uint32_t)sg, (uint32_t)p, pair);
                            });
 }
