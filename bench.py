@@ -59,7 +59,7 @@ def kernels_only(args):
     dev = torch.device("cuda:0")
     g, cam, desc = workload(args.config)
     gd = tg.to_device(g, dev)
-    rb = tg.Renderer(cam, tg.Params(raster="wave", packed=2), device=dev)
+    rb = tg.Renderer(cam, tg.Params(raster="wave", packed=0), device=dev)
     rg = tg.Renderer(cam, tg.Params(raster="plain", packed=0, tile_order=False), device=dev)
     splats, info = tg.project(gd, cam)
     bb = rb.bin(splats, info, "binned", sync=True)
@@ -126,8 +126,9 @@ def main():
     gd = tg.to_device(g, dev)
     stream = torch.cuda.current_stream()
 
-    # the product: binned stream, wave raster with per-entry block masks
-    rb = tg.Renderer(cam, tg.Params(raster="wave", packed=2), device=dev)
+    # the product: binned stream, wave raster gathering by id and culling
+    # per 8x8 block
+    rb = tg.Renderer(cam, tg.Params(raster="wave", packed=0), device=dev)
     # the comparator: globally sorted stream, one workgroup per tile gathering
     # batches by id, tiles in raster order
     rg = tg.Renderer(cam, tg.Params(raster="plain", packed=0, tile_order=False), device=dev)
@@ -210,11 +211,11 @@ def main():
     import copy
     bb_noorder = copy.copy(bb)
     bb_noorder.tile_order = None
-    ablation = {"binned wave masks (product)": float(np.median(ras_b)),
-                "binned wave masks, raster-order tiles": float(np.median(raster_only(rb, bb_noorder, out_b)))}
+    ablation = {"binned wave cull-in-raster (product)": float(np.median(ras_b)),
+                "binned wave cull-in-raster, raster-order tiles": float(np.median(raster_only(rb, bb_noorder, out_b)))}
     bin_ms = {}
     for name, prm in [("binned wave records+masks", tg.Params(raster="wave", packed=1)),
-                      ("binned wave cull-in-raster", tg.Params(raster="wave", packed=0)),
+                      ("binned wave masks", tg.Params(raster="wave", packed=2)),
                       ("binned plain gather-by-id", tg.Params(raster="plain", packed=0))]:
         rv = tg.Renderer(cam, prm, device=dev)
         bv = rv.bin(splats, info, "binned", sync=True)
@@ -278,7 +279,7 @@ def main():
         "bin_stage_ms_by_variant": bin_ms,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_LANE_OPS, "unit": "lane-op/s",
                      "frac": achieved / PEAK_LANE_OPS, "traffic": None,
-                     "kernel": "raster_wave_kernel (binned, block masks)",
+                     "kernel": "raster_wave_kernel (binned, gather by id, per-block cull)",
                      "work": f"{n_support} alpha-supported pixel tests x {OPS_PER_TEST} lane-op slots"},
     }
     if not args.no_cpu_baseline:

@@ -156,7 +156,7 @@ typedef struct {
 } tgs_binned;
 
 /* Fills the paper's defaults (16 px tiles, K = 64, S = 8192, 1st / 99th
-   percentiles, 5 % pad), the WAVE raster and block masks (packed = 2). */
+   percentiles, 5 % pad), the WAVE raster gathering by id (packed = 0). */
 TGS_API void tgs_default_params(tgs_params* params);
 
 /* Projection + SH colour + opacity-aware tile rect for every Gaussian. The

@@ -25,8 +25,8 @@ RASTERS = {"plain": L.RASTER_PLAIN, "wave": L.RASTER_WAVE}
 @dataclass
 class Params:
     """Ordering / raster options; defaults are the paper's (K = 64, 8192
-    samples, 1st / 99th percentiles, 5 % pad) with the wave raster and packed
-    records."""
+    samples, 1st / 99th percentiles, 5 % pad, no per-entry geometry written
+    before the raster) with the wave raster."""
     tile_size: int = 16
     num_bins: int = 64
     sample_count: int = 8192
@@ -34,7 +34,7 @@ class Params:
     p_hi: float = 99.0
     pad: float = 0.05
     raster: str = "wave"
-    packed: int = 2          # 0: gather + cull in the raster, 1: records + masks, 2: masks only
+    packed: int = 0          # 0: gather + cull in the raster, 1: records + masks, 2: masks only
     tile_order: bool = True
 
     def c(self):

@@ -155,7 +155,7 @@ void tgs_default_params(tgs_params* p) {
     p->p_hi = 99.0f;
     p->pad = 0.05f;
     p->raster = TGS_RASTER_WAVE;
-    p->packed = 2;
+    p->packed = 0;
 }
 
 const char* tgs_last_error(void) { return g_err.c_str(); }

@@ -31,7 +31,7 @@ def test_default_params():
     L.lib().tgs_default_params(ctypes.byref(p))
     assert (p.tile_size, p.num_bins, p.sample_count) == (16, 64, 8192)
     assert (p.p_lo, p.p_hi) == (1.0, 99.0) and abs(p.pad - 0.05) < 1e-7
-    assert p.raster == L.RASTER_WAVE and p.packed == 2
+    assert p.raster == L.RASTER_WAVE and p.packed == 0
 
 
 def cam(w=64, h=48):
@@ -92,7 +92,8 @@ def test_bin_workspace_and_argument_errors():
                       ctypes.byref(b), None, None)
     assert st == L.TGS_ERR_INVALID_ARG
     b.masks = None
-    st, msg = status_of(lib.tgs_bin, ctypes.byref(pr), ctypes.byref(c), ctypes.byref(p), L.ORDER_BINNED, None, 0,
+    p2 = tg.Params(packed=2).c()
+    st, msg = status_of(lib.tgs_bin, ctypes.byref(pr), ctypes.byref(c), ctypes.byref(p2), L.ORDER_BINNED, None, 0,
                         ctypes.byref(b), None, None)
     assert st == L.TGS_ERR_INVALID_ARG and "masks" in msg
     p1 = tg.Params(packed=1).c()
