@@ -35,6 +35,27 @@ OPS_PER_TEST = 17 + 4
 HBM_PEAK = 8.0e12
 
 
+def profiled_traffic():
+    """HBM bytes per launch of the product raster from the committed counter
+    summary (FETCH_SIZE / WRITE_SIZE scaled by a 256 MiB copy), or None when
+    the raster sources changed since the counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "raster_wave_1080p.md")
+    if not os.path.exists(path):
+        return None
+    h = hashlib.sha256()
+    for f in ("raster.hip", "common.hpp"):
+        with open(os.path.join(ROOT, "paper_2609_03613_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    text = open(path).read()
+    m_hash = re.search(r"source_sha256: ([0-9a-f]+)", text)
+    m_traffic = re.search(r"traffic_bytes_per_launch: ([0-9.e+]+)", text)
+    if not m_hash or not m_traffic or m_hash.group(1) != h.hexdigest():
+        return None
+    return float(m_traffic.group(1))
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -278,7 +299,7 @@ def main():
         "raster_ablation_ms": ablation,
         "bin_stage_ms_by_variant": bin_ms,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_LANE_OPS, "unit": "lane-op/s",
-                     "frac": achieved / PEAK_LANE_OPS, "traffic": None,
+                     "frac": achieved / PEAK_LANE_OPS, "traffic": profiled_traffic(),
                      "kernel": "raster_wave_kernel (binned, gather by id, per-block cull)",
                      "work": f"{n_support} alpha-supported pixel tests x {OPS_PER_TEST} lane-op slots"},
     }
