@@ -57,6 +57,7 @@ def lib():
         L.orc_bin_of.argtypes = [flt, flt, flt, i32]
         L.orc_schedule.argtypes = [i64, P, P, i32, i32, i32, i32, dbl, dbl, flt, flt, flt,
                                    P, P, P, P, P, P]
+        L.orc_adjoint.argtypes = [i64, P, P, P, P, P, i32, P, i32, P, P, P, P, P, P, P, P, P, P, P]
         _lib = L
     return _lib
 
@@ -193,3 +194,38 @@ def schedule(depth, rect, tiles_x, tiles_y, K=64, S=8192, p_lo=1.0, p_hi=99.0, p
     assert rc == 0, rc
     out["M"] = M
     return out
+
+
+def adjoint(g, cam, tile_size=16, bg=(0.0, 0.0, 0.0), d_img=None, d_alpha=None):
+    """Binary64 forward image of the parameters in ``g`` (converted to
+    float64) and, when ``d_img`` ([H, W, 3], dL/d rgb) is given, the
+    gradients: ``d_proj`` [n, 9] (mean2d x, y, conic a, b, c, opacity, r, g,
+    b) and ``means``, ``log_scales``, ``quats``, ``logits``, ``sh`` in the
+    input layouts. ``d_alpha`` [H, W] is dL/d alpha (optional)."""
+    n = g["means"].shape[0]
+    W, H = int(cam["width"]), int(cam["height"])
+    deg = int(g["sh_degree"])
+    nsh = (deg + 1) ** 2
+    ins = [_c(g[k], np.float64) for k in ("means", "log_scales", "quats", "logits", "sh")]
+    out = {"rgb": np.zeros((H, W, 3)), "alpha": np.zeros((H, W))}
+    grads = None
+    if d_img is not None:
+        grads = {"d_proj": np.zeros((n, 9)), "means": np.zeros((n, 3)), "log_scales": np.zeros((n, 3)),
+                 "quats": np.zeros((n, 4)), "logits": np.zeros(n), "sh": np.zeros((n, nsh, 3))}
+    dimg = None if d_img is None else _c(d_img, np.float64)
+    dal = None if d_alpha is None else _c(d_alpha, np.float64)
+    gp = (lambda k: None) if grads is None else (lambda k: _p(grads[k]))
+    rc = lib().orc_adjoint(n, *[_p(a) for a in ins], deg, _p(cam_array(cam)), int(tile_size),
+                           _p(_c(bg, np.float64)), _p(out["rgb"]), _p(out["alpha"]), _p(dimg), _p(dal),
+                           gp("d_proj"), gp("means"), gp("log_scales"), gp("quats"), gp("logits"), gp("sh"))
+    assert rc == 0, rc
+    if grads is not None:
+        out.update(grads)
+    return out
+
+
+def mse_upstream(rgb, target):
+    """Loss mean((rgb - target)^2) over pixels and channels and its gradient
+    with respect to rgb."""
+    d = np.asarray(rgb, np.float64) - np.asarray(target, np.float64)
+    return float(np.mean(d * d)), 2.0 * d / d.size

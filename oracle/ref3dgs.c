@@ -627,3 +627,358 @@ ORC_EXPORT int orc_schedule(int64_t n, const float* depth, const int32_t* rect, 
     free(e);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Adjoint: the gradient of a scalar loss of the image with respect to the  */
+/* Gaussian parameters. The paper leaves the backward pass to future work   */
+/* (Conclusion / Limitations); this is the derivative of the forward model  */
+/* above, written out by the chain rule in binary64 and taken in reverse    */
+/* order (compositing first, then the projection). Inputs are binary64 so   */
+/* that central finite differences of the same forward model can check it.  */
+/* Zero-gradient paths, as in the forward definition: the 0.99 alpha cap,   */
+/* colour channels clamped at 0, the frustum guard of the Jacobian, and     */
+/* Gaussians that are skipped, culled or after the stopping point.          */
+/* ------------------------------------------------------------------------ */
+
+/* The forward quantities of one Gaussian that its adjoint needs. */
+typedef struct {
+    int vis;
+    double mu[3], pc[3], z;
+    double qn, qh[4];      /* |q| and q / |q| as (w, x, y, z) */
+    double s2[3], M[9];    /* exp(log_scale)^2, R_cam R_q */
+    int clx, cly;          /* frustum guard active on x / y */
+    double limx, limy;     /* signed guard value when active */
+    double j00, j02, j11, j12;
+    double A[3], B[3];     /* rows of J M */
+    double c00, c01, c11, det;
+    double conic[3], mean[2], o;
+    double dir[3], Y[16];
+    double rgb[3], rgb_raw[3];
+    int rect[4];
+    float key;
+} adj_g;
+
+static void adj_project_one(const double* means, const double* log_scales, const double* quats,
+                            const double* logits, const double* sh, int nsh, int degree, const double* cam,
+                            int tile_size, int64_t g, adj_g* P) {
+    const double* R = cam;
+    const double* t = cam + 9;
+    const double fx = cam[12], fy = cam[13], cx = cam[14], cy = cam[15];
+    const int W = (int)cam[16], H = (int)cam[17];
+    memset(P, 0, sizeof(*P));
+    for (int i = 0; i < 3; ++i) P->mu[i] = means[3 * g + i];
+    for (int i = 0; i < 3; ++i)
+        P->pc[i] = R[3 * i] * P->mu[0] + R[3 * i + 1] * P->mu[1] + R[3 * i + 2] * P->mu[2] + t[i];
+    const double z = P->z = P->pc[2];
+    if (!(z > cam[18] && z < cam[19])) return;
+    const double* q = quats + 4 * g;
+    P->qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    if (!(P->qn > 0.0) || !isfinite(P->qn)) return;
+    for (int i = 0; i < 4; ++i) P->qh[i] = q[i] / P->qn;
+    const double w = P->qh[0], x = P->qh[1], y = P->qh[2], zq = P->qh[3];
+    const double Rq[9] = {1 - 2 * (y * y + zq * zq), 2 * (x * y - w * zq), 2 * (x * zq + w * y),
+                          2 * (x * y + w * zq), 1 - 2 * (x * x + zq * zq), 2 * (y * zq - w * x),
+                          2 * (x * zq - w * y), 2 * (y * zq + w * x), 1 - 2 * (x * x + y * y)};
+    for (int k = 0; k < 3; ++k) {
+        double s = exp(log_scales[3 * g + k]);
+        P->s2[k] = s * s;
+    }
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            P->M[3 * i + j] = R[3 * i] * Rq[j] + R[3 * i + 1] * Rq[3 + j] + R[3 * i + 2] * Rq[6 + j];
+    const double lxp = (W - cx) / fx + GUARD * W / fx, lxn = cx / fx + GUARD * W / fx;
+    const double lyp = (H - cy) / fy + GUARD * H / fy, lyn = cy / fy + GUARD * H / fy;
+    double tx = P->pc[0], ty = P->pc[1];
+    if (P->pc[0] / z > lxp) { P->clx = 1; P->limx = lxp; tx = z * lxp; }
+    else if (P->pc[0] / z < -lxn) { P->clx = 1; P->limx = -lxn; tx = -z * lxn; }
+    if (P->pc[1] / z > lyp) { P->cly = 1; P->limy = lyp; ty = z * lyp; }
+    else if (P->pc[1] / z < -lyn) { P->cly = 1; P->limy = -lyn; ty = -z * lyn; }
+    P->j00 = fx / z; P->j02 = -fx * tx / (z * z);
+    P->j11 = fy / z; P->j12 = -fy * ty / (z * z);
+    for (int k = 0; k < 3; ++k) {
+        P->A[k] = P->j00 * P->M[k] + P->j02 * P->M[6 + k];
+        P->B[k] = P->j11 * P->M[3 + k] + P->j12 * P->M[6 + k];
+    }
+    P->c00 = DILATION; P->c01 = 0.0; P->c11 = DILATION;
+    for (int k = 0; k < 3; ++k) {
+        P->c00 += P->A[k] * P->A[k] * P->s2[k];
+        P->c01 += P->A[k] * P->B[k] * P->s2[k];
+        P->c11 += P->B[k] * P->B[k] * P->s2[k];
+    }
+    P->det = P->c00 * P->c11 - P->c01 * P->c01;
+    if (!(P->det > 0.0) || !isfinite(P->det)) return;
+    P->conic[0] = P->c11 / P->det;
+    P->conic[1] = -P->c01 / P->det;
+    P->conic[2] = P->c00 / P->det;
+    P->mean[0] = fx * P->pc[0] / z + cx;
+    P->mean[1] = fy * P->pc[1] / z + cy;
+    P->o = 1.0 / (1.0 + exp(-logits[g]));
+    if (!(P->o >= ALPHA_MIN)) return;
+    for (int i = 0; i < 3; ++i) P->dir[i] = P->mu[i] + (R[i] * t[0] + R[3 + i] * t[1] + R[6 + i] * t[2]);
+    orc_sh_basis(P->dir, degree, P->Y);
+    for (int ch = 0; ch < 3; ++ch) {
+        double acc = 0.0;
+        for (int k = 0; k < nsh; ++k) acc += sh[((int64_t)g * nsh + k) * 3 + ch] * P->Y[k];
+        P->rgb_raw[ch] = 0.5 + acc;
+        P->rgb[ch] = fmax(0.0, P->rgb_raw[ch]);
+    }
+    const double tau = 2.0 * log(255.0 * P->o);
+    const double ex = sqrt(tau * P->c00) * (1.0 + 1e-4) + 1e-3, ey = sqrt(tau * P->c11) * (1.0 + 1e-4) + 1e-3;
+    const int tiles_x = (W + tile_size - 1) / tile_size, tiles_y = (H + tile_size - 1) / tile_size;
+    double x0 = floor((P->mean[0] - ex) / tile_size), x1 = floor((P->mean[0] + ex) / tile_size) + 1.0;
+    double y0 = floor((P->mean[1] - ey) / tile_size), y1 = floor((P->mean[1] + ey) / tile_size) + 1.0;
+    x0 = fmin(fmax(x0, 0.0), tiles_x); x1 = fmin(fmax(x1, 0.0), tiles_x);
+    y0 = fmin(fmax(y0, 0.0), tiles_y); y1 = fmin(fmax(y1, 0.0), tiles_y);
+    if (!(x1 > x0 && y1 > y0)) return;
+    P->rect[0] = (int)x0; P->rect[1] = (int)y0; P->rect[2] = (int)x1; P->rect[3] = (int)y1;
+    P->key = (float)z;
+    P->vis = 1;
+}
+
+/* One composited entry of a pixel: Gaussian, its alpha, the transmittance
+   in front of it, exp(-q/2), and whether the 0.99 cap was active. */
+typedef struct { uint32_t g; double alpha, T, G, dx, dy; int capped; } adj_c;
+
+/* Compositing adjoint of one pixel: given dL/d(rgb) (gc) and dL/d(alpha)
+   (ga) of the pixel, accumulate dL/d(mean2d, conic, opacity, rgb) of every
+   composited Gaussian into gm[9 g + 0..8]. The colour behind entry k,
+   S_k = sum_{i > k} T_i alpha_i c_i + T_final bg, gives
+   dC/d alpha_k = T_k c_k - S_k / (1 - alpha_k) and
+   d(1 - T_final)/d alpha_k = T_final / (1 - alpha_k). */
+static void adj_pixel_reverse(const adj_g* P, const adj_c* cl, int nc, double Tf, const double* bg,
+                              const double* gc, double ga, double* gm) {
+    double S[3] = {Tf * bg[0], Tf * bg[1], Tf * bg[2]};
+    for (int k = nc - 1; k >= 0; --k) {
+        const uint32_t g = cl[k].g;
+        const double a = cl[k].alpha, Tk = cl[k].T;
+        double dLda = ga * Tf / (1.0 - a);
+        for (int ch = 0; ch < 3; ++ch) {
+            gm[9 * g + 6 + ch] += gc[ch] * Tk * a;
+            dLda += gc[ch] * (Tk * P[g].rgb[ch] - S[ch] / (1.0 - a));
+        }
+        for (int ch = 0; ch < 3; ++ch) S[ch] += Tk * a * P[g].rgb[ch];
+        if (cl[k].capped) continue;
+        /* alpha = o G, G = exp(-q/2), q = a dx^2 + 2 b dx dy + c dy^2 */
+        const double dLdq = dLda * (-0.5 * a);
+        const double dx = cl[k].dx, dy = cl[k].dy;
+        gm[9 * g + 5] += dLda * cl[k].G;
+        gm[9 * g + 2] += dLdq * dx * dx;
+        gm[9 * g + 3] += dLdq * 2.0 * dx * dy;
+        gm[9 * g + 4] += dLdq * dy * dy;
+        gm[9 * g + 0] += dLdq * 2.0 * (P[g].conic[0] * dx + P[g].conic[1] * dy);
+        gm[9 * g + 1] += dLdq * 2.0 * (P[g].conic[1] * dx + P[g].conic[2] * dy);
+    }
+}
+
+/* Projection adjoint of one Gaussian: from d = dL/d(mean2d x, y, conic a, b,
+   c, opacity, r, g, b) to the parameter gradients. The direction derivative
+   of the SH basis is a central difference of orc_sh_basis with step
+   1e-6 |dir| (truncation and rounding error below 1e-9 relative). */
+static void adj_project_reverse(const adj_g* p, const double* d, const double* sh, int nsh, int degree,
+                                const double* cam, double* d_means, double* d_log_scales, double* d_quats,
+                                double* d_logit, double* d_sh) {
+    const double* R = cam;
+    const double fx = cam[12], fy = cam[13];
+    *d_logit = d[5] * p->o * (1.0 - p->o);
+    double gY[16] = {0};
+    for (int ch = 0; ch < 3; ++ch) {
+        if (!(p->rgb_raw[ch] > 0.0)) continue;
+        for (int k = 0; k < nsh; ++k) {
+            d_sh[3 * k + ch] = d[6 + ch] * p->Y[k];
+            gY[k] += d[6 + ch] * sh[3 * k + ch];
+        }
+    }
+    double gmu[3] = {0, 0, 0};
+    const double dn = sqrt(p->dir[0] * p->dir[0] + p->dir[1] * p->dir[1] + p->dir[2] * p->dir[2]);
+    const double h = 1e-6 * dn;
+    for (int c = 0; c < 3; ++c) {
+        double vp[3] = {p->dir[0], p->dir[1], p->dir[2]}, vm[3] = {p->dir[0], p->dir[1], p->dir[2]};
+        vp[c] += h;
+        vm[c] -= h;
+        double Yp[16], Ym[16];
+        orc_sh_basis(vp, degree, Yp);
+        orc_sh_basis(vm, degree, Ym);
+        for (int k = 0; k < nsh; ++k) gmu[c] += gY[k] * (Yp[k] - Ym[k]) / (vp[c] - vm[c]);
+    }
+    /* conic = [c11, -c01, c00] / det */
+    const double a = p->c00, b = p->c01, c = p->c11, det = p->det, d2 = det * det;
+    const double gA = d[2], gB = d[3], gC = d[4];
+    const double ga = gA * (-c * c / d2) + gB * (b * c / d2) + gC * (-b * b / d2);
+    const double gb = gA * (2.0 * b * c / d2) + gB * (-1.0 / det - 2.0 * b * b / d2) + gC * (2.0 * a * b / d2);
+    const double gc = gA * (-b * b / d2) + gB * (a * b / d2) + gC * (-a * a / d2);
+    /* c00 = sum A_k^2 s2_k + 0.3, c01 = sum A_k B_k s2_k, c11 = sum B_k^2 s2_k + 0.3 */
+    double gAr[3], gBr[3];
+    for (int k = 0; k < 3; ++k) {
+        gAr[k] = 2.0 * ga * p->A[k] * p->s2[k] + gb * p->B[k] * p->s2[k];
+        gBr[k] = 2.0 * gc * p->B[k] * p->s2[k] + gb * p->A[k] * p->s2[k];
+        const double gs2 = ga * p->A[k] * p->A[k] + gb * p->A[k] * p->B[k] + gc * p->B[k] * p->B[k];
+        d_log_scales[k] = gs2 * 2.0 * p->s2[k];
+    }
+    /* A = j00 M_0 + j02 M_2, B = j11 M_1 + j12 M_2 */
+    double gj00 = 0, gj02 = 0, gj11 = 0, gj12 = 0, gM[9];
+    for (int k = 0; k < 3; ++k) {
+        gj00 += gAr[k] * p->M[k];
+        gj02 += gAr[k] * p->M[6 + k];
+        gj11 += gBr[k] * p->M[3 + k];
+        gj12 += gBr[k] * p->M[6 + k];
+        gM[k] = gAr[k] * p->j00;
+        gM[3 + k] = gBr[k] * p->j11;
+        gM[6 + k] = gAr[k] * p->j02 + gBr[k] * p->j12;
+    }
+    /* M = R_cam R_q */
+    double gRq[9];
+    for (int l = 0; l < 3; ++l)
+        for (int j = 0; j < 3; ++j) gRq[3 * l + j] = R[l] * gM[j] + R[3 + l] * gM[3 + j] + R[6 + l] * gM[6 + j];
+    const double w = p->qh[0], x = p->qh[1], y = p->qh[2], zq = p->qh[3];
+    const double dRw[9] = {0, -2 * zq, 2 * y, 2 * zq, 0, -2 * x, -2 * y, 2 * x, 0};
+    const double dRx[9] = {0, 2 * y, 2 * zq, 2 * y, -4 * x, -2 * w, 2 * zq, 2 * w, -4 * x};
+    const double dRy[9] = {-4 * y, 2 * x, 2 * w, 2 * x, 0, 2 * zq, -2 * w, 2 * zq, -4 * y};
+    const double dRz[9] = {-4 * zq, -2 * w, 2 * x, 2 * w, -4 * zq, 2 * y, 2 * x, 2 * y, 0};
+    double gq[4] = {0, 0, 0, 0};
+    for (int k = 0; k < 9; ++k) {
+        gq[0] += gRq[k] * dRw[k];
+        gq[1] += gRq[k] * dRx[k];
+        gq[2] += gRq[k] * dRy[k];
+        gq[3] += gRq[k] * dRz[k];
+    }
+    /* q_hat = q / |q| */
+    const double qd = gq[0] * p->qh[0] + gq[1] * p->qh[1] + gq[2] * p->qh[2] + gq[3] * p->qh[3];
+    for (int k = 0; k < 4; ++k) d_quats[k] = (gq[k] - qd * p->qh[k]) / p->qn;
+    /* the Jacobian entries and the screen mean, as functions of the
+       camera-space point */
+    const double z = p->z, X = p->pc[0], Yc = p->pc[1];
+    double gp[3] = {0, 0, 0};
+    gp[2] += gj00 * (-fx / (z * z)) + gj11 * (-fy / (z * z));
+    if (p->clx) gp[2] += gj02 * (fx * p->limx / (z * z));
+    else { gp[0] += gj02 * (-fx / (z * z)); gp[2] += gj02 * (2.0 * fx * X / (z * z * z)); }
+    if (p->cly) gp[2] += gj12 * (fy * p->limy / (z * z));
+    else { gp[1] += gj12 * (-fy / (z * z)); gp[2] += gj12 * (2.0 * fy * Yc / (z * z * z)); }
+    gp[0] += d[0] * fx / z;
+    gp[1] += d[1] * fy / z;
+    gp[2] += -d[0] * fx * X / (z * z) - d[1] * fy * Yc / (z * z);
+    for (int c2 = 0; c2 < 3; ++c2) d_means[c2] = gmu[c2] + R[c2] * gp[0] + R[3 + c2] * gp[1] + R[6 + c2] * gp[2];
+}
+
+/*
+ * Forward image of the binary64 parameters (the tiled definition of
+ * orc_render over the Gaussians orc_project would make visible) into out_rgb
+ * [H][W][3] and out_alpha [H][W]; then, when d_img ([H][W][3], dL/d rgb) is
+ * not NULL, the gradients: d_proj [n][9] = dL/d(mean2d x, y, conic a, b, c,
+ * opacity, r, g, b) and the parameter gradients in the input layouts
+ * (d_sh: [n][(D+1)^2][3]). d_alpha ([H][W], dL/d alpha) may be NULL.
+ * Gaussians that are not visible get zero gradients.
+ */
+ORC_EXPORT int orc_adjoint(int64_t n, const double* means, const double* log_scales, const double* quats,
+                           const double* logits, const double* sh, int sh_degree, const double* cam, int tile_size,
+                           const double* bg, double* out_rgb, double* out_alpha, const double* d_img,
+                           const double* d_alpha, double* d_proj, double* d_means, double* d_log_scales,
+                           double* d_quats, double* d_logits, double* d_sh) {
+    if (n < 0 || sh_degree < 0 || sh_degree > 3 || tile_size <= 0) return 1;
+    const int W = (int)cam[16], H = (int)cam[17];
+    const int nsh = (sh_degree + 1) * (sh_degree + 1);
+    const int tiles_x = (W + tile_size - 1) / tile_size, tiles_y = (H + tile_size - 1) / tile_size;
+    const int64_t T = (int64_t)tiles_x * tiles_y;
+    const size_t n1 = (size_t)(n > 0 ? n : 1);
+    adj_g* P = (adj_g*)calloc(n1, sizeof(adj_g));
+    int64_t* off = (int64_t*)calloc((size_t)T + 1, sizeof(int64_t));
+    if (!P || !off) { free(P); free(off); return 2; }
+#pragma omp parallel for schedule(static)
+    for (int64_t g = 0; g < n; ++g)
+        adj_project_one(means, log_scales, quats, logits, sh, nsh, sh_degree, cam, tile_size, g, &P[g]);
+    /* ordered tile lists, as in orc_render */
+    for (int64_t g = 0; g < n; ++g)
+        if (P[g].vis)
+            for (int y = P[g].rect[1]; y < P[g].rect[3]; ++y)
+                for (int x = P[g].rect[0]; x < P[g].rect[2]; ++x) off[(int64_t)y * tiles_x + x + 1]++;
+    for (int64_t t = 0; t < T; ++t) off[t + 1] += off[t];
+    ord_t* lists = (ord_t*)malloc((size_t)(off[T] > 0 ? off[T] : 1) * sizeof(ord_t));
+    int64_t* cur = (int64_t*)malloc((size_t)(T > 0 ? T : 1) * sizeof(int64_t));
+    if (!lists || !cur) { free(P); free(off); free(lists); free(cur); return 2; }
+    memcpy(cur, off, (size_t)T * sizeof(int64_t));
+    for (int64_t g = 0; g < n; ++g)
+        if (P[g].vis)
+            for (int y = P[g].rect[1]; y < P[g].rect[3]; ++y)
+                for (int x = P[g].rect[0]; x < P[g].rect[2]; ++x) {
+                    const int64_t t = (int64_t)y * tiles_x + x;
+                    lists[cur[t]].key = P[g].key;
+                    lists[cur[t]].gid = (uint32_t)g;
+                    cur[t]++;
+                }
+    for (int64_t t = 0; t < T; ++t) qsort(lists + off[t], (size_t)(off[t + 1] - off[t]), sizeof(ord_t), ord_cmp);
+    int64_t maxlen = 1;
+    for (int64_t t = 0; t < T; ++t) if (off[t + 1] - off[t] > maxlen) maxlen = off[t + 1] - off[t];
+
+    /* per-thread accumulators of dL/d(projected), reduced in thread order */
+    int nth = 1;
+#ifdef _OPENMP
+    nth = omp_get_max_threads();
+#endif
+    double* acc = d_img ? (double*)calloc((size_t)nth * n1 * 9, sizeof(double)) : NULL;
+    if (d_img && !acc) { free(P); free(off); free(lists); free(cur); return 2; }
+    int err = 0;
+#pragma omp parallel num_threads(nth)
+    {
+        int me = 0;
+#ifdef _OPENMP
+        me = omp_get_thread_num();
+#endif
+        adj_c* cl = (adj_c*)malloc((size_t)maxlen * sizeof(adj_c));
+        if (!cl) {
+#pragma omp atomic write
+            err = 2;
+        }
+#pragma omp for schedule(static)
+        for (int py = 0; py < H; ++py) {
+            if (!cl) continue;
+            for (int px = 0; px < W; ++px) {
+                const int64_t t = (int64_t)(py / tile_size) * tiles_x + px / tile_size;
+                double Tr = 1.0, C[3] = {0.0, 0.0, 0.0};
+                int nc = 0;
+                for (int64_t i = off[t]; i < off[t + 1]; ++i) {
+                    const uint32_t g = lists[i].gid;
+                    const double dx = P[g].mean[0] - (px + 0.5), dy = P[g].mean[1] - (py + 0.5);
+                    const double q = P[g].conic[0] * dx * dx + 2.0 * P[g].conic[1] * dx * dy +
+                                     P[g].conic[2] * dy * dy;
+                    const double power = -0.5 * q;
+                    if (power > 0.0) continue;
+                    const double G = exp(power), araw = P[g].o * G;
+                    if (araw < ALPHA_MIN) continue;
+                    const double alpha = fmin(ALPHA_MAX, araw);
+                    const double test = Tr * (1.0 - alpha);
+                    if (test < T_MIN) break;
+                    for (int ch = 0; ch < 3; ++ch) C[ch] += Tr * alpha * P[g].rgb[ch];
+                    cl[nc].g = g; cl[nc].alpha = alpha; cl[nc].T = Tr; cl[nc].G = G;
+                    cl[nc].dx = dx; cl[nc].dy = dy; cl[nc].capped = araw > ALPHA_MAX;
+                    nc++;
+                    Tr = test;
+                }
+                const int64_t pix = (int64_t)py * W + px;
+                for (int ch = 0; ch < 3; ++ch) out_rgb[3 * pix + ch] = C[ch] + Tr * bg[ch];
+                out_alpha[pix] = 1.0 - Tr;
+                if (d_img)
+                    adj_pixel_reverse(P, cl, nc, Tr, bg, d_img + 3 * pix, d_alpha ? d_alpha[pix] : 0.0,
+                                      acc + (size_t)me * n1 * 9);
+            }
+        }
+        free(cl);
+    }
+    if (d_img && !err) {
+#pragma omp parallel for schedule(static)
+        for (int64_t g = 0; g < n; ++g) {
+            double d[9] = {0};
+            for (int th = 0; th < nth; ++th)
+                for (int k = 0; k < 9; ++k) d[k] += acc[((size_t)th * n1 + g) * 9 + k];
+            for (int k = 0; k < 9; ++k) d_proj[9 * g + k] = d[k];
+            for (int k = 0; k < 3; ++k) d_means[3 * g + k] = d_log_scales[3 * g + k] = 0.0;
+            for (int k = 0; k < 4; ++k) d_quats[4 * g + k] = 0.0;
+            d_logits[g] = 0.0;
+            for (int k = 0; k < nsh * 3; ++k) d_sh[(int64_t)g * nsh * 3 + k] = 0.0;
+            if (P[g].vis)
+                adj_project_reverse(&P[g], d, sh + (int64_t)g * nsh * 3, nsh, sh_degree, cam, d_means + 3 * g,
+                                    d_log_scales + 3 * g, d_quats + 4 * g, d_logits + g,
+                                    d_sh + (int64_t)g * nsh * 3);
+        }
+    }
+    free(P); free(off); free(lists); free(cur); free(acc);
+    return err;
+}

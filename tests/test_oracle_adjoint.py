@@ -1,0 +1,193 @@
+"""Pins of the oracle's adjoint (the gradient of a loss of the image).
+
+The paper has no backward pass; the adjoint is the derivative of the forward
+model, so it is pinned by binary64 central finite differences of the same
+forward model (h = 1e-6 max(1, |theta|)) on the 200-Gaussian 64x64 sub-case
+of the 500k training scene, with the loss mean((rgb - target)^2) against a
+U[0, 1] target (seed 1). A parameter whose stencil crosses a discontinuity
+(the 1/255 cut, the stopping rule, a rect edge) shows one-sided differences
+that disagree; such parameters are excluded and counted. Separate cases give
+the paths that the sub-case may not exercise: the 0.99 cap, colour clamped at
+zero, the frustum guard of the Jacobian, a background colour and a loss term
+on alpha. The compositing part alone (gradients with respect to the projected
+quantities) is checked against finite differences of ``oracle.render``.
+"""
+import numpy as np
+
+import oracle
+import scenes
+
+KEYS = ("means", "log_scales", "quats", "logits", "sh")
+
+
+def as64(g):
+    return {k: (np.array(v, np.float64) if k != "sh_degree" else v) for k, v in g.items()}
+
+
+def loss_fn(g, cam, target, bg=(0.0, 0.0, 0.0), w_alpha=None):
+    a = oracle.adjoint(g, cam, bg=bg)
+    L, up = oracle.mse_upstream(a["rgb"], target)
+    if w_alpha is not None:
+        L += float(np.sum(w_alpha * a["alpha"]))
+    return L, up
+
+
+def fd_check(g, cam, target, keys=KEYS, per_key=200, seed=0, bg=(0.0, 0.0, 0.0), w_alpha=None,
+             only=None, rel=1e-4):
+    """Compares the adjoint with central differences on a random sample of
+    each parameter array (or of the Gaussians listed in ``only``). Returns
+    (number compared, number excluded)."""
+    g = as64(g)
+    L0, up = loss_fn(g, cam, target, bg, w_alpha)
+    a = oracle.adjoint(g, cam, bg=bg, d_img=up, d_alpha=w_alpha)
+    rng = np.random.default_rng(seed)
+    compared = excluded = 0
+    for key in keys:
+        arr = g[key]
+        per_g = arr.size // arr.shape[0]
+        if only is None:
+            idx = rng.choice(arr.size, size=min(per_key, arr.size), replace=False)
+        else:
+            idx = np.concatenate([np.arange(per_g) + per_g * i for i in only])
+        gmax = np.abs(a[key]).max()
+        for i in idx:
+            th = float(arr.reshape(-1)[i])
+            h = 1e-6 * max(1.0, abs(th))
+            vals = []
+            for s in (+1, -1):
+                gg = dict(g)
+                gg[key] = arr.copy()
+                gg[key].reshape(-1)[i] = th + s * h
+                vals.append(loss_fn(gg, cam, target, bg, w_alpha)[0])
+            Lp, Lm = vals
+            if abs((Lp - L0) / h - (L0 - Lm) / h) > 1e-4 * gmax + 1e-9:
+                excluded += 1
+                continue
+            fd = (Lp - Lm) / (2 * h)
+            ad = a[key].reshape(-1)[i]
+            assert abs(ad - fd) <= rel * (abs(fd) + 1e-3 * gmax) + 1e-10, (key, int(i), ad, fd)
+            compared += 1
+    return compared, excluded
+
+
+def test_adjoint_forward_is_the_tiled_image():
+    for g, cam in (scenes.fd_subcase(), scenes.small_forward(n=500)):
+        for bg in ((0.0, 0.0, 0.0), (0.3, 0.6, 0.9)):
+            ref = oracle.render(oracle.project(g, cam), cam["width"], cam["height"], bg=bg)
+            a = oracle.adjoint(g, cam, bg=bg)
+            np.testing.assert_allclose(a["rgb"], ref["rgb"], rtol=0, atol=1e-12)
+            np.testing.assert_allclose(a["alpha"], ref["alpha"], rtol=0, atol=1e-12)
+
+
+def test_adjoint_matches_central_differences_on_fd_subcase():
+    g, cam = scenes.fd_subcase()
+    target = scenes.training_target(cam["width"], cam["height"])
+    compared, excluded = fd_check(g, cam, target)
+    assert compared >= 950 and excluded <= 0.02 * (compared + excluded), (compared, excluded)
+
+
+def test_adjoint_with_background_and_alpha_term():
+    g, cam = scenes.fd_subcase()
+    target = scenes.training_target(cam["width"], cam["height"])
+    w = np.random.default_rng(5).normal(0.0, 1e-4, size=(cam["height"], cam["width"]))
+    compared, excluded = fd_check(g, cam, target, per_key=60, seed=1, bg=(0.2, 0.5, 0.8), w_alpha=w)
+    assert compared >= 280 and excluded <= 6
+
+
+def _one(mean, log_scale, logit, sh0, quat=(1.0, 0.0, 0.0, 0.0), degree=0):
+    nsh = (degree + 1) ** 2
+    sh = np.zeros((1, nsh, 3))
+    sh[0, 0] = sh0
+    return {"means": np.array([mean], np.float64), "log_scales": np.array([log_scale], np.float64),
+            "quats": np.array([quat], np.float64), "logits": np.array([logit], np.float64), "sh": sh,
+            "sh_degree": degree}
+
+
+def _cat(*gs):
+    return {k: (np.concatenate([x[k] for x in gs]) if k != "sh_degree" else gs[0][k]) for k in gs[0]}
+
+
+def test_adjoint_capped_alpha_and_clamped_colour():
+    cam = scenes.camera(np.eye(3), np.zeros(3), 40.0, 40.0, 20.0, 20.0, 40, 40)
+    # o = sigmoid(7) ~ 0.9991: alpha is capped at 0.99 near the centre; the
+    # red channel's raw colour is negative, so it is clamped to zero
+    a = _one((0.05, -0.02, 3.0), (-1.6, -1.9, -1.7), 7.0, (-3.0, 0.8, 0.3), quat=(0.9, 0.2, -0.3, 0.1))
+    b = _one((-0.1, 0.1, 4.0), (-1.3, -1.5, -1.4), 0.5, (0.4, -0.2, 0.9))
+    g = _cat(a, b)
+    target = np.full((40, 40, 3), 0.25)
+    ga = as64(g)
+    alone = oracle.adjoint(as64(a), cam)
+    assert alone["alpha"].max() == 0.99 and alone["rgb"][..., 0].max() == 0.0
+    out = oracle.adjoint(ga, cam)
+    _, up = oracle.mse_upstream(out["rgb"], target)
+    grads = oracle.adjoint(ga, cam, d_img=up)
+    assert grads["sh"][0, 0, 0] == 0.0  # clamped channel
+    compared, excluded = fd_check(g, cam, target, only=[0, 1])
+    assert compared >= 20 and excluded == 0
+
+
+def test_adjoint_frustum_guard():
+    # mean far right of the image (x / z beyond the guard): the Jacobian uses
+    # the guarded tx, which no longer depends on x
+    cam = scenes.camera(np.eye(3), np.zeros(3), 30.0, 30.0, 16.0, 16.0, 32, 32)
+    far = _one((3.0, 0.05, 2.0), (0.2, -0.4, 0.1), 2.0, (0.6, 0.2, 0.1), quat=(0.8, 0.1, 0.5, -0.2))
+    near = _one((0.1, 0.0, 3.0), (-2.0, -2.1, -2.2), 1.0, (0.1, 0.3, 0.5))
+    g = _cat(far, near)
+    cam_d = dict(cam)
+    lim = (32 - 16.0) / 30.0 + 0.3 * 32 / 30.0
+    assert 3.0 / 2.0 > lim
+    target = np.full((32, 32, 3), 0.5)
+    ga = as64(g)
+    out = oracle.adjoint(ga, cam_d)
+    assert out["alpha"][:, -4:].max() > 0.05  # the far Gaussian reaches the image
+    compared, excluded = fd_check(g, cam_d, target, only=[0, 1])
+    assert compared >= 20 and excluded == 0
+
+
+def test_compositing_adjoint_matches_render_differences():
+    # dL/d(mean2d, conic, opacity, rgb) against central differences of the
+    # plain per-pixel compositing in oracle.render
+    g, cam = scenes.fd_subcase()
+    W, H = cam["width"], cam["height"]
+    target = scenes.training_target(W, H)
+    proj = oracle.project(g, cam)
+    img = oracle.render(proj, W, H)
+    L0, up = oracle.mse_upstream(img["rgb"], target)
+    d = oracle.adjoint(as64(g), cam, d_img=up)["d_proj"]
+    fields = [("mean2d", 0), ("mean2d", 1), ("conic", 0), ("conic", 1), ("conic", 2), ("opacity", None),
+              ("rgb", 0), ("rgb", 1), ("rgb", 2)]
+    rng = np.random.default_rng(3)
+    vis = np.flatnonzero(proj["flags"] & oracle.VISIBLE)
+    compared = 0
+    for j, (name, comp) in enumerate(fields):
+        gmax = np.abs(d[:, j]).max()
+        for gi in rng.choice(vis, size=25, replace=False):
+            base = proj[name][gi] if comp is None else proj[name][gi, comp]
+            h = 1e-6 * max(1.0, abs(base))
+            vals = []
+            for s in (+1, -1):
+                p = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in proj.items()}
+                if comp is None:
+                    p[name][gi] = base + s * h
+                else:
+                    p[name][gi, comp] = base + s * h
+                vals.append(oracle.mse_upstream(oracle.render(p, W, H)["rgb"], target)[0])
+            if abs((vals[0] - L0) - (L0 - vals[1])) / h > 1e-4 * gmax + 1e-9:
+                continue
+            fd = (vals[0] - vals[1]) / (2 * h)
+            assert abs(d[gi, j] - fd) <= 1e-4 * (abs(fd) + 1e-3 * gmax) + 5e-10, (name, comp, gi, d[gi, j], fd)
+            compared += 1
+    assert compared >= 200
+
+
+def test_invisible_gaussians_have_zero_gradient():
+    g, cam = scenes.fd_subcase()
+    g = as64(g)
+    g["means"][:5, 2] = -1.0  # behind the camera
+    g["logits"][5:8] = -8.0   # opacity below 1/255
+    target = scenes.training_target(cam["width"], cam["height"])
+    _, up = oracle.mse_upstream(oracle.adjoint(g, cam)["rgb"], target)
+    a = oracle.adjoint(g, cam, d_img=up)
+    for k in KEYS:
+        assert not np.any(a[k][:8]), k
+    assert np.abs(a["means"][8:]).max() > 0
