@@ -20,6 +20,12 @@
  *   tgs_rasterize  front-to-back alpha compositing of each tile's one
  *                  contiguous range (Algorithm "Binned raster traversal after
  *                  repair").
+ *   tgs_rasterize_backward, tgs_project_backward
+ *                  the gradient of a loss of the image with respect to the
+ *                  splats and then to the Gaussian parameters. The paper
+ *                  names training as future work (Conclusion); these are the
+ *                  derivatives of the forward model above over the same
+ *                  entry streams.
  *
  * Conventions
  *  - Pointers named *_dev are device pointers (hipMalloc'd or torch CUDA
@@ -194,6 +200,43 @@ TGS_API tgs_status tgs_rasterize(const tgs_projected* projected, const tgs_binne
                          const float* bg, float* rgb_dev, float* alpha_dev, int32_t* last_dev,
                          int32_t* n_contrib_dev, int32_t* n_visit_dev, int32_t* n_support_dev,
                          void* stream);
+
+/* Gradient lines of tgs_rasterize_backward: [n][12] fp32 per Gaussian,
+   dL/d of the splat's mean_x, mean_y (the mean hi + lo), conic_a, conic_b,
+   conic_c, opacity, r, g, b, then three zero words. */
+#define TGS_GRAD_WORDS 12
+
+/* Backward of tgs_rasterize for the same projected splats, entry stream
+   (tgs_bin output of `order`, unchanged since), camera, params and bg:
+   given d_rgb [H][W][3] = dL/d rgb and d_alpha [H][W] = dL/d alpha (NULL =
+   zero), writes d_splats [n][TGS_GRAD_WORDS] (overwritten; entries of
+   Gaussians that no pixel composited are zero). The per-pixel traversal is
+   recomputed from the stream, so no forward output is needed. Gradients
+   are summed with float atomics: the summation order, and so the last bits,
+   may differ between runs. With the overflow flag set in counters[2] the
+   result is all zero. */
+TGS_API tgs_status tgs_rasterize_backward(const tgs_projected* projected, const tgs_binned* binned,
+                                  const tgs_camera* camera, const tgs_params* params, int32_t order,
+                                  const float* bg, const float* d_rgb_dev, const float* d_alpha_dev,
+                                  float* d_splats_dev, void* stream);
+
+/* Parameter gradients, device pointers, fp32, in the layouts of
+   tgs_gaussians (sh: [n][(D+1)^2][3]); every element is overwritten. */
+typedef struct {
+    float* means_dev;
+    float* log_scales_dev;
+    float* quats_dev;
+    float* logits_dev;
+    float* sh_dev;
+} tgs_gaussian_grads;
+
+/* Backward of tgs_project: from the gradient lines d_splats [n][12] to
+   dL/d(means, log_scales, quats, logits, sh), recomputing the projection in
+   binary64. Gaussians that tgs_project makes invisible get zero gradients;
+   colour channels clamped at zero and the frustum guard of the Jacobian
+   pass no gradient, as in the forward definition. */
+TGS_API tgs_status tgs_project_backward(const tgs_gaussians* gaussians, const tgs_camera* camera,
+                                const float* d_splats_dev, tgs_gaussian_grads* grads, void* stream);
 
 /* Message for the last failing call on this thread ("" if none). */
 TGS_API const char* tgs_last_error(void);

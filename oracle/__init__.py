@@ -58,6 +58,7 @@ def lib():
         L.orc_schedule.argtypes = [i64, P, P, i32, i32, i32, i32, dbl, dbl, flt, flt, flt,
                                    P, P, P, P, P, P]
         L.orc_adjoint.argtypes = [i64, P, P, P, P, P, i32, P, i32, P, P, P, P, P, P, P, P, P, P, P]
+        L.orc_composite_adjoint.argtypes = [i64, P, P, P, P, P, P, P, i32, i32, i32, P, P, P, P, P, P]
         _lib = L
     return _lib
 
@@ -229,3 +230,24 @@ def mse_upstream(rgb, target):
     with respect to rgb."""
     d = np.asarray(rgb, np.float64) - np.asarray(target, np.float64)
     return float(np.mean(d * d)), 2.0 * d / d.size
+
+
+def composite_adjoint(proj, width, height, tile_size=16, bg=(0.0, 0.0, 0.0), d_img=None, d_alpha=None):
+    """The compositing adjoint alone for projected records (the dict that
+    ``render`` takes): image ``rgb`` [H, W, 3], ``alpha`` [H, W] and, when
+    ``d_img`` is given, ``d_proj`` [n, 9] (mean2d x, y, conic a, b, c,
+    opacity, r, g, b)."""
+    n = proj["mean2d"].shape[0]
+    out = {"rgb": np.zeros((height, width, 3)), "alpha": np.zeros((height, width))}
+    dp = np.zeros((n, 9)) if d_img is not None else None
+    flags = None if proj.get("flags") is None else _c(proj["flags"], np.uint8)
+    rc = lib().orc_composite_adjoint(
+        n, _p(_c(proj["mean2d"], np.float64)), _p(_c(proj["conic"], np.float64)),
+        _p(_c(proj["opacity"], np.float64)), _p(_c(proj["rgb"], np.float64)), _p(_c(proj["depth_key"], np.float32)),
+        _p(_c(proj["rect"], np.int32)), _p(flags), int(width), int(height), int(tile_size), _p(_c(bg, np.float64)),
+        _p(None if d_img is None else _c(d_img, np.float64)), _p(None if d_alpha is None else _c(d_alpha, np.float64)),
+        _p(out["rgb"]), _p(out["alpha"]), _p(dp))
+    assert rc == 0, rc
+    if dp is not None:
+        out["d_proj"] = dp
+    return out

@@ -860,31 +860,19 @@ static void adj_project_reverse(const adj_g* p, const double* d, const double* s
 }
 
 /*
- * Forward image of the binary64 parameters (the tiled definition of
- * orc_render over the Gaussians orc_project would make visible) into out_rgb
- * [H][W][3] and out_alpha [H][W]; then, when d_img ([H][W][3], dL/d rgb) is
- * not NULL, the gradients: d_proj [n][9] = dL/d(mean2d x, y, conic a, b, c,
- * opacity, r, g, b) and the parameter gradients in the input layouts
- * (d_sh: [n][(D+1)^2][3]). d_alpha ([H][W], dL/d alpha) may be NULL.
- * Gaussians that are not visible get zero gradients.
+ * Tiled compositing of the projected Gaussians P[0..n) (those with vis set),
+ * the per-pixel definition of orc_render: the image into out_rgb [H][W][3]
+ * and out_alpha [H][W]; with d_img != NULL also dL/d(projected) into d_proj
+ * [n][9] (mean2d x, y, conic a, b, c, opacity, r, g, b).
  */
-ORC_EXPORT int orc_adjoint(int64_t n, const double* means, const double* log_scales, const double* quats,
-                           const double* logits, const double* sh, int sh_degree, const double* cam, int tile_size,
-                           const double* bg, double* out_rgb, double* out_alpha, const double* d_img,
-                           const double* d_alpha, double* d_proj, double* d_means, double* d_log_scales,
-                           double* d_quats, double* d_logits, double* d_sh) {
-    if (n < 0 || sh_degree < 0 || sh_degree > 3 || tile_size <= 0) return 1;
-    const int W = (int)cam[16], H = (int)cam[17];
-    const int nsh = (sh_degree + 1) * (sh_degree + 1);
+static int adj_composite(const adj_g* P, int64_t n, int W, int H, int tile_size, const double* bg,
+                         double* out_rgb, double* out_alpha, const double* d_img, const double* d_alpha,
+                         double* d_proj) {
     const int tiles_x = (W + tile_size - 1) / tile_size, tiles_y = (H + tile_size - 1) / tile_size;
     const int64_t T = (int64_t)tiles_x * tiles_y;
     const size_t n1 = (size_t)(n > 0 ? n : 1);
-    adj_g* P = (adj_g*)calloc(n1, sizeof(adj_g));
     int64_t* off = (int64_t*)calloc((size_t)T + 1, sizeof(int64_t));
-    if (!P || !off) { free(P); free(off); return 2; }
-#pragma omp parallel for schedule(static)
-    for (int64_t g = 0; g < n; ++g)
-        adj_project_one(means, log_scales, quats, logits, sh, nsh, sh_degree, cam, tile_size, g, &P[g]);
+    if (!off) return 2;
     /* ordered tile lists, as in orc_render */
     for (int64_t g = 0; g < n; ++g)
         if (P[g].vis)
@@ -893,7 +881,7 @@ ORC_EXPORT int orc_adjoint(int64_t n, const double* means, const double* log_sca
     for (int64_t t = 0; t < T; ++t) off[t + 1] += off[t];
     ord_t* lists = (ord_t*)malloc((size_t)(off[T] > 0 ? off[T] : 1) * sizeof(ord_t));
     int64_t* cur = (int64_t*)malloc((size_t)(T > 0 ? T : 1) * sizeof(int64_t));
-    if (!lists || !cur) { free(P); free(off); free(lists); free(cur); return 2; }
+    if (!lists || !cur) { free(off); free(lists); free(cur); return 2; }
     memcpy(cur, off, (size_t)T * sizeof(int64_t));
     for (int64_t g = 0; g < n; ++g)
         if (P[g].vis)
@@ -904,6 +892,7 @@ ORC_EXPORT int orc_adjoint(int64_t n, const double* means, const double* log_sca
                     lists[cur[t]].gid = (uint32_t)g;
                     cur[t]++;
                 }
+#pragma omp parallel for schedule(dynamic, 16)
     for (int64_t t = 0; t < T; ++t) qsort(lists + off[t], (size_t)(off[t + 1] - off[t]), sizeof(ord_t), ord_cmp);
     int64_t maxlen = 1;
     for (int64_t t = 0; t < T; ++t) if (off[t + 1] - off[t] > maxlen) maxlen = off[t + 1] - off[t];
@@ -914,7 +903,7 @@ ORC_EXPORT int orc_adjoint(int64_t n, const double* means, const double* log_sca
     nth = omp_get_max_threads();
 #endif
     double* acc = d_img ? (double*)calloc((size_t)nth * n1 * 9, sizeof(double)) : NULL;
-    if (d_img && !acc) { free(P); free(off); free(lists); free(cur); return 2; }
+    if (d_img && !acc) { free(off); free(lists); free(cur); return 2; }
     int err = 0;
 #pragma omp parallel num_threads(nth)
     {
@@ -964,21 +953,83 @@ ORC_EXPORT int orc_adjoint(int64_t n, const double* means, const double* log_sca
     }
     if (d_img && !err) {
 #pragma omp parallel for schedule(static)
+        for (int64_t g = 0; g < n; ++g)
+            for (int k = 0; k < 9; ++k) {
+                double v = 0.0;
+                for (int th = 0; th < nth; ++th) v += acc[((size_t)th * n1 + g) * 9 + k];
+                d_proj[9 * g + k] = v;
+            }
+    }
+    free(off); free(lists); free(cur); free(acc);
+    return err;
+}
+
+/*
+ * Forward image of the binary64 parameters (the tiled definition of
+ * orc_render over the Gaussians orc_project would make visible) into out_rgb
+ * [H][W][3] and out_alpha [H][W]; then, when d_img ([H][W][3], dL/d rgb) is
+ * not NULL, the gradients: d_proj [n][9] = dL/d(mean2d x, y, conic a, b, c,
+ * opacity, r, g, b) and the parameter gradients in the input layouts
+ * (d_sh: [n][(D+1)^2][3]). d_alpha ([H][W], dL/d alpha) may be NULL.
+ * Gaussians that are not visible get zero gradients.
+ */
+ORC_EXPORT int orc_adjoint(int64_t n, const double* means, const double* log_scales, const double* quats,
+                           const double* logits, const double* sh, int sh_degree, const double* cam, int tile_size,
+                           const double* bg, double* out_rgb, double* out_alpha, const double* d_img,
+                           const double* d_alpha, double* d_proj, double* d_means, double* d_log_scales,
+                           double* d_quats, double* d_logits, double* d_sh) {
+    if (n < 0 || sh_degree < 0 || sh_degree > 3 || tile_size <= 0) return 1;
+    const int W = (int)cam[16], H = (int)cam[17];
+    const int nsh = (sh_degree + 1) * (sh_degree + 1);
+    adj_g* P = (adj_g*)calloc((size_t)(n > 0 ? n : 1), sizeof(adj_g));
+    if (!P) return 2;
+#pragma omp parallel for schedule(static)
+    for (int64_t g = 0; g < n; ++g)
+        adj_project_one(means, log_scales, quats, logits, sh, nsh, sh_degree, cam, tile_size, g, &P[g]);
+    int err = adj_composite(P, n, W, H, tile_size, bg, out_rgb, out_alpha, d_img, d_alpha, d_proj);
+    if (d_img && !err) {
+#pragma omp parallel for schedule(static)
         for (int64_t g = 0; g < n; ++g) {
-            double d[9] = {0};
-            for (int th = 0; th < nth; ++th)
-                for (int k = 0; k < 9; ++k) d[k] += acc[((size_t)th * n1 + g) * 9 + k];
-            for (int k = 0; k < 9; ++k) d_proj[9 * g + k] = d[k];
             for (int k = 0; k < 3; ++k) d_means[3 * g + k] = d_log_scales[3 * g + k] = 0.0;
             for (int k = 0; k < 4; ++k) d_quats[4 * g + k] = 0.0;
             d_logits[g] = 0.0;
             for (int k = 0; k < nsh * 3; ++k) d_sh[(int64_t)g * nsh * 3 + k] = 0.0;
             if (P[g].vis)
-                adj_project_reverse(&P[g], d, sh + (int64_t)g * nsh * 3, nsh, sh_degree, cam, d_means + 3 * g,
-                                    d_log_scales + 3 * g, d_quats + 4 * g, d_logits + g,
+                adj_project_reverse(&P[g], d_proj + 9 * g, sh + (int64_t)g * nsh * 3, nsh, sh_degree, cam,
+                                    d_means + 3 * g, d_log_scales + 3 * g, d_quats + 4 * g, d_logits + g,
                                     d_sh + (int64_t)g * nsh * 3);
         }
     }
-    free(P); free(off); free(lists); free(cur); free(acc);
+    free(P);
+    return err;
+}
+
+/*
+ * The compositing adjoint alone, for projected records in the layout of
+ * orc_render (mean2d [n][2], conic [n][3], opacity [n], rgb [n][3],
+ * depth_key [n], rect [n][4]; gflags NULL = every Gaussian with a non-empty
+ * rect is visible): the image into out_rgb / out_alpha and, when d_img is
+ * not NULL, d_proj [n][9] as in orc_adjoint.
+ */
+ORC_EXPORT int orc_composite_adjoint(int64_t n, const double* mean2d, const double* conic, const double* opacity,
+                                     const double* rgb, const float* depth_key, const int32_t* rect,
+                                     const uint8_t* gflags, int width, int height, int tile_size, const double* bg,
+                                     const double* d_img, const double* d_alpha, double* out_rgb, double* out_alpha,
+                                     double* d_proj) {
+    if (n < 0 || width <= 0 || height <= 0 || tile_size <= 0) return 1;
+    adj_g* P = (adj_g*)calloc((size_t)(n > 0 ? n : 1), sizeof(adj_g));
+    if (!P) return 2;
+    for (int64_t g = 0; g < n; ++g) {
+        for (int k = 0; k < 4; ++k) P[g].rect[k] = rect[4 * g + k];
+        P[g].vis = (gflags ? (gflags[g] & ORC_VISIBLE) != 0 : 1) && rect[4 * g + 2] > rect[4 * g] &&
+                   rect[4 * g + 3] > rect[4 * g + 1];
+        P[g].mean[0] = mean2d[2 * g];
+        P[g].mean[1] = mean2d[2 * g + 1];
+        for (int k = 0; k < 3; ++k) { P[g].conic[k] = conic[3 * g + k]; P[g].rgb[k] = rgb[3 * g + k]; }
+        P[g].o = opacity[g];
+        P[g].key = depth_key[g];
+    }
+    int err = adj_composite(P, n, width, height, tile_size, bg, out_rgb, out_alpha, d_img, d_alpha, d_proj);
+    free(P);
     return err;
 }

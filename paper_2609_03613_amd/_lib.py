@@ -17,7 +17,8 @@ ORDER_GLOBAL, ORDER_BINNED = 0, 1
 RASTER_PLAIN, RASTER_WAVE = 0, 1
 
 EXPORTS = ("tgs_default_params", "tgs_project", "tgs_bin_workspace_size", "tgs_bin", "tgs_rasterize",
-           "tgs_last_error")
+           "tgs_rasterize_backward", "tgs_project_backward", "tgs_last_error")
+GRAD_WORDS = 12
 
 _c_p = ctypes.c_void_p
 
@@ -50,6 +51,10 @@ class Binned(ctypes.Structure):
                 ("tile_order", _c_p)]
 
 
+class GaussianGrads(ctypes.Structure):
+    _fields_ = [("means", _c_p), ("log_scales", _c_p), ("quats", _c_p), ("logits", _c_p), ("sh", _c_p)]
+
+
 class TileGSError(RuntimeError):
     def __init__(self, status, message):
         super().__init__(f"tilegs status {status}: {message}")
@@ -79,6 +84,11 @@ def lib():
         L.tgs_rasterize.argtypes = [P(Projected), P(Binned), P(Camera), P(Params), ctypes.c_int32,
                                     P(ctypes.c_float), _c_p, _c_p, _c_p, _c_p, _c_p, _c_p, _c_p]
         L.tgs_rasterize.restype = ctypes.c_int
+        L.tgs_rasterize_backward.argtypes = [P(Projected), P(Binned), P(Camera), P(Params), ctypes.c_int32,
+                                             P(ctypes.c_float), _c_p, _c_p, _c_p, _c_p]
+        L.tgs_rasterize_backward.restype = ctypes.c_int
+        L.tgs_project_backward.argtypes = [P(Gaussians), P(Camera), _c_p, P(GaussianGrads), _c_p]
+        L.tgs_project_backward.restype = ctypes.c_int
         L.tgs_last_error.argtypes = []
         L.tgs_last_error.restype = ctypes.c_char_p
         _lib = L

@@ -140,13 +140,18 @@ class Renderer:
             self._ws[order] = ws
         return ws
 
-    def bin(self, splats, info, order="binned", capacity=None, sync=True):
+    def bin(self, splats, info, order="binned", capacity=None, sync=True, fresh=False):
         """tgs_bin. With sync, the entry count is read back and the buffers are
-        grown (and the call repeated) when it exceeds their capacity."""
+        grown (and the call repeated) when it exceeds their capacity. With
+        fresh, new entry buffers are allocated (a stream that must outlive
+        the next call, e.g. one a backward pass will read)."""
         o = ORDERS[order] if isinstance(order, str) else order
         n = int(splats.shape[0])
         pr = L.Projected(_ptr(splats).value, _ptr(info).value, n)
         b = self._binned.get(o)
+        if fresh and b is not None:
+            capacity = max(capacity or 0, b.capacity)
+            b = None
         if b is None or (capacity is not None and b.capacity < capacity):
             b = Binned(o, capacity if capacity is not None else max(1024, 4 * n), self.tiles,
                        self.params.num_bins, self.params.packed, self.device, self.params.tile_order)
@@ -190,6 +195,22 @@ class Renderer:
                                       _ptr(out.get("n_visit")), _ptr(out.get("n_support")), _stream()))
         return out
 
+    def rasterize_backward(self, splats, info, binned, d_rgb, d_alpha=None, bg=(0.0, 0.0, 0.0), out=None):
+        """tgs_rasterize_backward: gradient lines [n, 12] (dL/d mean_x, mean_y,
+        conic a, b, c, opacity, r, g, b, 0, 0, 0) from dL/d rgb [H, W, 3] and
+        dL/d alpha [H, W] (None = zero)."""
+        n = int(splats.shape[0])
+        if out is None:
+            out = torch.empty((n, L.GRAD_WORDS), dtype=torch.float32, device=self.device)
+        d_rgb = d_rgb.contiguous().float()
+        d_alpha = None if d_alpha is None else d_alpha.contiguous().float()
+        pr = L.Projected(_ptr(splats).value, _ptr(info).value, n)
+        bgc = (ctypes.c_float * 3)(*[float(v) for v in bg])
+        L.check(L.lib().tgs_rasterize_backward(ctypes.byref(pr), ctypes.byref(binned.c()), ctypes.byref(self.ccam),
+                                               ctypes.byref(self.cparams), binned.order, bgc, _ptr(d_rgb),
+                                               _ptr(d_alpha), _ptr(out), _stream()))
+        return out
+
     def render(self, g, order="binned", bg=(0.0, 0.0, 0.0), counts=False):
         splats, info = project(g, self.cam, self.params)
         b = self.bin(splats, info, order)
@@ -200,3 +221,53 @@ class Renderer:
 
 def render(g, cam, params=None, order="binned", bg=(0.0, 0.0, 0.0), counts=False):
     return Renderer(cam, params, device=g["means"].device).render(g, order=order, bg=bg, counts=counts)
+
+
+def _gaussians_struct(g):
+    n = int(g["means"].shape[0])
+    return L.Gaussians(_ptr(g["means"]).value, _ptr(g["log_scales"]).value, _ptr(g["quats"]).value,
+                       _ptr(g["logits"]).value, _ptr(g["sh"]).value, n, int(g["sh_degree"]))
+
+
+def project_backward(g, cam, d_splats):
+    """tgs_project_backward: dict of parameter gradients (same shapes as
+    ``g``'s tensors) from the gradient lines [n, 12]."""
+    gr = {k: torch.empty_like(g[k]) for k in ("means", "log_scales", "quats", "logits", "sh")}
+    out = L.GaussianGrads(_ptr(gr["means"]).value, _ptr(gr["log_scales"]).value, _ptr(gr["quats"]).value,
+                          _ptr(gr["logits"]).value, _ptr(gr["sh"]).value)
+    L.check(L.lib().tgs_project_backward(ctypes.byref(_gaussians_struct(g)), ctypes.byref(camera_struct(cam)),
+                                         _ptr(d_splats.contiguous()), ctypes.byref(out), _stream()))
+    return gr
+
+
+class _RenderFn(torch.autograd.Function):
+    """Image (rgb, alpha) of the Gaussian parameters; backward through
+    tgs_rasterize_backward and tgs_project_backward."""
+
+    @staticmethod
+    def forward(ctx, means, log_scales, quats, logits, sh, renderer, sh_degree, order, bg):
+        g = {"means": means.contiguous(), "log_scales": log_scales.contiguous(), "quats": quats.contiguous(),
+             "logits": logits.contiguous(), "sh": sh.contiguous(), "sh_degree": int(sh_degree)}
+        splats, info = project(g, renderer.cam, renderer.params)
+        binned = renderer.bin(splats, info, order, fresh=True)
+        out = renderer.rasterize(splats, info, binned, bg=bg)
+        ctx.renderer, ctx.binned, ctx.bg, ctx.g = renderer, binned, bg, g
+        ctx.save_for_backward(splats, info)
+        return out["rgb"], out["alpha"]
+
+    @staticmethod
+    def backward(ctx, d_rgb, d_alpha):
+        splats, info = ctx.saved_tensors
+        r = ctx.renderer
+        if d_rgb is None:
+            d_rgb = torch.zeros((int(r.cam["height"]), int(r.cam["width"]), 3), device=splats.device)
+        d_splats = r.rasterize_backward(splats, info, ctx.binned, d_rgb, d_alpha, bg=ctx.bg)
+        gr = project_backward(ctx.g, r.cam, d_splats)
+        return gr["means"], gr["log_scales"], gr["quats"], gr["logits"], gr["sh"], None, None, None, None
+
+
+def render_differentiable(renderer, g, order="binned", bg=(0.0, 0.0, 0.0)):
+    """(rgb [H, W, 3], alpha [H, W]) as differentiable functions of g's
+    means, log_scales, quats, logits and sh tensors."""
+    return _RenderFn.apply(g["means"], g["log_scales"], g["quats"], g["logits"], g["sh"], renderer,
+                           int(g["sh_degree"]), order, tuple(float(v) for v in bg))

@@ -318,4 +318,60 @@ tgs_status tgs_rasterize(const tgs_projected* pr, const tgs_binned* b, const tgs
     return TGS_OK;
 }
 
+tgs_status tgs_rasterize_backward(const tgs_projected* pr, const tgs_binned* b, const tgs_camera* cam,
+                                  const tgs_params* params, int32_t order, const float* bg, const float* d_rgb,
+                                  const float* d_alpha, float* d_splats, void* stream) {
+    g_err.clear();
+    tgs_status st = check_projected(pr);
+    if (st) return st;
+    if ((st = check_camera(cam))) return st;
+    if ((st = check_params(params))) return st;
+    if (order != TGS_ORDER_GLOBAL && order != TGS_ORDER_BINNED) return fail(TGS_ERR_INVALID_ARG, "unknown order %d", order);
+    if (!b || !b->offsets_dev || !b->counters_dev) return fail(TGS_ERR_INVALID_ARG, "binned buffers are NULL");
+    if (!bg || !d_rgb) return fail(TGS_ERR_INVALID_ARG, "bg or d_rgb is NULL");
+    if (pr->n > 0 && !d_splats) return fail(TGS_ERR_INVALID_ARG, "d_splats is NULL");
+    RasterArgs a{};
+    a.splats = pr->splats_dev;
+    a.offsets = b->offsets_dev;
+    a.counters = b->counters_dev;
+    a.order = b->tile_order_dev;
+    if (order == TGS_ORDER_GLOBAL) {
+        a.stride = 1;
+        a.vals = b->vals_dev;
+        if (!a.vals && b->capacity > 0) return fail(TGS_ERR_INVALID_ARG, "vals is NULL");
+    } else {
+        a.stride = params->num_bins;
+        a.pairs = b->pairs_dev;
+        if (!a.pairs && b->capacity > 0) return fail(TGS_ERR_INVALID_ARG, "pairs is NULL");
+    }
+    a.width = cam->width;
+    a.height = cam->height;
+    a.tiles_x = div_up(cam->width, kTile);
+    a.tiles_y = div_up(cam->height, kTile);
+    for (int i = 0; i < 3; ++i) a.bg[i] = bg[i];
+    hipStream_t s = (hipStream_t)stream;
+    if (pr->n == 0) return TGS_OK;
+    TGS_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(d_splats), 0u, pr->n * kGradWords, s), "fill");
+    TGS_HIP(launch_raster_backward(a, d_rgb, d_alpha, d_splats, s), "raster backward");
+    return TGS_OK;
+}
+
+tgs_status tgs_project_backward(const tgs_gaussians* g, const tgs_camera* cam, const float* d_splats,
+                                tgs_gaussian_grads* out, void* stream) {
+    g_err.clear();
+    if (!g) return fail(TGS_ERR_INVALID_ARG, "gaussians is NULL");
+    if (g->n < 0 || g->n >= (int64_t)1 << 31) return fail(TGS_ERR_INVALID_ARG, "n = %lld outside 0..2^31-1", (long long)g->n);
+    if (g->sh_degree < 0 || g->sh_degree > 3) return fail(TGS_ERR_INVALID_ARG, "sh_degree %d outside 0..3", g->sh_degree);
+    if (g->n > 0 && (!g->means_dev || !g->log_scales_dev || !g->quats_dev || !g->logits_dev || !g->sh_dev))
+        return fail(TGS_ERR_INVALID_ARG, "a Gaussian attribute pointer is NULL");
+    tgs_status st = check_camera(cam);
+    if (st) return st;
+    if (!out) return fail(TGS_ERR_INVALID_ARG, "grads is NULL");
+    if (g->n > 0 && (!d_splats || !out->means_dev || !out->log_scales_dev || !out->quats_dev || !out->logits_dev ||
+                     !out->sh_dev))
+        return fail(TGS_ERR_INVALID_ARG, "a gradient pointer is NULL");
+    TGS_HIP(launch_project_backward(*g, make_cam(*cam), d_splats, *out, (hipStream_t)stream), "project backward");
+    return TGS_OK;
+}
+
 }  // extern "C"

@@ -293,4 +293,16 @@ struct RasterArgs {
 hipError_t launch_raster_plain(const RasterArgs& a, hipStream_t s);
 hipError_t launch_raster_wave(const RasterArgs& a, hipStream_t s);
 
+// Gradient lines: 12 floats per Gaussian (dL/d mean_x, mean_y, conic a, b,
+// c, opacity, r, g, b, then 3 zero words).
+constexpr int kGradWords = 12;
+
+// dL/d(splat) into d_splats [n][kGradWords], which must be zero (float
+// atomics accumulate into it).
+hipError_t launch_raster_backward(const RasterArgs& a, const float* d_rgb, const float* d_alpha, float* d_splats,
+                                  hipStream_t s);
+// Parameter gradients from the gradient lines; every output is overwritten.
+hipError_t launch_project_backward(const tgs_gaussians& g, const Cam& cam, const float* d_splats,
+                                   const tgs_gaussian_grads& out, hipStream_t s);
+
 }  // namespace tgs

@@ -1,0 +1,148 @@
+// Per-pixel compositing step and entry staging shared by the forward
+// rasters and the backward raster (device code, included by raster.hip and
+// raster_bwd.hip only).
+#pragma once
+
+#include "common.hpp"
+
+namespace tgs {
+namespace raster {
+
+// One staged entry (see stage_splat) and its stream position.
+struct Staged {
+    float4 a;  // mx, my, a', 2b'
+    float4 b;  // c', opacity, r, g
+    float2 c;  // b, position bits
+};
+
+struct Pix {
+    float T, r, g, b;
+    int32_t last, ncon, nvis, nsup;
+    bool done;
+};
+
+// The per-pixel step shared by both kernels, without branches (explicit
+// operation order, no implicit contraction, so both produce identical bits):
+// skip when q < 0 (rounding only) or alpha < 1/255; stop, without
+// compositing, when T (1 - alpha) < 1e-4; otherwise C += alpha T c and
+// T *= 1 - alpha.
+template <bool COUNT>
+__device__ __forceinline__ void blend(Pix& p, float px, float py, const Staged& s) {
+#pragma clang fp contract(off)
+    const float dx = s.a.x - px;
+    const float dy = s.a.y - py;
+    const float w = fmaf(s.a.z, dx, s.a.w * dy);
+    const float q2 = fmaf(dx, w, (s.b.x * dy) * dy);  // = -q / (2 ln 2)
+    const float araw = s.b.y * __builtin_amdgcn_exp2f(q2);
+    const bool live = !p.done;
+    const bool sup = live && (q2 <= 0.0f) && (araw >= kAlphaMin);
+    const float alpha = fminf(kAlphaMax, araw);
+    const float test = p.T * (1.0f - alpha);
+    const bool comp = sup && (test >= kTMin);
+    if (COUNT) {
+        p.nvis += live ? 1 : 0;
+        p.nsup += sup ? 1 : 0;
+        p.ncon += comp ? 1 : 0;
+    }
+    p.done = p.done || (sup && !comp);
+    const float wt = comp ? alpha * p.T : 0.0f;
+    p.r = fmaf(wt, s.b.z, p.r);
+    p.g = fmaf(wt, s.b.w, p.g);
+    p.b = fmaf(wt, s.c.x, p.b);
+    p.T = comp ? test : p.T;
+    p.last = comp ? __float_as_int(s.c.y) : p.last;
+}
+
+enum Src { SRC_VALS = 0, SRC_PAIRS = 1, SRC_PACKED = 2 };
+
+template <int SRC>
+__device__ __forceinline__ uint32_t id_at(const RasterArgs& A, uint32_t p) {
+    if (SRC == SRC_VALS) return A.vals[p];
+    return (uint32_t)A.pairs[p];
+}
+
+// The staged entry at stream position p (packed records are already staged).
+template <int SRC>
+__device__ __forceinline__ Staged load_entry(const RasterArgs& A, uint32_t p, float ox, float oy) {
+    Staged s;
+    if (SRC == SRC_PACKED) {
+        const float4* r = reinterpret_cast<const float4*>(A.records) + kRecordVec * (int64_t)p;
+        s.a = r[0];
+        s.b = r[1];
+        s.c = make_float2(r[2].x, __int_as_float((int32_t)p));
+        return s;
+    }
+    const uint32_t g = id_at<SRC>(A, p);
+    const float4* q = reinterpret_cast<const float4*>(A.splats) + kSplatVec * (int64_t)g;
+    float s2;
+    stage_splat(q[0], q[1], q[2], ox, oy, s.a, s.b, s2);
+    s.c = make_float2(s2, __int_as_float((int32_t)p));
+    return s;
+}
+
+__device__ __forceinline__ int tile_of_block(const RasterArgs& A) {
+    const int T = A.tiles_x * A.tiles_y;
+    return A.order ? (int)A.order[blockIdx.x] : xcd_remap(blockIdx.x, T);
+}
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Composites the cnt staged survivors of st[], reading the next one from LDS
+// while the current one is evaluated.
+template <bool COUNT>
+__device__ __forceinline__ void composite_staged(Pix& p, float px, float py, const Staged* st, int cnt) {
+    if (cnt == 0) return;
+    Staged cur = st[0];
+    for (int j = 1; j < cnt; ++j) {
+        const Staged nxt = st[j];
+        blend<COUNT>(p, px, py, cur);
+        cur = nxt;
+    }
+    blend<COUNT>(p, px, py, cur);
+}
+
+
+// The forward walk of one 8x8 block over the tile range [begin, end) (the
+// WAVE raster's main loop): 64 entries at a time, kept when the block mask
+// (A.masks) or the conservative block test on the gathered splat says they
+// can reach alpha 1/255 in the block, compacted into the wavefront's LDS
+// slots st[] and composited by every lane.
+template <int SRC, bool COUNT>
+__device__ __forceinline__ void wave_forward(const RasterArgs& A, Staged* st, int w, uint32_t begin, uint32_t end,
+                                             float ox, float oy, float px, float py, float xa, float xb, float ya,
+                                             float yb, Pix& p) {
+    const int l = lane();
+    const uint32_t bit = 1u << w;
+    for (uint32_t base = begin; base < end; base += kWave) {
+        if (ballot(!p.done) == 0) break;
+        const uint32_t e = base + l;
+        bool keep = e < end;
+        Staged s;
+        if (A.masks) {
+            // the block mask decides; only survivors fetch their entry
+            if (keep) keep = (A.masks[e] & bit) != 0;
+            if (keep) s = load_entry<SRC>(A, e, ox, oy);
+        } else if (keep) {
+            const uint32_t g = id_at<SRC>(A, e);
+            const float4* q = reinterpret_cast<const float4*>(A.splats) + kSplatVec * (int64_t)g;
+            const float4 q0 = q[0], q1 = q[1], q2 = q[2];
+            float s2;
+            stage_splat(q0, q1, q2, ox, oy, s.a, s.b, s2);
+            s.c = make_float2(s2, __int_as_float((int32_t)e));
+            keep = block_may_touch(s.a.x, s.a.y, q1.x, q1.y, q1.z, q1.w, xa, xb, ya, yb);
+        }
+        const uint64_t m = ballot(keep);
+        if (m == 0) continue;
+        if (keep) st[rank_in(m)] = s;
+        wave_sync();
+        composite_staged<COUNT>(p, px, py, st, __builtin_popcountll(m));
+        wave_sync();
+    }
+}
+
+}  // namespace raster
+}  // namespace tgs

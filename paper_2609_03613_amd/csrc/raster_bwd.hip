@@ -1,0 +1,189 @@
+// Backward of the compositing: dL/d(splat) of every Gaussian from dL/d rgb
+// and dL/d alpha of the image. The paper has no backward pass (it lists
+// training as future work in its Conclusion); this is the derivative of the
+// per-pixel step the forward rasters evaluate, over the same entry stream.
+//
+// Each 64-lane wavefront owns one 8x8 pixel block, as in the forward WAVE
+// raster. Pass 1 repeats the forward walk (same staging, culling and blend,
+// so the final transmittance and the last composited position come out
+// bit-identical to the forward's). Pass 2 walks the range backwards from
+// the largest last position in the block, 64 entries at a time, with the
+// same block cull and LDS compaction; each lane recovers the transmittance
+// in front of an entry by dividing by the same binary32 (1 - alpha) the
+// forward multiplied by, and keeps the colour behind it,
+// S = T_final bg + sum over later entries of T alpha c. Per entry k:
+//   dL/dc_k     = g T_k alpha_k
+//   dL/dalpha_k = sum_ch g_ch (T_k c_ch - S_ch / (1 - alpha_k))
+//                 + g_alpha T_final / (1 - alpha_k)
+// and, when alpha is not capped at 0.99, through alpha = o exp2(q'):
+// dL/do = dL/dalpha exp2(q'), dL/dq' = dL/dalpha alpha ln 2, with q' the
+// scaled quadratic form of the staged conic. The 9 per-lane gradients of an
+// entry are summed over the wavefront (DPP within rows of 16, then two lane
+// swaps) and lanes 0..8 add the 9 sums to the Gaussian's gradient line with
+// one float atomic each.
+#include <math.h>
+
+#include "raster.hpp"
+
+namespace tgs {
+
+namespace {
+
+using namespace raster;
+
+// Sum over the 16 lanes of each row, result in every lane of the row.
+__device__ __forceinline__ float row_sum(float v) {
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));   // quad [1,0,3,2]
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));   // quad [2,3,0,1]
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, false));  // row half-mirror
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, false));  // row mirror
+    return v;
+}
+
+// Sum over the 64 lanes, result in every lane.
+__device__ __forceinline__ float wave_sum(float v) {
+    v = row_sum(v);
+    v += __shfl_xor(v, 16, kWave);
+    v += __shfl_xor(v, 32, kWave);
+    return v;
+}
+
+__device__ __forceinline__ int wave_max_i32(int v) {
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) v = max(v, __shfl_xor(v, d, kWave));
+    return v;
+}
+
+constexpr float kLn2 = 0.69314718055994531f;
+
+template <int SRC>
+__global__ void __launch_bounds__(256) raster_bwd_kernel(RasterArgs A, const float* __restrict__ d_rgb,
+                                                         const float* __restrict__ d_alpha,
+                                                         float* __restrict__ d_splats) {
+#pragma clang fp contract(off)
+    __shared__ Staged stage[4][kWave];
+    __shared__ uint32_t ids[4][kWave];
+    const int t = tile_of_block(A);
+    const int tx = t % A.tiles_x, ty = t / A.tiles_x;
+    const int w = threadIdx.x / kWave, l = lane();
+    float xa, xb, ya, yb;
+    if (!block_box(w, tx, ty, A.width, A.height, xa, xb, ya, yb)) return;  // block outside the image
+    if (A.counters[2] != 0) return;  // truncated stream: the forward image is NaN, no gradient
+    const int lx = (w & 1) * 8 + (l & 7), ly = (w >> 1) * 8 + (l >> 3);
+    const int x = tx * kTile + lx, y = ty * kTile + ly;
+    const bool inside = x < A.width && y < A.height;
+    const float ox = (float)(tx * kTile), oy = (float)(ty * kTile);
+    const float px = (float)lx + 0.5f, py = (float)ly + 0.5f;
+    const uint32_t begin = A.offsets[(int64_t)t * A.stride];
+    const uint32_t end = A.offsets[(int64_t)(t + 1) * A.stride];
+    Staged* st = stage[w];
+    uint32_t* idw = ids[w];
+
+    // pass 1: the forward walk
+    Pix p{1.0f, 0.f, 0.f, 0.f, -1, 0, 0, 0, !inside};
+    wave_forward<SRC, false>(A, st, w, begin, end, ox, oy, px, py, xa, xb, ya, yb, p);
+
+    // pass 2: backwards from the last composited entry
+    const int hi = wave_max_i32(p.last);
+    if (hi < 0) return;
+    float gr = 0.f, gg = 0.f, gb = 0.f, ga = 0.f;
+    if (inside) {
+        const int64_t i = (int64_t)y * A.width + x;
+        gr = d_rgb[3 * i];
+        gg = d_rgb[3 * i + 1];
+        gb = d_rgb[3 * i + 2];
+        ga = d_alpha ? d_alpha[i] : 0.f;
+    }
+    const float Tf = p.T;
+    const float gaT = ga * Tf;
+    float T = Tf;
+    float Sr = Tf * A.bg[0], Sg = Tf * A.bg[1], Sb = Tf * A.bg[2];
+    for (int64_t top = hi; top >= (int64_t)begin; top -= kWave) {
+        const int64_t e = top - l;
+        bool keep = e >= (int64_t)begin;
+        Staged s;
+        uint32_t gid = 0;
+        if (keep) {
+            gid = id_at<SRC>(A, (uint32_t)e);
+            const float4* q = reinterpret_cast<const float4*>(A.splats) + kSplatVec * (int64_t)gid;
+            const float4 q0 = q[0], q1 = q[1], q2 = q[2];
+            float s2;
+            stage_splat(q0, q1, q2, ox, oy, s.a, s.b, s2);
+            s.c = make_float2(s2, __int_as_float((int32_t)e));
+            keep = block_may_touch(s.a.x, s.a.y, q1.x, q1.y, q1.z, q1.w, xa, xb, ya, yb);
+        }
+        const uint64_t m = ballot(keep);
+        if (m == 0) continue;
+        if (keep) {
+            const uint32_t r = rank_in(m);
+            st[r] = s;
+            idw[r] = gid;
+        }
+        wave_sync();
+        const int cnt = __builtin_popcountll(m);
+        for (int j = 0; j < cnt; ++j) {
+            const Staged c = st[j];
+            const int pos = __float_as_int(c.c.y);
+            // the forward's per-pixel test, same operations
+            const float dx = c.a.x - px;
+            const float dy = c.a.y - py;
+            const float wq = fmaf(c.a.z, dx, c.a.w * dy);
+            const float q2 = fmaf(dx, wq, (c.b.x * dy) * dy);
+            const float G = __builtin_amdgcn_exp2f(q2);
+            const float araw = c.b.y * G;
+            const bool comp = pos <= p.last && q2 <= 0.0f && araw >= kAlphaMin;
+            if (ballot(comp) == 0) continue;
+            float d[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            if (comp) {
+                const float alpha = fminf(kAlphaMax, araw);
+                const float om = 1.0f - alpha;
+                T = T / om;
+                const float wt = alpha * T;
+                const float inv = 1.0f / om;
+                d[6] = gr * wt;
+                d[7] = gg * wt;
+                d[8] = gb * wt;
+                const float dLda = gaT * inv + gr * (T * c.b.z - Sr * inv) + gg * (T * c.b.w - Sg * inv) +
+                                   gb * (T * c.c.x - Sb * inv);
+                Sr = fmaf(wt, c.b.z, Sr);
+                Sg = fmaf(wt, c.b.w, Sg);
+                Sb = fmaf(wt, c.c.x, Sb);
+                if (araw <= kAlphaMax) {
+                    const float dq = dLda * araw * kLn2;  // dL/dq'
+                    // q' = a' dx^2 + 2b' dx dy + c' dy^2 with (a', 2b', c') =
+                    // kHalfLog2e (a, 2b, c); dx = mean_x - pixel_x
+                    d[0] = dq * (2.0f * c.a.z * dx + c.a.w * dy);
+                    d[1] = dq * (c.a.w * dx + 2.0f * c.b.x * dy);
+                    const float k = dq * kHalfLog2e;
+                    d[2] = k * dx * dx;
+                    d[3] = 2.0f * k * dx * dy;
+                    d[4] = k * dy * dy;
+                    d[5] = dLda * G;
+                }
+            }
+            float mine = 0.f;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                const float tot = wave_sum(d[k]);
+                mine = (l == k) ? tot : mine;
+            }
+            if (l < 9) unsafeAtomicAdd(d_splats + kGradWords * (int64_t)idw[j] + l, mine);
+        }
+        wave_sync();
+    }
+}
+
+}  // namespace
+
+hipError_t launch_raster_backward(const RasterArgs& a, const float* d_rgb, const float* d_alpha, float* d_splats,
+                                  hipStream_t s) {
+    const int T = a.tiles_x * a.tiles_y;
+    if (T == 0) return hipSuccess;
+    if (a.vals)
+        hipLaunchKernelGGL((raster_bwd_kernel<SRC_VALS>), dim3(T), dim3(256), 0, s, a, d_rgb, d_alpha, d_splats);
+    else
+        hipLaunchKernelGGL((raster_bwd_kernel<SRC_PAIRS>), dim3(T), dim3(256), 0, s, a, d_rgb, d_alpha, d_splats);
+    return hipGetLastError();
+}
+
+}  // namespace tgs

@@ -120,6 +120,51 @@ def test_rasterize_argument_errors():
     assert st == L.TGS_ERR_INVALID_ARG
 
 
+def test_backward_argument_errors():
+    # every case fails validation before anything could be launched
+    lib = L.lib()
+    c = cam()
+    p = tg.Params().c()
+    fake = ctypes.c_void_p(0x1000).value
+    pr = L.Projected(fake, fake, 10)
+    b = L.Binned(100, None, None, fake, fake, None, None, fake, fake, None)
+    bg = (ctypes.c_float * 3)(0, 0, 0)
+    rb = lib.tgs_rasterize_backward
+    st, msg = status_of(rb, ctypes.byref(pr), None, ctypes.byref(c), ctypes.byref(p), L.ORDER_BINNED, bg, fake, None,
+                        fake, None)
+    assert st == L.TGS_ERR_INVALID_ARG and "binned" in msg
+    st, msg = status_of(rb, ctypes.byref(pr), ctypes.byref(b), ctypes.byref(c), ctypes.byref(p), L.ORDER_BINNED, bg,
+                        None, None, fake, None)
+    assert st == L.TGS_ERR_INVALID_ARG and "d_rgb" in msg
+    st, msg = status_of(rb, ctypes.byref(pr), ctypes.byref(b), ctypes.byref(c), ctypes.byref(p), L.ORDER_BINNED, bg,
+                        fake, None, None, None)
+    assert st == L.TGS_ERR_INVALID_ARG and "d_splats" in msg
+    st, msg = status_of(rb, ctypes.byref(pr), ctypes.byref(b), ctypes.byref(c), ctypes.byref(p), 7, bg, fake, None,
+                        None, None)
+    assert st == L.TGS_ERR_INVALID_ARG and "order" in msg
+    b.pairs = None
+    st, msg = status_of(rb, ctypes.byref(pr), ctypes.byref(b), ctypes.byref(c), ctypes.byref(p), L.ORDER_BINNED, bg,
+                        fake, None, None, None)
+    assert st == L.TGS_ERR_INVALID_ARG
+    pb = lib.tgs_project_backward
+    gr = L.GaussianGrads(fake, fake, fake, fake, fake)
+    g = L.Gaussians(fake, fake, fake, fake, fake, 10, 4)
+    st, msg = status_of(pb, ctypes.byref(g), ctypes.byref(c), fake, ctypes.byref(gr), None)
+    assert st == L.TGS_ERR_INVALID_ARG and "sh_degree" in msg
+    g = L.Gaussians(fake, fake, fake, fake, fake, 10, 3)
+    st, msg = status_of(pb, ctypes.byref(g), ctypes.byref(c), None, ctypes.byref(gr), None)
+    assert st == L.TGS_ERR_INVALID_ARG and "gradient" in msg
+    st, msg = status_of(pb, ctypes.byref(g), ctypes.byref(c), fake, None, None)
+    assert st == L.TGS_ERR_INVALID_ARG and "grads" in msg
+    gr.sh = None
+    st, msg = status_of(pb, ctypes.byref(g), ctypes.byref(c), fake, ctypes.byref(gr), None)
+    assert st == L.TGS_ERR_INVALID_ARG
+    bad = cam(20000, 10)
+    gr.sh = fake
+    st, msg = status_of(pb, ctypes.byref(g), ctypes.byref(bad), fake, ctypes.byref(gr), None)
+    assert st == L.TGS_ERR_INVALID_ARG and "image size" in msg
+
+
 def test_error_type():
     with pytest.raises(tg.TileGSError):
         L.check(L.TGS_ERR_INVALID_ARG)

@@ -191,3 +191,21 @@ def test_invisible_gaussians_have_zero_gradient():
     for k in KEYS:
         assert not np.any(a[k][:8]), k
     assert np.abs(a["means"][8:]).max() > 0
+
+
+def test_composite_adjoint_on_records_matches_full_adjoint():
+    # the records-level entry (used with synthetic splats) on the projected
+    # records of a scene gives the same image and dL/d(projected)
+    g, cam = scenes.fd_subcase()
+    W, H = cam["width"], cam["height"]
+    target = scenes.training_target(W, H)
+    proj = oracle.project(g, cam)
+    full0 = oracle.adjoint(as64(g), cam, bg=(0.1, 0.2, 0.3))
+    _, up = oracle.mse_upstream(full0["rgb"], target)
+    w = np.random.default_rng(2).normal(0.0, 1e-4, size=(H, W))
+    full = oracle.adjoint(as64(g), cam, bg=(0.1, 0.2, 0.3), d_img=up, d_alpha=w)
+    rec = oracle.composite_adjoint(proj, W, H, bg=(0.1, 0.2, 0.3), d_img=up, d_alpha=w)
+    np.testing.assert_allclose(rec["rgb"], full["rgb"], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(rec["alpha"], full["alpha"], rtol=0, atol=1e-12)
+    scale = np.abs(full["d_proj"]).max(axis=0)
+    assert np.all(np.abs(rec["d_proj"] - full["d_proj"]) <= 1e-9 * scale + 1e-15)
