@@ -57,6 +57,7 @@ def lib():
         L.orc_bin_of.argtypes = [flt, flt, flt, i32]
         L.orc_schedule.argtypes = [i64, P, P, i32, i32, i32, i32, dbl, dbl, flt, flt, flt,
                                    P, P, P, P, P, P]
+        L.orc_schedule_tiles.argtypes = [i64, P, P, i32, i32, P, i32, dbl, dbl, flt, flt, flt, P, P, P, P]
         L.orc_adjoint.argtypes = [i64, P, P, P, P, P, i32, P, i32, P, P, P, P, P, P, P, P, P, P, P]
         L.orc_composite_adjoint.argtypes = [i64, P, P, P, P, P, P, P, i32, i32, i32, P, P, P, P, P, P]
         _lib = L
@@ -192,6 +193,26 @@ def schedule(depth, rect, tiles_x, tiles_y, K=64, S=8192, p_lo=1.0, p_hi=99.0, p
                             float(p_lo), float(p_hi), float(pad), float(znear), float(zfar),
                             _p(out["keys"]), _p(out["vals"]), _p(out["tile_offsets"]),
                             _p(out["zrange"]), _p(out["bin_offsets"]), _p(out["stream"]))
+    assert rc == 0, rc
+    out["M"] = M
+    return out
+
+
+def schedule_tiles(depth, rect, tiles_x, tiles_y, per_tile_bins, S=8192, p_lo=1.0, p_hi=99.0, pad=0.05,
+                   znear=0.01, zfar=1e10):
+    """Binned schedule with per_tile_bins[t] bins in tile t: zrange,
+    seg_base [T + 1], bin_offsets [sum + 1], stream [M]."""
+    depth = _c(depth, np.float32)
+    rect = _c(rect, np.int32)
+    kt = _c(per_tile_bins, np.int32)
+    T = tiles_x * tiles_y
+    assert kt.shape == (T,)
+    M = count_entries(rect)
+    out = {"zrange": np.zeros(2, np.float32), "seg_base": np.zeros(T + 1, np.uint32),
+           "bin_offsets": np.zeros(int(kt.astype(np.int64).sum()) + 1, np.uint32), "stream": np.zeros(M, np.uint64)}
+    rc = lib().orc_schedule_tiles(len(depth), _p(depth), _p(rect), int(tiles_x), int(tiles_y), _p(kt), int(S),
+                                  float(p_lo), float(p_hi), float(pad), float(znear), float(zfar), _p(out["zrange"]),
+                                  _p(out["seg_base"]), _p(out["bin_offsets"]), _p(out["stream"]))
     assert rc == 0, rc
     out["M"] = M
     return out

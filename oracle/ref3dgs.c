@@ -554,21 +554,30 @@ ORC_EXPORT int orc_bin_of(float z, float zmin, float zmax, int K) { return bin_o
  * The whole integer schedule for binary32 depths and tile rects.
  * keys/vals: the global list, sorted by (tile << 32 | depth bits, id).
  * tile_offsets[T+1]: each tile's range in it.
- * zrange[2]: the depth range; bin_offsets[T*K+1]: exclusive scan of the
- * (tile, bin) counts in tile-major, bin-minor order (supplement, Algorithm
- * "Tile-local bin construction").
+ * zrange[2]: the depth range.
+ * Bins: tile t has K_t = per_tile_bins[t] bins (per_tile_bins NULL: K in
+ * every tile); its segments are numbered from seg_base[t] = K_0 + ... +
+ * K_{t-1}, so segment seg_base[t] + b is bin b of tile t (tile-major,
+ * bin-minor; with a uniform K this is t K + b). bin_offsets[sum K_t + 1]:
+ * exclusive scan of the segment counts (supplement, Algorithm "Tile-local
+ * bin construction"); seg_base[T+1].
  * stream[M]: the tile-bin-major stream with every (tile, bin) segment sorted
  * by (depth bits << 32 | id), the exact-repair order.
  * Any output pointer may be NULL.
  */
-ORC_EXPORT int orc_schedule(int64_t n, const float* depth, const int32_t* rect, int tiles_x, int tiles_y,
-                            int K, int S, double p_lo, double p_hi, float pad, float znear, float zfar,
-                            uint64_t* keys, uint32_t* vals, uint32_t* tile_offsets, float* zrange,
-                            uint32_t* bin_offsets, uint64_t* stream) {
+static int schedule_impl(int64_t n, const float* depth, const int32_t* rect, int tiles_x, int tiles_y, int K,
+                         const int32_t* per_tile_bins, int S, double p_lo, double p_hi, float pad, float znear,
+                         float zfar, uint64_t* keys, uint32_t* vals, uint32_t* tile_offsets, float* zrange,
+                         uint32_t* seg_base_out, uint32_t* bin_offsets, uint64_t* stream) {
     const int64_t T = (int64_t)tiles_x * tiles_y;
     const int64_t M = orc_count_entries(n, rect);
     kv_t* e = (kv_t*)malloc((size_t)(M > 0 ? M : 1) * sizeof(kv_t));
-    if (!e) return 2;
+    int64_t* sb = (int64_t*)malloc(((size_t)T + 1) * sizeof(int64_t));
+    if (!e || !sb) { free(e); free(sb); return 2; }
+    sb[0] = 0;
+    for (int64_t t = 0; t < T; ++t) sb[t + 1] = sb[t] + (per_tile_bins ? per_tile_bins[t] : K);
+    if (seg_base_out)
+        for (int64_t t = 0; t <= T; ++t) seg_base_out[t] = (uint32_t)sb[t];
     int64_t m = 0;
     for (int64_t g = 0; g < n; ++g)
         for (int y = rect[4 * g + 1]; y < rect[4 * g + 3]; ++y)
@@ -592,40 +601,62 @@ ORC_EXPORT int orc_schedule(int64_t n, const float* depth, const int32_t* rect, 
     }
     float zr[2];
     int rc = orc_depth_range(n, depth, rect, S, p_lo, p_hi, pad, znear, zfar, zr);
-    if (rc) { free(e); return rc; }
+    if (rc) { free(e); free(sb); return rc; }
     if (zrange) { zrange[0] = zr[0]; zrange[1] = zr[1]; }
     if (bin_offsets || stream) {
-        const int64_t NS = T * K;
+        const int64_t NS = sb[T];
         uint32_t* cnt = (uint32_t*)calloc((size_t)NS + 1, sizeof(uint32_t));
         uint32_t* off = (uint32_t*)malloc(((size_t)NS + 1) * sizeof(uint32_t));
         uint32_t* cur = (uint32_t*)malloc(((size_t)NS + 1) * sizeof(uint32_t));
         uint64_t* st = (uint64_t*)malloc((size_t)(M > 0 ? M : 1) * sizeof(uint64_t));
-        if (!cnt || !off || !cur || !st) { free(cnt); free(off); free(cur); free(st); free(e); return 2; }
+        if (!cnt || !off || !cur || !st) { free(cnt); free(off); free(cur); free(st); free(e); free(sb); return 2; }
         /* count in emission order (the order is irrelevant for counts) */
-        for (int64_t g = 0; g < n; ++g) {
-            int b = bin_of(depth[g], zr[0], zr[1], K);
-            for (int y = rect[4 * g + 1]; y < rect[4 * g + 3]; ++y)
-                for (int x = rect[4 * g]; x < rect[4 * g + 2]; ++x) cnt[((int64_t)y * tiles_x + x) * K + b]++;
-        }
-        off[0] = 0;
-        for (int64_t s = 0; s < NS; ++s) off[s + 1] = off[s] + cnt[s];
-        memcpy(cur, off, ((size_t)NS + 1) * sizeof(uint32_t));
-        for (int64_t g = 0; g < n; ++g) {
-            int b = bin_of(depth[g], zr[0], zr[1], K);
+        for (int64_t g = 0; g < n; ++g)
             for (int y = rect[4 * g + 1]; y < rect[4 * g + 3]; ++y)
                 for (int x = rect[4 * g]; x < rect[4 * g + 2]; ++x) {
-                    int64_t s = ((int64_t)y * tiles_x + x) * K + b;
-                    st[cur[s]++] = ((uint64_t)f32_bits(depth[g]) << 32) | (uint64_t)g;
+                    const int64_t t = (int64_t)y * tiles_x + x;
+                    cnt[sb[t] + bin_of(depth[g], zr[0], zr[1], (int)(sb[t + 1] - sb[t]))]++;
                 }
-        }
-        for (int64_t s = 0; s < NS; ++s)
-            qsort(st + off[s], (size_t)(off[s + 1] - off[s]), sizeof(uint64_t), u64_cmp);
+        off[0] = 0;
+        for (int64_t s2 = 0; s2 < NS; ++s2) off[s2 + 1] = off[s2] + cnt[s2];
+        memcpy(cur, off, ((size_t)NS + 1) * sizeof(uint32_t));
+        for (int64_t g = 0; g < n; ++g)
+            for (int y = rect[4 * g + 1]; y < rect[4 * g + 3]; ++y)
+                for (int x = rect[4 * g]; x < rect[4 * g + 2]; ++x) {
+                    const int64_t t = (int64_t)y * tiles_x + x;
+                    const int64_t s2 = sb[t] + bin_of(depth[g], zr[0], zr[1], (int)(sb[t + 1] - sb[t]));
+                    st[cur[s2]++] = ((uint64_t)f32_bits(depth[g]) << 32) | (uint64_t)g;
+                }
+        for (int64_t s2 = 0; s2 < NS; ++s2)
+            qsort(st + off[s2], (size_t)(off[s2 + 1] - off[s2]), sizeof(uint64_t), u64_cmp);
         if (bin_offsets) memcpy(bin_offsets, off, ((size_t)NS + 1) * sizeof(uint32_t));
         if (stream) memcpy(stream, st, (size_t)M * sizeof(uint64_t));
         free(cnt); free(off); free(cur); free(st);
     }
     free(e);
+    free(sb);
     return 0;
+}
+
+/* The schedule with K bins in every tile (bin_offsets[T*K+1]). */
+ORC_EXPORT int orc_schedule(int64_t n, const float* depth, const int32_t* rect, int tiles_x, int tiles_y,
+                            int K, int S, double p_lo, double p_hi, float pad, float znear, float zfar,
+                            uint64_t* keys, uint32_t* vals, uint32_t* tile_offsets, float* zrange,
+                            uint32_t* bin_offsets, uint64_t* stream) {
+    return schedule_impl(n, depth, rect, tiles_x, tiles_y, K, NULL, S, p_lo, p_hi, pad, znear, zfar, keys, vals,
+                         tile_offsets, zrange, NULL, bin_offsets, stream);
+}
+
+/* The schedule with per_tile_bins[t] bins in tile t (each >= 1). */
+ORC_EXPORT int orc_schedule_tiles(int64_t n, const float* depth, const int32_t* rect, int tiles_x, int tiles_y,
+                                  const int32_t* per_tile_bins, int S, double p_lo, double p_hi, float pad,
+                                  float znear, float zfar, float* zrange, uint32_t* seg_base,
+                                  uint32_t* bin_offsets, uint64_t* stream) {
+    const int64_t T = (int64_t)tiles_x * tiles_y;
+    for (int64_t t = 0; t < T; ++t)
+        if (per_tile_bins[t] < 1) return 1;
+    return schedule_impl(n, depth, rect, tiles_x, tiles_y, 0, per_tile_bins, S, p_lo, p_hi, pad, znear, zfar, NULL,
+                         NULL, NULL, zrange, seg_base, bin_offsets, stream);
 }
 
 /* ------------------------------------------------------------------------ */

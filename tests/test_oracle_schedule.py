@@ -167,3 +167,46 @@ def test_empty_schedule():
     assert s["M"] == 0
     assert s["bin_offsets"].tolist() == [0] * 25
     assert s["tile_offsets"].tolist() == [0] * 7
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_per_tile_bins_brute_force(seed):
+    # tile t has K_t bins numbered from seg_base[t] = K_0 + ... + K_{t-1};
+    # counts, offsets and sorted segments written out by hand
+    tx, ty = 5, 4
+    depth, rect = tiny_case(seed, n=80, tx=tx, ty=ty)
+    rng = np.random.default_rng(seed + 10)
+    kt = (2 ** rng.integers(0, 7, size=tx * ty)).astype(np.int32)
+    s = oracle.schedule_tiles(depth, rect, tx, ty, kt)
+    zmin, zmax = s["zrange"]
+    base = np.concatenate([[0], np.cumsum(kt)])
+    np.testing.assert_array_equal(s["seg_base"], base)
+    cnt = np.zeros(base[-1], np.int64)
+    segs = {}
+    for g in range(len(depth)):
+        for y in range(rect[g, 1], rect[g, 3]):
+            for x in range(rect[g, 0], rect[g, 2]):
+                t = y * tx + x
+                q = base[t] + oracle.bin_of(depth[g], zmin, zmax, int(kt[t]))
+                cnt[q] += 1
+                segs.setdefault(q, []).append((bits(float(depth[g])), g))
+    off = np.concatenate([[0], np.cumsum(cnt)])
+    np.testing.assert_array_equal(s["bin_offsets"], off)
+    for q, items in segs.items():
+        assert s["stream"][off[q]:off[q + 1]].tolist() == [(d << 32) | g for d, g in sorted(items)]
+
+
+def test_per_tile_bins_special_cases():
+    g, cam = scenes.small_forward(seed=2, n=1500)
+    p = oracle.project(g, cam)
+    uni = oracle.schedule(p["depth_key"], p["rect"], 8, 8, K=16)
+    # the same K in every tile is the uniform schedule
+    same = oracle.schedule_tiles(p["depth_key"], p["rect"], 8, 8, np.full(64, 16, np.int32))
+    np.testing.assert_array_equal(same["bin_offsets"], uni["bin_offsets"])
+    np.testing.assert_array_equal(same["stream"], uni["stream"])
+    # any per-tile choice keeps the stream equal to the global list (bins are
+    # monotone in depth) and each tile's range unchanged
+    kt = (2 ** np.random.default_rng(4).integers(0, 9, size=64)).astype(np.int32)
+    var = oracle.schedule_tiles(p["depth_key"], p["rect"], 8, 8, kt)
+    np.testing.assert_array_equal(var["stream"], uni["stream"])
+    np.testing.assert_array_equal(var["bin_offsets"][var["seg_base"]], uni["tile_offsets"])
