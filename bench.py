@@ -64,9 +64,11 @@ def parse():
     ap.add_argument("--config", default="1080p", choices=["1080p", "small"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--mode", default="frame", choices=["frame", "kernels"],
+    ap.add_argument("--mode", default="frame", choices=["frame", "kernels", "train"],
                     help="kernels: only launch the product and comparator raster kernels and a "
-                         "256 MiB device copy (for profiler counter runs)")
+                         "256 MiB device copy (for profiler counter runs); train: only the training "
+                         "step (forward + backward) on the 500k-Gaussian 1297x840 scene")
+    ap.add_argument("--no-train", action="store_true", help="skip the training-step measurement")
     return ap.parse_args()
 
 
@@ -98,6 +100,68 @@ def kernels_only(args):
     torch.cuda.synchronize()
     print(json.dumps({"mode": "kernels", "entries": bb.num_entries, "steps": args.steps,
                       "copy_bytes": src.numel() * 4}), flush=True)
+
+
+def train_step(args):
+    """Forward + backward on the training scene (500k Gaussians of the
+    small-forward structure, SH degree 3, 1297x840), binned order, inputs
+    resident: project, bin, raster, the loss gradient of mean((rgb -
+    target)^2), raster backward, projection backward. Returns per-stage
+    median ms (HIP events on the launch stream) and the whole-step rate."""
+    import torch
+    import paper_2609_03613_amd as tg
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    g, cam = scenes.training_scene(seed=0)
+    gd = tg.to_device(g, dev)
+    target = torch.as_tensor(scenes.training_target(cam["width"], cam["height"])).to(dev)
+    r = tg.Renderer(cam, tg.Params(raster="wave", packed=0), device=dev)
+    splats, info = tg.project(gd, cam)
+    b = r.bin(splats, info, "binned", sync=True)
+    M = b.num_entries
+    H, W = cam["height"], cam["width"]
+    out = {"rgb": torch.empty((H, W, 3), dtype=torch.float32, device=dev),
+           "alpha": torch.empty((H, W), dtype=torch.float32, device=dev),
+           "last": torch.empty((H, W), dtype=torch.int32, device=dev)}
+    n = int(g["means"].shape[0])
+    d_splats = torch.empty((n, 12), dtype=torch.float32, device=dev)
+    d_rgb = torch.empty((H, W, 3), dtype=torch.float32, device=dev)
+    scale = 2.0 / (3 * W * H)
+
+    def step(evs=None):
+        if evs: evs[0].record(stream)
+        s, i = tg.project(gd, cam)
+        if evs: evs[1].record(stream)
+        bb = r.bin(s, i, "binned", sync=False)
+        if evs: evs[2].record(stream)
+        o = r.rasterize(s, i, bb, out=out)
+        if evs: evs[3].record(stream)
+        torch.sub(o["rgb"], target, out=d_rgb)
+        d_rgb.mul_(scale)
+        if evs: evs[4].record(stream)
+        r.rasterize_backward(s, i, bb, d_rgb, None, out=d_splats)
+        if evs: evs[5].record(stream)
+        grads = tg.project_backward(gd, cam, d_splats)
+        if evs: evs[6].record(stream)
+        return grads
+
+    for _ in range(args.warmup):
+        step()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(7)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    names = ["project", "bin+repair", "raster", "loss grad", "raster backward", "project backward"]
+    st = np.array([[evs[k][j].elapsed_time(evs[k][j + 1]) for j in range(6)] for k in range(args.steps)])
+    med = dict(zip(names, np.median(st, 0).tolist()))
+    return {"workload": "training scene: 500k Gaussians, SH3, 1297x840, f=1297, binned order",
+            "gaussians": n, "entries": M, "ms_per_step": 1000.0 * wall / args.steps,
+            "steps_per_s": args.steps / wall, "stage_ms_median": med,
+            "backward_ms": med["raster backward"] + med["project backward"],
+            "forward_ms": med["project"] + med["bin+repair"] + med["raster"]}
 
 
 def workload(name):
@@ -138,6 +202,9 @@ def main():
         sys.exit(2)
     if args.mode == "kernels":
         return kernels_only(args)
+    if args.mode == "train":
+        print(json.dumps({"mode": "train", **train_step(args)}), flush=True)
+        return
     import torch
     import paper_2609_03613_amd as tg
 
@@ -303,6 +370,8 @@ def main():
                      "kernel": "raster_wave_kernel (binned, gather by id, per-block cull)",
                      "work": f"{n_support} alpha-supported pixel tests x {OPS_PER_TEST} lane-op slots"},
     }
+    if not args.no_train:
+        result["training_step"] = train_step(args)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(g, cam, args.cpu_seconds)
     print(json.dumps(result), flush=True)

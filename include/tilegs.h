@@ -116,8 +116,10 @@ typedef struct {
 
 /* Ordering and raster options (tgs_default_params fills the paper's values). */
 typedef struct {
-    int32_t tile_size;    /* 16 */
-    int32_t num_bins;     /* K, 64 */
+    int32_t tile_size;    /* tile edge in pixels: 16; 8 and 32 with the WAVE
+                             raster and packed = 0 */
+    int32_t num_bins;     /* K, 64 (with per_tile_bins_dev: the upper bound of
+                             the per-tile counts, a power of two) */
     int32_t sample_count; /* depth-range samples, 8192 */
     float p_lo, p_hi;     /* depth-range percentiles, 1 and 99 */
     float pad;            /* depth-range padding fraction, 0.05 */
@@ -129,6 +131,14 @@ typedef struct {
                              records of the entries its block's mask keeps;
                              2: block masks only, the raster gathers the kept
                              entries by id */
+    const int32_t* per_tile_bins_dev; /* NULL: num_bins bins in every tile.
+                             Otherwise (BINNED, packed = 0) device int32 [T]:
+                             the bin count of each tile, clamped to
+                             1..num_bins and rounded down to a power of two;
+                             tile t's segments are numbered from seg_base[t],
+                             the prefix sum of the counts. The bin map of a
+                             tile with K_t bins is the paper's log-depth map
+                             with K_t in place of K; images are unchanged. */
 } tgs_params;
 
 /* Entry buffers written by tgs_bin and read by tgs_rasterize. All device
@@ -147,7 +157,11 @@ typedef struct {
    tile_order [T] (optional, NULL = none): tgs_bin writes the tiles in
        descending order of their entry count (grouped by the bit length of
        the count) and the WAVE raster dispatches tiles in that order, so the
-       longest tiles start first. */
+       longest tiles start first.
+   seg_base [T + 1] (required with params.per_tile_bins_dev, else unused):
+       tgs_bin writes the first segment of each tile, seg_base[T] = the
+       number of segments S; offsets then holds S + 1 meaningful words (size
+       it for T * num_bins + 1). */
 typedef struct {
     int64_t capacity;
     uint64_t* keys_dev;
@@ -159,6 +173,7 @@ typedef struct {
     float* zrange_dev;
     int64_t* counters_dev;
     uint32_t* tile_order_dev;
+    uint32_t* seg_base_dev;
 } tgs_binned;
 
 /* Fills the paper's defaults (16 px tiles, K = 64, S = 8192, 1st / 99th

@@ -42,13 +42,13 @@ class Projected(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [("tile_size", ctypes.c_int32), ("num_bins", ctypes.c_int32), ("sample_count", ctypes.c_int32),
                 ("p_lo", ctypes.c_float), ("p_hi", ctypes.c_float), ("pad", ctypes.c_float),
-                ("raster", ctypes.c_int32), ("packed", ctypes.c_int32)]
+                ("raster", ctypes.c_int32), ("packed", ctypes.c_int32), ("per_tile_bins", _c_p)]
 
 
 class Binned(ctypes.Structure):
     _fields_ = [("capacity", ctypes.c_int64), ("keys", _c_p), ("vals", _c_p), ("pairs", _c_p),
                 ("offsets", _c_p), ("records", _c_p), ("masks", _c_p), ("zrange", _c_p), ("counters", _c_p),
-                ("tile_order", _c_p)]
+                ("tile_order", _c_p), ("seg_base", _c_p)]
 
 
 class GaussianGrads(ctypes.Structure):

@@ -36,10 +36,11 @@ class Params:
     raster: str = "wave"
     packed: int = 0          # 0: gather + cull in the raster, 1: records + masks, 2: masks only
     tile_order: bool = True
+    per_tile_bins: object = None  # None, or a device int32 tensor [T]: bins per tile (num_bins = bound)
 
     def c(self):
         return L.Params(self.tile_size, self.num_bins, self.sample_count, self.p_lo, self.p_hi, self.pad,
-                        RASTERS[self.raster], int(self.packed))
+                        RASTERS[self.raster], int(self.packed), _ptr(self.per_tile_bins).value)
 
 
 def camera_struct(cam):
@@ -87,7 +88,7 @@ def project(g, cam, params=None):
 class Binned:
     """Device buffers of one entry stream (see tgs_binned)."""
 
-    def __init__(self, order, capacity, tiles, num_bins, packed, device, tile_order=True):
+    def __init__(self, order, capacity, tiles, num_bins, packed, device, tile_order=True, per_tile=False):
         self.order = ORDERS[order] if isinstance(order, str) else order
         self.capacity = int(capacity)
         cap = max(self.capacity, 1)
@@ -107,13 +108,14 @@ class Binned:
             if packed == 1:
                 self.records = torch.empty((cap, 12), dtype=torch.float32, **kw)
         self.tile_order = torch.empty(max(tiles, 1), dtype=torch.int32, **kw) if tile_order else None
+        self.seg_base = torch.empty(tiles + 1, dtype=torch.int32, **kw) if per_tile else None
         self.num_entries = None
 
     def c(self):
         return L.Binned(self.capacity, _ptr(self.keys).value, _ptr(self.vals).value, _ptr(self.pairs).value,
                         _ptr(self.offsets).value, _ptr(self.records).value, _ptr(self.masks).value,
                         _ptr(self.zrange).value,
-                        _ptr(self.counters).value, _ptr(self.tile_order).value)
+                        _ptr(self.counters).value, _ptr(self.tile_order).value, _ptr(self.seg_base).value)
 
 
 class Renderer:
@@ -125,11 +127,22 @@ class Renderer:
         self.ccam = camera_struct(cam)
         self.cparams = self.params.c()
         self.device = device
-        self.tiles_x = (int(cam["width"]) + 15) // 16
-        self.tiles_y = (int(cam["height"]) + 15) // 16
+        ts = int(self.params.tile_size)
+        self.tiles_x = (int(cam["width"]) + ts - 1) // ts
+        self.tiles_y = (int(cam["height"]) + ts - 1) // ts
         self.tiles = self.tiles_x * self.tiles_y
         self._binned = {}
         self._ws = {}
+
+    def set_per_tile_bins(self, kt):
+        """Per-tile bin counts for the next tgs_bin calls (device int32 [T],
+        or None for params.num_bins everywhere)."""
+        self.params.per_tile_bins = kt
+        self.cparams = self.params.c()
+
+    def _new_binned(self, o, capacity):
+        return Binned(o, capacity, self.tiles, self.params.num_bins, self.params.packed, self.device,
+                      self.params.tile_order, per_tile=self.params.per_tile_bins is not None)
 
     def _workspace(self, order, n, capacity):
         need = L.lib().tgs_bin_workspace_size(n, capacity, ctypes.byref(self.ccam), ctypes.byref(self.cparams),
@@ -152,9 +165,11 @@ class Renderer:
         if fresh and b is not None:
             capacity = max(capacity or 0, b.capacity)
             b = None
+        if b is not None and (b.seg_base is None) != (self.params.per_tile_bins is None):
+            capacity = max(capacity or 0, b.capacity)
+            b = None
         if b is None or (capacity is not None and b.capacity < capacity):
-            b = Binned(o, capacity if capacity is not None else max(1024, 4 * n), self.tiles,
-                       self.params.num_bins, self.params.packed, self.device, self.params.tile_order)
+            b = self._new_binned(o, capacity if capacity is not None else max(1024, 4 * n))
             self._binned[o] = b
         for _ in range(2):
             ws = self._workspace(o, n, b.capacity)
@@ -163,8 +178,7 @@ class Renderer:
                                  _ptr(ws), ws.numel(), ctypes.byref(b.c()),
                                  ctypes.byref(m) if sync else None, _stream())
             if st == L.TGS_ERR_CAPACITY:
-                b = Binned(o, int(m.value * 1.1) + 1024, self.tiles, self.params.num_bins, self.params.packed,
-                           self.device, self.params.tile_order)
+                b = self._new_binned(o, int(m.value * 1.1) + 1024)
                 self._binned[o] = b
                 continue
             L.check(st)

@@ -193,7 +193,32 @@ struct WaveGauss {
 // wavefront's exclusive entry counts. Entries of consecutive Gaussians are
 // consecutive in the global entry order, so entry e = emit_off[first] + k.
 // f(gid, tile_x, tile_y, e, depth_bits, bin) is called once per entry.
-template <bool WITH_BIN, class F>
+// Position of depth bits L in the depth range as a 32-bit fraction,
+// floor(2^32 (L - Lmin) / (Lmax - Lmin)), clamped to [0, 2^32 - 1]. For K =
+// 2^k bins, frac >> (32 - k) equals bin_of(L, Lmin, Lmax, K) exactly (floor
+// of a floor divided by an integer), which lets each tile pick its own
+// power-of-two bin count from one per-Gaussian value.
+__device__ __forceinline__ uint32_t depth_frac(uint32_t L, uint32_t Lmin, uint32_t Lmax) {
+    if (Lmax <= Lmin || L <= Lmin) return 0u;
+    if (L >= Lmax) return 0xFFFFFFFFu;
+    return (uint32_t)(((uint64_t)(L - Lmin) << 32) / (uint64_t)(Lmax - Lmin));
+}
+
+// Bin of a depth fraction in a tile with kt = 2^k bins.
+__device__ __forceinline__ uint32_t bin_of_frac(uint32_t frac, uint32_t kt) {
+    return kt <= 1u ? 0u : frac >> (32 - __builtin_ctz(kt));
+}
+
+// Segment of an entry of tile t whose Gaussian has bin value bv (the bin
+// for uniform K, the depth fraction for per-tile bin counts).
+template <bool VAR>
+__device__ __forceinline__ int64_t segment_of(const SegMap& sm, int64_t t, uint32_t bv) {
+    if (!VAR) return t * sm.K + bv;
+    const uint32_t s0 = sm.seg_base[t], s1 = sm.seg_base[t + 1];
+    return (int64_t)s0 + bin_of_frac(bv, s1 - s0);
+}
+
+template <bool WITH_BIN, bool VAR, class F>
 __device__ __forceinline__ void for_wave_entries(const uint4* __restrict__ info, int64_t n,
                                                  const uint32_t* __restrict__ emit_off, int tiles_x, int tiles_y,
                                                  const float* __restrict__ zrange, int K, WaveGauss* W, F&& f) {
@@ -215,7 +240,10 @@ __device__ __forceinline__ void for_wave_entries(const uint4* __restrict__ info,
     W->rect[l] = (uint32_t)x0 | ((uint32_t)y0 << 16);
     W->width[l] = (uint32_t)(x1 - x0);
     W->key[l] = key;
-    if (WITH_BIN) W->bin[l] = cnt ? (uint32_t)bin_of(key, __float_as_uint(zrange[0]), __float_as_uint(zrange[1]), K) : 0u;
+    if (WITH_BIN) {
+        const uint32_t Lmin = __float_as_uint(zrange[0]), Lmax = __float_as_uint(zrange[1]);
+        W->bin[l] = !cnt ? 0u : VAR ? depth_frac(key, Lmin, Lmax) : (uint32_t)bin_of(key, Lmin, Lmax, K);
+    }
     const int64_t ebase = emit_off[g0];
     wave_sync();
     for (uint32_t base = 0; base < total; base += kWave) {
@@ -236,46 +264,51 @@ __device__ __forceinline__ void for_wave_entries(const uint4* __restrict__ info,
 // All atomics on copy x come from XCD x, so they are carried out in that
 // XCD's L2 (workgroup scope) instead of at the memory side; the returned old
 // value is the entry's rank inside its copy.
+template <bool VAR>
 __global__ void __launch_bounds__(256) bin_count_kernel(const uint4* __restrict__ info, int64_t n,
                                                         const uint32_t* __restrict__ emit_off,
-                                                        const float* __restrict__ zrange, int K, int tiles_x,
+                                                        const float* __restrict__ zrange, SegMap sm, int tiles_x,
                                                         int tiles_y, uint32_t* __restrict__ count, int64_t nseg,
                                                         uint32_t* __restrict__ entry_rank, int64_t capacity) {
     __shared__ WaveGauss wg[4];
     const uint32_t x = (uint32_t)xcc_id();
-    uint32_t* cnt = count + (int64_t)x * nseg;
-    for_wave_entries<true>(info, n, emit_off, tiles_x, tiles_y, zrange, K, &wg[threadIdx.x / kWave],
-                           [&](int64_t, int tx, int ty, int64_t e, uint32_t, uint32_t b) {
-                               const uint32_t r = __hip_atomic_fetch_add(&cnt[(int64_t)(ty * tiles_x + tx) * K + b], 1u,
-                                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                               if (e < capacity) entry_rank[e] = (r & 0x1FFFFFFFu) | (x << 29);
-                           });
+    const int64_t S = VAR ? (int64_t)sm.seg_base[(int64_t)tiles_x * tiles_y] : nseg;
+    uint32_t* cnt = count + (int64_t)x * S;
+    for_wave_entries<true, VAR>(info, n, emit_off, tiles_x, tiles_y, zrange, sm.K, &wg[threadIdx.x / kWave],
+                                [&](int64_t, int tx, int ty, int64_t e, uint32_t, uint32_t b) {
+                                    const int64_t sg = segment_of<VAR>(sm, (int64_t)ty * tiles_x + tx, b);
+                                    const uint32_t r = __hip_atomic_fetch_add(&cnt[sg], 1u, __ATOMIC_RELAXED,
+                                                                              __HIP_MEMORY_SCOPE_WORKGROUP);
+                                    if (e < capacity) entry_rank[e] = (r & 0x1FFFFFFFu) | (x << 29);
+                                });
 }
 
 // pair = depth bits << 32 | id at base[copy][segment] + rank. An entry that
 // is alone in its segment is final here, so its packed record is written
 // too; longer segments get theirs from the repair sorts.
+template <bool VAR>
 __global__ void __launch_bounds__(256) bin_scatter_kernel(const uint4* __restrict__ info, int64_t n,
                                                           const uint32_t* __restrict__ emit_off,
-                                                          const float* __restrict__ zrange, int K, int tiles_x,
+                                                          const float* __restrict__ zrange, SegMap sm, int tiles_x,
                                                           int tiles_y, const uint32_t* __restrict__ bin_off,
                                                           const uint32_t* __restrict__ base, int64_t nseg,
                                                           const uint32_t* __restrict__ entry_rank,
                                                           uint64_t* __restrict__ pairs, int64_t capacity,
                                                           RecordSink rs) {
     __shared__ WaveGauss wg[4];
-    for_wave_entries<true>(info, n, emit_off, tiles_x, tiles_y, zrange, K, &wg[threadIdx.x / kWave],
-                           [&](int64_t gid, int tx, int ty, int64_t e, uint32_t key, uint32_t b) {
-                               if (e >= capacity) return;
-                               const uint32_t rk = entry_rank[e];
-                               const int64_t sg = (int64_t)(ty * tiles_x + tx) * K + b;
-                               const int64_t p = (int64_t)base[(int64_t)(rk >> 29) * nseg + sg] + (rk & 0x1FFFFFFFu);
-                               if (p >= capacity) return;
-                               const uint64_t pair = ((uint64_t)key << 32) | (uint64_t)gid;
-                               pairs[p] = pair;
-                               if (rs.masks && bin_off[sg + 1] - bin_off[sg] == 1)
-                                   rs.put((uint32_t)sg, (uint32_t)p, pair);
-                           });
+    const int64_t S = VAR ? (int64_t)sm.seg_base[(int64_t)tiles_x * tiles_y] : nseg;
+    for_wave_entries<true, VAR>(info, n, emit_off, tiles_x, tiles_y, zrange, sm.K, &wg[threadIdx.x / kWave],
+                                [&](int64_t gid, int tx, int ty, int64_t e, uint32_t key, uint32_t b) {
+                                    if (e >= capacity) return;
+                                    const uint32_t rk = entry_rank[e];
+                                    const int64_t sg = segment_of<VAR>(sm, (int64_t)ty * tiles_x + tx, b);
+                                    const int64_t p = (int64_t)base[(int64_t)(rk >> 29) * S + sg] + (rk & 0x1FFFFFFFu);
+                                    if (p >= capacity) return;
+                                    const uint64_t pair = ((uint64_t)key << 32) | (uint64_t)gid;
+                                    pairs[p] = pair;
+                                    if (rs.masks && bin_off[sg + 1] - bin_off[sg] == 1)
+                                        rs.put((uint32_t)sg, (uint32_t)p, pair);
+                                });
 }
 
 // ---------------------------------------------------------------------------
@@ -492,23 +525,23 @@ __device__ __forceinline__ uint32_t wave_aggregated_add(uint32_t* ctr, int b, bo
 // then one global atomic per bucket and workgroup), (2) placement: every
 // workgroup scans the global histogram and reserves its slots per bucket
 // with one global atomic per bucket. Order inside a bucket is arbitrary.
-__device__ __forceinline__ uint32_t tile_count(const uint32_t* offsets, int stride, int64_t t) {
-    return offsets[(t + 1) * stride] - offsets[t * stride];
+__device__ __forceinline__ uint32_t tile_count(const uint32_t* offsets, const SegMap& sm, int64_t t) {
+    return offsets[sm.first(t + 1)] - offsets[sm.first(t)];
 }
 
-__global__ void __launch_bounds__(256) tile_hist_kernel(const uint32_t* __restrict__ offsets, int stride, int64_t T,
+__global__ void __launch_bounds__(256) tile_hist_kernel(const uint32_t* __restrict__ offsets, SegMap sm, int64_t T,
                                                         uint32_t* __restrict__ hist) {
     __shared__ uint32_t h[kOrderBuckets];
     if (threadIdx.x < kOrderBuckets) h[threadIdx.x] = 0;
     __syncthreads();
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool act = t < T;
-    (void)wave_aggregated_add(h, act ? order_bucket(tile_count(offsets, stride, t)) : 0, act);
+    (void)wave_aggregated_add(h, act ? order_bucket(tile_count(offsets, sm, t)) : 0, act);
     __syncthreads();
     if (threadIdx.x < kOrderBuckets && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
 }
 
-__global__ void __launch_bounds__(256) tile_place_kernel(const uint32_t* __restrict__ offsets, int stride, int64_t T,
+__global__ void __launch_bounds__(256) tile_place_kernel(const uint32_t* __restrict__ offsets, SegMap sm, int64_t T,
                                                          const uint32_t* __restrict__ hist, uint32_t* __restrict__ cursor,
                                                          uint32_t* __restrict__ order) {
     __shared__ uint32_t h[kOrderBuckets], base[kOrderBuckets];
@@ -516,7 +549,7 @@ __global__ void __launch_bounds__(256) tile_place_kernel(const uint32_t* __restr
     __syncthreads();
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool act = t < T;
-    const int b = act ? order_bucket(tile_count(offsets, stride, t)) : 0;
+    const int b = act ? order_bucket(tile_count(offsets, sm, t)) : 0;
     const uint32_t slot = wave_aggregated_add(h, b, act);
     __syncthreads();
     if (threadIdx.x < kOrderBuckets) {
@@ -537,7 +570,7 @@ __global__ void __launch_bounds__(256) emit_keys_kernel(const uint4* __restrict_
                                                         int tiles_y, uint64_t* __restrict__ keys,
                                                         uint32_t* __restrict__ vals, int64_t capacity) {
     __shared__ WaveGauss wg[4];
-    for_wave_entries<false>(info, n, emit_off, tiles_x, tiles_y, nullptr, 1, &wg[threadIdx.x / kWave],
+    for_wave_entries<false, false>(info, n, emit_off, tiles_x, tiles_y, nullptr, 1, &wg[threadIdx.x / kWave],
                             [&](int64_t gid, int tx, int ty, int64_t e, uint32_t key, uint32_t) {
                                 if (e >= capacity) return;
                                 keys[e] = ((uint64_t)(ty * tiles_x + tx) << 32) | key;
@@ -572,24 +605,32 @@ hipError_t launch_depth_range(const uint32_t* info, const uint32_t* vis_ids, con
     return hipGetLastError();
 }
 
-hipError_t launch_bin_count(const uint32_t* info, int64_t n, const uint32_t* emit_off, const float* zrange, int K,
-                            int tiles_x, int tiles_y, uint32_t* count, int64_t nseg, uint32_t* entry_rank,
+hipError_t launch_bin_count(const uint32_t* info, int64_t n, const uint32_t* emit_off, const float* zrange,
+                            SegMap sm, int tiles_x, int tiles_y, uint32_t* count, int64_t nseg, uint32_t* entry_rank,
                             int64_t capacity, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(bin_count_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s,
-                       reinterpret_cast<const uint4*>(info), n, emit_off, zrange, K, tiles_x, tiles_y, count, nseg,
-                       entry_rank, capacity);
+    const auto* in = reinterpret_cast<const uint4*>(info);
+    if (sm.seg_base)
+        hipLaunchKernelGGL(bin_count_kernel<true>, dim3(grid_for(n, 256)), dim3(256), 0, s, in, n, emit_off, zrange,
+                           sm, tiles_x, tiles_y, count, nseg, entry_rank, capacity);
+    else
+        hipLaunchKernelGGL(bin_count_kernel<false>, dim3(grid_for(n, 256)), dim3(256), 0, s, in, n, emit_off, zrange,
+                           sm, tiles_x, tiles_y, count, nseg, entry_rank, capacity);
     return hipGetLastError();
 }
 
-hipError_t launch_bin_scatter(const uint32_t* info, int64_t n, const uint32_t* emit_off, const float* zrange, int K,
-                              int tiles_x, int tiles_y, const uint32_t* bin_off, const uint32_t* base, int64_t nseg,
-                              const uint32_t* entry_rank, uint64_t* pairs, int64_t capacity, RecordSink rs,
-                              hipStream_t s) {
+hipError_t launch_bin_scatter(const uint32_t* info, int64_t n, const uint32_t* emit_off, const float* zrange,
+                              SegMap sm, int tiles_x, int tiles_y, const uint32_t* bin_off, const uint32_t* base,
+                              int64_t nseg, const uint32_t* entry_rank, uint64_t* pairs, int64_t capacity,
+                              RecordSink rs, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(bin_scatter_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s,
-                       reinterpret_cast<const uint4*>(info), n, emit_off, zrange, K, tiles_x, tiles_y, bin_off, base,
-                       nseg, entry_rank, pairs, capacity, rs);
+    const auto* in = reinterpret_cast<const uint4*>(info);
+    if (sm.seg_base)
+        hipLaunchKernelGGL(bin_scatter_kernel<true>, dim3(grid_for(n, 256)), dim3(256), 0, s, in, n, emit_off, zrange,
+                           sm, tiles_x, tiles_y, bin_off, base, nseg, entry_rank, pairs, capacity, rs);
+    else
+        hipLaunchKernelGGL(bin_scatter_kernel<false>, dim3(grid_for(n, 256)), dim3(256), 0, s, in, n, emit_off,
+                           zrange, sm, tiles_x, tiles_y, bin_off, base, nseg, entry_rank, pairs, capacity, rs);
     return hipGetLastError();
 }
 
@@ -604,11 +645,11 @@ hipError_t launch_repair(const uint32_t* bin_off, int64_t nseg, uint64_t* pairs,
     return hipGetLastError();
 }
 
-hipError_t launch_tile_order(const uint32_t* offsets, int stride, int64_t T, uint32_t* hist, uint32_t* order,
+hipError_t launch_tile_order(const uint32_t* offsets, SegMap sm, int64_t T, uint32_t* hist, uint32_t* order,
                              hipStream_t s) {
     if (T == 0) return hipSuccess;
-    hipLaunchKernelGGL(tile_hist_kernel, dim3(grid_for(T, 256)), dim3(256), 0, s, offsets, stride, T, hist);
-    hipLaunchKernelGGL(tile_place_kernel, dim3(grid_for(T, 256)), dim3(256), 0, s, offsets, stride, T, hist,
+    hipLaunchKernelGGL(tile_hist_kernel, dim3(grid_for(T, 256)), dim3(256), 0, s, offsets, sm, T, hist);
+    hipLaunchKernelGGL(tile_place_kernel, dim3(grid_for(T, 256)), dim3(256), 0, s, offsets, sm, T, hist,
                        hist + kOrderBuckets, order);
     return hipGetLastError();
 }

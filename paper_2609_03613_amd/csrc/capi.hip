@@ -54,7 +54,8 @@ tgs_status check_camera(const tgs_camera* c) {
 
 tgs_status check_params(const tgs_params* p) {
     if (!p) return fail(TGS_ERR_INVALID_ARG, "params is NULL");
-    if (p->tile_size != kTile) return fail(TGS_ERR_UNSUPPORTED, "tile_size %d (only 16 is implemented)", p->tile_size);
+    if (p->tile_size != 8 && p->tile_size != 16 && p->tile_size != 32)
+        return fail(TGS_ERR_UNSUPPORTED, "tile_size %d (8, 16 or 32)", p->tile_size);
     if (p->num_bins < 1 || p->num_bins > 1024) return fail(TGS_ERR_INVALID_ARG, "num_bins %d outside 1..1024", p->num_bins);
     if (p->sample_count < 1 || p->sample_count > 8192)
         return fail(TGS_ERR_INVALID_ARG, "sample_count %d outside 1..8192", p->sample_count);
@@ -64,6 +65,13 @@ tgs_status check_params(const tgs_params* p) {
     if (p->packed < 0 || p->packed > 2) return fail(TGS_ERR_INVALID_ARG, "packed must be 0, 1 or 2");
     if (p->raster != TGS_RASTER_PLAIN && p->raster != TGS_RASTER_WAVE)
         return fail(TGS_ERR_INVALID_ARG, "unknown raster %d", p->raster);
+    if (p->tile_size != kTile && (p->raster == TGS_RASTER_PLAIN || p->packed != 0))
+        return fail(TGS_ERR_UNSUPPORTED, "tile_size %d needs the WAVE raster with packed = 0", p->tile_size);
+    if (p->per_tile_bins_dev) {
+        if (p->num_bins & (p->num_bins - 1))
+            return fail(TGS_ERR_INVALID_ARG, "num_bins %d must be a power of two with per_tile_bins", p->num_bins);
+        if (p->packed != 0) return fail(TGS_ERR_UNSUPPORTED, "per_tile_bins needs packed = 0");
+    }
     return TGS_OK;
 }
 
@@ -77,13 +85,14 @@ tgs_status check_projected(const tgs_projected* pr) {
 inline size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t emit_off, vis_ids, zero, zero_words, status_emit_x, status_emit_y, status_bins, count, entry_rank,
-        seg_lists, keys_in, vals_in, sort_tmp, sort_tmp_bytes, total;
+    size_t emit_off, vis_ids, zero, zero_words, status_emit_x, status_emit_y, status_bins, status_segs, count,
+        count_var, entry_rank, seg_lists, keys_in, vals_in, sort_tmp, sort_tmp_bytes, total;
 };
 
 // Control words at the start of the zeroed region (uint32 offsets).
 constexpr int kTicketEmit = 0;
 constexpr int kTicketBins = 1;
+constexpr int kTicketSegs = 2;
 constexpr int kBucketCount = 16;
 constexpr int kTileHist = 32;  // 66 words: histogram and cursors of the tile order
 constexpr int kControlWords = 128;
@@ -95,10 +104,14 @@ int end_bit_for(int64_t T) {
 }
 
 // Workspace: [emit offsets][visible ids][zeroed region: control words,
-// scan status words, per-XCD counts (BINNED)][entry ranks][repair lists]
-// (BINNED) or [...][unsorted keys][unsorted ids][sort scratch] (GLOBAL).
-// The zeroed region is cleared by one fill at the start of each tgs_bin.
-Layout layout(int64_t n, int64_t capacity, int64_t T, int K, int order) {
+// scan status words, per-XCD counts (BINNED, uniform K)][entry ranks]
+// [repair lists][per-XCD counts (BINNED, per-tile bin counts)] (BINNED) or
+// [...][unsorted keys][unsorted ids][sort scratch] (GLOBAL). The zeroed
+// region is cleared by one fill at the start of each tgs_bin; with per-tile
+// bin counts only the first kXcc * S words of the counts are cleared, by a
+// fill sized on the device. K is the uniform bin count or the bound of the
+// per-tile counts.
+Layout layout(int64_t n, int64_t capacity, int64_t T, int K, int order, bool var) {
     Layout L{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -118,7 +131,9 @@ Layout layout(int64_t n, int64_t capacity, int64_t T, int K, int order) {
     z += 2 * nbe;
     L.status_bins = z;
     z += 2 * nbb;
-    if (order == TGS_ORDER_BINNED) {
+    L.status_segs = z;
+    z += var ? 2 * (size_t)scan_blocks(T) : 0;
+    if (order == TGS_ORDER_BINNED && !var) {
         z = (z + 63) & ~(size_t)63;
         L.count = z;
         z += (size_t)kXcc * (size_t)nseg;
@@ -128,6 +143,7 @@ Layout layout(int64_t n, int64_t capacity, int64_t T, int K, int order) {
     if (order == TGS_ORDER_BINNED) {
         L.entry_rank = take(sizeof(uint32_t) * (size_t)capacity);
         L.seg_lists = take(sizeof(uint32_t) * (size_t)kBuckets * (size_t)nseg);
+        if (var) L.count_var = take(sizeof(uint32_t) * (size_t)kXcc * (size_t)nseg);
     } else {
         L.keys_in = take(sizeof(uint64_t) * (size_t)capacity);
         L.vals_in = take(sizeof(uint32_t) * (size_t)capacity);
@@ -138,8 +154,8 @@ Layout layout(int64_t n, int64_t capacity, int64_t T, int K, int order) {
     return L;
 }
 
-int64_t tiles_of(const tgs_camera* c) {
-    return (int64_t)div_up(c->width, kTile) * div_up(c->height, kTile);
+int64_t tiles_of(const tgs_camera* c, int tile) {
+    return (int64_t)div_up(c->width, tile) * div_up(c->height, tile);
 }
 
 }  // namespace
@@ -156,6 +172,7 @@ void tgs_default_params(tgs_params* p) {
     p->pad = 0.05f;
     p->raster = TGS_RASTER_WAVE;
     p->packed = 0;
+    p->per_tile_bins_dev = nullptr;
 }
 
 const char* tgs_last_error(void) { return g_err.c_str(); }
@@ -173,7 +190,8 @@ tgs_status tgs_project(const tgs_gaussians* g, const tgs_camera* cam, const tgs_
     if ((st = check_params(params))) return st;
     if (!out || out->n != g->n) return fail(TGS_ERR_INVALID_ARG, "projected output missing or n mismatch");
     if (g->n > 0 && (!out->splats_dev || !out->info_dev)) return fail(TGS_ERR_INVALID_ARG, "projected buffers are NULL");
-    TGS_HIP(launch_project(*g, make_cam(*cam), out->splats_dev, out->info_dev, (hipStream_t)stream), "project");
+    TGS_HIP(launch_project(*g, make_cam(*cam, params->tile_size), out->splats_dev, out->info_dev, (hipStream_t)stream),
+            "project");
     return TGS_OK;
 }
 
@@ -181,7 +199,10 @@ size_t tgs_bin_workspace_size(int64_t n, int64_t capacity, const tgs_camera* cam
                               int32_t order) {
     if (!cam || !params || n < 0 || capacity < 0) return 0;
     if (cam->width < 1 || cam->height < 1 || params->num_bins < 1) return 0;
-    return layout(n, capacity, tiles_of(cam), params->num_bins, order).total;
+    if (params->tile_size != 8 && params->tile_size != 16 && params->tile_size != 32) return 0;
+    return layout(n, capacity, tiles_of(cam, params->tile_size), params->num_bins, order,
+                  params->per_tile_bins_dev != nullptr && order == TGS_ORDER_BINNED)
+        .total;
 }
 
 tgs_status tgs_bin(const tgs_projected* pr, const tgs_camera* cam, const tgs_params* params, int32_t order, void* ws,
@@ -195,8 +216,11 @@ tgs_status tgs_bin(const tgs_projected* pr, const tgs_camera* cam, const tgs_par
     if (!out) return fail(TGS_ERR_INVALID_ARG, "binned output is NULL");
     if (out->capacity < 0 || out->capacity >= ((int64_t)1 << 32)) return fail(TGS_ERR_INVALID_ARG, "capacity outside 0..2^32-1");
     if (!out->counters_dev || !out->offsets_dev) return fail(TGS_ERR_INVALID_ARG, "counters or offsets is NULL");
-    const int64_t n = pr->n, cap = out->capacity, T = tiles_of(cam);
+    const int64_t n = pr->n, cap = out->capacity, T = tiles_of(cam, params->tile_size);
     const int K = params->num_bins;
+    const bool var = params->per_tile_bins_dev != nullptr;
+    if (var && order != TGS_ORDER_BINNED) return fail(TGS_ERR_INVALID_ARG, "per_tile_bins needs the BINNED order");
+    if (var && !out->seg_base_dev) return fail(TGS_ERR_INVALID_ARG, "seg_base is NULL with per_tile_bins");
     if (order == TGS_ORDER_BINNED) {
         if (!out->zrange_dev || (cap > 0 && !out->pairs_dev)) return fail(TGS_ERR_INVALID_ARG, "pairs or zrange is NULL");
         if (params->packed == 1 && cap > 0 && (!out->records_dev || !out->masks_dev))
@@ -207,7 +231,7 @@ tgs_status tgs_bin(const tgs_projected* pr, const tgs_camera* cam, const tgs_par
     } else if (cap > 0 && (!out->keys_dev || !out->vals_dev)) {
         return fail(TGS_ERR_INVALID_ARG, "keys or vals is NULL");
     }
-    const Layout L = layout(n, cap, T, K, order);
+    const Layout L = layout(n, cap, T, K, order, var);
     if (!ws || ws_bytes < L.total)
         return fail(TGS_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
     hipStream_t s = (hipStream_t)stream;
@@ -216,7 +240,7 @@ tgs_status tgs_bin(const tgs_projected* pr, const tgs_camera* cam, const tgs_par
     uint32_t* vis_ids = (uint32_t*)(w + L.vis_ids);
     uint32_t* zero = (uint32_t*)(w + L.zero);
     const int S = params->sample_count;
-    const int tiles_x = div_up(cam->width, kTile), tiles_y = div_up(cam->height, kTile);
+    const int tiles_x = div_up(cam->width, params->tile_size), tiles_y = div_up(cam->height, params->tile_size);
 
     TGS_HIP(launch_fill_u32(zero, 0u, (int64_t)L.zero_words, s), "clear control words");
     TGS_HIP(launch_emit_scan(pr->info_dev, n, tiles_x, tiles_y, emit_off, vis_ids, zero + kTicketEmit,
@@ -239,10 +263,13 @@ tgs_status tgs_bin(const tgs_projected* pr, const tgs_camera* cam, const tgs_par
                 "radix sort");
         TGS_HIP(launch_tile_ranges(out->keys_dev, M, T, out->offsets_dev, s), "tile ranges");
         if (out->tile_order_dev)
-            TGS_HIP(launch_tile_order(out->offsets_dev, 1, T, zero + kTileHist, out->tile_order_dev, s), "tile order");
+            TGS_HIP(launch_tile_order(out->offsets_dev, SegMap{nullptr, 1}, T, zero + kTileHist, out->tile_order_dev, s),
+                    "tile order");
         return TGS_OK;
     }
-    uint32_t* count = zero + L.count;
+    uint32_t* count = var ? (uint32_t*)(w + L.count_var) : zero + L.count;
+    const SegMap sm{var ? out->seg_base_dev : nullptr, K};
+    const uint32_t* nseg_dev = var ? out->seg_base_dev + T : nullptr;
     uint32_t* entry_rank = (uint32_t*)(w + L.entry_rank);
     uint32_t* seg_lists = (uint32_t*)(w + L.seg_lists);
     uint32_t* bucket_count = zero + kBucketCount;
@@ -250,21 +277,27 @@ tgs_status tgs_bin(const tgs_projected* pr, const tgs_camera* cam, const tgs_par
     RecordSink rs{reinterpret_cast<const float4*>(pr->splats_dev),
                   params->packed == 1 ? reinterpret_cast<float4*>(out->records_dev) : nullptr,
                   params->packed ? out->masks_dev : nullptr, K, tiles_x, cam->width, cam->height};
+    if (var) {
+        TGS_HIP(launch_seg_base(params->per_tile_bins_dev, T, K, out->seg_base_dev, zero + kTicketSegs,
+                                (uint64_t*)(zero + L.status_segs), s),
+                "segment bases");
+        TGS_HIP(launch_fill_u32_dyn(count, 0u, nseg_dev, kXcc, (int64_t)kXcc * nseg, s), "clear counts");
+    }
     TGS_HIP(launch_depth_range(pr->info_dev, vis_ids, out->counters_dev, S, params->p_lo, params->p_hi, params->pad,
                                (float)cam->znear, (float)cam->zfar, out->zrange_dev, s),
             "depth range");
-    TGS_HIP(launch_bin_count(pr->info_dev, n, emit_off, out->zrange_dev, K, tiles_x, tiles_y, count, nseg, entry_rank,
+    TGS_HIP(launch_bin_count(pr->info_dev, n, emit_off, out->zrange_dev, sm, tiles_x, tiles_y, count, nseg, entry_rank,
                              cap, s),
             "bin count");
-    TGS_HIP(launch_bin_offsets(count, nseg, out->offsets_dev, zero + kTicketBins, (uint64_t*)(zero + L.status_bins),
-                               seg_lists, bucket_count, out->counters_dev, s),
+    TGS_HIP(launch_bin_offsets(count, nseg, nseg_dev, out->offsets_dev, zero + kTicketBins,
+                               (uint64_t*)(zero + L.status_bins), seg_lists, bucket_count, out->counters_dev, s),
             "bin offsets");
-    TGS_HIP(launch_bin_scatter(pr->info_dev, n, emit_off, out->zrange_dev, K, tiles_x, tiles_y, out->offsets_dev, count,
+    TGS_HIP(launch_bin_scatter(pr->info_dev, n, emit_off, out->zrange_dev, sm, tiles_x, tiles_y, out->offsets_dev, count,
                                nseg, entry_rank, out->pairs_dev, cap, rs, s),
             "bin scatter");
     TGS_HIP(launch_repair(out->offsets_dev, nseg, out->pairs_dev, seg_lists, bucket_count, rs, s), "repair");
     if (out->tile_order_dev)
-        TGS_HIP(launch_tile_order(out->offsets_dev, K, T, zero + kTileHist, out->tile_order_dev, s), "tile order");
+        TGS_HIP(launch_tile_order(out->offsets_dev, sm, T, zero + kTileHist, out->tile_order_dev, s), "tile order");
     return TGS_OK;
 }
 
@@ -290,6 +323,8 @@ tgs_status tgs_rasterize(const tgs_projected* pr, const tgs_binned* b, const tgs
         if (!a.vals && b->capacity > 0) return fail(TGS_ERR_INVALID_ARG, "vals is NULL");
     } else {
         a.stride = params->num_bins;
+        a.seg_base = params->per_tile_bins_dev ? b->seg_base_dev : nullptr;
+        if (params->per_tile_bins_dev && !a.seg_base) return fail(TGS_ERR_INVALID_ARG, "seg_base is NULL with per_tile_bins");
         a.pairs = b->pairs_dev;
         a.records = params->packed == 1 ? b->records_dev : nullptr;
         a.masks = params->packed ? b->masks_dev : nullptr;
@@ -301,8 +336,9 @@ tgs_status tgs_rasterize(const tgs_projected* pr, const tgs_binned* b, const tgs
     if (pr->n > 0 && !a.splats && !a.records) return fail(TGS_ERR_INVALID_ARG, "splats is NULL");
     a.width = cam->width;
     a.height = cam->height;
-    a.tiles_x = div_up(cam->width, kTile);
-    a.tiles_y = div_up(cam->height, kTile);
+    a.tile = params->tile_size;
+    a.tiles_x = div_up(cam->width, params->tile_size);
+    a.tiles_y = div_up(cam->height, params->tile_size);
     for (int i = 0; i < 3; ++i) a.bg[i] = bg[i];
     a.rgb = rgb;
     a.alpha = alpha;
@@ -341,13 +377,16 @@ tgs_status tgs_rasterize_backward(const tgs_projected* pr, const tgs_binned* b, 
         if (!a.vals && b->capacity > 0) return fail(TGS_ERR_INVALID_ARG, "vals is NULL");
     } else {
         a.stride = params->num_bins;
+        a.seg_base = params->per_tile_bins_dev ? b->seg_base_dev : nullptr;
+        if (params->per_tile_bins_dev && !a.seg_base) return fail(TGS_ERR_INVALID_ARG, "seg_base is NULL with per_tile_bins");
         a.pairs = b->pairs_dev;
         if (!a.pairs && b->capacity > 0) return fail(TGS_ERR_INVALID_ARG, "pairs is NULL");
     }
     a.width = cam->width;
     a.height = cam->height;
-    a.tiles_x = div_up(cam->width, kTile);
-    a.tiles_y = div_up(cam->height, kTile);
+    a.tile = params->tile_size;
+    a.tiles_x = div_up(cam->width, params->tile_size);
+    a.tiles_y = div_up(cam->height, params->tile_size);
     for (int i = 0; i < 3; ++i) a.bg[i] = bg[i];
     hipStream_t s = (hipStream_t)stream;
     if (pr->n == 0) return TGS_OK;
@@ -370,7 +409,7 @@ tgs_status tgs_project_backward(const tgs_gaussians* g, const tgs_camera* cam, c
     if (g->n > 0 && (!d_splats || !out->means_dev || !out->log_scales_dev || !out->quats_dev || !out->logits_dev ||
                      !out->sh_dev))
         return fail(TGS_ERR_INVALID_ARG, "a gradient pointer is NULL");
-    TGS_HIP(launch_project_backward(*g, make_cam(*cam), d_splats, *out, (hipStream_t)stream), "project backward");
+    TGS_HIP(launch_project_backward(*g, make_cam(*cam, kTile), d_splats, *out, (hipStream_t)stream), "project backward");
     return TGS_OK;
 }
 

@@ -132,18 +132,24 @@ __device__ __forceinline__ bool block_may_touch(float mx, float my, float a, flo
     return qmin <= tau + 1e-3f + 4e-6f * mag;
 }
 
-// Pixel-centre box (tile-local) of the in-image pixels of 8x8 block w of
-// tile (tx, ty); false when the block lies outside the image.
-__device__ __forceinline__ bool block_box(int w, int tx, int ty, int width, int height, float& xa, float& xb,
-                                          float& ya, float& yb) {
-    const int bx = (w & 1) * 8, by = (w >> 1) * 8;
-    const int nx = min(8, width - (tx * kTile + bx)), ny = min(8, height - (ty * kTile + by));
+// Pixel-centre box (tile-local) of the in-image pixels of the 8x8 block at
+// tile-local offset (bx, by) of the tile whose first pixel is (x0, y0);
+// false when the block lies outside the image.
+__device__ __forceinline__ bool block_box_at(int bx, int by, int x0, int y0, int width, int height, float& xa,
+                                             float& xb, float& ya, float& yb) {
+    const int nx = min(8, width - (x0 + bx)), ny = min(8, height - (y0 + by));
     if (nx <= 0 || ny <= 0) return false;
     xa = bx + 0.5f;
     xb = bx + nx - 0.5f;
     ya = by + 0.5f;
     yb = by + ny - 0.5f;
     return true;
+}
+
+// The same for 8x8 block w (0..3, row-major) of 16x16 tile (tx, ty).
+__device__ __forceinline__ bool block_box(int w, int tx, int ty, int width, int height, float& xa, float& xb,
+                                          float& ya, float& yb) {
+    return block_box_at((w & 1) * 8, (w >> 1) * 8, tx * kTile, ty * kTile, width, height, xa, xb, ya, yb);
 }
 
 // Where the entry-placing kernels put the per-entry raster data. masks ==
@@ -185,16 +191,30 @@ struct RecordSink {
     }
 };
 
+// Segment numbering of the BINNED stream: segment first(t) + b is bin b of
+// tile t. Uniform (seg_base == null): K bins per tile, first(t) = t K.
+// Per-tile bin counts: seg_base [T + 1] is the exclusive prefix sum of the
+// counts (powers of two), first(t) = seg_base[t], and the number of
+// segments S = seg_base[T] is known on the device only.
+struct SegMap {
+    const uint32_t* seg_base;
+    int K;
+    __device__ __forceinline__ uint32_t first(int64_t t) const {
+        return seg_base ? seg_base[t] : (uint32_t)(t * K);
+    }
+};
+
 struct Cam {
     double R[9], t[3];
     double fx, fy, cx, cy;
     double znear, zfar;
     double campos[3];
     double lim_xp, lim_xn, lim_yp, lim_yn;
-    int width, height, tiles_x, tiles_y;
+    int width, height, tile, tiles_x, tiles_y;
 };
 
-Cam make_cam(const tgs_camera& c);
+// tile: tile edge in pixels (8, 16 or 32).
+Cam make_cam(const tgs_camera& c, int tile);
 
 // Launch helpers (host), implemented next to their kernels.
 hipError_t launch_project(const tgs_gaussians& g, const Cam& cam, float* splats, uint32_t* info,
@@ -220,11 +240,11 @@ hipError_t launch_depth_range(const uint32_t* info, const uint32_t* vis_ids, con
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 
-// (tile, bin) counting with one count copy per XCD: count [kXcc][nseg]. The
-// rank of each entry in its copy, with the copy index in the top three bits,
-// goes to entry_rank.
+// (tile, bin) counting with one count copy per XCD: count [kXcc][S] (S =
+// nseg, or seg_base[T] with per-tile bin counts). The rank of each entry in
+// its copy, with the copy index in the top three bits, goes to entry_rank.
 hipError_t launch_bin_count(const uint32_t* info, int64_t n, const uint32_t* emit_off, const float* zrange,
-                            int K, int tiles_x, int tiles_y, uint32_t* count, int64_t nseg, uint32_t* entry_rank,
+                            SegMap sm, int tiles_x, int tiles_y, uint32_t* count, int64_t nseg, uint32_t* entry_rank,
                             int64_t capacity, hipStream_t s);
 // Repair length buckets: 2..8, 9..16, 17..32, 33..64 (lane groups of one
 // wavefront, registers), 65..512 (one wavefront, LDS), 513..4096 and
@@ -242,17 +262,29 @@ __host__ __device__ __forceinline__ int bucket_of(uint32_t len) {
     return 7;
 }
 
-// bin_off[s] = exclusive scan of the summed copies (bin_off[nseg] = M);
+// bin_off[s] = exclusive scan of the summed copies (bin_off[S] = M);
 // count[x][s] becomes the base position of copy x inside segment s; every
-// segment of two or more entries is appended to lists[bucket][...] with
-// bucket_count[bucket] entries (not when counters[2] flags an overflow).
-// ticket, status [scan_blocks(nseg)] and bucket_count must be zero.
-hipError_t launch_bin_offsets(uint32_t* count, int64_t nseg, uint32_t* bin_off, uint32_t* ticket, uint64_t* status,
-                              uint32_t* lists, uint32_t* bucket_count, const int64_t* counters, hipStream_t s);
+// segment of two or more entries is appended to lists[bucket][...] (bucket
+// stride: nseg) with bucket_count[bucket] entries (not when counters[2]
+// flags an overflow). S = nseg, or *nseg_dev when nseg_dev is not null
+// (then nseg is its upper bound). ticket, status [scan_blocks(nseg)] and
+// bucket_count must be zero.
+hipError_t launch_bin_offsets(uint32_t* count, int64_t nseg, const uint32_t* nseg_dev, uint32_t* bin_off,
+                              uint32_t* ticket, uint64_t* status, uint32_t* lists, uint32_t* bucket_count,
+                              const int64_t* counters, hipStream_t s);
 hipError_t launch_bin_scatter(const uint32_t* info, int64_t n, const uint32_t* emit_off, const float* zrange,
-                              int K, int tiles_x, int tiles_y, const uint32_t* bin_off, const uint32_t* base,
+                              SegMap sm, int tiles_x, int tiles_y, const uint32_t* bin_off, const uint32_t* base,
                               int64_t nseg, const uint32_t* entry_rank, uint64_t* pairs, int64_t capacity,
                               RecordSink rs, hipStream_t s);
+
+// Per-tile bin counts: seg_base[t] = exclusive prefix sum of the bin counts
+// (each clamped to 1..kmax and rounded down to a power of two), seg_base[T]
+// = S. ticket and status [scan_blocks(T)] must be zero.
+hipError_t launch_seg_base(const int32_t* per_tile_bins, int64_t T, int kmax, uint32_t* seg_base, uint32_t* ticket,
+                           uint64_t* status, hipStream_t s);
+// p[0 .. mult * *n_dev) = v.
+hipError_t launch_fill_u32_dyn(uint32_t* p, uint32_t v, const uint32_t* n_dev, int mult, int64_t max_n,
+                               hipStream_t s);
 
 // Sorts every queued segment by its 64-bit pairs and writes its records.
 hipError_t launch_repair(const uint32_t* bin_off, int64_t nseg, uint64_t* pairs, const uint32_t* seg_lists,
@@ -261,7 +293,7 @@ hipError_t launch_repair(const uint32_t* bin_off, int64_t nseg, uint64_t* pairs,
 // Tiles in descending order of their entry count (coarse: by bit length of
 // the count), so the heaviest tiles are dispatched first. hist [66] must be
 // zero.
-hipError_t launch_tile_order(const uint32_t* offsets, int stride, int64_t T, uint32_t* hist, uint32_t* order,
+hipError_t launch_tile_order(const uint32_t* offsets, SegMap sm, int64_t T, uint32_t* hist, uint32_t* order,
                              hipStream_t s);
 
 hipError_t launch_emit_keys(const uint32_t* info, int64_t n, const uint32_t* emit_off, int tiles_x, int tiles_y,
@@ -275,13 +307,14 @@ struct RasterArgs {
     const float* splats;    // [n][16]
     const uint32_t* offsets;
     int stride;             // offsets index step per tile (1 for GLOBAL, K for BINNED)
+    const uint32_t* seg_base;  // BINNED with per-tile bin counts: first segment of each tile [T + 1]
     const uint32_t* vals;   // GLOBAL ids
     const uint64_t* pairs;  // BINNED pairs
     const float* records;   // BINNED packed records or null
     const uint8_t* masks;   // block masks of the packed records
     const int64_t* counters;
     const uint32_t* order;  // tile dispatch order or null
-    int width, height, tiles_x, tiles_y;
+    int width, height, tile, tiles_x, tiles_y;  // tile: edge in pixels (the PLAIN raster: 16 only)
     float bg[3];
     float* rgb;
     float* alpha;

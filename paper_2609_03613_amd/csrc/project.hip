@@ -14,15 +14,16 @@
 
 namespace tgs {
 
-Cam make_cam(const tgs_camera& c) {
+Cam make_cam(const tgs_camera& c, int tile) {
     Cam k;
     for (int i = 0; i < 9; ++i) k.R[i] = c.R[i];
     for (int i = 0; i < 3; ++i) k.t[i] = c.t[i];
     k.fx = c.fx; k.fy = c.fy; k.cx = c.cx; k.cy = c.cy;
     k.znear = c.znear; k.zfar = c.zfar;
     k.width = c.width; k.height = c.height;
-    k.tiles_x = div_up(c.width, kTile);
-    k.tiles_y = div_up(c.height, kTile);
+    k.tile = tile;
+    k.tiles_x = div_up(c.width, tile);
+    k.tiles_y = div_up(c.height, tile);
     for (int i = 0; i < 3; ++i) k.campos[i] = -(c.R[i] * c.t[0] + c.R[3 + i] * c.t[1] + c.R[6 + i] * c.t[2]);
     k.lim_xp = (c.width - c.cx) / c.fx + 0.3 * c.width / c.fx;
     k.lim_xn = c.cx / c.fx + 0.3 * c.width / c.fx;
@@ -151,8 +152,9 @@ __global__ void __launch_bounds__(kProjThreads) project_kernel(const float* __re
         const double tau = 2.0 * log(255.0 * o);
         const double ex = sqrt(tau * c00) * (1.0 + 1e-4) + 1e-3;
         const double ey = sqrt(tau * c11) * (1.0 + 1e-4) + 1e-3;
-        double fx0 = floor((mxs - ex) / kTile), fx1 = floor((mxs + ex) / kTile) + 1.0;
-        double fy0 = floor((mys - ey) / kTile), fy1 = floor((mys + ey) / kTile) + 1.0;
+        const double ts = (double)cam.tile;
+        double fx0 = floor((mxs - ex) / ts), fx1 = floor((mxs + ex) / ts) + 1.0;
+        double fy0 = floor((mys - ey) / ts), fy1 = floor((mys + ey) / ts) + 1.0;
         fx0 = fmin(fmax(fx0, 0.0), (double)cam.tiles_x);
         fx1 = fmin(fmax(fx1, 0.0), (double)cam.tiles_x);
         fy0 = fmin(fmax(fy0, 0.0), (double)cam.tiles_y);

@@ -72,8 +72,8 @@ __global__ void __launch_bounds__(256) raster_plain_kernel(RasterArgs A) {
     const float ox = (float)(tx * kTile), oy = (float)(ty * kTile);
     const float px = (float)lx + 0.5f, py = (float)ly + 0.5f;
     Pix p{1.0f, 0.f, 0.f, 0.f, -1, 0, 0, 0, !inside || bad};
-    const uint32_t begin = A.offsets[(int64_t)t * A.stride];
-    const uint32_t end = bad ? begin : A.offsets[(int64_t)(t + 1) * A.stride];
+    const uint32_t begin = tile_begin(A, t);
+    const uint32_t end = bad ? begin : tile_end(A, t);
     for (uint32_t base = begin; base < end; base += 256) {
         if (__syncthreads_count(p.done) == 256) break;
         const uint32_t e = base + threadIdx.x;
@@ -102,21 +102,22 @@ __global__ void __launch_bounds__(256) raster_plain_kernel(RasterArgs A) {
 template <int SRC, bool COUNT>
 __global__ void __launch_bounds__(256) raster_wave_kernel(RasterArgs A) {
     __shared__ Staged stage[4][kWave];
-    const int t = tile_of_block(A);
-    const int tx = t % A.tiles_x, ty = t / A.tiles_x;
     const int w = threadIdx.x / kWave, l = lane();
+    WaveBlock wb;
+    if (!block_of_wave(A, w, wb)) return;
+    const int x0 = wb.tx * A.tile, y0 = wb.ty * A.tile;
     float xa, xb, ya, yb;
-    if (!block_box(w, tx, ty, A.width, A.height, xa, xb, ya, yb)) return;  // block outside the image
-    const int lx = (w & 1) * 8 + (l & 7), ly = (w >> 1) * 8 + (l >> 3);
-    const int x = tx * kTile + lx, y = ty * kTile + ly;
+    if (!block_box_at(wb.bx, wb.by, x0, y0, A.width, A.height, xa, xb, ya, yb)) return;  // block outside the image
+    const int lx = wb.bx + (l & 7), ly = wb.by + (l >> 3);
+    const int x = x0 + lx, y = y0 + ly;
     const bool inside = x < A.width && y < A.height;
     const bool bad = A.counters[2] != 0;
-    const float ox = (float)(tx * kTile), oy = (float)(ty * kTile);
+    const float ox = (float)x0, oy = (float)y0;
     const float px = (float)lx + 0.5f, py = (float)ly + 0.5f;
     Pix p{1.0f, 0.f, 0.f, 0.f, -1, 0, 0, 0, !inside || bad};
-    const uint32_t begin = A.offsets[(int64_t)t * A.stride];
-    const uint32_t end = bad ? begin : A.offsets[(int64_t)(t + 1) * A.stride];
-    wave_forward<SRC, COUNT>(A, stage[w], w, begin, end, ox, oy, px, py, xa, xb, ya, yb, p);
+    const uint32_t begin = tile_begin(A, wb.t);
+    const uint32_t end = bad ? begin : tile_end(A, wb.t);
+    wave_forward<SRC, COUNT>(A, stage[w], wb.bi, begin, end, ox, oy, px, py, xa, xb, ya, yb, p);
     if (inside) write_pixel(A, x, y, p, bad);
 }
 
@@ -133,10 +134,12 @@ hipError_t plain_dispatch(const RasterArgs& a, hipStream_t s) {
 template <int SRC>
 hipError_t wave_dispatch(const RasterArgs& a, hipStream_t s) {
     const int T = a.tiles_x * a.tiles_y;
+    const int B = blocks_per_tile(a.tile), G = groups_per_tile(a.tile);
+    const dim3 grid((unsigned)(T * G)), block((unsigned)(kWave * (B < 4 ? B : 4)));
     if (a.n_visit || a.n_support || a.n_contrib)
-        hipLaunchKernelGGL((raster_wave_kernel<SRC, true>), dim3(T), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((raster_wave_kernel<SRC, true>), grid, block, 0, s, a);
     else
-        hipLaunchKernelGGL((raster_wave_kernel<SRC, false>), dim3(T), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((raster_wave_kernel<SRC, false>), grid, block, 0, s, a);
     return hipGetLastError();
 }
 

@@ -80,9 +80,53 @@ __device__ __forceinline__ Staged load_entry(const RasterArgs& A, uint32_t p, fl
     return s;
 }
 
+// First and one-past-last stream position of tile t.
+__device__ __forceinline__ uint32_t tile_begin(const RasterArgs& A, int t) {
+    return A.offsets[A.seg_base ? (int64_t)A.seg_base[t] : (int64_t)t * A.stride];
+}
+__device__ __forceinline__ uint32_t tile_end(const RasterArgs& A, int t) {
+    return A.offsets[A.seg_base ? (int64_t)A.seg_base[t + 1] : (int64_t)(t + 1) * A.stride];
+}
+
 __device__ __forceinline__ int tile_of_block(const RasterArgs& A) {
     const int T = A.tiles_x * A.tiles_y;
     return A.order ? (int)A.order[blockIdx.x] : xcd_remap(blockIdx.x, T);
+}
+
+// 8x8 pixel blocks per tile and workgroups (of up to four 64-lane
+// wavefronts, one block each) per tile for a tile edge of `tile` pixels.
+__host__ __device__ __forceinline__ int blocks_per_tile(int tile) { return (tile >> 3) * (tile >> 3); }
+__host__ __device__ __forceinline__ int groups_per_tile(int tile) { return (blocks_per_tile(tile) + 3) >> 2; }
+
+// The block a wavefront of the WAVE rasters owns: tile t = (tx, ty) and the
+// block's tile-local pixel offset (bx, by) and index bi. Workgroup i serves
+// group i % G of tile slot i / G (slot = position in the dispatch order, or
+// the XCD-aware remap of i); false for the idle wavefronts of a short last
+// group.
+struct WaveBlock {
+    int t, tx, ty, bi, bx, by;
+};
+__device__ __forceinline__ bool block_of_wave(const RasterArgs& A, int w, WaveBlock& b) {
+    const int nb = A.tile >> 3, B = nb * nb, G = (B + 3) >> 2;
+    const int T = A.tiles_x * A.tiles_y;
+    int slot, grp;
+    if (A.order) {
+        slot = (int)blockIdx.x / G;
+        grp = (int)blockIdx.x % G;
+        b.t = (int)A.order[slot];
+    } else {
+        const int i = xcd_remap((int)blockIdx.x, T * G);
+        slot = i / G;
+        grp = i % G;
+        b.t = slot;
+    }
+    b.bi = grp * 4 + w;
+    if (b.bi >= B) return false;
+    b.tx = b.t % A.tiles_x;
+    b.ty = b.t / A.tiles_x;
+    b.bx = (b.bi % nb) * 8;
+    b.by = (b.bi / nb) * 8;
+    return true;
 }
 
 __device__ __forceinline__ void wave_sync() {
@@ -112,11 +156,11 @@ __device__ __forceinline__ void composite_staged(Pix& p, float px, float py, con
 // can reach alpha 1/255 in the block, compacted into the wavefront's LDS
 // slots st[] and composited by every lane.
 template <int SRC, bool COUNT>
-__device__ __forceinline__ void wave_forward(const RasterArgs& A, Staged* st, int w, uint32_t begin, uint32_t end,
+__device__ __forceinline__ void wave_forward(const RasterArgs& A, Staged* st, int bi, uint32_t begin, uint32_t end,
                                              float ox, float oy, float px, float py, float xa, float xb, float ya,
                                              float yb, Pix& p) {
     const int l = lane();
-    const uint32_t bit = 1u << w;
+    const uint32_t bit = 1u << bi;  // block masks exist for 16-pixel tiles only (bi < 4)
     for (uint32_t base = begin; base < end; base += kWave) {
         if (ballot(!p.done) == 0) break;
         const uint32_t e = base + l;

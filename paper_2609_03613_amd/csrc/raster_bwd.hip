@@ -63,25 +63,26 @@ __global__ void __launch_bounds__(256) raster_bwd_kernel(RasterArgs A, const flo
 #pragma clang fp contract(off)
     __shared__ Staged stage[4][kWave];
     __shared__ uint32_t ids[4][kWave];
-    const int t = tile_of_block(A);
-    const int tx = t % A.tiles_x, ty = t / A.tiles_x;
     const int w = threadIdx.x / kWave, l = lane();
+    WaveBlock wb;
+    if (!block_of_wave(A, w, wb)) return;
+    const int x0 = wb.tx * A.tile, y0 = wb.ty * A.tile;
     float xa, xb, ya, yb;
-    if (!block_box(w, tx, ty, A.width, A.height, xa, xb, ya, yb)) return;  // block outside the image
+    if (!block_box_at(wb.bx, wb.by, x0, y0, A.width, A.height, xa, xb, ya, yb)) return;  // block outside the image
     if (A.counters[2] != 0) return;  // truncated stream: the forward image is NaN, no gradient
-    const int lx = (w & 1) * 8 + (l & 7), ly = (w >> 1) * 8 + (l >> 3);
-    const int x = tx * kTile + lx, y = ty * kTile + ly;
+    const int lx = wb.bx + (l & 7), ly = wb.by + (l >> 3);
+    const int x = x0 + lx, y = y0 + ly;
     const bool inside = x < A.width && y < A.height;
-    const float ox = (float)(tx * kTile), oy = (float)(ty * kTile);
+    const float ox = (float)x0, oy = (float)y0;
     const float px = (float)lx + 0.5f, py = (float)ly + 0.5f;
-    const uint32_t begin = A.offsets[(int64_t)t * A.stride];
-    const uint32_t end = A.offsets[(int64_t)(t + 1) * A.stride];
+    const uint32_t begin = tile_begin(A, wb.t);
+    const uint32_t end = tile_end(A, wb.t);
     Staged* st = stage[w];
     uint32_t* idw = ids[w];
 
     // pass 1: the forward walk
     Pix p{1.0f, 0.f, 0.f, 0.f, -1, 0, 0, 0, !inside};
-    wave_forward<SRC, false>(A, st, w, begin, end, ox, oy, px, py, xa, xb, ya, yb, p);
+    wave_forward<SRC, false>(A, st, wb.bi, begin, end, ox, oy, px, py, xa, xb, ya, yb, p);
 
     // pass 2: backwards from the last composited entry
     const int hi = wave_max_i32(p.last);
@@ -179,10 +180,12 @@ hipError_t launch_raster_backward(const RasterArgs& a, const float* d_rgb, const
                                   hipStream_t s) {
     const int T = a.tiles_x * a.tiles_y;
     if (T == 0) return hipSuccess;
+    const int B = blocks_per_tile(a.tile), G = groups_per_tile(a.tile);
+    const dim3 grid((unsigned)(T * G)), block((unsigned)(kWave * (B < 4 ? B : 4)));
     if (a.vals)
-        hipLaunchKernelGGL((raster_bwd_kernel<SRC_VALS>), dim3(T), dim3(256), 0, s, a, d_rgb, d_alpha, d_splats);
+        hipLaunchKernelGGL((raster_bwd_kernel<SRC_VALS>), grid, block, 0, s, a, d_rgb, d_alpha, d_splats);
     else
-        hipLaunchKernelGGL((raster_bwd_kernel<SRC_PAIRS>), dim3(T), dim3(256), 0, s, a, d_rgb, d_alpha, d_splats);
+        hipLaunchKernelGGL((raster_bwd_kernel<SRC_PAIRS>), grid, block, 0, s, a, d_rgb, d_alpha, d_splats);
     return hipGetLastError();
 }
 

@@ -173,6 +173,11 @@ __global__ void __launch_bounds__(kThreads) emit_scan_kernel(const uint4* __rest
 
 // ---- bin offsets from the per-XCD count copies ---------------------------
 
+__host__ __device__ __forceinline__ int64_t blocks_for(int64_t n) {
+    const int64_t b = (n + kPerBlock - 1) / kPerBlock;
+    return b > 0 ? b : 1;
+}
+
 __device__ __forceinline__ uint32_t seg_total(const uint32_t* __restrict__ count, int64_t nseg, int64_t s) {
     uint32_t t = 0;
     if (s < nseg)
@@ -186,8 +191,11 @@ __device__ __forceinline__ uint32_t seg_total(const uint32_t* __restrict__ count
 // s. Every segment with two or more entries is appended to the list of its
 // repair bucket (aggregated per wavefront and per workgroup: one global
 // atomic per bucket and workgroup). Nothing is queued when the stream
-// overflowed (counters[2]).
-__global__ void __launch_bounds__(kThreads) bin_offsets_kernel(uint32_t* __restrict__ count, int64_t nseg,
+// overflowed (counters[2]). With nseg_dev, the number of segments (and the
+// stride of the count copies) is *nseg_dev and the grid is sized for its
+// upper bound: workgroups past the last needed one leave after their ticket.
+__global__ void __launch_bounds__(kThreads) bin_offsets_kernel(uint32_t* __restrict__ count, int64_t nseg_max,
+                                                               const uint32_t* __restrict__ nseg_dev,
                                                                uint32_t* __restrict__ bin_off, uint32_t* ticket,
                                                                uint64_t* status, uint32_t* __restrict__ lists,
                                                                uint32_t* __restrict__ bucket_count,
@@ -200,7 +208,9 @@ __global__ void __launch_bounds__(kThreads) bin_offsets_kernel(uint32_t* __restr
     if (threadIdx.x < kBuckets) lcount[threadIdx.x] = 0;
     __syncthreads();
     const int64_t b = tk;
-    const int64_t nb = gridDim.x;
+    const int64_t nseg = nseg_dev ? (int64_t)*nseg_dev : nseg_max;
+    const int64_t nb = blocks_for(nseg);
+    if (b >= nb) return;
     const int64_t base = b * kPerBlock;
     const bool queue = counters[2] == 0;
     uint32_t v[kRounds];
@@ -256,8 +266,57 @@ __global__ void __launch_bounds__(kThreads) bin_offsets_kernel(uint32_t* __restr
     for (int r = 0; r < kRounds; ++r) {
         if (bk[r] < 0) continue;
         const int64_t sg = base + r * kThreads + threadIdx.x;
-        lists[(int64_t)bk[r] * nseg + lbase[bk[r]] + slot[r]] = (uint32_t)sg;
+        lists[(int64_t)bk[r] * nseg_max + lbase[bk[r]] + slot[r]] = (uint32_t)sg;
     }
+}
+
+// ---- per-tile segment bases -------------------------------------------------
+// seg_base[t] = exclusive prefix of the per-tile bin counts, each clamped to
+// 1..kmax and rounded down to a power of two; seg_base[T] = S.
+
+__device__ __forceinline__ uint32_t pow2_bins(int32_t k, int kmax) {
+    const uint32_t c = (uint32_t)(k < 1 ? 1 : (k > kmax ? kmax : k));
+    return 1u << (31 - __builtin_clz(c));
+}
+
+__global__ void __launch_bounds__(kThreads) seg_base_kernel(const int32_t* __restrict__ kt, int64_t T, int kmax,
+                                                            uint32_t* __restrict__ seg_base, uint32_t* ticket,
+                                                            uint64_t* status) {
+    __shared__ uint32_t tk;
+    __shared__ uint32_t lds32[kThreads / kWave];
+    __shared__ uint64_t pre;
+    if (threadIdx.x == 0) tk = atomicAdd(ticket, 1u);
+    __syncthreads();
+    const int64_t b = tk;
+    const int64_t nb = gridDim.x;
+    const int64_t base = b * kPerBlock;
+    uint32_t v[kRounds];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+        const int64_t t = base + r * kThreads + threadIdx.x;
+        v[r] = t < T ? pow2_bins(kt[t], kmax) : 0u;
+        sum += v[r];
+    }
+    const uint32_t agg = block_sum_u32(sum, lds32);
+    if (threadIdx.x == 0) pre = publish_and_look_back(status, b, agg);
+    __syncthreads();
+    uint32_t carry = (uint32_t)pre;
+    if (b == nb - 1 && threadIdx.x == 0) seg_base[T] = carry + agg;
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+        const int64_t t = base + r * kThreads + threadIdx.x;
+        uint32_t tot;
+        const uint32_t ex = block_excl_u32(v[r], lds32, &tot);
+        if (t < T) seg_base[t] = carry + ex;
+        carry += tot;
+    }
+}
+
+__global__ void fill_u32_dyn_kernel(uint32_t* p, uint32_t v, const uint32_t* n_dev, int mult) {
+    const int64_t n = (int64_t)*n_dev * mult;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
 }
 
 __global__ void fill_u32_kernel(uint32_t* p, uint32_t v, int64_t n) {
@@ -278,10 +337,27 @@ hipError_t launch_emit_scan(const uint32_t* info, int64_t n, int tiles_x, int ti
     return hipGetLastError();
 }
 
-hipError_t launch_bin_offsets(uint32_t* count, int64_t nseg, uint32_t* bin_off, uint32_t* ticket, uint64_t* status,
-                              uint32_t* lists, uint32_t* bucket_count, const int64_t* counters, hipStream_t s) {
+hipError_t launch_bin_offsets(uint32_t* count, int64_t nseg, const uint32_t* nseg_dev, uint32_t* bin_off,
+                              uint32_t* ticket, uint64_t* status, uint32_t* lists, uint32_t* bucket_count,
+                              const int64_t* counters, hipStream_t s) {
     hipLaunchKernelGGL(bin_offsets_kernel, dim3((unsigned)scan_blocks(nseg)), dim3(kThreads), 0, s, count, nseg,
-                       bin_off, ticket, status, lists, bucket_count, counters);
+                       nseg_dev, bin_off, ticket, status, lists, bucket_count, counters);
+    return hipGetLastError();
+}
+
+hipError_t launch_seg_base(const int32_t* per_tile_bins, int64_t T, int kmax, uint32_t* seg_base, uint32_t* ticket,
+                           uint64_t* status, hipStream_t s) {
+    hipLaunchKernelGGL(seg_base_kernel, dim3((unsigned)scan_blocks(T)), dim3(kThreads), 0, s, per_tile_bins, T, kmax,
+                       seg_base, ticket, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32_dyn(uint32_t* p, uint32_t v, const uint32_t* n_dev, int mult, int64_t max_n,
+                               hipStream_t s) {
+    if (max_n <= 0) return hipSuccess;
+    int64_t grid = (max_n + 255) / 256;
+    if (grid > 4096) grid = 4096;
+    hipLaunchKernelGGL(fill_u32_dyn_kernel, dim3((unsigned)grid), dim3(256), 0, s, p, v, n_dev, mult);
     return hipGetLastError();
 }
 

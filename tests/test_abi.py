@@ -62,9 +62,13 @@ def test_project_argument_errors():
     c.zfar = 1.0
     st, msg = status_of(lib.tgs_project, ctypes.byref(g), ctypes.byref(c), ctypes.byref(p), ctypes.byref(out), None)
     assert st == L.TGS_ERR_INVALID_ARG and "znear" in msg
-    p8 = tg.Params(tile_size=8).c()
-    st, msg = status_of(lib.tgs_project, ctypes.byref(g), ctypes.byref(cam()), ctypes.byref(p8), ctypes.byref(out), None)
-    assert st == L.TGS_ERR_UNSUPPORTED
+    for bad_p in (tg.Params(tile_size=12), tg.Params(tile_size=8, raster="plain"), tg.Params(tile_size=32, packed=1)):
+        st, msg = status_of(lib.tgs_project, ctypes.byref(g), ctypes.byref(cam()), ctypes.byref(bad_p.c()),
+                            ctypes.byref(out), None)
+        assert st == L.TGS_ERR_UNSUPPORTED and "tile_size" in msg
+    for ts in (8, 16, 32):
+        assert lib.tgs_bin_workspace_size(100, 1000, ctypes.byref(cam()), ctypes.byref(tg.Params(tile_size=ts).c()),
+                                          L.ORDER_BINNED) > 0
 
 
 def test_bin_workspace_and_argument_errors():

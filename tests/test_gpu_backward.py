@@ -58,6 +58,7 @@ def upstream(W, H, mask, seed):
 
 
 def gpu_raster_backward(splats, info, cam, order, d_img, d_alpha, bg, params=None):
+    """Bins and runs tgs_rasterize_backward; returns the gradient lines."""
     r = tg.Renderer(cam, params or tg.Params(), device=dev())
     s = torch.as_tensor(splats).to(dev())
     i = torch.as_tensor(np.ascontiguousarray(info).view(np.int32)).to(dev())
@@ -103,6 +104,24 @@ def test_raster_backward_matches_oracle(seed, W, H, density, sigma):
     # same per-pixel contributions in both orders; only the order of the
     # float atomic sums can differ
     assert grad_err(outs["global"][:, :9], outs["binned"][:, :9]) <= 1e-4
+
+
+@pytest.mark.parametrize("ts", [8, 32])
+def test_raster_backward_tile_sizes(ts):
+    W, H = 100, 70
+    n = W * H // 6
+    splats, info = scenes.random_splats(n, W, H, tile_size=ts, seed=20 + ts, hidden_fraction=0.05)
+    cam = cam_for(W, H)
+    proj = oracle.splats_to_proj(splats, info)
+    fwd = oracle.render(proj, W, H, tile_size=ts)
+    mask = (fwd["flags"] & AMBIG) == 0
+    d_img, d_alpha = upstream(W, H, mask, ts)
+    ref = oracle.composite_adjoint(proj, W, H, tile_size=ts, d_img=d_img, d_alpha=d_alpha)
+    for order in ("global", "binned"):
+        g = gpu_raster_backward(splats, info, cam, order, d_img, d_alpha, (0.0, 0.0, 0.0),
+                                tg.Params(tile_size=ts, num_bins=16))
+        e = [grad_err(g[:, k], ref["d_proj"][:, k]) for k in range(9)]
+        assert max(e) <= GRAD_TOL, (ts, order, e)
 
 
 def test_raster_backward_without_alpha_gradient_and_repeat():

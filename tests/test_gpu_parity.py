@@ -261,7 +261,7 @@ def test_invalid_arguments_raise():
     cam = cam_for(32, 32)
     splats, info = scenes.random_splats(10, 32, 32, seed=0)
     with pytest.raises(tg.TileGSError):
-        tg.Renderer(cam, tg.Params(tile_size=8), device=dev()).bin(
+        tg.Renderer(cam, tg.Params(tile_size=12), device=dev()).bin(
             torch.as_tensor(splats).to(dev()), torch.as_tensor(info.view(np.int32)).to(dev()))
 
 
@@ -330,3 +330,109 @@ def check_block_masks(masks, sp, tiles, W, H, tiles_x=None):
                 assert bit == 1, (i, w)
             if not blk.any():
                 assert bit == 0, (i, w)
+
+
+@pytest.mark.parametrize("ts", [8, 32])
+def test_tile_sizes(ts):
+    # 8- and 32-pixel tiles (WAVE raster, gather by id): projection rects in
+    # those tile units, the schedule bit-exact against the oracle on the same
+    # tile grid, both orders bitwise equal, and images within rounding of the
+    # 16-pixel path (the per-pixel sequence of composited entries does not
+    # depend on the tile size; the tile-relative mean's rounding does)
+    g, cam = scenes.small_forward(seed=1, n=3000)
+    W, H = cam["width"], cam["height"]
+    ref_p = oracle.project(g, cam, tile_size=ts)
+    gd = tg.to_device(g, dev())
+    p = tg.Params(tile_size=ts, num_bins=32)
+    splats, info = tg.project(gd, cam, p)
+    torch.cuda.synchronize()
+    depth, rect = decode_info(to_np(info))
+    vis_ref = (ref_p["flags"] & oracle.VISIBLE) > 0
+    amb = (ref_p["flags"] & (oracle.AMBIG_RECT | oracle.AMBIG_VIS)) > 0
+    ok = vis_ref & ~amb
+    assert np.array_equal(rect[ok], ref_p["rect"][ok].astype(np.int64))
+    tx, ty = (W + ts - 1) // ts, (H + ts - 1) // ts
+    ref_s = oracle.schedule(depth, rect, tx, ty, K=32, znear=cam["znear"], zfar=cam["zfar"])
+    r = tg.Renderer(cam, p, device=dev())
+    outs = {}
+    for order in ("global", "binned"):
+        b = r.bin(splats, info, order)
+        M = ref_s["M"]
+        assert b.num_entries == M
+        if order == "binned":
+            assert np.array_equal(to_np(b.offsets).view(np.uint32), ref_s["bin_offsets"])
+            assert np.array_equal(to_np(b.pairs)[:M].view(np.uint64), ref_s["stream"])
+        else:
+            assert np.array_equal(to_np(b.offsets).view(np.uint32), ref_s["tile_offsets"])
+        out = r.rasterize(splats, info, b, counts=True)
+        torch.cuda.synchronize()
+        outs[order] = {k: to_np(v) for k, v in out.items()}
+    ref = oracle.render(oracle.project(g, cam), W, H)
+    e_rgb, e_a, _ = image_compare(outs["binned"]["rgb"], outs["binned"]["alpha"], ref)
+    assert e_rgb <= TOL and e_a <= TOL
+    base = tg.render(gd, cam, order="binned")
+    torch.cuda.synchronize()
+    for key in ("rgb", "alpha", "last", "n_contrib"):
+        assert np.array_equal(outs["global"][key], outs["binned"][key]), key
+    assert np.abs(outs["binned"]["rgb"] - to_np(base["rgb"])).max() <= 1e-5
+
+
+def effective_bins(kt, kmax):
+    """Per-tile bin counts as the library applies them: clamped to
+    1..kmax and rounded down to a power of two."""
+    k = np.clip(np.asarray(kt, np.int64), 1, kmax)
+    return (2 ** np.floor(np.log2(k))).astype(np.int32)
+
+
+@pytest.mark.parametrize("ts", [16, 8])
+def test_per_tile_bins_bit_exact(ts):
+    # variable bin counts per tile (segments numbered by a prefix sum):
+    # seg_base, bin offsets and the repaired stream bit-exact against the
+    # oracle, images bitwise equal to the uniform-K path, backward unchanged
+    n, W, H = 6000, 203, 130
+    splats, info = scenes.random_splats(n, W, H, tile_size=ts, seed=31, tie_fraction=0.1, hidden_fraction=0.05)
+    cam = cam_for(W, H)
+    tx, ty = (W + ts - 1) // ts, (H + ts - 1) // ts
+    T = tx * ty
+    rng = np.random.default_rng(ts)
+    kt = rng.choice([0, 1, 2, 3, 5, 16, 64, 100, 256, 1000], size=T).astype(np.int32)
+    kmax = 256
+    keff = effective_bins(kt, kmax)
+    depth, rect = scenes.info_depth(info), scenes.info_rects(info)
+    ref = oracle.schedule_tiles(depth, rect, tx, ty, keff, znear=cam["znear"], zfar=cam["zfar"])
+    s = torch.as_tensor(splats).to(dev())
+    i = torch.as_tensor(info.view(np.int32)).to(dev())
+    p = tg.Params(tile_size=ts, num_bins=kmax, per_tile_bins=torch.as_tensor(kt).to(dev()))
+    r = tg.Renderer(cam, p, device=dev())
+    b = r.bin(s, i, "binned")
+    torch.cuda.synchronize()
+    M = ref["M"]
+    S = int(ref["seg_base"][-1])
+    assert b.num_entries == M
+    assert np.array_equal(to_np(b.seg_base).view(np.uint32), ref["seg_base"])
+    assert np.array_equal(to_np(b.offsets).view(np.uint32)[:S + 1], ref["bin_offsets"])
+    assert np.array_equal(to_np(b.pairs)[:M].view(np.uint64), ref["stream"])
+    out = r.rasterize(s, i, b, bg=(0.2, 0.1, 0.0), counts=True)
+    r_u = tg.Renderer(cam, tg.Params(tile_size=ts, num_bins=32), device=dev())
+    b_u = r_u.bin(s, i, "binned")
+    out_u = r_u.rasterize(s, i, b_u, bg=(0.2, 0.1, 0.0), counts=True)
+    torch.cuda.synchronize()
+    for k in ("rgb", "alpha", "last", "n_contrib"):
+        assert torch.equal(out[k], out_u[k]), k
+    # a second call with other counts reuses the buffers
+    kt2 = np.full(T, 4, np.int32)
+    r.set_per_tile_bins(torch.as_tensor(kt2).to(dev()))
+    b2 = r.bin(s, i, "binned")
+    ref2 = oracle.schedule_tiles(depth, rect, tx, ty, kt2, znear=cam["znear"], zfar=cam["zfar"])
+    torch.cuda.synchronize()
+    assert np.array_equal(to_np(b2.offsets).view(np.uint32)[:4 * T + 1], ref2["bin_offsets"])
+    assert np.array_equal(to_np(b2.pairs)[:M].view(np.uint64), ref2["stream"])
+    # backward over the per-tile stream equals the uniform one up to the
+    # order of the float atomic sums
+    d = torch.as_tensor(np.random.default_rng(1).normal(size=(H, W, 3)).astype(np.float32)).to(dev())
+    g1 = r.rasterize_backward(s, i, b2, d, None)
+    g2 = r_u.rasterize_backward(s, i, b_u, d, None)
+    torch.cuda.synchronize()
+    a1, a2 = to_np(g1).astype(np.float64), to_np(g2).astype(np.float64)
+    scale = np.abs(a2).max(axis=0, keepdims=True) + 1e-30
+    assert np.all(np.abs(a1 - a2) <= 1e-4 * (np.abs(a2) + 1e-3 * scale))
