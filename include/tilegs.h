@@ -253,6 +253,26 @@ typedef struct {
 TGS_API tgs_status tgs_project_backward(const tgs_gaussians* gaussians, const tgs_camera* camera,
                                 const float* d_splats_dev, tgs_gaussian_grads* grads, void* stream);
 
+/* Batched rendering: up to TGS_MAX_VIEWS cameras (views), each with its own
+   projected splats, tgs_bin stream (any order, tile size and bin counts of
+   its params), composited in ONE persistent launch. Work items are (view,
+   tile, 8x8 block), ordered heaviest tile first over all views and pulled
+   by wavefronts from device-scope cursors until none is left; each item is
+   the WAVE raster's block walk, so every view's rgb / alpha / last are
+   bit-identical to tgs_rasterize with that view's arguments. All host
+   arrays have num_views elements; rgb / alpha / last are host arrays of
+   device pointers. The call enqueues a fill, two small ordering launches
+   and the persistent launch on `stream` and never synchronises, so it can
+   be captured in a HIP graph (the view descriptors travel in the kernel
+   arguments). Workspace: tgs_batch_workspace_size bytes, caller-owned. */
+#define TGS_MAX_VIEWS 16
+TGS_API size_t tgs_batch_workspace_size(int32_t num_views, const tgs_camera* cameras, const tgs_params* params);
+TGS_API tgs_status tgs_rasterize_batch(int32_t num_views, const tgs_projected* projected, const tgs_binned* binned,
+                               const tgs_camera* cameras, const tgs_params* params, const int32_t* orders,
+                               const float* bg, float* const* rgb_dev, float* const* alpha_dev,
+                               int32_t* const* last_dev, void* workspace_dev, size_t workspace_bytes,
+                               void* stream);
+
 /* Message for the last failing call on this thread ("" if none). */
 TGS_API const char* tgs_last_error(void);
 

@@ -5,5 +5,5 @@ The compute path is the HIP library ``libtilegs.so`` behind the C ABI in
 """
 from ._lib import (ORDER_BINNED, ORDER_GLOBAL, RASTER_PLAIN, RASTER_WAVE, TileGSError,  # noqa: F401
                    LIB_PATH, EXPORTS, lib)
-from .api import (Binned, Params, Renderer, camera_struct, project, project_backward, render,  # noqa: F401
-                  render_differentiable, to_device)
+from .api import (BatchRenderer, Binned, Params, Renderer, camera_struct, project, project_backward,  # noqa: F401
+                  render, render_differentiable, to_device)

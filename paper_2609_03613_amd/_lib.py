@@ -17,7 +17,9 @@ ORDER_GLOBAL, ORDER_BINNED = 0, 1
 RASTER_PLAIN, RASTER_WAVE = 0, 1
 
 EXPORTS = ("tgs_default_params", "tgs_project", "tgs_bin_workspace_size", "tgs_bin", "tgs_rasterize",
-           "tgs_rasterize_backward", "tgs_project_backward", "tgs_last_error")
+           "tgs_rasterize_backward", "tgs_project_backward", "tgs_batch_workspace_size", "tgs_rasterize_batch",
+           "tgs_last_error")
+MAX_VIEWS = 16
 GRAD_WORDS = 12
 
 _c_p = ctypes.c_void_p
@@ -89,6 +91,11 @@ def lib():
         L.tgs_rasterize_backward.restype = ctypes.c_int
         L.tgs_project_backward.argtypes = [P(Gaussians), P(Camera), _c_p, P(GaussianGrads), _c_p]
         L.tgs_project_backward.restype = ctypes.c_int
+        L.tgs_batch_workspace_size.argtypes = [ctypes.c_int32, _c_p, _c_p]
+        L.tgs_batch_workspace_size.restype = ctypes.c_size_t
+        L.tgs_rasterize_batch.argtypes = [ctypes.c_int32, _c_p, _c_p, _c_p, _c_p, _c_p, P(ctypes.c_float), _c_p, _c_p,
+                                          _c_p, _c_p, ctypes.c_size_t, _c_p]
+        L.tgs_rasterize_batch.restype = ctypes.c_int
         L.tgs_last_error.argtypes = []
         L.tgs_last_error.restype = ctypes.c_char_p
         _lib = L

@@ -70,13 +70,17 @@ def to_device(g, device="cuda"):
     return out
 
 
-def project(g, cam, params=None):
-    """tgs_project: returns (splats [n, 16] float32, info [n, 4] int32)."""
+def project(g, cam, params=None, out=None):
+    """tgs_project: returns (splats [n, 16] float32, info [n, 4] int32),
+    written into ``out`` = (splats, info) when given."""
     params = params or Params()
     n = int(g["means"].shape[0])
     dev = g["means"].device
-    splats = torch.empty((n, 16), dtype=torch.float32, device=dev)
-    info = torch.empty((n, 4), dtype=torch.int32, device=dev)
+    if out is not None:
+        splats, info = out
+    else:
+        splats = torch.empty((n, 16), dtype=torch.float32, device=dev)
+        info = torch.empty((n, 4), dtype=torch.int32, device=dev)
     gs = L.Gaussians(_ptr(g["means"]).value, _ptr(g["log_scales"]).value, _ptr(g["quats"]).value,
                      _ptr(g["logits"]).value, _ptr(g["sh"]).value, n, int(g["sh_degree"]))
     pr = L.Projected(_ptr(splats).value, _ptr(info).value, n)
@@ -285,3 +289,94 @@ def render_differentiable(renderer, g, order="binned", bg=(0.0, 0.0, 0.0)):
     means, log_scales, quats, logits and sh tensors."""
     return _RenderFn.apply(g["means"], g["log_scales"], g["quats"], g["logits"], g["sh"], renderer,
                            int(g["sh_degree"]), order, tuple(float(v) for v in bg))
+
+
+class BatchRenderer:
+    """Several cameras per frame: per-view tgs_project and tgs_bin (BINNED,
+    each view with its own params: tile size, bins), then one
+    tgs_rasterize_batch persistent launch for all views. ``capture`` records
+    the whole frame in a HIP graph (torch.cuda.CUDAGraph) after an eager
+    frame has sized every buffer; ``replay`` launches it."""
+
+    def __init__(self, cams, params=None, device="cuda", bg=(0.0, 0.0, 0.0)):
+        if len(cams) > L.MAX_VIEWS:
+            raise ValueError(f"at most {L.MAX_VIEWS} views per batch")
+        params = params or [Params() for _ in cams]
+        self.views = [Renderer(c, p, device=device) for c, p in zip(cams, params)]
+        self.device = device
+        self.bg = tuple(float(v) for v in bg)
+        self.outs = []
+        for c in cams:
+            H, W = int(c["height"]), int(c["width"])
+            self.outs.append({"rgb": torch.empty((H, W, 3), dtype=torch.float32, device=device),
+                              "alpha": torch.empty((H, W), dtype=torch.float32, device=device),
+                              "last": torch.empty((H, W), dtype=torch.int32, device=device)})
+        nv = len(cams)
+        self._ccams = (L.Camera * nv)(*[r.ccam for r in self.views])
+        self._cparams = (L.Params * nv)(*[r.cparams for r in self.views])
+        need = L.lib().tgs_batch_workspace_size(nv, ctypes.cast(self._ccams, ctypes.c_void_p),
+                                                ctypes.cast(self._cparams, ctypes.c_void_p))
+        if need == 0:
+            raise L.TileGSError(L.TGS_ERR_INVALID_ARG, "invalid batch cameras or params")
+        self.ws = torch.empty(need, dtype=torch.uint8, device=device)
+        self.proj = None
+        self.binned = None
+        self.graph = None
+
+    def _alloc_proj(self, n):
+        if self.proj is None or int(self.proj[0][0].shape[0]) != n:
+            self.proj = [(torch.empty((n, 16), dtype=torch.float32, device=self.device),
+                          torch.empty((n, 4), dtype=torch.int32, device=self.device)) for _ in self.views]
+
+    def rasterize(self, projs, binned):
+        """tgs_rasterize_batch over (splats, info) and Binned per view."""
+        nv = len(self.views)
+        prs = (L.Projected * nv)(*[L.Projected(_ptr(s).value, _ptr(i).value, int(s.shape[0])) for s, i in projs])
+        bs = (L.Binned * nv)(*[b.c() for b in binned])
+        orders = (ctypes.c_int32 * nv)(*[b.order for b in binned])
+        self._cparams = (L.Params * nv)(*[r.cparams for r in self.views])
+        bgc = (ctypes.c_float * 3)(*self.bg)
+        ptrs = lambda k: (ctypes.c_void_p * nv)(*[o[k].data_ptr() for o in self.outs])
+        self._keep = (prs, bs, orders, bgc)
+        L.check(L.lib().tgs_rasterize_batch(nv, ctypes.cast(prs, ctypes.c_void_p), ctypes.cast(bs, ctypes.c_void_p),
+                                            ctypes.cast(self._ccams, ctypes.c_void_p),
+                                            ctypes.cast(self._cparams, ctypes.c_void_p),
+                                            ctypes.cast(orders, ctypes.c_void_p), bgc, ptrs("rgb"), ptrs("alpha"),
+                                            ptrs("last"), _ptr(self.ws), self.ws.numel(), _stream()))
+        return self.outs
+
+    def frame(self, g, sync=False):
+        """One eager frame: project and bin every view, one batched raster.
+        With sync, entry counts are read back and buffers grown as needed
+        (do this once before capture)."""
+        self._alloc_proj(int(g["means"].shape[0]))
+        binned = []
+        for r, (s, i) in zip(self.views, self.proj):
+            project(g, r.cam, r.params, out=(s, i))
+            binned.append(r.bin(s, i, "binned", sync=sync))
+        self.binned = binned
+        return self.rasterize(self.proj, binned)
+
+    def overflowed(self):
+        return any(int(b.counters[2].item()) != 0 for b in self.binned)
+
+    def capture(self, g):
+        """Sizes the buffers with an eager frame and records one frame in a
+        HIP graph (projection, binning and the batched raster of every
+        view)."""
+        self.frame(g, sync=True)
+        torch.cuda.synchronize()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            self.frame(g, sync=False)  # warm-up on the capture stream
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self.frame(g, sync=False)
+        return self.graph
+
+    def replay(self):
+        self.graph.replay()
+        return self.outs

@@ -413,4 +413,88 @@ tgs_status tgs_project_backward(const tgs_gaussians* g, const tgs_camera* cam, c
     return TGS_OK;
 }
 
+size_t tgs_batch_workspace_size(int32_t num_views, const tgs_camera* cams, const tgs_params* params) {
+    if (num_views < 1 || num_views > kMaxViews || !cams || !params) return 0;
+    int64_t blocks = 0;
+    for (int v = 0; v < num_views; ++v) {
+        const int ts = params[v].tile_size;
+        if (ts != 8 && ts != 16 && ts != 32) return 0;
+        if (cams[v].width < 1 || cams[v].height < 1) return 0;
+        blocks += tiles_of(&cams[v], ts) * (int64_t)((ts / 8) * (ts / 8));
+    }
+    return sizeof(uint32_t) * (size_t)(256 + 8 * ((blocks + 7) / 8));
+}
+
+tgs_status tgs_rasterize_batch(int32_t num_views, const tgs_projected* pr, const tgs_binned* b,
+                               const tgs_camera* cams, const tgs_params* params, const int32_t* orders,
+                               const float* bg, float* const* rgb, float* const* alpha, int32_t* const* last,
+                               void* ws, size_t ws_bytes, void* stream) {
+    g_err.clear();
+    if (num_views < 1 || num_views > kMaxViews) return fail(TGS_ERR_INVALID_ARG, "num_views %d outside 1..%d", num_views, kMaxViews);
+    if (!pr || !b || !cams || !params || !orders || !bg || !rgb || !alpha || !last)
+        return fail(TGS_ERR_INVALID_ARG, "an argument array is NULL");
+    BatchArgs a{};
+    a.nv = num_views;
+    for (int i = 0; i < 3; ++i) a.bg[i] = bg[i];
+    int64_t tiles = 0, blocks = 0;
+    for (int v = 0; v < num_views; ++v) {
+        tgs_status st = check_projected(&pr[v]);
+        if (st) return st;
+        if ((st = check_camera(&cams[v]))) return st;
+        if ((st = check_params(&params[v]))) return st;
+        if (orders[v] != TGS_ORDER_GLOBAL && orders[v] != TGS_ORDER_BINNED)
+            return fail(TGS_ERR_INVALID_ARG, "view %d: unknown order %d", v, orders[v]);
+        if (!b[v].offsets_dev || !b[v].counters_dev) return fail(TGS_ERR_INVALID_ARG, "view %d: binned buffers are NULL", v);
+        if (!rgb[v] || !alpha[v] || !last[v]) return fail(TGS_ERR_INVALID_ARG, "view %d: an output pointer is NULL", v);
+        if (pr[v].n > 0 && !pr[v].splats_dev) return fail(TGS_ERR_INVALID_ARG, "view %d: splats is NULL", v);
+        BatchView& d = a.v[v];
+        const int ts = params[v].tile_size;
+        d.splats = pr[v].splats_dev;
+        d.offsets = b[v].offsets_dev;
+        d.counters = b[v].counters_dev;
+        if (orders[v] == TGS_ORDER_GLOBAL) {
+            d.stride = 1;
+            d.vals = b[v].vals_dev;
+            if (!d.vals && b[v].capacity > 0) return fail(TGS_ERR_INVALID_ARG, "view %d: vals is NULL", v);
+        } else {
+            d.stride = params[v].num_bins;
+            d.seg_base = params[v].per_tile_bins_dev ? b[v].seg_base_dev : nullptr;
+            if (params[v].per_tile_bins_dev && !d.seg_base)
+                return fail(TGS_ERR_INVALID_ARG, "view %d: seg_base is NULL with per_tile_bins", v);
+            d.pairs = b[v].pairs_dev;
+            if (!d.pairs && b[v].capacity > 0) return fail(TGS_ERR_INVALID_ARG, "view %d: pairs is NULL", v);
+        }
+        d.width = cams[v].width;
+        d.height = cams[v].height;
+        d.tile = ts;
+        d.tiles_x = div_up(cams[v].width, ts);
+        d.tiles_y = div_up(cams[v].height, ts);
+        d.rgb = rgb[v];
+        d.alpha = alpha[v];
+        d.last = last[v];
+        a.tile_base[v] = (uint32_t)tiles;
+        tiles += (int64_t)d.tiles_x * d.tiles_y;
+        blocks += (int64_t)d.tiles_x * d.tiles_y * ((ts / 8) * (ts / 8));
+    }
+    if (tiles >= ((int64_t)1 << 31) || blocks >= ((int64_t)1 << 32)) return fail(TGS_ERR_INVALID_ARG, "too many tiles");
+    a.tile_base[num_views] = (uint32_t)tiles;
+    const size_t need = tgs_batch_workspace_size(num_views, cams, params);
+    if (!ws || ws_bytes < need) return fail(TGS_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+    static int grid = 0;
+    if (grid == 0) {
+        int dev = 0, cus = 0, occ = 0;
+        TGS_HIP(hipGetDevice(&dev), "device");
+        TGS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "device attributes");
+        occ = 8;
+        grid = cus * occ;
+    }
+    const int64_t want = (blocks + 3) / 4;
+    const int g = (int)(want < grid ? want : grid);
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t* ctl = (uint32_t*)ws;
+    TGS_HIP(launch_fill_u32(ctl, 0u, 256, s), "clear batch control words");
+    TGS_HIP(launch_raster_batch(a, ctl, ctl + 256, blocks, g > 0 ? g : 1, s), "batched raster");
+    return TGS_OK;
+}
+
 }  // extern "C"

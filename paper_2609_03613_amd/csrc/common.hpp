@@ -326,6 +326,31 @@ struct RasterArgs {
 hipError_t launch_raster_plain(const RasterArgs& a, hipStream_t s);
 hipError_t launch_raster_wave(const RasterArgs& a, hipStream_t s);
 
+// Batched persistent raster: up to kMaxViews views in one launch (passed by
+// value as the kernel argument, so a captured graph keeps them).
+constexpr int kMaxViews = 16;
+struct BatchView {
+    const float* splats;
+    const uint32_t* offsets;
+    const uint32_t* seg_base;
+    const uint32_t* vals;
+    const uint64_t* pairs;
+    const int64_t* counters;
+    float* rgb;
+    float* alpha;
+    int32_t* last;
+    int stride, width, height, tile, tiles_x, tiles_y;
+};
+struct BatchArgs {
+    BatchView v[kMaxViews];
+    uint32_t tile_base[kMaxViews + 1];  // first flattened tile of each view; [nv] = all tiles
+    int nv;
+    float bg[3];
+};
+// ctl: 256 zeroed words; work: 8 * ceil(total_blocks / 8) words.
+hipError_t launch_raster_batch(const BatchArgs& b, uint32_t* ctl, uint32_t* work, int64_t total_blocks, int grid,
+                               hipStream_t s);
+
 // Gradient lines: 12 floats per Gaussian (dL/d mean_x, mean_y, conic a, b,
 // c, opacity, r, g, b, then 3 zero words).
 constexpr int kGradWords = 12;

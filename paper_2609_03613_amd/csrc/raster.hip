@@ -34,28 +34,6 @@ namespace {
 
 using namespace raster;
 
-__device__ __forceinline__ void write_pixel(const RasterArgs& A, int x, int y, const Pix& p, bool bad) {
-    const int64_t i = (int64_t)y * A.width + x;
-    if (bad) {
-        const float nan = __builtin_nanf("");
-        A.rgb[3 * i] = nan; A.rgb[3 * i + 1] = nan; A.rgb[3 * i + 2] = nan;
-        A.alpha[i] = nan;
-        A.last[i] = -1;
-        if (A.n_contrib) A.n_contrib[i] = 0;
-        if (A.n_visit) A.n_visit[i] = 0;
-        if (A.n_support) A.n_support[i] = 0;
-        return;
-    }
-    A.rgb[3 * i] = p.r + p.T * A.bg[0];
-    A.rgb[3 * i + 1] = p.g + p.T * A.bg[1];
-    A.rgb[3 * i + 2] = p.b + p.T * A.bg[2];
-    A.alpha[i] = 1.0f - p.T;
-    A.last[i] = p.last;
-    if (A.n_contrib) A.n_contrib[i] = p.ncon;
-    if (A.n_visit) A.n_visit[i] = p.nvis;
-    if (A.n_support) A.n_support[i] = p.nsup;
-}
-
 // ---------------------------------------------------------------------------
 
 template <int SRC, bool COUNT>

@@ -1,6 +1,6 @@
-// Per-pixel compositing step and entry staging shared by the forward
-// rasters and the backward raster (device code, included by raster.hip and
-// raster_bwd.hip only).
+// Per-pixel compositing step, entry staging and the 8x8-block walk shared by
+// the forward rasters, the batched persistent raster and the backward raster
+// (device code, included by the raster sources only).
 #pragma once
 
 #include "common.hpp"
@@ -51,6 +51,28 @@ __device__ __forceinline__ void blend(Pix& p, float px, float py, const Staged& 
     p.b = fmaf(wt, s.c.x, p.b);
     p.T = comp ? test : p.T;
     p.last = comp ? __float_as_int(s.c.y) : p.last;
+}
+
+__device__ __forceinline__ void write_pixel(const RasterArgs& A, int x, int y, const Pix& p, bool bad) {
+    const int64_t i = (int64_t)y * A.width + x;
+    if (bad) {
+        const float nan = __builtin_nanf("");
+        A.rgb[3 * i] = nan; A.rgb[3 * i + 1] = nan; A.rgb[3 * i + 2] = nan;
+        A.alpha[i] = nan;
+        A.last[i] = -1;
+        if (A.n_contrib) A.n_contrib[i] = 0;
+        if (A.n_visit) A.n_visit[i] = 0;
+        if (A.n_support) A.n_support[i] = 0;
+        return;
+    }
+    A.rgb[3 * i] = p.r + p.T * A.bg[0];
+    A.rgb[3 * i + 1] = p.g + p.T * A.bg[1];
+    A.rgb[3 * i + 2] = p.b + p.T * A.bg[2];
+    A.alpha[i] = 1.0f - p.T;
+    A.last[i] = p.last;
+    if (A.n_contrib) A.n_contrib[i] = p.ncon;
+    if (A.n_visit) A.n_visit[i] = p.nvis;
+    if (A.n_support) A.n_support[i] = p.nsup;
 }
 
 enum Src { SRC_VALS = 0, SRC_PAIRS = 1, SRC_PACKED = 2 };
