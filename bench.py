@@ -64,11 +64,12 @@ def parse():
     ap.add_argument("--config", default="1080p", choices=["1080p", "small"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--mode", default="frame", choices=["frame", "kernels", "train"],
+    ap.add_argument("--mode", default="frame", choices=["frame", "kernels", "train", "batch"],
                     help="kernels: only launch the product and comparator raster kernels and a "
                          "256 MiB device copy (for profiler counter runs); train: only the training "
                          "step (forward + backward) on the 500k-Gaussian 1297x840 scene")
     ap.add_argument("--no-train", action="store_true", help="skip the training-step measurement")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched multi-camera measurement")
     return ap.parse_args()
 
 
@@ -164,6 +165,69 @@ def train_step(args):
             "forward_ms": med["project"] + med["bin+repair"] + med["raster"]}
 
 
+def batched(args):
+    """16 cameras of uneven resolution on a ring around 3M Gaussians (SH0):
+    per-view tile size and bins from the autotuner, the whole multi-view
+    frame (16 projections, 16 binnings, one persistent raster launch)
+    captured in a HIP graph and replayed. Beside it: the same frame launched
+    eagerly, and the per-view default path (16 px tiles, K = 64, one raster
+    launch per view)."""
+    import torch
+    import paper_2609_03613_amd as tg
+    from paper_2609_03613_amd import autotune
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    g, cams = scenes.batched_scene(seed=0)
+    gd = tg.to_device(g, dev)
+    tuned, tune_recs = [], []
+    for c in cams:
+        p, rec = autotune.tune(gd, c, cache_path=None, reps=3)
+        tuned.append(p)
+        tune_recs.append({"tile_size": p.tile_size, "num_bins": p.num_bins, "ms": rec["ms"]})
+    br = tg.BatchRenderer(cams, tuned, device=dev)
+    br.capture(gd)
+    torch.cuda.synchronize()
+    entries = int(sum(br.entries))
+    pixels = int(sum(c["width"] * c["height"] for c in cams))
+
+    def timed(fn, k):
+        for _ in range(args.warmup):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(k):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k
+
+    graph_ms = timed(br.replay, args.steps)
+    assert not br.overflowed()
+    eager_ms = timed(lambda: br.frame(gd), args.steps)
+    # per-view default path, one raster launch per view
+    views = [tg.Renderer(c, tg.Params(), device=dev) for c in cams]
+    prep = []
+    for r in views:
+        s_, i_ = tg.project(gd, r.cam, r.params)
+        r.bin(s_, i_, "binned", sync=True)
+        prep.append((s_, i_))
+
+    def per_view():
+        for r, (s_, i_) in zip(views, prep):
+            tg.project(gd, r.cam, r.params, out=(s_, i_))
+            b = r.bin(s_, i_, "binned", sync=False)
+            r.rasterize(s_, i_, b)
+
+    default_ms = timed(per_view, args.steps)
+    return {"workload": "batched: 3M Gaussians (SH0) on 16 ring cameras, 640x360 .. 2560x1440",
+            "views": len(cams), "pixels": pixels, "entries": entries,
+            "graph_ms_per_batch": graph_ms, "eager_batched_ms_per_batch": eager_ms,
+            "per_view_default_ms_per_batch": default_ms,
+            "views_per_s": len(cams) / (graph_ms * 1e-3), "pairs_per_s": entries / (graph_ms * 1e-3),
+            "speedup_vs_per_view_default": default_ms / graph_ms, "tuned": tune_recs}
+
+
 def workload(name):
     if name == "1080p":
         g, cam = scenes.scene_1080p(seed=0)
@@ -204,6 +268,9 @@ def main():
         return kernels_only(args)
     if args.mode == "train":
         print(json.dumps({"mode": "train", **train_step(args)}), flush=True)
+        return
+    if args.mode == "batch":
+        print(json.dumps({"mode": "batch", **batched(args)}), flush=True)
         return
     import torch
     import paper_2609_03613_amd as tg
@@ -372,6 +439,8 @@ def main():
     }
     if not args.no_train:
         result["training_step"] = train_step(args)
+    if not args.no_batch:
+        result["batched"] = batched(args)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(g, cam, args.cpu_seconds)
     print(json.dumps(result), flush=True)

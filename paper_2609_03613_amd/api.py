@@ -321,6 +321,7 @@ class BatchRenderer:
         self.ws = torch.empty(need, dtype=torch.uint8, device=device)
         self.proj = None
         self.binned = None
+        self.entries = None
         self.graph = None
 
     def _alloc_proj(self, n):
@@ -355,6 +356,8 @@ class BatchRenderer:
             project(g, r.cam, r.params, out=(s, i))
             binned.append(r.bin(s, i, "binned", sync=sync))
         self.binned = binned
+        if sync:
+            self.entries = [b.num_entries for b in binned]
         return self.rasterize(self.proj, binned)
 
     def overflowed(self):

@@ -1,0 +1,107 @@
+"""Per-camera tile-size / bin-count autotuner.
+
+For one camera and scene size it times the whole per-view frame (projection,
+binning with exact repair, WAVE raster) for every candidate (tile size in
+{8, 16, 32}) x (bins K in {16, 32, 64, 128}) with HIP events on the launch
+stream and keeps the fastest. The choice never changes the image beyond
+rounding (exact repair keeps the global order; the tile size only moves the
+tile-relative origin of the staged means), so only time is compared.
+
+Results are cached in a JSON file keyed by (GPU architecture, W x H, power-
+of-two bucket of the Gaussian count); a cached entry is reused without
+timing. The cache is plain data and can be deleted at any time.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+
+import numpy as np
+import torch
+
+from .api import Params, Renderer, project
+
+TILE_SIZES = (8, 16, 32)
+BIN_COUNTS = (16, 32, 64, 128)
+CANDIDATES = tuple((ts, k) for ts in TILE_SIZES for k in BIN_COUNTS)
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "tilegs", "autotune.json")
+
+
+def cache_key(cam, n):
+    arch = torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName.split(":")[0]
+    bucket = int(round(math.log2(max(int(n), 1))))
+    return f"{arch}|{int(cam['width'])}x{int(cam['height'])}|n2^{bucket}"
+
+
+def measure(g, cam, tile_size, num_bins, reps=5, warmup=2):
+    """Median ms of one view's frame (project + bin + raster) with these
+    options, inputs resident."""
+    p = Params(tile_size=tile_size, num_bins=num_bins)
+    r = Renderer(cam, p, device=g["means"].device)
+    s, i = project(g, cam, p)
+    b = r.bin(s, i, "binned", sync=True)  # sizes the buffers
+    H, W = int(cam["height"]), int(cam["width"])
+    dev = g["means"].device
+    out = {"rgb": torch.empty((H, W, 3), dtype=torch.float32, device=dev),
+           "alpha": torch.empty((H, W), dtype=torch.float32, device=dev),
+           "last": torch.empty((H, W), dtype=torch.int32, device=dev)}
+    stream = torch.cuda.current_stream()
+
+    def once():
+        project(g, cam, p, out=(s, i))
+        bb = r.bin(s, i, "binned", sync=False)
+        r.rasterize(s, i, bb, out=out)
+
+    for _ in range(warmup):
+        once()
+    ms = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        once()
+        e1.record(stream)
+        e1.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    if int(b.counters[2].item()) != 0:
+        return float("inf"), b.num_entries
+    return float(np.median(ms)), b.num_entries
+
+
+def load_cache(path):
+    try:
+        with open(path) as f:
+            data = json.load(f)
+        return data if isinstance(data, dict) else {}
+    except (OSError, ValueError):
+        return {}
+
+
+def save_cache(path, data):
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def tune(g, cam, cache_path=DEFAULT_CACHE, candidates=CANDIDATES, reps=5, use_cache=True):
+    """Returns (Params, record) for this camera and scene; record holds the
+    per-candidate times (ms) and whether it came from the cache."""
+    key = cache_key(cam, int(g["means"].shape[0]))
+    cache = load_cache(cache_path) if cache_path else {}
+    hit = cache.get(key) if use_cache else None
+    valid = (isinstance(hit, dict) and hit.get("tile_size") in TILE_SIZES
+             and isinstance(hit.get("num_bins"), int) and 1 <= hit["num_bins"] <= 1024)
+    if valid:
+        return Params(tile_size=hit["tile_size"], num_bins=hit["num_bins"]), dict(hit, cached=True)
+    table = {}
+    for ts, k in candidates:
+        ms, m = measure(g, cam, ts, k, reps=reps)
+        table[f"{ts}x{k}"] = {"ms": ms, "entries": m}
+    best = min(candidates, key=lambda c: table[f"{c[0]}x{c[1]}"]["ms"])
+    rec = {"tile_size": best[0], "num_bins": best[1], "ms": table[f"{best[0]}x{best[1]}"]["ms"], "table": table}
+    if cache_path:
+        cache[key] = rec
+        save_cache(cache_path, cache)
+    return Params(tile_size=best[0], num_bins=best[1]), dict(rec, cached=False)

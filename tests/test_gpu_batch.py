@@ -110,3 +110,23 @@ def test_batch_argument_errors():
         tg.BatchRenderer([cam] * 17, device=dev())
     with pytest.raises(tg.TileGSError):
         tg.BatchRenderer([cam], [tg.Params(tile_size=12)], device=dev())
+
+
+def test_autotuner_picks_valid_schedule_and_caches(tmp_path):
+    from paper_2609_03613_amd import autotune
+    gnp, _ = scenes.batched_scene(seed=4, n=20000)
+    cam = small_views(1, scale=0.5, seed=4)[0]
+    g = tg.to_device(gnp, dev())
+    path = str(tmp_path / "tune.json")
+    cands = ((8, 16), (16, 64), (32, 32))
+    p, rec = autotune.tune(g, cam, cache_path=path, candidates=cands, reps=2)
+    assert not rec["cached"]
+    assert (p.tile_size, p.num_bins) in cands
+    assert rec["ms"] == min(v["ms"] for v in rec["table"].values())
+    p2, rec2 = autotune.tune(g, cam, cache_path=path, candidates=cands, reps=2)
+    assert rec2["cached"] and (p2.tile_size, p2.num_bins) == (p.tile_size, p.num_bins)
+    # the tuned schedule renders the same image up to rounding
+    a = tg.render(g, cam, p)
+    b = tg.render(g, cam)
+    torch.cuda.synchronize()
+    assert (a["rgb"] - b["rgb"]).abs().max().item() <= 1e-5
