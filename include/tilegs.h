@@ -273,6 +273,45 @@ TGS_API tgs_status tgs_rasterize_batch(int32_t num_views, const tgs_projected* p
                                int32_t* const* last_dev, void* workspace_dev, size_t workspace_bytes,
                                void* stream);
 
+/* Learned bin-count proposal. The paper fixes K = 64 bins per tile (section
+   "Implementation details") and varies K per frame in its bin-count table;
+   this addition picks K_t per tile with a small network from the previous
+   frame's per-tile depth histogram and counts. Exact repair keeps every
+   image unchanged whatever it picks (only bin construction and repair time
+   move), and the fixed K remains the fallback.
+   Network: 16 features -> 64 -> 64 -> 8 (ReLU), fp32 parameters in one
+   array of TGS_MLP_PARAMS floats, row-major: W1 [16][64], b1 [64],
+   W2 [64][64], b2 [64], W3 [64][8], b3 [8]; choice k -> K_t = 2^(k+1).
+   Features [T][16] of tile t (K_t bins, lengths l_b, n_t = sum l_b, M
+   entries): log2(1+n_t); an 8-cell depth histogram / max(n_t,1) (bins
+   merged, or spread evenly when K_t < 8); log2(1+max l_b); non-empty bins
+   / K_t; log2(K_t)/8; entries in bins of 2 or more / max(n_t,1);
+   log2(1 + sum l_b^2 / max(n_t,1)); log2(1+M/T); log2(1+n_t) - log2(1+M/T). */
+#define TGS_MLP_PARAMS 5768
+
+/* Features [T][16] of the stream in `binned` (written by tgs_bin with the
+   same camera and params). */
+TGS_API tgs_status tgs_tile_features(const tgs_binned* binned, const tgs_camera* camera, const tgs_params* params,
+                             float* features_dev, void* stream);
+
+/* per_tile_bins [T] = 2^(argmax logit + 1) for each tile (first maximum on
+   ties); fallback_bins everywhere when a weight is not finite, and where a
+   logit is not finite. logits [T][8] are written when not NULL (not for a
+   non-finite weight vector). */
+TGS_API tgs_status tgs_propose_bins(const float* weights_dev, const float* features_dev, int64_t num_tiles,
+                            int32_t fallback_bins, int32_t* per_tile_bins_dev, float* logits_dev, void* stream);
+
+/* One training step on T tiles: loss L = (1/T) sum_t sum_k softmax(z_t)_k
+   regret[t][k] (regret: the cost of choice k above the tile's best, [T][8]),
+   its gradient g by backpropagation, then velocity = momentum * velocity +
+   g and weights -= lr * velocity. loss_dev (nullable) receives L. With lr
+   = momentum = 0 and a zero velocity, velocity returns g. Workspace:
+   tgs_mlp_train_workspace_size(T) bytes. */
+TGS_API size_t tgs_mlp_train_workspace_size(int64_t num_tiles);
+TGS_API tgs_status tgs_mlp_train_step(float* weights_dev, float* velocity_dev, const float* features_dev,
+                              const float* regret_dev, int64_t num_tiles, float lr, float momentum,
+                              void* workspace_dev, size_t workspace_bytes, float* loss_dev, void* stream);
+
 /* Message for the last failing call on this thread ("" if none). */
 TGS_API const char* tgs_last_error(void);
 

@@ -497,4 +497,54 @@ tgs_status tgs_rasterize_batch(int32_t num_views, const tgs_projected* pr, const
     return TGS_OK;
 }
 
+tgs_status tgs_tile_features(const tgs_binned* b, const tgs_camera* cam, const tgs_params* params, float* features,
+                             void* stream) {
+    g_err.clear();
+    tgs_status st = check_camera(cam);
+    if (st) return st;
+    if ((st = check_params(params))) return st;
+    if (!b || !b->offsets_dev || !b->counters_dev) return fail(TGS_ERR_INVALID_ARG, "binned buffers are NULL");
+    if (!features) return fail(TGS_ERR_INVALID_ARG, "features is NULL");
+    if (params->per_tile_bins_dev && !b->seg_base_dev)
+        return fail(TGS_ERR_INVALID_ARG, "seg_base is NULL with per_tile_bins");
+    const SegMap sm{params->per_tile_bins_dev ? b->seg_base_dev : nullptr, params->num_bins};
+    TGS_HIP(launch_tile_features(b->offsets_dev, sm, tiles_of(cam, params->tile_size), b->counters_dev, features,
+                                 (hipStream_t)stream),
+            "tile features");
+    return TGS_OK;
+}
+
+tgs_status tgs_propose_bins(const float* weights, const float* features, int64_t num_tiles, int32_t fallback_bins,
+                            int32_t* per_tile_bins, float* logits, void* stream) {
+    g_err.clear();
+    if (num_tiles < 0 || num_tiles >= ((int64_t)1 << 31)) return fail(TGS_ERR_INVALID_ARG, "num_tiles outside 0..2^31-1");
+    if (num_tiles > 0 && (!weights || !features || !per_tile_bins))
+        return fail(TGS_ERR_INVALID_ARG, "weights, features or per_tile_bins is NULL");
+    if (fallback_bins < 1 || fallback_bins > 1024) return fail(TGS_ERR_INVALID_ARG, "fallback_bins outside 1..1024");
+    TGS_HIP(launch_propose(weights, features, num_tiles, per_tile_bins, logits, fallback_bins, (hipStream_t)stream),
+            "bin proposal");
+    return TGS_OK;
+}
+
+size_t tgs_mlp_train_workspace_size(int64_t num_tiles) {
+    if (num_tiles < 0) return 0;
+    return sizeof(float) * mlp_train_workspace_floats(num_tiles);
+}
+
+tgs_status tgs_mlp_train_step(float* weights, float* velocity, const float* features, const float* regret,
+                              int64_t num_tiles, float lr, float momentum, void* ws, size_t ws_bytes, float* loss,
+                              void* stream) {
+    g_err.clear();
+    if (num_tiles < 0 || num_tiles >= ((int64_t)1 << 31)) return fail(TGS_ERR_INVALID_ARG, "num_tiles outside 0..2^31-1");
+    if (!weights || !velocity) return fail(TGS_ERR_INVALID_ARG, "weights or velocity is NULL");
+    if (num_tiles > 0 && (!features || !regret)) return fail(TGS_ERR_INVALID_ARG, "features or regret is NULL");
+    if (!isfinite(lr) || !isfinite(momentum)) return fail(TGS_ERR_INVALID_ARG, "lr and momentum must be finite");
+    const size_t need = tgs_mlp_train_workspace_size(num_tiles);
+    if (!ws || ws_bytes < need) return fail(TGS_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+    TGS_HIP(launch_mlp_train_step(weights, velocity, features, regret, num_tiles, lr, momentum, (float*)ws, loss,
+                                  (hipStream_t)stream),
+            "network training step");
+    return TGS_OK;
+}
+
 }  // extern "C"

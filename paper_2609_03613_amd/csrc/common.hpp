@@ -347,6 +347,16 @@ struct BatchArgs {
     int nv;
     float bg[3];
 };
+// Bin-count proposal network (see mlp.hip).
+int mlp_num_params();
+hipError_t launch_tile_features(const uint32_t* offsets, SegMap sm, int64_t T, const int64_t* counters, float* feat,
+                                hipStream_t s);
+hipError_t launch_propose(const float* w, const float* feat, int64_t T, int32_t* bins, float* logits, int fallback,
+                          hipStream_t s);
+size_t mlp_train_workspace_floats(int64_t T);
+hipError_t launch_mlp_train_step(float* w, float* v, const float* feat, const float* regret, int64_t T, float lr,
+                                 float mu, float* ws, float* loss, hipStream_t s);
+
 // ctl: 256 zeroed words; work: 8 * ceil(total_blocks / 8) words.
 hipError_t launch_raster_batch(const BatchArgs& b, uint32_t* ctl, uint32_t* work, int64_t total_blocks, int grid,
                                hipStream_t s);

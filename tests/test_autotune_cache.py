@@ -22,3 +22,21 @@ def test_corrupt_cache_is_ignored(tmp_path):
 def test_candidates_cover_tile_sizes_and_bins():
     assert set(ts for ts, _ in autotune.CANDIDATES) == {8, 16, 32}
     assert all(k & (k - 1) == 0 for _, k in autotune.CANDIDATES)
+
+
+def test_bin_weights_fallback(tmp_path):
+    import numpy as np
+    from paper_2609_03613_amd import bins
+    assert bins.load_weights(str(tmp_path / "missing.npz")) is None
+    p = str(tmp_path / "w.npz")
+    bins.save_weights(p, np.zeros(10))
+    assert bins.load_weights(p) is None  # wrong size
+    w = bins.init_weights()
+    w[3] = np.inf
+    bins.save_weights(p, w)
+    assert bins.load_weights(p) is None  # not finite
+    w = bins.init_weights()
+    bins.save_weights(p, w, note="x")
+    assert np.array_equal(bins.load_weights(p), w)
+    (tmp_path / "bad.npz").write_bytes(b"not a zip")
+    assert bins.load_weights(str(tmp_path / "bad.npz")) is None
