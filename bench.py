@@ -64,7 +64,7 @@ def parse():
     ap.add_argument("--config", default="1080p", choices=["1080p", "small"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--mode", default="frame", choices=["frame", "kernels", "train", "batch"],
+    ap.add_argument("--mode", default="frame", choices=["frame", "kernels", "train", "batch", "learned"],
                     help="kernels: only launch the product and comparator raster kernels and a "
                          "256 MiB device copy (for profiler counter runs); train: only the training "
                          "step (forward + backward) on the 500k-Gaussian 1297x840 scene")
@@ -228,6 +228,68 @@ def batched(args):
             "speedup_vs_per_view_default": default_ms / graph_ms, "tuned": tune_recs}
 
 
+def learned_bins(args):
+    """Steady-state bin construction + exact repair per frame on the
+    6M-Gaussian 3840x2160 scene (SH3): fixed K = 64 against the learned
+    per-tile counts (features of the previous frame's stream + network
+    proposal + binning, all timed), and whether the images are equal."""
+    import torch
+    import paper_2609_03613_amd as tg
+    from paper_2609_03613_amd import bins
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    g, cam = scenes.learned_eval_scene(seed=0)
+    gd = tg.to_device(g, dev)
+    del g
+    w = bins.load_weights()
+    fixed = tg.Renderer(cam, tg.Params(), device=dev)
+    s, i = tg.project(gd, cam, fixed.params)
+    bf = fixed.bin(s, i, "binned", sync=True)
+    lb = bins.LearnedBins(cam, weights=w, device=dev)
+    for _ in range(3):
+        lb.bin(s, i, sync=True)  # frame 1 fixed K, then learned; sizes the buffers
+
+    def timed(fn, k):
+        for _ in range(2):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(k):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k
+
+    steps = max(args.steps, 10)
+    # the per-tile machinery with 64 bins everywhere (its own overhead)
+    var = tg.Renderer(cam, tg.Params(num_bins=bins.MAX_BINS), device=dev)
+    var.set_per_tile_bins(torch.full((fixed.tiles,), 64, dtype=torch.int32, device=dev))
+    var.bin(s, i, "binned", sync=True)
+    var64_ms = timed(lambda: var.bin(s, i, "binned", sync=False), steps)
+    sweep = {}
+    for K in (8, 16, 32, 64, 128, 256):
+        rk = tg.Renderer(cam, tg.Params(num_bins=K), device=dev)
+        rk.bin(s, i, "binned", sync=True)
+        sweep[K] = timed(lambda: rk.bin(s, i, "binned", sync=False), steps)
+    fixed_ms = timed(lambda: fixed.bin(s, i, "binned", sync=False), steps)
+    learned_ms = timed(lambda: lb.bin(s, i, sync=False), steps)
+    fixed_ms2 = timed(lambda: fixed.bin(s, i, "binned", sync=False), steps)
+    r, b = lb.bin(s, i, sync=True)
+    out_l = r.rasterize(s, i, b)
+    out_f = fixed.rasterize(s, i, fixed.bin(s, i, "binned", sync=True))
+    torch.cuda.synchronize()
+    same = bool(torch.equal(out_l["rgb"], out_f["rgb"]) and torch.equal(out_l["last"], out_f["last"]))
+    kt = lb.kt.cpu().numpy()
+    ks, counts = np.unique(kt, return_counts=True)
+    fixed_ms = min(fixed_ms, fixed_ms2)
+    return {"workload": "6M Gaussians on 64 surfaces (SH3), 3840x2160, f=2200", "entries": bf.num_entries,
+            "weights": "trained" if w is not None else "missing (fixed K fallback)",
+            "fixed64_bin_ms": fixed_ms, "learned_bin_ms": learned_ms, "gain": fixed_ms / learned_ms,
+            "per_tile_machinery_all64_ms": var64_ms, "uniform_k_sweep_ms": sweep,
+            "images_equal": same, "per_tile_bins": {int(k): int(c) for k, c in zip(ks, counts)}}
+
+
 def workload(name):
     if name == "1080p":
         g, cam = scenes.scene_1080p(seed=0)
@@ -271,6 +333,9 @@ def main():
         return
     if args.mode == "batch":
         print(json.dumps({"mode": "batch", **batched(args)}), flush=True)
+        return
+    if args.mode == "learned":
+        print(json.dumps({"mode": "learned", **learned_bins(args)}), flush=True)
         return
     import torch
     import paper_2609_03613_amd as tg

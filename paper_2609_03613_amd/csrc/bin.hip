@@ -204,18 +204,14 @@ __device__ __forceinline__ uint32_t depth_frac(uint32_t L, uint32_t Lmin, uint32
     return (uint32_t)(((uint64_t)(L - Lmin) << 32) / (uint64_t)(Lmax - Lmin));
 }
 
-// Bin of a depth fraction in a tile with kt = 2^k bins.
-__device__ __forceinline__ uint32_t bin_of_frac(uint32_t frac, uint32_t kt) {
-    return kt <= 1u ? 0u : frac >> (32 - __builtin_ctz(kt));
-}
-
 // Segment of an entry of tile t whose Gaussian has bin value bv (the bin
-// for uniform K, the depth fraction for per-tile bin counts).
+// for uniform K; for per-tile bin counts the depth fraction, whose top
+// log2 K_t bits are the bin: shift = 32 - log2 K_t, 32 for one bin).
 template <bool VAR>
 __device__ __forceinline__ int64_t segment_of(const SegMap& sm, int64_t t, uint32_t bv) {
     if (!VAR) return t * sm.K + bv;
-    const uint32_t s0 = sm.seg_base[t], s1 = sm.seg_base[t + 1];
-    return (int64_t)s0 + bin_of_frac(bv, s1 - s0);
+    const uint2 ts = sm.tile_seg[t];
+    return (int64_t)ts.x + (int64_t)((uint64_t)bv >> ts.y);
 }
 
 template <bool WITH_BIN, bool VAR, class F>

@@ -86,7 +86,7 @@ inline size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Layout {
     size_t emit_off, vis_ids, zero, zero_words, status_emit_x, status_emit_y, status_bins, status_segs, count,
-        count_var, entry_rank, seg_lists, keys_in, vals_in, sort_tmp, sort_tmp_bytes, total;
+        count_var, tile_seg, entry_rank, seg_lists, keys_in, vals_in, sort_tmp, sort_tmp_bytes, total;
 };
 
 // Control words at the start of the zeroed region (uint32 offsets).
@@ -143,7 +143,10 @@ Layout layout(int64_t n, int64_t capacity, int64_t T, int K, int order, bool var
     if (order == TGS_ORDER_BINNED) {
         L.entry_rank = take(sizeof(uint32_t) * (size_t)capacity);
         L.seg_lists = take(sizeof(uint32_t) * (size_t)kBuckets * (size_t)nseg);
-        if (var) L.count_var = take(sizeof(uint32_t) * (size_t)kXcc * (size_t)nseg);
+        if (var) {
+            L.count_var = take(sizeof(uint32_t) * (size_t)kXcc * (size_t)nseg);
+            L.tile_seg = take(sizeof(uint2) * (size_t)T);
+        }
     } else {
         L.keys_in = take(sizeof(uint64_t) * (size_t)capacity);
         L.vals_in = take(sizeof(uint32_t) * (size_t)capacity);
@@ -263,12 +266,14 @@ tgs_status tgs_bin(const tgs_projected* pr, const tgs_camera* cam, const tgs_par
                 "radix sort");
         TGS_HIP(launch_tile_ranges(out->keys_dev, M, T, out->offsets_dev, s), "tile ranges");
         if (out->tile_order_dev)
-            TGS_HIP(launch_tile_order(out->offsets_dev, SegMap{nullptr, 1}, T, zero + kTileHist, out->tile_order_dev, s),
+            TGS_HIP(launch_tile_order(out->offsets_dev, SegMap{nullptr, 1, nullptr}, T, zero + kTileHist,
+                                      out->tile_order_dev, s),
                     "tile order");
         return TGS_OK;
     }
     uint32_t* count = var ? (uint32_t*)(w + L.count_var) : zero + L.count;
-    const SegMap sm{var ? out->seg_base_dev : nullptr, K};
+    uint2* tile_seg = var ? (uint2*)(w + L.tile_seg) : nullptr;
+    const SegMap sm{var ? out->seg_base_dev : nullptr, K, tile_seg};
     const uint32_t* nseg_dev = var ? out->seg_base_dev + T : nullptr;
     uint32_t* entry_rank = (uint32_t*)(w + L.entry_rank);
     uint32_t* seg_lists = (uint32_t*)(w + L.seg_lists);
@@ -278,7 +283,7 @@ tgs_status tgs_bin(const tgs_projected* pr, const tgs_camera* cam, const tgs_par
                   params->packed == 1 ? reinterpret_cast<float4*>(out->records_dev) : nullptr,
                   params->packed ? out->masks_dev : nullptr, K, tiles_x, cam->width, cam->height};
     if (var) {
-        TGS_HIP(launch_seg_base(params->per_tile_bins_dev, T, K, out->seg_base_dev, zero + kTicketSegs,
+        TGS_HIP(launch_seg_base(params->per_tile_bins_dev, T, K, out->seg_base_dev, tile_seg, zero + kTicketSegs,
                                 (uint64_t*)(zero + L.status_segs), s),
                 "segment bases");
         TGS_HIP(launch_fill_u32_dyn(count, 0u, nseg_dev, kXcc, (int64_t)kXcc * nseg, s), "clear counts");
@@ -507,7 +512,7 @@ tgs_status tgs_tile_features(const tgs_binned* b, const tgs_camera* cam, const t
     if (!features) return fail(TGS_ERR_INVALID_ARG, "features is NULL");
     if (params->per_tile_bins_dev && !b->seg_base_dev)
         return fail(TGS_ERR_INVALID_ARG, "seg_base is NULL with per_tile_bins");
-    const SegMap sm{params->per_tile_bins_dev ? b->seg_base_dev : nullptr, params->num_bins};
+    const SegMap sm{params->per_tile_bins_dev ? b->seg_base_dev : nullptr, params->num_bins, nullptr};
     TGS_HIP(launch_tile_features(b->offsets_dev, sm, tiles_of(cam, params->tile_size), b->counters_dev, features,
                                  (hipStream_t)stream),
             "tile features");

@@ -199,6 +199,7 @@ struct RecordSink {
 struct SegMap {
     const uint32_t* seg_base;
     int K;
+    const uint2* tile_seg;  // per-tile bin counts: {seg_base[t], 32 - log2 K_t} [T]
     __device__ __forceinline__ uint32_t first(int64_t t) const {
         return seg_base ? seg_base[t] : (uint32_t)(t * K);
     }
@@ -279,9 +280,11 @@ hipError_t launch_bin_scatter(const uint32_t* info, int64_t n, const uint32_t* e
 
 // Per-tile bin counts: seg_base[t] = exclusive prefix sum of the bin counts
 // (each clamped to 1..kmax and rounded down to a power of two), seg_base[T]
-// = S. ticket and status [scan_blocks(T)] must be zero.
-hipError_t launch_seg_base(const int32_t* per_tile_bins, int64_t T, int kmax, uint32_t* seg_base, uint32_t* ticket,
-                           uint64_t* status, hipStream_t s);
+// = S, and tile_seg[t] = {seg_base[t], 32 - log2 K_t} for the entry
+// kernels (one 8-byte load per entry). ticket and status [scan_blocks(T)]
+// must be zero.
+hipError_t launch_seg_base(const int32_t* per_tile_bins, int64_t T, int kmax, uint32_t* seg_base, uint2* tile_seg,
+                           uint32_t* ticket, uint64_t* status, hipStream_t s);
 // p[0 .. mult * *n_dev) = v.
 hipError_t launch_fill_u32_dyn(uint32_t* p, uint32_t v, const uint32_t* n_dev, int mult, int64_t max_n,
                                hipStream_t s);

@@ -9,7 +9,7 @@
 // W2 [64][64], b2 [64], W3 [64][8], b3 [8].
 //
 // Kernels (lane = tile unless stated; weights staged in LDS):
-//   features   one lane per tile walks its K_t bin lengths
+//   features   one wavefront per tile reads its K_t bin lengths
 //   forward    a1, a2, relu(a1), relu(a2) [T][64] (training) and logits
 //              [T][8]; inference writes K_t (and optionally the logits)
 //   softmax    p, dL/dz = p (r - p.r) / T and the loss
@@ -37,34 +37,54 @@ __device__ __forceinline__ void stage_weights(const float* __restrict__ w, float
 
 // ---- features ----------------------------------------------------------------
 
+// One wavefront per tile: lanes take the tile's bins 64 at a time
+// (coalesced reads of the offsets), then wave reductions.
+__device__ __forceinline__ float wave_sum_f(float v) {
+#pragma unroll
+    for (int m = 1; m < kWave; m <<= 1) v += __shfl_xor(v, m, kWave);
+    return v;
+}
+__device__ __forceinline__ float wave_max_f(float v) {
+#pragma unroll
+    for (int m = 1; m < kWave; m <<= 1) v = fmaxf(v, __shfl_xor(v, m, kWave));
+    return v;
+}
+
 __global__ void __launch_bounds__(256) features_kernel(const uint32_t* __restrict__ offsets, SegMap sm, int64_t T,
                                                        const int64_t* __restrict__ counters,
                                                        float* __restrict__ feat) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     if (t >= T) return;
+    const int l = lane();
     const uint32_t s0 = sm.first(t), s1 = sm.first(t + 1);
     const int K = (int)(s1 - s0);
     float hist[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     float n = 0.f, mx = 0.f, nz = 0.f, rep = 0.f, sq = 0.f;
-    uint32_t prev = offsets[s0];
-    for (int b = 0; b < K; ++b) {
-        const uint32_t nxt = offsets[s0 + b + 1];
-        const float l = (float)(nxt - prev);
-        prev = nxt;
-        n += l;
-        mx = fmaxf(mx, l);
-        nz += l > 0.f ? 1.f : 0.f;
-        rep += l >= 2.f ? l : 0.f;
-        sq += l * l;
+    for (int b = l; b < K; b += kWave) {
+        const float len = (float)(offsets[s0 + b + 1] - offsets[s0 + b]);
+        n += len;
+        mx = fmaxf(mx, len);
+        nz += len > 0.f ? 1.f : 0.f;
+        rep += len >= 2.f ? len : 0.f;
+        sq += len * len;
         if (K >= 8) {
-            hist[(8 * b) / K] += l;
-        } else {
-            const int c = 8 / K;
+            const int j = (8 * b) / K;
 #pragma unroll
-            for (int j = 0; j < 8; ++j)
-                if (j >= b * c && j < (b + 1) * c) hist[j] += l / (float)c;
+            for (int c = 0; c < 8; ++c) hist[c] += c == j ? len : 0.f;
+        } else {
+            const int c8 = 8 / K;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) hist[c] += (c >= b * c8 && c < (b + 1) * c8) ? len / (float)c8 : 0.f;
         }
     }
+    n = wave_sum_f(n);
+    mx = wave_max_f(mx);
+    nz = wave_sum_f(nz);
+    rep = wave_sum_f(rep);
+    sq = wave_sum_f(sq);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) hist[c] = wave_sum_f(hist[c]);
+    if (l != 0) return;
     const float d = fmaxf(n, 1.f);
     const float M = (float)counters[0];
     const float dens = log2f(1.f + M / (float)T);
@@ -110,7 +130,7 @@ __device__ __forceinline__ void mlp_forward(const float* s, const float* x, floa
 
 // Inference: K_t = 2^(argmax z + 1) (the first maximum wins); a non-finite
 // weight or logit gives the fallback count.
-__global__ void __launch_bounds__(256) propose_kernel(const float* __restrict__ w, const float* __restrict__ feat,
+__global__ void __launch_bounds__(64) propose_kernel(const float* __restrict__ w, const float* __restrict__ feat,
                                                       int64_t T, int32_t* __restrict__ bins,
                                                       float* __restrict__ logits, int fallback) {
     __shared__ float s[kNumParams];
@@ -293,14 +313,15 @@ int mlp_num_params() { return kNumParams; }
 hipError_t launch_tile_features(const uint32_t* offsets, SegMap sm, int64_t T, const int64_t* counters, float* feat,
                                 hipStream_t s) {
     if (T == 0) return hipSuccess;
-    hipLaunchKernelGGL(features_kernel, dim3(grid_of(T, 256)), dim3(256), 0, s, offsets, sm, T, counters, feat);
+    hipLaunchKernelGGL(features_kernel, dim3(grid_of(T * kWave, 256)), dim3(256), 0, s, offsets, sm, T, counters,
+                       feat);
     return hipGetLastError();
 }
 
 hipError_t launch_propose(const float* w, const float* feat, int64_t T, int32_t* bins, float* logits, int fallback,
                           hipStream_t s) {
     if (T == 0) return hipSuccess;
-    hipLaunchKernelGGL(propose_kernel, dim3(grid_of(T, 256)), dim3(256), 0, s, w, feat, T, bins, logits, fallback);
+    hipLaunchKernelGGL(propose_kernel, dim3(grid_of(T, kWave)), dim3(kWave), 0, s, w, feat, T, bins, logits, fallback);
     return hipGetLastError();
 }
 

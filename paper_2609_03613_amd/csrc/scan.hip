@@ -7,6 +7,8 @@
 // Used for the per-Gaussian entry offsets (fused with the visible-Gaussian
 // list) and for the (tile, bin) counts -> bin offsets (fused with the
 // per-XCD bases and the repair-bucket classification).
+#include <algorithm>
+
 #include "common.hpp"
 
 namespace tgs {
@@ -280,8 +282,8 @@ __device__ __forceinline__ uint32_t pow2_bins(int32_t k, int kmax) {
 }
 
 __global__ void __launch_bounds__(kThreads) seg_base_kernel(const int32_t* __restrict__ kt, int64_t T, int kmax,
-                                                            uint32_t* __restrict__ seg_base, uint32_t* ticket,
-                                                            uint64_t* status) {
+                                                            uint32_t* __restrict__ seg_base, uint2* __restrict__ tile_seg,
+                                                            uint32_t* ticket, uint64_t* status) {
     __shared__ uint32_t tk;
     __shared__ uint32_t lds32[kThreads / kWave];
     __shared__ uint64_t pre;
@@ -308,7 +310,10 @@ __global__ void __launch_bounds__(kThreads) seg_base_kernel(const int32_t* __res
         const int64_t t = base + r * kThreads + threadIdx.x;
         uint32_t tot;
         const uint32_t ex = block_excl_u32(v[r], lds32, &tot);
-        if (t < T) seg_base[t] = carry + ex;
+        if (t < T) {
+            seg_base[t] = carry + ex;
+            tile_seg[t] = make_uint2(carry + ex, 32u - (uint32_t)__builtin_ctz(v[r]));
+        }
         carry += tot;
     }
 }
@@ -345,10 +350,10 @@ hipError_t launch_bin_offsets(uint32_t* count, int64_t nseg, const uint32_t* nse
     return hipGetLastError();
 }
 
-hipError_t launch_seg_base(const int32_t* per_tile_bins, int64_t T, int kmax, uint32_t* seg_base, uint32_t* ticket,
-                           uint64_t* status, hipStream_t s) {
+hipError_t launch_seg_base(const int32_t* per_tile_bins, int64_t T, int kmax, uint32_t* seg_base, uint2* tile_seg,
+                           uint32_t* ticket, uint64_t* status, hipStream_t s) {
     hipLaunchKernelGGL(seg_base_kernel, dim3((unsigned)scan_blocks(T)), dim3(kThreads), 0, s, per_tile_bins, T, kmax,
-                       seg_base, ticket, status);
+                       seg_base, tile_seg, ticket, status);
     return hipGetLastError();
 }
 

@@ -40,3 +40,12 @@ def test_bin_weights_fallback(tmp_path):
     assert np.array_equal(bins.load_weights(p), w)
     (tmp_path / "bad.npz").write_bytes(b"not a zip")
     assert bins.load_weights(str(tmp_path / "bad.npz")) is None
+
+
+def test_committed_bin_weights_are_valid():
+    import numpy as np
+    from paper_2609_03613_amd import bins
+    w = bins.load_weights()
+    assert w is not None and w.shape == (5768,) and np.all(np.isfinite(w))
+    with np.load(bins.WEIGHTS_PATH, allow_pickle=False) as z:
+        assert float(z["c_seg"]) >= 0 and np.all(np.asarray(z["c_bucket"]) >= 0)
