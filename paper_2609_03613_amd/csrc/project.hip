@@ -249,196 +249,241 @@ __device__ __forceinline__ void sh_basis_vjp(double x, double y, double z, int d
     out[1] += gY[15] * k9 * 6.0 * x * y;
 }
 
-// Backward of project_kernel, one lane per Gaussian, binary64: the forward
-// quantities are recomputed with the forward's operations (so the same
-// Gaussians are visible and the same guards are active) and the gradient
-// line d = dL/d(mean_x, mean_y, conic a, b, c, opacity, r, g, b) is taken
-// back through the conic inverse, the screen covariance J M diag(s^2) M^T
-// J^T + 0.3 I (M = R_cam R_q), the guarded perspective Jacobian, the screen
-// mean, the quaternion normalisation, exp of the log-scales, the sigmoid and
-// the clamped SH colour (whose direction depends on the mean).
-__global__ void __launch_bounds__(kProjThreads) project_bwd_kernel(
-    const float* __restrict__ means, const float* __restrict__ log_scales, const float* __restrict__ quats,
-    const float* __restrict__ logits, const float* __restrict__ sh, int64_t n, int degree, Cam cam,
-    const float4* __restrict__ dsp, float* __restrict__ d_means, float* __restrict__ d_ls,
-    float* __restrict__ d_quats, float* __restrict__ d_logits, float* __restrict__ d_sh) {
+// Backward of project_kernel in two launches, one lane per Gaussian,
+// binary64: the forward quantities are recomputed with the forward's
+// operations (so the same Gaussians are visible and the same guards and
+// clamps are active) and the gradient line d = dL/d(mean_x, mean_y, conic
+// a, b, c, opacity, r, g, b) is taken back through
+//   sh_bwd:   the clamped SH colour (coefficients, and the mean through the
+//             view direction); writes d_sh and the SH part of d_means;
+//   geom_bwd: the conic inverse, the screen covariance J M diag(s^2) M^T
+//             J^T + 0.3 I (M = R_cam R_q), the guarded perspective Jacobian,
+//             the screen mean, the quaternion normalisation, exp of the
+//             log-scales and the sigmoid; adds to d_means.
+// Splitting keeps each kernel's binary64 register footprint small enough
+// for several wavefronts per SIMD. Gaussians whose gradient line is zero
+// (invisible or never composited) are skipped and get zero gradients.
+__global__ void __launch_bounds__(kProjThreads) sh_bwd_kernel(const float* __restrict__ means,
+                                                             const float* __restrict__ sh, int64_t n, int degree,
+                                                             Cam cam, const float4* __restrict__ dsp,
+                                                             float* __restrict__ d_means, float* __restrict__ d_sh) {
 #pragma clang fp contract(off)
-    __shared__ float sh_in[kProjThreads * kMaxShFloats];
-    __shared__ float sh_out[kProjThreads * kMaxShFloats];
+    __shared__ float4 sh_lds[kProjThreads * kMaxShFloats / 4];
     const int nsh = (degree + 1) * (degree + 1);
     const int nf = nsh * 3;
     const int64_t g0 = (int64_t)blockIdx.x * kProjThreads;
-    const int64_t cnt = min((int64_t)kProjThreads, n - g0) * nf;
-    for (int64_t i = threadIdx.x; i < cnt; i += kProjThreads) sh_in[i] = sh[g0 * nf + i];
+    const int64_t cnt = min((int64_t)kProjThreads, n - g0) * nf;  // floats
+    float* f = reinterpret_cast<float*>(sh_lds);
+    {
+        const float* src = sh + g0 * nf;
+        if ((reinterpret_cast<uintptr_t>(src) & 15) == 0) {
+            const float4* s4 = reinterpret_cast<const float4*>(src);
+            for (int64_t i = threadIdx.x; i < cnt / 4; i += kProjThreads) sh_lds[i] = s4[i];
+            for (int64_t i = (cnt / 4) * 4 + threadIdx.x; i < cnt; i += kProjThreads) f[i] = src[i];
+        } else {
+            for (int64_t i = threadIdx.x; i < cnt; i += kProjThreads) f[i] = src[i];
+        }
+    }
     __syncthreads();
     const int64_t g = g0 + threadIdx.x;
-    float* dsh = sh_out + threadIdx.x * nf;
-    const float* shg = sh_in + threadIdx.x * nf;
     if (g < n) {
-        double gm[3] = {0.0, 0.0, 0.0}, gls[3] = {0.0, 0.0, 0.0}, gq4[4] = {0.0, 0.0, 0.0, 0.0}, glogit = 0.0;
-        for (int k = 0; k < nf; ++k) dsh[k] = 0.f;
-        const double mx3 = means[3 * g], my3 = means[3 * g + 1], mz3 = means[3 * g + 2];
-        const double* R = cam.R;
-        const double px = R[0] * mx3 + R[1] * my3 + R[2] * mz3 + cam.t[0];
-        const double py = R[3] * mx3 + R[4] * my3 + R[5] * mz3 + cam.t[1];
-        const double z = R[6] * mx3 + R[7] * my3 + R[8] * mz3 + cam.t[2];
-        bool ok = (z > cam.znear) && (z < cam.zfar);
-        double qv[4] = {quats[4 * g], quats[4 * g + 1], quats[4 * g + 2], quats[4 * g + 3]};
-        const double qn = sqrt(qv[0] * qv[0] + qv[1] * qv[1] + qv[2] * qv[2] + qv[3] * qv[3]);
-        ok = ok && (qn > 0.0) && isfinite(qn);
+        float* shg = f + threadIdx.x * nf;  // coefficients in, gradients out (in place)
+        const float4 d1 = dsp[kGradWords / 4 * g + 1], d2 = dsp[kGradWords / 4 * g + 2];
+        const double dcol[3] = {d1.z, d1.w, d2.x};
+        double gm[3] = {0.0, 0.0, 0.0};
+        if (dcol[0] != 0.0 || dcol[1] != 0.0 || dcol[2] != 0.0) {
+            const double mx3 = means[3 * g], my3 = means[3 * g + 1], mz3 = means[3 * g + 2];
+            double ux = mx3 - cam.campos[0], uy = my3 - cam.campos[1], uz = mz3 - cam.campos[2];
+            const double dn = sqrt(ux * ux + uy * uy + uz * uz);
+            ux /= dn; uy /= dn; uz /= dn;
+            double Y[16];
+            sh_basis(ux, uy, uz, degree, Y);
+            double col[3] = {0.0, 0.0, 0.0};
+            for (int k = 0; k < nsh; ++k) {
+                col[0] += (double)shg[3 * k] * Y[k];
+                col[1] += (double)shg[3 * k + 1] * Y[k];
+                col[2] += (double)shg[3 * k + 2] * Y[k];
+            }
+            const bool on[3] = {0.5 + col[0] > 0.0, 0.5 + col[1] > 0.0, 0.5 + col[2] > 0.0};
+            double gY[16];
+            for (int k = 0; k < nsh; ++k) {
+                double acc = 0.0;
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) {
+                    if (!on[ch]) continue;
+                    acc += dcol[ch] * (double)shg[3 * k + ch];
+                }
+                gY[k] = acc;
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) shg[3 * k + ch] = on[ch] ? (float)(dcol[ch] * Y[k]) : 0.f;
+            }
+            double gu[3];
+            sh_basis_vjp(ux, uy, uz, degree, gY, gu);
+            const double gdot = gu[0] * ux + gu[1] * uy + gu[2] * uz;
+            gm[0] = (gu[0] - gdot * ux) / dn;
+            gm[1] = (gu[1] - gdot * uy) / dn;
+            gm[2] = (gu[2] - gdot * uz) / dn;
+        } else {
+            for (int k = 0; k < nf; ++k) shg[k] = 0.f;
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) d_means[3 * g + k] = (float)gm[k];
+    }
+    __syncthreads();
+    {
+        float* dst = d_sh + g0 * nf;
+        if ((reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
+            float4* d4 = reinterpret_cast<float4*>(dst);
+            for (int64_t i = threadIdx.x; i < cnt / 4; i += kProjThreads) d4[i] = sh_lds[i];
+            for (int64_t i = (cnt / 4) * 4 + threadIdx.x; i < cnt; i += kProjThreads) dst[i] = f[i];
+        } else {
+            for (int64_t i = threadIdx.x; i < cnt; i += kProjThreads) dst[i] = f[i];
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) geom_bwd_kernel(const float* __restrict__ means,
+                                                      const float* __restrict__ log_scales,
+                                                      const float* __restrict__ quats,
+                                                      const float* __restrict__ logits, int64_t n, Cam cam,
+                                                      const float4* __restrict__ dsp, float* __restrict__ d_means,
+                                                      float* __restrict__ d_ls, float* __restrict__ d_quats,
+                                                      float* __restrict__ d_logits) {
+#pragma clang fp contract(off)
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    double gm[3] = {0.0, 0.0, 0.0}, gls[3] = {0.0, 0.0, 0.0}, gq4[4] = {0.0, 0.0, 0.0, 0.0}, glogit = 0.0;
+    const float4 d0 = dsp[kGradWords / 4 * g], d1 = dsp[kGradWords / 4 * g + 1];
+    const bool any = d0.x != 0.f || d0.y != 0.f || d0.z != 0.f || d0.w != 0.f || d1.x != 0.f || d1.y != 0.f;
+    const double mx3 = means[3 * g], my3 = means[3 * g + 1], mz3 = means[3 * g + 2];
+    const double* R = cam.R;
+    const double px = R[0] * mx3 + R[1] * my3 + R[2] * mz3 + cam.t[0];
+    const double py = R[3] * mx3 + R[4] * my3 + R[5] * mz3 + cam.t[1];
+    const double z = R[6] * mx3 + R[7] * my3 + R[8] * mz3 + cam.t[2];
+    bool ok = any && (z > cam.znear) && (z < cam.zfar);
+    double qv[4] = {quats[4 * g], quats[4 * g + 1], quats[4 * g + 2], quats[4 * g + 3]};
+    const double qn = sqrt(qv[0] * qv[0] + qv[1] * qv[1] + qv[2] * qv[2] + qv[3] * qv[3]);
+    ok = ok && (qn > 0.0) && isfinite(qn);
+    if (ok) {
+        const double qw = qv[0] / qn, qx = qv[1] / qn, qy = qv[2] / qn, qz = qv[3] / qn;
+        const double Rq[9] = {1.0 - 2.0 * (qy * qy + qz * qz), 2.0 * (qx * qy - qw * qz),
+                              2.0 * (qx * qz + qw * qy),       2.0 * (qx * qy + qw * qz),
+                              1.0 - 2.0 * (qx * qx + qz * qz), 2.0 * (qy * qz - qw * qx),
+                              2.0 * (qx * qz - qw * qy),       2.0 * (qy * qz + qw * qx),
+                              1.0 - 2.0 * (qx * qx + qy * qy)};
+        double s2[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double sc = exp((double)log_scales[3 * g + k]);
+            s2[k] = sc * sc;
+        }
+        double M[9];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                M[3 * i + j] = R[3 * i] * Rq[j] + R[3 * i + 1] * Rq[3 + j] + R[3 * i + 2] * Rq[6 + j];
+        const double txz = px / z, tyz = py / z;
+        const double cxz = fmin(cam.lim_xp, fmax(-cam.lim_xn, txz));
+        const double cyz = fmin(cam.lim_yp, fmax(-cam.lim_yn, tyz));
+        const bool gx = cxz != txz, gy = cyz != tyz;  // frustum guard active
+        const double tx = z * cxz, ty = z * cyz;
+        const double j00 = cam.fx / z, j02 = -cam.fx * tx / (z * z);
+        const double j11 = cam.fy / z, j12 = -cam.fy * ty / (z * z);
+        double A[3], B[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            A[k] = j00 * M[k] + j02 * M[6 + k];
+            B[k] = j11 * M[3 + k] + j12 * M[6 + k];
+        }
+        const double c00 = A[0] * A[0] * s2[0] + A[1] * A[1] * s2[1] + A[2] * A[2] * s2[2] + 0.3;
+        const double c01 = A[0] * B[0] * s2[0] + A[1] * B[1] * s2[1] + A[2] * B[2] * s2[2];
+        const double c11 = B[0] * B[0] * s2[0] + B[1] * B[1] * s2[1] + B[2] * B[2] * s2[2] + 0.3;
+        const double det = c00 * c11 - c01 * c01;
+        ok = (det > 0.0) && isfinite(det);
+        const double mxs = cam.fx * px / z + cam.cx;
+        const double mys = cam.fy * py / z + cam.cy;
+        const double o = 1.0 / (1.0 + exp(-(double)logits[g]));
+        ok = ok && (o >= 1.0 / 255.0) && isfinite(mxs) && isfinite(mys);
         if (ok) {
-            const double qw = qv[0] / qn, qx = qv[1] / qn, qy = qv[2] / qn, qz = qv[3] / qn;
-            const double Rq[9] = {1.0 - 2.0 * (qy * qy + qz * qz), 2.0 * (qx * qy - qw * qz),
-                                  2.0 * (qx * qz + qw * qy),       2.0 * (qx * qy + qw * qz),
-                                  1.0 - 2.0 * (qx * qx + qz * qz), 2.0 * (qy * qz - qw * qx),
-                                  2.0 * (qx * qz - qw * qy),       2.0 * (qy * qz + qw * qx),
-                                  1.0 - 2.0 * (qx * qx + qy * qy)};
-            double s2[3];
+            const double dmx = d0.x, dmy = d0.y, dA = d0.z, dB = d0.w, dC = d1.x, dop = d1.y;
+            // opacity = sigmoid(logit)
+            glogit = dop * o * (1.0 - o);
+            // conic = [c11, -c01, c00] / det
+            const double dd = det * det;
+            const double ga = dA * (-c11 * c11 / dd) + dB * (c01 * c11 / dd) + dC * (-c01 * c01 / dd);
+            const double gb = dA * (2.0 * c01 * c11 / dd) + dB * (-1.0 / det - 2.0 * c01 * c01 / dd) +
+                              dC * (2.0 * c00 * c01 / dd);
+            const double gc = dA * (-c01 * c01 / dd) + dB * (c00 * c01 / dd) + dC * (-c00 * c00 / dd);
+            // covariance entries from the rows A, B of J M and s^2
+            double gA[3], gB[3];
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                const double s = exp((double)log_scales[3 * g + k]);
-                s2[k] = s * s;
+                gA[k] = 2.0 * ga * A[k] * s2[k] + gb * B[k] * s2[k];
+                gB[k] = 2.0 * gc * B[k] * s2[k] + gb * A[k] * s2[k];
+                gls[k] = 2.0 * s2[k] * (ga * A[k] * A[k] + gb * A[k] * B[k] + gc * B[k] * B[k]);
             }
-            double M[9];
+            double g00 = 0.0, g02 = 0.0, g11 = 0.0, g12 = 0.0, gM[9];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                g00 += gA[k] * M[k];
+                g02 += gA[k] * M[6 + k];
+                g11 += gB[k] * M[3 + k];
+                g12 += gB[k] * M[6 + k];
+                gM[k] = gA[k] * j00;
+                gM[3 + k] = gB[k] * j11;
+                gM[6 + k] = gA[k] * j02 + gB[k] * j12;
+            }
+            // M = R_cam R_q  =>  dL/dR_q = R_cam^T dL/dM
+            double gR[9];
 #pragma unroll
             for (int i = 0; i < 3; ++i)
 #pragma unroll
-                for (int j = 0; j < 3; ++j)
-                    M[3 * i + j] = R[3 * i] * Rq[j] + R[3 * i + 1] * Rq[3 + j] + R[3 * i + 2] * Rq[6 + j];
-            const double txz = px / z, tyz = py / z;
-            const double cxz = fmin(cam.lim_xp, fmax(-cam.lim_xn, txz));
-            const double cyz = fmin(cam.lim_yp, fmax(-cam.lim_yn, tyz));
-            const bool gx = cxz != txz, gy = cyz != tyz;  // frustum guard active
-            const double tx = z * cxz, ty = z * cyz;
-            const double j00 = cam.fx / z, j02 = -cam.fx * tx / (z * z);
-            const double j11 = cam.fy / z, j12 = -cam.fy * ty / (z * z);
-            double A[3], B[3];
+                for (int j = 0; j < 3; ++j) gR[3 * i + j] = R[i] * gM[j] + R[3 + i] * gM[3 + j] + R[6 + i] * gM[6 + j];
+            // R_q entries as functions of the unit quaternion
+            const double gw = 2.0 * (-qz * gR[1] + qy * gR[2] + qz * gR[3] - qx * gR[5] - qy * gR[6] + qx * gR[7]);
+            const double gxq = 2.0 * (qy * gR[1] + qz * gR[2] + qy * gR[3] - 2.0 * qx * gR[4] - qw * gR[5] +
+                                      qz * gR[6] + qw * gR[7] - 2.0 * qx * gR[8]);
+            const double gyq = 2.0 * (-2.0 * qy * gR[0] + qx * gR[1] + qw * gR[2] + qx * gR[3] + qz * gR[5] -
+                                      qw * gR[6] + qz * gR[7] - 2.0 * qy * gR[8]);
+            const double gzq = 2.0 * (-2.0 * qz * gR[0] - qw * gR[1] + qx * gR[2] + qw * gR[3] - 2.0 * qz * gR[4] +
+                                      qy * gR[5] + qx * gR[6] + qy * gR[7]);
+            // q_hat = q / |q|
+            const double qh[4] = {qw, qx, qy, qz};
+            const double gh[4] = {gw, gxq, gyq, gzq};
+            const double hd = gw * qw + gxq * qx + gyq * qy + gzq * qz;
 #pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                A[k] = j00 * M[k] + j02 * M[6 + k];
-                B[k] = j11 * M[3 + k] + j12 * M[6 + k];
+            for (int k = 0; k < 4; ++k) gq4[k] = (gh[k] - hd * qh[k]) / qn;
+            // J entries and the screen mean as functions of the camera-space point
+            double gp0 = dmx * cam.fx / z, gp1 = dmy * cam.fy / z;
+            double gz = -dmx * cam.fx * px / (z * z) - dmy * cam.fy * py / (z * z);
+            gz += -g00 * cam.fx / (z * z) - g11 * cam.fy / (z * z);
+            if (gx) {
+                gz += g02 * cam.fx * cxz / (z * z);
+            } else {
+                gp0 += -g02 * cam.fx / (z * z);
+                gz += g02 * 2.0 * cam.fx * px / (z * z * z);
             }
-            const double c00 = A[0] * A[0] * s2[0] + A[1] * A[1] * s2[1] + A[2] * A[2] * s2[2] + 0.3;
-            const double c01 = A[0] * B[0] * s2[0] + A[1] * B[1] * s2[1] + A[2] * B[2] * s2[2];
-            const double c11 = B[0] * B[0] * s2[0] + B[1] * B[1] * s2[1] + B[2] * B[2] * s2[2] + 0.3;
-            const double det = c00 * c11 - c01 * c01;
-            ok = (det > 0.0) && isfinite(det);
-            const double mxs = cam.fx * px / z + cam.cx;
-            const double mys = cam.fy * py / z + cam.cy;
-            const double o = 1.0 / (1.0 + exp(-(double)logits[g]));
-            ok = ok && (o >= 1.0 / 255.0) && isfinite(mxs) && isfinite(mys);
-            if (ok) {
-                const float4 d0 = dsp[kGradWords / 4 * g], d1 = dsp[kGradWords / 4 * g + 1],
-                             d2v = dsp[kGradWords / 4 * g + 2];
-                const double dmx = d0.x, dmy = d0.y, dA = d0.z, dB = d0.w, dC = d1.x, dop = d1.y;
-                const double dcol[3] = {d1.z, d1.w, d2v.x};
-                // opacity = sigmoid(logit)
-                glogit = dop * o * (1.0 - o);
-                // colour = max(0, 0.5 + sum sh Y(dir)), dir = mean - camera centre
-                double ux = mx3 - cam.campos[0], uy = my3 - cam.campos[1], uz = mz3 - cam.campos[2];
-                const double dn = sqrt(ux * ux + uy * uy + uz * uz);
-                ux /= dn; uy /= dn; uz /= dn;
-                double Y[16];
-                sh_basis(ux, uy, uz, degree, Y);
-                double col[3] = {0.0, 0.0, 0.0};
-                for (int k = 0; k < nsh; ++k) {
-                    col[0] += (double)shg[3 * k] * Y[k];
-                    col[1] += (double)shg[3 * k + 1] * Y[k];
-                    col[2] += (double)shg[3 * k + 2] * Y[k];
-                }
-                double gY[16];
-                for (int k = 0; k < nsh; ++k) gY[k] = 0.0;
-#pragma unroll
-                for (int ch = 0; ch < 3; ++ch) {
-                    if (!(0.5 + col[ch] > 0.0)) continue;
-                    for (int k = 0; k < nsh; ++k) {
-                        dsh[3 * k + ch] = (float)(dcol[ch] * Y[k]);
-                        gY[k] += dcol[ch] * (double)shg[3 * k + ch];
-                    }
-                }
-                double gu[3];
-                sh_basis_vjp(ux, uy, uz, degree, gY, gu);
-                const double gdot = gu[0] * ux + gu[1] * uy + gu[2] * uz;
-                gm[0] = (gu[0] - gdot * ux) / dn;
-                gm[1] = (gu[1] - gdot * uy) / dn;
-                gm[2] = (gu[2] - gdot * uz) / dn;
-                // conic = [c11, -c01, c00] / det
-                const double dd = det * det;
-                const double ga = dA * (-c11 * c11 / dd) + dB * (c01 * c11 / dd) + dC * (-c01 * c01 / dd);
-                const double gb = dA * (2.0 * c01 * c11 / dd) + dB * (-1.0 / det - 2.0 * c01 * c01 / dd) +
-                                  dC * (2.0 * c00 * c01 / dd);
-                const double gc = dA * (-c01 * c01 / dd) + dB * (c00 * c01 / dd) + dC * (-c00 * c00 / dd);
-                // covariance entries from the rows A, B of J M and s^2
-                double gA[3], gB[3];
-#pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    gA[k] = 2.0 * ga * A[k] * s2[k] + gb * B[k] * s2[k];
-                    gB[k] = 2.0 * gc * B[k] * s2[k] + gb * A[k] * s2[k];
-                    gls[k] = 2.0 * s2[k] * (ga * A[k] * A[k] + gb * A[k] * B[k] + gc * B[k] * B[k]);
-                }
-                double g00 = 0.0, g02 = 0.0, g11 = 0.0, g12 = 0.0, gM[9];
-#pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    g00 += gA[k] * M[k];
-                    g02 += gA[k] * M[6 + k];
-                    g11 += gB[k] * M[3 + k];
-                    g12 += gB[k] * M[6 + k];
-                    gM[k] = gA[k] * j00;
-                    gM[3 + k] = gB[k] * j11;
-                    gM[6 + k] = gA[k] * j02 + gB[k] * j12;
-                }
-                // M = R_cam R_q  =>  dL/dR_q = R_cam^T dL/dM
-                double gR[9];
-#pragma unroll
-                for (int i = 0; i < 3; ++i)
-#pragma unroll
-                    for (int j = 0; j < 3; ++j) gR[3 * i + j] = R[i] * gM[j] + R[3 + i] * gM[3 + j] + R[6 + i] * gM[6 + j];
-                // R_q entries as functions of the unit quaternion
-                const double gw = 2.0 * (-qz * gR[1] + qy * gR[2] + qz * gR[3] - qx * gR[5] - qy * gR[6] + qx * gR[7]);
-                const double gxq = 2.0 * (qy * gR[1] + qz * gR[2] + qy * gR[3] - 2.0 * qx * gR[4] - qw * gR[5] +
-                                          qz * gR[6] + qw * gR[7] - 2.0 * qx * gR[8]);
-                const double gyq = 2.0 * (-2.0 * qy * gR[0] + qx * gR[1] + qw * gR[2] + qx * gR[3] + qz * gR[5] -
-                                          qw * gR[6] + qz * gR[7] - 2.0 * qy * gR[8]);
-                const double gzq = 2.0 * (-2.0 * qz * gR[0] - qw * gR[1] + qx * gR[2] + qw * gR[3] - 2.0 * qz * gR[4] +
-                                          qy * gR[5] + qx * gR[6] + qy * gR[7]);
-                // q_hat = q / |q|
-                const double qh[4] = {qw, qx, qy, qz};
-                const double gh[4] = {gw, gxq, gyq, gzq};
-                const double hd = gw * qw + gxq * qx + gyq * qy + gzq * qz;
-#pragma unroll
-                for (int k = 0; k < 4; ++k) gq4[k] = (gh[k] - hd * qh[k]) / qn;
-                // J entries and the screen mean as functions of the camera-space point
-                double gp0 = dmx * cam.fx / z, gp1 = dmy * cam.fy / z;
-                double gz = -dmx * cam.fx * px / (z * z) - dmy * cam.fy * py / (z * z);
-                gz += -g00 * cam.fx / (z * z) - g11 * cam.fy / (z * z);
-                if (gx) {
-                    gz += g02 * cam.fx * cxz / (z * z);
-                } else {
-                    gp0 += -g02 * cam.fx / (z * z);
-                    gz += g02 * 2.0 * cam.fx * px / (z * z * z);
-                }
-                if (gy) {
-                    gz += g12 * cam.fy * cyz / (z * z);
-                } else {
-                    gp1 += -g12 * cam.fy / (z * z);
-                    gz += g12 * 2.0 * cam.fy * py / (z * z * z);
-                }
-                // p_cam = R_cam mean + t
-#pragma unroll
-                for (int c = 0; c < 3; ++c) gm[c] += R[c] * gp0 + R[3 + c] * gp1 + R[6 + c] * gz;
+            if (gy) {
+                gz += g12 * cam.fy * cyz / (z * z);
+            } else {
+                gp1 += -g12 * cam.fy / (z * z);
+                gz += g12 * 2.0 * cam.fy * py / (z * z * z);
             }
-        }
+            // p_cam = R_cam mean + t
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            d_means[3 * g + k] = (float)gm[k];
-            d_ls[3 * g + k] = (float)gls[k];
+            for (int c = 0; c < 3; ++c) gm[c] = R[c] * gp0 + R[3 + c] * gp1 + R[6 + c] * gz;
         }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) d_quats[4 * g + k] = (float)gq4[k];
-        d_logits[g] = (float)glogit;
     }
-    __syncthreads();
-    for (int64_t i = threadIdx.x; i < cnt; i += kProjThreads) d_sh[g0 * nf + i] = sh_out[i];
+    // the SH part of d_means was written by sh_bwd_kernel (same lane layout)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        d_means[3 * g + k] = (float)((double)d_means[3 * g + k] + gm[k]);
+        d_ls[3 * g + k] = (float)gls[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) d_quats[4 * g + k] = (float)gq4[k];
+    d_logits[g] = (float)glogit;
 }
 
 hipError_t launch_project(const tgs_gaussians& g, const Cam& cam, float* splats, uint32_t* info, hipStream_t s) {
@@ -455,10 +500,12 @@ hipError_t launch_project_backward(const tgs_gaussians& g, const Cam& cam, const
                                    const tgs_gaussian_grads& out, hipStream_t s) {
     if (g.n == 0) return hipSuccess;
     const int64_t grid = (g.n + kProjThreads - 1) / kProjThreads;
-    hipLaunchKernelGGL(project_bwd_kernel, dim3((unsigned)grid), dim3(kProjThreads), 0, s, g.means_dev,
-                       g.log_scales_dev, g.quats_dev, g.logits_dev, g.sh_dev, g.n, g.sh_degree, cam,
-                       reinterpret_cast<const float4*>(d_splats), out.means_dev, out.log_scales_dev, out.quats_dev,
-                       out.logits_dev, out.sh_dev);
+    const auto* dsp = reinterpret_cast<const float4*>(d_splats);
+    hipLaunchKernelGGL(sh_bwd_kernel, dim3((unsigned)grid), dim3(kProjThreads), 0, s, g.means_dev, g.sh_dev, g.n,
+                       g.sh_degree, cam, dsp, out.means_dev, out.sh_dev);
+    hipLaunchKernelGGL(geom_bwd_kernel, dim3((unsigned)((g.n + 255) / 256)), dim3(256), 0, s, g.means_dev,
+                       g.log_scales_dev, g.quats_dev, g.logits_dev, g.n, cam, dsp, out.means_dev, out.log_scales_dev,
+                       out.quats_dev, out.logits_dev);
     return hipGetLastError();
 }
 
