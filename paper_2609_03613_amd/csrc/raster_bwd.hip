@@ -10,7 +10,8 @@
 // the largest last position in the block, 64 entries at a time, with the
 // same block cull and LDS compaction; each lane recovers the transmittance
 // in front of an entry by dividing by the same binary32 (1 - alpha) the
-// forward multiplied by, and keeps the colour behind it,
+// forward multiplied by (a hardware reciprocal, within an ulp), and keeps the
+// colour behind it,
 // S = T_final bg + sum over later entries of T alpha c. Per entry k:
 //   dL/dc_k     = g T_k alpha_k
 //   dL/dalpha_k = sum_ch g_ch (T_k c_ch - S_ch / (1 - alpha_k))
@@ -18,9 +19,9 @@
 // and, when alpha is not capped at 0.99, through alpha = o exp2(q'):
 // dL/do = dL/dalpha exp2(q'), dL/dq' = dL/dalpha alpha ln 2, with q' the
 // scaled quadratic form of the staged conic. The 9 per-lane gradients of an
-// entry are summed over the wavefront (DPP within rows of 16, then two lane
-// swaps) and lanes 0..8 add the 9 sums to the Gaussian's gradient line with
-// one float atomic each.
+// entry are summed over the wavefront (DPP within rows of 16 for each, then
+// one select and two lane swaps for all nine) and lanes 0..8 add the 9 sums
+// to the Gaussian's gradient line with one float atomic each.
 #include <math.h>
 
 #include "raster.hpp"
@@ -40,12 +41,21 @@ __device__ __forceinline__ float row_sum(float v) {
     return v;
 }
 
-// Sum over the 64 lanes, result in every lane.
-__device__ __forceinline__ float wave_sum(float v) {
-    v = row_sum(v);
-    v += __shfl_xor(v, 16, kWave);
-    v += __shfl_xor(v, 32, kWave);
-    return v;
+// Wavefront sums of 9 values: d[k] summed over the 64 lanes ends in lane k
+// (k < 9). Every value is first summed within each row of 16 lanes (DPP,
+// result in every lane of the row); lane c of each row then keeps the row
+// sum of value c, and two lane swaps add the four rows.
+__device__ __forceinline__ float wave_sums9(const float* d) {
+    const int c = lane() & 15;
+    float mine = 0.f;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const float r = row_sum(d[k]);
+        mine = c == k ? r : mine;
+    }
+    mine += __shfl_xor(mine, 16, kWave);
+    mine += __shfl_xor(mine, 32, kWave);
+    return mine;
 }
 
 __device__ __forceinline__ int wave_max_i32(int v) {
@@ -138,9 +148,12 @@ __global__ void __launch_bounds__(256) raster_bwd_kernel(RasterArgs A, const flo
             if (comp) {
                 const float alpha = fminf(kAlphaMax, araw);
                 const float om = 1.0f - alpha;
-                T = T / om;
+                // 1 / (1 - alpha) to within an ulp (hardware reciprocal);
+                // the gradients carry a 1e-3 tolerance, not the forward's
+                // bit-exactness
+                const float inv = __builtin_amdgcn_rcpf(om);
+                T = T * inv;
                 const float wt = alpha * T;
-                const float inv = 1.0f / om;
                 d[6] = gr * wt;
                 d[7] = gg * wt;
                 d[8] = gb * wt;
@@ -162,12 +175,7 @@ __global__ void __launch_bounds__(256) raster_bwd_kernel(RasterArgs A, const flo
                     d[5] = dLda * G;
                 }
             }
-            float mine = 0.f;
-#pragma unroll
-            for (int k = 0; k < 9; ++k) {
-                const float tot = wave_sum(d[k]);
-                mine = (l == k) ? tot : mine;
-            }
+            const float mine = wave_sums9(d);
             if (l < 9) unsafeAtomicAdd(d_splats + kGradWords * (int64_t)idw[j] + l, mine);
         }
         wave_sync();
