@@ -123,7 +123,8 @@ def train_step(args):
     H, W = cam["height"], cam["width"]
     out = {"rgb": torch.empty((H, W, 3), dtype=torch.float32, device=dev),
            "alpha": torch.empty((H, W), dtype=torch.float32, device=dev),
-           "last": torch.empty((H, W), dtype=torch.int32, device=dev)}
+           "last": torch.empty((H, W), dtype=torch.int32, device=dev),
+           "trans": torch.empty((H, W), dtype=torch.float32, device=dev)}
     n = int(g["means"].shape[0])
     d_splats = torch.empty((n, 12), dtype=torch.float32, device=dev)
     d_rgb = torch.empty((H, W, 3), dtype=torch.float32, device=dev)
@@ -140,7 +141,7 @@ def train_step(args):
         torch.sub(o["rgb"], target, out=d_rgb)
         d_rgb.mul_(scale)
         if evs: evs[4].record(stream)
-        r.rasterize_backward(s, i, bb, d_rgb, None, out=d_splats)
+        r.rasterize_backward(s, i, bb, d_rgb, None, out=d_splats, saved=o)
         if evs: evs[5].record(stream)
         grads = tg.project_backward(gd, cam, d_splats)
         if evs: evs[6].record(stream)

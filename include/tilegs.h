@@ -209,12 +209,14 @@ TGS_API tgs_status tgs_bin(const tgs_projected* projected, const tgs_camera* cam
    instrumented kernel instance): n_contrib [H][W] composited entries,
    n_visit [H][W] entries the pixel evaluated before it stopped, n_support
    [H][W] evaluated entries with alpha >= 1/255 (including the one that
-   stopped the pixel). */
+   stopped the pixel). trans_dev [H][W] (optional, WAVE raster only): the
+   final transmittance T itself (alpha = 1 - T loses its low bits), which
+   tgs_rasterize_backward can take instead of repeating the forward walk. */
 TGS_API tgs_status tgs_rasterize(const tgs_projected* projected, const tgs_binned* binned,
                          const tgs_camera* camera, const tgs_params* params, int32_t order,
                          const float* bg, float* rgb_dev, float* alpha_dev, int32_t* last_dev,
                          int32_t* n_contrib_dev, int32_t* n_visit_dev, int32_t* n_support_dev,
-                         void* stream);
+                         float* trans_dev, void* stream);
 
 /* Gradient lines of tgs_rasterize_backward: [n][12] fp32 per Gaussian,
    dL/d of the splat's mean_x, mean_y (the mean hi + lo), conic_a, conic_b,
@@ -225,15 +227,18 @@ TGS_API tgs_status tgs_rasterize(const tgs_projected* projected, const tgs_binne
    (tgs_bin output of `order`, unchanged since), camera, params and bg:
    given d_rgb [H][W][3] = dL/d rgb and d_alpha [H][W] = dL/d alpha (NULL =
    zero), writes d_splats [n][TGS_GRAD_WORDS] (overwritten; entries of
-   Gaussians that no pixel composited are zero). The per-pixel traversal is
-   recomputed from the stream, so no forward output is needed. Gradients
+   Gaussians that no pixel composited are zero). trans_dev and last_dev
+   [H][W]: the forward's final transmittance and last position (both from a
+   tgs_rasterize of the same stream, WAVE raster), or both NULL, when the
+   per-pixel forward walk is recomputed from the stream instead. Gradients
    are summed with float atomics: the summation order, and so the last bits,
    may differ between runs. With the overflow flag set in counters[2] the
    result is all zero. */
 TGS_API tgs_status tgs_rasterize_backward(const tgs_projected* projected, const tgs_binned* binned,
                                   const tgs_camera* camera, const tgs_params* params, int32_t order,
                                   const float* bg, const float* d_rgb_dev, const float* d_alpha_dev,
-                                  float* d_splats_dev, void* stream);
+                                  const float* trans_dev, const int32_t* last_dev, float* d_splats_dev,
+                                  void* stream);
 
 /* Parameter gradients, device pointers, fp32, in the layouts of
    tgs_gaussians (sh: [n][(D+1)^2][3]); every element is overwritten. */

@@ -86,10 +86,10 @@ def lib():
                               P(ctypes.c_int64), _c_p]
         L.tgs_bin.restype = ctypes.c_int
         L.tgs_rasterize.argtypes = [P(Projected), P(Binned), P(Camera), P(Params), ctypes.c_int32,
-                                    P(ctypes.c_float), _c_p, _c_p, _c_p, _c_p, _c_p, _c_p, _c_p]
+                                    P(ctypes.c_float), _c_p, _c_p, _c_p, _c_p, _c_p, _c_p, _c_p, _c_p]
         L.tgs_rasterize.restype = ctypes.c_int
         L.tgs_rasterize_backward.argtypes = [P(Projected), P(Binned), P(Camera), P(Params), ctypes.c_int32,
-                                             P(ctypes.c_float), _c_p, _c_p, _c_p, _c_p]
+                                             P(ctypes.c_float), _c_p, _c_p, _c_p, _c_p, _c_p, _c_p]
         L.tgs_rasterize_backward.restype = ctypes.c_int
         L.tgs_project_backward.argtypes = [P(Gaussians), P(Camera), _c_p, P(GaussianGrads), _c_p]
         L.tgs_project_backward.restype = ctypes.c_int

@@ -190,9 +190,10 @@ class Renderer:
             return b
         raise L.TileGSError(L.TGS_ERR_CAPACITY, "capacity still exceeded after growing")
 
-    def rasterize(self, splats, info, binned, bg=(0.0, 0.0, 0.0), counts=False, out=None):
+    def rasterize(self, splats, info, binned, bg=(0.0, 0.0, 0.0), counts=False, out=None, trans=False):
         """tgs_rasterize: dict with rgb [H, W, 3], alpha [H, W], last [H, W]
-        (and n_contrib, n_visit, n_support when counts)."""
+        (and n_contrib, n_visit, n_support when counts; the final
+        transmittance `trans` [H, W] when trans)."""
         H, W = int(self.cam["height"]), int(self.cam["width"])
         if out is None:
             out = {
@@ -204,19 +205,24 @@ class Renderer:
                 out["n_contrib"] = torch.empty((H, W), dtype=torch.int32, device=self.device)
                 out["n_visit"] = torch.empty((H, W), dtype=torch.int32, device=self.device)
                 out["n_support"] = torch.empty((H, W), dtype=torch.int32, device=self.device)
+            if trans:
+                out["trans"] = torch.empty((H, W), dtype=torch.float32, device=self.device)
         n = int(splats.shape[0])
         pr = L.Projected(_ptr(splats).value, _ptr(info).value, n)
         bgc = (ctypes.c_float * 3)(*[float(v) for v in bg])
         L.check(L.lib().tgs_rasterize(ctypes.byref(pr), ctypes.byref(binned.c()), ctypes.byref(self.ccam),
                                       ctypes.byref(self.cparams), binned.order, bgc, _ptr(out["rgb"]),
                                       _ptr(out["alpha"]), _ptr(out["last"]), _ptr(out.get("n_contrib")),
-                                      _ptr(out.get("n_visit")), _ptr(out.get("n_support")), _stream()))
+                                      _ptr(out.get("n_visit")), _ptr(out.get("n_support")), _ptr(out.get("trans")),
+                                      _stream()))
         return out
 
-    def rasterize_backward(self, splats, info, binned, d_rgb, d_alpha=None, bg=(0.0, 0.0, 0.0), out=None):
+    def rasterize_backward(self, splats, info, binned, d_rgb, d_alpha=None, bg=(0.0, 0.0, 0.0), out=None,
+                           saved=None):
         """tgs_rasterize_backward: gradient lines [n, 12] (dL/d mean_x, mean_y,
         conic a, b, c, opacity, r, g, b, 0, 0, 0) from dL/d rgb [H, W, 3] and
-        dL/d alpha [H, W] (None = zero)."""
+        dL/d alpha [H, W] (None = zero). saved: the forward's output dict
+        with "trans" and "last" (skips the recomputed forward walk)."""
         n = int(splats.shape[0])
         if out is None:
             out = torch.empty((n, L.GRAD_WORDS), dtype=torch.float32, device=self.device)
@@ -224,9 +230,11 @@ class Renderer:
         d_alpha = None if d_alpha is None else d_alpha.contiguous().float()
         pr = L.Projected(_ptr(splats).value, _ptr(info).value, n)
         bgc = (ctypes.c_float * 3)(*[float(v) for v in bg])
+        tr = None if saved is None else saved["trans"]
+        la = None if saved is None else saved["last"]
         L.check(L.lib().tgs_rasterize_backward(ctypes.byref(pr), ctypes.byref(binned.c()), ctypes.byref(self.ccam),
                                                ctypes.byref(self.cparams), binned.order, bgc, _ptr(d_rgb),
-                                               _ptr(d_alpha), _ptr(out), _stream()))
+                                               _ptr(d_alpha), _ptr(tr), _ptr(la), _ptr(out), _stream()))
         return out
 
     def render(self, g, order="binned", bg=(0.0, 0.0, 0.0), counts=False):
@@ -268,8 +276,10 @@ class _RenderFn(torch.autograd.Function):
              "logits": logits.contiguous(), "sh": sh.contiguous(), "sh_degree": int(sh_degree)}
         splats, info = project(g, renderer.cam, renderer.params)
         binned = renderer.bin(splats, info, order, fresh=True)
-        out = renderer.rasterize(splats, info, binned, bg=bg)
+        wave = renderer.params.raster == "wave"
+        out = renderer.rasterize(splats, info, binned, bg=bg, trans=wave)
         ctx.renderer, ctx.binned, ctx.bg, ctx.g = renderer, binned, bg, g
+        ctx.saved = {"trans": out["trans"], "last": out["last"]} if wave else None
         ctx.save_for_backward(splats, info)
         return out["rgb"], out["alpha"]
 
@@ -279,7 +289,7 @@ class _RenderFn(torch.autograd.Function):
         r = ctx.renderer
         if d_rgb is None:
             d_rgb = torch.zeros((int(r.cam["height"]), int(r.cam["width"]), 3), device=splats.device)
-        d_splats = r.rasterize_backward(splats, info, ctx.binned, d_rgb, d_alpha, bg=ctx.bg)
+        d_splats = r.rasterize_backward(splats, info, ctx.binned, d_rgb, d_alpha, bg=ctx.bg, saved=ctx.saved)
         gr = project_backward(ctx.g, r.cam, d_splats)
         return gr["means"], gr["log_scales"], gr["quats"], gr["logits"], gr["sh"], None, None, None, None
 

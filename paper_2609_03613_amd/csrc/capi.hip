@@ -308,7 +308,7 @@ tgs_status tgs_bin(const tgs_projected* pr, const tgs_camera* cam, const tgs_par
 
 tgs_status tgs_rasterize(const tgs_projected* pr, const tgs_binned* b, const tgs_camera* cam, const tgs_params* params,
                          int32_t order, const float* bg, float* rgb, float* alpha, int32_t* last, int32_t* n_contrib,
-                         int32_t* n_visit, int32_t* n_support, void* stream) {
+                         int32_t* n_visit, int32_t* n_support, float* trans, void* stream) {
     g_err.clear();
     tgs_status st = check_projected(pr);
     if (st) return st;
@@ -351,6 +351,8 @@ tgs_status tgs_rasterize(const tgs_projected* pr, const tgs_binned* b, const tgs
     a.n_contrib = n_contrib;
     a.n_visit = n_visit;
     a.n_support = n_support;
+    a.trans = trans;
+    if (trans && params->raster != TGS_RASTER_WAVE) return fail(TGS_ERR_UNSUPPORTED, "trans needs the WAVE raster");
     hipStream_t s = (hipStream_t)stream;
     if (params->raster == TGS_RASTER_PLAIN)
         TGS_HIP(launch_raster_plain(a, s), "raster");
@@ -361,7 +363,8 @@ tgs_status tgs_rasterize(const tgs_projected* pr, const tgs_binned* b, const tgs
 
 tgs_status tgs_rasterize_backward(const tgs_projected* pr, const tgs_binned* b, const tgs_camera* cam,
                                   const tgs_params* params, int32_t order, const float* bg, const float* d_rgb,
-                                  const float* d_alpha, float* d_splats, void* stream) {
+                                  const float* d_alpha, const float* trans_in, const int32_t* last_in,
+                                  float* d_splats, void* stream) {
     g_err.clear();
     tgs_status st = check_projected(pr);
     if (st) return st;
@@ -371,6 +374,8 @@ tgs_status tgs_rasterize_backward(const tgs_projected* pr, const tgs_binned* b, 
     if (!b || !b->offsets_dev || !b->counters_dev) return fail(TGS_ERR_INVALID_ARG, "binned buffers are NULL");
     if (!bg || !d_rgb) return fail(TGS_ERR_INVALID_ARG, "bg or d_rgb is NULL");
     if (pr->n > 0 && !d_splats) return fail(TGS_ERR_INVALID_ARG, "d_splats is NULL");
+    if ((trans_in == nullptr) != (last_in == nullptr))
+        return fail(TGS_ERR_INVALID_ARG, "give both trans and last, or neither");
     RasterArgs a{};
     a.splats = pr->splats_dev;
     a.offsets = b->offsets_dev;
@@ -396,7 +401,7 @@ tgs_status tgs_rasterize_backward(const tgs_projected* pr, const tgs_binned* b, 
     hipStream_t s = (hipStream_t)stream;
     if (pr->n == 0) return TGS_OK;
     TGS_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(d_splats), 0u, pr->n * kGradWords, s), "fill");
-    TGS_HIP(launch_raster_backward(a, d_rgb, d_alpha, d_splats, s), "raster backward");
+    TGS_HIP(launch_raster_backward(a, d_rgb, d_alpha, trans_in, last_in, d_splats, s), "raster backward");
     return TGS_OK;
 }
 

@@ -325,6 +325,7 @@ struct RasterArgs {
     int32_t* n_contrib;
     int32_t* n_visit;
     int32_t* n_support;
+    float* trans;           // final transmittance [H][W] (optional)
 };
 hipError_t launch_raster_plain(const RasterArgs& a, hipStream_t s);
 hipError_t launch_raster_wave(const RasterArgs& a, hipStream_t s);
@@ -370,8 +371,8 @@ constexpr int kGradWords = 12;
 
 // dL/d(splat) into d_splats [n][kGradWords], which must be zero (float
 // atomics accumulate into it).
-hipError_t launch_raster_backward(const RasterArgs& a, const float* d_rgb, const float* d_alpha, float* d_splats,
-                                  hipStream_t s);
+hipError_t launch_raster_backward(const RasterArgs& a, const float* d_rgb, const float* d_alpha,
+                                  const float* trans_in, const int32_t* last_in, float* d_splats, hipStream_t s);
 // Parameter gradients from the gradient lines; every output is overwritten.
 hipError_t launch_project_backward(const tgs_gaussians& g, const Cam& cam, const float* d_splats,
                                    const tgs_gaussian_grads& out, hipStream_t s);

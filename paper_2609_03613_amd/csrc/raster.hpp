@@ -60,6 +60,7 @@ __device__ __forceinline__ void write_pixel(const RasterArgs& A, int x, int y, c
         A.rgb[3 * i] = nan; A.rgb[3 * i + 1] = nan; A.rgb[3 * i + 2] = nan;
         A.alpha[i] = nan;
         A.last[i] = -1;
+        if (A.trans) A.trans[i] = nan;
         if (A.n_contrib) A.n_contrib[i] = 0;
         if (A.n_visit) A.n_visit[i] = 0;
         if (A.n_support) A.n_support[i] = 0;
@@ -70,6 +71,7 @@ __device__ __forceinline__ void write_pixel(const RasterArgs& A, int x, int y, c
     A.rgb[3 * i + 2] = p.b + p.T * A.bg[2];
     A.alpha[i] = 1.0f - p.T;
     A.last[i] = p.last;
+    if (A.trans) A.trans[i] = p.T;
     if (A.n_contrib) A.n_contrib[i] = p.ncon;
     if (A.n_visit) A.n_visit[i] = p.nvis;
     if (A.n_support) A.n_support[i] = p.nsup;

@@ -6,7 +6,8 @@
 // Each 64-lane wavefront owns one 8x8 pixel block, as in the forward WAVE
 // raster. Pass 1 repeats the forward walk (same staging, culling and blend,
 // so the final transmittance and the last composited position come out
-// bit-identical to the forward's). Pass 2 walks the range backwards from
+// bit-identical to the forward's), unless the forward's saved final
+// transmittance and last position are given. Pass 2 walks the range backwards from
 // the largest last position in the block, 64 entries at a time, with the
 // same block cull and LDS compaction; each lane recovers the transmittance
 // in front of an entry by dividing by the same binary32 (1 - alpha) the
@@ -69,6 +70,8 @@ constexpr float kLn2 = 0.69314718055994531f;
 template <int SRC>
 __global__ void __launch_bounds__(256) raster_bwd_kernel(RasterArgs A, const float* __restrict__ d_rgb,
                                                          const float* __restrict__ d_alpha,
+                                                         const float* __restrict__ trans_in,
+                                                         const int32_t* __restrict__ last_in,
                                                          float* __restrict__ d_splats) {
 #pragma clang fp contract(off)
     __shared__ Staged stage[4][kWave];
@@ -90,9 +93,17 @@ __global__ void __launch_bounds__(256) raster_bwd_kernel(RasterArgs A, const flo
     Staged* st = stage[w];
     uint32_t* idw = ids[w];
 
-    // pass 1: the forward walk
+    // pass 1: the forward walk, or the forward's saved T and last
     Pix p{1.0f, 0.f, 0.f, 0.f, -1, 0, 0, 0, !inside};
-    wave_forward<SRC, false>(A, st, wb.bi, begin, end, ox, oy, px, py, xa, xb, ya, yb, p);
+    if (trans_in) {
+        if (inside) {
+            const int64_t i = (int64_t)y * A.width + x;
+            p.T = trans_in[i];
+            p.last = last_in[i];
+        }
+    } else {
+        wave_forward<SRC, false>(A, st, wb.bi, begin, end, ox, oy, px, py, xa, xb, ya, yb, p);
+    }
 
     // pass 2: backwards from the last composited entry
     const int hi = wave_max_i32(p.last);
@@ -184,16 +195,18 @@ __global__ void __launch_bounds__(256) raster_bwd_kernel(RasterArgs A, const flo
 
 }  // namespace
 
-hipError_t launch_raster_backward(const RasterArgs& a, const float* d_rgb, const float* d_alpha, float* d_splats,
-                                  hipStream_t s) {
+hipError_t launch_raster_backward(const RasterArgs& a, const float* d_rgb, const float* d_alpha,
+                                  const float* trans_in, const int32_t* last_in, float* d_splats, hipStream_t s) {
     const int T = a.tiles_x * a.tiles_y;
     if (T == 0) return hipSuccess;
     const int B = blocks_per_tile(a.tile), G = groups_per_tile(a.tile);
     const dim3 grid((unsigned)(T * G)), block((unsigned)(kWave * (B < 4 ? B : 4)));
     if (a.vals)
-        hipLaunchKernelGGL((raster_bwd_kernel<SRC_VALS>), grid, block, 0, s, a, d_rgb, d_alpha, d_splats);
+        hipLaunchKernelGGL((raster_bwd_kernel<SRC_VALS>), grid, block, 0, s, a, d_rgb, d_alpha, trans_in, last_in,
+                           d_splats);
     else
-        hipLaunchKernelGGL((raster_bwd_kernel<SRC_PAIRS>), grid, block, 0, s, a, d_rgb, d_alpha, d_splats);
+        hipLaunchKernelGGL((raster_bwd_kernel<SRC_PAIRS>), grid, block, 0, s, a, d_rgb, d_alpha, trans_in, last_in,
+                           d_splats);
     return hipGetLastError();
 }
 

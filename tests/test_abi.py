@@ -120,7 +120,7 @@ def test_rasterize_argument_errors():
     b = L.Binned(0, None, None, None, None, None, None, None, None)
     bg = (ctypes.c_float * 3)(0, 0, 0)
     st, msg = status_of(lib.tgs_rasterize, ctypes.byref(pr), ctypes.byref(b), ctypes.byref(c), ctypes.byref(p),
-                        L.ORDER_BINNED, bg, None, None, None, None, None, None, None)
+                        L.ORDER_BINNED, bg, None, None, None, None, None, None, None, None)
     assert st == L.TGS_ERR_INVALID_ARG
 
 
@@ -135,20 +135,23 @@ def test_backward_argument_errors():
     bg = (ctypes.c_float * 3)(0, 0, 0)
     rb = lib.tgs_rasterize_backward
     st, msg = status_of(rb, ctypes.byref(pr), None, ctypes.byref(c), ctypes.byref(p), L.ORDER_BINNED, bg, fake, None,
-                        fake, None)
+                        None, None, fake, None)
     assert st == L.TGS_ERR_INVALID_ARG and "binned" in msg
     st, msg = status_of(rb, ctypes.byref(pr), ctypes.byref(b), ctypes.byref(c), ctypes.byref(p), L.ORDER_BINNED, bg,
-                        None, None, fake, None)
+                        None, None, None, None, fake, None)
     assert st == L.TGS_ERR_INVALID_ARG and "d_rgb" in msg
     st, msg = status_of(rb, ctypes.byref(pr), ctypes.byref(b), ctypes.byref(c), ctypes.byref(p), L.ORDER_BINNED, bg,
-                        fake, None, None, None)
+                        fake, None, None, None, None, None)
     assert st == L.TGS_ERR_INVALID_ARG and "d_splats" in msg
+    st, msg = status_of(rb, ctypes.byref(pr), ctypes.byref(b), ctypes.byref(c), ctypes.byref(p), L.ORDER_BINNED, bg,
+                        fake, None, fake, None, fake, None)
+    assert st == L.TGS_ERR_INVALID_ARG and "trans" in msg
     st, msg = status_of(rb, ctypes.byref(pr), ctypes.byref(b), ctypes.byref(c), ctypes.byref(p), 7, bg, fake, None,
-                        None, None)
+                        None, None, None, None)
     assert st == L.TGS_ERR_INVALID_ARG and "order" in msg
     b.pairs = None
     st, msg = status_of(rb, ctypes.byref(pr), ctypes.byref(b), ctypes.byref(c), ctypes.byref(p), L.ORDER_BINNED, bg,
-                        fake, None, None, None)
+                        fake, None, None, None, None, None)
     assert st == L.TGS_ERR_INVALID_ARG
     pb = lib.tgs_project_backward
     gr = L.GaussianGrads(fake, fake, fake, fake, fake)

@@ -124,6 +124,26 @@ def test_raster_backward_tile_sizes(ts):
         assert max(e) <= GRAD_TOL, (ts, order, e)
 
 
+def test_raster_backward_from_saved_forward_state():
+    # the forward's saved transmittance and last position replace the
+    # recomputed walk: same gradients up to the atomic summation order
+    W, H, n = 150, 100, 3000
+    splats, info = scenes.random_splats(n, W, H, seed=12, max_sigma_px=16.0)
+    cam = cam_for(W, H)
+    r = tg.Renderer(cam, device=dev())
+    s = torch.as_tensor(splats).to(dev())
+    i = torch.as_tensor(info.view(np.int32)).to(dev())
+    b = r.bin(s, i, "binned")
+    fwd = r.rasterize(s, i, b, bg=(0.3, 0.2, 0.1), trans=True)
+    assert torch.allclose(1.0 - fwd["trans"], fwd["alpha"])
+    d = torch.as_tensor(np.random.default_rng(2).normal(size=(H, W, 3)).astype(np.float32)).to(dev())
+    da = torch.as_tensor(np.random.default_rng(3).normal(size=(H, W)).astype(np.float32)).to(dev())
+    g1 = to_np(r.rasterize_backward(s, i, b, d, da, bg=(0.3, 0.2, 0.1)))
+    g2 = to_np(r.rasterize_backward(s, i, b, d, da, bg=(0.3, 0.2, 0.1), saved=fwd))
+    torch.cuda.synchronize()
+    assert grad_err(g2[:, :9], g1[:, :9]) <= 1e-4
+
+
 def test_raster_backward_without_alpha_gradient_and_repeat():
     W, H, n = 64, 48, 500
     splats, info = scenes.random_splats(n, W, H, seed=7)
