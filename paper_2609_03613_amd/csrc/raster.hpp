@@ -159,18 +159,17 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Composites the cnt staged survivors of st[], reading the next one from LDS
-// while the current one is evaluated.
+// Composites the cnt staged survivors of st[], two at a time (both read from
+// LDS before the first is evaluated).
 template <bool COUNT>
 __device__ __forceinline__ void composite_staged(Pix& p, float px, float py, const Staged* st, int cnt) {
-    if (cnt == 0) return;
-    Staged cur = st[0];
-    for (int j = 1; j < cnt; ++j) {
-        const Staged nxt = st[j];
-        blend<COUNT>(p, px, py, cur);
-        cur = nxt;
+    int j = 0;
+    for (; j + 2 <= cnt; j += 2) {
+        const Staged s0 = st[j], s1 = st[j + 1];
+        blend<COUNT>(p, px, py, s0);
+        blend<COUNT>(p, px, py, s1);
     }
-    blend<COUNT>(p, px, py, cur);
+    if (j < cnt) blend<COUNT>(p, px, py, st[j]);
 }
 
 
