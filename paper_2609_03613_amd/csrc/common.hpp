@@ -101,13 +101,15 @@ __device__ __forceinline__ void stage_splat(const float4& a, const float4& b, co
 // the mean is inside, otherwise the smallest of the four edge minima. The
 // margin exceeds the binary32 error of both this bound and the per-pixel
 // evaluation, so a block that fails the test fails the alpha >= 1/255 test
-// at every one of its pixels.
+// at every one of its pixels. The edge minimisers use the hardware
+// reciprocal: an edge point that misses the exact minimiser by a relative
+// 1e-7 raises q only by c (1e-7 e)^2, far inside the margin.
 __device__ __forceinline__ bool block_may_touch(float mx, float my, float a, float b, float c, float o, float xa,
                                                 float xb, float ya, float yb) {
     const float dxl = mx - xb, dxh = mx - xa, dyl = my - yb, dyh = my - ya;
     float qmin = 0.0f;
     if (!(dxl <= 0.0f && dxh >= 0.0f && dyl <= 0.0f && dyh >= 0.0f)) {
-        const float ic = 1.0f / c, ia = 1.0f / a;
+        const float ic = __builtin_amdgcn_rcpf(c), ia = __builtin_amdgcn_rcpf(a);
         qmin = INFINITY;
         {
             const float d = dxl, e = fminf(fmaxf(-b * d * ic, dyl), dyh);
