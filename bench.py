@@ -26,8 +26,12 @@ import numpy as np  # noqa: E402
 
 import scenes  # noqa: E402
 
-# MI355X: 256 CUs x 64 lanes x 2.4 GHz of non-packed fp32 VALU issue
-PEAK_LANE_OPS = 256 * 64 * 2.4e9
+# MI355X fp32 vector peak 157.3 TFLOP/s = 256 CUs x 128 FMA lanes x 2 FLOP x
+# 2.4 GHz; counting one lane-op per VALU lane operation (an FMA is one),
+# 256 x 128 x 2.4e9 = 78.6e12 lane-op/s. (Measured wave64 VALU issue of the
+# rasters exceeds one instruction per CU per cycle, so 64 lanes per cycle is
+# not the bound.)
+PEAK_LANE_OPS = 256 * 128 * 2.4e9
 # algorithmic lane-op slots per alpha-supported pixel test: 2 sub (dx, dy),
 # 5 for q, 1 mul (opacity), 2 compares, 1 min, 2 for T (1 - alpha), 1 mul
 # (weight), 3 fma (colour); exp2 on the quarter-rate transcendental unit = 4
@@ -45,7 +49,7 @@ def profiled_traffic():
     if not os.path.exists(path):
         return None
     h = hashlib.sha256()
-    for f in ("raster.hip", "common.hpp"):
+    for f in ("raster.hip", "raster.hpp", "common.hpp"):
         with open(os.path.join(ROOT, "paper_2609_03613_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     text = open(path).read()
