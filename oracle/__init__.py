@@ -58,6 +58,12 @@ def lib():
         L.orc_schedule.argtypes = [i64, P, P, i32, i32, i32, i32, dbl, dbl, flt, flt, flt,
                                    P, P, P, P, P, P]
         L.orc_schedule_tiles.argtypes = [i64, P, P, i32, i32, P, i32, dbl, dbl, flt, flt, flt, P, P, P, P]
+        L.orc_near_keys.argtypes = [i64, P, P, flt, flt, flt, flt, P]
+        L.orc_schedule_keyed.argtypes = [i64, P, P, P, i32, i32, i32, i32, dbl, dbl, flt, flt, flt, P, P, P]
+        L.orc_repair_select.argtypes = [i64, i32, P, dbl, P]
+        L.orc_repair_select.restype = i64
+        L.orc_render_stream.argtypes = [i64, P, P, P, P, P, i32, i32, i32, P, P, P, i64, P,
+                                        P, P, P, P, P, P, P, P]
         L.orc_adjoint.argtypes = [i64, P, P, P, P, P, i32, P, i32, P, P, P, P, P, P, P, P, P, P, P]
         L.orc_composite_adjoint.argtypes = [i64, P, P, P, P, P, P, P, i32, i32, i32, P, P, P, P, P, P]
         _lib = L
@@ -109,6 +115,8 @@ def project(g, cam, tile_size=16):
                            _p(out["conic"]), _p(out["depth"]), _p(out["opacity"]), _p(out["rgb"]),
                            _p(out["rect"]), _p(out["depth_key"]), _p(out["flags"]))
     assert rc == 0, rc
+    # largest activated axis scale, the s_max of the near-depth binning key
+    out["smax"] = np.exp(ls.astype(np.float64).max(axis=1)).astype(np.float32)
     return out
 
 
@@ -132,6 +140,38 @@ def render(proj, width, height, tile_size=16, bg=(0.0, 0.0, 0.0), pix=None, mode
                           int(height), int(tile_size), _p(_c(bg, np.float64)), npix, _p(pixa),
                           _p(out["rgb"]), _p(out["alpha"]), _p(out["last_gid"]), _p(out["last_pos"]),
                           _p(out["ncontrib"]), _p(out["nvisit"]), _p(out["nsupport"]), _p(out["flags"]))
+    assert rc == 0, rc
+    if pix is None:
+        for k in list(out):
+            v = out[k]
+            out[k] = v.reshape((height, width) + v.shape[1:])
+    return out
+
+
+def render_stream(proj, width, height, tile_offsets, ids, tile_size=16, bg=(0.0, 0.0, 0.0), pix=None):
+    """Composite each tile's pixels over the Gaussian ids of its range
+    ids[tile_offsets[t]:tile_offsets[t + 1]] in the listed order."""
+    n = proj["mean2d"].shape[0]
+    npix = width * height if pix is None else len(pix)
+    pixa = None if pix is None else _c(pix, np.int32)
+    off = _c(tile_offsets, np.uint32)
+    tiles = ((width + tile_size - 1) // tile_size) * ((height + tile_size - 1) // tile_size)
+    assert off.shape == (tiles + 1,)
+    idv = _c(ids, np.uint32)
+    assert len(idv) >= int(off[-1])
+    out = {
+        "rgb": np.zeros((npix, 3)), "alpha": np.zeros(npix), "last_gid": np.zeros(npix, np.int64),
+        "last_pos": np.zeros(npix, np.int64), "ncontrib": np.zeros(npix, np.int32),
+        "nvisit": np.zeros(npix, np.int32), "nsupport": np.zeros(npix, np.int32),
+        "flags": np.zeros(npix, np.uint8),
+    }
+    flags = None if proj.get("flags") is None else _c(proj["flags"], np.uint8)
+    rc = lib().orc_render_stream(n, _p(_c(proj["mean2d"], np.float64)), _p(_c(proj["conic"], np.float64)),
+                                 _p(_c(proj["opacity"], np.float64)), _p(_c(proj["rgb"], np.float64)), _p(flags),
+                                 int(width), int(height), int(tile_size), _p(_c(bg, np.float64)), _p(off), _p(idv),
+                                 npix, _p(pixa), _p(out["rgb"]), _p(out["alpha"]), _p(out["last_gid"]),
+                                 _p(out["last_pos"]), _p(out["ncontrib"]), _p(out["nvisit"]), _p(out["nsupport"]),
+                                 _p(out["flags"]))
     assert rc == 0, rc
     if pix is None:
         for k in list(out):
@@ -196,6 +236,45 @@ def schedule(depth, rect, tiles_x, tiles_y, K=64, S=8192, p_lo=1.0, p_hi=99.0, p
     assert rc == 0, rc
     out["M"] = M
     return out
+
+
+def near_keys(depth, smax, alpha=1.0, gamma=0.25, znear=0.01, zfar=1e10):
+    """Near-depth binning keys (binary32) of the Gaussians."""
+    d = _c(depth, np.float32)
+    out = np.zeros(len(d), np.float32)
+    lib().orc_near_keys(len(d), _p(d), _p(_c(smax, np.float32)), float(alpha), float(gamma), float(znear),
+                        float(zfar), _p(out))
+    return out
+
+
+def schedule_keyed(depth, bin_depth, rect, tiles_x, tiles_y, K=64, S=8192, p_lo=1.0, p_hi=99.0, pad=0.05,
+                   znear=0.01, zfar=1e10):
+    """Binned schedule with the bins (and the depth range) formed on
+    ``bin_depth`` and every segment sorted by (depth bits, id): zrange,
+    bin_offsets [T K + 1], stream [M]."""
+    depth = _c(depth, np.float32)
+    bd = _c(bin_depth, np.float32)
+    rect = _c(rect, np.int32)
+    M = count_entries(rect)
+    T = tiles_x * tiles_y
+    out = {"zrange": np.zeros(2, np.float32), "bin_offsets": np.zeros(T * K + 1, np.uint32),
+           "stream": np.zeros(M, np.uint64)}
+    rc = lib().orc_schedule_keyed(len(depth), _p(depth), _p(bd), _p(rect), int(tiles_x), int(tiles_y), int(K),
+                                  int(S), float(p_lo), float(p_hi), float(pad), float(znear), float(zfar),
+                                  _p(out["zrange"]), _p(out["bin_offsets"]), _p(out["stream"]))
+    assert rc == 0, rc
+    out["M"] = M
+    return out
+
+
+def repair_select(bin_offsets, T, K, budget_frac=0.25):
+    """Selected segments (uint8 [T K]) and the selected entry count of the
+    rule-based, budgeted repair selection."""
+    off = _c(bin_offsets, np.uint32)
+    assert off.shape == (T * K + 1,)
+    sel = np.zeros(T * K, np.uint8)
+    used = int(lib().orc_repair_select(int(T), int(K), _p(off), float(budget_frac), _p(sel)))
+    return sel, used
 
 
 def schedule_tiles(depth, rect, tiles_x, tiles_y, per_tile_bins, S=8192, p_lo=1.0, p_hi=99.0, pad=0.05,

@@ -446,6 +446,46 @@ ORC_EXPORT int orc_render(int64_t n, const double* mean2d, const double* conic, 
     return err;
 }
 
+/*
+ * Render over a given per-tile traversal order instead of the depth order:
+ * tile t's pixels walk ids[tile_offsets[t] .. tile_offsets[t+1]) front to
+ * back in the order listed (the binned order of a schedule whose bins are
+ * not monotone in the depth, section "Repair for correctness"). Same outputs
+ * as orc_render in tiled mode; last_pos is the position in ids.
+ */
+ORC_EXPORT int orc_render_stream(int64_t n, const double* mean2d, const double* conic, const double* opacity,
+                                 const double* rgb, const uint8_t* gflags, int width, int height, int tile_size,
+                                 const double* bg, const uint32_t* tile_offsets, const uint32_t* ids, int64_t npix,
+                                 const int32_t* pix, double* out_rgb, double* out_alpha, int64_t* out_last_gid,
+                                 int64_t* out_last_pos, int32_t* out_ncontrib, int32_t* out_nvisit,
+                                 int32_t* out_nsupport, uint8_t* out_flags) {
+    if (n < 0 || width <= 0 || height <= 0 || tile_size <= 0) return 1;
+    const int64_t P = pix ? npix : (int64_t)width * height;
+    const int tiles_x = (width + tile_size - 1) / tile_size;
+    const int tiles_y = (height + tile_size - 1) / tile_size;
+    const int64_t T = (int64_t)tiles_x * tiles_y;
+    const int64_t M = tile_offsets[T];
+    ord_t* lists = (ord_t*)malloc((size_t)(M > 0 ? M : 1) * sizeof(ord_t));
+    if (!lists) return 2;
+    for (int64_t i = 0; i < M; ++i) {
+        if (ids[i] >= (uint64_t)n) { free(lists); return 1; }
+        lists[i].key = 0.0f;
+        lists[i].gid = ids[i];
+    }
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t p = 0; p < P; ++p) {
+        int x = pix ? pix[2 * p] : (int)(p % width);
+        int y = pix ? pix[2 * p + 1] : (int)(p / width);
+        int64_t t = (int64_t)(y / tile_size) * tiles_x + x / tile_size;
+        composite_pixel(lists + tile_offsets[t], (int64_t)tile_offsets[t + 1] - tile_offsets[t], tile_offsets[t],
+                        x + 0.5, y + 0.5, mean2d, conic, opacity, rgb, gflags, bg, out_rgb + 3 * p,
+                        out_alpha + p, out_last_gid + p, out_last_pos + p, out_ncontrib + p, out_nvisit + p,
+                        out_nsupport + p, out_flags + p);
+    }
+    free(lists);
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Integer schedule: keys, global order, depth range, bins, offsets.        */
 /* ------------------------------------------------------------------------ */
@@ -565,7 +605,8 @@ ORC_EXPORT int orc_bin_of(float z, float zmin, float zmax, int K) { return bin_o
  * by (depth bits << 32 | id), the exact-repair order.
  * Any output pointer may be NULL.
  */
-static int schedule_impl(int64_t n, const float* depth, const int32_t* rect, int tiles_x, int tiles_y, int K,
+static int schedule_impl(int64_t n, const float* depth, const float* bin_depth, const int32_t* rect, int tiles_x,
+                         int tiles_y, int K,
                          const int32_t* per_tile_bins, int S, double p_lo, double p_hi, float pad, float znear,
                          float zfar, uint64_t* keys, uint32_t* vals, uint32_t* tile_offsets, float* zrange,
                          uint32_t* seg_base_out, uint32_t* bin_offsets, uint64_t* stream) {
@@ -600,7 +641,8 @@ static int schedule_impl(int64_t n, const float* depth, const int32_t* rect, int
         }
     }
     float zr[2];
-    int rc = orc_depth_range(n, depth, rect, S, p_lo, p_hi, pad, znear, zfar, zr);
+    const float* bd = bin_depth ? bin_depth : depth;
+    int rc = orc_depth_range(n, bd, rect, S, p_lo, p_hi, pad, znear, zfar, zr);
     if (rc) { free(e); free(sb); return rc; }
     if (zrange) { zrange[0] = zr[0]; zrange[1] = zr[1]; }
     if (bin_offsets || stream) {
@@ -615,7 +657,7 @@ static int schedule_impl(int64_t n, const float* depth, const int32_t* rect, int
             for (int y = rect[4 * g + 1]; y < rect[4 * g + 3]; ++y)
                 for (int x = rect[4 * g]; x < rect[4 * g + 2]; ++x) {
                     const int64_t t = (int64_t)y * tiles_x + x;
-                    cnt[sb[t] + bin_of(depth[g], zr[0], zr[1], (int)(sb[t + 1] - sb[t]))]++;
+                    cnt[sb[t] + bin_of(bd[g], zr[0], zr[1], (int)(sb[t + 1] - sb[t]))]++;
                 }
         off[0] = 0;
         for (int64_t s2 = 0; s2 < NS; ++s2) off[s2 + 1] = off[s2] + cnt[s2];
@@ -624,7 +666,7 @@ static int schedule_impl(int64_t n, const float* depth, const int32_t* rect, int
             for (int y = rect[4 * g + 1]; y < rect[4 * g + 3]; ++y)
                 for (int x = rect[4 * g]; x < rect[4 * g + 2]; ++x) {
                     const int64_t t = (int64_t)y * tiles_x + x;
-                    const int64_t s2 = sb[t] + bin_of(depth[g], zr[0], zr[1], (int)(sb[t + 1] - sb[t]));
+                    const int64_t s2 = sb[t] + bin_of(bd[g], zr[0], zr[1], (int)(sb[t + 1] - sb[t]));
                     st[cur[s2]++] = ((uint64_t)f32_bits(depth[g]) << 32) | (uint64_t)g;
                 }
         for (int64_t s2 = 0; s2 < NS; ++s2)
@@ -638,12 +680,92 @@ static int schedule_impl(int64_t n, const float* depth, const int32_t* rect, int
     return 0;
 }
 
+/*
+ * Near-depth binning key (supplement, Algorithm "Robust depth-range
+ * estimation", near-depth mode; the tile-local bin map takes the same key):
+ * z_key = z - min(alpha s_max, gamma z), with s_max the Gaussian's largest
+ * axis scale (world units). Binary32 arithmetic without contraction, the
+ * minimum taken as (a < b ? a : b). Readings: s_max is the largest of the
+ * three activated scales exp(log_scale); the clamp "using the near/far planes
+ * and epsilon" is to [max(znear, 1e-4), zfar]; with gamma < 1 every key of a
+ * visible Gaussian is positive, so the discard of keys <= 0 never applies.
+ */
+static float near_key(float z, float smax, float alpha, float gamma, float znear, float zfar) {
+    volatile float a = alpha * smax;
+    volatile float b = gamma * z;
+    float d = a < b ? a : b;
+    volatile float k = z - d;
+    float lo = znear > 1e-4f ? znear : 1e-4f;
+    float v = k;
+    if (v < lo) v = lo;
+    if (v > zfar) v = zfar;
+    return v;
+}
+
+ORC_EXPORT void orc_near_keys(int64_t n, const float* depth, const float* smax, float alpha, float gamma,
+                              float znear, float zfar, float* out) {
+    for (int64_t g = 0; g < n; ++g) out[g] = near_key(depth[g], smax[g], alpha, gamma, znear, zfar);
+}
+
+/*
+ * The binned schedule when bins are formed on another per-Gaussian key
+ * (bin_depth, e.g. the near-depth key) than the depth the baseline sorts by:
+ * the depth range is sampled from bin_depth and each entry's bin is that of
+ * its bin_depth, while the stream entries stay (depth bits << 32 | id) and
+ * each segment is sorted by them. bin_offsets[T*K+1], stream[M].
+ */
+ORC_EXPORT int orc_schedule_keyed(int64_t n, const float* depth, const float* bin_depth, const int32_t* rect,
+                                  int tiles_x, int tiles_y, int K, int S, double p_lo, double p_hi, float pad,
+                                  float znear, float zfar, float* zrange, uint32_t* bin_offsets, uint64_t* stream) {
+    return schedule_impl(n, depth, bin_depth, rect, tiles_x, tiles_y, K, NULL, S, p_lo, p_hi, pad, znear, zfar,
+                         NULL, NULL, NULL, zrange, NULL, bin_offsets, stream);
+}
+
+/*
+ * Selective repair selection (Table "Exact-repair selection rules" and the
+ * supplement's Algorithm "Selective repair selection and local exact
+ * sorting"): segments q = t K + b are visited in that order; a segment of
+ * length l >= 2 in a tile of l_tile entries is kept when any of
+ *   (i) l >= 320, (ii) l > 512, (iii) l / l_tile >= 45 %,
+ *   (iv) 129 <= l <= 256 and l / l_tile >= 10 %, (v) b < 2 and l >= 16
+ * holds, and a kept segment is selected when used + l <= B, B =
+ * floor(budget_frac M), after which used grows by l (first fit). Reading:
+ * the shares are compared in integers, 100 l >= 45 l_tile and 100 l >= 10
+ * l_tile. selected[T*K] gets 1 / 0; returns the selected entries (used).
+ */
+ORC_EXPORT int64_t orc_repair_select(int64_t T, int K, const uint32_t* bin_offsets, double budget_frac,
+                                     uint8_t* selected) {
+    const int64_t M = bin_offsets[T * K];
+    const int64_t B = (int64_t)floor(budget_frac * (double)M);
+    int64_t used = 0;
+    for (int64_t t = 0; t < T; ++t) {
+        const int64_t tile_len = (int64_t)bin_offsets[t * K + K] - bin_offsets[t * K];
+        for (int b = 0; b < K; ++b) {
+            const int64_t q = t * K + b;
+            const int64_t len = (int64_t)bin_offsets[q + 1] - bin_offsets[q];
+            selected[q] = 0;
+            if (len <= 1) continue;
+            int keep = 0;
+            if (len >= 320) keep = 1;                                    /* (i) */
+            if (len > 512) keep = 1;                                     /* (ii) */
+            if (100 * len >= 45 * tile_len) keep = 1;                    /* (iii) */
+            if (len >= 129 && len <= 256 && 100 * len >= 10 * tile_len) keep = 1; /* (iv) */
+            if (b < 2 && len >= 16) keep = 1;                            /* (v) */
+            if (keep && used + len <= B) {
+                selected[q] = 1;
+                used += len;
+            }
+        }
+    }
+    return used;
+}
+
 /* The schedule with K bins in every tile (bin_offsets[T*K+1]). */
 ORC_EXPORT int orc_schedule(int64_t n, const float* depth, const int32_t* rect, int tiles_x, int tiles_y,
                             int K, int S, double p_lo, double p_hi, float pad, float znear, float zfar,
                             uint64_t* keys, uint32_t* vals, uint32_t* tile_offsets, float* zrange,
                             uint32_t* bin_offsets, uint64_t* stream) {
-    return schedule_impl(n, depth, rect, tiles_x, tiles_y, K, NULL, S, p_lo, p_hi, pad, znear, zfar, keys, vals,
+    return schedule_impl(n, depth, NULL, rect, tiles_x, tiles_y, K, NULL, S, p_lo, p_hi, pad, znear, zfar, keys, vals,
                          tile_offsets, zrange, NULL, bin_offsets, stream);
 }
 
@@ -655,7 +777,7 @@ ORC_EXPORT int orc_schedule_tiles(int64_t n, const float* depth, const int32_t* 
     const int64_t T = (int64_t)tiles_x * tiles_y;
     for (int64_t t = 0; t < T; ++t)
         if (per_tile_bins[t] < 1) return 1;
-    return schedule_impl(n, depth, rect, tiles_x, tiles_y, 0, per_tile_bins, S, p_lo, p_hi, pad, znear, zfar, NULL,
+    return schedule_impl(n, depth, NULL, rect, tiles_x, tiles_y, 0, per_tile_bins, S, p_lo, p_hi, pad, znear, zfar, NULL,
                          NULL, NULL, zrange, seg_base, bin_offsets, stream);
 }
 
