@@ -74,6 +74,21 @@ enum { TGS_ORDER_GLOBAL = 0, TGS_ORDER_BINNED = 1 };
    and exits on its own. Both produce bit-identical images. */
 enum { TGS_RASTER_PLAIN = 0, TGS_RASTER_WAVE = 1 };
 
+/* Repair of the (tile, bin) segments of the BINNED order (section "Repair
+   for correctness"). ALL: every segment of two or more entries is sorted by
+   its (depth bits, id) pairs, which with near_shift = 0 makes the stream
+   equal to the globally sorted one, tile by tile. RULES: the paper's
+   selective repair (Table "Exact-repair selection rules" and the
+   supplement's Algorithm "Selective repair selection and local exact
+   sorting"): a segment of length l >= 2 is kept when l >= 320, l > 512,
+   100 l >= 45 l_tile, 129 <= l <= 256 and 100 l >= 10 l_tile, or bin < 2
+   and l >= 16 (l_tile: the entries of its tile); kept segments are taken in
+   (tile, bin) order while the taken entries stay within floor(repair_budget
+   M) (first fit) and only those are sorted. NONE: no segment is sorted.
+   With RULES and NONE, the entries of an unsorted segment keep the order of
+   the parallel scatter, which varies from call to call. */
+enum { TGS_REPAIR_ALL = 0, TGS_REPAIR_RULES = 1, TGS_REPAIR_NONE = 2 };
+
 /* Pinhole camera, host struct. p_cam = R p_world + t, R row-major, image x
    right, y down, z forward; pixel (i, j) is sampled at (i + 0.5, j + 0.5). */
 typedef struct {
@@ -104,7 +119,9 @@ typedef struct {
        (binary32 rounding of the pixel-space mean), mean_x_lo, mean_y_lo (the
        remainders, so hi + lo is the mean to about 1e-11 px), conic_a,
        conic_b, conic_c (inverse screen covariance, q = a dx^2 + 2 b dx dy +
-       c dy^2), opacity, r, g, b, then five zero words.
+       c dy^2), opacity, r, g, b, s_max (the largest axis scale
+       exp(log_scale), world units; read by tgs_bin with near_shift = 1),
+       then four zero words.
    info [n][4] uint32: depth (binary32 bits of the camera-space z, the
        ordering key), x0 | y0 << 16, x1 | y1 << 16 (half-open tile rect),
        number of tiles (x1 - x0) * (y1 - y0); an empty rect = invisible. */
@@ -139,6 +156,19 @@ typedef struct {
                              the prefix sum of the counts. The bin map of a
                              tile with K_t bins is the paper's log-depth map
                              with K_t in place of K; images are unchanged. */
+    int32_t repair;       /* BINNED: TGS_REPAIR_*, ALL by default; RULES and
+                             NONE need packed = 0, RULES also a uniform K */
+    float repair_budget;  /* RULES: the entry budget as a fraction of M,
+                             0.25; 0..1 */
+    int32_t near_shift;   /* BINNED: 0 (default) bins the depth z; 1 bins the
+                             near-depth key z - min(alpha s_max, gamma z),
+                             clamped to [max(znear, 1e-4), zfar], for both the
+                             depth range and the bin map (supplement,
+                             Algorithm "Robust depth-range estimation", and
+                             the paragraph after the log-depth bin map); the
+                             pairs keep the depth bits */
+    float shift_alpha;    /* alpha >= 0, 1.0 */
+    float shift_gamma;    /* gamma in [0, 1), 0.25 */
 } tgs_params;
 
 /* Entry buffers written by tgs_bin and read by tgs_rasterize. All device
@@ -153,7 +183,7 @@ typedef struct {
        0, 0), zrange [2] (the depth range).
    counters [4] int64: entries M, visible Gaussians V, overflow flag (1 when
        M > capacity: the stream was truncated and tgs_rasterize writes NaN),
-       reserved.
+       repaired entries (BINNED: the entries of the sorted segments).
    tile_order [T] (optional, NULL = none): tgs_bin writes the tiles in
        descending order of their entry count (grouped by the bit length of
        the count) and the WAVE raster dispatches tiles in that order, so the
@@ -161,7 +191,9 @@ typedef struct {
    seg_base [T + 1] (required with params.per_tile_bins_dev, else unused):
        tgs_bin writes the first segment of each tile, seg_base[T] = the
        number of segments S; offsets then holds S + 1 meaningful words (size
-       it for T * num_bins + 1). */
+       it for T * num_bins + 1).
+   repaired [T * K] (optional, NULL = none; BINNED, uniform K): 1 for every
+       segment tgs_bin sorted, else 0. */
 typedef struct {
     int64_t capacity;
     uint64_t* keys_dev;
@@ -174,10 +206,14 @@ typedef struct {
     int64_t* counters_dev;
     uint32_t* tile_order_dev;
     uint32_t* seg_base_dev;
+    uint8_t* repaired_dev;
 } tgs_binned;
 
 /* Fills the paper's defaults (16 px tiles, K = 64, S = 8192, 1st / 99th
-   percentiles, 5 % pad), the WAVE raster gathering by id (packed = 0). */
+   percentiles, 5 % pad, repair budget 0.25, shift alpha 1 and gamma 0.25),
+   the WAVE raster gathering by id (packed = 0) and exact repair (repair =
+   ALL, near_shift = 0). The paper's own selective mode is repair = RULES
+   with near_shift = 1. */
 TGS_API void tgs_default_params(tgs_params* params);
 
 /* Projection + SH colour + opacity-aware tile rect for every Gaussian. The

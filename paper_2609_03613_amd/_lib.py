@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libtilegs.so")
 TGS_OK, TGS_ERR_INVALID_ARG, TGS_ERR_CAPACITY, TGS_ERR_HIP, TGS_ERR_UNSUPPORTED, TGS_ERR_WORKSPACE = range(6)
 ORDER_GLOBAL, ORDER_BINNED = 0, 1
 RASTER_PLAIN, RASTER_WAVE = 0, 1
+REPAIR_ALL, REPAIR_RULES, REPAIR_NONE = 0, 1, 2
 
 EXPORTS = ("tgs_default_params", "tgs_project", "tgs_bin_workspace_size", "tgs_bin", "tgs_rasterize",
            "tgs_rasterize_backward", "tgs_project_backward", "tgs_batch_workspace_size", "tgs_rasterize_batch",
@@ -46,13 +47,15 @@ class Projected(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [("tile_size", ctypes.c_int32), ("num_bins", ctypes.c_int32), ("sample_count", ctypes.c_int32),
                 ("p_lo", ctypes.c_float), ("p_hi", ctypes.c_float), ("pad", ctypes.c_float),
-                ("raster", ctypes.c_int32), ("packed", ctypes.c_int32), ("per_tile_bins", _c_p)]
+                ("raster", ctypes.c_int32), ("packed", ctypes.c_int32), ("per_tile_bins", _c_p),
+                ("repair", ctypes.c_int32), ("repair_budget", ctypes.c_float), ("near_shift", ctypes.c_int32),
+                ("shift_alpha", ctypes.c_float), ("shift_gamma", ctypes.c_float)]
 
 
 class Binned(ctypes.Structure):
     _fields_ = [("capacity", ctypes.c_int64), ("keys", _c_p), ("vals", _c_p), ("pairs", _c_p),
                 ("offsets", _c_p), ("records", _c_p), ("masks", _c_p), ("zrange", _c_p), ("counters", _c_p),
-                ("tile_order", _c_p), ("seg_base", _c_p)]
+                ("tile_order", _c_p), ("seg_base", _c_p), ("repaired", _c_p)]
 
 
 class GaussianGrads(ctypes.Structure):

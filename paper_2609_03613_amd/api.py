@@ -20,6 +20,7 @@ from . import _lib as L
 
 ORDERS = {"global": L.ORDER_GLOBAL, "binned": L.ORDER_BINNED}
 RASTERS = {"plain": L.RASTER_PLAIN, "wave": L.RASTER_WAVE}
+REPAIRS = {"all": L.REPAIR_ALL, "rules": L.REPAIR_RULES, "none": L.REPAIR_NONE}
 
 
 @dataclass
@@ -37,10 +38,23 @@ class Params:
     packed: int = 0          # 0: gather + cull in the raster, 1: records + masks, 2: masks only
     tile_order: bool = True
     per_tile_bins: object = None  # None, or a device int32 tensor [T]: bins per tile (num_bins = bound)
+    repair: str = "all"      # "all" (exact), "rules" (the paper's selective repair), "none"
+    repair_budget: float = 0.25
+    near_shift: bool = False  # bin on z - min(alpha s_max, gamma z) instead of z
+    shift_alpha: float = 1.0
+    shift_gamma: float = 0.25
 
     def c(self):
         return L.Params(self.tile_size, self.num_bins, self.sample_count, self.p_lo, self.p_hi, self.pad,
-                        RASTERS[self.raster], int(self.packed), _ptr(self.per_tile_bins).value)
+                        RASTERS[self.raster], int(self.packed), _ptr(self.per_tile_bins).value,
+                        REPAIRS[self.repair], float(self.repair_budget), int(bool(self.near_shift)),
+                        float(self.shift_alpha), float(self.shift_gamma))
+
+
+def paper_params(**kw):
+    """The paper's selective mode: rule-based repair within a 25 % entry
+    budget and bins on the near-depth key."""
+    return Params(repair="rules", near_shift=True, **kw)
 
 
 def camera_struct(cam):
@@ -113,13 +127,16 @@ class Binned:
                 self.records = torch.empty((cap, 12), dtype=torch.float32, **kw)
         self.tile_order = torch.empty(max(tiles, 1), dtype=torch.int32, **kw) if tile_order else None
         self.seg_base = torch.empty(tiles + 1, dtype=torch.int32, **kw) if per_tile else None
+        self.repaired = (torch.empty(max(tiles * num_bins, 1), dtype=torch.uint8, **kw)
+                         if self.order == L.ORDER_BINNED else None)
         self.num_entries = None
 
     def c(self):
         return L.Binned(self.capacity, _ptr(self.keys).value, _ptr(self.vals).value, _ptr(self.pairs).value,
                         _ptr(self.offsets).value, _ptr(self.records).value, _ptr(self.masks).value,
                         _ptr(self.zrange).value,
-                        _ptr(self.counters).value, _ptr(self.tile_order).value, _ptr(self.seg_base).value)
+                        _ptr(self.counters).value, _ptr(self.tile_order).value, _ptr(self.seg_base).value,
+                        _ptr(self.repaired).value)
 
 
 class Renderer:

@@ -47,13 +47,15 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
     return v;
 }
 
-// Exact order statistics of the sampled depths (binary32 bits; depths are
-// positive so the bit order is the value order). Both ranks are selected
+// Exact order statistics of the sampled binning keys (binary32 bits of the
+// depth or of the near-depth key; both are positive, so the bit order is the
+// value order). Both ranks are selected
 // together by radix passes of 11 bits over key - min(key), which spreads the
 // histogram even when all depths share their top bits.
 __global__ void __launch_bounds__(kRangeThreads) depth_range_kernel(const uint4* __restrict__ info,
                                                                    const uint32_t* __restrict__ vis_ids,
-                                                                   const int64_t* __restrict__ counters, int S,
+                                                                   const int64_t* __restrict__ counters, NearKey nk,
+                                                                   int S,
                                                                    float p_lo, float p_hi, float pad, float znear,
                                                                    float zfar, float* __restrict__ zrange) {
 #pragma clang fp contract(off)
@@ -81,6 +83,11 @@ __global__ void __launch_bounds__(kRangeThreads) depth_range_kernel(const uint4*
     }
 #pragma unroll
     for (int j = 0; j < kPer; ++j) key[j] = (j * kRangeThreads + (int)threadIdx.x) < n ? info[gid[j]].x : 0u;
+    if (nk.splats) {
+#pragma unroll
+        for (int j = 0; j < kPer; ++j)
+            if ((j * kRangeThreads + (int)threadIdx.x) < n) key[j] = nk(key[j], gid[j]);
+    }
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
         const int i = j * kRangeThreads + threadIdx.x;
@@ -217,7 +224,8 @@ __device__ __forceinline__ int64_t segment_of(const SegMap& sm, int64_t t, uint3
 template <bool WITH_BIN, bool VAR, class F>
 __device__ __forceinline__ void for_wave_entries(const uint4* __restrict__ info, int64_t n,
                                                  const uint32_t* __restrict__ emit_off, int tiles_x, int tiles_y,
-                                                 const float* __restrict__ zrange, int K, WaveGauss* W, F&& f) {
+                                                 const float* __restrict__ zrange, const NearKey& nk, int K,
+                                                 WaveGauss* W, F&& f) {
     const int l = lane();
     const int64_t g0 = ((int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~(kWave - 1)));
     if (g0 >= n) return;
@@ -238,7 +246,8 @@ __device__ __forceinline__ void for_wave_entries(const uint4* __restrict__ info,
     W->key[l] = key;
     if (WITH_BIN) {
         const uint32_t Lmin = __float_as_uint(zrange[0]), Lmax = __float_as_uint(zrange[1]);
-        W->bin[l] = !cnt ? 0u : VAR ? depth_frac(key, Lmin, Lmax) : (uint32_t)bin_of(key, Lmin, Lmax, K);
+        const uint32_t bk = cnt ? nk(key, g) : 0u;
+        W->bin[l] = !cnt ? 0u : VAR ? depth_frac(bk, Lmin, Lmax) : (uint32_t)bin_of(bk, Lmin, Lmax, K);
     }
     const int64_t ebase = emit_off[g0];
     wave_sync();
@@ -263,14 +272,15 @@ __device__ __forceinline__ void for_wave_entries(const uint4* __restrict__ info,
 template <bool VAR>
 __global__ void __launch_bounds__(256) bin_count_kernel(const uint4* __restrict__ info, int64_t n,
                                                         const uint32_t* __restrict__ emit_off,
-                                                        const float* __restrict__ zrange, SegMap sm, int tiles_x,
-                                                        int tiles_y, uint32_t* __restrict__ count, int64_t nseg,
+                                                        const float* __restrict__ zrange, NearKey nk, SegMap sm,
+                                                        int tiles_x, int tiles_y, uint32_t* __restrict__ count,
+                                                        int64_t nseg,
                                                         uint32_t* __restrict__ entry_rank, int64_t capacity) {
     __shared__ WaveGauss wg[4];
     const uint32_t x = (uint32_t)xcc_id();
     const int64_t S = VAR ? (int64_t)sm.seg_base[(int64_t)tiles_x * tiles_y] : nseg;
     uint32_t* cnt = count + (int64_t)x * S;
-    for_wave_entries<true, VAR>(info, n, emit_off, tiles_x, tiles_y, zrange, sm.K, &wg[threadIdx.x / kWave],
+    for_wave_entries<true, VAR>(info, n, emit_off, tiles_x, tiles_y, zrange, nk, sm.K, &wg[threadIdx.x / kWave],
                                 [&](int64_t, int tx, int ty, int64_t e, uint32_t, uint32_t b) {
                                     const int64_t sg = segment_of<VAR>(sm, (int64_t)ty * tiles_x + tx, b);
                                     const uint32_t r = __hip_atomic_fetch_add(&cnt[sg], 1u, __ATOMIC_RELAXED,
@@ -285,15 +295,16 @@ __global__ void __launch_bounds__(256) bin_count_kernel(const uint4* __restrict_
 template <bool VAR>
 __global__ void __launch_bounds__(256) bin_scatter_kernel(const uint4* __restrict__ info, int64_t n,
                                                           const uint32_t* __restrict__ emit_off,
-                                                          const float* __restrict__ zrange, SegMap sm, int tiles_x,
-                                                          int tiles_y, const uint32_t* __restrict__ bin_off,
+                                                          const float* __restrict__ zrange, NearKey nk, SegMap sm,
+                                                          int tiles_x, int tiles_y,
+                                                          const uint32_t* __restrict__ bin_off,
                                                           const uint32_t* __restrict__ base, int64_t nseg,
                                                           const uint32_t* __restrict__ entry_rank,
                                                           uint64_t* __restrict__ pairs, int64_t capacity,
                                                           RecordSink rs) {
     __shared__ WaveGauss wg[4];
     const int64_t S = VAR ? (int64_t)sm.seg_base[(int64_t)tiles_x * tiles_y] : nseg;
-    for_wave_entries<true, VAR>(info, n, emit_off, tiles_x, tiles_y, zrange, sm.K, &wg[threadIdx.x / kWave],
+    for_wave_entries<true, VAR>(info, n, emit_off, tiles_x, tiles_y, zrange, nk, sm.K, &wg[threadIdx.x / kWave],
                                 [&](int64_t gid, int tx, int ty, int64_t e, uint32_t key, uint32_t b) {
                                     if (e >= capacity) return;
                                     const uint32_t rk = entry_rank[e];
@@ -566,7 +577,8 @@ __global__ void __launch_bounds__(256) emit_keys_kernel(const uint4* __restrict_
                                                         int tiles_y, uint64_t* __restrict__ keys,
                                                         uint32_t* __restrict__ vals, int64_t capacity) {
     __shared__ WaveGauss wg[4];
-    for_wave_entries<false, false>(info, n, emit_off, tiles_x, tiles_y, nullptr, 1, &wg[threadIdx.x / kWave],
+    for_wave_entries<false, false>(info, n, emit_off, tiles_x, tiles_y, nullptr, NearKey{}, 1,
+                                   &wg[threadIdx.x / kWave],
                             [&](int64_t gid, int tx, int ty, int64_t e, uint32_t key, uint32_t) {
                                 if (e >= capacity) return;
                                 keys[e] = ((uint64_t)(ty * tiles_x + tx) << 32) | key;
@@ -594,39 +606,40 @@ inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 
 
 }  // namespace
 
-hipError_t launch_depth_range(const uint32_t* info, const uint32_t* vis_ids, const int64_t* counters, int S,
-                              float p_lo, float p_hi, float pad, float znear, float zfar, float* zrange, hipStream_t s) {
+hipError_t launch_depth_range(const uint32_t* info, const uint32_t* vis_ids, const int64_t* counters, NearKey nk,
+                              int S, float p_lo, float p_hi, float pad, float znear, float zfar, float* zrange,
+                              hipStream_t s) {
     hipLaunchKernelGGL(depth_range_kernel, dim3(1), dim3(kRangeThreads), 0, s, reinterpret_cast<const uint4*>(info),
-                       vis_ids, counters, S, p_lo, p_hi, pad, znear, zfar, zrange);
+                       vis_ids, counters, nk, S, p_lo, p_hi, pad, znear, zfar, zrange);
     return hipGetLastError();
 }
 
 hipError_t launch_bin_count(const uint32_t* info, int64_t n, const uint32_t* emit_off, const float* zrange,
-                            SegMap sm, int tiles_x, int tiles_y, uint32_t* count, int64_t nseg, uint32_t* entry_rank,
-                            int64_t capacity, hipStream_t s) {
+                            NearKey nk, SegMap sm, int tiles_x, int tiles_y, uint32_t* count, int64_t nseg,
+                            uint32_t* entry_rank, int64_t capacity, hipStream_t s) {
     if (n == 0) return hipSuccess;
     const auto* in = reinterpret_cast<const uint4*>(info);
     if (sm.seg_base)
         hipLaunchKernelGGL(bin_count_kernel<true>, dim3(grid_for(n, 256)), dim3(256), 0, s, in, n, emit_off, zrange,
-                           sm, tiles_x, tiles_y, count, nseg, entry_rank, capacity);
+                           nk, sm, tiles_x, tiles_y, count, nseg, entry_rank, capacity);
     else
         hipLaunchKernelGGL(bin_count_kernel<false>, dim3(grid_for(n, 256)), dim3(256), 0, s, in, n, emit_off, zrange,
-                           sm, tiles_x, tiles_y, count, nseg, entry_rank, capacity);
+                           nk, sm, tiles_x, tiles_y, count, nseg, entry_rank, capacity);
     return hipGetLastError();
 }
 
 hipError_t launch_bin_scatter(const uint32_t* info, int64_t n, const uint32_t* emit_off, const float* zrange,
-                              SegMap sm, int tiles_x, int tiles_y, const uint32_t* bin_off, const uint32_t* base,
-                              int64_t nseg, const uint32_t* entry_rank, uint64_t* pairs, int64_t capacity,
-                              RecordSink rs, hipStream_t s) {
+                              NearKey nk, SegMap sm, int tiles_x, int tiles_y, const uint32_t* bin_off,
+                              const uint32_t* base, int64_t nseg, const uint32_t* entry_rank, uint64_t* pairs,
+                              int64_t capacity, RecordSink rs, hipStream_t s) {
     if (n == 0) return hipSuccess;
     const auto* in = reinterpret_cast<const uint4*>(info);
     if (sm.seg_base)
         hipLaunchKernelGGL(bin_scatter_kernel<true>, dim3(grid_for(n, 256)), dim3(256), 0, s, in, n, emit_off, zrange,
-                           sm, tiles_x, tiles_y, bin_off, base, nseg, entry_rank, pairs, capacity, rs);
+                           nk, sm, tiles_x, tiles_y, bin_off, base, nseg, entry_rank, pairs, capacity, rs);
     else
         hipLaunchKernelGGL(bin_scatter_kernel<false>, dim3(grid_for(n, 256)), dim3(256), 0, s, in, n, emit_off,
-                           zrange, sm, tiles_x, tiles_y, bin_off, base, nseg, entry_rank, pairs, capacity, rs);
+                           zrange, nk, sm, tiles_x, tiles_y, bin_off, base, nseg, entry_rank, pairs, capacity, rs);
     return hipGetLastError();
 }
 

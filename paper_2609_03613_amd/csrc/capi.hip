@@ -72,6 +72,19 @@ tgs_status check_params(const tgs_params* p) {
             return fail(TGS_ERR_INVALID_ARG, "num_bins %d must be a power of two with per_tile_bins", p->num_bins);
         if (p->packed != 0) return fail(TGS_ERR_UNSUPPORTED, "per_tile_bins needs packed = 0");
     }
+    if (p->repair != TGS_REPAIR_ALL && p->repair != TGS_REPAIR_RULES && p->repair != TGS_REPAIR_NONE)
+        return fail(TGS_ERR_INVALID_ARG, "unknown repair %d", p->repair);
+    if (!(p->repair_budget >= 0.f && p->repair_budget <= 1.f))
+        return fail(TGS_ERR_INVALID_ARG, "repair_budget must be in [0, 1]");
+    if (p->repair != TGS_REPAIR_ALL && p->packed != 0)
+        return fail(TGS_ERR_UNSUPPORTED, "repair RULES / NONE needs packed = 0");
+    if (p->repair == TGS_REPAIR_RULES && p->per_tile_bins_dev)
+        return fail(TGS_ERR_UNSUPPORTED, "repair RULES needs a uniform num_bins");
+    if (p->near_shift != 0 && p->near_shift != 1) return fail(TGS_ERR_INVALID_ARG, "near_shift must be 0 or 1");
+    if (!(p->shift_alpha >= 0.f) || !isfinite(p->shift_alpha))
+        return fail(TGS_ERR_INVALID_ARG, "shift_alpha must be finite and >= 0");
+    if (!(p->shift_gamma >= 0.f && p->shift_gamma < 1.f))
+        return fail(TGS_ERR_INVALID_ARG, "shift_gamma must be in [0, 1)");
     return TGS_OK;
 }
 
@@ -85,7 +98,8 @@ tgs_status check_projected(const tgs_projected* pr) {
 inline size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t emit_off, vis_ids, zero, zero_words, status_emit_x, status_emit_y, status_bins, status_segs, count,
+    size_t emit_off, vis_ids, zero, zero_words, status_emit_x, status_emit_y, status_bins, status_segs, status_sel,
+        count,
         count_var, tile_seg, entry_rank, seg_lists, keys_in, vals_in, sort_tmp, sort_tmp_bytes, total;
 };
 
@@ -93,6 +107,8 @@ struct Layout {
 constexpr int kTicketEmit = 0;
 constexpr int kTicketBins = 1;
 constexpr int kTicketSegs = 2;
+constexpr int kTicketSel = 3;
+constexpr int kSelCtl = 4;  // 2 words: first rejected segment + 1, remaining budget
 constexpr int kBucketCount = 16;
 constexpr int kTileHist = 32;  // 66 words: histogram and cursors of the tile order
 constexpr int kControlWords = 128;
@@ -104,14 +120,15 @@ int end_bit_for(int64_t T) {
 }
 
 // Workspace: [emit offsets][visible ids][zeroed region: control words,
-// scan status words, per-XCD counts (BINNED, uniform K)][entry ranks]
+// scan status words (with rule-based repair also those of the selection
+// scan), per-XCD counts (BINNED, uniform K)][entry ranks]
 // [repair lists][per-XCD counts (BINNED, per-tile bin counts)] (BINNED) or
 // [...][unsorted keys][unsorted ids][sort scratch] (GLOBAL). The zeroed
 // region is cleared by one fill at the start of each tgs_bin; with per-tile
 // bin counts only the first kXcc * S words of the counts are cleared, by a
 // fill sized on the device. K is the uniform bin count or the bound of the
 // per-tile counts.
-Layout layout(int64_t n, int64_t capacity, int64_t T, int K, int order, bool var) {
+Layout layout(int64_t n, int64_t capacity, int64_t T, int K, int order, bool var, bool rules) {
     Layout L{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -133,6 +150,8 @@ Layout layout(int64_t n, int64_t capacity, int64_t T, int K, int order, bool var
     z += 2 * nbb;
     L.status_segs = z;
     z += var ? 2 * (size_t)scan_blocks(T) : 0;
+    L.status_sel = z;
+    z += rules ? 2 * nbb : 0;
     if (order == TGS_ORDER_BINNED && !var) {
         z = (z + 63) & ~(size_t)63;
         L.count = z;
@@ -176,6 +195,11 @@ void tgs_default_params(tgs_params* p) {
     p->raster = TGS_RASTER_WAVE;
     p->packed = 0;
     p->per_tile_bins_dev = nullptr;
+    p->repair = TGS_REPAIR_ALL;
+    p->repair_budget = 0.25f;
+    p->near_shift = 0;
+    p->shift_alpha = 1.0f;
+    p->shift_gamma = 0.25f;
 }
 
 const char* tgs_last_error(void) { return g_err.c_str(); }
@@ -204,7 +228,8 @@ size_t tgs_bin_workspace_size(int64_t n, int64_t capacity, const tgs_camera* cam
     if (cam->width < 1 || cam->height < 1 || params->num_bins < 1) return 0;
     if (params->tile_size != 8 && params->tile_size != 16 && params->tile_size != 32) return 0;
     return layout(n, capacity, tiles_of(cam, params->tile_size), params->num_bins, order,
-                  params->per_tile_bins_dev != nullptr && order == TGS_ORDER_BINNED)
+                  params->per_tile_bins_dev != nullptr && order == TGS_ORDER_BINNED,
+                  params->repair == TGS_REPAIR_RULES && order == TGS_ORDER_BINNED)
         .total;
 }
 
@@ -234,7 +259,8 @@ tgs_status tgs_bin(const tgs_projected* pr, const tgs_camera* cam, const tgs_par
     } else if (cap > 0 && (!out->keys_dev || !out->vals_dev)) {
         return fail(TGS_ERR_INVALID_ARG, "keys or vals is NULL");
     }
-    const Layout L = layout(n, cap, T, K, order, var);
+    const bool rules = order == TGS_ORDER_BINNED && params->repair == TGS_REPAIR_RULES;
+    const Layout L = layout(n, cap, T, K, order, var, rules);
     if (!ws || ws_bytes < L.total)
         return fail(TGS_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
     hipStream_t s = (hipStream_t)stream;
@@ -288,19 +314,29 @@ tgs_status tgs_bin(const tgs_projected* pr, const tgs_camera* cam, const tgs_par
                 "segment bases");
         TGS_HIP(launch_fill_u32_dyn(count, 0u, nseg_dev, kXcc, (int64_t)kXcc * nseg, s), "clear counts");
     }
-    TGS_HIP(launch_depth_range(pr->info_dev, vis_ids, out->counters_dev, S, params->p_lo, params->p_hi, params->pad,
-                               (float)cam->znear, (float)cam->zfar, out->zrange_dev, s),
+    const float zn = (float)cam->znear, zf = (float)cam->zfar;
+    const NearKey nk{params->near_shift ? reinterpret_cast<const float4*>(pr->splats_dev) : nullptr,
+                     params->shift_alpha, params->shift_gamma, zn > 1e-4f ? zn : 1e-4f, zf};
+    TGS_HIP(launch_depth_range(pr->info_dev, vis_ids, out->counters_dev, nk, S, params->p_lo, params->p_hi,
+                               params->pad, zn, zf, out->zrange_dev, s),
             "depth range");
-    TGS_HIP(launch_bin_count(pr->info_dev, n, emit_off, out->zrange_dev, sm, tiles_x, tiles_y, count, nseg, entry_rank,
-                             cap, s),
+    TGS_HIP(launch_bin_count(pr->info_dev, n, emit_off, out->zrange_dev, nk, sm, tiles_x, tiles_y, count, nseg,
+                             entry_rank, cap, s),
             "bin count");
     TGS_HIP(launch_bin_offsets(count, nseg, nseg_dev, out->offsets_dev, zero + kTicketBins,
-                               (uint64_t*)(zero + L.status_bins), seg_lists, bucket_count, out->counters_dev, s),
+                               (uint64_t*)(zero + L.status_bins), seg_lists, bucket_count, out->counters_dev,
+                               params->repair == TGS_REPAIR_ALL, out->repaired_dev, s),
             "bin offsets");
-    TGS_HIP(launch_bin_scatter(pr->info_dev, n, emit_off, out->zrange_dev, sm, tiles_x, tiles_y, out->offsets_dev, count,
-                               nseg, entry_rank, out->pairs_dev, cap, rs, s),
+    if (rules)
+        TGS_HIP(launch_repair_select(out->offsets_dev, T, K, params->repair_budget, zero + kTicketSel,
+                                     (uint64_t*)(zero + L.status_sel), zero + kSelCtl, seg_lists, bucket_count,
+                                     out->counters_dev, out->repaired_dev, s),
+                "repair selection");
+    TGS_HIP(launch_bin_scatter(pr->info_dev, n, emit_off, out->zrange_dev, nk, sm, tiles_x, tiles_y, out->offsets_dev,
+                               count, nseg, entry_rank, out->pairs_dev, cap, rs, s),
             "bin scatter");
-    TGS_HIP(launch_repair(out->offsets_dev, nseg, out->pairs_dev, seg_lists, bucket_count, rs, s), "repair");
+    if (params->repair != TGS_REPAIR_NONE)
+        TGS_HIP(launch_repair(out->offsets_dev, nseg, out->pairs_dev, seg_lists, bucket_count, rs, s), "repair");
     if (out->tile_order_dev)
         TGS_HIP(launch_tile_order(out->offsets_dev, sm, T, zero + kTileHist, out->tile_order_dev, s), "tile order");
     return TGS_OK;

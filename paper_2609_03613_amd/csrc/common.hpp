@@ -207,6 +207,28 @@ struct SegMap {
     }
 };
 
+// Binning key of a Gaussian. splats == null: its depth. Otherwise the
+// near-depth key z - min(alpha s_max, gamma z) (s_max: splat word 11),
+// clamped to [lo, hi] = [max(znear, 1e-4), zfar], in binary32 without
+// contraction (supplement, Algorithm "Robust depth-range estimation",
+// near-depth mode; the bin map takes the same key).
+struct NearKey {
+    const float4* splats;
+    float alpha, gamma, lo, hi;
+    __device__ __forceinline__ uint32_t operator()(uint32_t depth_bits, int64_t g) const {
+#pragma clang fp contract(off)
+        if (!splats) return depth_bits;
+        const float z = __uint_as_float(depth_bits);
+        const float smax = splats[kSplatVec * g + 2].w;
+        const float a = alpha * smax, b = gamma * z;
+        const float d = a < b ? a : b;
+        float k = z - d;
+        if (k < lo) k = lo;
+        if (k > hi) k = hi;
+        return __float_as_uint(k);
+    }
+};
+
 struct Cam {
     double R[9], t[3];
     double fx, fy, cx, cy;
@@ -237,8 +259,8 @@ hipError_t launch_emit_scan(const uint32_t* info, int64_t n, int tiles_x, int ti
 
 // Depth samples: the visible Gaussians at ranks floor(i V / S), i < S (all
 // of them when V <= S), read through vis_ids.
-hipError_t launch_depth_range(const uint32_t* info, const uint32_t* vis_ids, const int64_t* counters, int S,
-                              float p_lo, float p_hi, float pad, float znear, float zfar, float* zrange,
+hipError_t launch_depth_range(const uint32_t* info, const uint32_t* vis_ids, const int64_t* counters, NearKey nk,
+                              int S, float p_lo, float p_hi, float pad, float znear, float zfar, float* zrange,
                               hipStream_t s);
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
@@ -247,8 +269,8 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 // nseg, or seg_base[T] with per-tile bin counts). The rank of each entry in
 // its copy, with the copy index in the top three bits, goes to entry_rank.
 hipError_t launch_bin_count(const uint32_t* info, int64_t n, const uint32_t* emit_off, const float* zrange,
-                            SegMap sm, int tiles_x, int tiles_y, uint32_t* count, int64_t nseg, uint32_t* entry_rank,
-                            int64_t capacity, hipStream_t s);
+                            NearKey nk, SegMap sm, int tiles_x, int tiles_y, uint32_t* count, int64_t nseg,
+                            uint32_t* entry_rank, int64_t capacity, hipStream_t s);
 // Repair length buckets: 2..8, 9..16, 17..32, 33..64 (lane groups of one
 // wavefront, registers), 65..512 (one wavefront, LDS), 513..4096 and
 // 4097..8192 (one workgroup, LDS), above 8192 (one workgroup, global memory).
@@ -266,19 +288,31 @@ __host__ __device__ __forceinline__ int bucket_of(uint32_t len) {
 }
 
 // bin_off[s] = exclusive scan of the summed copies (bin_off[S] = M);
-// count[x][s] becomes the base position of copy x inside segment s; every
-// segment of two or more entries is appended to lists[bucket][...] (bucket
-// stride: nseg) with bucket_count[bucket] entries (not when counters[2]
-// flags an overflow). S = nseg, or *nseg_dev when nseg_dev is not null
-// (then nseg is its upper bound). ticket, status [scan_blocks(nseg)] and
-// bucket_count must be zero.
+// count[x][s] becomes the base position of copy x inside segment s. With
+// queue_all, every segment of two or more entries is appended to
+// lists[bucket][...] (bucket stride: nseg) with bucket_count[bucket]
+// entries, its entries are added to counters[3] and repaired[s] (when not
+// null) is set; nothing is queued when counters[2] flags an overflow.
+// Without queue_all, repaired[s] = 0. S = nseg, or *nseg_dev when nseg_dev
+// is not null (then nseg is its upper bound). ticket, status
+// [scan_blocks(nseg)] and bucket_count must be zero.
 hipError_t launch_bin_offsets(uint32_t* count, int64_t nseg, const uint32_t* nseg_dev, uint32_t* bin_off,
                               uint32_t* ticket, uint64_t* status, uint32_t* lists, uint32_t* bucket_count,
-                              const int64_t* counters, hipStream_t s);
+                              int64_t* counters, bool queue_all, uint8_t* repaired, hipStream_t s);
+// Rule-based repair selection over the T * K segments (uniform K): the
+// keep rules per segment, the prefix of the kept lengths by a single-pass
+// scan (segments whose inclusive prefix is within the budget are queued as
+// in launch_bin_offsets), then one workgroup continues the first-fit scan
+// after the first kept segment that does not fit. ticket, status
+// [scan_blocks(T K)] and ctl [2] must be zero; counters[3] gets the
+// selected entries.
+hipError_t launch_repair_select(const uint32_t* bin_off, int64_t T, int K, float budget, uint32_t* ticket,
+                                uint64_t* status, uint32_t* ctl, uint32_t* lists, uint32_t* bucket_count,
+                                int64_t* counters, uint8_t* repaired, hipStream_t s);
 hipError_t launch_bin_scatter(const uint32_t* info, int64_t n, const uint32_t* emit_off, const float* zrange,
-                              SegMap sm, int tiles_x, int tiles_y, const uint32_t* bin_off, const uint32_t* base,
-                              int64_t nseg, const uint32_t* entry_rank, uint64_t* pairs, int64_t capacity,
-                              RecordSink rs, hipStream_t s);
+                              NearKey nk, SegMap sm, int tiles_x, int tiles_y, const uint32_t* bin_off,
+                              const uint32_t* base, int64_t nseg, const uint32_t* entry_rank, uint64_t* pairs,
+                              int64_t capacity, RecordSink rs, hipStream_t s);
 
 // Per-tile bin counts: seg_base[t] = exclusive prefix sum of the bin counts
 // (each clamped to 1..kmax and rounded down to a power of two), seg_base[T]

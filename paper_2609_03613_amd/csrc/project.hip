@@ -105,7 +105,7 @@ __global__ void __launch_bounds__(kProjThreads) project_kernel(const float* __re
     double qw = quats[4 * g], qx = quats[4 * g + 1], qy = quats[4 * g + 2], qz = quats[4 * g + 3];
     const double qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
     ok = ok && (qn > 0.0) && isfinite(qn);
-    double c00 = 0, c01 = 0, c11 = 0, det = 0, mxs = 0, mys = 0, o = 0;
+    double c00 = 0, c01 = 0, c11 = 0, det = 0, mxs = 0, mys = 0, o = 0, smax = 0;
     if (ok) {
         qw /= qn; qx /= qn; qy /= qn; qz /= qn;
         const double Rq[9] = {1.0 - 2.0 * (qy * qy + qz * qz), 2.0 * (qx * qy - qw * qz), 2.0 * (qx * qz + qw * qy),
@@ -116,6 +116,7 @@ __global__ void __launch_bounds__(kProjThreads) project_kernel(const float* __re
         for (int k = 0; k < 3; ++k) {
             const double s = exp((double)log_scales[3 * g + k]);
             s2[k] = s * s;
+            smax = fmax(smax, s);
         }
         // M = R_cam Rq: camera covariance = M diag(s^2) M^T
         double M[9];
@@ -184,7 +185,7 @@ __global__ void __launch_bounds__(kProjThreads) project_kernel(const float* __re
     out[0] = make_float4(hx, hy, (float)(mxs - (double)hx), (float)(mys - (double)hy));
     out[1] = make_float4((float)(c11 / det), (float)(-c01 / det), (float)(c00 / det), (float)o);
     out[2] = make_float4((float)fmax(0.0, 0.5 + col[0]), (float)fmax(0.0, 0.5 + col[1]),
-                         (float)fmax(0.0, 0.5 + col[2]), 0.f);
+                         (float)fmax(0.0, 0.5 + col[2]), (float)smax);
     out[3] = zero4;
     const float zf = (float)z;
     inf.x = __float_as_uint(zf);

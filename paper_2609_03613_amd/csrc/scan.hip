@@ -188,66 +188,18 @@ __device__ __forceinline__ uint32_t seg_total(const uint32_t* __restrict__ count
     return t;
 }
 
-// bin_off[s] = exclusive prefix of the summed copies (bin_off[nseg] = M);
-// count[x][s] becomes bin_off[s] + the counts of copies 0..x-1 in segment
-// s. Every segment with two or more entries is appended to the list of its
-// repair bucket (aggregated per wavefront and per workgroup: one global
-// atomic per bucket and workgroup). Nothing is queued when the stream
-// overflowed (counters[2]). With nseg_dev, the number of segments (and the
-// stride of the count copies) is *nseg_dev and the grid is sized for its
-// upper bound: workgroups past the last needed one leave after their ticket.
-__global__ void __launch_bounds__(kThreads) bin_offsets_kernel(uint32_t* __restrict__ count, int64_t nseg_max,
-                                                               const uint32_t* __restrict__ nseg_dev,
-                                                               uint32_t* __restrict__ bin_off, uint32_t* ticket,
-                                                               uint64_t* status, uint32_t* __restrict__ lists,
-                                                               uint32_t* __restrict__ bucket_count,
-                                                               const int64_t* __restrict__ counters) {
-    __shared__ uint32_t tk;
-    __shared__ uint32_t lds32[kThreads / kWave];
-    __shared__ uint64_t pre;
-    __shared__ uint32_t lcount[kBuckets], lbase[kBuckets];
-    if (threadIdx.x == 0) tk = atomicAdd(ticket, 1u);
-    if (threadIdx.x < kBuckets) lcount[threadIdx.x] = 0;
-    __syncthreads();
-    const int64_t b = tk;
-    const int64_t nseg = nseg_dev ? (int64_t)*nseg_dev : nseg_max;
-    const int64_t nb = blocks_for(nseg);
-    if (b >= nb) return;
-    const int64_t base = b * kPerBlock;
-    const bool queue = counters[2] == 0;
-    uint32_t v[kRounds];
-    uint32_t s = 0;
+// Appends the segments with bk >= 0 (one per thread and round) to the
+// list of their repair bucket: aggregated per wavefront and per workgroup,
+// one global atomic per bucket and workgroup. lcount / lbase: LDS [kBuckets],
+// lcount zeroed before the first round.
+template <int R>
+__device__ __forceinline__ void queue_segments(const int (&bk)[R], int64_t base, int64_t list_stride,
+                                               uint32_t* lcount, uint32_t* lbase, uint32_t* __restrict__ lists,
+                                               uint32_t* __restrict__ bucket_count) {
+    uint32_t slot[R];
 #pragma unroll
-    for (int r = 0; r < kRounds; ++r) {
-        v[r] = seg_total(count, nseg, base + r * kThreads + threadIdx.x);
-        s += v[r];
-    }
-    const uint32_t agg = block_sum_u32(s, lds32);
-    if (threadIdx.x == 0) pre = publish_and_look_back(status, b, agg);
-    __syncthreads();
-    uint32_t carry = (uint32_t)pre;
-    if (b == nb - 1 && threadIdx.x == 0) bin_off[nseg] = carry + agg;
-    int bk[kRounds];
-    uint32_t slot[kRounds];
-#pragma unroll
-    for (int r = 0; r < kRounds; ++r) {
-        const int64_t sg = base + r * kThreads + threadIdx.x;
-        uint32_t tot;
-        uint32_t run = carry + block_excl_u32(v[r], lds32, &tot);
-        carry += tot;
-        bk[r] = -1;
+    for (int r = 0; r < R; ++r) {
         slot[r] = 0;
-        if (sg < nseg) {
-            bin_off[sg] = run;
-#pragma unroll
-            for (int x = 0; x < kXcc; ++x) {
-                uint32_t* c = count + (int64_t)x * nseg + sg;
-                const uint32_t cv = *c;
-                *c = run;
-                run += cv;
-            }
-            if (queue) bk[r] = bucket_of(v[r]);
-        }
         if (ballot(bk[r] >= 0) == 0) continue;
 #pragma unroll
         for (int k = 0; k < kBuckets; ++k) {
@@ -265,11 +217,247 @@ __global__ void __launch_bounds__(kThreads) bin_offsets_kernel(uint32_t* __restr
         lbase[threadIdx.x] = lcount[threadIdx.x] ? atomicAdd(&bucket_count[threadIdx.x], lcount[threadIdx.x]) : 0u;
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < kRounds; ++r) {
+    for (int r = 0; r < R; ++r) {
         if (bk[r] < 0) continue;
         const int64_t sg = base + r * kThreads + threadIdx.x;
-        lists[(int64_t)bk[r] * nseg_max + lbase[bk[r]] + slot[r]] = (uint32_t)sg;
+        lists[(int64_t)bk[r] * list_stride + lbase[bk[r]] + slot[r]] = (uint32_t)sg;
     }
+}
+
+// bin_off[s] = exclusive prefix of the summed copies (bin_off[nseg] = M);
+// count[x][s] becomes bin_off[s] + the counts of copies 0..x-1 in segment
+// s. With queue_all, every segment with two or more entries is appended to
+// the list of its repair bucket and its entries are added to counters[3];
+// nothing is queued when the stream overflowed (counters[2]). repaired[s]
+// (optional) records whether segment s was queued. With nseg_dev, the
+// number of segments (and the stride of the count copies) is *nseg_dev and
+// the grid is sized for its upper bound: workgroups past the last needed one
+// leave after their ticket.
+__global__ void __launch_bounds__(kThreads) bin_offsets_kernel(uint32_t* __restrict__ count, int64_t nseg_max,
+                                                               const uint32_t* __restrict__ nseg_dev,
+                                                               uint32_t* __restrict__ bin_off, uint32_t* ticket,
+                                                               uint64_t* status, uint32_t* __restrict__ lists,
+                                                               uint32_t* __restrict__ bucket_count,
+                                                               int64_t* __restrict__ counters, bool queue_all,
+                                                               uint8_t* __restrict__ repaired) {
+    __shared__ uint32_t tk;
+    __shared__ uint32_t lds32[kThreads / kWave];
+    __shared__ uint64_t pre;
+    __shared__ uint32_t lcount[kBuckets], lbase[kBuckets];
+    if (threadIdx.x == 0) tk = atomicAdd(ticket, 1u);
+    if (threadIdx.x < kBuckets) lcount[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t b = tk;
+    const int64_t nseg = nseg_dev ? (int64_t)*nseg_dev : nseg_max;
+    const int64_t nb = blocks_for(nseg);
+    if (b >= nb) return;
+    const int64_t base = b * kPerBlock;
+    const bool queue = queue_all && counters[2] == 0;
+    uint32_t v[kRounds];
+    uint32_t s = 0;
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+        v[r] = seg_total(count, nseg, base + r * kThreads + threadIdx.x);
+        s += v[r];
+    }
+    const uint32_t agg = block_sum_u32(s, lds32);
+    if (threadIdx.x == 0) pre = publish_and_look_back(status, b, agg);
+    __syncthreads();
+    uint32_t carry = (uint32_t)pre;
+    if (b == nb - 1 && threadIdx.x == 0) bin_off[nseg] = carry + agg;
+    int bk[kRounds];
+    uint32_t queued = 0;
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+        const int64_t sg = base + r * kThreads + threadIdx.x;
+        uint32_t tot;
+        uint32_t run = carry + block_excl_u32(v[r], lds32, &tot);
+        carry += tot;
+        bk[r] = -1;
+        if (sg < nseg) {
+            bin_off[sg] = run;
+#pragma unroll
+            for (int x = 0; x < kXcc; ++x) {
+                uint32_t* c = count + (int64_t)x * nseg + sg;
+                const uint32_t cv = *c;
+                *c = run;
+                run += cv;
+            }
+            if (queue) bk[r] = bucket_of(v[r]);
+            if (repaired) repaired[sg] = bk[r] >= 0 ? 1 : 0;
+            if (bk[r] >= 0) queued += v[r];
+        }
+    }
+    if (!queue) return;
+    queue_segments(bk, base, nseg_max, lcount, lbase, lists, bucket_count);
+    const uint32_t qsum = block_sum_u32(queued, lds32);
+    if (threadIdx.x == 0 && qsum)
+        atomicAdd(reinterpret_cast<unsigned long long*>(&counters[3]), (unsigned long long)qsum);
+}
+
+// ---- rule-based repair selection -------------------------------------------
+// Table "Exact-repair selection rules" and the supplement's Algorithm
+// "Selective repair selection and local exact sorting": a segment of length
+// l >= 2, bin b, in a tile of l_tile entries is kept when l >= 320, l > 512,
+// 100 l >= 45 l_tile, 129 <= l <= 256 and 100 l >= 10 l_tile, or b < 2 and
+// l >= 16; kept segments are selected in (tile, bin) order while the
+// selected entries fit the budget B (first fit). Kept length of segment q
+// (0 when not kept or past the end).
+__device__ __forceinline__ uint32_t kept_length(const uint32_t* __restrict__ bin_off, int64_t q, int K,
+                                                int64_t nseg) {
+    if (q >= nseg) return 0u;
+    const int64_t t = q / K;
+    const int b = (int)(q - t * K);
+    const uint32_t len = bin_off[q + 1] - bin_off[q];
+    if (len <= 1) return 0u;
+    const uint64_t tl = bin_off[t * K + K] - bin_off[t * K];
+    const uint64_t l100 = 100ull * len;
+    const bool keep = len >= 320u || len > 512u || l100 >= 45ull * tl || (len >= 129u && len <= 256u && l100 >= 10ull * tl) ||
+                      (b < 2 && len >= 16u);
+    return keep ? len : 0u;
+}
+
+__device__ __forceinline__ uint64_t budget_of(float frac, uint32_t M) {
+    return (uint64_t)floor((double)frac * (double)M);
+}
+
+// Pass 1: prefix of the kept lengths by a single-pass scan. A kept segment
+// whose inclusive prefix is within B is selected (all kept segments before
+// it were selected and fit). The one kept segment whose prefix first
+// exceeds B is rejected; it leaves ctl = {its index + 1, B - the exclusive
+// prefix} for the sequential continuation. When everything fits,
+// counters[3] = the kept total.
+__global__ void __launch_bounds__(kThreads) select_prefix_kernel(const uint32_t* __restrict__ bin_off, int64_t nseg,
+                                                                 int K, float budget, uint32_t* ticket,
+                                                                 uint64_t* status, uint32_t* __restrict__ ctl,
+                                                                 uint32_t* __restrict__ lists,
+                                                                 uint32_t* __restrict__ bucket_count,
+                                                                 int64_t* __restrict__ counters,
+                                                                 uint8_t* __restrict__ repaired) {
+    __shared__ uint32_t tk;
+    __shared__ uint32_t lds32[kThreads / kWave];
+    __shared__ uint64_t pre;
+    __shared__ uint32_t lcount[kBuckets], lbase[kBuckets];
+    if (threadIdx.x == 0) tk = atomicAdd(ticket, 1u);
+    if (threadIdx.x < kBuckets) lcount[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t b = tk;
+    const int64_t nb = blocks_for(nseg);
+    if (b >= nb) return;
+    const int64_t base = b * kPerBlock;
+    const bool queue = counters[2] == 0;
+    const uint64_t B = budget_of(budget, bin_off[nseg]);
+    uint32_t v[kRounds];
+    uint32_t s = 0;
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+        v[r] = kept_length(bin_off, base + r * kThreads + threadIdx.x, K, nseg);
+        s += v[r];
+    }
+    const uint32_t agg = block_sum_u32(s, lds32);
+    if (threadIdx.x == 0) pre = publish_and_look_back(status, b, agg);
+    __syncthreads();
+    uint64_t carry = pre;
+    if (b == nb - 1 && threadIdx.x == 0 && carry + agg <= B) counters[3] = (int64_t)(carry + agg);
+    int bk[kRounds];
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+        const int64_t sg = base + r * kThreads + threadIdx.x;
+        uint32_t tot;
+        const uint64_t excl = carry + block_excl_u32(v[r], lds32, &tot);
+        carry += tot;
+        const uint64_t incl = excl + v[r];
+        const bool sel = v[r] != 0 && incl <= B;
+        if (v[r] != 0 && incl > B && excl <= B) {
+            ctl[0] = (uint32_t)(sg + 1);
+            ctl[1] = (uint32_t)(B - excl);
+        }
+        if (repaired && sg < nseg) repaired[sg] = sel ? 1 : 0;
+        bk[r] = queue && sel ? bucket_of(v[r]) : -1;
+    }
+    queue_segments(bk, base, nseg, lcount, lbase, lists, bucket_count);
+}
+
+constexpr int kTailThreads = 1024;
+
+// Exclusive scan over a workgroup of kTailThreads; *total gets the sum.
+// Ends with a barrier.
+__device__ __forceinline__ uint32_t tail_excl_u32(uint32_t v, uint32_t* lds, uint32_t* total) {
+    constexpr int NW = kTailThreads / kWave;
+    const int w = threadIdx.x / kWave, l = lane();
+    uint32_t inc = v;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t o = shfl_up_u32(inc, d);
+        if (l >= d) inc += o;
+    }
+    if (l == kWave - 1) lds[w] = inc;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+        const uint32_t t = lds[i];
+        before += i < w ? t : 0u;
+        all += t;
+    }
+    __syncthreads();
+    *total = all;
+    return before + inc - v;
+}
+
+// Pass 2 (one workgroup): first fit over the segments after the first
+// rejected one, with the remaining budget R, 1024 segments at a time. In a
+// chunk, candidates are the kept segments with length <= R; the longest run
+// of candidates whose running sum fits R is selected, the candidate that
+// ends it is rejected, R drops by the run's sum and the candidates after it
+// are filtered against the new R, until none is left. Stops once R < 2 (a
+// kept segment has two or more entries). counters[3] = B - R at the end.
+__global__ void __launch_bounds__(kTailThreads) select_tail_kernel(const uint32_t* __restrict__ bin_off,
+                                                                   int64_t nseg, int K, float budget,
+                                                                   const uint32_t* __restrict__ ctl,
+                                                                   uint32_t* __restrict__ lists,
+                                                                   uint32_t* __restrict__ bucket_count,
+                                                                   int64_t* __restrict__ counters,
+                                                                   uint8_t* __restrict__ repaired) {
+    __shared__ uint32_t lds[kTailThreads / kWave];
+    __shared__ uint32_t first, rem;
+    if (ctl[0] == 0 || counters[2] != 0) return;
+    const uint64_t B = budget_of(budget, bin_off[nseg]);
+    uint32_t R = ctl[1];
+    for (int64_t base = ctl[0]; base < nseg && R >= 2u; base += kTailThreads) {
+        const int64_t q = base + threadIdx.x;
+        const uint32_t kl = kept_length(bin_off, q, K, nseg);
+        bool cand = kl != 0u && kl <= R;
+        bool sel = false;
+        while (__syncthreads_or(cand)) {
+            uint32_t tot;
+            const uint32_t excl = tail_excl_u32(cand ? kl : 0u, lds, &tot);
+            if (threadIdx.x == 0) first = 0xFFFFFFFFu;
+            __syncthreads();
+            if (cand && excl + kl > R) atomicMin(&first, (uint32_t)threadIdx.x);
+            __syncthreads();
+            const uint32_t f = first;
+            if (f == 0xFFFFFFFFu) {
+                sel = sel || cand;
+                cand = false;
+                R -= tot;
+            } else {
+                if (threadIdx.x == f) rem = R - excl;
+                __syncthreads();
+                if (cand && threadIdx.x < f) sel = true;
+                if (threadIdx.x <= f) cand = false;
+                R = rem;
+                cand = cand && kl <= R;
+            }
+        }
+        if (sel) {
+            if (repaired) repaired[q] = 1;
+            const int bk = bucket_of(kl);
+            const uint32_t at = atomicAdd(&bucket_count[bk], 1u);
+            lists[(int64_t)bk * nseg + at] = (uint32_t)q;
+        }
+    }
+    if (threadIdx.x == 0) counters[3] = (int64_t)(B - R);
 }
 
 // ---- per-tile segment bases -------------------------------------------------
@@ -344,9 +532,21 @@ hipError_t launch_emit_scan(const uint32_t* info, int64_t n, int tiles_x, int ti
 
 hipError_t launch_bin_offsets(uint32_t* count, int64_t nseg, const uint32_t* nseg_dev, uint32_t* bin_off,
                               uint32_t* ticket, uint64_t* status, uint32_t* lists, uint32_t* bucket_count,
-                              const int64_t* counters, hipStream_t s) {
+                              int64_t* counters, bool queue_all, uint8_t* repaired, hipStream_t s) {
     hipLaunchKernelGGL(bin_offsets_kernel, dim3((unsigned)scan_blocks(nseg)), dim3(kThreads), 0, s, count, nseg,
-                       nseg_dev, bin_off, ticket, status, lists, bucket_count, counters);
+                       nseg_dev, bin_off, ticket, status, lists, bucket_count, counters, queue_all, repaired);
+    return hipGetLastError();
+}
+
+hipError_t launch_repair_select(const uint32_t* bin_off, int64_t T, int K, float budget, uint32_t* ticket,
+                                uint64_t* status, uint32_t* ctl, uint32_t* lists, uint32_t* bucket_count,
+                                int64_t* counters, uint8_t* repaired, hipStream_t s) {
+    const int64_t nseg = T * K;
+    if (nseg == 0) return hipSuccess;
+    hipLaunchKernelGGL(select_prefix_kernel, dim3((unsigned)scan_blocks(nseg)), dim3(kThreads), 0, s, bin_off, nseg,
+                       K, budget, ticket, status, ctl, lists, bucket_count, counters, repaired);
+    hipLaunchKernelGGL(select_tail_kernel, dim3(1), dim3(kTailThreads), 0, s, bin_off, nseg, K, budget, ctl, lists,
+                       bucket_count, counters, repaired);
     return hipGetLastError();
 }
 

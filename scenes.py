@@ -250,7 +250,7 @@ def subset(g, idx):
 # ---------------------------------------------------------------------------
 
 def random_splats(n, width, height, tile_size=16, seed=0, depth_lo=1.0, depth_hi=50.0,
-                  max_sigma_px=12.0, tie_fraction=0.0, opacity_lo=0.02, hidden_fraction=0.0):
+                  max_sigma_px=12.0, tie_fraction=0.0, opacity_lo=0.02, hidden_fraction=0.0, smax_range=None):
     """Random projected splats (splats, info), see the layout above.
 
     Each splat's screen covariance has standard deviations log-uniform in
@@ -259,7 +259,9 @@ def random_splats(n, width, height, tile_size=16, seed=0, depth_lo=1.0, depth_hi
     of where any splat with opacity <= 1 can reach 1/255 (that needs
     q <= 2 ln 255 < 3.5^2). ``tie_fraction`` of the splats copy the depth of
     another one so that the id tie-break is exercised; ``hidden_fraction``
-    get an empty rect.
+    get an empty rect. ``smax_range`` = (lo, hi): word 11 (the largest world
+    axis scale) log-uniform in [lo, hi], drawn after everything else; None
+    leaves it zero.
     """
     rng = np.random.default_rng(seed)
     tx = (width + tile_size - 1) // tile_size
@@ -295,6 +297,8 @@ def random_splats(n, width, height, tile_size=16, seed=0, depth_lo=1.0, depth_hi
     y0 = np.clip(np.floor((my - ey) / tile_size), 0, ty).astype(np.int64)
     y1 = np.clip(np.floor((my + ey) / tile_size) + 1, 0, ty).astype(np.int64)
     x1 = np.where(hidden, x0, x1)
+    if smax_range is not None:
+        splats[:, 11] = np.exp(rng.uniform(np.log(smax_range[0]), np.log(smax_range[1]), size=n))
     return splats, make_info(depth, np.stack([x0, y0, x1, y1], 1))
 
 

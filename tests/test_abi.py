@@ -175,3 +175,40 @@ def test_backward_argument_errors():
 def test_error_type():
     with pytest.raises(tg.TileGSError):
         L.check(L.TGS_ERR_INVALID_ARG)
+
+
+def test_repair_mode_argument_errors():
+    lib = L.lib()
+    g = L.Gaussians(None, None, None, None, None, 0, 0)
+    out = L.Projected(None, None, 0)
+    p = L.Params()
+    lib.tgs_default_params(ctypes.byref(p))
+    assert (p.repair, p.near_shift) == (L.REPAIR_ALL, 0)
+    assert abs(p.repair_budget - 0.25) < 1e-7 and p.shift_alpha == 1.0 and p.shift_gamma == 0.25
+    cases = [(tg.Params(repair="rules", packed=1), L.TGS_ERR_UNSUPPORTED, "packed"),
+             (tg.Params(repair="none", packed=2), L.TGS_ERR_UNSUPPORTED, "packed"),
+             (tg.Params(repair="rules", repair_budget=1.5), L.TGS_ERR_INVALID_ARG, "repair_budget"),
+             (tg.Params(repair="rules", repair_budget=float("nan")), L.TGS_ERR_INVALID_ARG, "repair_budget"),
+             (tg.Params(near_shift=True, shift_gamma=1.0), L.TGS_ERR_INVALID_ARG, "shift_gamma"),
+             (tg.Params(near_shift=True, shift_alpha=-1.0), L.TGS_ERR_INVALID_ARG, "shift_alpha"),
+             (tg.Params(near_shift=True, shift_alpha=float("inf")), L.TGS_ERR_INVALID_ARG, "shift_alpha")]
+    for bad, code, word in cases:
+        st, msg = status_of(lib.tgs_project, ctypes.byref(g), ctypes.byref(cam()), ctypes.byref(bad.c()),
+                            ctypes.byref(out), None)
+        assert st == code and word in msg, (bad, st, msg)
+    raw = tg.Params().c()
+    raw.repair = 3
+    st, msg = status_of(lib.tgs_project, ctypes.byref(g), ctypes.byref(cam()), ctypes.byref(raw), ctypes.byref(out),
+                        None)
+    assert st == L.TGS_ERR_INVALID_ARG and "repair" in msg
+    raw = tg.Params(repair="rules").c()
+    raw.per_tile_bins = 0x1000
+    st, msg = status_of(lib.tgs_project, ctypes.byref(g), ctypes.byref(cam()), ctypes.byref(raw), ctypes.byref(out),
+                        None)
+    assert st == L.TGS_ERR_UNSUPPORTED and "uniform" in msg
+    # the selection scan needs its own status words (one pair per 4096 segments)
+    c = cam(1920, 1080)
+    base = lib.tgs_bin_workspace_size(1000, 5000, ctypes.byref(c), ctypes.byref(tg.Params().c()), L.ORDER_BINNED)
+    rules = lib.tgs_bin_workspace_size(1000, 5000, ctypes.byref(c), ctypes.byref(tg.paper_params().c()),
+                                       L.ORDER_BINNED)
+    assert rules > base

@@ -70,6 +70,9 @@ def test_project_matches_oracle(case):
     np.testing.assert_allclose(s[v, 4:7], ref["conic"][v], rtol=2e-7, atol=1e-12 * np.abs(ref["conic"][v]).max())
     np.testing.assert_allclose(s[v, 7], ref["opacity"][v], rtol=2e-7)
     np.testing.assert_allclose(s[v, 8:11], ref["rgb"][v], rtol=2e-7, atol=1e-7)
+    # largest axis scale (word 11, the near-depth key's s_max): one rounding
+    # of a binary64 exp on both sides
+    np.testing.assert_allclose(s[v, 11], ref["smax"][v], rtol=1.2e-7, atol=0)
 
 
 # ---------------------------------------------------------------------------

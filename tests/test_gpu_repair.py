@@ -1,0 +1,198 @@
+"""GPU parity of the paper's selective-repair mode (near-depth binning key,
+keep rules, first-fit entry budget; section "Repair for correctness" and
+the supplement's selection algorithm) and of the no-repair ablation.
+
+Bars: depth range, bin offsets, the selected segments (one flag per
+segment) and the selected entry count bit-exact against the oracle; every
+selected segment's entries in exactly the oracle's order; every other
+segment the oracle's entries as a multiset (their order is the parallel
+scatter's and not defined). With every segment sorted (exact repair) the
+near-depth-keyed stream is fully deterministic and is compared bit for bit,
+and its image within 1e-4 of the oracle composited over the same order.
+"""
+import functools
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import scenes
+from helpers import image_compare, proj_to_splats, to_np
+
+pytestmark = pytest.mark.gpu
+
+tg = pytest.importorskip("paper_2609_03613_amd")
+
+TOL = 1e-4
+
+
+def dev():
+    return torch.device("cuda:0")
+
+
+def cam_for(W, H, f=100.0):
+    return scenes.camera(np.eye(3), np.zeros(3), f, f, W / 2, H / 2, W, H)
+
+
+def run_bin(splats_np, info_np, cam, params):
+    r = tg.Renderer(cam, params, device=dev())
+    s = torch.as_tensor(splats_np).to(dev())
+    i = torch.as_tensor(np.ascontiguousarray(info_np).view(np.int32)).to(dev())
+    b = r.bin(s, i, "binned")
+    torch.cuda.synchronize()
+    return r, s, i, b
+
+
+def keyed_reference(splats, info, cam, K, shift=True):
+    depth, rect = scenes.info_depth(info), scenes.info_rects(info)
+    key = (oracle.near_keys(depth, splats[:, 11], 1.0, 0.25, cam["znear"], cam["zfar"]) if shift else depth)
+    tx = (int(cam["width"]) + 15) // 16
+    ty = (int(cam["height"]) + 15) // 16
+    ref = oracle.schedule_keyed(depth, key, rect, tx, ty, K=K, znear=cam["znear"], zfar=cam["zfar"])
+    return ref, tx * ty
+
+
+def check_segments(pairs, ref, sel):
+    """Selected segments exactly as the oracle's; the others as multisets."""
+    off = ref["bin_offsets"].astype(np.int64)
+    lens = np.diff(off)
+    seg = np.repeat(np.arange(len(lens)), lens)
+    order = np.lexsort((pairs, seg))
+    assert np.array_equal(pairs[order], ref["stream"]), "segment contents differ"
+    on = np.repeat(sel.astype(bool), lens)
+    assert np.array_equal(pairs[on], ref["stream"][on]), "a selected segment is not in the oracle's order"
+
+
+SPLAT_CASES = [  # n, W, H, K, seed, ties
+    (3000, 200, 150, 8, 1, 0.0),
+    (6000, 160, 160, 16, 2, 0.2),
+    (20000, 320, 240, 64, 3, 0.05),
+]
+
+
+@pytest.mark.parametrize("case", SPLAT_CASES)
+def test_near_shift_exact_repair_bit_exact(case):
+    n, W, H, K, seed, ties = case
+    splats, info = scenes.random_splats(n, W, H, seed=seed, tie_fraction=ties, smax_range=(0.01, 8.0))
+    cam = cam_for(W, H)
+    ref, T = keyed_reference(splats, info, cam, K)
+    _, _, _, b = run_bin(splats, info, cam, tg.Params(num_bins=K, near_shift=True))
+    M = ref["M"]
+    assert b.num_entries == M
+    assert np.array_equal(to_np(b.zrange).view(np.uint32), ref["zrange"].view(np.uint32))
+    assert np.array_equal(to_np(b.offsets).view(np.uint32), ref["bin_offsets"])
+    assert np.array_equal(to_np(b.pairs)[:M].view(np.uint64), ref["stream"])
+    lens = np.diff(ref["bin_offsets"].astype(np.int64))
+    assert np.array_equal(to_np(b.repaired)[:T * K], (lens >= 2).astype(np.uint8))
+    assert int(to_np(b.counters)[3]) == int(lens[lens >= 2].sum())
+    # the shift changed some bins (otherwise this case would not test it)
+    plain, _ = keyed_reference(splats, info, cam, K, shift=False)
+    assert not np.array_equal(plain["bin_offsets"], ref["bin_offsets"])
+
+
+# Projected scenes of the surface structure: their depth slices are
+# concentrated enough for the keep rules to fire and for the budget to bind.
+PROJ_CASES = [  # kind, n, W, H, seed, K
+    ("training", 30000, 320, 208, 4, 8),
+    ("training", 60000, 480, 270, 5, 16),
+    ("surface", 50000, 480, 270, 6, 64),
+]
+
+
+@functools.lru_cache(maxsize=None)
+def projected_case(kind, n, W, H, seed):
+    if kind == "training":
+        g, cam = scenes.training_scene(seed=seed, n=n, width=W, height=H)
+    else:
+        g, cam = scenes.scene_1080p(seed=seed, n=n, width=W, height=H, focal=275.0)
+    proj = oracle.project(g, cam)
+    splats, info = proj_to_splats(proj)
+    return splats, info, cam, proj
+
+
+@pytest.mark.parametrize("budget", [0.0, 0.01, 0.05, 0.25, 1.0])
+@pytest.mark.parametrize("case", PROJ_CASES)
+def test_rules_selection_matches_oracle(case, budget):
+    kind, n, W, H, seed, K = case
+    splats, info, cam, _ = projected_case(kind, n, W, H, seed)
+    ref, T = keyed_reference(splats, info, cam, K)
+    sel, used = oracle.repair_select(ref["bin_offsets"], T, K, budget)
+    p = tg.paper_params(num_bins=K, repair_budget=budget)
+    r, s, i, b = run_bin(splats, info, cam, p)
+    M = ref["M"]
+    assert b.num_entries == M
+    assert np.array_equal(to_np(b.zrange).view(np.uint32), ref["zrange"].view(np.uint32))
+    assert np.array_equal(to_np(b.offsets).view(np.uint32), ref["bin_offsets"])
+    rep = to_np(b.repaired)[:T * K].copy()
+    assert np.array_equal(rep, sel), (int(rep.sum()), int(sel.sum()))
+    assert int(to_np(b.counters)[3]) == used
+    check_segments(to_np(b.pairs)[:M].view(np.uint64), ref, sel)
+    # the selection is deterministic
+    b2 = r.bin(s, i, "binned")
+    torch.cuda.synchronize()
+    assert np.array_equal(to_np(b2.repaired)[:T * K], rep)
+
+
+def test_budget_binds_in_the_tail():
+    # many kept segments and a budget that is reached early, so most of the
+    # first-fit scan runs after the first segment that does not fit
+    splats, info = scenes.random_splats(40000, 256, 256, seed=7, max_sigma_px=20.0, smax_range=(0.01, 2.0))
+    cam = cam_for(256, 256)
+    K = 16
+    ref, T = keyed_reference(splats, info, cam, K)
+    kept, kept_n = oracle.repair_select(ref["bin_offsets"], T, K, 1.0)
+    for budget in (0.02, 0.1):
+        sel, used = oracle.repair_select(ref["bin_offsets"], T, K, budget)
+        assert kept_n > budget * ref["M"] and 0 < sel.sum() < kept.sum()
+        _, _, _, b = run_bin(splats, info, cam, tg.paper_params(num_bins=K, repair_budget=budget))
+        assert np.array_equal(to_np(b.repaired)[:T * K], sel)
+        assert int(to_np(b.counters)[3]) == used
+        check_segments(to_np(b.pairs)[:ref["M"]].view(np.uint64), ref, sel)
+
+
+@pytest.mark.parametrize("case", SPLAT_CASES[:2])
+def test_no_repair(case):
+    n, W, H, K, seed, ties = case
+    splats, info = scenes.random_splats(n, W, H, seed=seed, tie_fraction=ties, smax_range=(0.01, 8.0))
+    cam = cam_for(W, H)
+    ref, T = keyed_reference(splats, info, cam, K)
+    _, _, _, b = run_bin(splats, info, cam, tg.Params(num_bins=K, near_shift=True, repair="none"))
+    assert not to_np(b.repaired)[:T * K].any()
+    assert int(to_np(b.counters)[3]) == 0
+    check_segments(to_np(b.pairs)[:ref["M"]].view(np.uint64), ref, np.zeros(T * K, np.uint8))
+
+
+def test_paper_mode_image():
+    """Near-shift stream with every segment sorted: the whole image within
+    1e-4 of the oracle composited over the same order. Paper mode: the same
+    on every tile whose multi-entry segments were all selected; the error
+    elsewhere is measured against the exact image and reported."""
+    splats, info, cam, proj = projected_case("training", 30000, 320, 208, 4)
+    W, H, K = 320, 208, 4
+    ref, T = keyed_reference(splats, info, cam, K)
+    ids = (ref["stream"] & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+    tile_off = ref["bin_offsets"][::K]
+    want = oracle.render_stream(proj, W, H, tile_off, ids)
+    r, s, i, b = run_bin(splats, info, cam, tg.Params(num_bins=K, near_shift=True))
+    out = r.rasterize(s, i, b)
+    torch.cuda.synchronize()
+    e_rgb, e_a, nflag = image_compare(to_np(out["rgb"]), to_np(out["alpha"]), want)
+    assert e_rgb <= TOL and e_a <= TOL and nflag < 0.005 * W * H, (e_rgb, e_a, nflag)
+
+    rp, sp_, ip, bp = run_bin(splats, info, cam, tg.paper_params(num_bins=K, repair_budget=1.0))
+    outp = rp.rasterize(sp_, ip, bp)
+    torch.cuda.synchronize()
+    lens = np.diff(ref["bin_offsets"].astype(np.int64)).reshape(T, K)
+    sel = to_np(bp.repaired)[:T * K].reshape(T, K).astype(bool)
+    clean = np.all(sel | (lens <= 1), axis=1)  # tiles whose order is fully defined
+    assert clean.any()
+    tx = (W + 15) // 16
+    pix_tile = (np.arange(H)[:, None] // 16) * tx + (np.arange(W)[None, :] // 16)
+    mask = clean[pix_tile] & (want["flags"] == 0)
+    d = np.abs(to_np(outp["rgb"]).astype(np.float64) - want["rgb"])[mask]
+    assert d.size and d.max() <= TOL, d.max()
+    exact = oracle.render(proj, W, H)
+    err = float(np.abs(to_np(outp["rgb"]).astype(np.float64) - exact["rgb"]).max())
+    print(f"paper mode: {int(clean.sum())}/{T} tiles fully ordered, max |delta| vs exact image {err:.3e}")
+    assert np.isfinite(err) and err < 1.0
