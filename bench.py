@@ -68,12 +68,16 @@ def parse():
     ap.add_argument("--config", default="1080p", choices=["1080p", "small"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--mode", default="frame", choices=["frame", "kernels", "train", "batch", "learned"],
+    ap.add_argument("--mode", default="frame", choices=["frame", "kernels", "train", "batch", "learned", "repair",
+                                                      "scale"],
                     help="kernels: only launch the product and comparator raster kernels and a "
                          "256 MiB device copy (for profiler counter runs); train: only the training "
                          "step (forward + backward) on the 500k-Gaussian 1297x840 scene")
     ap.add_argument("--no-train", action="store_true", help="skip the training-step measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched multi-camera measurement")
+    ap.add_argument("--no-repair", action="store_true", help="skip the repair-variant ablation")
+    ap.add_argument("--no-ksweep", action="store_true", help="skip the bins-per-tile sweep")
+    ap.add_argument("--scale-max", type=int, default=30, help="largest N (millions) of --mode scale")
     return ap.parse_args()
 
 
@@ -295,6 +299,180 @@ def learned_bins(args):
             "images_equal": same, "per_tile_bins": {int(k): int(c) for k, c in zip(ks, counts)}}
 
 
+def repair_ablation(args, gd, cam):
+    """Repair variants on the same workload: the exact default, every
+    segment sorted on near-depth bins, the paper's rule-based selection with
+    the 25 % entry budget (near-depth bins, and plain depth bins), and no
+    repair. Per variant: bin stage, raster and whole-frame ms (HIP events,
+    medians), the repaired share of the entries, and the image error against
+    the exact image (max |delta|, PSNR over RGB, pixels off by more than
+    1e-4), plus the largest change between two frames of the same variant
+    (unsorted segments keep the scatter's order, which varies)."""
+    import torch
+    import paper_2609_03613_amd as tg
+    dev = gd["means"].device
+    stream = torch.cuda.current_stream()
+    variants = [("exact: all segments, depth bins", tg.Params()),
+                ("all segments, near-depth bins", tg.Params(near_shift=True)),
+                ("paper: rules + 25% budget, near-depth bins", tg.paper_params()),
+                ("rules + 25% budget, depth bins", tg.Params(repair="rules")),
+                ("none, near-depth bins", tg.Params(near_shift=True, repair="none"))]
+    steps = max(args.steps, 10)
+
+    def timed(fn):
+        for _ in range(3):
+            fn()
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        torch.cuda.synchronize()
+        e[0].record(stream)
+        for k in range(steps):
+            fn()
+            e[k + 1].record(stream)
+        torch.cuda.synchronize()
+        return float(np.median([e[k].elapsed_time(e[k + 1]) for k in range(steps)]))
+
+    out, ref = {}, None
+    for name, prm in variants:
+        r = tg.Renderer(cam, prm, device=dev)
+        s, i = tg.project(gd, cam)
+        b = r.bin(s, i, "binned", sync=True)
+        M = b.num_entries
+        img = r.rasterize(s, i, b)
+        frame_out = {k: torch.empty_like(v) for k, v in img.items()}
+        bin_ms = timed(lambda: r.bin(s, i, "binned", sync=False))
+        b = r.bin(s, i, "binned", sync=True)
+        rep = int(b.counters[3].item())
+        segs = int(b.repaired[: r.tiles * prm.num_bins].sum().item())
+        img = {k: v.clone() for k, v in r.rasterize(s, i, b).items()}
+        raster_ms = timed(lambda: r.rasterize(s, i, b, out=frame_out))
+
+        def frame():
+            s2, i2 = tg.project(gd, cam, prm, out=(s, i))
+            r.rasterize(s2, i2, r.bin(s2, i2, "binned", sync=False), out=frame_out)
+        frame_ms = timed(frame)
+        b2 = r.bin(s, i, "binned", sync=True)
+        img2 = r.rasterize(s, i, b2)
+        torch.cuda.synchronize()
+        rgb = img["rgb"].double()
+        if ref is None:
+            ref = rgb
+        d = (rgb - ref).abs()
+        mse = float(((rgb - ref) ** 2).mean().item())
+        out[name] = {"bin_ms": bin_ms, "raster_ms": raster_ms, "frame_ms": frame_ms,
+                     "repaired_entries_frac": rep / max(M, 1), "repaired_segments": segs,
+                     "max_abs_delta_vs_exact": float(d.max().item()),
+                     "psnr_vs_exact_db": (float("inf") if mse == 0.0 else float(10.0 * np.log10(1.0 / mse))),
+                     "pixels_off_1e-4": int((d.amax(dim=2) > 1e-4).sum().item()),
+                     "frame_to_frame_max_delta": float((img2["rgb"].double() - rgb).abs().max().item())}
+    return out
+
+
+def k_sweep(args, gd, cam):
+    """Bins per tile K in {4, ..., 128} on the same workload (the paper's
+    bin-count ablation): bin stage, raster and whole-frame ms, and whether
+    the image equals the K = 64 one bit for bit (exact repair makes the
+    stream independent of K)."""
+    import torch
+    import paper_2609_03613_amd as tg
+    dev = gd["means"].device
+    stream = torch.cuda.current_stream()
+    steps = max(args.steps, 10)
+
+    def timed(fn):
+        for _ in range(3):
+            fn()
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        torch.cuda.synchronize()
+        e[0].record(stream)
+        for k in range(steps):
+            fn()
+            e[k + 1].record(stream)
+        torch.cuda.synchronize()
+        return float(np.median([e[k].elapsed_time(e[k + 1]) for k in range(steps)]))
+
+    out, ref = {}, None
+    for K in (64, 4, 8, 16, 32, 128):
+        prm = tg.Params(num_bins=K)
+        r = tg.Renderer(cam, prm, device=dev)
+        s, i = tg.project(gd, cam)
+        b = r.bin(s, i, "binned", sync=True)
+        img = {k: v.clone() for k, v in r.rasterize(s, i, b).items()}
+        buf = {k: torch.empty_like(v) for k, v in img.items()}
+        bin_ms = timed(lambda: r.bin(s, i, "binned", sync=False))
+        raster_ms = timed(lambda: r.rasterize(s, i, b, out=buf))
+
+        def frame():
+            s2, i2 = tg.project(gd, cam, prm, out=(s, i))
+            r.rasterize(s2, i2, r.bin(s2, i2, "binned", sync=False), out=buf)
+        frame_ms = timed(frame)
+        if ref is None:
+            ref = img
+        same = bool(torch.equal(img["rgb"], ref["rgb"]) and torch.equal(img["last"], ref["last"]))
+        lens = torch.diff(b.offsets[: r.tiles * K + 1].long())
+        out[K] = {"bin_ms": bin_ms, "raster_ms": raster_ms, "frame_ms": frame_ms, "image_equals_k64": same,
+                  "segments_ge2": int((lens >= 2).sum().item()), "longest_segment": int(lens.max().item())}
+    return {int(k): out[k] for k in sorted(out)}
+
+
+def scale_up(args):
+    """Synthetic scale-up with the 1080p workload's structure: N = 5M ..
+    30M Gaussians (seeded random subsets of one 30M-Gaussian draw on the 64
+    surfaces, SH3, same 1920x1080 camera); per N the ordering stage (binned:
+    range, bins, repair; global: key emission, radix sort, tile ranges), the
+    raster and the whole frame, medians over the steps (the paper's
+    scale-up table)."""
+    import torch
+    import paper_2609_03613_amd as tg
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    steps = max(min(args.steps, 10), 5)
+    top = int(args.scale_max)
+    t0 = time.perf_counter()
+    g_all, cam = scenes.scene_1080p(seed=0, n=top * 1_000_000)
+    print(f"scale: generated {top}M Gaussians in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    perm = np.random.default_rng(1).permutation(top * 1_000_000)
+    rows = {}
+    for n_m in range(5, top + 1, 5):
+        idx = np.sort(perm[: n_m * 1_000_000])
+        gd = tg.to_device(scenes.subset(g_all, idx), dev)
+        rb = tg.Renderer(cam, tg.Params(), device=dev)
+        rg = tg.Renderer(cam, tg.Params(raster="plain", tile_order=False), device=dev)
+        s, i = tg.project(gd, cam)
+        bb = rb.bin(s, i, "binned", sync=True)
+        bgl = rg.bin(s, i, "global", sync=True)
+        M = bb.num_entries
+        H, W = cam["height"], cam["width"]
+        buf = {"rgb": torch.empty((H, W, 3), device=dev), "alpha": torch.empty((H, W), device=dev),
+               "last": torch.empty((H, W), dtype=torch.int32, device=dev)}
+
+        def stages(r, order):
+            ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+            for k in range(steps + 2):
+                e = ev[k - 2] if k >= 2 else None
+                if e: e[0].record(stream)
+                s2, i2 = tg.project(gd, cam, r.params, out=(s, i))
+                if e: e[1].record(stream)
+                b2 = r.bin(s2, i2, order, sync=(order == "global"))
+                if e: e[2].record(stream)
+                r.rasterize(s2, i2, b2, out=buf)
+                if e: e[3].record(stream)
+            torch.cuda.synchronize()
+            a = np.array([[e[j].elapsed_time(e[j + 1]) for j in range(3)] + [e[0].elapsed_time(e[3])] for e in ev])
+            return np.median(a, 0).tolist()
+
+        pb, sb, rb_ms, tb = stages(rb, "binned")
+        pg, sg, rg_ms, tg_ms = stages(rg, "global")
+        rows[n_m] = {"entries": M, "sort_ms": {"global": sg, "binned": sb, "x": sg / sb},
+                     "raster_ms": {"global": rg_ms, "binned": rb_ms, "x": rg_ms / rb_ms},
+                     "total_ms": {"global": tg_ms, "binned": tb, "x": tg_ms / tb}, "project_ms": pb}
+        print(f"scale: {n_m}M done ({M} entries, binned {tb:.3f} ms, global {tg_ms:.3f} ms)",
+              file=sys.stderr, flush=True)
+        del gd, rb, rg, s, i, bb, bgl
+        torch.cuda.empty_cache()
+    return {"workload": "1080p scene-shaped structure, 5M..%dM Gaussians (random subsets of one draw), SH3, "
+                        "1920x1080, f=1100" % top, "rows": rows}
+
+
 def workload(name):
     if name == "1080p":
         g, cam = scenes.scene_1080p(seed=0)
@@ -341,6 +519,17 @@ def main():
         return
     if args.mode == "learned":
         print(json.dumps({"mode": "learned", **learned_bins(args)}), flush=True)
+        return
+    if args.mode == "scale":
+        print(json.dumps({"mode": "scale", **scale_up(args)}), flush=True)
+        return
+    if args.mode == "repair":
+        import torch
+        import paper_2609_03613_amd as tg
+        g, cam, desc = workload(args.config)
+        gd = tg.to_device(g, torch.device("cuda:0"))
+        print(json.dumps({"mode": "repair", "workload": desc, "variants": repair_ablation(args, gd, cam)}),
+              flush=True)
         return
     import torch
     import paper_2609_03613_amd as tg
@@ -507,6 +696,10 @@ def main():
                      "kernel": "raster_wave_kernel (binned, gather by id, per-block cull)",
                      "work": f"{n_support} alpha-supported pixel tests x {OPS_PER_TEST} lane-op slots"},
     }
+    if not args.no_repair:
+        result["repair_ablation"] = repair_ablation(args, gd, cam)
+    if not args.no_ksweep:
+        result["k_sweep"] = k_sweep(args, gd, cam)
     if not args.no_train:
         result["training_step"] = train_step(args)
     if not args.no_batch:

@@ -243,7 +243,8 @@ def subset(g, idx):
 # on their own. Two arrays per splat set:
 #   splats [n, 16] fp32: mean_x, mean_y (binary32 parts), mean_x_lo, mean_y_lo
 #       (the remainders, so that hi + lo carries the mean to ~1e-11 px),
-#       conic_a, conic_b, conic_c, opacity, r, g, b, five zeros.
+#       conic_a, conic_b, conic_c, opacity, r, g, b, s_max (the largest
+#       world axis scale; zero unless drawn), four zeros.
 #   info [n, 4] uint32: depth (binary32 bits), rect word 0 (x0 | y0 << 16),
 #       rect word 1 (x1 | y1 << 16), number of tiles; the rect is half-open
 #       in tile units.
