@@ -77,7 +77,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched multi-camera measurement")
     ap.add_argument("--no-repair", action="store_true", help="skip the repair-variant ablation")
     ap.add_argument("--no-ksweep", action="store_true", help="skip the bins-per-tile sweep")
-    ap.add_argument("--scale-max", type=int, default=30, help="largest N (millions) of --mode scale")
+    ap.add_argument("--scale-sizes", default="5,10,15,20,25,30",
+                    help="Gaussian counts (millions) of --mode scale, comma separated")
     return ap.parse_args()
 
 
@@ -426,13 +427,14 @@ def scale_up(args):
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     steps = max(min(args.steps, 10), 5)
-    top = int(args.scale_max)
+    sizes = sorted({int(v) for v in args.scale_sizes.split(",") if v.strip()})
+    top = sizes[-1]
     t0 = time.perf_counter()
     g_all, cam = scenes.scene_1080p(seed=0, n=top * 1_000_000)
     print(f"scale: generated {top}M Gaussians in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     perm = np.random.default_rng(1).permutation(top * 1_000_000)
     rows = {}
-    for n_m in range(5, top + 1, 5):
+    for n_m in sizes:
         idx = np.sort(perm[: n_m * 1_000_000])
         gd = tg.to_device(scenes.subset(g_all, idx), dev)
         rb = tg.Renderer(cam, tg.Params(), device=dev)
@@ -469,8 +471,8 @@ def scale_up(args):
               file=sys.stderr, flush=True)
         del gd, rb, rg, s, i, bb, bgl
         torch.cuda.empty_cache()
-    return {"workload": "1080p scene-shaped structure, 5M..%dM Gaussians (random subsets of one draw), SH3, "
-                        "1920x1080, f=1100" % top, "rows": rows}
+    return {"workload": "1080p scene-shaped structure, %s M Gaussians (random subsets of one draw), SH3, "
+                        "1920x1080, f=1100" % ",".join(map(str, sizes)), "rows": rows}
 
 
 def workload(name):

@@ -277,7 +277,7 @@ __global__ void __launch_bounds__(256) bin_count_kernel(const uint4* __restrict_
                                                         int64_t nseg,
                                                         uint32_t* __restrict__ entry_rank, int64_t capacity) {
     __shared__ WaveGauss wg[4];
-    const uint32_t x = (uint32_t)xcc_id();
+    const uint32_t x = (uint32_t)xcc_id() % (uint32_t)kCopies;
     const int64_t S = VAR ? (int64_t)sm.seg_base[(int64_t)tiles_x * tiles_y] : nseg;
     uint32_t* cnt = count + (int64_t)x * S;
     for_wave_entries<true, VAR>(info, n, emit_off, tiles_x, tiles_y, zrange, nk, sm.K, &wg[threadIdx.x / kWave],

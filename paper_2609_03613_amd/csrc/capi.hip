@@ -125,7 +125,7 @@ int end_bit_for(int64_t T) {
 // [repair lists][per-XCD counts (BINNED, per-tile bin counts)] (BINNED) or
 // [...][unsorted keys][unsorted ids][sort scratch] (GLOBAL). The zeroed
 // region is cleared by one fill at the start of each tgs_bin; with per-tile
-// bin counts only the first kXcc * S words of the counts are cleared, by a
+// bin counts only the first kCopies * S words of the counts are cleared, by a
 // fill sized on the device. K is the uniform bin count or the bound of the
 // per-tile counts.
 Layout layout(int64_t n, int64_t capacity, int64_t T, int K, int order, bool var, bool rules) {
@@ -155,7 +155,7 @@ Layout layout(int64_t n, int64_t capacity, int64_t T, int K, int order, bool var
     if (order == TGS_ORDER_BINNED && !var) {
         z = (z + 63) & ~(size_t)63;
         L.count = z;
-        z += (size_t)kXcc * (size_t)nseg;
+        z += (size_t)kCopies * (size_t)nseg;
     }
     L.zero_words = z;
     L.zero = take(sizeof(uint32_t) * z);
@@ -163,7 +163,7 @@ Layout layout(int64_t n, int64_t capacity, int64_t T, int K, int order, bool var
         L.entry_rank = take(sizeof(uint32_t) * (size_t)capacity);
         L.seg_lists = take(sizeof(uint32_t) * (size_t)kBuckets * (size_t)nseg);
         if (var) {
-            L.count_var = take(sizeof(uint32_t) * (size_t)kXcc * (size_t)nseg);
+            L.count_var = take(sizeof(uint32_t) * (size_t)kCopies * (size_t)nseg);
             L.tile_seg = take(sizeof(uint2) * (size_t)T);
         }
     } else {
@@ -312,7 +312,7 @@ tgs_status tgs_bin(const tgs_projected* pr, const tgs_camera* cam, const tgs_par
         TGS_HIP(launch_seg_base(params->per_tile_bins_dev, T, K, out->seg_base_dev, tile_seg, zero + kTicketSegs,
                                 (uint64_t*)(zero + L.status_segs), s),
                 "segment bases");
-        TGS_HIP(launch_fill_u32_dyn(count, 0u, nseg_dev, kXcc, (int64_t)kXcc * nseg, s), "clear counts");
+        TGS_HIP(launch_fill_u32_dyn(count, 0u, nseg_dev, kCopies, (int64_t)kCopies * nseg, s), "clear counts");
     }
     const float zn = (float)cam->znear, zf = (float)cam->zfar;
     const NearKey nk{params->near_shift ? reinterpret_cast<const float4*>(pr->splats_dev) : nullptr,

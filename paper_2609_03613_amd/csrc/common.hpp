@@ -78,6 +78,11 @@ __device__ __forceinline__ int xcc_id() {
     return (int)(__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 7u);
 }
 constexpr int kXcc = 8;
+#ifndef TGS_COUNT_COPIES
+#define TGS_COUNT_COPIES 8
+#endif
+// Copies of the (tile, bin) counts; waves count into copy xcc_id() mod kCopies.
+constexpr int kCopies = TGS_COUNT_COPIES;
 
 // -0.5 / ln 2: with the conic scaled by it, exp(-q / 2) = exp2(q').
 constexpr float kHalfLog2e = -0.72134752044448170f;

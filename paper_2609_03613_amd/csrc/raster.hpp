@@ -177,37 +177,79 @@ __device__ __forceinline__ void composite_staged(Pix& p, float px, float py, con
 // WAVE raster's main loop): 64 entries at a time, kept when the block mask
 // (A.masks) or the conservative block test on the gathered splat says they
 // can reach alpha 1/255 in the block, compacted into the wavefront's LDS
-// slots st[] and composited by every lane.
+// slots st[] and composited by every lane. Without masks the gathers are
+// software-pipelined: while chunk i is culled and composited, the splats of
+// chunk i + 1 and the ids of chunk i + 2 are in flight.
 template <int SRC, bool COUNT>
 __device__ __forceinline__ void wave_forward(const RasterArgs& A, Staged* st, int bi, uint32_t begin, uint32_t end,
                                              float ox, float oy, float px, float py, float xa, float xb, float ya,
                                              float yb, Pix& p) {
     const int l = lane();
-    const uint32_t bit = 1u << bi;  // block masks exist for 16-pixel tiles only (bi < 4)
-    for (uint32_t base = begin; base < end; base += kWave) {
-        if (ballot(!p.done) == 0) break;
-        const uint32_t e = base + l;
-        bool keep = e < end;
-        Staged s;
-        if (A.masks) {
+    if (A.masks) {
+        const uint32_t bit = 1u << bi;  // block masks exist for 16-pixel tiles only (bi < 4)
+        for (uint32_t base = begin; base < end; base += kWave) {
+            if (ballot(!p.done) == 0) break;
+            const uint32_t e = base + l;
+            bool keep = e < end;
+            Staged s;
             // the block mask decides; only survivors fetch their entry
             if (keep) keep = (A.masks[e] & bit) != 0;
             if (keep) s = load_entry<SRC>(A, e, ox, oy);
-        } else if (keep) {
-            const uint32_t g = id_at<SRC>(A, e);
-            const float4* q = reinterpret_cast<const float4*>(A.splats) + kSplatVec * (int64_t)g;
-            const float4 q0 = q[0], q1 = q[1], q2 = q[2];
+            const uint64_t m = ballot(keep);
+            if (m == 0) continue;
+            if (keep) st[rank_in(m)] = s;
+            wave_sync();
+            composite_staged<COUNT>(p, px, py, st, __builtin_popcountll(m));
+            wave_sync();
+        }
+        return;
+    }
+    if (begin >= end) return;
+    const float4* sp = reinterpret_cast<const float4*>(A.splats);
+    // Two register sets alternate (the loop is unrolled by two, so no set is
+    // copied while its loads are in flight): chunk i is processed from one
+    // set while the other receives chunk i + 1, whose ids arrived during
+    // chunk i - 1. Every lane issues every load (lanes past the range read
+    // the range's last entry and are dropped by the range test), so the
+    // loads stay in issue order and only the older set is waited for.
+    auto id_clamped = [&](uint32_t e) { return id_at<SRC>(A, e < end ? e : end - 1); };
+    auto gather = [&](uint32_t g, float4& r0, float4& r1, float4& r2) {
+        const float4* q = sp + kSplatVec * (int64_t)g;
+        r0 = q[0];
+        r1 = q[1];
+        r2 = q[2];
+    };
+    auto chunk = [&](uint32_t base, const float4& c0, const float4& c1, const float4& c2, uint32_t g_next,
+                     float4& n0, float4& n1, float4& n2, uint32_t& g_after) {
+        const uint32_t e = base + l;
+        bool keep = e < end;
+        gather(g_next, n0, n1, n2);
+        g_after = id_clamped(e + 2 * kWave);
+        Staged s;
+        if (keep) {
             float s2;
-            stage_splat(q0, q1, q2, ox, oy, s.a, s.b, s2);
+            stage_splat(c0, c1, c2, ox, oy, s.a, s.b, s2);
             s.c = make_float2(s2, __int_as_float((int32_t)e));
-            keep = block_may_touch(s.a.x, s.a.y, q1.x, q1.y, q1.z, q1.w, xa, xb, ya, yb);
+            keep = block_may_touch(s.a.x, s.a.y, c1.x, c1.y, c1.z, c1.w, xa, xb, ya, yb);
         }
         const uint64_t m = ballot(keep);
-        if (m == 0) continue;
+        if (m == 0) return;
         if (keep) st[rank_in(m)] = s;
         wave_sync();
         composite_staged<COUNT>(p, px, py, st, __builtin_popcountll(m));
         wave_sync();
+    };
+    float4 a0, a1, a2, b0, b1, b2;
+    uint32_t ga = id_clamped(begin + l), gb;
+    gather(ga, a0, a1, a2);
+    gb = id_clamped(begin + kWave + l);
+    for (uint32_t base = begin;;) {
+        if (base >= end || ballot(!p.done) == 0) break;
+        chunk(base, a0, a1, a2, gb, b0, b1, b2, ga);
+        base += kWave;
+        if (base >= end || ballot(!p.done) == 0) break;
+        chunk(base, b0, b1, b2, ga, a0, a1, a2, gb);
+        base += kWave;
     }
 }
 

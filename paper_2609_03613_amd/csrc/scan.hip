@@ -184,7 +184,7 @@ __device__ __forceinline__ uint32_t seg_total(const uint32_t* __restrict__ count
     uint32_t t = 0;
     if (s < nseg)
 #pragma unroll
-        for (int x = 0; x < kXcc; ++x) t += count[(int64_t)x * nseg + s];
+        for (int x = 0; x < kCopies; ++x) t += count[(int64_t)x * nseg + s];
     return t;
 }
 
@@ -277,7 +277,7 @@ __global__ void __launch_bounds__(kThreads) bin_offsets_kernel(uint32_t* __restr
         if (sg < nseg) {
             bin_off[sg] = run;
 #pragma unroll
-            for (int x = 0; x < kXcc; ++x) {
+            for (int x = 0; x < kCopies; ++x) {
                 uint32_t* c = count + (int64_t)x * nseg + sg;
                 const uint32_t cv = *c;
                 *c = run;
