@@ -655,7 +655,15 @@ def main():
     n_support = int(cb["n_support"].sum().item())
     n_visit_b = int(cb["n_visit"].sum().item())
     n_visit_g = int(cg["n_visit"].sum().item())
-    same = bool(torch.equal(cb["rgb"], cg["rgb"]) and torch.equal(cb["last"], cg["last"]))
+    # the product without the heavy-tile split equals the comparator bit for
+    # bit; the split regroups the products of the longest tiles
+    r_unsplit = tg.Renderer(cam, tg.Params(raster="wave", packed=0, split_entries=0), device=dev)
+    cu = r_unsplit.rasterize(splats, info, r_unsplit.bin(splats, info, "binned", sync=True), counts=True)
+    torch.cuda.synchronize()
+    same = bool(torch.equal(cu["rgb"], cg["rgb"]) and torch.equal(cu["last"], cg["last"]))
+    split_diff = float((cb["rgb"] - cu["rgb"]).abs().max().item())
+    split_last_equal = bool(torch.equal(cb["last"], cu["last"]))
+    n_split = int(bb.tile_order[-1].item())
 
     raster_ms_b = float(np.median(ras_b))
     raster_ms_g = float(np.median(ras_g))
@@ -691,6 +699,8 @@ def main():
         "tests_per_pixel": {"support": n_support / (W * H), "visit_binned": n_visit_b / (W * H),
                             "visit_global": n_visit_g / (W * H)},
         "images_bitwise_equal": same,
+        "heavy_tile_split": {"tiles": n_split, "min_entries": tg.Params().split_entries,
+                             "max_abs_diff_vs_unsplit": split_diff, "last_equal": split_last_equal},
         "raster_ablation_ms": ablation,
         "bin_stage_ms_by_variant": bin_ms,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_LANE_OPS, "unit": "lane-op/s",

@@ -43,12 +43,13 @@ class Params:
     near_shift: bool = False  # bin on z - min(alpha s_max, gamma z) instead of z
     shift_alpha: float = 1.0
     shift_gamma: float = 0.25
+    split_entries: int = 4096  # tiles with this many entries are split over 4 wavefronts per block (0: never)
 
     def c(self):
         return L.Params(self.tile_size, self.num_bins, self.sample_count, self.p_lo, self.p_hi, self.pad,
                         RASTERS[self.raster], int(self.packed), _ptr(self.per_tile_bins).value,
                         REPAIRS[self.repair], float(self.repair_budget), int(bool(self.near_shift)),
-                        float(self.shift_alpha), float(self.shift_gamma))
+                        float(self.shift_alpha), float(self.shift_gamma), int(self.split_entries))
 
 
 def paper_params(**kw):
@@ -125,7 +126,7 @@ class Binned:
                 self.masks = torch.empty(cap, dtype=torch.uint8, **kw)
             if packed == 1:
                 self.records = torch.empty((cap, 12), dtype=torch.float32, **kw)
-        self.tile_order = torch.empty(max(tiles, 1), dtype=torch.int32, **kw) if tile_order else None
+        self.tile_order = torch.empty(tiles + 1, dtype=torch.int32, **kw) if tile_order else None
         self.seg_base = torch.empty(tiles + 1, dtype=torch.int32, **kw) if per_tile else None
         self.repaired = (torch.empty(max(tiles * num_bins, 1), dtype=torch.uint8, **kw)
                          if self.order == L.ORDER_BINNED else None)

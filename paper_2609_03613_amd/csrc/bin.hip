@@ -550,7 +550,7 @@ __global__ void __launch_bounds__(256) tile_hist_kernel(const uint32_t* __restri
 
 __global__ void __launch_bounds__(256) tile_place_kernel(const uint32_t* __restrict__ offsets, SegMap sm, int64_t T,
                                                          const uint32_t* __restrict__ hist, uint32_t* __restrict__ cursor,
-                                                         uint32_t* __restrict__ order) {
+                                                         uint32_t* __restrict__ order, int split) {
     __shared__ uint32_t h[kOrderBuckets], base[kOrderBuckets];
     if (threadIdx.x < kOrderBuckets) h[threadIdx.x] = 0;
     __syncthreads();
@@ -566,6 +566,15 @@ __global__ void __launch_bounds__(256) tile_place_kernel(const uint32_t* __restr
     }
     __syncthreads();
     if (act) order[base[b] + slot] = (uint32_t)t;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        // counts >= split = 2^h have a bit length > h: buckets 0 .. 31 - h
+        uint32_t nh = 0;
+        if (split > 0) {
+            const int last = 31 - (31 - __builtin_clz((uint32_t)split));
+            for (int k = 0; k <= last; ++k) nh += hist[k];
+        }
+        order[T] = nh;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -654,12 +663,12 @@ hipError_t launch_repair(const uint32_t* bin_off, int64_t nseg, uint64_t* pairs,
     return hipGetLastError();
 }
 
-hipError_t launch_tile_order(const uint32_t* offsets, SegMap sm, int64_t T, uint32_t* hist, uint32_t* order,
+hipError_t launch_tile_order(const uint32_t* offsets, SegMap sm, int64_t T, uint32_t* hist, uint32_t* order, int split,
                              hipStream_t s) {
     if (T == 0) return hipSuccess;
     hipLaunchKernelGGL(tile_hist_kernel, dim3(grid_for(T, 256)), dim3(256), 0, s, offsets, sm, T, hist);
     hipLaunchKernelGGL(tile_place_kernel, dim3(grid_for(T, 256)), dim3(256), 0, s, offsets, sm, T, hist,
-                       hist + kOrderBuckets, order);
+                       hist + kOrderBuckets, order, split);
     return hipGetLastError();
 }
 

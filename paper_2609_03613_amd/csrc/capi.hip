@@ -81,6 +81,9 @@ tgs_status check_params(const tgs_params* p) {
     if (p->repair == TGS_REPAIR_RULES && p->per_tile_bins_dev)
         return fail(TGS_ERR_UNSUPPORTED, "repair RULES needs a uniform num_bins");
     if (p->near_shift != 0 && p->near_shift != 1) return fail(TGS_ERR_INVALID_ARG, "near_shift must be 0 or 1");
+    if (p->split_entries != 0 &&
+        (p->split_entries < 256 || p->split_entries > (1 << 24) || (p->split_entries & (p->split_entries - 1))))
+        return fail(TGS_ERR_INVALID_ARG, "split_entries %d: 0 or a power of two in 256..2^24", p->split_entries);
     if (!(p->shift_alpha >= 0.f) || !isfinite(p->shift_alpha))
         return fail(TGS_ERR_INVALID_ARG, "shift_alpha must be finite and >= 0");
     if (!(p->shift_gamma >= 0.f && p->shift_gamma < 1.f))
@@ -200,6 +203,7 @@ void tgs_default_params(tgs_params* p) {
     p->near_shift = 0;
     p->shift_alpha = 1.0f;
     p->shift_gamma = 0.25f;
+    p->split_entries = 4096;
 }
 
 const char* tgs_last_error(void) { return g_err.c_str(); }
@@ -293,7 +297,7 @@ tgs_status tgs_bin(const tgs_projected* pr, const tgs_camera* cam, const tgs_par
         TGS_HIP(launch_tile_ranges(out->keys_dev, M, T, out->offsets_dev, s), "tile ranges");
         if (out->tile_order_dev)
             TGS_HIP(launch_tile_order(out->offsets_dev, SegMap{nullptr, 1, nullptr}, T, zero + kTileHist,
-                                      out->tile_order_dev, s),
+                                      out->tile_order_dev, params->split_entries, s),
                     "tile order");
         return TGS_OK;
     }
@@ -338,7 +342,9 @@ tgs_status tgs_bin(const tgs_projected* pr, const tgs_camera* cam, const tgs_par
     if (params->repair != TGS_REPAIR_NONE)
         TGS_HIP(launch_repair(out->offsets_dev, nseg, out->pairs_dev, seg_lists, bucket_count, rs, s), "repair");
     if (out->tile_order_dev)
-        TGS_HIP(launch_tile_order(out->offsets_dev, sm, T, zero + kTileHist, out->tile_order_dev, s), "tile order");
+        TGS_HIP(launch_tile_order(out->offsets_dev, sm, T, zero + kTileHist, out->tile_order_dev,
+                                  params->split_entries, s),
+                "tile order");
     return TGS_OK;
 }
 
@@ -388,6 +394,7 @@ tgs_status tgs_rasterize(const tgs_projected* pr, const tgs_binned* b, const tgs
     a.n_visit = n_visit;
     a.n_support = n_support;
     a.trans = trans;
+    a.split = params->split_entries;
     if (trans && params->raster != TGS_RASTER_WAVE) return fail(TGS_ERR_UNSUPPORTED, "trans needs the WAVE raster");
     hipStream_t s = (hipStream_t)stream;
     if (params->raster == TGS_RASTER_PLAIN)

@@ -25,9 +25,10 @@ struct Pix {
 // operation order, no implicit contraction, so both produce identical bits):
 // skip when q < 0 (rounding only) or alpha < 1/255; stop, without
 // compositing, when T (1 - alpha) < 1e-4; otherwise C += alpha T c and
-// T *= 1 - alpha.
+// T *= 1 - alpha. nostop (a later part of a split range, whose entering
+// transmittance is not known yet): every supported entry is composited.
 template <bool COUNT>
-__device__ __forceinline__ void blend(Pix& p, float px, float py, const Staged& s) {
+__device__ __forceinline__ void blend(Pix& p, float px, float py, const Staged& s, bool nostop = false) {
 #pragma clang fp contract(off)
     const float dx = s.a.x - px;
     const float dy = s.a.y - py;
@@ -38,7 +39,7 @@ __device__ __forceinline__ void blend(Pix& p, float px, float py, const Staged& 
     const bool sup = live && (q2 <= 0.0f) && (araw >= kAlphaMin);
     const float alpha = fminf(kAlphaMax, araw);
     const float test = p.T * (1.0f - alpha);
-    const bool comp = sup && (test >= kTMin);
+    const bool comp = sup && (nostop || test >= kTMin);
     if (COUNT) {
         p.nvis += live ? 1 : 0;
         p.nsup += sup ? 1 : 0;
@@ -162,14 +163,15 @@ __device__ __forceinline__ void wave_sync() {
 // Composites the cnt staged survivors of st[], two at a time (both read from
 // LDS before the first is evaluated).
 template <bool COUNT>
-__device__ __forceinline__ void composite_staged(Pix& p, float px, float py, const Staged* st, int cnt) {
+__device__ __forceinline__ void composite_staged(Pix& p, float px, float py, const Staged* st, int cnt,
+                                                 bool nostop = false) {
     int j = 0;
     for (; j + 2 <= cnt; j += 2) {
         const Staged s0 = st[j], s1 = st[j + 1];
-        blend<COUNT>(p, px, py, s0);
-        blend<COUNT>(p, px, py, s1);
+        blend<COUNT>(p, px, py, s0, nostop);
+        blend<COUNT>(p, px, py, s1, nostop);
     }
-    if (j < cnt) blend<COUNT>(p, px, py, st[j]);
+    if (j < cnt) blend<COUNT>(p, px, py, st[j], nostop);
 }
 
 
@@ -183,7 +185,7 @@ __device__ __forceinline__ void composite_staged(Pix& p, float px, float py, con
 template <int SRC, bool COUNT>
 __device__ __forceinline__ void wave_forward(const RasterArgs& A, Staged* st, int bi, uint32_t begin, uint32_t end,
                                              float ox, float oy, float px, float py, float xa, float xb, float ya,
-                                             float yb, Pix& p) {
+                                             float yb, Pix& p, bool nostop = false) {
     const int l = lane();
     if (A.masks) {
         const uint32_t bit = 1u << bi;  // block masks exist for 16-pixel tiles only (bi < 4)
@@ -199,7 +201,7 @@ __device__ __forceinline__ void wave_forward(const RasterArgs& A, Staged* st, in
             if (m == 0) continue;
             if (keep) st[rank_in(m)] = s;
             wave_sync();
-            composite_staged<COUNT>(p, px, py, st, __builtin_popcountll(m));
+            composite_staged<COUNT>(p, px, py, st, __builtin_popcountll(m), nostop);
             wave_sync();
         }
         return;
@@ -236,7 +238,7 @@ __device__ __forceinline__ void wave_forward(const RasterArgs& A, Staged* st, in
         if (m == 0) return;
         if (keep) st[rank_in(m)] = s;
         wave_sync();
-        composite_staged<COUNT>(p, px, py, st, __builtin_popcountll(m));
+        composite_staged<COUNT>(p, px, py, st, __builtin_popcountll(m), nostop);
         wave_sync();
     };
     float4 a0, a1, a2, b0, b1, b2;

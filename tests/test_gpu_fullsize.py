@@ -85,12 +85,14 @@ def test_fullsize_schedule_bit_exact():
     assert np.array_equal(to_np(bb.zrange).view(np.uint32), ref["zrange"].view(np.uint32))
     assert np.array_equal(to_np(bb.offsets).view(np.uint32), ref["bin_offsets"])
     assert np.array_equal(to_np(bb.pairs)[:M].view(np.uint64), ref["stream"])
-    # heaviest-first dispatch order: a permutation of the tiles, non-increasing bit length of the counts
+    # heaviest-first dispatch order: a permutation of the tiles, non-increasing bit length of the counts,
+    # then the number of tiles with at least split_entries (4096) entries
     order = to_np(bb.tile_order).view(np.uint32)
-    assert np.array_equal(np.sort(order), np.arange(120 * 68))
-    cnt = np.diff(ref["tile_offsets"].astype(np.int64))[order]
-    blen = np.where(cnt > 0, np.floor(np.log2(np.maximum(cnt, 1))) + 1, 0)
+    assert np.array_equal(np.sort(order[:-1]), np.arange(120 * 68))
+    cnt = np.diff(ref["tile_offsets"].astype(np.int64))
+    blen = np.where(cnt[order[:-1]] > 0, np.floor(np.log2(np.maximum(cnt[order[:-1]], 1))) + 1, 0)
     assert np.all(np.diff(blen) <= 0)
+    assert order[-1] == int((cnt >= 4096).sum()) > 0
 
 
 def test_fullsize_image_sampled_pixels():
@@ -107,12 +109,13 @@ def test_fullsize_image_sampled_pixels():
     gd = tg.to_device(g, dev())
     r = tg.Renderer(cam, tg.Params(), device=dev())
     splats, info = tg.project(gd, cam)
-    imgs = {}
+    imgs, lasts = {}, {}
     for order in ("binned", "global"):
         b = r.bin(splats, info, order)
         out = r.rasterize(splats, info, b)
         torch.cuda.synchronize()
         imgs[order] = to_np(out["rgb"])
+        lasts[order] = to_np(out["last"])
         rgb = imgs[order][pix[:, 1], pix[:, 0]].astype(np.float64)
         a = to_np(out["alpha"])[pix[:, 1], pix[:, 0]].astype(np.float64)
         m = want["flags"] == 0
@@ -120,7 +123,17 @@ def test_fullsize_image_sampled_pixels():
         e_rgb = np.abs(rgb - want["rgb"])[m].max()
         e_a = np.abs(a - want["alpha"])[m].max()
         assert e_rgb <= TOL and e_a <= TOL, (order, e_rgb, e_a)
-    assert np.array_equal(imgs["binned"], imgs["global"])
+    # both orders take the heavy-tile split on the same tiles; without it
+    # the product raster equals the comparator bit for bit
+    assert np.array_equal(imgs["binned"], imgs["global"]) and np.array_equal(lasts["binned"], lasts["global"])
+    r0 = tg.Renderer(cam, tg.Params(split_entries=0), device=dev())
+    rp = tg.Renderer(cam, tg.Params(raster="plain", tile_order=False), device=dev())
+    u = r0.rasterize(splats, info, r0.bin(splats, info, "binned"))
+    c = rp.rasterize(splats, info, rp.bin(splats, info, "global"))
+    torch.cuda.synchronize()
+    assert torch.equal(u["rgb"], c["rgb"]) and torch.equal(u["last"], c["last"])
+    assert float(np.abs(imgs["binned"] - to_np(u["rgb"])).max()) <= 1e-5
+    assert np.array_equal(lasts["binned"], to_np(u["last"]))
 
 
 def test_fullsize_paper_mode_selection():
