@@ -663,7 +663,7 @@ def main():
     same = bool(torch.equal(cu["rgb"], cg["rgb"]) and torch.equal(cu["last"], cg["last"]))
     split_diff = float((cb["rgb"] - cu["rgb"]).abs().max().item())
     split_last_equal = bool(torch.equal(cb["last"], cu["last"]))
-    n_split = int(bb.tile_order[-1].item())
+    n_split = [int(v) for v in bb.tile_order[-2:].tolist()]
 
     raster_ms_b = float(np.median(ras_b))
     raster_ms_g = float(np.median(ras_g))
@@ -699,7 +699,8 @@ def main():
         "tests_per_pixel": {"support": n_support / (W * H), "visit_binned": n_visit_b / (W * H),
                             "visit_global": n_visit_g / (W * H)},
         "images_bitwise_equal": same,
-        "heavy_tile_split": {"tiles": n_split, "min_entries": tg.Params().split_entries,
+        "heavy_tile_split": {"tiles": n_split[0], "tiles_with_half_as_many": n_split[1],
+                             "min_entries": tg.Params().split_entries, "waves_per_block": 8,
                              "max_abs_diff_vs_unsplit": split_diff, "last_equal": split_last_equal},
         "raster_ablation_ms": ablation,
         "bin_stage_ms_by_variant": bin_ms,

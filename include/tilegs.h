@@ -172,13 +172,13 @@ typedef struct {
     int32_t split_entries; /* 0, or a power of two in 256..2^24 (4096): with
                              the WAVE raster, 16-pixel tiles, packed = 0 and
                              a tile order, the (at most 1024) tiles with at
-                             least this many entries get 4 wavefronts per
-                             8x8 block, one per quarter of the range: a
-                             transmittance pass per quarter, then each
-                             quarter composited from its entering
-                             transmittance; images equal the unsplit ones up
-                             to rounding (<= 1e-6), last ids and counts
-                             except at that rounding */
+                             least this many entries get 8 wavefronts per
+                             8x8 block, each over an eighth of the range
+                             (merged in order, parts where a pixel stops
+                             walked again from their entering transmittance);
+                             images equal the unsplit ones up to rounding
+                             (<= 1e-6), last ids and counts except at that
+                             rounding */
 } tgs_params;
 
 /* Entry buffers written by tgs_bin and read by tgs_rasterize. All device
@@ -194,11 +194,12 @@ typedef struct {
    counters [4] int64: entries M, visible Gaussians V, overflow flag (1 when
        M > capacity: the stream was truncated and tgs_rasterize writes NaN),
        repaired entries (BINNED: the entries of the sorted segments).
-   tile_order [T + 1] (optional, NULL = none): tgs_bin writes the tiles in
+   tile_order [T + 2] (optional, NULL = none): tgs_bin writes the tiles in
        descending order of their entry count (grouped by the bit length of
        the count) and the WAVE raster dispatches tiles in that order, so the
-       longest tiles start first; tile_order[T] = the number of tiles with at
-       least params.split_entries entries (the first ones of the order).
+       longest tiles start first; tile_order[T] and [T + 1] = the numbers of
+       tiles with at least params.split_entries and split_entries / 2 entries
+       (the first ones of the order).
    seg_base [T + 1] (required with params.per_tile_bins_dev, else unused):
        tgs_bin writes the first segment of each tile, seg_base[T] = the
        number of segments S; offsets then holds S + 1 meaningful words (size

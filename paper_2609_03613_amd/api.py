@@ -126,7 +126,7 @@ class Binned:
                 self.masks = torch.empty(cap, dtype=torch.uint8, **kw)
             if packed == 1:
                 self.records = torch.empty((cap, 12), dtype=torch.float32, **kw)
-        self.tile_order = torch.empty(tiles + 1, dtype=torch.int32, **kw) if tile_order else None
+        self.tile_order = torch.empty(tiles + 2, dtype=torch.int32, **kw) if tile_order else None
         self.seg_base = torch.empty(tiles + 1, dtype=torch.int32, **kw) if per_tile else None
         self.repaired = (torch.empty(max(tiles * num_bins, 1), dtype=torch.uint8, **kw)
                          if self.order == L.ORDER_BINNED else None)

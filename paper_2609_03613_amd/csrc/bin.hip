@@ -567,13 +567,16 @@ __global__ void __launch_bounds__(256) tile_place_kernel(const uint32_t* __restr
     __syncthreads();
     if (act) order[base[b] + slot] = (uint32_t)t;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        // counts >= split = 2^h have a bit length > h: buckets 0 .. 31 - h
-        uint32_t nh = 0;
+        // counts >= split = 2^h have a bit length > h: buckets 0 .. 31 - h;
+        // order[T + 1] also counts those >= split / 2
+        uint32_t nh = 0, nh2 = 0;
         if (split > 0) {
             const int last = 31 - (31 - __builtin_clz((uint32_t)split));
             for (int k = 0; k <= last; ++k) nh += hist[k];
+            nh2 = nh + hist[last + 1];
         }
         order[T] = nh;
+        order[T + 1] = nh2;
     }
 }
 

@@ -335,9 +335,10 @@ hipError_t launch_repair(const uint32_t* bin_off, int64_t nseg, uint64_t* pairs,
                          const uint32_t* bucket_count, RecordSink rs, hipStream_t s);
 
 // Tiles in descending order of their entry count (coarse: by bit length of
-// the count), so the heaviest tiles are dispatched first; order[T] = the
-// number of tiles with at least `split` entries (a power of two; 0: none),
-// which are the first order[T] tiles. hist [66] must be zero.
+// the count), so the heaviest tiles are dispatched first; order[T] and
+// order[T + 1] = the numbers of tiles with at least `split` and split / 2
+// entries (split a power of two; 0: none), which come first. hist [66] must
+// be zero.
 hipError_t launch_tile_order(const uint32_t* offsets, SegMap sm, int64_t T, uint32_t* hist, uint32_t* order, int split,
                              hipStream_t s);
 
@@ -358,7 +359,7 @@ struct RasterArgs {
     const float* records;   // BINNED packed records or null
     const uint8_t* masks;   // block masks of the packed records
     const int64_t* counters;
-    const uint32_t* order;  // tile dispatch order [T + 1] or null
+    const uint32_t* order;  // tile dispatch order [T + 2] or null
     int split;              // WAVE, 16-pixel tiles, with order: split the first order[T] tiles
     int width, height, tile, tiles_x, tiles_y;  // tile: edge in pixels (the PLAIN raster: 16 only)
     float bg[3];

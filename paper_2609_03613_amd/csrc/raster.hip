@@ -79,22 +79,49 @@ __global__ void __launch_bounds__(256) raster_plain_kernel(RasterArgs A) {
 
 // ---------------------------------------------------------------------------
 
-// Heavy-tile split. A pixel is composited sequentially over its tile's
-// whole range, so the wavefronts of the few longest tiles decide when the
-// kernel ends. With A.split, the first NS = min(order[T], kSplitTiles)
-// tiles of the dispatch order (those with at least A.split entries) get one
-// workgroup per 8x8 block instead of one per tile, whose 4 wavefronts take
-// the 4 quarters of the range in two passes. Pass 1: each wavefront finds
-// its quarter's local transmittance T_k (every supported entry applied, no
-// stop test). From these each wavefront derives its entering transmittance
-// T_in = T_0 ... T_{k-1}, or that the pixel stopped in an earlier quarter
-// (a running product below 1e-4: the local transmittance only decreases, so
-// a quarter's last value is its smallest test). Pass 2: each wavefront
-// composites its quarter from T_in with the stop test, and the quarter-0
-// wavefront adds the colours and takes T and the last id of the last live
-// quarter. Images equal the unsplit ones up to the rounding of the
-// regrouped products; the critical path is about half a tile walk.
+template <int SRC, bool COUNT>
+__global__ void __launch_bounds__(256) raster_wave_kernel(RasterArgs A) {
+    __shared__ Staged stage[4][kWave];
+    const int w = threadIdx.x / kWave, l = lane();
+    WaveBlock wb;
+    if (!block_of_wave(A, w, wb)) return;
+    const int x0 = wb.tx * A.tile, y0 = wb.ty * A.tile;
+    float xa, xb, ya, yb;
+    if (!block_box_at(wb.bx, wb.by, x0, y0, A.width, A.height, xa, xb, ya, yb)) return;  // block outside the image
+    const int lx = wb.bx + (l & 7), ly = wb.by + (l >> 3);
+    const int x = x0 + lx, y = y0 + ly;
+    const bool inside = x < A.width && y < A.height;
+    const bool bad = A.counters[2] != 0;
+    const float ox = (float)x0, oy = (float)y0;
+    const float px = (float)lx + 0.5f, py = (float)ly + 0.5f;
+    Pix p{1.0f, 0.f, 0.f, 0.f, -1, 0, 0, 0, !inside || bad};
+    const uint32_t begin = tile_begin(A, wb.t);
+    const uint32_t end = bad ? begin : tile_end(A, wb.t);
+    wave_forward<SRC, COUNT>(A, stage[w], wb.bi, begin, end, ox, oy, px, py, xa, xb, ya, yb, p);
+    if (inside) write_pixel(A, x, y, p, bad);
+}
+
+// ---------------------------------------------------------------------------
+// Heavy-tile split (16-pixel tiles, heaviest-first dispatch order). A pixel
+// is composited sequentially over its tile's whole range, so the
+// wavefronts of the few longest tiles decide when the WAVE raster ends.
+// Workgroups of 8 wavefronts take, in this order: the first NA =
+// min(order[T], kSplitTiles) tiles of the order (at least A.split entries)
+// one 8x8 block each, with 8 parts of the range; all other tiles two per
+// workgroup, one wavefront per block, as in the WAVE raster. (Giving the
+// tiles of half that size 4 parts per block was measured no faster.) Part 0 of a block composites as usual; parts 1..
+// composite every supported entry from a local transmittance of 1, giving
+// local colour C_k and transmittance T_k. Each part then derives its
+// entering transmittance T_in = T_0 ... T_{k-1}, or that the pixel stopped
+// in an earlier part (a running product below 1e-4: the local
+// transmittance only decreases, so a part's last value is its smallest
+// test). A live part contributes T_in C_k and leaves T_in T_k, except where
+// T_in T_k < 1e-4: the pixel stops inside it, and the part is walked again
+// from T_in with the stop test. The part-0 wavefront adds the colours and
+// takes T and the last id of the last live part. Images equal the unsplit
+// ones up to the rounding of the regrouped products.
 constexpr int kSplitTiles = 1024;
+constexpr int kSplitWaves = 8;
 
 struct PixLds {
     float r, g, b, T;
@@ -102,82 +129,94 @@ struct PixLds {
 };
 
 template <int SRC, bool COUNT>
-__global__ void __launch_bounds__(256) raster_wave_kernel(RasterArgs A) {
-    __shared__ Staged stage[4][kWave];
-    __shared__ float tloc[4][kWave];
+__global__ void __launch_bounds__(kSplitWaves * kWave) raster_split_kernel(RasterArgs A) {
+    __shared__ Staged stage[kSplitWaves][kWave];
+    __shared__ float tloc[kSplitWaves][kWave];
     const int w = threadIdx.x / kWave, l = lane();
-    WaveBlock wb;
-    bool heavy = false;
-    if (A.split) {
-        // 16-pixel tiles, dispatch order present
-        const int T = A.tiles_x * A.tiles_y;
-        const int ns = min(min((int)A.order[T], T), kSplitTiles);
-        const int i = (int)blockIdx.x;
-        int slot;
-        if (i < 4 * ns) {
-            heavy = true;
-            slot = i >> 2;
-            wb.bi = i & 3;
-        } else {
-            slot = ns + (i - 4 * ns);
-            if (slot >= T) return;
-            wb.bi = w;
-        }
-        wb.t = (int)A.order[slot];
-        wb.tx = wb.t % A.tiles_x;
-        wb.ty = wb.t / A.tiles_x;
-        wb.bx = (wb.bi & 1) * 8;
-        wb.by = (wb.bi >> 1) * 8;
-    } else if (!block_of_wave(A, w, wb)) {
-        return;
+    const int T = A.tiles_x * A.tiles_y;
+    const int na = min(min((int)A.order[T], T), kSplitTiles);
+    const int i = (int)blockIdx.x;
+    int slot, bi, parts, part;
+    if (i < 4 * na) {
+        slot = i >> 2;
+        bi = i & 3;
+        parts = kSplitWaves;
+        part = w;
+    } else {
+        slot = na + 2 * (i - 4 * na) + (w >> 2);
+        bi = w & 3;
+        parts = 1;
+        part = 0;
+        if (slot >= T) return;
     }
-    const int x0 = wb.tx * A.tile, y0 = wb.ty * A.tile;
+    const int t = (int)A.order[slot];
+    const int bx = (bi & 1) * 8, by = (bi >> 1) * 8;
+    const int x0 = (t % A.tiles_x) * kTile, y0 = (t / A.tiles_x) * kTile;
     float xa, xb, ya, yb;
-    // block outside the image (uniform over a heavy tile's workgroup)
-    if (!block_box_at(wb.bx, wb.by, x0, y0, A.width, A.height, xa, xb, ya, yb)) return;
-    const int lx = wb.bx + (l & 7), ly = wb.by + (l >> 3);
+    // block outside the image (uniform over the wavefronts of a split block)
+    const bool valid = block_box_at(bx, by, x0, y0, A.width, A.height, xa, xb, ya, yb);
+    if (parts == 1 && !valid) return;
+    const int lx = bx + (l & 7), ly = by + (l >> 3);
     const int x = x0 + lx, y = y0 + ly;
-    const bool inside = x < A.width && y < A.height;
+    const bool inside = valid && x < A.width && y < A.height;
     const bool bad = A.counters[2] != 0;
     const float ox = (float)x0, oy = (float)y0;
     const float px = (float)lx + 0.5f, py = (float)ly + 0.5f;
-    const uint32_t begin = tile_begin(A, wb.t);
-    const uint32_t end = bad ? begin : tile_end(A, wb.t);
-    Pix p{1.0f, 0.f, 0.f, 0.f, -1, 0, 0, 0, !inside || bad};
-    if (!heavy) {
-        wave_forward<SRC, COUNT>(A, stage[w], wb.bi, begin, end, ox, oy, px, py, xa, xb, ya, yb, p);
+    const uint32_t begin = tile_begin(A, t);
+    const uint32_t end = bad ? begin : tile_end(A, t);
+    const bool out = !inside || bad;
+    Pix p{1.0f, 0.f, 0.f, 0.f, -1, 0, 0, 0, out};
+    if (parts == 1) {
+        wave_forward<SRC, COUNT>(A, stage[w], bi, begin, end, ox, oy, px, py, xa, xb, ya, yb, p);
         if (inside) write_pixel(A, x, y, p, bad);
         return;
     }
+    const int w0 = w - part;  // the block's part-0 wavefront
     const uint64_t len = end - begin;
-    const uint32_t qa = begin + (uint32_t)(len * (uint64_t)w / 4), qb = begin + (uint32_t)(len * (uint64_t)(w + 1) / 4);
-    const bool out = !inside || bad;
+    const uint32_t qa = begin + (uint32_t)(len * (uint64_t)part / parts);
+    const uint32_t qb = begin + (uint32_t)(len * (uint64_t)(part + 1) / parts);
+    // part 0 composites exactly; parts 1.. composite every supported entry
+    // from a local transmittance of 1
+    if (valid) wave_forward<SRC, COUNT>(A, stage[w], bi, qa, qb, ox, oy, px, py, xa, xb, ya, yb, p, part > 0);
+    // (a pixel that stopped inside part 0 publishes 0: every later part is dead)
+    tloc[w][l] = (part == 0 && p.done) ? 0.0f : p.T;
+    __syncthreads();
     float t_in = 1.0f;
     bool dead = out;
-    for (int pass = 0; pass < 2; ++pass) {
-        p = Pix{t_in, 0.f, 0.f, 0.f, -1, 0, 0, 0, dead};
-        wave_forward<SRC, COUNT>(A, stage[w], wb.bi, qa, qb, ox, oy, px, py, xa, xb, ya, yb, p, pass == 0);
-        if (pass == 0) {
-            tloc[w][l] = p.T;
-            __syncthreads();
-            for (int j = 0; j < w; ++j) {
-                const float tt = t_in * tloc[j][l];
-                dead = dead || tt < kTMin;
-                t_in = dead ? t_in : tt;
-            }
-        }
+    for (int j = 0; j < part; ++j) {
+        const float tt = t_in * tloc[w0 + j][l];
+        dead = dead || tt < kTMin;
+        t_in = dead ? t_in : tt;
     }
-    if (w > 0) reinterpret_cast<PixLds*>(stage[w])[l] = PixLds{p.r, p.g, p.b, p.T, p.last, p.ncon, p.nvis, p.nsup,
-                                                                dead ? 0 : 1};
+    // a pixel whose running product falls below 1e-4 inside this part stops
+    // in it: the part is walked again for those pixels, from t_in with the
+    // stop test (the other lanes are marked done, which leaves them as they are)
+    const bool fix = part > 0 && !dead && t_in * p.T < kTMin;
+    if (ballot(fix) != 0) {
+        if (fix) p = Pix{t_in, 0.f, 0.f, 0.f, -1, 0, 0, 0, false};
+        const bool keep_done = p.done;
+        p.done = !fix;
+        wave_forward<SRC, COUNT>(A, stage[w], bi, qa, qb, ox, oy, px, py, xa, xb, ya, yb, p);
+        p.done = keep_done;
+    }
+    if (part > 0 && !fix) {
+        p.r *= t_in;
+        p.g *= t_in;
+        p.b *= t_in;
+        p.T *= t_in;
+    }
+    if (part > 0) reinterpret_cast<PixLds*>(stage[w])[l] = PixLds{p.r, p.g, p.b, p.T, p.last, p.ncon, p.nvis, p.nsup,
+                                                                   dead ? 0 : 1};
     __syncthreads();
-    if (w > 0) return;
-    for (int j = 1; j < 4; ++j) {
-        const PixLds r = reinterpret_cast<const PixLds*>(stage[j])[l];
+    if (part > 0) return;
+    for (int j = 1; j < parts; ++j) {
+        const PixLds r = reinterpret_cast<const PixLds*>(stage[w + j])[l];
+        if (!r.live) continue;  // the pixel stopped in an earlier part
         p.r += r.r;
         p.g += r.g;
         p.b += r.b;
-        p.T = r.live ? r.T : p.T;
-        p.last = r.live && r.last >= 0 ? r.last : p.last;
+        p.T = r.T;
+        p.last = r.last >= 0 ? r.last : p.last;
         if (COUNT) {
             p.ncon += r.ncon;
             p.nvis += r.nvis;
@@ -185,6 +224,19 @@ __global__ void __launch_bounds__(256) raster_wave_kernel(RasterArgs A) {
         }
     }
     if (inside) write_pixel(A, x, y, p, bad);
+}
+
+template <int SRC>
+hipError_t split_dispatch(const RasterArgs& a, hipStream_t s) {
+    const int T = a.tiles_x * a.tiles_y;
+    // split blocks first, then two light tiles per workgroup; workgroups
+    // past the last item leave at once
+    const int grid = 4 * std::min(T, kSplitTiles) + (T + 1) / 2;
+    if (a.n_visit || a.n_support || a.n_contrib)
+        hipLaunchKernelGGL((raster_split_kernel<SRC, true>), dim3(grid), dim3(kSplitWaves * kWave), 0, s, a);
+    else
+        hipLaunchKernelGGL((raster_split_kernel<SRC, false>), dim3(grid), dim3(kSplitWaves * kWave), 0, s, a);
+    return hipGetLastError();
 }
 
 template <int SRC>
@@ -199,10 +251,10 @@ hipError_t plain_dispatch(const RasterArgs& a, hipStream_t s) {
 
 template <int SRC>
 hipError_t wave_dispatch(const RasterArgs& a, hipStream_t s) {
+    if (a.split) return split_dispatch<SRC>(a, s);
     const int T = a.tiles_x * a.tiles_y;
     const int B = blocks_per_tile(a.tile), G = groups_per_tile(a.tile);
-    const int extra = a.split ? 3 * std::min(T, kSplitTiles) : 0;
-    const dim3 grid((unsigned)(T * G + extra)), block((unsigned)(kWave * (B < 4 ? B : 4)));
+    const dim3 grid((unsigned)(T * G)), block((unsigned)(kWave * (B < 4 ? B : 4)));
     if (a.n_visit || a.n_support || a.n_contrib)
         hipLaunchKernelGGL((raster_wave_kernel<SRC, true>), grid, block, 0, s, a);
     else

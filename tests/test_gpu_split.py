@@ -1,7 +1,7 @@
 """Heavy-tile split of the WAVE raster: the tiles with at least
-split_entries entries get four wavefronts per 8x8 block (a transmittance
-pass per quarter of the range, then every quarter composited from its
-entering transmittance).
+split_entries entries get 8 wavefronts per 8x8 block, each over an eighth
+of the range (merged in order; parts inside which a pixel stops are walked
+again from their entering transmittance).
 
 Bars: images within 1e-4 of the FP64 oracle with last ids and contribution
 counts equal on unflagged pixels; against the unsplit raster within 1e-5
@@ -64,11 +64,11 @@ def test_split_matches_oracle_and_unsplit(case):
     out = rs.rasterize(s, i, bs, counts=True, trans=True)
     out0 = r0.rasterize(s, i, b0, counts=True, trans=True)
     torch.cuda.synchronize()
-    ns = int(to_np(bs.tile_order)[-1])
+    ns, ns2 = (int(v) for v in to_np(bs.tile_order)[-2:])
     offs = to_np(bs.offsets).view(np.uint32).astype(np.int64)
     tiles = rs.tiles
     counts = offs[64::64][:tiles] - offs[0:tiles * 64:64]
-    assert ns == int((counts >= split).sum()) > 0
+    assert ns == int((counts >= split).sum()) > 0 and ns2 == int((counts >= split // 2).sum()) > ns
     e_rgb, e_a, nflag = image_compare(to_np(out["rgb"]), to_np(out["alpha"]), ref)
     assert e_rgb <= TOL and e_a <= TOL, (e_rgb, e_a, nflag)
     m = ref["flags"] == 0
