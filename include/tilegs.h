@@ -171,9 +171,10 @@ typedef struct {
     float shift_gamma;    /* gamma in [0, 1), 0.25 */
     int32_t split_entries; /* 0, or a power of two in 256..2^24 (4096): with
                              the WAVE raster, 16-pixel tiles, packed = 0 and
-                             a tile order, the (at most 1024) tiles with at
-                             least this many entries get 8 wavefronts per
-                             8x8 block, each over an eighth of the range
+                             a tile order, the tiles with at least this many
+                             entries (the threshold raised by powers of two
+                             to at most 1024 tiles) get 8 wavefronts per 8x8
+                             block, each over an eighth of the range
                              (merged in order, parts where a pixel stops
                              walked again from their entering transmittance);
                              images equal the unsplit ones up to rounding
@@ -197,9 +198,11 @@ typedef struct {
    tile_order [T + 2] (optional, NULL = none): tgs_bin writes the tiles in
        descending order of their entry count (grouped by the bit length of
        the count) and the WAVE raster dispatches tiles in that order, so the
-       longest tiles start first; tile_order[T] and [T + 1] = the numbers of
-       tiles with at least params.split_entries and split_entries / 2 entries
-       (the first ones of the order).
+       longest tiles start first; tile_order[T] = the number of tiles the
+       raster splits (the first ones of the order): those with at least
+       tile_order[T + 1] entries, the smallest power of two >=
+       params.split_entries that leaves at most 1024 of them (0 and 0 when
+       split_entries is 0).
    seg_base [T + 1] (required with params.per_tile_bins_dev, else unused):
        tgs_bin writes the first segment of each tile, seg_base[T] = the
        number of segments S; offsets then holds S + 1 meaningful words (size

@@ -339,81 +339,89 @@ __device__ __forceinline__ uint64_t group_bitonic(uint64_t v, int li) {
     return v;
 }
 
-// Segments of 2..64 keys: 64 / G segments per wavefront, G lanes each.
+// Segments of 2..64 keys: 64 / G segments per wavefront job, G lanes each
+// (job i: segments i * 64 / G + lane / G of the bucket list).
 template <int G>
-__device__ __forceinline__ void sort_groups(const uint32_t* __restrict__ bin_off, const uint32_t* __restrict__ list,
-                                            uint32_t cnt, int wid, int waves, uint64_t* __restrict__ pairs,
-                                            const RecordSink& rs) {
+__device__ __forceinline__ void sort_group_job(const uint32_t* __restrict__ bin_off, const uint32_t* __restrict__ list,
+                                               uint32_t cnt, uint32_t job, uint64_t* __restrict__ pairs,
+                                               const RecordSink& rs) {
     constexpr int SPW = kWave / G;
     const int l = lane(), gi = l / G, li = l % G;
-    for (uint32_t i0 = (uint32_t)wid * SPW; i0 < cnt; i0 += (uint32_t)waves * SPW) {
-        const uint32_t i = i0 + gi;
-        uint32_t s = 0, begin = 0, len = 0;
-        if (i < cnt) {
-            s = list[i];
-            begin = bin_off[s];
-            len = bin_off[s + 1] - begin;
-        }
-        uint64_t v = (uint32_t)li < len ? pairs[begin + li] : ~0ull;
-        v = group_bitonic<G>(v, li);
-        if ((uint32_t)li < len) {
-            pairs[begin + li] = v;
-            rs.put(s, begin + li, v);
-        }
+    const uint32_t i = job * SPW + gi;
+    uint32_t s = 0, begin = 0, len = 0;
+    if (i < cnt) {
+        s = list[i];
+        begin = bin_off[s];
+        len = bin_off[s + 1] - begin;
+    }
+    uint64_t v = (uint32_t)li < len ? pairs[begin + li] : ~0ull;
+    v = group_bitonic<G>(v, li);
+    if ((uint32_t)li < len) {
+        pairs[begin + li] = v;
+        rs.put(s, begin + li, v);
     }
 }
 
 // Segments of 65..512 keys: one wavefront, bitonic network in its own LDS
 // region (no workgroup barriers; LDS operations of a wavefront complete in
 // order).
-__device__ __forceinline__ void sort_wave_lds(const uint32_t* __restrict__ bin_off, const uint32_t* __restrict__ list,
-                                              uint32_t cnt, int wid, int waves, uint64_t* __restrict__ pairs,
-                                              uint64_t* buf, const RecordSink& rs) {
+__device__ __forceinline__ void sort_wave_lds_job(const uint32_t* __restrict__ bin_off, uint32_t s,
+                                                  uint64_t* __restrict__ pairs, uint64_t* buf, const RecordSink& rs) {
     const int l = lane();
-    for (uint32_t i = (uint32_t)wid; i < cnt; i += (uint32_t)waves) {
-        const uint32_t s = list[i];
-        const uint32_t begin = bin_off[s], len = bin_off[s + 1] - begin;
-        uint32_t P = 1;
-        while (P < len) P <<= 1;
-        for (uint32_t e = l; e < P; e += kWave) buf[e] = e < len ? pairs[begin + e] : ~0ull;
-        wave_sync();
-        for (uint32_t k = 2; k <= P; k <<= 1) {
-            for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-                for (uint32_t t = l; t < P / 2; t += kWave) {
-                    const uint32_t lo = (t / j) * 2 * j + (t % j), hi = lo + j;
-                    const uint64_t a = buf[lo], b = buf[hi];
-                    const bool up = (lo & k) == 0;
-                    if ((a > b) == up) {
-                        buf[lo] = b;
-                        buf[hi] = a;
-                    }
+    const uint32_t begin = bin_off[s], len = bin_off[s + 1] - begin;
+    uint32_t P = 1;
+    while (P < len) P <<= 1;
+    for (uint32_t e = l; e < P; e += kWave) buf[e] = e < len ? pairs[begin + e] : ~0ull;
+    wave_sync();
+    for (uint32_t k = 2; k <= P; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t t = l; t < P / 2; t += kWave) {
+                const uint32_t lo = (t / j) * 2 * j + (t % j), hi = lo + j;
+                const uint64_t a = buf[lo], b = buf[hi];
+                const bool up = (lo & k) == 0;
+                if ((a > b) == up) {
+                    buf[lo] = b;
+                    buf[hi] = a;
                 }
-                wave_sync();
             }
+            wave_sync();
         }
-        for (uint32_t e = l; e < len; e += kWave) {
-            const uint64_t v = buf[e];
-            pairs[begin + e] = v;
-            rs.put(s, begin + e, v);
-        }
-        wave_sync();
     }
+    for (uint32_t e = l; e < len; e += kWave) {
+        const uint64_t v = buf[e];
+        pairs[begin + e] = v;
+        rs.put(s, begin + e, v);
+    }
+    wave_sync();
 }
 
-// Buckets 0..4 in one launch: every wavefront walks every bucket with a
-// static stride (no shared work counter).
+// Buckets 0..4 in one launch. The wavefront jobs of all five buckets form
+// one list, longest first (bucket 4: one 65..512 segment per job; buckets
+// 3..0: 1, 2, 4, 8 segments per job), which every wavefront strides through,
+// so that no wavefront gets a job of every bucket.
 __global__ void __launch_bounds__(256) sort_small_kernel(const uint32_t* __restrict__ bin_off,
                                                          const uint32_t* __restrict__ lists, int64_t nseg,
                                                          const uint32_t* __restrict__ bucket_count,
                                                          uint64_t* __restrict__ pairs, RecordSink rs) {
     __shared__ uint64_t buf[4][512];
-    const int waves = gridDim.x * (blockDim.x / kWave);
-    const int wid = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-    sort_groups<8>(bin_off, lists + 0 * nseg, bucket_count[0], wid, waves, pairs, rs);
-    sort_groups<16>(bin_off, lists + 1 * nseg, bucket_count[1], wid, waves, pairs, rs);
-    sort_groups<32>(bin_off, lists + 2 * nseg, bucket_count[2], wid, waves, pairs, rs);
-    sort_groups<64>(bin_off, lists + 3 * nseg, bucket_count[3], wid, waves, pairs, rs);
-    sort_wave_lds(bin_off, lists + 4 * nseg, bucket_count[4], wid, waves, pairs, buf[threadIdx.x / kWave], rs);
+    const uint32_t waves = gridDim.x * (blockDim.x / kWave);
+    const uint32_t wid = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    const uint32_t c0 = bucket_count[0], c1 = bucket_count[1], c2 = bucket_count[2], c3 = bucket_count[3],
+                   c4 = bucket_count[4];
+    // job counts and their running sums, bucket 4 first
+    const uint32_t j4 = c4, j3 = j4 + c3, j2 = j3 + (c2 + 1) / 2, j1 = j2 + (c1 + 3) / 4, j0 = j1 + (c0 + 7) / 8;
+    for (uint32_t j = wid; j < j0; j += waves) {
+        if (j < j4)
+            sort_wave_lds_job(bin_off, lists[4 * nseg + j], pairs, buf[threadIdx.x / kWave], rs);
+        else if (j < j3)
+            sort_group_job<64>(bin_off, lists + 3 * nseg, c3, j - j4, pairs, rs);
+        else if (j < j2)
+            sort_group_job<32>(bin_off, lists + 2 * nseg, c2, j - j3, pairs, rs);
+        else if (j < j1)
+            sort_group_job<16>(bin_off, lists + 1 * nseg, c1, j - j2, pairs, rs);
+        else
+            sort_group_job<8>(bin_off, lists + 0 * nseg, c0, j - j1, pairs, rs);
+    }
 }
 
 // Buckets 5..7: one workgroup per segment. 513..8192 keys: bitonic network
@@ -567,16 +575,24 @@ __global__ void __launch_bounds__(256) tile_place_kernel(const uint32_t* __restr
     __syncthreads();
     if (act) order[base[b] + slot] = (uint32_t)t;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        // counts >= split = 2^h have a bit length > h: buckets 0 .. 31 - h;
-        // order[T + 1] also counts those >= split / 2
-        uint32_t nh = 0, nh2 = 0;
+        // counts >= 2^h have a bit length > h: buckets 0 .. 31 - h. The
+        // threshold is the smallest power of two >= split that leaves at
+        // most kSplitTiles tiles above it, so the split set is a union of
+        // whole buckets (independent of the order inside a bucket).
+        uint32_t nh = 0, thr = 0;
         if (split > 0) {
-            const int last = 31 - (31 - __builtin_clz((uint32_t)split));
-            for (int k = 0; k <= last; ++k) nh += hist[k];
-            nh2 = nh + hist[last + 1];
+            for (int h = 31 - __builtin_clz((uint32_t)split); h <= 31; ++h) {
+                uint32_t c = 0;
+                for (int k = 0; k <= 31 - h; ++k) c += hist[k];
+                if (c <= (uint32_t)kSplitTiles) {
+                    nh = c;
+                    thr = 1u << h;
+                    break;
+                }
+            }
         }
         order[T] = nh;
-        order[T + 1] = nh2;
+        order[T + 1] = thr;
     }
 }
 

@@ -335,10 +335,11 @@ hipError_t launch_repair(const uint32_t* bin_off, int64_t nseg, uint64_t* pairs,
                          const uint32_t* bucket_count, RecordSink rs, hipStream_t s);
 
 // Tiles in descending order of their entry count (coarse: by bit length of
-// the count), so the heaviest tiles are dispatched first; order[T] and
-// order[T + 1] = the numbers of tiles with at least `split` and split / 2
-// entries (split a power of two; 0: none), which come first. hist [66] must
-// be zero.
+// the count), so the heaviest tiles are dispatched first. order[T] = the
+// number of tiles the WAVE raster splits: those with at least order[T + 1]
+// entries, the smallest power of two >= `split` (0: none) that leaves at
+// most kSplitTiles of them; they come first. hist [66] must be zero.
+constexpr int kSplitTiles = 1024;
 hipError_t launch_tile_order(const uint32_t* offsets, SegMap sm, int64_t T, uint32_t* hist, uint32_t* order, int split,
                              hipStream_t s);
 

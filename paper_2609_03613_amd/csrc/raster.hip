@@ -105,9 +105,9 @@ __global__ void __launch_bounds__(256) raster_wave_kernel(RasterArgs A) {
 // Heavy-tile split (16-pixel tiles, heaviest-first dispatch order). A pixel
 // is composited sequentially over its tile's whole range, so the
 // wavefronts of the few longest tiles decide when the WAVE raster ends.
-// Workgroups of 8 wavefronts take, in this order: the first NA =
-// min(order[T], kSplitTiles) tiles of the order (at least A.split entries)
-// one 8x8 block each, with 8 parts of the range; all other tiles two per
+// Workgroups of 8 wavefronts take, in this order: the first NA = order[T]
+// tiles of the order (those with at least order[T + 1] >= A.split entries,
+// at most kSplitTiles) one 8x8 block each, with 8 parts of the range; all other tiles two per
 // workgroup, one wavefront per block, as in the WAVE raster. (Giving the
 // tiles of half that size 4 parts per block was measured no faster.) Part 0 of a block composites as usual; parts 1..
 // composite every supported entry from a local transmittance of 1, giving
@@ -120,7 +120,6 @@ __global__ void __launch_bounds__(256) raster_wave_kernel(RasterArgs A) {
 // from T_in with the stop test. The part-0 wavefront adds the colours and
 // takes T and the last id of the last live part. Images equal the unsplit
 // ones up to the rounding of the regrouped products.
-constexpr int kSplitTiles = 1024;
 constexpr int kSplitWaves = 8;
 
 struct PixLds {

@@ -16,7 +16,7 @@ namespace tgs {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kRounds = 16;
+constexpr int kRounds = 8;
 constexpr int kPerBlock = kThreads * kRounds;
 constexpr uint64_t kFlagAgg = 1ull << 62;
 constexpr uint64_t kFlagInc = 2ull << 62;
