@@ -172,14 +172,18 @@ typedef struct {
     int32_t split_entries; /* 0, or a power of two in 256..2^24 (4096): with
                              the WAVE raster, 16-pixel tiles, packed = 0 and
                              a tile order, the tiles with at least this many
-                             entries (the threshold raised by powers of two
-                             to at most 1024 tiles) get 8 wavefronts per 8x8
-                             block, each over an eighth of the range
+                             entries and split_mean_factor x the mean of the
+                             non-empty tiles (the threshold raised by powers
+                             of two to at most 1024 tiles) get 8 wavefronts
+                             per 8x8 block, each over an eighth of the range
                              (merged in order, parts where a pixel stops
                              walked again from their entering transmittance);
                              images equal the unsplit ones up to rounding
                              (<= 1e-6), last ids and counts except at that
                              rounding */
+    int32_t split_mean_factor; /* 0..64 (4); 0: the threshold is split_entries
+                             alone. Where every tile is long, pixels stop
+                             early and a split part's walk is mostly wasted */
 } tgs_params;
 
 /* Entry buffers written by tgs_bin and read by tgs_rasterize. All device
@@ -201,8 +205,9 @@ typedef struct {
        longest tiles start first; tile_order[T] = the number of tiles the
        raster splits (the first ones of the order): those with at least
        tile_order[T + 1] entries, the smallest power of two >=
-       params.split_entries that leaves at most 1024 of them (0 and 0 when
-       split_entries is 0).
+       params.split_entries and >= params.split_mean_factor x the mean
+       entries of the non-empty tiles that leaves at most 1024 of them (0
+       and 0 when split_entries is 0).
    seg_base [T + 1] (required with params.per_tile_bins_dev, else unused):
        tgs_bin writes the first segment of each tile, seg_base[T] = the
        number of segments S; offsets then holds S + 1 meaningful words (size

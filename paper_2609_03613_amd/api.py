@@ -43,13 +43,15 @@ class Params:
     near_shift: bool = False  # bin on z - min(alpha s_max, gamma z) instead of z
     shift_alpha: float = 1.0
     shift_gamma: float = 0.25
-    split_entries: int = 4096  # tiles with this many entries are split over 4 wavefronts per block (0: never)
+    split_entries: int = 4096  # tiles with this many entries are split over 8 wavefronts per block (0: never)
+    split_mean_factor: int = 4  # ... and with this many times the mean of the non-empty tiles (0: no such bound)
 
     def c(self):
         return L.Params(self.tile_size, self.num_bins, self.sample_count, self.p_lo, self.p_hi, self.pad,
                         RASTERS[self.raster], int(self.packed), _ptr(self.per_tile_bins).value,
                         REPAIRS[self.repair], float(self.repair_budget), int(bool(self.near_shift)),
-                        float(self.shift_alpha), float(self.shift_gamma), int(self.split_entries))
+                        float(self.shift_alpha), float(self.shift_gamma), int(self.split_entries),
+                        int(self.split_mean_factor))
 
 
 def paper_params(**kw):

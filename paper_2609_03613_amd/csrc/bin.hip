@@ -558,7 +558,7 @@ __global__ void __launch_bounds__(256) tile_hist_kernel(const uint32_t* __restri
 
 __global__ void __launch_bounds__(256) tile_place_kernel(const uint32_t* __restrict__ offsets, SegMap sm, int64_t T,
                                                          const uint32_t* __restrict__ hist, uint32_t* __restrict__ cursor,
-                                                         uint32_t* __restrict__ order, int split) {
+                                                         uint32_t* __restrict__ order, int split, int factor) {
     __shared__ uint32_t h[kOrderBuckets], base[kOrderBuckets];
     if (threadIdx.x < kOrderBuckets) h[threadIdx.x] = 0;
     __syncthreads();
@@ -576,12 +576,21 @@ __global__ void __launch_bounds__(256) tile_place_kernel(const uint32_t* __restr
     if (act) order[base[b] + slot] = (uint32_t)t;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         // counts >= 2^h have a bit length > h: buckets 0 .. 31 - h. The
-        // threshold is the smallest power of two >= split that leaves at
-        // most kSplitTiles tiles above it, so the split set is a union of
-        // whole buckets (independent of the order inside a bucket).
+        // threshold is the smallest power of two >= split and >= `factor`
+        // times the mean count of the non-empty tiles (only tiles far longer
+        // than the typical walk are on the critical path; where all tiles
+        // are long, pixels tend to stop early and a split part's walk is
+        // mostly wasted) that leaves at most kSplitTiles tiles above it, so
+        // the split set is a union of whole buckets (independent of the
+        // order inside a bucket).
         uint32_t nh = 0, thr = 0;
         if (split > 0) {
-            for (int h = 31 - __builtin_clz((uint32_t)split); h <= 31; ++h) {
+            const uint64_t m = offsets[sm.first(T)];
+            const uint64_t nonempty = (uint64_t)T - hist[32];
+            const uint64_t rel = nonempty ? (uint64_t)factor * m / nonempty : 0;
+            int h0 = 31 - __builtin_clz((uint32_t)split);
+            while (h0 < 31 && ((uint64_t)1 << h0) < rel) ++h0;
+            for (int h = h0; h <= 31; ++h) {
                 uint32_t c = 0;
                 for (int k = 0; k <= 31 - h; ++k) c += hist[k];
                 if (c <= (uint32_t)kSplitTiles) {
@@ -683,11 +692,11 @@ hipError_t launch_repair(const uint32_t* bin_off, int64_t nseg, uint64_t* pairs,
 }
 
 hipError_t launch_tile_order(const uint32_t* offsets, SegMap sm, int64_t T, uint32_t* hist, uint32_t* order, int split,
-                             hipStream_t s) {
+                             int factor, hipStream_t s) {
     if (T == 0) return hipSuccess;
     hipLaunchKernelGGL(tile_hist_kernel, dim3(grid_for(T, 256)), dim3(256), 0, s, offsets, sm, T, hist);
     hipLaunchKernelGGL(tile_place_kernel, dim3(grid_for(T, 256)), dim3(256), 0, s, offsets, sm, T, hist,
-                       hist + kOrderBuckets, order, split);
+                       hist + kOrderBuckets, order, split, factor);
     return hipGetLastError();
 }
 

@@ -84,6 +84,8 @@ tgs_status check_params(const tgs_params* p) {
     if (p->split_entries != 0 &&
         (p->split_entries < 256 || p->split_entries > (1 << 24) || (p->split_entries & (p->split_entries - 1))))
         return fail(TGS_ERR_INVALID_ARG, "split_entries %d: 0 or a power of two in 256..2^24", p->split_entries);
+    if (p->split_mean_factor < 0 || p->split_mean_factor > 64)
+        return fail(TGS_ERR_INVALID_ARG, "split_mean_factor %d outside 0..64", p->split_mean_factor);
     if (!(p->shift_alpha >= 0.f) || !isfinite(p->shift_alpha))
         return fail(TGS_ERR_INVALID_ARG, "shift_alpha must be finite and >= 0");
     if (!(p->shift_gamma >= 0.f && p->shift_gamma < 1.f))
@@ -204,6 +206,7 @@ void tgs_default_params(tgs_params* p) {
     p->shift_alpha = 1.0f;
     p->shift_gamma = 0.25f;
     p->split_entries = 4096;
+    p->split_mean_factor = 4;
 }
 
 const char* tgs_last_error(void) { return g_err.c_str(); }
@@ -297,7 +300,7 @@ tgs_status tgs_bin(const tgs_projected* pr, const tgs_camera* cam, const tgs_par
         TGS_HIP(launch_tile_ranges(out->keys_dev, M, T, out->offsets_dev, s), "tile ranges");
         if (out->tile_order_dev)
             TGS_HIP(launch_tile_order(out->offsets_dev, SegMap{nullptr, 1, nullptr}, T, zero + kTileHist,
-                                      out->tile_order_dev, params->split_entries, s),
+                                      out->tile_order_dev, params->split_entries, params->split_mean_factor, s),
                     "tile order");
         return TGS_OK;
     }
@@ -343,7 +346,7 @@ tgs_status tgs_bin(const tgs_projected* pr, const tgs_camera* cam, const tgs_par
         TGS_HIP(launch_repair(out->offsets_dev, nseg, out->pairs_dev, seg_lists, bucket_count, rs, s), "repair");
     if (out->tile_order_dev)
         TGS_HIP(launch_tile_order(out->offsets_dev, sm, T, zero + kTileHist, out->tile_order_dev,
-                                  params->split_entries, s),
+                                  params->split_entries, params->split_mean_factor, s),
                 "tile order");
     return TGS_OK;
 }

@@ -337,11 +337,12 @@ hipError_t launch_repair(const uint32_t* bin_off, int64_t nseg, uint64_t* pairs,
 // Tiles in descending order of their entry count (coarse: by bit length of
 // the count), so the heaviest tiles are dispatched first. order[T] = the
 // number of tiles the WAVE raster splits: those with at least order[T + 1]
-// entries, the smallest power of two >= `split` (0: none) that leaves at
-// most kSplitTiles of them; they come first. hist [66] must be zero.
+// entries, the smallest power of two >= `split` (0: none) and >= factor x
+// the mean count of the non-empty tiles that leaves at most kSplitTiles of
+// them; they come first. hist [66] must be zero.
 constexpr int kSplitTiles = 1024;
 hipError_t launch_tile_order(const uint32_t* offsets, SegMap sm, int64_t T, uint32_t* hist, uint32_t* order, int split,
-                             hipStream_t s);
+                             int factor, hipStream_t s);
 
 hipError_t launch_emit_keys(const uint32_t* info, int64_t n, const uint32_t* emit_off, int tiles_x, int tiles_y,
                             uint64_t* keys, uint32_t* vals, int64_t capacity, hipStream_t s);

@@ -175,8 +175,23 @@ __global__ void __launch_bounds__(kSplitWaves * kWave) raster_split_kernel(Raste
     const uint32_t qa = begin + (uint32_t)(len * (uint64_t)part / parts);
     const uint32_t qb = begin + (uint32_t)(len * (uint64_t)(part + 1) / parts);
     // part 0 composites exactly; parts 1.. composite every supported entry
-    // from a local transmittance of 1
-    if (valid) wave_forward<SRC, COUNT>(A, stage[w], bi, qa, qb, ox, oy, px, py, xa, xb, ya, yb, p, part > 0);
+    // from a local transmittance of 1. After every chunk a part publishes
+    // its running local transmittance (0 once part 0's pixel has stopped)
+    // and drops the pixels whose earlier parts' running product is already
+    // below 1e-4: the final product can only be smaller, so those pixels
+    // stop before this part. Reading a stale value only delays the drop.
+    tloc[w][l] = 1.0f;
+    __syncthreads();
+    auto progress = [&](Pix& q) {
+        tloc[w][l] = (part == 0 && q.done) ? 0.0f : q.T;
+        if (part > 0) {
+            float prod = 1.0f;
+            for (int j = 0; j < part; ++j) prod *= tloc[w0 + j][l];
+            q.done = q.done || prod < kTMin;
+        }
+    };
+    if (valid)
+        wave_forward<SRC, COUNT>(A, stage[w], bi, qa, qb, ox, oy, px, py, xa, xb, ya, yb, p, part > 0, progress);
     // (a pixel that stopped inside part 0 publishes 0: every later part is dead)
     tloc[w][l] = (part == 0 && p.done) ? 0.0f : p.T;
     __syncthreads();

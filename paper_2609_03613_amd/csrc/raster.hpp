@@ -182,10 +182,16 @@ __device__ __forceinline__ void composite_staged(Pix& p, float px, float py, con
 // slots st[] and composited by every lane. Without masks the gathers are
 // software-pipelined: while chunk i is culled and composited, the splats of
 // chunk i + 1 and the ids of chunk i + 2 are in flight.
-template <int SRC, bool COUNT>
+struct NoHook {
+    __device__ __forceinline__ void operator()(Pix&) const {}
+};
+
+// hook(p) runs after every chunk (a split part publishes its progress and
+// drops pixels that stopped in an earlier part).
+template <int SRC, bool COUNT, class Hook = NoHook>
 __device__ __forceinline__ void wave_forward(const RasterArgs& A, Staged* st, int bi, uint32_t begin, uint32_t end,
                                              float ox, float oy, float px, float py, float xa, float xb, float ya,
-                                             float yb, Pix& p, bool nostop = false) {
+                                             float yb, Pix& p, bool nostop = false, Hook hook = Hook()) {
     const int l = lane();
     if (A.masks) {
         const uint32_t bit = 1u << bi;  // block masks exist for 16-pixel tiles only (bi < 4)
@@ -198,11 +204,13 @@ __device__ __forceinline__ void wave_forward(const RasterArgs& A, Staged* st, in
             if (keep) keep = (A.masks[e] & bit) != 0;
             if (keep) s = load_entry<SRC>(A, e, ox, oy);
             const uint64_t m = ballot(keep);
-            if (m == 0) continue;
-            if (keep) st[rank_in(m)] = s;
-            wave_sync();
-            composite_staged<COUNT>(p, px, py, st, __builtin_popcountll(m), nostop);
-            wave_sync();
+            if (m != 0) {
+                if (keep) st[rank_in(m)] = s;
+                wave_sync();
+                composite_staged<COUNT>(p, px, py, st, __builtin_popcountll(m), nostop);
+                wave_sync();
+            }
+            hook(p);
         }
         return;
     }
@@ -235,11 +243,13 @@ __device__ __forceinline__ void wave_forward(const RasterArgs& A, Staged* st, in
             keep = block_may_touch(s.a.x, s.a.y, c1.x, c1.y, c1.z, c1.w, xa, xb, ya, yb);
         }
         const uint64_t m = ballot(keep);
-        if (m == 0) return;
-        if (keep) st[rank_in(m)] = s;
-        wave_sync();
-        composite_staged<COUNT>(p, px, py, st, __builtin_popcountll(m), nostop);
-        wave_sync();
+        if (m != 0) {
+            if (keep) st[rank_in(m)] = s;
+            wave_sync();
+            composite_staged<COUNT>(p, px, py, st, __builtin_popcountll(m), nostop);
+            wave_sync();
+        }
+        hook(p);
     };
     float4 a0, a1, a2, b0, b1, b2;
     uint32_t ga = id_clamped(begin + l), gb;

@@ -120,27 +120,40 @@ __global__ void __launch_bounds__(256) raster_bwd_kernel(RasterArgs A, const flo
     const float gaT = ga * Tf;
     float T = Tf;
     float Sr = Tf * A.bg[0], Sg = Tf * A.bg[1], Sb = Tf * A.bg[2];
-    for (int64_t top = hi; top >= (int64_t)begin; top -= kWave) {
+    // Chunks of 64 entries downwards from hi; lane l holds entry top - l. The
+    // gathers are software-pipelined as in the forward walk: while chunk i
+    // is processed, the splats of chunk i + 1 are in flight and the ids of
+    // chunk i + 2 follow once chunk i's ids are staged. Every lane issues
+    // every load (lanes below the range read its first entry and are
+    // dropped by the range test).
+    const float4* sp = reinterpret_cast<const float4*>(A.splats);
+    auto id_clamped = [&](int64_t e) { return id_at<SRC>(A, (uint32_t)(e >= (int64_t)begin ? e : (int64_t)begin)); };
+    auto gather = [&](uint32_t g, float4& r0, float4& r1, float4& r2) {
+        const float4* q = sp + kSplatVec * (int64_t)g;
+        r0 = q[0];
+        r1 = q[1];
+        r2 = q[2];
+    };
+    auto chunk = [&](int64_t top, const float4& q0, const float4& q1, const float4& q2, uint32_t& gcur,
+                     uint32_t g_next, float4& n0, float4& n1, float4& n2) {
         const int64_t e = top - l;
         bool keep = e >= (int64_t)begin;
+        gather(g_next, n0, n1, n2);
         Staged s;
-        uint32_t gid = 0;
         if (keep) {
-            gid = id_at<SRC>(A, (uint32_t)e);
-            const float4* q = reinterpret_cast<const float4*>(A.splats) + kSplatVec * (int64_t)gid;
-            const float4 q0 = q[0], q1 = q[1], q2 = q[2];
             float s2;
             stage_splat(q0, q1, q2, ox, oy, s.a, s.b, s2);
             s.c = make_float2(s2, __int_as_float((int32_t)e));
             keep = block_may_touch(s.a.x, s.a.y, q1.x, q1.y, q1.z, q1.w, xa, xb, ya, yb);
         }
         const uint64_t m = ballot(keep);
-        if (m == 0) continue;
         if (keep) {
             const uint32_t r = rank_in(m);
             st[r] = s;
-            idw[r] = gid;
+            idw[r] = gcur;
         }
+        gcur = id_clamped(e - 2 * kWave);  // this set's next chunk (i + 2)
+        if (m == 0) return;
         wave_sync();
         const int cnt = __builtin_popcountll(m);
         for (int j = 0; j < cnt; ++j) {
@@ -190,6 +203,18 @@ __global__ void __launch_bounds__(256) raster_bwd_kernel(RasterArgs A, const flo
             if (l < 9) unsafeAtomicAdd(d_splats + kGradWords * (int64_t)idw[j] + l, mine);
         }
         wave_sync();
+    };
+    float4 a0, a1, a2, b0, b1, b2;
+    uint32_t ida = id_clamped((int64_t)hi - l), idb;
+    gather(ida, a0, a1, a2);
+    idb = id_clamped((int64_t)hi - kWave - l);
+    for (int64_t top = hi;;) {
+        if (top < (int64_t)begin) break;
+        chunk(top, a0, a1, a2, ida, idb, b0, b1, b2);
+        top -= kWave;
+        if (top < (int64_t)begin) break;
+        chunk(top, b0, b1, b2, idb, ida, a0, a1, a2);
+        top -= kWave;
     }
 }
 

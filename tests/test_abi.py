@@ -185,7 +185,7 @@ def test_repair_mode_argument_errors():
     lib.tgs_default_params(ctypes.byref(p))
     assert (p.repair, p.near_shift) == (L.REPAIR_ALL, 0)
     assert abs(p.repair_budget - 0.25) < 1e-7 and p.shift_alpha == 1.0 and p.shift_gamma == 0.25
-    assert p.split_entries == 4096
+    assert p.split_entries == 4096 and p.split_mean_factor == 4
     cases = [(tg.Params(repair="rules", packed=1), L.TGS_ERR_UNSUPPORTED, "packed"),
              (tg.Params(repair="none", packed=2), L.TGS_ERR_UNSUPPORTED, "packed"),
              (tg.Params(repair="rules", repair_budget=1.5), L.TGS_ERR_INVALID_ARG, "repair_budget"),
@@ -194,7 +194,8 @@ def test_repair_mode_argument_errors():
              (tg.Params(near_shift=True, shift_alpha=-1.0), L.TGS_ERR_INVALID_ARG, "shift_alpha"),
              (tg.Params(near_shift=True, shift_alpha=float("inf")), L.TGS_ERR_INVALID_ARG, "shift_alpha"),
              (tg.Params(split_entries=1000), L.TGS_ERR_INVALID_ARG, "split_entries"),
-             (tg.Params(split_entries=128), L.TGS_ERR_INVALID_ARG, "split_entries")]
+             (tg.Params(split_entries=128), L.TGS_ERR_INVALID_ARG, "split_entries"),
+             (tg.Params(split_mean_factor=-1), L.TGS_ERR_INVALID_ARG, "split_mean_factor")]
     for bad, code, word in cases:
         st, msg = status_of(lib.tgs_project, ctypes.byref(g), ctypes.byref(cam()), ctypes.byref(bad.c()),
                             ctypes.byref(out), None)

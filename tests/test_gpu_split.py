@@ -1,7 +1,9 @@
 """Heavy-tile split of the WAVE raster: the tiles with at least
 split_entries entries get 8 wavefronts per 8x8 block, each over an eighth
 of the range (merged in order; parts inside which a pixel stops are walked
-again from their entering transmittance).
+again from their entering transmittance). The scenes here are uniformly
+dense, so the bound relative to the mean tile (split_mean_factor) is
+turned off to force the split; the default bound is checked on its own.
 
 Bars: images within 1e-4 of the FP64 oracle with last ids and contribution
 counts equal on unflagged pixels; against the unsplit raster within 1e-5
@@ -56,7 +58,7 @@ def test_split_matches_oracle_and_unsplit(case):
     proj = oracle.project(g, cam)
     ref = oracle.render(proj, W, H)
     gd = tg.to_device(g, dev())
-    rs = tg.Renderer(cam, tg.Params(split_entries=split), device=dev())
+    rs = tg.Renderer(cam, tg.Params(split_entries=split, split_mean_factor=0), device=dev())
     r0 = tg.Renderer(cam, tg.Params(split_entries=0), device=dev())
     s, i = tg.project(gd, cam)
     bs = rs.bin(s, i, "binned")
@@ -95,9 +97,9 @@ def test_split_global_order_and_no_order():
     gd = tg.to_device(g, dev())
     s, i = tg.project(gd, cam)
     imgs = {}
-    for name, prm, order in [("binned", tg.Params(split_entries=256), "binned"),
-                             ("global", tg.Params(split_entries=256), "global"),
-                             ("no order", tg.Params(split_entries=256, tile_order=False), "binned"),
+    for name, prm, order in [("binned", tg.Params(split_entries=256, split_mean_factor=0), "binned"),
+                             ("global", tg.Params(split_entries=256, split_mean_factor=0), "global"),
+                             ("no order", tg.Params(split_entries=256, split_mean_factor=0, tile_order=False), "binned"),
                              ("unsplit", tg.Params(split_entries=0), "binned")]:
         r = tg.Renderer(cam, prm, device=dev())
         out = r.rasterize(s, i, r.bin(s, i, order))
@@ -113,7 +115,7 @@ def test_split_global_order_and_no_order():
 def test_split_overflow_writes_nan():
     g, cam = dense(5, 4000, 1.5)
     gd = tg.to_device(g, dev())
-    r = tg.Renderer(cam, tg.Params(split_entries=256), device=dev())
+    r = tg.Renderer(cam, tg.Params(split_entries=256, split_mean_factor=0), device=dev())
     s, i = tg.project(gd, cam)
     full = r.bin(s, i, "binned", sync=True)
     M = full.num_entries
@@ -132,7 +134,7 @@ def test_split_cap_is_deterministic():
     # the order inside a count bucket, so repeated frames are bitwise equal
     g, cam = scenes.training_scene(seed=6, n=300000, width=1297, height=840)
     gd = tg.to_device(g, dev())
-    r = tg.Renderer(cam, tg.Params(split_entries=256), device=dev())
+    r = tg.Renderer(cam, tg.Params(split_entries=256, split_mean_factor=0), device=dev())
     r0 = tg.Renderer(cam, tg.Params(split_entries=0), device=dev())
     s, i = tg.project(gd, cam)
     outs = []
@@ -152,3 +154,23 @@ def test_split_cap_is_deterministic():
     torch.cuda.synchronize()
     assert float((outs[0]["rgb"] - u["rgb"]).abs().max()) <= 1e-5
     assert torch.equal(outs[0]["last"], u["last"])
+
+
+def test_split_relative_bound():
+    # with the default factor (4 x the mean entries of the non-empty tiles)
+    # a uniformly dense scene splits nothing, and the raster is the unsplit one
+    g, cam = dense(2, 3000, 2.0)
+    gd = tg.to_device(g, dev())
+    r = tg.Renderer(cam, tg.Params(split_entries=256), device=dev())
+    r0 = tg.Renderer(cam, tg.Params(split_entries=0), device=dev())
+    s, i = tg.project(gd, cam)
+    b = r.bin(s, i, "binned")
+    out = r.rasterize(s, i, b)
+    u = r0.rasterize(s, i, r0.bin(s, i, "binned"))
+    torch.cuda.synchronize()
+    ns, thr = (int(v) for v in to_np(b.tile_order)[-2:])
+    offs = to_np(b.offsets).view(np.uint32).astype(np.int64)
+    counts = offs[64::64][:r.tiles] - offs[0:r.tiles * 64:64]
+    mean = counts.sum() / max(int((counts > 0).sum()), 1)
+    assert thr >= 4 * mean and thr & (thr - 1) == 0 and ns == int((counts >= thr).sum())
+    assert torch.equal(out["rgb"], u["rgb"]) == (ns == 0)
