@@ -45,7 +45,7 @@ def profiled_traffic():
     the raster sources changed since the counters were taken."""
     import hashlib
     import re
-    path = os.path.join(ROOT, "profiles", "raster_wave_1080p.md")
+    path = os.path.join(ROOT, "profiles", "raster_1080p.md")
     if not os.path.exists(path):
         return None
     h = hashlib.sha256()
@@ -705,7 +705,7 @@ def main():
         "bin_stage_ms_by_variant": bin_ms,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_LANE_OPS, "unit": "lane-op/s",
                      "frac": achieved / PEAK_LANE_OPS, "traffic": profiled_traffic(),
-                     "kernel": "raster_wave_kernel (binned, gather by id, per-block cull)",
+                     "kernel": "raster_split_kernel (binned, gather by id, per-block cull, longest tiles split)",
                      "work": f"{n_support} alpha-supported pixel tests x {OPS_PER_TEST} lane-op slots"},
     }
     if not args.no_repair:
