@@ -69,7 +69,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--mode", default="frame", choices=["frame", "kernels", "train", "batch", "learned", "repair",
-                                                      "scale"],
+                                                      "scale", "stress"],
                     help="kernels: only launch the product and comparator raster kernels and a "
                          "256 MiB device copy (for profiler counter runs); train: only the training "
                          "step (forward + backward) on the 500k-Gaussian 1297x840 scene")
@@ -475,6 +475,82 @@ def scale_up(args):
                         "1920x1080, f=1100" % ",".join(map(str, sizes)), "rows": rows}
 
 
+def _stage_times(tg, r, gd, cam, order, steps, stream):
+    """Median project / ordering / raster / frame ms of `steps` frames."""
+    import torch
+    s, i = tg.project(gd, cam, r.params)
+    b = r.bin(s, i, order, sync=True)
+    out = r.rasterize(s, i, b)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+    for k in range(steps + 2):
+        e = ev[k - 2] if k >= 2 else None
+        if e: e[0].record(stream)
+        tg.project(gd, cam, r.params, out=(s, i))
+        if e: e[1].record(stream)
+        b2 = r.bin(s, i, order, sync=(order == "global"))
+        if e: e[2].record(stream)
+        r.rasterize(s, i, b2, out=out)
+        if e: e[3].record(stream)
+    torch.cuda.synchronize()
+    a = np.array([[e[j].elapsed_time(e[j + 1]) for j in range(3)] + [e[0].elapsed_time(e[3])] for e in ev])
+    med = np.median(a, 0).tolist()
+    return {"project": med[0], "order": med[1], "raster": med[2], "frame": med[3]}, b, out
+
+
+def stress(args):
+    """Depth-distribution stress (sparse, dense slab in a wide range,
+    bimodal; 1920x1080) and a resolution sweep of the 1080p scene (640x360
+    .. 3840x2160, focal length scaled with the width): binned against
+    globally sorted frames (project, ordering, raster, whole frame), the
+    entry and segment statistics, whether the paper's repair budget is
+    active (kept entries above 25 % of M) and whether the images agree."""
+    import torch
+    import paper_2609_03613_amd as tg
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    steps = max(min(args.steps, 10), 5)
+
+    def compare(g, cam):
+        gd = tg.to_device(g, dev)
+        rb = tg.Renderer(cam, tg.Params(), device=dev)
+        rg = tg.Renderer(cam, tg.Params(raster="plain", tile_order=False), device=dev)
+        tb, bb, ob = _stage_times(tg, rb, gd, cam, "binned", steps, stream)
+        M = bb.num_entries if bb.num_entries is not None else int(bb.counters[0].item())
+        bb = rb.bin(*tg.project(gd, cam), "binned", sync=True)
+        lens = torch.diff(bb.offsets[: rb.tiles * 64 + 1].long())
+        tgl, bg, og = _stage_times(tg, rg, gd, cam, "global", steps, stream)
+        rp = tg.Renderer(cam, tg.paper_params(repair_budget=1.0), device=dev)
+        sp, ip = tg.project(gd, cam)
+        kept = int(rp.bin(sp, ip, "binned", sync=True).counters[3].item())
+        r0 = tg.Renderer(cam, tg.Params(split_entries=0), device=dev)
+        o0 = r0.rasterize(sp, ip, r0.bin(sp, ip, "binned", sync=True))
+        torch.cuda.synchronize()
+        row = {"entries": M, "binned_ms": tb, "global_ms": tgl,
+               "raster_x": tgl["raster"] / tb["raster"], "order_x": tgl["order"] / tb["order"],
+               "frame_x": tgl["frame"] / tb["frame"], "longest_segment": int(lens.max().item()),
+               "entries_in_segments_over_64": float(lens[lens > 64].sum().item()) / max(M, 1),
+               "paper_kept_frac": kept / max(M, 1), "paper_budget_active": kept > 0.25 * M,
+               "split_tiles": int(bb.tile_order[-2].item()),
+               "unsplit_equals_global": bool(torch.equal(o0["rgb"], og["rgb"])),
+               "split_max_abs_diff": float((ob["rgb"] - o0["rgb"]).abs().max().item())}
+        del gd
+        torch.cuda.empty_cache()
+        return row
+
+    out = {"depth": {}, "resolution": {}}
+    for kind in scenes.STRESS_KINDS:
+        g, cam = scenes.depth_stress_scene(kind, seed=0)
+        out["depth"][kind] = compare(g, cam)
+        print(f"stress: {kind} done", file=sys.stderr, flush=True)
+    g1, _ = scenes.scene_1080p(seed=0)
+    for W, H in ((640, 360), (1280, 720), (1920, 1080), (2560, 1440), (3840, 2160)):
+        f = 1100.0 * W / 1920.0
+        cam = scenes.camera(np.eye(3), np.array([0.0, 0.0, 15.0]), f, f, W / 2.0, H / 2.0, W, H)
+        out["resolution"][f"{W}x{H}"] = compare(g1, cam)
+        print(f"stress: {W}x{H} done", file=sys.stderr, flush=True)
+    return out
+
+
 def workload(name):
     if name == "1080p":
         g, cam = scenes.scene_1080p(seed=0)
@@ -521,6 +597,9 @@ def main():
         return
     if args.mode == "learned":
         print(json.dumps({"mode": "learned", **learned_bins(args)}), flush=True)
+        return
+    if args.mode == "stress":
+        print(json.dumps({"mode": "stress", **stress(args)}), flush=True)
         return
     if args.mode == "scale":
         print(json.dumps({"mode": "scale", **scale_up(args)}), flush=True)

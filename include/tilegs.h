@@ -206,8 +206,9 @@ typedef struct {
        raster splits (the first ones of the order): those with at least
        tile_order[T + 1] entries, the smallest power of two >=
        params.split_entries and >= params.split_mean_factor x the mean
-       entries of the non-empty tiles that leaves at most 1024 of them (0
-       and 0 when split_entries is 0).
+       entries of the non-empty tiles (this bound only when the non-empty
+       tiles have at least 8192 blocks, enough wavefronts to fill the GPU)
+       that leaves at most 1024 of them (0 and 0 when split_entries is 0).
    seg_base [T + 1] (required with params.per_tile_bins_dev, else unused):
        tgs_bin writes the first segment of each tile, seg_base[T] = the
        number of segments S; offsets then holds S + 1 meaningful words (size

@@ -587,7 +587,10 @@ __global__ void __launch_bounds__(256) tile_place_kernel(const uint32_t* __restr
         if (split > 0) {
             const uint64_t m = offsets[sm.first(T)];
             const uint64_t nonempty = (uint64_t)T - hist[32];
-            const uint64_t rel = nonempty ? (uint64_t)factor * m / nonempty : 0;
+            // with fewer block wavefronts than the CUs hold (256 x 32), the
+            // split parts run on otherwise idle SIMDs: no bound from the mean
+            const bool filled = 4 * nonempty >= (uint64_t)kFillWaves;
+            const uint64_t rel = nonempty && filled ? (uint64_t)factor * m / nonempty : 0;
             int h0 = 31 - __builtin_clz((uint32_t)split);
             while (h0 < 31 && ((uint64_t)1 << h0) < rel) ++h0;
             for (int h = h0; h <= 31; ++h) {

@@ -338,9 +338,11 @@ hipError_t launch_repair(const uint32_t* bin_off, int64_t nseg, uint64_t* pairs,
 // the count), so the heaviest tiles are dispatched first. order[T] = the
 // number of tiles the WAVE raster splits: those with at least order[T + 1]
 // entries, the smallest power of two >= `split` (0: none) and >= factor x
-// the mean count of the non-empty tiles that leaves at most kSplitTiles of
-// them; they come first. hist [66] must be zero.
+// the mean count of the non-empty tiles (when their 4 block wavefronts each
+// would fill the CUs) that leaves at most kSplitTiles of them; they come
+// first. hist [66] must be zero.
 constexpr int kSplitTiles = 1024;
+constexpr int kFillWaves = 256 * 32;  // wavefronts the 256 CUs hold at 8 per SIMD
 hipError_t launch_tile_order(const uint32_t* offsets, SegMap sm, int64_t T, uint32_t* hist, uint32_t* order, int split,
                              int factor, hipStream_t s);
 

@@ -231,6 +231,53 @@ def learned_train_scenes(first_seed=1000, count=50, small_n=2000, surface_n=200_
     return out
 
 
+STRESS_KINDS = ("sparse", "dense", "bimodal")
+
+
+def depth_stress_scene(kind, n=None, seed=0, width=1920, height=1080, focal=1100.0, sh_degree=3):
+    """Synthetic depth-distribution stress scenes (identity camera at the
+    origin looking down +z; means spread uniformly over the image, 5 % beyond
+    its edges; log-scales N(-4.5, 0.5) + ln(z / 10), so that the screen size
+    does not depend on the depth; logits N(0, 2); SH coefficients N(0, 0.2)).
+
+    sparse:  n = 100k, depth log-uniform in [2, 200] (few entries per
+             tile, spread over the whole bin range);
+    dense:   n = 1M, 96 % at depth U[10, 10.05], 2 % log-uniform in [2, 10]
+             and 2 % in [10.05, 200] (a thin slab inside a wide depth range:
+             one or two bins hold nearly every entry of a tile, long
+             segments);
+    bimodal: n = 1M, half at depth U[3, 3.2] and half at U[40, 42] (two
+             slabs, the bins between them empty).
+    Draw order: depths, image positions, log-scales, quaternions, logits, SH.
+    """
+    defaults = {"sparse": 100_000, "dense": 1_000_000, "bimodal": 1_000_000}
+    if kind not in defaults:
+        raise ValueError(f"unknown stress kind {kind!r}")
+    n = defaults[kind] if n is None else int(n)
+    rng = np.random.default_rng(seed)
+    if kind == "sparse":
+        z = np.exp(rng.uniform(np.log(2.0), np.log(200.0), size=n))
+    elif kind == "dense":
+        r = rng.random(n)
+        z = np.where(r < 0.96, rng.uniform(10.0, 10.05, size=n),
+                     np.where(r < 0.98, np.exp(rng.uniform(np.log(2.0), np.log(10.0), size=n)),
+                              np.exp(rng.uniform(np.log(10.05), np.log(200.0), size=n))))
+    else:
+        near = rng.random(n) < 0.5
+        z = np.where(near, rng.uniform(3.0, 3.2, size=n), rng.uniform(40.0, 42.0, size=n))
+    u = rng.uniform(-0.05 * width, 1.05 * width, size=n)
+    v = rng.uniform(-0.05 * height, 1.05 * height, size=n)
+    means = np.stack([(u - width / 2.0) * z / focal, (v - height / 2.0) * z / focal, z], axis=1)
+    log_scales = rng.normal(-4.5, 0.5, size=(n, 3)) + np.log(z / 10.0)[:, None]
+    quats = _unit_quats(rng, n)
+    logits = rng.normal(0.0, 2.0, size=n)
+    k = (sh_degree + 1) ** 2
+    sh = rng.normal(0.0, 0.2, size=(n, k, 3))
+    g = _pack(means, log_scales, quats, logits, sh, sh_degree)
+    cam = camera(np.eye(3), np.zeros(3), focal, focal, width / 2.0, height / 2.0, width, height)
+    return g, cam
+
+
 def subset(g, idx):
     """Gaussians ``idx`` of scene ``g`` (keeps the degree)."""
     out = {k: np.ascontiguousarray(v[idx]) for k, v in g.items() if k != "sh_degree"}

@@ -158,19 +158,30 @@ def test_split_cap_is_deterministic():
 
 def test_split_relative_bound():
     # with the default factor (4 x the mean entries of the non-empty tiles)
-    # a uniformly dense scene splits nothing, and the raster is the unsplit one
-    g, cam = dense(2, 3000, 2.0)
-    gd = tg.to_device(g, dev())
-    r = tg.Renderer(cam, tg.Params(split_entries=256), device=dev())
-    r0 = tg.Renderer(cam, tg.Params(split_entries=0), device=dev())
-    s, i = tg.project(gd, cam)
-    b = r.bin(s, i, "binned")
-    out = r.rasterize(s, i, b)
-    u = r0.rasterize(s, i, r0.bin(s, i, "binned"))
-    torch.cuda.synchronize()
-    ns, thr = (int(v) for v in to_np(b.tile_order)[-2:])
-    offs = to_np(b.offsets).view(np.uint32).astype(np.int64)
-    counts = offs[64::64][:r.tiles] - offs[0:r.tiles * 64:64]
-    mean = counts.sum() / max(int((counts > 0).sum()), 1)
-    assert thr >= 4 * mean and thr & (thr - 1) == 0 and ns == int((counts >= thr).sum())
-    assert torch.equal(out["rgb"], u["rgb"]) == (ns == 0)
+    # a uniformly dense scene with enough tiles to fill the GPU splits only
+    # tiles far above the mean; with too few tiles to fill it, the bound
+    # from the mean is skipped
+    cases = [(scenes.training_scene(seed=7, n=300000, width=1297, height=840), True),
+             (dense(2, 3000, 2.0), False)]
+    for (g, cam), filled in cases:
+        gd = tg.to_device(g, dev())
+        r = tg.Renderer(cam, tg.Params(split_entries=256), device=dev())
+        r0 = tg.Renderer(cam, tg.Params(split_entries=0), device=dev())
+        s, i = tg.project(gd, cam)
+        b = r.bin(s, i, "binned")
+        out = r.rasterize(s, i, b)
+        u = r0.rasterize(s, i, r0.bin(s, i, "binned"))
+        torch.cuda.synchronize()
+        ns, thr = (int(v) for v in to_np(b.tile_order)[-2:])
+        offs = to_np(b.offsets).view(np.uint32).astype(np.int64)
+        counts = offs[64::64][:r.tiles] - offs[0:r.tiles * 64:64]
+        nonempty = int((counts > 0).sum())
+        mean = counts.sum() / max(nonempty, 1)
+        assert (4 * nonempty >= 8192) == filled
+        assert thr & (thr - 1) == 0 and ns == int((counts >= thr).sum()) <= 1024
+        if filled:
+            assert thr >= 4 * mean
+        else:
+            assert thr == 256 and ns > 0
+        assert float((out["rgb"] - u["rgb"]).abs().max()) <= 1e-5
+        assert torch.equal(out["last"], u["last"])
