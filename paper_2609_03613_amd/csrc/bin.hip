@@ -4,9 +4,16 @@
 //   depth_range  robust [zmin, zmax] from exact order statistics of the
 //                sampled depths (supplement, Algorithm "Robust depth-range
 //                estimation"), one workgroup, LDS radix select;
-//   bin_count    log-depth bin of each Gaussian and an atomic count per
-//                (tile, bin); the returned old count is the entry's rank in
-//                its segment (Algorithm "Tile-local bin construction");
+//   grouped      (uniform K) the count / scan / scatter of Algorithm
+//                "Tile-local bin construction" in two levels: entries are
+//                counted and scattered per group of consecutive tiles with
+//                LDS counters and one global atomic per (workgroup, group),
+//                then each group is counting-sorted by (tile, bin) in LDS;
+//                per-entry global atomics on scattered counters run at
+//                ~25 G/s on this GPU and would dominate the stage;
+//   bin_count    (per-tile K, or group shapes out of range) log-depth bin of
+//                each Gaussian and an atomic count per (tile, bin); the
+//                returned old count is the entry's rank in its segment;
 //   bin_scatter  pair = depth bits << 32 | id written at bin offset + rank;
 //   repair       every (tile, bin) segment with two or more entries is sorted
 //                by its unique 64-bit pair, routed by length to a wavefront
@@ -194,12 +201,6 @@ struct WaveGauss {
     uint32_t bin[kWave];
 };
 
-// Load-balanced expansion of the (Gaussian, tile) entries of a wavefront's
-// 64 consecutive Gaussians: the entries are enumerated 64 at a time, one per
-// lane, and each lane finds its Gaussian by binary search over the
-// wavefront's exclusive entry counts. Entries of consecutive Gaussians are
-// consecutive in the global entry order, so entry e = emit_off[first] + k.
-// f(gid, tile_x, tile_y, e, depth_bits, bin) is called once per entry.
 // Position of depth bits L in the depth range as a 32-bit fraction,
 // floor(2^32 (L - Lmin) / (Lmax - Lmin)), clamped to [0, 2^32 - 1]. For K =
 // 2^k bins, frac >> (32 - k) equals bin_of(L, Lmin, Lmax, K) exactly (floor
@@ -221,13 +222,28 @@ __device__ __forceinline__ int64_t segment_of(const SegMap& sm, int64_t t, uint3
     return (int64_t)ts.x + (int64_t)((uint64_t)bv >> ts.y);
 }
 
-template <bool WITH_BIN, bool VAR, class F>
-__device__ __forceinline__ void for_wave_entries(const uint4* __restrict__ info, int64_t n,
-                                                 const uint32_t* __restrict__ emit_off, int tiles_x, int tiles_y,
-                                                 const float* __restrict__ zrange, const NearKey& nk, int K,
-                                                 WaveGauss* W, F&& f) {
+// One (Gaussian, tile) entry of a wavefront's expansion; ok = false for the
+// lanes past the wavefront's last entry.
+struct Ent {
+    int64_t gid, e;
+    int tx, ty;
+    uint32_t key, bin;
+    bool ok;
+};
+
+// Load-balanced expansion of the (Gaussian, tile) entries of a wavefront's
+// 64 consecutive Gaussians: the entries are enumerated 64 at a time, one per
+// lane, and each lane finds its Gaussian by binary search over the
+// wavefront's exclusive entry counts. Entries of consecutive Gaussians are
+// consecutive in the global entry order, so entry e = emit_off[first] + k.
+// f(en) receives R rounds (R x 64 entries) at once, so that it can issue the
+// memory operations of all R rounds before waiting for any of them.
+template <int R, bool WITH_BIN, bool VAR, class F>
+__device__ __forceinline__ void for_wave_entries_at(int64_t g0, const uint4* __restrict__ info, int64_t n,
+                                                    const uint32_t* __restrict__ emit_off, int tiles_x, int tiles_y,
+                                                    const float* __restrict__ zrange, const NearKey& nk, int K,
+                                                    WaveGauss* W, F&& f) {
     const int l = lane();
-    const int64_t g0 = ((int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~(kWave - 1)));
     if (g0 >= n) return;
     const int64_t g = g0 + l;
     int cnt = 0, x0 = 0, y0 = 0, x1 = 0, y1 = 0;
@@ -251,19 +267,51 @@ __device__ __forceinline__ void for_wave_entries(const uint4* __restrict__ info,
     }
     const int64_t ebase = emit_off[g0];
     wave_sync();
-    for (uint32_t base = 0; base < total; base += kWave) {
-        const uint32_t k = base + (uint32_t)l;
-        if (k < total) {
-            int lo = 0;
+    for (uint32_t base = 0; base < total; base += R * kWave) {
+        Ent en[R];
+        int lo[R];
 #pragma unroll
-            for (int step = kWave / 2; step > 0; step >>= 1)
-                if (W->excl[lo + step] <= k) lo += step;
-            const uint32_t j = k - W->excl[lo], w = W->width[lo], r = W->rect[lo];
-            const int tx = (int)(r & 0xFFFFu) + (int)(j % w), ty = (int)(r >> 16) + (int)(j / w);
-            f(g0 + lo, tx, ty, ebase + k, W->key[lo], WITH_BIN ? W->bin[lo] : 0u);
+        for (int r = 0; r < R; ++r) {
+            const uint32_t k = base + (uint32_t)(r * kWave + l);
+            en[r].ok = k < total;
+            en[r].e = ebase + k;
+            lo[r] = 0;
         }
+        // the R searches are independent; interleaved, their LDS reads overlap
+#pragma unroll
+        for (int step = kWave / 2; step > 0; step >>= 1)
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const uint32_t k = base + (uint32_t)(r * kWave + l);
+                if (W->excl[lo[r] + step] <= k) lo[r] += step;
+            }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t k = base + (uint32_t)(r * kWave + l);
+            const uint32_t j = k - W->excl[lo[r]], w = W->width[lo[r]], rc = W->rect[lo[r]];
+            // lanes past the end hold lo = 63 with a width that may be 0
+            const uint32_t ws = w ? w : 1u;
+            en[r].tx = (int)(rc & 0xFFFFu) + (int)(j % ws);
+            en[r].ty = (int)(rc >> 16) + (int)(j / ws);
+            en[r].gid = g0 + lo[r];
+            en[r].key = W->key[lo[r]];
+            en[r].bin = WITH_BIN ? W->bin[lo[r]] : 0u;
+        }
+        f(en);
     }
 }
+
+// The wavefront's 64 Gaussians of a one-Gaussian-per-thread grid.
+template <int R, bool WITH_BIN, bool VAR, class F>
+__device__ __forceinline__ void for_wave_entries(const uint4* __restrict__ info, int64_t n,
+                                                 const uint32_t* __restrict__ emit_off, int tiles_x, int tiles_y,
+                                                 const float* __restrict__ zrange, const NearKey& nk, int K,
+                                                 WaveGauss* W, F&& f) {
+    const int64_t g0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~(kWave - 1));
+    for_wave_entries_at<R, WITH_BIN, VAR>(g0, info, n, emit_off, tiles_x, tiles_y, zrange, nk, K, W, f);
+}
+
+constexpr int kExpandRounds = 4;
 
 // Atomic count per (tile, bin) into the calling XCD's copy of the counts.
 // All atomics on copy x come from XCD x, so they are carried out in that
@@ -280,13 +328,25 @@ __global__ void __launch_bounds__(256) bin_count_kernel(const uint4* __restrict_
     const uint32_t x = (uint32_t)xcc_id() % (uint32_t)kCopies;
     const int64_t S = VAR ? (int64_t)sm.seg_base[(int64_t)tiles_x * tiles_y] : nseg;
     uint32_t* cnt = count + (int64_t)x * S;
-    for_wave_entries<true, VAR>(info, n, emit_off, tiles_x, tiles_y, zrange, nk, sm.K, &wg[threadIdx.x / kWave],
-                                [&](int64_t, int tx, int ty, int64_t e, uint32_t, uint32_t b) {
-                                    const int64_t sg = segment_of<VAR>(sm, (int64_t)ty * tiles_x + tx, b);
-                                    const uint32_t r = __hip_atomic_fetch_add(&cnt[sg], 1u, __ATOMIC_RELAXED,
+    constexpr int R = kExpandRounds;
+    for_wave_entries<R, true, VAR>(info, n, emit_off, tiles_x, tiles_y, zrange, nk, sm.K, &wg[threadIdx.x / kWave],
+                                   [&](const Ent (&en)[R]) {
+                                       uint32_t rk[R];
+#pragma unroll
+                                       for (int r = 0; r < R; ++r) {
+                                           rk[r] = 0;
+                                           if (en[r].ok) {
+                                               const int64_t sg =
+                                                   segment_of<VAR>(sm, (int64_t)en[r].ty * tiles_x + en[r].tx, en[r].bin);
+                                               rk[r] = __hip_atomic_fetch_add(&cnt[sg], 1u, __ATOMIC_RELAXED,
                                                                               __HIP_MEMORY_SCOPE_WORKGROUP);
-                                    if (e < capacity) entry_rank[e] = (r & 0x1FFFFFFFu) | (x << 29);
-                                });
+                                           }
+                                       }
+#pragma unroll
+                                       for (int r = 0; r < R; ++r)
+                                           if (en[r].ok && en[r].e < capacity)
+                                               entry_rank[en[r].e] = (rk[r] & 0x1FFFFFFFu) | (x << 29);
+                                   });
 }
 
 // pair = depth bits << 32 | id at base[copy][segment] + rank. An entry that
@@ -304,18 +364,119 @@ __global__ void __launch_bounds__(256) bin_scatter_kernel(const uint4* __restric
                                                           RecordSink rs) {
     __shared__ WaveGauss wg[4];
     const int64_t S = VAR ? (int64_t)sm.seg_base[(int64_t)tiles_x * tiles_y] : nseg;
-    for_wave_entries<true, VAR>(info, n, emit_off, tiles_x, tiles_y, zrange, nk, sm.K, &wg[threadIdx.x / kWave],
-                                [&](int64_t gid, int tx, int ty, int64_t e, uint32_t key, uint32_t b) {
-                                    if (e >= capacity) return;
-                                    const uint32_t rk = entry_rank[e];
-                                    const int64_t sg = segment_of<VAR>(sm, (int64_t)ty * tiles_x + tx, b);
-                                    const int64_t p = (int64_t)base[(int64_t)(rk >> 29) * S + sg] + (rk & 0x1FFFFFFFu);
-                                    if (p >= capacity) return;
-                                    const uint64_t pair = ((uint64_t)key << 32) | (uint64_t)gid;
-                                    pairs[p] = pair;
-                                    if (rs.masks && bin_off[sg + 1] - bin_off[sg] == 1)
-                                        rs.put((uint32_t)sg, (uint32_t)p, pair);
-                                });
+    constexpr int R = kExpandRounds;
+    for_wave_entries<R, true, VAR>(info, n, emit_off, tiles_x, tiles_y, zrange, nk, sm.K, &wg[threadIdx.x / kWave],
+                                   [&](const Ent (&en)[R]) {
+                                       bool ok[R];
+                                       uint32_t rk[R];
+#pragma unroll
+                                       for (int r = 0; r < R; ++r) {
+                                           ok[r] = en[r].ok && en[r].e < capacity;
+                                           rk[r] = ok[r] ? entry_rank[en[r].e] : 0u;
+                                       }
+                                       int64_t sg[R];
+                                       uint32_t bs[R];
+#pragma unroll
+                                       for (int r = 0; r < R; ++r) {
+                                           sg[r] = ok[r] ? segment_of<VAR>(sm, (int64_t)en[r].ty * tiles_x + en[r].tx,
+                                                                           en[r].bin)
+                                                         : 0;
+                                           bs[r] = ok[r] ? base[(int64_t)(rk[r] >> 29) * S + sg[r]] : 0u;
+                                       }
+#pragma unroll
+                                       for (int r = 0; r < R; ++r) {
+                                           const int64_t p = (int64_t)bs[r] + (rk[r] & 0x1FFFFFFFu);
+                                           if (!ok[r] || p >= capacity) continue;
+                                           const uint64_t pair = ((uint64_t)en[r].key << 32) | (uint64_t)en[r].gid;
+                                           pairs[p] = pair;
+                                           if (rs.masks && bin_off[sg[r] + 1] - bin_off[sg[r]] == 1)
+                                               rs.put((uint32_t)sg[r], (uint32_t)p, pair);
+                                       }
+                                   });
+}
+
+// ---------------------------------------------------------------------------
+// grouped binning (uniform K): the same count / scan / scatter, done in two
+// levels so that no per-entry global atomic is needed. Groups are runs of
+// GT consecutive tiles, i.e. contiguous ranges of GS = GT K segments.
+//   group_count    each workgroup expands the entries of kGroupChunk
+//                  Gaussians, counts them per group in LDS and reserves its
+//                  slice of every group it touches with one global atomic
+//                  per (workgroup, group): wgbase[wg][g];
+//   group_scan     exclusive prefix of the group totals;
+//   group_scatter  the same workgroups expand their entries again and write
+//                  (pair, segment within the group) at group offset + slice
+//                  base + an LDS rank;
+//   group_sort     one workgroup per group: LDS counting sort of its entries
+//                  by segment, bin offsets, repair queues.
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256) group_count_kernel(const uint4* __restrict__ info, int64_t n,
+                                                          const uint32_t* __restrict__ emit_off,
+                                                          const float* __restrict__ zrange, NearKey nk, GroupMap gm,
+                                                          int tiles_x, int tiles_y, uint32_t* __restrict__ gcount,
+                                                          uint32_t* __restrict__ wgbase) {
+    __shared__ WaveGauss wg[4];
+    __shared__ uint32_t hist[kMaxGroups];
+    for (int g = threadIdx.x; g < gm.G; g += 256) hist[g] = 0;
+    __syncthreads();
+    const int w = threadIdx.x / kWave;
+    const int64_t first = (int64_t)blockIdx.x * kGroupChunk;
+    constexpr int R = kExpandRounds;
+    for (int it = 0; it < kGroupChunk / 256; ++it) {
+        const int64_t g0 = first + (int64_t)(it * 4 + w) * kWave;
+        for_wave_entries_at<R, false, false>(g0, info, n, emit_off, tiles_x, tiles_y, zrange, nk, gm.K, &wg[w],
+                                             [&](const Ent (&en)[R]) {
+#pragma unroll
+                                                 for (int r = 0; r < R; ++r)
+                                                     if (en[r].ok)
+                                                         atomicAdd(&hist[(uint32_t)(en[r].ty * tiles_x + en[r].tx) /
+                                                                         (uint32_t)gm.GT],
+                                                                   1u);
+                                             });
+    }
+    __syncthreads();
+    uint32_t* row = wgbase + (int64_t)blockIdx.x * gm.G;
+    for (int g = threadIdx.x; g < gm.G; g += 256) {
+        const uint32_t h = hist[g];
+        if (h) row[g] = atomicAdd(&gcount[g], h);
+    }
+}
+
+__global__ void __launch_bounds__(256) group_scatter_kernel(const uint4* __restrict__ info, int64_t n,
+                                                            const uint32_t* __restrict__ emit_off,
+                                                            const float* __restrict__ zrange, NearKey nk, GroupMap gm,
+                                                            int tiles_x, int tiles_y,
+                                                            const uint32_t* __restrict__ group_off,
+                                                            const uint32_t* __restrict__ wgbase,
+                                                            uint64_t* __restrict__ tmp_pair,
+                                                            uint16_t* __restrict__ tmp_code, int64_t capacity) {
+    __shared__ WaveGauss wg[4];
+    __shared__ uint32_t cursor[kMaxGroups];
+    const uint32_t* row = wgbase + (int64_t)blockIdx.x * gm.G;
+    // slots of groups this workgroup does not touch hold stale values and
+    // are never used
+    for (int g = threadIdx.x; g < gm.G; g += 256) cursor[g] = group_off[g] + row[g];
+    __syncthreads();
+    const int w = threadIdx.x / kWave;
+    const int64_t first = (int64_t)blockIdx.x * kGroupChunk;
+    constexpr int R = kExpandRounds;
+    for (int it = 0; it < kGroupChunk / 256; ++it) {
+        const int64_t g0 = first + (int64_t)(it * 4 + w) * kWave;
+        for_wave_entries_at<R, true, false>(
+            g0, info, n, emit_off, tiles_x, tiles_y, zrange, nk, gm.K, &wg[w], [&](const Ent (&en)[R]) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    if (!en[r].ok) continue;
+                    const uint32_t t = (uint32_t)(en[r].ty * tiles_x + en[r].tx);
+                    const uint32_t grp = t / (uint32_t)gm.GT;
+                    const uint32_t pos = atomicAdd(&cursor[grp], 1u);
+                    if (pos >= capacity) continue;
+                    tmp_pair[pos] = ((uint64_t)en[r].key << 32) | (uint64_t)en[r].gid;
+                    tmp_code[pos] = (uint16_t)((t - grp * (uint32_t)gm.GT) * (uint32_t)gm.K + en[r].bin);
+                }
+            });
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -617,13 +778,17 @@ __global__ void __launch_bounds__(256) emit_keys_kernel(const uint4* __restrict_
                                                         int tiles_y, uint64_t* __restrict__ keys,
                                                         uint32_t* __restrict__ vals, int64_t capacity) {
     __shared__ WaveGauss wg[4];
-    for_wave_entries<false, false>(info, n, emit_off, tiles_x, tiles_y, nullptr, NearKey{}, 1,
-                                   &wg[threadIdx.x / kWave],
-                            [&](int64_t gid, int tx, int ty, int64_t e, uint32_t key, uint32_t) {
-                                if (e >= capacity) return;
-                                keys[e] = ((uint64_t)(ty * tiles_x + tx) << 32) | key;
-                                vals[e] = (uint32_t)gid;
-                            });
+    constexpr int R = kExpandRounds;
+    for_wave_entries<R, false, false>(info, n, emit_off, tiles_x, tiles_y, nullptr, NearKey{}, 1,
+                                      &wg[threadIdx.x / kWave], [&](const Ent (&en)[R]) {
+#pragma unroll
+                                          for (int r = 0; r < R; ++r) {
+                                              if (!en[r].ok || en[r].e >= capacity) continue;
+                                              keys[en[r].e] = ((uint64_t)(en[r].ty * tiles_x + en[r].tx) << 32) |
+                                                              en[r].key;
+                                              vals[en[r].e] = (uint32_t)en[r].gid;
+                                          }
+                                      });
 }
 
 // tile_off[t] = first position whose tile is >= t (t = 0..T).
@@ -700,6 +865,39 @@ hipError_t launch_tile_order(const uint32_t* offsets, SegMap sm, int64_t T, uint
     hipLaunchKernelGGL(tile_hist_kernel, dim3(grid_for(T, 256)), dim3(256), 0, s, offsets, sm, T, hist);
     hipLaunchKernelGGL(tile_place_kernel, dim3(grid_for(T, 256)), dim3(256), 0, s, offsets, sm, T, hist,
                        hist + kOrderBuckets, order, split, factor);
+    return hipGetLastError();
+}
+
+GroupMap group_map(int64_t T, int K) {
+    GroupMap gm{K, 1, 0, 0};
+    if (T <= 0 || K <= 0) return gm;
+    int64_t gt = K >= kGroupSegTarget ? 1 : kGroupSegTarget / K;
+    while ((T + gt - 1) / gt > kMaxGroups) gt *= 2;
+    if (gt * K > kMaxGroupSegs) return gm;
+    gm.GT = (int)gt;
+    gm.G = (int)((T + gt - 1) / gt);
+    gm.GS = (int)(gt * K);
+    return gm;
+}
+
+hipError_t launch_group_count(const uint32_t* info, int64_t n, const uint32_t* emit_off, GroupMap gm, int tiles_x,
+                              int tiles_y, uint32_t* gcount, uint32_t* wgbase, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const int64_t blocks = (n + kGroupChunk - 1) / kGroupChunk;
+    hipLaunchKernelGGL(group_count_kernel, dim3((unsigned)blocks), dim3(256), 0, s, reinterpret_cast<const uint4*>(info),
+                       n, emit_off, nullptr, NearKey{}, gm, tiles_x, tiles_y, gcount, wgbase);
+    return hipGetLastError();
+}
+
+hipError_t launch_group_scatter(const uint32_t* info, int64_t n, const uint32_t* emit_off, const float* zrange,
+                                NearKey nk, GroupMap gm, int tiles_x, int tiles_y, const uint32_t* group_off,
+                                const uint32_t* wgbase, uint64_t* tmp_pair, uint16_t* tmp_code, int64_t capacity,
+                                hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const int64_t blocks = (n + kGroupChunk - 1) / kGroupChunk;
+    hipLaunchKernelGGL(group_scatter_kernel, dim3((unsigned)blocks), dim3(256), 0, s,
+                       reinterpret_cast<const uint4*>(info), n, emit_off, zrange, nk, gm, tiles_x, tiles_y, group_off,
+                       wgbase, tmp_pair, tmp_code, capacity);
     return hipGetLastError();
 }
 

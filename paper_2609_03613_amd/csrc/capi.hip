@@ -105,7 +105,9 @@ inline size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 struct Layout {
     size_t emit_off, vis_ids, zero, zero_words, status_emit_x, status_emit_y, status_bins, status_segs, status_sel,
         count,
-        count_var, tile_seg, entry_rank, seg_lists, keys_in, vals_in, sort_tmp, sort_tmp_bytes, total;
+        count_var, tile_seg, entry_rank, seg_lists, keys_in, vals_in, sort_tmp, sort_tmp_bytes, gcount, group_off,
+        wgbase, tmp_pair, tmp_code, group_order, total;
+    GroupMap gm;  // gm.G > 0: grouped binning
 };
 
 // Control words at the start of the zeroed region (uint32 offsets).
@@ -126,13 +128,15 @@ int end_bit_for(int64_t T) {
 
 // Workspace: [emit offsets][visible ids][zeroed region: control words,
 // scan status words (with rule-based repair also those of the selection
-// scan), per-XCD counts (BINNED, uniform K)][entry ranks]
-// [repair lists][per-XCD counts (BINNED, per-tile bin counts)] (BINNED) or
-// [...][unsorted keys][unsorted ids][sort scratch] (GLOBAL). The zeroed
-// region is cleared by one fill at the start of each tgs_bin; with per-tile
-// bin counts only the first kCopies * S words of the counts are cleared, by a
-// fill sized on the device. K is the uniform bin count or the bound of the
-// per-tile counts.
+// scan), group totals (grouped binning)][repair lists] then, for BINNED
+// with uniform K, [group offsets][workgroup slice bases][grouped pairs]
+// [grouped segment codes][group order] (grouped binning) or [per-XCD counts in the zeroed
+// region][entry ranks] (group shape out of range), with per-tile bin counts
+// [entry ranks][per-XCD counts][tile segments]; GLOBAL: [unsorted keys]
+// [unsorted ids][sort scratch]. The zeroed region is cleared by one fill at
+// the start of each tgs_bin; with per-tile bin counts only the first
+// kCopies * S words of the counts are cleared, by a fill sized on the
+// device. K is the uniform bin count or the bound of the per-tile counts.
 Layout layout(int64_t n, int64_t capacity, int64_t T, int K, int order, bool var, bool rules) {
     Layout L{};
     size_t off = 0;
@@ -157,14 +161,28 @@ Layout layout(int64_t n, int64_t capacity, int64_t T, int K, int order, bool var
     z += var ? 2 * (size_t)scan_blocks(T) : 0;
     L.status_sel = z;
     z += rules ? 2 * nbb : 0;
-    if (order == TGS_ORDER_BINNED && !var) {
+    L.gm = order == TGS_ORDER_BINNED && !var ? group_map(T, K) : GroupMap{K, 1, 0, 0};
+    const bool grouped = L.gm.G > 0;
+    if (grouped) {
+        z = (z + 63) & ~(size_t)63;
+        L.gcount = z;
+        z += (size_t)L.gm.G;
+    } else if (order == TGS_ORDER_BINNED && !var) {
         z = (z + 63) & ~(size_t)63;
         L.count = z;
         z += (size_t)kCopies * (size_t)nseg;
     }
     L.zero_words = z;
     L.zero = take(sizeof(uint32_t) * z);
-    if (order == TGS_ORDER_BINNED) {
+    if (grouped) {
+        const size_t chunks = (size_t)((n + kGroupChunk - 1) / kGroupChunk);
+        L.seg_lists = take(sizeof(uint32_t) * (size_t)kBuckets * (size_t)nseg);
+        L.group_off = take(sizeof(uint32_t) * ((size_t)L.gm.G + 1));
+        L.group_order = take(sizeof(uint32_t) * (size_t)L.gm.G);
+        L.wgbase = take(sizeof(uint32_t) * (chunks > 0 ? chunks : 1) * (size_t)L.gm.G);
+        L.tmp_pair = take(sizeof(uint64_t) * (size_t)capacity);
+        L.tmp_code = take(sizeof(uint16_t) * (size_t)capacity);
+    } else if (order == TGS_ORDER_BINNED) {
         L.entry_rank = take(sizeof(uint32_t) * (size_t)capacity);
         L.seg_lists = take(sizeof(uint32_t) * (size_t)kBuckets * (size_t)nseg);
         if (var) {
@@ -327,6 +345,35 @@ tgs_status tgs_bin(const tgs_projected* pr, const tgs_camera* cam, const tgs_par
     TGS_HIP(launch_depth_range(pr->info_dev, vis_ids, out->counters_dev, nk, S, params->p_lo, params->p_hi,
                                params->pad, zn, zf, out->zrange_dev, s),
             "depth range");
+    if (L.gm.G > 0) {
+        uint32_t* gcount = zero + L.gcount;
+        uint32_t* group_off = (uint32_t*)(w + L.group_off);
+        uint32_t* wgbase = (uint32_t*)(w + L.wgbase);
+        uint64_t* tmp_pair = (uint64_t*)(w + L.tmp_pair);
+        uint16_t* tmp_code = (uint16_t*)(w + L.tmp_code);
+        uint32_t* group_order = (uint32_t*)(w + L.group_order);
+        TGS_HIP(launch_group_count(pr->info_dev, n, emit_off, L.gm, tiles_x, tiles_y, gcount, wgbase, s), "group count");
+        TGS_HIP(launch_group_scan(gcount, L.gm, group_off, group_order, s), "group scan");
+        TGS_HIP(launch_group_scatter(pr->info_dev, n, emit_off, out->zrange_dev, nk, L.gm, tiles_x, tiles_y, group_off,
+                                     wgbase, tmp_pair, tmp_code, cap, s),
+                "group scatter");
+        TGS_HIP(launch_group_sort(tmp_pair, tmp_code, group_off, group_order, L.gm, nseg, cap, out->pairs_dev, out->offsets_dev,
+                                  seg_lists, bucket_count, out->counters_dev, params->repair == TGS_REPAIR_ALL,
+                                  out->repaired_dev, rs, s),
+                "group sort");
+        if (rules)
+            TGS_HIP(launch_repair_select(out->offsets_dev, T, K, params->repair_budget, zero + kTicketSel,
+                                         (uint64_t*)(zero + L.status_sel), zero + kSelCtl, seg_lists, bucket_count,
+                                         out->counters_dev, out->repaired_dev, s),
+                    "repair selection");
+        if (params->repair != TGS_REPAIR_NONE)
+            TGS_HIP(launch_repair(out->offsets_dev, nseg, out->pairs_dev, seg_lists, bucket_count, rs, s), "repair");
+        if (out->tile_order_dev)
+            TGS_HIP(launch_tile_order(out->offsets_dev, sm, T, zero + kTileHist, out->tile_order_dev,
+                                      params->split_entries, params->split_mean_factor, s),
+                    "tile order");
+        return TGS_OK;
+    }
     TGS_HIP(launch_bin_count(pr->info_dev, n, emit_off, out->zrange_dev, nk, sm, tiles_x, tiles_y, count, nseg,
                              entry_rank, cap, s),
             "bin count");

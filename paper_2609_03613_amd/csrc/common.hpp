@@ -200,6 +200,23 @@ struct RecordSink {
 
 // Segment numbering of the BINNED stream: segment first(t) + b is bin b of
 // tile t. Uniform (seg_base == null): K bins per tile, first(t) = t K.
+// Grouped binning (uniform K): groups of GT consecutive tiles, G groups,
+// GS = GT K segments per group (group g holds segments g GS .. g GS + GS - 1).
+struct GroupMap {
+    int K, GT, G, GS;
+};
+#ifndef TGS_GROUP_SEGS
+#define TGS_GROUP_SEGS 512
+#endif
+constexpr int kGroupSegTarget = TGS_GROUP_SEGS;  // segments per group aimed at
+constexpr int kMaxGroups = 8192;      // LDS counters of one workgroup
+constexpr int kMaxGroupSegs = 4096;   // LDS counters of one group sort
+constexpr int kGroupChunk = 2048;     // Gaussians per workgroup of the group count / scatter
+// The grouped path's group shape for T tiles and K bins: GT = max(1,
+// kGroupSegTarget / K) tiles, doubled until G <= kMaxGroups; .G = 0 when GS would exceed
+// kMaxGroupSegs (then the per-entry atomic path is used).
+GroupMap group_map(int64_t T, int K);
+
 // Per-tile bin counts: seg_base [T + 1] is the exclusive prefix sum of the
 // counts (powers of two), first(t) = seg_base[t], and the number of
 // segments S = seg_base[T] is known on the device only.
@@ -318,6 +335,28 @@ hipError_t launch_bin_scatter(const uint32_t* info, int64_t n, const uint32_t* e
                               NearKey nk, SegMap sm, int tiles_x, int tiles_y, const uint32_t* bin_off,
                               const uint32_t* base, int64_t nseg, const uint32_t* entry_rank, uint64_t* pairs,
                               int64_t capacity, RecordSink rs, hipStream_t s);
+
+// Grouped binning, see GroupMap. group_count: gcount [G] must be zero;
+// wgbase [ceil(n / kGroupChunk) x G] receives each workgroup's slice base
+// in the groups it touches. group_scan: group_off [G + 1] = exclusive
+// prefix of gcount. group_scatter: tmp_pair / tmp_code [capacity] get every
+// entry (pair, segment within its group) grouped by group; positions past
+// the capacity are dropped; order [G] = the groups, longest first.
+// group_sort: pairs in (tile, bin) order, bin_off
+// [S + 1] (S = T K), repair queues and repaired[] as launch_bin_offsets,
+// single-entry segments' records; bucket_count must be zero.
+hipError_t launch_group_count(const uint32_t* info, int64_t n, const uint32_t* emit_off, GroupMap gm, int tiles_x,
+                              int tiles_y, uint32_t* gcount, uint32_t* wgbase, hipStream_t s);
+hipError_t launch_group_scan(const uint32_t* gcount, GroupMap gm, uint32_t* group_off, uint32_t* order,
+                             hipStream_t s);
+hipError_t launch_group_scatter(const uint32_t* info, int64_t n, const uint32_t* emit_off, const float* zrange,
+                                NearKey nk, GroupMap gm, int tiles_x, int tiles_y, const uint32_t* group_off,
+                                const uint32_t* wgbase, uint64_t* tmp_pair, uint16_t* tmp_code, int64_t capacity,
+                                hipStream_t s);
+hipError_t launch_group_sort(const uint64_t* tmp_pair, const uint16_t* tmp_code, const uint32_t* group_off,
+                             const uint32_t* order, GroupMap gm, int64_t nseg, int64_t capacity, uint64_t* pairs, uint32_t* bin_off,
+                             uint32_t* lists, uint32_t* bucket_count, int64_t* counters, bool queue_all,
+                             uint8_t* repaired, RecordSink rs, hipStream_t s);
 
 // Per-tile bin counts: seg_base[t] = exclusive prefix sum of the bin counts
 // (each clamped to 1..kmax and rounded down to a power of two), seg_base[T]

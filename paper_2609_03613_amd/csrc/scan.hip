@@ -22,8 +22,9 @@ constexpr uint64_t kFlagAgg = 1ull << 62;
 constexpr uint64_t kFlagInc = 2ull << 62;
 constexpr uint64_t kValMask = (1ull << 62) - 1;
 
+template <int NT = kThreads>
 __device__ __forceinline__ uint32_t block_sum_u32(uint32_t v, uint32_t* lds) {
-    constexpr int NW = kThreads / kWave;
+    constexpr int NW = NT / kWave;
 #pragma unroll
     for (int m = 1; m < kWave; m <<= 1) v += shfl_xor_u32(v, m);
     if (lane() == 0) lds[threadIdx.x / kWave] = v;
@@ -53,8 +54,9 @@ __device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t* lds) {
 
 // Exclusive scan of one uint32 per thread across the workgroup; *total
 // receives the sum. Ends with a barrier, so lds is reusable.
+template <int NT = kThreads>
 __device__ __forceinline__ uint32_t block_excl_u32(uint32_t v, uint32_t* lds, uint32_t* total) {
-    constexpr int NW = kThreads / kWave;
+    constexpr int NW = NT / kWave;
     const int w = threadIdx.x / kWave, l = lane();
     uint32_t inc = v;
 #pragma unroll
@@ -83,75 +85,145 @@ __device__ __forceinline__ void status_store(uint64_t* p, uint64_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Sum of the values of workgroups 0..b-1. Waits only on workgroups with a
-// smaller ticket, which are running or done, and stops at the first
-// inclusive prefix (workgroup 0 always publishes one).
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+    for (int m = 1; m < kWave; m <<= 1) {
+        const uint32_t lo = shfl_xor_u32((uint32_t)v, m), hi = shfl_xor_u32((uint32_t)(v >> 32), m);
+        v += ((uint64_t)hi << 32) | lo;
+    }
+    return v;
+}
+
+// Sum of the values of workgroups 0..b-1, by one whole wavefront: each
+// lane reads one status word of a window of 64 predecessors (nearest in lane
+// 0) and waits until it is published; the window's values up to the nearest
+// inclusive prefix are summed, else the whole window is added and the next
+// window further back is read. Waits only on workgroups with a smaller
+// ticket, which are running or done; workgroup 0 always publishes an
+// inclusive prefix, and positions before it count as an inclusive zero.
 __device__ uint64_t look_back(const uint64_t* status, int64_t b) {
     uint64_t prefix = 0;
-    for (int64_t p = b - 1; p >= 0; --p) {
-        uint64_t s;
-        do {
-            s = status_load(&status[p]);
-        } while ((s >> 62) == 0);
-        prefix += s & kValMask;
-        if ((s & ~kValMask) == kFlagInc) break;
+    for (int64_t hi = b - 1;; hi -= kWave) {
+        const int64_t p = hi - lane();
+        uint64_t s = kFlagInc;
+        if (p >= 0) {
+            do {
+                s = status_load(&status[p]);
+            } while ((s >> 62) == 0);
+        }
+        const uint64_t inc = ballot((s & ~kValMask) == kFlagInc);
+        const int stop = inc ? __builtin_ctzll(inc) : kWave - 1;
+        prefix += wave_sum_u64(lane() <= stop ? (s & kValMask) : 0ull);
+        if (inc) return prefix;
     }
+}
+
+// Called by every lane of one wavefront: publishes the aggregate, looks
+// back and publishes the inclusive prefix; returns the exclusive prefix of
+// workgroup b (in every lane).
+__device__ __forceinline__ uint64_t publish_and_look_back(uint64_t* status, int64_t b, uint64_t agg) {
+    if (b == 0) {
+        if (lane() == 0) status_store(&status[0], kFlagInc | agg);
+        return 0;
+    }
+    if (lane() == 0) status_store(&status[b], kFlagAgg | agg);
+    const uint64_t prefix = look_back(status, b);
+    if (lane() == 0) status_store(&status[b], kFlagInc | ((prefix + agg) & kValMask));
     return prefix;
 }
 
-// Publishes the aggregate, looks back and publishes the inclusive prefix;
-// returns the exclusive prefix of workgroup b (thread 0 only).
-__device__ __forceinline__ uint64_t publish_and_look_back(uint64_t* status, int64_t b, uint64_t agg) {
-    if (b == 0) {
-        status_store(&status[0], kFlagInc | agg);
-        return 0;
+// Exclusive scan of one uint64 per thread across the workgroup; *total
+// receives the sum. Ends with a barrier, so lds is reusable.
+__device__ __forceinline__ uint64_t block_excl_u64(uint64_t v, uint64_t* lds, uint64_t* total) {
+    constexpr int NW = kThreads / kWave;
+    const int w = threadIdx.x / kWave, l = lane();
+    uint64_t inc = v;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t lo = shfl_up_u32((uint32_t)inc, d), hi = shfl_up_u32((uint32_t)(inc >> 32), d);
+        if (l >= d) inc += ((uint64_t)hi << 32) | lo;
     }
-    status_store(&status[b], kFlagAgg | agg);
-    const uint64_t prefix = look_back(status, b);
-    status_store(&status[b], kFlagInc | ((prefix + agg) & kValMask));
-    return prefix;
+    if (l == kWave - 1) lds[w] = inc;
+    __syncthreads();
+    uint64_t before = 0, all = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+        const uint64_t t = lds[i];
+        before += i < w ? t : 0ull;
+        all += t;
+    }
+    __syncthreads();
+    *total = all;
+    return before + inc - v;
 }
 
 // ---- entry-emission scan ---------------------------------------------------
 // Per Gaussian: x = number of tiles (entries), y = 1 if visible. Writes
 // emit_off[g] (exclusive prefix of x), vis_ids[rank] = g for visible g, and
 // counters[0] = M, counters[1] = V, counters[2] = M > capacity.
+// Items are loaded and stored in coalesced rounds; in between they pass
+// through LDS so that each thread scans kRounds consecutive items and one
+// workgroup scan of the packed pair (x << 24 | y; y <= kPerBlock) serves
+// both prefixes.
 
 __global__ void __launch_bounds__(kThreads) emit_scan_kernel(const uint4* __restrict__ info, int64_t n, int tiles_x,
                                                              int tiles_y, uint32_t* __restrict__ emit_off,
                                                              uint32_t* __restrict__ vis_ids, uint32_t* ticket,
                                                              uint64_t* status_x, uint64_t* status_y,
                                                              int64_t* __restrict__ counters, int64_t capacity) {
+    static_assert(kRounds == 8 && kPerBlock < (1 << 24), "packed pair layout");
     __shared__ uint32_t tk;
+    __shared__ __align__(16) uint32_t item_x[kPerBlock];  // tile counts, then exclusive x
+    __shared__ __align__(16) uint32_t item_y[kPerBlock];  // exclusive y | visible << 31
     __shared__ uint64_t lds64[kThreads / kWave];
-    __shared__ uint32_t lds32[kThreads / kWave];
     __shared__ uint64_t pre[2];
     if (threadIdx.x == 0) tk = atomicAdd(ticket, 1u);
     __syncthreads();
     const int64_t b = tk;
     const int64_t nb = gridDim.x;
     const int64_t base = b * kPerBlock;
-    uint32_t nt[kRounds];
-    uint64_t sx = 0;
-    uint32_t sy = 0;
 #pragma unroll
     for (int r = 0; r < kRounds; ++r) {
         const int64_t g = base + r * kThreads + threadIdx.x;
         int x0, y0, x1, y1;
-        nt[r] = g < n ? (uint32_t)rect_of(info[g], tiles_x, tiles_y, x0, y0, x1, y1) : 0u;
-        sx += nt[r];
-        sy += nt[r] ? 1u : 0u;
-    }
-    const uint64_t ax = block_sum_u64(sx, lds64);
-    const uint32_t ay = block_sum_u32(sy, lds32);
-    if (threadIdx.x == 0) {
-        pre[0] = publish_and_look_back(status_x, b, ax);
-    } else if (threadIdx.x == kWave) {
-        pre[1] = publish_and_look_back(status_y, b, ay);
+        item_x[r * kThreads + threadIdx.x] = g < n ? (uint32_t)rect_of(info[g], tiles_x, tiles_y, x0, y0, x1, y1) : 0u;
     }
     __syncthreads();
-    uint64_t cx = pre[0];
-    uint32_t cy = (uint32_t)pre[1];
+    const uint4* own = reinterpret_cast<const uint4*>(item_x) + 2 * threadIdx.x;
+    const uint4 c0 = own[0], c1 = own[1];
+    const uint32_t c[kRounds] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
+    uint32_t ex[kRounds], ey[kRounds];
+    uint64_t sx = 0;
+    uint32_t sy = 0;
+#pragma unroll
+    for (int i = 0; i < kRounds; ++i) {
+        ex[i] = (uint32_t)sx;
+        ey[i] = sy;
+        sx += c[i];
+        sy += c[i] ? 1u : 0u;
+    }
+    uint64_t tot;
+    const uint64_t tex = block_excl_u64((sx << 24) | sy, lds64, &tot);
+    const uint64_t ax = tot >> 24;
+    const uint32_t ay = (uint32_t)(tot & 0xFFFFFFu);
+    const uint32_t tx0 = (uint32_t)(tex >> 24), ty0 = (uint32_t)(tex & 0xFFFFFFu);
+    uint4* own_x = reinterpret_cast<uint4*>(item_x) + 2 * threadIdx.x;
+    uint4* own_y = reinterpret_cast<uint4*>(item_y) + 2 * threadIdx.x;
+    auto vy = [&](int i) { return (ty0 + ey[i]) | (c[i] ? 0x80000000u : 0u); };
+    own_x[0] = make_uint4(tx0 + ex[0], tx0 + ex[1], tx0 + ex[2], tx0 + ex[3]);
+    own_x[1] = make_uint4(tx0 + ex[4], tx0 + ex[5], tx0 + ex[6], tx0 + ex[7]);
+    own_y[0] = make_uint4(vy(0), vy(1), vy(2), vy(3));
+    own_y[1] = make_uint4(vy(4), vy(5), vy(6), vy(7));
+    if (threadIdx.x < kWave) {
+        const uint64_t px = publish_and_look_back(status_x, b, ax);
+        if (threadIdx.x == 0) pre[0] = px;
+    } else if (threadIdx.x < 2 * kWave) {
+        const uint64_t py = publish_and_look_back(status_y, b, ay);
+        if (threadIdx.x == kWave) pre[1] = py;
+    }
+    __syncthreads();
+    const uint64_t cx = pre[0];
+    const uint32_t cy = (uint32_t)pre[1];
     if (b == nb - 1 && threadIdx.x == 0) {
         counters[0] = (int64_t)(cx + ax);
         counters[1] = (int64_t)(cy + ay);
@@ -161,15 +233,12 @@ __global__ void __launch_bounds__(kThreads) emit_scan_kernel(const uint4* __rest
 #pragma unroll
     for (int r = 0; r < kRounds; ++r) {
         const int64_t g = base + r * kThreads + threadIdx.x;
-        uint32_t tx_, ty_;
-        const uint32_t ex = block_excl_u32(nt[r], lds32, &tx_);
-        const uint32_t ey = block_excl_u32(nt[r] ? 1u : 0u, lds32, &ty_);
         if (g < n) {
-            emit_off[g] = (uint32_t)(cx + ex);
-            if (nt[r]) vis_ids[cy + ey] = (uint32_t)g;
+            const int i = r * kThreads + threadIdx.x;
+            emit_off[g] = (uint32_t)(cx + item_x[i]);
+            const uint32_t y = item_y[i];
+            if (y >> 31) vis_ids[cy + (y & 0x7FFFFFFFu)] = (uint32_t)g;
         }
-        cx += tx_;
-        cy += ty_;
     }
 }
 
@@ -180,19 +249,11 @@ __host__ __device__ __forceinline__ int64_t blocks_for(int64_t n) {
     return b > 0 ? b : 1;
 }
 
-__device__ __forceinline__ uint32_t seg_total(const uint32_t* __restrict__ count, int64_t nseg, int64_t s) {
-    uint32_t t = 0;
-    if (s < nseg)
-#pragma unroll
-        for (int x = 0; x < kCopies; ++x) t += count[(int64_t)x * nseg + s];
-    return t;
-}
-
 // Appends the segments with bk >= 0 (one per thread and round) to the
 // list of their repair bucket: aggregated per wavefront and per workgroup,
 // one global atomic per bucket and workgroup. lcount / lbase: LDS [kBuckets],
 // lcount zeroed before the first round.
-template <int R>
+template <int R, int NT = kThreads>
 __device__ __forceinline__ void queue_segments(const int (&bk)[R], int64_t base, int64_t list_stride,
                                                uint32_t* lcount, uint32_t* lbase, uint32_t* __restrict__ lists,
                                                uint32_t* __restrict__ bucket_count) {
@@ -219,7 +280,7 @@ __device__ __forceinline__ void queue_segments(const int (&bk)[R], int64_t base,
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         if (bk[r] < 0) continue;
-        const int64_t sg = base + r * kThreads + threadIdx.x;
+        const int64_t sg = base + r * NT + threadIdx.x;
         lists[(int64_t)bk[r] * list_stride + lbase[bk[r]] + slot[r]] = (uint32_t)sg;
     }
 }
@@ -244,6 +305,7 @@ __global__ void __launch_bounds__(kThreads) bin_offsets_kernel(uint32_t* __restr
     __shared__ uint32_t lds32[kThreads / kWave];
     __shared__ uint64_t pre;
     __shared__ uint32_t lcount[kBuckets], lbase[kBuckets];
+    __shared__ __align__(16) uint32_t tots[kPerBlock];  // segment totals, then block-exclusive prefixes
     if (threadIdx.x == 0) tk = atomicAdd(ticket, 1u);
     if (threadIdx.x < kBuckets) lcount[threadIdx.x] = 0;
     __syncthreads();
@@ -253,35 +315,55 @@ __global__ void __launch_bounds__(kThreads) bin_offsets_kernel(uint32_t* __restr
     if (b >= nb) return;
     const int64_t base = b * kPerBlock;
     const bool queue = queue_all && counters[2] == 0;
+    // the copies' counts stay in registers for the base pass below
+    uint32_t cv[kRounds][kCopies];
     uint32_t v[kRounds];
-    uint32_t s = 0;
 #pragma unroll
     for (int r = 0; r < kRounds; ++r) {
-        v[r] = seg_total(count, nseg, base + r * kThreads + threadIdx.x);
-        s += v[r];
+        const int64_t sg = base + r * kThreads + threadIdx.x;
+        v[r] = 0;
+#pragma unroll
+        for (int x = 0; x < kCopies; ++x) {
+            cv[r][x] = sg < nseg ? count[(int64_t)x * nseg + sg] : 0u;
+            v[r] += cv[r][x];
+        }
+        tots[r * kThreads + threadIdx.x] = v[r];
     }
-    const uint32_t agg = block_sum_u32(s, lds32);
-    if (threadIdx.x == 0) pre = publish_and_look_back(status, b, agg);
     __syncthreads();
-    uint32_t carry = (uint32_t)pre;
+    // each thread scans kRounds consecutive segment totals
+    uint4* own = reinterpret_cast<uint4*>(tots) + 2 * threadIdx.x;
+    const uint4 t0 = own[0], t1 = own[1];
+    const uint32_t c[kRounds] = {t0.x, t0.y, t0.z, t0.w, t1.x, t1.y, t1.z, t1.w};
+    uint32_t ex[kRounds], s = 0;
+#pragma unroll
+    for (int i = 0; i < kRounds; ++i) {
+        ex[i] = s;
+        s += c[i];
+    }
+    uint32_t agg;
+    const uint32_t tex = block_excl_u32(s, lds32, &agg);
+    own[0] = make_uint4(tex + ex[0], tex + ex[1], tex + ex[2], tex + ex[3]);
+    own[1] = make_uint4(tex + ex[4], tex + ex[5], tex + ex[6], tex + ex[7]);
+    if (threadIdx.x < kWave) {
+        const uint64_t pv = publish_and_look_back(status, b, agg);
+        if (threadIdx.x == 0) pre = pv;
+    }
+    __syncthreads();
+    const uint32_t carry = (uint32_t)pre;
     if (b == nb - 1 && threadIdx.x == 0) bin_off[nseg] = carry + agg;
     int bk[kRounds];
     uint32_t queued = 0;
 #pragma unroll
     for (int r = 0; r < kRounds; ++r) {
         const int64_t sg = base + r * kThreads + threadIdx.x;
-        uint32_t tot;
-        uint32_t run = carry + block_excl_u32(v[r], lds32, &tot);
-        carry += tot;
+        uint32_t run = carry + tots[r * kThreads + threadIdx.x];
         bk[r] = -1;
         if (sg < nseg) {
             bin_off[sg] = run;
 #pragma unroll
             for (int x = 0; x < kCopies; ++x) {
-                uint32_t* c = count + (int64_t)x * nseg + sg;
-                const uint32_t cv = *c;
-                *c = run;
-                run += cv;
+                count[(int64_t)x * nseg + sg] = run;
+                run += cv[r][x];
             }
             if (queue) bk[r] = bucket_of(v[r]);
             if (repaired) repaired[sg] = bk[r] >= 0 ? 1 : 0;
@@ -355,7 +437,10 @@ __global__ void __launch_bounds__(kThreads) select_prefix_kernel(const uint32_t*
         s += v[r];
     }
     const uint32_t agg = block_sum_u32(s, lds32);
-    if (threadIdx.x == 0) pre = publish_and_look_back(status, b, agg);
+    if (threadIdx.x < kWave) {
+        const uint64_t pv = publish_and_look_back(status, b, agg);
+        if (threadIdx.x == 0) pre = pv;
+    }
     __syncthreads();
     uint64_t carry = pre;
     if (b == nb - 1 && threadIdx.x == 0 && carry + agg <= B) counters[3] = (int64_t)(carry + agg);
@@ -489,7 +574,10 @@ __global__ void __launch_bounds__(kThreads) seg_base_kernel(const int32_t* __res
         sum += v[r];
     }
     const uint32_t agg = block_sum_u32(sum, lds32);
-    if (threadIdx.x == 0) pre = publish_and_look_back(status, b, agg);
+    if (threadIdx.x < kWave) {
+        const uint64_t pv = publish_and_look_back(status, b, agg);
+        if (threadIdx.x == 0) pre = pv;
+    }
     __syncthreads();
     uint32_t carry = (uint32_t)pre;
     if (b == nb - 1 && threadIdx.x == 0) seg_base[T] = carry + agg;
@@ -503,6 +591,153 @@ __global__ void __launch_bounds__(kThreads) seg_base_kernel(const int32_t* __res
             tile_seg[t] = make_uint2(carry + ex, 32u - (uint32_t)__builtin_ctz(v[r]));
         }
         carry += tot;
+    }
+}
+
+// ---- grouped binning: group prefix and per-group counting sort ---------------
+
+// group_off[g] = exclusive prefix of gcount over g < G, group_off[G] = total
+// (one workgroup; G <= kMaxGroups = 8 per thread), and order[0 .. G) = the
+// groups by decreasing floor(log2(count)) (empty groups last; arbitrary
+// inside a class), so that the group sort starts the longest groups first.
+__global__ void __launch_bounds__(kTailThreads) group_scan_kernel(const uint32_t* __restrict__ gcount, int G,
+                                                                  uint32_t* __restrict__ group_off,
+                                                                  uint32_t* __restrict__ order) {
+    static_assert(kMaxGroups <= 8 * kTailThreads, "eight groups per thread");
+    constexpr int kClasses = 33;  // class 31 - floor(log2 count) for count > 0, 32 for empty
+    __shared__ uint32_t lds[kTailThreads / kWave];
+    __shared__ uint32_t chist[kClasses], cbase[kClasses];
+    if (threadIdx.x < kClasses) chist[threadIdx.x] = 0;
+    const int i0 = 8 * threadIdx.x;
+    uint32_t v[8], s = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        v[j] = i0 + j < G ? gcount[i0 + j] : 0u;
+        s += v[j];
+    }
+    uint32_t total;
+    uint32_t run = tail_excl_u32(s, lds, &total);  // ends with a barrier: chist is cleared
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        if (i0 + j < G) {
+            group_off[i0 + j] = run;
+            atomicAdd(&chist[v[j] ? __builtin_clz(v[j]) : 32], 1u);
+        }
+        run += v[j];
+    }
+    if (threadIdx.x == 0) group_off[G] = total;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t b = 0;
+        for (int c = 0; c < kClasses; ++c) {
+            cbase[c] = b;
+            b += chist[c];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+        if (i0 + j < G) order[atomicAdd(&cbase[v[j] ? __builtin_clz(v[j]) : 32], 1u)] = (uint32_t)(i0 + j);
+}
+
+constexpr int kSortThreads = 1024;
+constexpr int kSortBatch = 8;  // entries per thread and sweep step, loaded before any is used
+
+// One workgroup per group: its entries [group_off[g], group_off[g + 1])
+// (clipped to the capacity) are counted per segment in LDS, the segment
+// offsets follow by a workgroup scan, and a second sweep places every entry
+// at its segment offset + an LDS rank. Also writes bin_off for the group's
+// segments, queues the repair segments (as bin_offsets_kernel) and writes
+// the records of single-entry segments.
+__global__ void __launch_bounds__(kSortThreads) group_sort_kernel(
+    const uint64_t* __restrict__ tmp_pair, const uint16_t* __restrict__ tmp_code, const uint32_t* __restrict__ group_off,
+    const uint32_t* __restrict__ order, GroupMap gm, int64_t nseg, int64_t capacity, uint64_t* __restrict__ pairs, uint32_t* __restrict__ bin_off,
+    uint32_t* __restrict__ lists, uint32_t* __restrict__ bucket_count, int64_t* __restrict__ counters, bool queue_all,
+    uint8_t* __restrict__ repaired, RecordSink rs) {
+    constexpr int NT = kSortThreads;
+    constexpr int kMaxPer = kMaxGroupSegs / NT;
+    constexpr uint32_t kNone = 0xFFFFFFFFu;
+    __shared__ uint32_t hist[kMaxGroupSegs];
+    __shared__ uint32_t cur[kMaxGroupSegs];
+    __shared__ uint32_t lds32[NT / kWave];
+    __shared__ uint32_t lcount[kBuckets], lbase[kBuckets];
+    const int g = (int)order[blockIdx.x];
+    const int64_t cap = capacity;
+    const uint32_t lo = (uint32_t)min((int64_t)group_off[g], cap);
+    const uint32_t hi = (uint32_t)min((int64_t)group_off[g + 1], cap);
+    const int per = (gm.GS + NT - 1) / NT;  // segments per thread, <= kMaxPer
+    for (int c = threadIdx.x; c < per * NT; c += NT) hist[c] = 0;
+    if (threadIdx.x < kBuckets) lcount[threadIdx.x] = 0;
+    __syncthreads();
+    for (uint32_t base = lo; base < hi; base += NT * kSortBatch) {
+        uint32_t c[kSortBatch];
+#pragma unroll
+        for (int j = 0; j < kSortBatch; ++j) {
+            const uint32_t e = base + (uint32_t)(j * NT) + threadIdx.x;
+            c[j] = e < hi ? (uint32_t)tmp_code[e] : kNone;
+        }
+#pragma unroll
+        for (int j = 0; j < kSortBatch; ++j)
+            if (c[j] != kNone) atomicAdd(&hist[c[j]], 1u);
+    }
+    __syncthreads();
+    // exclusive prefix of the segment lengths: thread i owns segments i per ..
+    uint32_t ex[kMaxPer], sum = 0;
+#pragma unroll
+    for (int j = 0; j < kMaxPer; ++j) {
+        ex[j] = sum;
+        if (j < per) sum += hist[threadIdx.x * per + j];
+    }
+    uint32_t agg;
+    const uint32_t tex = block_excl_u32<NT>(sum, lds32, &agg);
+#pragma unroll
+    for (int j = 0; j < kMaxPer; ++j)
+        if (j < per) cur[threadIdx.x * per + j] = tex + ex[j];
+    __syncthreads();
+    const bool queue = queue_all && counters[2] == 0;
+    const int64_t sbase = (int64_t)g * gm.GS;
+    int bk[kMaxPer];
+    uint32_t queued = 0;
+#pragma unroll
+    for (int r = 0; r < kMaxPer; ++r) {
+        const int c = r * NT + threadIdx.x;
+        const int64_t sg = sbase + c;
+        bk[r] = -1;
+        if (r < per && c < gm.GS && sg < nseg) {
+            const uint32_t len = hist[c];
+            bin_off[sg] = lo + cur[c];
+            if (queue) bk[r] = bucket_of(len);
+            if (repaired) repaired[sg] = bk[r] >= 0 ? 1 : 0;
+            if (bk[r] >= 0) queued += len;
+        }
+    }
+    if (g == gm.G - 1 && threadIdx.x == 0) bin_off[nseg] = hi;
+    queue_segments<kMaxPer, NT>(bk, sbase, nseg, lcount, lbase, lists, bucket_count);
+    if (queue) {
+        const uint32_t qsum = block_sum_u32<NT>(queued, lds32);
+        if (threadIdx.x == 0 && qsum)
+            atomicAdd(reinterpret_cast<unsigned long long*>(&counters[3]), (unsigned long long)qsum);
+    }
+    for (uint32_t base = lo; base < hi; base += NT * kSortBatch) {
+        uint32_t c[kSortBatch];
+        uint64_t pr[kSortBatch];
+#pragma unroll
+        for (int j = 0; j < kSortBatch; ++j) {
+            const uint32_t e = base + (uint32_t)(j * NT) + threadIdx.x;
+            c[j] = kNone;
+            pr[j] = 0;
+            if (e < hi) {
+                c[j] = tmp_code[e];
+                pr[j] = tmp_pair[e];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kSortBatch; ++j) {
+            if (c[j] == kNone) continue;
+            const uint32_t p = lo + atomicAdd(&cur[c[j]], 1u);
+            pairs[p] = pr[j];
+            if (rs.masks && hist[c[j]] == 1u) rs.put((uint32_t)(sbase + c[j]), p, pr[j]);
+        }
     }
 }
 
@@ -547,6 +782,21 @@ hipError_t launch_repair_select(const uint32_t* bin_off, int64_t T, int K, float
                        K, budget, ticket, status, ctl, lists, bucket_count, counters, repaired);
     hipLaunchKernelGGL(select_tail_kernel, dim3(1), dim3(kTailThreads), 0, s, bin_off, nseg, K, budget, ctl, lists,
                        bucket_count, counters, repaired);
+    return hipGetLastError();
+}
+
+hipError_t launch_group_scan(const uint32_t* gcount, GroupMap gm, uint32_t* group_off, uint32_t* order,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(group_scan_kernel, dim3(1), dim3(kTailThreads), 0, s, gcount, gm.G, group_off, order);
+    return hipGetLastError();
+}
+
+hipError_t launch_group_sort(const uint64_t* tmp_pair, const uint16_t* tmp_code, const uint32_t* group_off,
+                             const uint32_t* order, GroupMap gm, int64_t nseg, int64_t capacity, uint64_t* pairs, uint32_t* bin_off,
+                             uint32_t* lists, uint32_t* bucket_count, int64_t* counters, bool queue_all,
+                             uint8_t* repaired, RecordSink rs, hipStream_t s) {
+    hipLaunchKernelGGL(group_sort_kernel, dim3((unsigned)gm.G), dim3(kSortThreads), 0, s, tmp_pair, tmp_code, group_off, order, gm,
+                       nseg, capacity, pairs, bin_off, lists, bucket_count, counters, queue_all, repaired, rs);
     return hipGetLastError();
 }
 
