@@ -29,6 +29,7 @@
 #include <algorithm>
 
 #include "common.hpp"
+#include "wave_sort.hpp"
 
 namespace tgs {
 
@@ -483,23 +484,6 @@ __global__ void __launch_bounds__(256) group_scatter_kernel(const uint4* __restr
 // exact repair
 // ---------------------------------------------------------------------------
 
-// Bitonic network over groups of G lanes, one key per lane (the partner at
-// distance j < G is lane l ^ j, inside the group).
-template <int G>
-__device__ __forceinline__ uint64_t group_bitonic(uint64_t v, int li) {
-#pragma unroll
-    for (int k = 2; k <= G; k <<= 1) {
-#pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            const uint64_t o = shfl_xor_u64(v, j);
-            const bool up = (li & k) == 0, lower = (li & j) == 0;
-            const uint64_t mn = v < o ? v : o, mx = v < o ? o : v;
-            v = (lower == up) ? mn : mx;
-        }
-    }
-    return v;
-}
-
 // Segments of 2..64 keys: 64 / G segments per wavefront job, G lanes each
 // (job i: segments i * 64 / G + lane / G of the bucket list).
 template <int G>
@@ -523,37 +507,15 @@ __device__ __forceinline__ void sort_group_job(const uint32_t* __restrict__ bin_
     }
 }
 
-// Segments of 65..512 keys: one wavefront, bitonic network in its own LDS
-// region (no workgroup barriers; LDS operations of a wavefront complete in
-// order).
-__device__ __forceinline__ void sort_wave_lds_job(const uint32_t* __restrict__ bin_off, uint32_t s,
-                                                  uint64_t* __restrict__ pairs, uint64_t* buf, const RecordSink& rs) {
-    const int l = lane();
+__device__ __forceinline__ void sort_wave_reg_job(const uint32_t* __restrict__ bin_off, uint32_t s,
+                                                  uint64_t* __restrict__ pairs, const RecordSink& rs) {
     const uint32_t begin = bin_off[s], len = bin_off[s + 1] - begin;
-    uint32_t P = 1;
-    while (P < len) P <<= 1;
-    for (uint32_t e = l; e < P; e += kWave) buf[e] = e < len ? pairs[begin + e] : ~0ull;
-    wave_sync();
-    for (uint32_t k = 2; k <= P; k <<= 1) {
-        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            for (uint32_t t = l; t < P / 2; t += kWave) {
-                const uint32_t lo = (t / j) * 2 * j + (t % j), hi = lo + j;
-                const uint64_t a = buf[lo], b = buf[hi];
-                const bool up = (lo & k) == 0;
-                if ((a > b) == up) {
-                    buf[lo] = b;
-                    buf[hi] = a;
-                }
-            }
-            wave_sync();
-        }
-    }
-    for (uint32_t e = l; e < len; e += kWave) {
-        const uint64_t v = buf[e];
-        pairs[begin + e] = v;
-        rs.put(s, begin + e, v);
-    }
-    wave_sync();
+    if (len <= 2 * kWave)
+        sort_wave_reg<2>(pairs + begin, s, begin, len, rs);
+    else if (len <= 4 * kWave)
+        sort_wave_reg<4>(pairs + begin, s, begin, len, rs);
+    else
+        sort_wave_reg<8>(pairs + begin, s, begin, len, rs);
 }
 
 // Buckets 0..4 in one launch. The wavefront jobs of all five buckets form
@@ -564,7 +526,6 @@ __global__ void __launch_bounds__(256) sort_small_kernel(const uint32_t* __restr
                                                          const uint32_t* __restrict__ lists, int64_t nseg,
                                                          const uint32_t* __restrict__ bucket_count,
                                                          uint64_t* __restrict__ pairs, RecordSink rs) {
-    __shared__ uint64_t buf[4][512];
     const uint32_t waves = gridDim.x * (blockDim.x / kWave);
     const uint32_t wid = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
     const uint32_t c0 = bucket_count[0], c1 = bucket_count[1], c2 = bucket_count[2], c3 = bucket_count[3],
@@ -573,7 +534,7 @@ __global__ void __launch_bounds__(256) sort_small_kernel(const uint32_t* __restr
     const uint32_t j4 = c4, j3 = j4 + c3, j2 = j3 + (c2 + 1) / 2, j1 = j2 + (c1 + 3) / 4, j0 = j1 + (c0 + 7) / 8;
     for (uint32_t j = wid; j < j0; j += waves) {
         if (j < j4)
-            sort_wave_lds_job(bin_off, lists[4 * nseg + j], pairs, buf[threadIdx.x / kWave], rs);
+            sort_wave_reg_job(bin_off, lists[4 * nseg + j], pairs, rs);
         else if (j < j3)
             sort_group_job<64>(bin_off, lists + 3 * nseg, c3, j - j4, pairs, rs);
         else if (j < j2)
