@@ -465,7 +465,7 @@ __global__ void __launch_bounds__(256) group_scatter_kernel(const uint4* __restr
     for (int it = 0; it < kGroupChunk / 256; ++it) {
         const int64_t g0 = first + (int64_t)(it * 4 + w) * kWave;
         for_wave_entries_at<R, true, false>(
-            g0, info, n, emit_off, tiles_x, tiles_y, zrange, nk, gm.K, &wg[w], [&](const Ent (&en)[R]) {
+            g0, info, n, emit_off, tiles_x, tiles_y, zrange, nk, gm.K * gm.SB, &wg[w], [&](const Ent (&en)[R]) {
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     if (!en[r].ok) continue;
@@ -474,7 +474,8 @@ __global__ void __launch_bounds__(256) group_scatter_kernel(const uint4* __restr
                     const uint32_t pos = atomicAdd(&cursor[grp], 1u);
                     if (pos >= capacity) continue;
                     tmp_pair[pos] = ((uint64_t)en[r].key << 32) | (uint64_t)en[r].gid;
-                    tmp_code[pos] = (uint16_t)((t - grp * (uint32_t)gm.GT) * (uint32_t)gm.K + en[r].bin);
+                    // en.bin is the bin at K SB bins: (bin, sub) = (bin / SB, bin % SB)
+                    tmp_code[pos] = (uint16_t)((t - grp * (uint32_t)gm.GT) * (uint32_t)(gm.K * gm.SB) + en[r].bin);
                 }
             });
     }
@@ -829,8 +830,8 @@ hipError_t launch_tile_order(const uint32_t* offsets, SegMap sm, int64_t T, uint
     return hipGetLastError();
 }
 
-GroupMap group_map(int64_t T, int K) {
-    GroupMap gm{K, 1, 0, 0};
+GroupMap group_map(int64_t T, int K, int sub) {
+    GroupMap gm{K, 1, 0, 0, 1};
     if (T <= 0 || K <= 0) return gm;
     int64_t gt = K >= kGroupSegTarget ? 1 : kGroupSegTarget / K;
     while ((T + gt - 1) / gt > kMaxGroups) gt *= 2;
@@ -838,6 +839,7 @@ GroupMap group_map(int64_t T, int K) {
     gm.GT = (int)gt;
     gm.G = (int)((T + gt - 1) / gt);
     gm.GS = (int)(gt * K);
+    if (sub > 1 && (int64_t)gm.GS * sub <= kMaxGroupSegs) gm.SB = sub;
     return gm;
 }
 

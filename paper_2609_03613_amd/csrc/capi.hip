@@ -1,6 +1,7 @@
 // C ABI: argument validation, workspace layout and the launch sequences of
 // tgs_project / tgs_bin / tgs_rasterize.
 #include <math.h>
+#include <algorithm>
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
@@ -106,7 +107,8 @@ struct Layout {
     size_t emit_off, vis_ids, zero, zero_words, status_emit_x, status_emit_y, status_bins, status_segs, status_sel,
         count,
         count_var, tile_seg, entry_rank, seg_lists, keys_in, vals_in, sort_tmp, sort_tmp_bytes, gcount, group_off,
-        wgbase, tmp_pair, tmp_code, group_order, total;
+        wgbase, tmp_pair, tmp_code, group_order, sub_off, total;
+    int64_t list_stride;  // entries per repair bucket list
     GroupMap gm;  // gm.G > 0: grouped binning
 };
 
@@ -128,16 +130,26 @@ int end_bit_for(int64_t T) {
 
 // Workspace: [emit offsets][visible ids][zeroed region: control words,
 // scan status words (with rule-based repair also those of the selection
-// scan), group totals (grouped binning)][repair lists] then, for BINNED
-// with uniform K, [group offsets][workgroup slice bases][grouped pairs]
-// [grouped segment codes][group order] (grouped binning) or [per-XCD counts in the zeroed
-// region][entry ranks] (group shape out of range), with per-tile bin counts
-// [entry ranks][per-XCD counts][tile segments]; GLOBAL: [unsorted keys]
+// scan), then the group totals (grouped binning) or the per-XCD counts
+// (uniform K, group shape out of range)] followed by, for BINNED:
+// grouped: [sub-segment offsets (sub-bins only)][repair lists][group
+// offsets][group order][workgroup slice bases][grouped pairs][grouped
+// codes]; otherwise [entry ranks][repair lists] and, with per-tile bin
+// counts, [per-XCD counts][tile segments]. GLOBAL: [unsorted keys]
 // [unsorted ids][sort scratch]. The zeroed region is cleared by one fill at
 // the start of each tgs_bin; with per-tile bin counts only the first
 // kCopies * S words of the counts are cleared, by a fill sized on the
 // device. K is the uniform bin count or the bound of the per-tile counts.
-Layout layout(int64_t n, int64_t capacity, int64_t T, int K, int order, bool var, bool rules) {
+// Sub-bins per bin of the grouped path: exact repair without records, and
+// bins of the depth itself (the sub-bin order is the depth order only when
+// the binning key is the sort key; the near-depth key is not).
+int sub_bins_for(const tgs_params* p, int order) {
+    const bool ok = order == TGS_ORDER_BINNED && p->repair == TGS_REPAIR_ALL && !p->packed && !p->per_tile_bins_dev &&
+                    !p->near_shift;
+    return ok ? kSubBins : 1;
+}
+
+Layout layout(int64_t n, int64_t capacity, int64_t T, int K, int order, bool var, bool rules, int sub) {
     Layout L{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -161,7 +173,7 @@ Layout layout(int64_t n, int64_t capacity, int64_t T, int K, int order, bool var
     z += var ? 2 * (size_t)scan_blocks(T) : 0;
     L.status_sel = z;
     z += rules ? 2 * nbb : 0;
-    L.gm = order == TGS_ORDER_BINNED && !var ? group_map(T, K) : GroupMap{K, 1, 0, 0};
+    L.gm = order == TGS_ORDER_BINNED && !var ? group_map(T, K, sub) : GroupMap{K, 1, 0, 0, 1};
     const bool grouped = L.gm.G > 0;
     if (grouped) {
         z = (z + 63) & ~(size_t)63;
@@ -174,9 +186,15 @@ Layout layout(int64_t n, int64_t capacity, int64_t T, int K, int order, bool var
     }
     L.zero_words = z;
     L.zero = take(sizeof(uint32_t) * z);
+    L.list_stride = nseg;
     if (grouped) {
         const size_t chunks = (size_t)((n + kGroupChunk - 1) / kGroupChunk);
-        L.seg_lists = take(sizeof(uint32_t) * (size_t)kBuckets * (size_t)nseg);
+        if (L.gm.SB > 1) {
+            // a queued sub-segment holds two or more of the at most capacity entries
+            L.list_stride = std::min<int64_t>(nseg * L.gm.SB, capacity / 2 + 1);
+            L.sub_off = take(sizeof(uint32_t) * ((size_t)nseg * L.gm.SB + 1));
+        }
+        L.seg_lists = take(sizeof(uint32_t) * (size_t)kBuckets * (size_t)L.list_stride);
         L.group_off = take(sizeof(uint32_t) * ((size_t)L.gm.G + 1));
         L.group_order = take(sizeof(uint32_t) * (size_t)L.gm.G);
         L.wgbase = take(sizeof(uint32_t) * (chunks > 0 ? chunks : 1) * (size_t)L.gm.G);
@@ -254,7 +272,7 @@ size_t tgs_bin_workspace_size(int64_t n, int64_t capacity, const tgs_camera* cam
     if (params->tile_size != 8 && params->tile_size != 16 && params->tile_size != 32) return 0;
     return layout(n, capacity, tiles_of(cam, params->tile_size), params->num_bins, order,
                   params->per_tile_bins_dev != nullptr && order == TGS_ORDER_BINNED,
-                  params->repair == TGS_REPAIR_RULES && order == TGS_ORDER_BINNED)
+                  params->repair == TGS_REPAIR_RULES && order == TGS_ORDER_BINNED, sub_bins_for(params, order))
         .total;
 }
 
@@ -285,7 +303,7 @@ tgs_status tgs_bin(const tgs_projected* pr, const tgs_camera* cam, const tgs_par
         return fail(TGS_ERR_INVALID_ARG, "keys or vals is NULL");
     }
     const bool rules = order == TGS_ORDER_BINNED && params->repair == TGS_REPAIR_RULES;
-    const Layout L = layout(n, cap, T, K, order, var, rules);
+    const Layout L = layout(n, cap, T, K, order, var, rules, sub_bins_for(params, order));
     if (!ws || ws_bytes < L.total)
         return fail(TGS_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
     hipStream_t s = (hipStream_t)stream;
@@ -357,17 +375,21 @@ tgs_status tgs_bin(const tgs_projected* pr, const tgs_camera* cam, const tgs_par
         TGS_HIP(launch_group_scatter(pr->info_dev, n, emit_off, out->zrange_dev, nk, L.gm, tiles_x, tiles_y, group_off,
                                      wgbase, tmp_pair, tmp_code, cap, s),
                 "group scatter");
-        TGS_HIP(launch_group_sort(tmp_pair, tmp_code, group_off, group_order, L.gm, nseg, cap, out->pairs_dev, out->offsets_dev,
-                                  seg_lists, bucket_count, out->counters_dev, params->repair == TGS_REPAIR_ALL,
-                                  out->repaired_dev, rs, s),
+        uint32_t* sub_off = L.gm.SB > 1 ? (uint32_t*)(w + L.sub_off) : nullptr;
+        TGS_HIP(launch_group_sort(tmp_pair, tmp_code, group_off, group_order, L.gm, nseg, cap, out->pairs_dev,
+                                  out->offsets_dev, sub_off, seg_lists, L.list_stride, bucket_count, out->counters_dev,
+                                  params->repair == TGS_REPAIR_ALL, out->repaired_dev, rs, s),
                 "group sort");
         if (rules)
             TGS_HIP(launch_repair_select(out->offsets_dev, T, K, params->repair_budget, zero + kTicketSel,
                                          (uint64_t*)(zero + L.status_sel), zero + kSelCtl, seg_lists, bucket_count,
                                          out->counters_dev, out->repaired_dev, s),
                     "repair selection");
+        // with sub-bins the queues hold sub-segments, located by sub_off
         if (params->repair != TGS_REPAIR_NONE)
-            TGS_HIP(launch_repair(out->offsets_dev, nseg, out->pairs_dev, seg_lists, bucket_count, rs, s), "repair");
+            TGS_HIP(launch_repair(sub_off ? sub_off : out->offsets_dev, L.list_stride, out->pairs_dev, seg_lists,
+                                  bucket_count, rs, s),
+                    "repair");
         if (out->tile_order_dev)
             TGS_HIP(launch_tile_order(out->offsets_dev, sm, T, zero + kTileHist, out->tile_order_dev,
                                       params->split_entries, params->split_mean_factor, s),

@@ -202,20 +202,30 @@ struct RecordSink {
 // tile t. Uniform (seg_base == null): K bins per tile, first(t) = t K.
 // Grouped binning (uniform K): groups of GT consecutive tiles, G groups,
 // GS = GT K segments per group (group g holds segments g GS .. g GS + GS - 1).
+// SB > 1 (exact repair with depth bins): every bin is split further into SB
+// sub-bins of the log-depth map at SB K bins (bin = sub-bin / SB exactly),
+// so the group sort leaves each segment ordered by sub-bin, which is the
+// depth order between sub-bins, and the repair sorts only the sub-segments;
+// entry code in the group = (tile in group K + bin) SB + sub.
 struct GroupMap {
-    int K, GT, G, GS;
+    int K, GT, G, GS, SB;
 };
 #ifndef TGS_GROUP_SEGS
 #define TGS_GROUP_SEGS 512
 #endif
+#ifndef TGS_SUB_BINS
+#define TGS_SUB_BINS 4
+#endif
+constexpr int kSubBins = TGS_SUB_BINS;  // sub-bins per bin in exact-repair mode
 constexpr int kGroupSegTarget = TGS_GROUP_SEGS;  // segments per group aimed at
 constexpr int kMaxGroups = 8192;      // LDS counters of one workgroup
 constexpr int kMaxGroupSegs = 4096;   // LDS counters of one group sort
 constexpr int kGroupChunk = 2048;     // Gaussians per workgroup of the group count / scatter
 // The grouped path's group shape for T tiles and K bins: GT = max(1,
-// kGroupSegTarget / K) tiles, doubled until G <= kMaxGroups; .G = 0 when GS would exceed
-// kMaxGroupSegs (then the per-entry atomic path is used).
-GroupMap group_map(int64_t T, int K);
+// kGroupSegTarget / K) tiles, doubled until G <= kMaxGroups; .G = 0 when GS
+// would exceed kMaxGroupSegs (then the per-entry atomic path is used). SB =
+// sub (a power of two) when GS sub <= kMaxGroupSegs, else 1.
+GroupMap group_map(int64_t T, int K, int sub);
 
 // Per-tile bin counts: seg_base [T + 1] is the exclusive prefix sum of the
 // counts (powers of two), first(t) = seg_base[t], and the number of
@@ -344,7 +354,10 @@ hipError_t launch_bin_scatter(const uint32_t* info, int64_t n, const uint32_t* e
 // the capacity are dropped; order [G] = the groups, longest first.
 // group_sort: pairs in (tile, bin) order, bin_off
 // [S + 1] (S = T K), repair queues and repaired[] as launch_bin_offsets,
-// single-entry segments' records; bucket_count must be zero.
+// single-entry segments' records; bucket_count must be zero. With SB > 1
+// the repair queues hold sub-segments: sub_off [S SB + 1] gets their
+// offsets and lists their ids (list stride list_stride); repaired[] and
+// counters[3] stay per segment.
 hipError_t launch_group_count(const uint32_t* info, int64_t n, const uint32_t* emit_off, GroupMap gm, int tiles_x,
                               int tiles_y, uint32_t* gcount, uint32_t* wgbase, hipStream_t s);
 hipError_t launch_group_scan(const uint32_t* gcount, GroupMap gm, uint32_t* group_off, uint32_t* order,
@@ -355,8 +368,8 @@ hipError_t launch_group_scatter(const uint32_t* info, int64_t n, const uint32_t*
                                 hipStream_t s);
 hipError_t launch_group_sort(const uint64_t* tmp_pair, const uint16_t* tmp_code, const uint32_t* group_off,
                              const uint32_t* order, GroupMap gm, int64_t nseg, int64_t capacity, uint64_t* pairs, uint32_t* bin_off,
-                             uint32_t* lists, uint32_t* bucket_count, int64_t* counters, bool queue_all,
-                             uint8_t* repaired, RecordSink rs, hipStream_t s);
+                             uint32_t* sub_off, uint32_t* lists, int64_t list_stride, uint32_t* bucket_count,
+                             int64_t* counters, bool queue_all, uint8_t* repaired, RecordSink rs, hipStream_t s);
 
 // Per-tile bin counts: seg_base[t] = exclusive prefix sum of the bin counts
 // (each clamped to 1..kmax and rounded down to a power of two), seg_base[T]

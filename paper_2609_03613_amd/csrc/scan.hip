@@ -644,16 +644,18 @@ constexpr int kSortThreads = 1024;
 constexpr int kSortBatch = 8;  // entries per thread and sweep step, loaded before any is used
 
 // One workgroup per group: its entries [group_off[g], group_off[g + 1])
-// (clipped to the capacity) are counted per segment in LDS, the segment
-// offsets follow by a workgroup scan, and a second sweep places every entry
-// at its segment offset + an LDS rank. Also writes bin_off for the group's
-// segments, queues the repair segments (as bin_offsets_kernel) and writes
-// the records of single-entry segments.
+// (clipped to the capacity) are counted per code (segment, or sub-segment
+// when SB > 1) in LDS, the code offsets follow by a workgroup scan, and a
+// second sweep places every entry at its code offset + an LDS rank. Also
+// writes bin_off for the group's segments (and sub_off for its
+// sub-segments), queues the repair (sub-)segments (as bin_offsets_kernel),
+// and writes the records of single-entry segments.
 __global__ void __launch_bounds__(kSortThreads) group_sort_kernel(
     const uint64_t* __restrict__ tmp_pair, const uint16_t* __restrict__ tmp_code, const uint32_t* __restrict__ group_off,
-    const uint32_t* __restrict__ order, GroupMap gm, int64_t nseg, int64_t capacity, uint64_t* __restrict__ pairs, uint32_t* __restrict__ bin_off,
-    uint32_t* __restrict__ lists, uint32_t* __restrict__ bucket_count, int64_t* __restrict__ counters, bool queue_all,
-    uint8_t* __restrict__ repaired, RecordSink rs) {
+    const uint32_t* __restrict__ order, GroupMap gm, int64_t nseg, int64_t capacity, uint64_t* __restrict__ pairs,
+    uint32_t* __restrict__ bin_off, uint32_t* __restrict__ sub_off, uint32_t* __restrict__ lists, int64_t list_stride,
+    uint32_t* __restrict__ bucket_count, int64_t* __restrict__ counters, bool queue_all, uint8_t* __restrict__ repaired,
+    RecordSink rs) {
     constexpr int NT = kSortThreads;
     constexpr int kMaxPer = kMaxGroupSegs / NT;
     constexpr uint32_t kNone = 0xFFFFFFFFu;
@@ -665,7 +667,9 @@ __global__ void __launch_bounds__(kSortThreads) group_sort_kernel(
     const int64_t cap = capacity;
     const uint32_t lo = (uint32_t)min((int64_t)group_off[g], cap);
     const uint32_t hi = (uint32_t)min((int64_t)group_off[g + 1], cap);
-    const int per = (gm.GS + NT - 1) / NT;  // segments per thread, <= kMaxPer
+    const int SB = gm.SB;
+    const int codes = gm.GS * SB;
+    const int per = (codes + NT - 1) / NT;  // codes per thread, <= kMaxPer
     for (int c = threadIdx.x; c < per * NT; c += NT) hist[c] = 0;
     if (threadIdx.x < kBuckets) lcount[threadIdx.x] = 0;
     __syncthreads();
@@ -681,7 +685,7 @@ __global__ void __launch_bounds__(kSortThreads) group_sort_kernel(
             if (c[j] != kNone) atomicAdd(&hist[c[j]], 1u);
     }
     __syncthreads();
-    // exclusive prefix of the segment lengths: thread i owns segments i per ..
+    // exclusive prefix of the code counts: thread i owns codes i per ..
     uint32_t ex[kMaxPer], sum = 0;
 #pragma unroll
     for (int j = 0; j < kMaxPer; ++j) {
@@ -695,24 +699,37 @@ __global__ void __launch_bounds__(kSortThreads) group_sort_kernel(
         if (j < per) cur[threadIdx.x * per + j] = tex + ex[j];
     __syncthreads();
     const bool queue = queue_all && counters[2] == 0;
-    const int64_t sbase = (int64_t)g * gm.GS;
+    const int64_t sbase = (int64_t)g * gm.GS;  // first segment of the group
+    const int64_t cbase = sbase * SB;          // first code id of the group
+    const int64_t ncode = nseg * SB;
+    // repair queues per code (segments when SB == 1, sub-segments otherwise)
     int bk[kMaxPer];
-    uint32_t queued = 0;
 #pragma unroll
     for (int r = 0; r < kMaxPer; ++r) {
         const int c = r * NT + threadIdx.x;
-        const int64_t sg = sbase + c;
         bk[r] = -1;
-        if (r < per && c < gm.GS && sg < nseg) {
-            const uint32_t len = hist[c];
-            bin_off[sg] = lo + cur[c];
-            if (queue) bk[r] = bucket_of(len);
-            if (repaired) repaired[sg] = bk[r] >= 0 ? 1 : 0;
-            if (bk[r] >= 0) queued += len;
+        if (r < per && c < codes && cbase + c < ncode) {
+            if (SB > 1) sub_off[cbase + c] = lo + cur[c];
+            if (queue) bk[r] = bucket_of(hist[c]);
         }
     }
-    if (g == gm.G - 1 && threadIdx.x == 0) bin_off[nseg] = hi;
-    queue_segments<kMaxPer, NT>(bk, sbase, nseg, lcount, lbase, lists, bucket_count);
+    // offsets, repair flags and repaired entries per segment
+    uint32_t queued = 0;
+    for (int c = threadIdx.x; c < gm.GS; c += NT) {
+        const int64_t sg = sbase + c;
+        if (sg >= nseg) break;
+        uint32_t len = 0;
+        for (int k = 0; k < SB; ++k) len += hist[c * SB + k];
+        bin_off[sg] = lo + cur[c * SB];
+        const bool rep = queue && len >= 2;
+        if (repaired) repaired[sg] = rep ? 1 : 0;
+        if (rep) queued += len;
+    }
+    if (g == gm.G - 1 && threadIdx.x == 0) {
+        bin_off[nseg] = hi;
+        if (SB > 1) sub_off[ncode] = hi;
+    }
+    queue_segments<kMaxPer, NT>(bk, cbase, list_stride, lcount, lbase, lists, bucket_count);
     if (queue) {
         const uint32_t qsum = block_sum_u32<NT>(queued, lds32);
         if (threadIdx.x == 0 && qsum)
@@ -736,6 +753,7 @@ __global__ void __launch_bounds__(kSortThreads) group_sort_kernel(
             if (c[j] == kNone) continue;
             const uint32_t p = lo + atomicAdd(&cur[c[j]], 1u);
             pairs[p] = pr[j];
+            // records exist only with SB == 1, where a code is a segment
             if (rs.masks && hist[c[j]] == 1u) rs.put((uint32_t)(sbase + c[j]), p, pr[j]);
         }
     }
@@ -793,10 +811,11 @@ hipError_t launch_group_scan(const uint32_t* gcount, GroupMap gm, uint32_t* grou
 
 hipError_t launch_group_sort(const uint64_t* tmp_pair, const uint16_t* tmp_code, const uint32_t* group_off,
                              const uint32_t* order, GroupMap gm, int64_t nseg, int64_t capacity, uint64_t* pairs, uint32_t* bin_off,
-                             uint32_t* lists, uint32_t* bucket_count, int64_t* counters, bool queue_all,
-                             uint8_t* repaired, RecordSink rs, hipStream_t s) {
+                             uint32_t* sub_off, uint32_t* lists, int64_t list_stride, uint32_t* bucket_count,
+                             int64_t* counters, bool queue_all, uint8_t* repaired, RecordSink rs, hipStream_t s) {
     hipLaunchKernelGGL(group_sort_kernel, dim3((unsigned)gm.G), dim3(kSortThreads), 0, s, tmp_pair, tmp_code, group_off, order, gm,
-                       nseg, capacity, pairs, bin_off, lists, bucket_count, counters, queue_all, repaired, rs);
+                       nseg, capacity, pairs, bin_off, sub_off, lists, list_stride, bucket_count, counters, queue_all, repaired,
+                       rs);
     return hipGetLastError();
 }
 
