@@ -214,7 +214,7 @@ struct GroupMap {
 #define TGS_GROUP_SEGS 512
 #endif
 #ifndef TGS_SUB_BINS
-#define TGS_SUB_BINS 4
+#define TGS_SUB_BINS 8
 #endif
 constexpr int kSubBins = TGS_SUB_BINS;  // sub-bins per bin in exact-repair mode
 constexpr int kGroupSegTarget = TGS_GROUP_SEGS;  // segments per group aimed at
