@@ -55,22 +55,26 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
     return v;
 }
 
+// LDS of one depth-range workgroup.
+struct RangeLds {
+    uint32_t keys[kMaxSamples];
+    uint32_t hist[2][kBinsR];
+    uint32_t sel[2][3];  // prefix (relative), mask, remaining rank
+    uint32_t red[2][kRangeThreads / kWave];
+};
+
 // Exact order statistics of the sampled binning keys (binary32 bits of the
 // depth or of the near-depth key; both are positive, so the bit order is the
-// value order). Both ranks are selected
-// together by radix passes of 11 bits over key - min(key), which spreads the
-// histogram even when all depths share their top bits.
-__global__ void __launch_bounds__(kRangeThreads) depth_range_kernel(const uint4* __restrict__ info,
-                                                                   const uint32_t* __restrict__ vis_ids,
-                                                                   const int64_t* __restrict__ counters, NearKey nk,
-                                                                   int S,
-                                                                   float p_lo, float p_hi, float pad, float znear,
-                                                                   float zfar, float* __restrict__ zrange) {
+// value order). Both ranks are selected together by radix passes of 11 bits
+// over key - min(key), which spreads the histogram even when all depths
+// share their top bits; while both ranks share their prefix (always in the
+// first pass) one histogram serves both. Run by one workgroup of
+// kRangeThreads threads.
+__device__ __forceinline__ void depth_range_block(const uint4* __restrict__ info, const uint32_t* __restrict__ vis_ids,
+                                                  const int64_t* __restrict__ counters, const NearKey& nk, int S,
+                                                  float p_lo, float p_hi, float pad, float znear, float zfar,
+                                                  float* __restrict__ zrange, RangeLds& R) {
 #pragma clang fp contract(off)
-    __shared__ uint32_t keys[kMaxSamples];
-    __shared__ uint32_t hist[2][kBinsR];
-    __shared__ uint32_t sel[2][3];  // prefix (relative), mask, remaining rank
-    __shared__ uint32_t red[2][kRangeThreads / kWave];
     const int64_t V = counters[1];
     const int n = (int)(V < S ? V : S);
     if (n == 0) {
@@ -100,7 +104,7 @@ __global__ void __launch_bounds__(kRangeThreads) depth_range_kernel(const uint4*
     for (int j = 0; j < kPer; ++j) {
         const int i = j * kRangeThreads + threadIdx.x;
         if (i < n) {
-            keys[i] = key[j];
+            R.keys[i] = key[j];
             lo = min(lo, key[j]);
             hi = max(hi, key[j]);
         }
@@ -109,64 +113,66 @@ __global__ void __launch_bounds__(kRangeThreads) depth_range_kernel(const uint4*
     hi = wave_max_u32(hi);
     const int w = threadIdx.x / kWave;
     if (lane() == 0) {
-        red[0][w] = lo;
-        red[1][w] = hi;
+        R.red[0][w] = lo;
+        R.red[1][w] = hi;
     }
     if (threadIdx.x < 2) {
         int64_t k = threadIdx.x == 0 ? (int64_t)floor((double)p_lo / 100.0 * (double)(n - 1))
                                      : (int64_t)ceil((double)p_hi / 100.0 * (double)(n - 1));
         if (k < 0) k = 0;
         if (k > n - 1) k = n - 1;
-        sel[threadIdx.x][0] = 0;
-        sel[threadIdx.x][1] = 0;
-        sel[threadIdx.x][2] = (uint32_t)k;
+        R.sel[threadIdx.x][0] = 0;
+        R.sel[threadIdx.x][1] = 0;
+        R.sel[threadIdx.x][2] = (uint32_t)k;
     }
     __syncthreads();
-    uint32_t kmin = red[0][0], kmax = red[1][0];
+    uint32_t kmin = R.red[0][0], kmax = R.red[1][0];
     for (int i = 1; i < kRangeThreads / kWave; ++i) {
-        kmin = min(kmin, red[0][i]);
-        kmax = max(kmax, red[1][i]);
+        kmin = min(kmin, R.red[0][i]);
+        kmax = max(kmax, R.red[1][i]);
     }
     const uint32_t span_bits = kmax - kmin;
     const int L = span_bits == 0 ? 0 : 32 - __builtin_clz(span_bits);
     for (int top = L; top > 0; top -= kDigit) {
         const int shift = top > kDigit ? top - kDigit : 0;
-        for (int i = threadIdx.x; i < 2 * kBinsR; i += kRangeThreads) hist[i / kBinsR][i % kBinsR] = 0;
+        const uint32_t pre0 = R.sel[0][0], msk0 = R.sel[0][1], pre1 = R.sel[1][0], msk1 = R.sel[1][1];
+        const bool same = pre0 == pre1 && msk0 == msk1;
+        for (int i = threadIdx.x; i < (same ? 1 : 2) * kBinsR; i += kRangeThreads) R.hist[i / kBinsR][i % kBinsR] = 0;
         __syncthreads();
-        const uint32_t pre0 = sel[0][0], msk0 = sel[0][1], pre1 = sel[1][0], msk1 = sel[1][1];
         for (int i = threadIdx.x; i < n; i += kRangeThreads) {
-            const uint32_t k = keys[i] - kmin;
+            const uint32_t k = R.keys[i] - kmin;
             const uint32_t d = (k >> shift) & (kBinsR - 1);
-            if ((k & msk0) == pre0) atomicAdd(&hist[0][d], 1u);
-            if ((k & msk1) == pre1) atomicAdd(&hist[1][d], 1u);
+            if ((k & msk0) == pre0) atomicAdd(&R.hist[0][d], 1u);
+            if (!same && (k & msk1) == pre1) atomicAdd(&R.hist[1][d], 1u);
         }
         __syncthreads();
         // waves 0 and 1 each resolve one rank: lane l owns 32 consecutive bins
         if (w < 2) {
+            const uint32_t* h = R.hist[same ? 0 : w];
             const int l = lane();
             constexpr int per = kBinsR / kWave;
             uint32_t own = 0;
-            for (int j = 0; j < per; ++j) own += hist[w][l * per + j];
+            for (int j = 0; j < per; ++j) own += h[l * per + j];
             const uint32_t inc = wave_inclusive_sum(own);
             const uint32_t exc = inc - own;
-            const uint32_t r = sel[w][2];
+            const uint32_t r = R.sel[w][2];
             if (exc <= r && r < inc) {
                 uint32_t rr = r - exc;
                 int d = l * per;
-                while (rr >= hist[w][d]) {
-                    rr -= hist[w][d];
+                while (rr >= h[d]) {
+                    rr -= h[d];
                     ++d;
                 }
-                sel[w][0] |= (uint32_t)d << shift;
-                sel[w][1] |= (uint32_t)(kBinsR - 1) << shift;
-                sel[w][2] = rr;
+                R.sel[w][0] |= (uint32_t)d << shift;
+                R.sel[w][1] |= (uint32_t)(kBinsR - 1) << shift;
+                R.sel[w][2] = rr;
             }
         }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        const float zlo = __uint_as_float(sel[0][0] + kmin);
-        const float zhi = __uint_as_float(sel[1][0] + kmin);
+        const float zlo = __uint_as_float(R.sel[0][0] + kmin);
+        const float zhi = __uint_as_float(R.sel[1][0] + kmin);
         const float diff = zhi - zlo;
         const float span = diff > 1e-6f ? diff : 1e-6f;
         const float padv = pad * span;
@@ -175,6 +181,15 @@ __global__ void __launch_bounds__(kRangeThreads) depth_range_kernel(const uint4*
         zrange[0] = a > znear ? a : znear;
         zrange[1] = b < zfar ? b : zfar;
     }
+}
+
+__global__ void __launch_bounds__(kRangeThreads) depth_range_kernel(const uint4* __restrict__ info,
+                                                                   const uint32_t* __restrict__ vis_ids,
+                                                                   const int64_t* __restrict__ counters, NearKey nk,
+                                                                   int S, float p_lo, float p_hi, float pad,
+                                                                   float znear, float zfar, float* __restrict__ zrange) {
+    __shared__ RangeLds R;
+    depth_range_block(info, vis_ids, counters, nk, S, p_lo, p_hi, pad, znear, zfar, zrange, R);
 }
 
 // Log-depth bin: the clamped log-space map floor(K u), realised with the
@@ -412,22 +427,41 @@ __global__ void __launch_bounds__(256) bin_scatter_kernel(const uint4* __restric
 //                  by segment, bin offsets, repair queues.
 // ---------------------------------------------------------------------------
 
-__global__ void __launch_bounds__(256) group_count_kernel(const uint4* __restrict__ info, int64_t n,
-                                                          const uint32_t* __restrict__ emit_off,
-                                                          const float* __restrict__ zrange, NearKey nk, GroupMap gm,
-                                                          int tiles_x, int tiles_y, uint32_t* __restrict__ gcount,
-                                                          uint32_t* __restrict__ wgbase) {
-    __shared__ WaveGauss wg[4];
-    __shared__ uint32_t hist[kMaxGroups];
-    for (int g = threadIdx.x; g < gm.G; g += 256) hist[g] = 0;
+constexpr int kCountThreads = kRangeThreads;
+
+struct CountLds {
+    uint32_t hist[kMaxGroups];
+    WaveGauss wg[kCountThreads / kWave];
+};
+
+// Workgroup 0: the depth range. Workgroups 1..: the group count of chunk
+// blockIdx.x - 1 (kGroupChunk Gaussians, 16 wavefronts).
+__global__ void __launch_bounds__(kCountThreads) group_count_kernel(const uint4* __restrict__ info, int64_t n,
+                                                                    const uint32_t* __restrict__ emit_off, GroupMap gm,
+                                                                    int tiles_x, int tiles_y,
+                                                                    uint32_t* __restrict__ gcount,
+                                                                    uint32_t* __restrict__ wgbase, RangeArgs ra) {
+    __shared__ union {
+        CountLds c;
+        RangeLds r;
+    } U;
+    if (blockIdx.x == 0) {
+        depth_range_block(info, ra.vis_ids, ra.counters, ra.nk, ra.S, ra.p_lo, ra.p_hi, ra.pad, ra.znear, ra.zfar,
+                          ra.zrange, U.r);
+        return;
+    }
+    const int64_t chunk = blockIdx.x - 1;
+    uint32_t* hist = U.c.hist;
+    for (int g = threadIdx.x; g < gm.G; g += kCountThreads) hist[g] = 0;
     __syncthreads();
     const int w = threadIdx.x / kWave;
-    const int64_t first = (int64_t)blockIdx.x * kGroupChunk;
+    constexpr int NW = kCountThreads / kWave;
+    const int64_t first = chunk * kGroupChunk;
     constexpr int R = kExpandRounds;
-    for (int it = 0; it < kGroupChunk / 256; ++it) {
-        const int64_t g0 = first + (int64_t)(it * 4 + w) * kWave;
-        for_wave_entries_at<R, false, false>(g0, info, n, emit_off, tiles_x, tiles_y, zrange, nk, gm.K, &wg[w],
-                                             [&](const Ent (&en)[R]) {
+    for (int it = 0; it < kGroupChunk / kCountThreads; ++it) {
+        const int64_t g0 = first + (int64_t)(it * NW + w) * kWave;
+        for_wave_entries_at<R, false, false>(g0, info, n, emit_off, tiles_x, tiles_y, nullptr, NearKey{}, gm.K,
+                                             &U.c.wg[w], [&](const Ent (&en)[R]) {
 #pragma unroll
                                                  for (int r = 0; r < R; ++r)
                                                      if (en[r].ok)
@@ -437,8 +471,8 @@ __global__ void __launch_bounds__(256) group_count_kernel(const uint4* __restric
                                              });
     }
     __syncthreads();
-    uint32_t* row = wgbase + (int64_t)blockIdx.x * gm.G;
-    for (int g = threadIdx.x; g < gm.G; g += 256) {
+    uint32_t* row = wgbase + chunk * gm.G;
+    for (int g = threadIdx.x; g < gm.G; g += kCountThreads) {
         const uint32_t h = hist[g];
         if (h) row[g] = atomicAdd(&gcount[g], h);
     }
@@ -844,11 +878,11 @@ GroupMap group_map(int64_t T, int K, int sub) {
 }
 
 hipError_t launch_group_count(const uint32_t* info, int64_t n, const uint32_t* emit_off, GroupMap gm, int tiles_x,
-                              int tiles_y, uint32_t* gcount, uint32_t* wgbase, hipStream_t s) {
-    if (n == 0) return hipSuccess;
-    const int64_t blocks = (n + kGroupChunk - 1) / kGroupChunk;
-    hipLaunchKernelGGL(group_count_kernel, dim3((unsigned)blocks), dim3(256), 0, s, reinterpret_cast<const uint4*>(info),
-                       n, emit_off, nullptr, NearKey{}, gm, tiles_x, tiles_y, gcount, wgbase);
+                              int tiles_y, uint32_t* gcount, uint32_t* wgbase, const RangeArgs& ra, hipStream_t s) {
+    static_assert(kGroupChunk % kCountThreads == 0, "whole wavefront slabs per chunk");
+    const int64_t chunks = (n + kGroupChunk - 1) / kGroupChunk;
+    hipLaunchKernelGGL(group_count_kernel, dim3((unsigned)(chunks + 1)), dim3(kCountThreads), 0, s,
+                       reinterpret_cast<const uint4*>(info), n, emit_off, gm, tiles_x, tiles_y, gcount, wgbase, ra);
     return hipGetLastError();
 }
 

@@ -360,9 +360,6 @@ tgs_status tgs_bin(const tgs_projected* pr, const tgs_camera* cam, const tgs_par
     const float zn = (float)cam->znear, zf = (float)cam->zfar;
     const NearKey nk{params->near_shift ? reinterpret_cast<const float4*>(pr->splats_dev) : nullptr,
                      params->shift_alpha, params->shift_gamma, zn > 1e-4f ? zn : 1e-4f, zf};
-    TGS_HIP(launch_depth_range(pr->info_dev, vis_ids, out->counters_dev, nk, S, params->p_lo, params->p_hi,
-                               params->pad, zn, zf, out->zrange_dev, s),
-            "depth range");
     if (L.gm.G > 0) {
         uint32_t* gcount = zero + L.gcount;
         uint32_t* group_off = (uint32_t*)(w + L.group_off);
@@ -370,7 +367,10 @@ tgs_status tgs_bin(const tgs_projected* pr, const tgs_camera* cam, const tgs_par
         uint64_t* tmp_pair = (uint64_t*)(w + L.tmp_pair);
         uint16_t* tmp_code = (uint16_t*)(w + L.tmp_code);
         uint32_t* group_order = (uint32_t*)(w + L.group_order);
-        TGS_HIP(launch_group_count(pr->info_dev, n, emit_off, L.gm, tiles_x, tiles_y, gcount, wgbase, s), "group count");
+        const RangeArgs ra{vis_ids, out->counters_dev, nk, S, params->p_lo, params->p_hi, params->pad, zn, zf,
+                           out->zrange_dev};
+        TGS_HIP(launch_group_count(pr->info_dev, n, emit_off, L.gm, tiles_x, tiles_y, gcount, wgbase, ra, s),
+                "depth range and group count");
         TGS_HIP(launch_group_scan(gcount, L.gm, group_off, group_order, s), "group scan");
         TGS_HIP(launch_group_scatter(pr->info_dev, n, emit_off, out->zrange_dev, nk, L.gm, tiles_x, tiles_y, group_off,
                                      wgbase, tmp_pair, tmp_code, cap, s),
@@ -396,6 +396,9 @@ tgs_status tgs_bin(const tgs_projected* pr, const tgs_camera* cam, const tgs_par
                     "tile order");
         return TGS_OK;
     }
+    TGS_HIP(launch_depth_range(pr->info_dev, vis_ids, out->counters_dev, nk, S, params->p_lo, params->p_hi,
+                               params->pad, zn, zf, out->zrange_dev, s),
+            "depth range");
     TGS_HIP(launch_bin_count(pr->info_dev, n, emit_off, out->zrange_dev, nk, sm, tiles_x, tiles_y, count, nseg,
                              entry_rank, cap, s),
             "bin count");

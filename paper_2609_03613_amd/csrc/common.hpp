@@ -294,6 +294,16 @@ hipError_t launch_emit_scan(const uint32_t* info, int64_t n, int tiles_x, int ti
 hipError_t launch_depth_range(const uint32_t* info, const uint32_t* vis_ids, const int64_t* counters, NearKey nk,
                               int S, float p_lo, float p_hi, float pad, float znear, float zfar, float* zrange,
                               hipStream_t s);
+// The arguments of the depth range, for the launch that runs it beside the
+// group count.
+struct RangeArgs {
+    const uint32_t* vis_ids;
+    const int64_t* counters;
+    NearKey nk;
+    int S;
+    float p_lo, p_hi, pad, znear, zfar;
+    float* zrange;
+};
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 
@@ -358,8 +368,10 @@ hipError_t launch_bin_scatter(const uint32_t* info, int64_t n, const uint32_t* e
 // the repair queues hold sub-segments: sub_off [S SB + 1] gets their
 // offsets and lists their ids (list stride list_stride); repaired[] and
 // counters[3] stay per segment.
+// The group count needs no bins; its first workgroup computes the depth
+// range (ra) meanwhile, which the group scatter then uses.
 hipError_t launch_group_count(const uint32_t* info, int64_t n, const uint32_t* emit_off, GroupMap gm, int tiles_x,
-                              int tiles_y, uint32_t* gcount, uint32_t* wgbase, hipStream_t s);
+                              int tiles_y, uint32_t* gcount, uint32_t* wgbase, const RangeArgs& ra, hipStream_t s);
 hipError_t launch_group_scan(const uint32_t* gcount, GroupMap gm, uint32_t* group_off, uint32_t* order,
                              hipStream_t s);
 hipError_t launch_group_scatter(const uint32_t* info, int64_t n, const uint32_t* emit_off, const float* zrange,
