@@ -212,7 +212,9 @@ def test_repair_mode_argument_errors():
     assert st == L.TGS_ERR_UNSUPPORTED and "uniform" in msg
     # the selection scan needs its own status words (one pair per 4096 segments)
     c = cam(1920, 1080)
-    base = lib.tgs_bin_workspace_size(1000, 5000, ctypes.byref(c), ctypes.byref(tg.Params().c()), L.ORDER_BINNED)
+    # (against exact repair on the same near-depth bins, which uses no sub-bins either)
+    base = lib.tgs_bin_workspace_size(1000, 5000, ctypes.byref(c), ctypes.byref(tg.Params(near_shift=True).c()),
+                                      L.ORDER_BINNED)
     rules = lib.tgs_bin_workspace_size(1000, 5000, ctypes.byref(c), ctypes.byref(tg.paper_params().c()),
                                        L.ORDER_BINNED)
     assert rules > base
