@@ -70,10 +70,35 @@ struct RangeLds {
 // share their top bits; while both ranks share their prefix (always in the
 // first pass) one histogram serves both. Run by one workgroup of
 // kRangeThreads threads.
+// Binning key of depth sample i < n = min(V, S): the visible Gaussian at
+// rank floor(i V / S) (rank i when V <= S).
+__device__ __forceinline__ uint32_t sample_key(const uint4* __restrict__ info, const uint32_t* __restrict__ vis_ids,
+                                               const NearKey& nk, int64_t V, int S, int i) {
+    const int64_t r = V <= S ? (int64_t)i : ((int64_t)i * V) / S;
+    const uint32_t g = vis_ids[r];
+    const uint32_t key = info[g].x;
+    return nk.splats ? nk(key, g) : key;
+}
+
+// The sample keys gathered by many workgroups into samples[0 .. n): the
+// random reads of one workgroup alone would take longer than the selection.
+__global__ void __launch_bounds__(256) range_samples_kernel(const uint4* __restrict__ info,
+                                                            const uint32_t* __restrict__ vis_ids,
+                                                            const int64_t* __restrict__ counters, NearKey nk, int S,
+                                                            uint32_t* __restrict__ samples) {
+#pragma clang fp contract(off)
+    const int64_t V = counters[1];
+    const int n = (int)(V < S ? V : S);
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) samples[i] = sample_key(info, vis_ids, nk, V, S, i);
+}
+
+// samples: the keys from range_samples_kernel, or null to gather them here.
 __device__ __forceinline__ void depth_range_block(const uint4* __restrict__ info, const uint32_t* __restrict__ vis_ids,
                                                   const int64_t* __restrict__ counters, const NearKey& nk, int S,
                                                   float p_lo, float p_hi, float pad, float znear, float zfar,
-                                                  float* __restrict__ zrange, RangeLds& R) {
+                                                  float* __restrict__ zrange, const uint32_t* __restrict__ samples,
+                                                  RangeLds& R) {
 #pragma clang fp contract(off)
     const int64_t V = counters[1];
     const int n = (int)(V < S ? V : S);
@@ -86,19 +111,11 @@ __device__ __forceinline__ void depth_range_block(const uint4* __restrict__ info
     }
     uint32_t lo = 0xFFFFFFFFu, hi = 0u;
     constexpr int kPer = kMaxSamples / kRangeThreads;
-    uint32_t gid[kPer], key[kPer];
+    uint32_t key[kPer];
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
         const int i = j * kRangeThreads + threadIdx.x;
-        const int64_t r = V <= S ? (int64_t)i : ((int64_t)i * V) / S;
-        gid[j] = i < n ? vis_ids[r] : 0u;
-    }
-#pragma unroll
-    for (int j = 0; j < kPer; ++j) key[j] = (j * kRangeThreads + (int)threadIdx.x) < n ? info[gid[j]].x : 0u;
-    if (nk.splats) {
-#pragma unroll
-        for (int j = 0; j < kPer; ++j)
-            if ((j * kRangeThreads + (int)threadIdx.x) < n) key[j] = nk(key[j], gid[j]);
+        key[j] = i >= n ? 0u : samples ? samples[i] : sample_key(info, vis_ids, nk, V, S, i);
     }
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
@@ -187,9 +204,10 @@ __global__ void __launch_bounds__(kRangeThreads) depth_range_kernel(const uint4*
                                                                    const uint32_t* __restrict__ vis_ids,
                                                                    const int64_t* __restrict__ counters, NearKey nk,
                                                                    int S, float p_lo, float p_hi, float pad,
-                                                                   float znear, float zfar, float* __restrict__ zrange) {
+                                                                   float znear, float zfar, float* __restrict__ zrange,
+                                                                   const uint32_t* __restrict__ samples) {
     __shared__ RangeLds R;
-    depth_range_block(info, vis_ids, counters, nk, S, p_lo, p_hi, pad, znear, zfar, zrange, R);
+    depth_range_block(info, vis_ids, counters, nk, S, p_lo, p_hi, pad, znear, zfar, zrange, samples, R);
 }
 
 // Log-depth bin: the clamped log-space map floor(K u), realised with the
@@ -447,7 +465,7 @@ __global__ void __launch_bounds__(kCountThreads) group_count_kernel(const uint4*
     } U;
     if (blockIdx.x == 0) {
         depth_range_block(info, ra.vis_ids, ra.counters, ra.nk, ra.S, ra.p_lo, ra.p_hi, ra.pad, ra.znear, ra.zfar,
-                          ra.zrange, U.r);
+                          ra.zrange, ra.samples, U.r);
         return;
     }
     const int64_t chunk = blockIdx.x - 1;
@@ -809,9 +827,12 @@ inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 
 
 hipError_t launch_depth_range(const uint32_t* info, const uint32_t* vis_ids, const int64_t* counters, NearKey nk,
                               int S, float p_lo, float p_hi, float pad, float znear, float zfar, float* zrange,
-                              hipStream_t s) {
-    hipLaunchKernelGGL(depth_range_kernel, dim3(1), dim3(kRangeThreads), 0, s, reinterpret_cast<const uint4*>(info),
-                       vis_ids, counters, nk, S, p_lo, p_hi, pad, znear, zfar, zrange);
+                              uint32_t* samples, hipStream_t s) {
+    const auto* in = reinterpret_cast<const uint4*>(info);
+    hipLaunchKernelGGL(range_samples_kernel, dim3((unsigned)((S + 255) / 256)), dim3(256), 0, s, in, vis_ids, counters,
+                       nk, S, samples);
+    hipLaunchKernelGGL(depth_range_kernel, dim3(1), dim3(kRangeThreads), 0, s, in, vis_ids, counters, nk, S, p_lo, p_hi,
+                       pad, znear, zfar, zrange, samples);
     return hipGetLastError();
 }
 
@@ -880,6 +901,9 @@ GroupMap group_map(int64_t T, int K, int sub) {
 hipError_t launch_group_count(const uint32_t* info, int64_t n, const uint32_t* emit_off, GroupMap gm, int tiles_x,
                               int tiles_y, uint32_t* gcount, uint32_t* wgbase, const RangeArgs& ra, hipStream_t s) {
     static_assert(kGroupChunk % kCountThreads == 0, "whole wavefront slabs per chunk");
+    if (ra.samples)
+        hipLaunchKernelGGL(range_samples_kernel, dim3((unsigned)((ra.S + 255) / 256)), dim3(256), 0, s,
+                           reinterpret_cast<const uint4*>(info), ra.vis_ids, ra.counters, ra.nk, ra.S, ra.samples);
     const int64_t chunks = (n + kGroupChunk - 1) / kGroupChunk;
     hipLaunchKernelGGL(group_count_kernel, dim3((unsigned)(chunks + 1)), dim3(kCountThreads), 0, s,
                        reinterpret_cast<const uint4*>(info), n, emit_off, gm, tiles_x, tiles_y, gcount, wgbase, ra);

@@ -107,7 +107,7 @@ struct Layout {
     size_t emit_off, vis_ids, zero, zero_words, status_emit_x, status_emit_y, status_bins, status_segs, status_sel,
         count,
         count_var, tile_seg, entry_rank, seg_lists, keys_in, vals_in, sort_tmp, sort_tmp_bytes, gcount, group_off,
-        wgbase, tmp_pair, tmp_code, group_order, sub_off, total;
+        wgbase, tmp_pair, tmp_code, group_order, sub_off, samples, total;
     int64_t list_stride;  // entries per repair bucket list
     GroupMap gm;  // gm.G > 0: grouped binning
 };
@@ -131,8 +131,9 @@ int end_bit_for(int64_t T) {
 // Workspace: [emit offsets][visible ids][zeroed region: control words,
 // scan status words (with rule-based repair also those of the selection
 // scan), then the group totals (grouped binning) or the per-XCD counts
-// (uniform K, group shape out of range)] followed by, for BINNED:
-// grouped: [sub-segment offsets (sub-bins only)][repair lists][group
+// (uniform K, group shape out of range)] followed by, for BINNED, [depth
+// samples] and then, grouped: [sub-segment offsets (sub-bins only)][repair
+// lists][group
 // offsets][group order][workgroup slice bases][grouped pairs][grouped
 // codes]; otherwise [entry ranks][repair lists] and, with per-tile bin
 // counts, [per-XCD counts][tile segments]. GLOBAL: [unsorted keys]
@@ -186,6 +187,7 @@ Layout layout(int64_t n, int64_t capacity, int64_t T, int K, int order, bool var
     }
     L.zero_words = z;
     L.zero = take(sizeof(uint32_t) * z);
+    if (order == TGS_ORDER_BINNED) L.samples = take(sizeof(uint32_t) * 8192);
     L.list_stride = nseg;
     if (grouped) {
         const size_t chunks = (size_t)((n + kGroupChunk - 1) / kGroupChunk);
@@ -368,7 +370,7 @@ tgs_status tgs_bin(const tgs_projected* pr, const tgs_camera* cam, const tgs_par
         uint16_t* tmp_code = (uint16_t*)(w + L.tmp_code);
         uint32_t* group_order = (uint32_t*)(w + L.group_order);
         const RangeArgs ra{vis_ids, out->counters_dev, nk, S, params->p_lo, params->p_hi, params->pad, zn, zf,
-                           out->zrange_dev};
+                           out->zrange_dev, (uint32_t*)(w + L.samples)};
         TGS_HIP(launch_group_count(pr->info_dev, n, emit_off, L.gm, tiles_x, tiles_y, gcount, wgbase, ra, s),
                 "depth range and group count");
         TGS_HIP(launch_group_scan(gcount, L.gm, group_off, group_order, s), "group scan");
@@ -397,7 +399,7 @@ tgs_status tgs_bin(const tgs_projected* pr, const tgs_camera* cam, const tgs_par
         return TGS_OK;
     }
     TGS_HIP(launch_depth_range(pr->info_dev, vis_ids, out->counters_dev, nk, S, params->p_lo, params->p_hi,
-                               params->pad, zn, zf, out->zrange_dev, s),
+                               params->pad, zn, zf, out->zrange_dev, (uint32_t*)(w + L.samples), s),
             "depth range");
     TGS_HIP(launch_bin_count(pr->info_dev, n, emit_off, out->zrange_dev, nk, sm, tiles_x, tiles_y, count, nseg,
                              entry_rank, cap, s),

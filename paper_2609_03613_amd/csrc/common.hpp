@@ -290,10 +290,11 @@ hipError_t launch_emit_scan(const uint32_t* info, int64_t n, int tiles_x, int ti
                             int64_t* counters, int64_t capacity, hipStream_t s);
 
 // Depth samples: the visible Gaussians at ranks floor(i V / S), i < S (all
-// of them when V <= S), read through vis_ids.
+// of them when V <= S), read through vis_ids; samples [S] is scratch for
+// their keys.
 hipError_t launch_depth_range(const uint32_t* info, const uint32_t* vis_ids, const int64_t* counters, NearKey nk,
                               int S, float p_lo, float p_hi, float pad, float znear, float zfar, float* zrange,
-                              hipStream_t s);
+                              uint32_t* samples, hipStream_t s);
 // The arguments of the depth range, for the launch that runs it beside the
 // group count.
 struct RangeArgs {
@@ -303,6 +304,7 @@ struct RangeArgs {
     int S;
     float p_lo, p_hi, pad, znear, zfar;
     float* zrange;
+    uint32_t* samples;  // [S] scratch for the gathered sample keys
 };
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
