@@ -71,30 +71,66 @@ __global__ void __launch_bounds__(kProjThreads) project_kernel(const float* __re
 #pragma clang fp contract(off)
     // The SH coefficients of the workgroup's Gaussians are one contiguous
     // block; stage it through LDS with coalesced 16-byte loads.
-    __shared__ float4 sh_lds[kProjThreads * kMaxShFloats / 4];
+    constexpr int kSink = kProjThreads * kMaxShFloats / 4;  // slot for the stores past the block's data
+    __shared__ float4 sh_lds[kSink + 1];
     const int nsh = (degree + 1) * (degree + 1);
     const int64_t g0 = (int64_t)blockIdx.x * kProjThreads;
+    const int64_t g = g0 + threadIdx.x;
+    // the Gaussian's own inputs, requested while the SH block is in flight
+    float in_m[3] = {0.f, 0.f, 0.f}, in_q[4] = {0.f, 0.f, 0.f, 0.f}, in_s[3] = {0.f, 0.f, 0.f}, in_l = 0.f;
+    auto prefetch = [&]() {
+        if (g >= n) return;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            in_m[k] = means[3 * g + k];
+            in_s[k] = log_scales[3 * g + k];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) in_q[k] = quats[4 * g + k];
+        in_l = logits[g];
+    };
+    bool fetched = false;
     {
         const int64_t cnt = min((int64_t)kProjThreads, n - g0) * nsh * 3;  // floats
         const float* src = sh + g0 * nsh * 3;
         if ((reinterpret_cast<uintptr_t>(src) & 15) == 0) {
+            // all loads of the block in flight at once, then the LDS stores
+            constexpr int kVecPerThread = kMaxShFloats / 4;
             const float4* s4 = reinterpret_cast<const float4*>(src);
-            for (int64_t i = threadIdx.x; i < cnt / 4; i += kProjThreads) sh_lds[i] = s4[i];
+            const int cnt4 = (int)(cnt / 4);
+            if (cnt4 > 0) {
+                // unconditional loads (clamped index), so that none waits for another
+                float4 v[kVecPerThread];
+#pragma unroll
+                for (int j = 0; j < kVecPerThread; ++j) {
+                    const int i = j * kProjThreads + (int)threadIdx.x;
+                    v[j] = s4[i < cnt4 ? i : cnt4 - 1];
+                }
+                prefetch();
+                fetched = true;
+                // unconditional stores too (past cnt4 into the sink slot),
+                // which keeps the loads from being moved next to them
+#pragma unroll
+                for (int j = 0; j < kVecPerThread; ++j) {
+                    const int i = j * kProjThreads + (int)threadIdx.x;
+                    sh_lds[i < cnt4 ? i : kSink] = v[j];
+                }
+            }
             float* f = reinterpret_cast<float*>(sh_lds);
-            for (int64_t i = (cnt / 4) * 4 + threadIdx.x; i < cnt; i += kProjThreads) f[i] = src[i];
+            for (int64_t i = (int64_t)cnt4 * 4 + threadIdx.x; i < cnt; i += kProjThreads) f[i] = src[i];
         } else {
             float* f = reinterpret_cast<float*>(sh_lds);
             for (int64_t i = threadIdx.x; i < cnt; i += kProjThreads) f[i] = src[i];
         }
     }
+    if (!fetched) prefetch();
     __syncthreads();
-    const int64_t g = g0 + threadIdx.x;
     if (g >= n) return;
     float4* out = splats + kSplatVec * g;
     const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
     uint4 inf = make_uint4(0u, 0u, 0u, 0u);
 
-    const double mx3 = means[3 * g], my3 = means[3 * g + 1], mz3 = means[3 * g + 2];
+    const double mx3 = in_m[0], my3 = in_m[1], mz3 = in_m[2];
     const double* R = cam.R;
     // camera-space point; the z expression is the ordering key's definition
     const double px = R[0] * mx3 + R[1] * my3 + R[2] * mz3 + cam.t[0];
@@ -102,7 +138,7 @@ __global__ void __launch_bounds__(kProjThreads) project_kernel(const float* __re
     const double z = R[6] * mx3 + R[7] * my3 + R[8] * mz3 + cam.t[2];
 
     bool ok = (z > cam.znear) && (z < cam.zfar);
-    double qw = quats[4 * g], qx = quats[4 * g + 1], qy = quats[4 * g + 2], qz = quats[4 * g + 3];
+    double qw = in_q[0], qx = in_q[1], qy = in_q[2], qz = in_q[3];
     const double qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
     ok = ok && (qn > 0.0) && isfinite(qn);
     double c00 = 0, c01 = 0, c11 = 0, det = 0, mxs = 0, mys = 0, o = 0, smax = 0;
@@ -114,7 +150,7 @@ __global__ void __launch_bounds__(kProjThreads) project_kernel(const float* __re
         double s2[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const double s = exp((double)log_scales[3 * g + k]);
+            const double s = exp((double)in_s[k]);
             s2[k] = s * s;
             smax = fmax(smax, s);
         }
@@ -143,7 +179,7 @@ __global__ void __launch_bounds__(kProjThreads) project_kernel(const float* __re
         ok = (det > 0.0) && isfinite(det);
         mxs = cam.fx * px / z + cam.cx;
         mys = cam.fy * py / z + cam.cy;
-        o = 1.0 / (1.0 + exp(-(double)logits[g]));
+        o = 1.0 / (1.0 + exp(-(double)in_l));
         ok = ok && (o >= 1.0 / 255.0) && isfinite(mxs) && isfinite(mys);
     }
     int x0 = 0, y0 = 0, x1 = 0, y1 = 0;
