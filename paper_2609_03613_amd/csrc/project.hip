@@ -60,6 +60,39 @@ __device__ __forceinline__ void sh_basis(double x, double y, double z, int degre
 
 constexpr int kProjThreads = 128;
 constexpr int kMaxShFloats = 16 * 3;
+constexpr int kShSink = kProjThreads * kMaxShFloats / 4;  // LDS slot for the stores past the block's data
+
+// Stages cnt floats at src (the SH block of the workgroup's Gaussians) into
+// sh_lds [kShSink + 1] with coalesced 16-byte loads, all in flight at once;
+// pre() issues the lane's other loads while they are. The loads use a
+// clamped index and the stores go to the sink slot past cnt, so no load is
+// made conditional (which would let the compiler move it next to its use).
+// The caller synchronises before reading sh_lds.
+template <class Pre>
+__device__ __forceinline__ void stage_sh_block(float4* sh_lds, const float* __restrict__ src, int64_t cnt, Pre&& pre) {
+    float* f = reinterpret_cast<float*>(sh_lds);
+    if ((reinterpret_cast<uintptr_t>(src) & 15) == 0 && cnt >= 4) {
+        constexpr int kVecPerThread = kMaxShFloats / 4;
+        const float4* s4 = reinterpret_cast<const float4*>(src);
+        const int cnt4 = (int)(cnt / 4);
+        float4 v[kVecPerThread];
+#pragma unroll
+        for (int j = 0; j < kVecPerThread; ++j) {
+            const int i = j * kProjThreads + (int)threadIdx.x;
+            v[j] = s4[i < cnt4 ? i : cnt4 - 1];
+        }
+        pre();
+#pragma unroll
+        for (int j = 0; j < kVecPerThread; ++j) {
+            const int i = j * kProjThreads + (int)threadIdx.x;
+            sh_lds[i < cnt4 ? i : kShSink] = v[j];
+        }
+        for (int64_t i = (int64_t)cnt4 * 4 + threadIdx.x; i < cnt; i += kProjThreads) f[i] = src[i];
+    } else {
+        pre();
+        for (int64_t i = threadIdx.x; i < cnt; i += kProjThreads) f[i] = src[i];
+    }
+}
 
 __global__ void __launch_bounds__(kProjThreads) project_kernel(const float* __restrict__ means,
                                                       const float* __restrict__ log_scales,
@@ -71,14 +104,13 @@ __global__ void __launch_bounds__(kProjThreads) project_kernel(const float* __re
 #pragma clang fp contract(off)
     // The SH coefficients of the workgroup's Gaussians are one contiguous
     // block; stage it through LDS with coalesced 16-byte loads.
-    constexpr int kSink = kProjThreads * kMaxShFloats / 4;  // slot for the stores past the block's data
-    __shared__ float4 sh_lds[kSink + 1];
+    __shared__ float4 sh_lds[kShSink + 1];
     const int nsh = (degree + 1) * (degree + 1);
     const int64_t g0 = (int64_t)blockIdx.x * kProjThreads;
     const int64_t g = g0 + threadIdx.x;
     // the Gaussian's own inputs, requested while the SH block is in flight
     float in_m[3] = {0.f, 0.f, 0.f}, in_q[4] = {0.f, 0.f, 0.f, 0.f}, in_s[3] = {0.f, 0.f, 0.f}, in_l = 0.f;
-    auto prefetch = [&]() {
+    stage_sh_block(sh_lds, sh + g0 * nsh * 3, min((int64_t)kProjThreads, n - g0) * nsh * 3, [&]() {
         if (g >= n) return;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
@@ -88,42 +120,7 @@ __global__ void __launch_bounds__(kProjThreads) project_kernel(const float* __re
 #pragma unroll
         for (int k = 0; k < 4; ++k) in_q[k] = quats[4 * g + k];
         in_l = logits[g];
-    };
-    bool fetched = false;
-    {
-        const int64_t cnt = min((int64_t)kProjThreads, n - g0) * nsh * 3;  // floats
-        const float* src = sh + g0 * nsh * 3;
-        if ((reinterpret_cast<uintptr_t>(src) & 15) == 0) {
-            // all loads of the block in flight at once, then the LDS stores
-            constexpr int kVecPerThread = kMaxShFloats / 4;
-            const float4* s4 = reinterpret_cast<const float4*>(src);
-            const int cnt4 = (int)(cnt / 4);
-            if (cnt4 > 0) {
-                // unconditional loads (clamped index), so that none waits for another
-                float4 v[kVecPerThread];
-#pragma unroll
-                for (int j = 0; j < kVecPerThread; ++j) {
-                    const int i = j * kProjThreads + (int)threadIdx.x;
-                    v[j] = s4[i < cnt4 ? i : cnt4 - 1];
-                }
-                prefetch();
-                fetched = true;
-                // unconditional stores too (past cnt4 into the sink slot),
-                // which keeps the loads from being moved next to them
-#pragma unroll
-                for (int j = 0; j < kVecPerThread; ++j) {
-                    const int i = j * kProjThreads + (int)threadIdx.x;
-                    sh_lds[i < cnt4 ? i : kSink] = v[j];
-                }
-            }
-            float* f = reinterpret_cast<float*>(sh_lds);
-            for (int64_t i = (int64_t)cnt4 * 4 + threadIdx.x; i < cnt; i += kProjThreads) f[i] = src[i];
-        } else {
-            float* f = reinterpret_cast<float*>(sh_lds);
-            for (int64_t i = threadIdx.x; i < cnt; i += kProjThreads) f[i] = src[i];
-        }
-    }
-    if (!fetched) prefetch();
+    });
     __syncthreads();
     if (g >= n) return;
     float4* out = splats + kSplatVec * g;
@@ -305,31 +302,29 @@ __global__ void __launch_bounds__(kProjThreads) sh_bwd_kernel(const float* __res
                                                              Cam cam, const float4* __restrict__ dsp,
                                                              float* __restrict__ d_means, float* __restrict__ d_sh) {
 #pragma clang fp contract(off)
-    __shared__ float4 sh_lds[kProjThreads * kMaxShFloats / 4];
+    __shared__ float4 sh_lds[kShSink + 1];
     const int nsh = (degree + 1) * (degree + 1);
     const int nf = nsh * 3;
     const int64_t g0 = (int64_t)blockIdx.x * kProjThreads;
     const int64_t cnt = min((int64_t)kProjThreads, n - g0) * nf;  // floats
     float* f = reinterpret_cast<float*>(sh_lds);
-    {
-        const float* src = sh + g0 * nf;
-        if ((reinterpret_cast<uintptr_t>(src) & 15) == 0) {
-            const float4* s4 = reinterpret_cast<const float4*>(src);
-            for (int64_t i = threadIdx.x; i < cnt / 4; i += kProjThreads) sh_lds[i] = s4[i];
-            for (int64_t i = (cnt / 4) * 4 + threadIdx.x; i < cnt; i += kProjThreads) f[i] = src[i];
-        } else {
-            for (int64_t i = threadIdx.x; i < cnt; i += kProjThreads) f[i] = src[i];
-        }
-    }
-    __syncthreads();
     const int64_t g = g0 + threadIdx.x;
+    float4 d1 = make_float4(0.f, 0.f, 0.f, 0.f), d2 = d1;
+    float in_m[3] = {0.f, 0.f, 0.f};
+    stage_sh_block(sh_lds, sh + g0 * nf, cnt, [&]() {
+        if (g >= n) return;
+        d1 = dsp[kGradWords / 4 * g + 1];
+        d2 = dsp[kGradWords / 4 * g + 2];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) in_m[k] = means[3 * g + k];
+    });
+    __syncthreads();
     if (g < n) {
         float* shg = f + threadIdx.x * nf;  // coefficients in, gradients out (in place)
-        const float4 d1 = dsp[kGradWords / 4 * g + 1], d2 = dsp[kGradWords / 4 * g + 2];
         const double dcol[3] = {d1.z, d1.w, d2.x};
         double gm[3] = {0.0, 0.0, 0.0};
         if (dcol[0] != 0.0 || dcol[1] != 0.0 || dcol[2] != 0.0) {
-            const double mx3 = means[3 * g], my3 = means[3 * g + 1], mz3 = means[3 * g + 2];
+            const double mx3 = in_m[0], my3 = in_m[1], mz3 = in_m[2];
             double ux = mx3 - cam.campos[0], uy = my3 - cam.campos[1], uz = mz3 - cam.campos[2];
             const double dn = sqrt(ux * ux + uy * uy + uz * uz);
             ux /= dn; uy /= dn; uz /= dn;
