@@ -6,6 +6,35 @@
 
 namespace tgs {
 
+// The value of lane l ^ m (m a power of two below 64, a constant after
+// unrolling). Distances 1, 2, 4 and 8 stay inside a row of 16 lanes and use
+// DPP moves (ALU, no LDS traffic): quad permutations for 1 and 2, a row
+// rotation by 8 for 8, and for 4 a rotation by 4 or 12 chosen by lane bit 2.
+// Larger distances use the LDS crossbar (ds_bpermute).
+__device__ __forceinline__ uint32_t xor_lane_u32(uint32_t v, int m) {
+    const int x = (int)v;
+    switch (m) {
+        case 1:
+            return (uint32_t)__builtin_amdgcn_update_dpp(x, x, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+        case 2:
+            return (uint32_t)__builtin_amdgcn_update_dpp(x, x, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+        case 4: {
+            const int r4 = __builtin_amdgcn_update_dpp(x, x, 0x124, 0xF, 0xF, false);   // row_ror:4
+            const int r12 = __builtin_amdgcn_update_dpp(x, x, 0x12C, 0xF, 0xF, false);  // row_ror:12
+            return (uint32_t)((lane() & 4) ? r4 : r12);
+        }
+        case 8:
+            return (uint32_t)__builtin_amdgcn_update_dpp(x, x, 0x128, 0xF, 0xF, false);  // row_ror:8
+        default:
+            return shfl_xor_u32(v, m);
+    }
+}
+
+__device__ __forceinline__ uint64_t xor_lane_u64(uint64_t v, int m) {
+    const uint32_t lo = xor_lane_u32((uint32_t)v, m), hi = xor_lane_u32((uint32_t)(v >> 32), m);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 // Bitonic network over groups of G lanes, one key per lane (the partner at
 // distance j < G is lane l ^ j, inside the group).
 template <int G>
@@ -14,7 +43,7 @@ __device__ __forceinline__ uint64_t group_bitonic(uint64_t v, int li) {
     for (int k = 2; k <= G; k <<= 1) {
 #pragma unroll
         for (int j = k >> 1; j > 0; j >>= 1) {
-            const uint64_t o = shfl_xor_u64(v, j);
+            const uint64_t o = xor_lane_u64(v, j);
             const bool up = (li & k) == 0, lower = (li & j) == 0;
             const uint64_t mn = v < o ? v : o, mx = v < o ? o : v;
             v = (lower == up) ? mn : mx;
@@ -23,10 +52,10 @@ __device__ __forceinline__ uint64_t group_bitonic(uint64_t v, int li) {
     return v;
 }
 
-// Segments of 65..512 keys: one wavefront, E = 2, 4 or 8 keys per lane in
-// registers (key i = k * 64 + lane in register k, padded with the maximum
-// key): bitonic network whose comparators at distance j < 64 exchange keys
-// across lanes and at j >= 64 between registers of the same lane.
+// Segments of 65..512 keys: one wavefront, E = 2, 4 or 8 consecutive keys
+// per lane in registers (key i = lane * E + k in register k, padded with
+// the maximum key): bitonic network whose comparators at distance j < E
+// stay inside a lane and at j >= E exchange register k with lane l ^ (j / E).
 template <int E>
 __device__ __forceinline__ void sort_wave_reg(uint64_t* __restrict__ seg, uint32_t s, uint32_t begin, uint32_t len,
                                               const RecordSink& rs) {
@@ -34,29 +63,29 @@ __device__ __forceinline__ void sort_wave_reg(uint64_t* __restrict__ seg, uint32
     uint64_t v[E];
 #pragma unroll
     for (int k = 0; k < E; ++k) {
-        const uint32_t i = (uint32_t)(k * kWave + l);
+        const uint32_t i = (uint32_t)(l * E + k);
         v[k] = i < len ? seg[i] : ~0ull;
     }
 #pragma unroll
     for (int kk = 2; kk <= E * kWave; kk <<= 1) {
 #pragma unroll
         for (int j = kk >> 1; j > 0; j >>= 1) {
-            if (j >= kWave) {
-                const int jr = j / kWave;
+            if (j < E) {
 #pragma unroll
                 for (int k = 0; k < E; ++k) {
-                    if (k & jr) continue;
-                    const bool up = ((k * kWave) & kk) == 0;
-                    const uint64_t a = v[k], b = v[k | jr];
+                    if (k & j) continue;
+                    const bool up = ((l * E + k) & kk) == 0;
+                    const uint64_t a = v[k], b = v[k | j];
                     const bool sw = (a > b) == up;
                     v[k] = sw ? b : a;
-                    v[k | jr] = sw ? a : b;
+                    v[k | j] = sw ? a : b;
                 }
             } else {
+                const int m = j / E;
 #pragma unroll
                 for (int k = 0; k < E; ++k) {
-                    const uint64_t o = shfl_xor_u64(v[k], j);
-                    const bool up = ((k * kWave + l) & kk) == 0, lower = (l & j) == 0;
+                    const uint64_t o = xor_lane_u64(v[k], m);
+                    const bool up = ((l * E + k) & kk) == 0, lower = (l & m) == 0;
                     const uint64_t mn = v[k] < o ? v[k] : o, mx = v[k] < o ? o : v[k];
                     v[k] = (lower == up) ? mn : mx;
                 }
@@ -65,7 +94,7 @@ __device__ __forceinline__ void sort_wave_reg(uint64_t* __restrict__ seg, uint32
     }
 #pragma unroll
     for (int k = 0; k < E; ++k) {
-        const uint32_t i = (uint32_t)(k * kWave + l);
+        const uint32_t i = (uint32_t)(l * E + k);
         if (i < len) {
             seg[i] = v[k];
             rs.put(s, begin + i, v[k]);
