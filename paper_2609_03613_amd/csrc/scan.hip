@@ -640,8 +640,11 @@ __global__ void __launch_bounds__(kTailThreads) group_scan_kernel(const uint32_t
         if (i0 + j < G) order[atomicAdd(&cbase[v[j] ? __builtin_clz(v[j]) : 32], 1u)] = (uint32_t)(i0 + j);
 }
 
-constexpr int kSortThreads = 1024;
-constexpr int kSortBatch = 8;  // entries per thread and sweep step, loaded before any is used
+#ifndef TGS_SORT_THREADS
+#define TGS_SORT_THREADS 512
+#endif
+constexpr int kSortThreads = TGS_SORT_THREADS;  // threads of a group-sort workgroup
+constexpr int kSortBatch = 8192 / kSortThreads;  // entries per thread and sweep step, loaded before any is used
 
 // One workgroup per group: its entries [group_off[g], group_off[g + 1])
 // (clipped to the capacity) are counted per code (segment, or sub-segment
