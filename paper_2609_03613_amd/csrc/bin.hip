@@ -496,6 +496,7 @@ __global__ void __launch_bounds__(kCountThreads) group_count_kernel(const uint4*
     }
 }
 
+template <bool VAR>
 __global__ void __launch_bounds__(256) group_scatter_kernel(const uint4* __restrict__ info, int64_t n,
                                                             const uint32_t* __restrict__ emit_off,
                                                             const float* __restrict__ zrange, NearKey nk, GroupMap gm,
@@ -516,18 +517,31 @@ __global__ void __launch_bounds__(256) group_scatter_kernel(const uint4* __restr
     constexpr int R = kExpandRounds;
     for (int it = 0; it < kGroupChunk / 256; ++it) {
         const int64_t g0 = first + (int64_t)(it * 4 + w) * kWave;
-        for_wave_entries_at<R, true, false>(
+        for_wave_entries_at<R, true, VAR>(
             g0, info, n, emit_off, tiles_x, tiles_y, zrange, nk, gm.K * gm.SB, &wg[w], [&](const Ent (&en)[R]) {
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     if (!en[r].ok) continue;
                     const uint32_t t = (uint32_t)(en[r].ty * tiles_x + en[r].tx);
                     const uint32_t grp = t / (uint32_t)gm.GT;
+                    uint32_t code;
+                    if (VAR) {
+                        // en.bin is the depth fraction: bin = frac >> shift, then
+                        // the next log2 SB_g bits are the sub-bin
+                        const uint2 ts = gm.tile_seg[t];
+                        const uint4 gi = gm.ginfo[grp];
+                        const uint64_t f = en[r].bin;
+                        const uint32_t seg = ts.x + (uint32_t)(f >> ts.y) - gi.x;
+                        const uint32_t sub = (uint32_t)(f >> (ts.y - gi.z)) & ((1u << gi.z) - 1u);
+                        code = (seg << gi.z) + sub;
+                    } else {
+                        // en.bin is the bin at K SB bins: (bin, sub) = (bin / SB, bin % SB)
+                        code = (t - grp * (uint32_t)gm.GT) * (uint32_t)(gm.K * gm.SB) + en[r].bin;
+                    }
                     const uint32_t pos = atomicAdd(&cursor[grp], 1u);
                     if (pos >= capacity) continue;
                     tmp_pair[pos] = ((uint64_t)en[r].key << 32) | (uint64_t)en[r].gid;
-                    // en.bin is the bin at K SB bins: (bin, sub) = (bin / SB, bin % SB)
-                    tmp_code[pos] = (uint16_t)((t - grp * (uint32_t)gm.GT) * (uint32_t)(gm.K * gm.SB) + en[r].bin);
+                    tmp_code[pos] = (uint16_t)code;
                 }
             });
     }
@@ -886,7 +900,7 @@ hipError_t launch_tile_order(const uint32_t* offsets, SegMap sm, int64_t T, uint
 }
 
 GroupMap group_map(int64_t T, int K, int sub) {
-    GroupMap gm{K, 1, 0, 0, 1};
+    GroupMap gm{K, 1, 0, 0, 1, T, nullptr, nullptr, nullptr};
     if (T <= 0 || K <= 0) return gm;
     int64_t gt = K >= kGroupSegTarget ? 1 : kGroupSegTarget / K;
     while ((T + gt - 1) / gt > kMaxGroups) gt *= 2;
@@ -895,6 +909,19 @@ GroupMap group_map(int64_t T, int K, int sub) {
     gm.G = (int)((T + gt - 1) / gt);
     gm.GS = (int)(gt * K);
     if (sub > 1 && (int64_t)gm.GS * sub <= kMaxGroupSegs) gm.SB = sub;
+    return gm;
+}
+
+GroupMap group_map_var(int64_t T, int K, int sub) {
+    GroupMap gm{K, 1, 0, 0, 1, T, nullptr, nullptr, nullptr};
+    if (T <= 0 || K <= 0 || K > kMaxGroupSegs) return gm;
+    int64_t gt = std::min<int64_t>(8, kMaxGroupSegs / K);
+    while ((T + gt - 1) / gt > kMaxGroups) gt *= 2;
+    if (gt * K > kMaxGroupSegs) return gm;
+    gm.GT = (int)gt;
+    gm.G = (int)((T + gt - 1) / gt);
+    gm.GS = (int)(gt * K);
+    gm.SB = sub > 1 ? sub : 1;
     return gm;
 }
 
@@ -916,9 +943,14 @@ hipError_t launch_group_scatter(const uint32_t* info, int64_t n, const uint32_t*
                                 hipStream_t s) {
     if (n == 0) return hipSuccess;
     const int64_t blocks = (n + kGroupChunk - 1) / kGroupChunk;
-    hipLaunchKernelGGL(group_scatter_kernel, dim3((unsigned)blocks), dim3(256), 0, s,
-                       reinterpret_cast<const uint4*>(info), n, emit_off, zrange, nk, gm, tiles_x, tiles_y, group_off,
-                       wgbase, tmp_pair, tmp_code, capacity);
+    if (gm.seg_base)
+        hipLaunchKernelGGL(group_scatter_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, s,
+                           reinterpret_cast<const uint4*>(info), n, emit_off, zrange, nk, gm, tiles_x, tiles_y,
+                           group_off, wgbase, tmp_pair, tmp_code, capacity);
+    else
+        hipLaunchKernelGGL(group_scatter_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, s,
+                           reinterpret_cast<const uint4*>(info), n, emit_off, zrange, nk, gm, tiles_x, tiles_y,
+                           group_off, wgbase, tmp_pair, tmp_code, capacity);
     return hipGetLastError();
 }
 

@@ -107,7 +107,7 @@ struct Layout {
     size_t emit_off, vis_ids, zero, zero_words, status_emit_x, status_emit_y, status_bins, status_segs, status_sel,
         count,
         count_var, tile_seg, entry_rank, seg_lists, keys_in, vals_in, sort_tmp, sort_tmp_bytes, gcount, group_off,
-        wgbase, tmp_pair, tmp_code, group_order, sub_off, samples, total;
+        wgbase, tmp_pair, tmp_code, group_order, sub_off, samples, ginfo, total;
     int64_t list_stride;  // entries per repair bucket list
     GroupMap gm;  // gm.G > 0: grouped binning
 };
@@ -145,8 +145,7 @@ int end_bit_for(int64_t T) {
 // bins of the depth itself (the sub-bin order is the depth order only when
 // the binning key is the sort key; the near-depth key is not).
 int sub_bins_for(const tgs_params* p, int order) {
-    const bool ok = order == TGS_ORDER_BINNED && p->repair == TGS_REPAIR_ALL && !p->packed && !p->per_tile_bins_dev &&
-                    !p->near_shift;
+    const bool ok = order == TGS_ORDER_BINNED && p->repair == TGS_REPAIR_ALL && !p->packed && !p->near_shift;
     return ok ? kSubBins : 1;
 }
 
@@ -174,7 +173,9 @@ Layout layout(int64_t n, int64_t capacity, int64_t T, int K, int order, bool var
     z += var ? 2 * (size_t)scan_blocks(T) : 0;
     L.status_sel = z;
     z += rules ? 2 * nbb : 0;
-    L.gm = order == TGS_ORDER_BINNED && !var ? group_map(T, K, sub) : GroupMap{K, 1, 0, 0, 1};
+    L.gm = order != TGS_ORDER_BINNED ? GroupMap{K, 1, 0, 0, 1, T, nullptr, nullptr, nullptr}
+           : var                     ? group_map_var(T, K, sub)
+                                     : group_map(T, K, sub);
     const bool grouped = L.gm.G > 0;
     if (grouped) {
         z = (z + 63) & ~(size_t)63;
@@ -202,6 +203,10 @@ Layout layout(int64_t n, int64_t capacity, int64_t T, int K, int order, bool var
         L.wgbase = take(sizeof(uint32_t) * (chunks > 0 ? chunks : 1) * (size_t)L.gm.G);
         L.tmp_pair = take(sizeof(uint64_t) * (size_t)capacity);
         L.tmp_code = take(sizeof(uint16_t) * (size_t)capacity);
+        if (var) {
+            L.tile_seg = take(sizeof(uint2) * (size_t)T);
+            L.ginfo = take(sizeof(uint4) * (size_t)L.gm.G);
+        }
     } else if (order == TGS_ORDER_BINNED) {
         L.entry_rank = take(sizeof(uint32_t) * (size_t)capacity);
         L.seg_lists = take(sizeof(uint32_t) * (size_t)kBuckets * (size_t)nseg);
@@ -357,12 +362,19 @@ tgs_status tgs_bin(const tgs_projected* pr, const tgs_camera* cam, const tgs_par
         TGS_HIP(launch_seg_base(params->per_tile_bins_dev, T, K, out->seg_base_dev, tile_seg, zero + kTicketSegs,
                                 (uint64_t*)(zero + L.status_segs), s),
                 "segment bases");
-        TGS_HIP(launch_fill_u32_dyn(count, 0u, nseg_dev, kCopies, (int64_t)kCopies * nseg, s), "clear counts");
+        if (L.gm.G == 0)
+            TGS_HIP(launch_fill_u32_dyn(count, 0u, nseg_dev, kCopies, (int64_t)kCopies * nseg, s), "clear counts");
     }
     const float zn = (float)cam->znear, zf = (float)cam->zfar;
     const NearKey nk{params->near_shift ? reinterpret_cast<const float4*>(pr->splats_dev) : nullptr,
                      params->shift_alpha, params->shift_gamma, zn > 1e-4f ? zn : 1e-4f, zf};
     if (L.gm.G > 0) {
+        GroupMap gm = L.gm;
+        if (var) {
+            gm.seg_base = out->seg_base_dev;
+            gm.tile_seg = tile_seg;
+            gm.ginfo = (uint4*)(w + L.ginfo);
+        }
         uint32_t* gcount = zero + L.gcount;
         uint32_t* group_off = (uint32_t*)(w + L.group_off);
         uint32_t* wgbase = (uint32_t*)(w + L.wgbase);
@@ -371,14 +383,14 @@ tgs_status tgs_bin(const tgs_projected* pr, const tgs_camera* cam, const tgs_par
         uint32_t* group_order = (uint32_t*)(w + L.group_order);
         const RangeArgs ra{vis_ids, out->counters_dev, nk, S, params->p_lo, params->p_hi, params->pad, zn, zf,
                            out->zrange_dev, (uint32_t*)(w + L.samples)};
-        TGS_HIP(launch_group_count(pr->info_dev, n, emit_off, L.gm, tiles_x, tiles_y, gcount, wgbase, ra, s),
+        TGS_HIP(launch_group_count(pr->info_dev, n, emit_off, gm, tiles_x, tiles_y, gcount, wgbase, ra, s),
                 "depth range and group count");
-        TGS_HIP(launch_group_scan(gcount, L.gm, group_off, group_order, s), "group scan");
-        TGS_HIP(launch_group_scatter(pr->info_dev, n, emit_off, out->zrange_dev, nk, L.gm, tiles_x, tiles_y, group_off,
+        TGS_HIP(launch_group_scan(gcount, gm, group_off, group_order, s), "group scan");
+        TGS_HIP(launch_group_scatter(pr->info_dev, n, emit_off, out->zrange_dev, nk, gm, tiles_x, tiles_y, group_off,
                                      wgbase, tmp_pair, tmp_code, cap, s),
                 "group scatter");
-        uint32_t* sub_off = L.gm.SB > 1 ? (uint32_t*)(w + L.sub_off) : nullptr;
-        TGS_HIP(launch_group_sort(tmp_pair, tmp_code, group_off, group_order, L.gm, nseg, cap, out->pairs_dev,
+        uint32_t* sub_off = gm.SB > 1 ? (uint32_t*)(w + L.sub_off) : nullptr;
+        TGS_HIP(launch_group_sort(tmp_pair, tmp_code, group_off, group_order, gm, nseg, cap, out->pairs_dev,
                                   out->offsets_dev, sub_off, seg_lists, L.list_stride, bucket_count, out->counters_dev,
                                   params->repair == TGS_REPAIR_ALL, out->repaired_dev, rs, s),
                 "group sort");

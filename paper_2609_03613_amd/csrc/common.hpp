@@ -207,8 +207,18 @@ struct RecordSink {
 // so the group sort leaves each segment ordered by sub-bin, which is the
 // depth order between sub-bins, and the repair sorts only the sub-segments;
 // entry code in the group = (tile in group K + bin) SB + sub.
+// Per-tile bin counts (seg_base != null): K is their bound, group g holds
+// segments seg_base[g GT] .. seg_base[min(T, g GT + GT)] - 1, and its
+// sub-bin count is chosen per group (ginfo[g] = {first segment, segments,
+// log2 sub-bins}, written by the group scan) so that its codes fit LDS; SB
+// is then the largest sub-bin count and sub-segment ids are first segment
+// SB + code.
 struct GroupMap {
     int K, GT, G, GS, SB;
+    int64_t T;
+    const uint32_t* seg_base;
+    const uint2* tile_seg;
+    uint4* ginfo;
 };
 #ifndef TGS_GROUP_SEGS
 #define TGS_GROUP_SEGS 512
@@ -226,6 +236,9 @@ constexpr int kGroupChunk = 2048;     // Gaussians per workgroup of the group co
 // would exceed kMaxGroupSegs (then the per-entry atomic path is used). SB =
 // sub (a power of two) when GS sub <= kMaxGroupSegs, else 1.
 GroupMap group_map(int64_t T, int K, int sub);
+// The same for per-tile bin counts bounded by K (a power of two): GT =
+// min(8, kMaxGroupSegs / K) tiles; sub-bins are chosen per group.
+GroupMap group_map_var(int64_t T, int K, int sub);
 
 // Per-tile bin counts: seg_base [T + 1] is the exclusive prefix sum of the
 // counts (powers of two), first(t) = seg_base[t], and the number of

@@ -600,9 +600,21 @@ __global__ void __launch_bounds__(kThreads) seg_base_kernel(const int32_t* __res
 // (one workgroup; G <= kMaxGroups = 8 per thread), and order[0 .. G) = the
 // groups by decreasing floor(log2(count)) (empty groups last; arbitrary
 // inside a class), so that the group sort starts the longest groups first.
-__global__ void __launch_bounds__(kTailThreads) group_scan_kernel(const uint32_t* __restrict__ gcount, int G,
+__global__ void __launch_bounds__(kTailThreads) group_scan_kernel(const uint32_t* __restrict__ gcount, GroupMap gm,
                                                                   uint32_t* __restrict__ group_off,
                                                                   uint32_t* __restrict__ order) {
+    const int G = gm.G;
+    // per-tile bin counts: each group's first segment, segment count and the
+    // most sub-bins (up to SB) whose codes fit the group sort's counters
+    if (gm.seg_base) {
+        for (int g = threadIdx.x; g < G; g += kTailThreads) {
+            const int64_t t0 = (int64_t)g * gm.GT, t1 = min(t0 + gm.GT, gm.T);
+            const uint32_t first = gm.seg_base[t0], segs = gm.seg_base[t1] - first;
+            uint32_t lg = 0;
+            while ((2u << lg) <= (uint32_t)gm.SB && (uint64_t)segs << (lg + 1) <= (uint64_t)kMaxGroupSegs) ++lg;
+            gm.ginfo[g] = make_uint4(first, segs, lg, 0u);
+        }
+    }
     static_assert(kMaxGroups <= 8 * kTailThreads, "eight groups per thread");
     constexpr int kClasses = 33;  // class 31 - floor(log2 count) for count > 0, 32 for empty
     __shared__ uint32_t lds[kTailThreads / kWave];
@@ -670,8 +682,21 @@ __global__ void __launch_bounds__(kSortThreads) group_sort_kernel(
     const int64_t cap = capacity;
     const uint32_t lo = (uint32_t)min((int64_t)group_off[g], cap);
     const uint32_t hi = (uint32_t)min((int64_t)group_off[g + 1], cap);
-    const int SB = gm.SB;
-    const int codes = gm.GS * SB;
+    // the group's segments [sbase, sbase + segs), sub-bins SB, codes segs SB
+    int64_t sbase, segs;
+    int SB;
+    if (gm.seg_base) {
+        const uint4 gi = gm.ginfo[g];
+        sbase = gi.x;
+        segs = gi.y;
+        SB = 1 << gi.z;
+        nseg = gm.seg_base[gm.T];
+    } else {
+        sbase = (int64_t)g * gm.GS;
+        segs = min((int64_t)gm.GS, nseg - sbase);
+        SB = gm.SB;
+    }
+    const int codes = (int)(segs * SB);
     const int per = (codes + NT - 1) / NT;  // codes per thread, <= kMaxPer
     for (int c = threadIdx.x; c < per * NT; c += NT) hist[c] = 0;
     if (threadIdx.x < kBuckets) lcount[threadIdx.x] = 0;
@@ -702,25 +727,25 @@ __global__ void __launch_bounds__(kSortThreads) group_sort_kernel(
         if (j < per) cur[threadIdx.x * per + j] = tex + ex[j];
     __syncthreads();
     const bool queue = queue_all && counters[2] == 0;
-    const int64_t sbase = (int64_t)g * gm.GS;  // first segment of the group
-    const int64_t cbase = sbase * SB;          // first code id of the group
-    const int64_t ncode = nseg * SB;
+    const int64_t cbase = sbase * gm.SB;  // id of the group's first code (ids of SB > 1 index sub_off)
     // repair queues per code (segments when SB == 1, sub-segments otherwise)
     int bk[kMaxPer];
 #pragma unroll
     for (int r = 0; r < kMaxPer; ++r) {
         const int c = r * NT + threadIdx.x;
         bk[r] = -1;
-        if (r < per && c < codes && cbase + c < ncode) {
-            if (SB > 1) sub_off[cbase + c] = lo + cur[c];
+        if (r < per && c < codes) {
+            if (gm.SB > 1) sub_off[cbase + c] = lo + cur[c];
             if (queue) bk[r] = bucket_of(hist[c]);
         }
     }
+    // the end of the group's last code (the next group's first offset when
+    // its ids follow directly)
+    if (gm.SB > 1 && threadIdx.x == 0) sub_off[cbase + codes] = hi;
     // offsets, repair flags and repaired entries per segment
     uint32_t queued = 0;
-    for (int c = threadIdx.x; c < gm.GS; c += NT) {
+    for (int c = threadIdx.x; c < segs; c += NT) {
         const int64_t sg = sbase + c;
-        if (sg >= nseg) break;
         uint32_t len = 0;
         for (int k = 0; k < SB; ++k) len += hist[c * SB + k];
         bin_off[sg] = lo + cur[c * SB];
@@ -728,10 +753,7 @@ __global__ void __launch_bounds__(kSortThreads) group_sort_kernel(
         if (repaired) repaired[sg] = rep ? 1 : 0;
         if (rep) queued += len;
     }
-    if (g == gm.G - 1 && threadIdx.x == 0) {
-        bin_off[nseg] = hi;
-        if (SB > 1) sub_off[ncode] = hi;
-    }
+    if (g == gm.G - 1 && threadIdx.x == 0) bin_off[nseg] = hi;
     queue_segments<kMaxPer, NT>(bk, cbase, list_stride, lcount, lbase, lists, bucket_count);
     if (queue) {
         const uint32_t qsum = block_sum_u32<NT>(queued, lds32);
@@ -808,7 +830,7 @@ hipError_t launch_repair_select(const uint32_t* bin_off, int64_t T, int K, float
 
 hipError_t launch_group_scan(const uint32_t* gcount, GroupMap gm, uint32_t* group_off, uint32_t* order,
                              hipStream_t s) {
-    hipLaunchKernelGGL(group_scan_kernel, dim3(1), dim3(kTailThreads), 0, s, gcount, gm.G, group_off, order);
+    hipLaunchKernelGGL(group_scan_kernel, dim3(1), dim3(kTailThreads), 0, s, gcount, gm, group_off, order);
     return hipGetLastError();
 }
 
