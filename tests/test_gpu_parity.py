@@ -129,10 +129,44 @@ def test_tail_segments_bit_exact():
     info = scenes.make_info(scenes.info_depth(info), rect)
     cam = cam_for(32, 16)
     ref = oracle.schedule(scenes.info_depth(info), rect, 2, 1, K=1)
-    _, _, _, bb = run_bin(splats, info, cam, "binned", tg.Params(num_bins=1))
-    assert np.array_equal(to_np(bb.pairs)[:n].view(np.uint64), ref["stream"])
-    assert np.array_equal(to_np(bb.offsets).view(np.uint32), ref["bin_offsets"])
+    # packed = 2 (block masks) keeps whole segments in the repair queues (no
+    # sub-bins), so the > 8192 segment reaches the global-memory tail sort;
+    # the default splits it into sub-segments first
+    for p in (tg.Params(num_bins=1, packed=2), tg.Params(num_bins=1)):
+        _, _, _, bb = run_bin(splats, info, cam, "binned", p)
+        assert np.array_equal(to_np(bb.pairs)[:n].view(np.uint64), ref["stream"])
+        assert np.array_equal(to_np(bb.offsets).view(np.uint32), ref["bin_offsets"])
     del rng
+
+
+@pytest.mark.parametrize("per_tile", [False, True])
+def test_per_entry_atomic_path_bit_exact(per_tile):
+    # 8-pixel tiles at 2560x1440 (57,600 tiles) with K = 1024: a group of
+    # tiles would exceed the group sort's 4096 counters, so binning takes the
+    # per-entry atomic count / offsets / scatter path instead
+    n, W, H, ts, kmax = 3000, 2560, 1440, 8, 1024
+    splats, info = scenes.random_splats(n, W, H, tile_size=ts, seed=41, tie_fraction=0.1, hidden_fraction=0.05,
+                                        max_sigma_px=6.0)
+    cam = cam_for(W, H, f=1000.0)
+    tx, ty = W // ts, H // ts
+    depth, rect = scenes.info_depth(info), scenes.info_rects(info)
+    s = torch.as_tensor(splats).to(dev())
+    i = torch.as_tensor(info.view(np.int32)).to(dev())
+    if per_tile:
+        kt = np.random.default_rng(5).choice([1, 2, 64, 256, 1024], size=tx * ty).astype(np.int32)
+        ref = oracle.schedule_tiles(depth, rect, tx, ty, kt, znear=cam["znear"], zfar=cam["zfar"])
+        p = tg.Params(tile_size=ts, num_bins=kmax, per_tile_bins=torch.as_tensor(kt).to(dev()))
+    else:
+        ref = oracle.schedule(depth, rect, tx, ty, K=kmax, znear=cam["znear"], zfar=cam["zfar"])
+        p = tg.Params(tile_size=ts, num_bins=kmax)
+    r = tg.Renderer(cam, p, device=dev())
+    b = r.bin(s, i, "binned")
+    torch.cuda.synchronize()
+    M = ref["M"]
+    S = len(ref["bin_offsets"]) - 1
+    assert b.num_entries == M
+    assert np.array_equal(to_np(b.offsets).view(np.uint32)[:S + 1], ref["bin_offsets"])
+    assert np.array_equal(to_np(b.pairs)[:M].view(np.uint64), ref["stream"])
 
 
 def test_empty_and_invisible():
