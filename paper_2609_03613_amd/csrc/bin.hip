@@ -551,44 +551,29 @@ __global__ void __launch_bounds__(256) group_scatter_kernel(const uint4* __restr
 // exact repair
 // ---------------------------------------------------------------------------
 
-// Segments of 2..64 keys: 64 / G segments per wavefront job, G lanes each
-// (job i: segments i * 64 / G + lane / G of the bucket list).
-template <int G>
-__device__ __forceinline__ void sort_group_job(const uint32_t* __restrict__ bin_off, const uint32_t* __restrict__ list,
-                                               uint32_t cnt, uint32_t job, uint64_t* __restrict__ pairs,
-                                               const RecordSink& rs) {
-    constexpr int SPW = kWave / G;
-    const int l = lane(), gi = l / G, li = l % G;
-    const uint32_t i = job * SPW + gi;
-    uint32_t s = 0, begin = 0, len = 0;
-    if (i < cnt) {
-        s = list[i];
+// A queued segment: its id s (for the records) and position. The lists
+// hold segment ids located by bin_off, or (DESC) {begin, length} pairs of
+// sub-segments, which carry no records.
+template <bool DESC>
+__device__ __forceinline__ void locate(const uint32_t* __restrict__ bin_off, uint2 entry, uint32_t& s,
+                                       uint32_t& begin, uint32_t& len) {
+    if (DESC) {
+        s = 0;
+        begin = entry.x;
+        len = entry.y;
+    } else {
+        s = entry.x;
         begin = bin_off[s];
         len = bin_off[s + 1] - begin;
     }
-    uint64_t v = (uint32_t)li < len ? pairs[begin + li] : ~0ull;
-    v = group_bitonic<G>(v, li);
-    if ((uint32_t)li < len) {
-        pairs[begin + li] = v;
-        rs.put(s, begin + li, v);
-    }
-}
-
-__device__ __forceinline__ void sort_wave_reg_job(const uint32_t* __restrict__ bin_off, uint32_t s,
-                                                  uint64_t* __restrict__ pairs, const RecordSink& rs) {
-    const uint32_t begin = bin_off[s], len = bin_off[s + 1] - begin;
-    if (len <= 2 * kWave)
-        sort_wave_reg<2>(pairs + begin, s, begin, len, rs);
-    else if (len <= 4 * kWave)
-        sort_wave_reg<4>(pairs + begin, s, begin, len, rs);
-    else
-        sort_wave_reg<8>(pairs + begin, s, begin, len, rs);
 }
 
 // Buckets 0..4 in one launch. The wavefront jobs of all five buckets form
-// one list, longest first (bucket 4: one 65..512 segment per job; buckets
-// 3..0: 1, 2, 4, 8 segments per job), which every wavefront strides through,
-// so that no wavefront gets a job of every bucket.
+// one list, longest first (bucket 4: one 65..512 segment per wavefront job,
+// 2, 4 or 8 keys per lane; buckets 3..0: 1, 2, 4, 8 segments of 64 / G
+// lanes each), which every wavefront strides through, so that no wavefront
+// gets a job of every bucket.
+template <bool DESC>
 __global__ void __launch_bounds__(256) sort_small_kernel(const uint32_t* __restrict__ bin_off,
                                                          const uint32_t* __restrict__ lists, int64_t nseg,
                                                          const uint32_t* __restrict__ bucket_count,
@@ -599,17 +584,64 @@ __global__ void __launch_bounds__(256) sort_small_kernel(const uint32_t* __restr
                    c4 = bucket_count[4];
     // job counts and their running sums, bucket 4 first
     const uint32_t j4 = c4, j3 = j4 + c3, j2 = j3 + (c2 + 1) / 2, j1 = j2 + (c1 + 3) / 4, j0 = j1 + (c0 + 7) / 8;
+    if (wid >= j0) return;
+    const int l = lane();
+    // bucket and list index of this lane's segment in job j
+    auto ref = [&](uint32_t j, int& b, uint32_t& i, bool& ok) {
+        uint32_t cnt;
+        if (j < j4) {
+            b = 4; i = j; cnt = c4;
+        } else if (j < j3) {
+            b = 3; i = j - j4; cnt = c3;
+        } else if (j < j2) {
+            b = 2; i = (j - j3) * 2 + (uint32_t)(l >> 5); cnt = c2;
+        } else if (j < j1) {
+            b = 1; i = (j - j2) * 4 + (uint32_t)(l >> 4); cnt = c1;
+        } else {
+            b = 0; i = (j - j1) * 8 + (uint32_t)(l >> 3); cnt = c0;
+        }
+        ok = i < cnt;
+    };
+    auto fetch = [&](uint32_t j) {
+        int b;
+        uint32_t i;
+        bool ok;
+        ref(j, b, i, ok);
+        if (!ok) return make_uint2(0u, 0u);
+        const int64_t at = (int64_t)b * nseg + i;
+        return DESC ? reinterpret_cast<const uint2*>(lists)[at] : make_uint2(lists[at], 0u);
+    };
     for (uint32_t j = wid; j < j0; j += waves) {
-        if (j < j4)
-            sort_wave_reg_job(bin_off, lists[4 * nseg + j], pairs, rs);
-        else if (j < j3)
-            sort_group_job<64>(bin_off, lists + 3 * nseg, c3, j - j4, pairs, rs);
-        else if (j < j2)
-            sort_group_job<32>(bin_off, lists + 2 * nseg, c2, j - j3, pairs, rs);
-        else if (j < j1)
-            sort_group_job<16>(bin_off, lists + 1 * nseg, c1, j - j2, pairs, rs);
-        else
-            sort_group_job<8>(bin_off, lists + 0 * nseg, c0, j - j1, pairs, rs);
+        int b;
+        uint32_t i;
+        bool ok;
+        ref(j, b, i, ok);
+        uint32_t sg = 0, begin = 0, len = 0;
+        if (ok) locate<DESC>(bin_off, fetch(j), sg, begin, len);
+        if (b == 4) {
+            if (len <= 2 * kWave)
+                sort_wave_reg<2, !DESC>(pairs + begin, sg, begin, len, rs);
+            else if (len <= 4 * kWave)
+                sort_wave_reg<4, !DESC>(pairs + begin, sg, begin, len, rs);
+            else
+                sort_wave_reg<8, !DESC>(pairs + begin, sg, begin, len, rs);
+        } else {
+            const int G = b == 3 ? 64 : b == 2 ? 32 : b == 1 ? 16 : 8;
+            const int li = l & (G - 1);
+            uint64_t v = (uint32_t)li < len ? pairs[begin + li] : ~0ull;
+            if (b == 3)
+                v = group_bitonic<64>(v, li);
+            else if (b == 2)
+                v = group_bitonic<32>(v, li);
+            else if (b == 1)
+                v = group_bitonic<16>(v, li);
+            else
+                v = group_bitonic<8>(v, li);
+            if ((uint32_t)li < len) {
+                pairs[begin + li] = v;
+                if (!DESC) rs.put(sg, begin + li, v);
+            }
+        }
     }
 }
 
@@ -622,17 +654,21 @@ __global__ void __launch_bounds__(256) sort_small_kernel(const uint32_t* __restr
 constexpr int kLargeThreads = 512;
 constexpr int kLargeCap = 8192;
 
+template <bool DESC>
 __global__ void __launch_bounds__(kLargeThreads) sort_large_kernel(const uint32_t* __restrict__ bin_off,
                                                                    const uint32_t* __restrict__ lists, int64_t nseg,
                                                                    const uint32_t* __restrict__ bucket_count,
                                                                    uint64_t* pairs, RecordSink rs) {
     __shared__ uint64_t buf[kLargeCap];
+    auto entry = [&](int bucket, uint32_t i) {
+        const int64_t at = (int64_t)bucket * nseg + i;
+        return DESC ? reinterpret_cast<const uint2*>(lists)[at] : make_uint2(lists[at], 0u);
+    };
     for (int bucket = 5; bucket <= 6; ++bucket) {
         const uint32_t cnt = bucket_count[bucket];
-        const uint32_t* list = lists + (int64_t)bucket * nseg;
         for (uint32_t i = blockIdx.x; i < cnt; i += gridDim.x) {
-            const uint32_t s = list[i];
-            const uint32_t begin = bin_off[s], len = bin_off[s + 1] - begin;
+            uint32_t s, begin, len;
+            locate<DESC>(bin_off, entry(bucket, i), s, begin, len);
             uint32_t P = 1;
             while (P < len) P <<= 1;
             for (uint32_t e = threadIdx.x; e < P; e += kLargeThreads) buf[e] = e < len ? pairs[begin + e] : ~0ull;
@@ -653,16 +689,15 @@ __global__ void __launch_bounds__(kLargeThreads) sort_large_kernel(const uint32_
             }
             for (uint32_t e = threadIdx.x; e < len; e += kLargeThreads) {
                 pairs[begin + e] = buf[e];
-                rs.put(s, begin + e, buf[e]);
+                if (!DESC) rs.put(s, begin + e, buf[e]);
             }
             __syncthreads();
         }
     }
     const uint32_t cnt = bucket_count[7];
-    const uint32_t* list = lists + 7 * nseg;
     for (uint32_t i = blockIdx.x; i < cnt; i += gridDim.x) {
-        const uint32_t s = list[i];
-        const uint32_t begin = bin_off[s], len = bin_off[s + 1] - begin;
+        uint32_t s, begin, len;
+        locate<DESC>(bin_off, entry(7, i), s, begin, len);
         uint64_t* a = pairs + begin;
         uint32_t P = 1;
         while (P < len) P <<= 1;
@@ -694,7 +729,8 @@ __global__ void __launch_bounds__(kLargeThreads) sort_large_kernel(const uint32_
                 __syncthreads();
             }
         }
-        for (uint32_t e = threadIdx.x; e < len; e += kLargeThreads) rs.put(s, begin + e, a[e]);
+        if (!DESC)
+            for (uint32_t e = threadIdx.x; e < len; e += kLargeThreads) rs.put(s, begin + e, a[e]);
         __syncthreads();
     }
 }
@@ -880,13 +916,20 @@ hipError_t launch_bin_scatter(const uint32_t* info, int64_t n, const uint32_t* e
 }
 
 hipError_t launch_repair(const uint32_t* bin_off, int64_t nseg, uint64_t* pairs, const uint32_t* seg_lists,
-                         const uint32_t* bucket_count, RecordSink rs, hipStream_t s) {
+                         const uint32_t* bucket_count, RecordSink rs, bool desc, hipStream_t s) {
     if (nseg == 0) return hipSuccess;
     const unsigned small_blocks = (unsigned)std::min<int64_t>(std::max<int64_t>((nseg + 31) / 32, 1), 4096);
-    hipLaunchKernelGGL(sort_small_kernel, dim3(small_blocks), dim3(256), 0, s, bin_off, seg_lists, nseg, bucket_count,
-                       pairs, rs);
-    hipLaunchKernelGGL(sort_large_kernel, dim3(512), dim3(kLargeThreads), 0, s, bin_off, seg_lists, nseg, bucket_count,
-                       pairs, rs);
+    if (desc) {
+        hipLaunchKernelGGL(sort_small_kernel<true>, dim3(small_blocks), dim3(256), 0, s, bin_off, seg_lists, nseg,
+                           bucket_count, pairs, rs);
+        hipLaunchKernelGGL(sort_large_kernel<true>, dim3(512), dim3(kLargeThreads), 0, s, bin_off, seg_lists, nseg,
+                           bucket_count, pairs, rs);
+    } else {
+        hipLaunchKernelGGL(sort_small_kernel<false>, dim3(small_blocks), dim3(256), 0, s, bin_off, seg_lists, nseg,
+                           bucket_count, pairs, rs);
+        hipLaunchKernelGGL(sort_large_kernel<false>, dim3(512), dim3(kLargeThreads), 0, s, bin_off, seg_lists, nseg,
+                           bucket_count, pairs, rs);
+    }
     return hipGetLastError();
 }
 

@@ -107,7 +107,7 @@ struct Layout {
     size_t emit_off, vis_ids, zero, zero_words, status_emit_x, status_emit_y, status_bins, status_segs, status_sel,
         count,
         count_var, tile_seg, entry_rank, seg_lists, keys_in, vals_in, sort_tmp, sort_tmp_bytes, gcount, group_off,
-        wgbase, tmp_pair, tmp_code, group_order, sub_off, samples, ginfo, total;
+        wgbase, tmp_pair, tmp_code, group_order, samples, ginfo, total;
     int64_t list_stride;  // entries per repair bucket list
     GroupMap gm;  // gm.G > 0: grouped binning
 };
@@ -132,14 +132,14 @@ int end_bit_for(int64_t T) {
 // scan status words (with rule-based repair also those of the selection
 // scan), then the group totals (grouped binning) or the per-XCD counts
 // (uniform K, group shape out of range)] followed by, for BINNED, [depth
-// samples] and then, grouped: [sub-segment offsets (sub-bins only)][repair
-// lists][group
-// offsets][group order][workgroup slice bases][grouped pairs][grouped
-// codes]; otherwise [entry ranks][repair lists] and, with per-tile bin
-// counts, [per-XCD counts][tile segments]. GLOBAL: [unsorted keys]
-// [unsorted ids][sort scratch]. The zeroed region is cleared by one fill at
-// the start of each tgs_bin; with per-tile bin counts only the first
-// kCopies * S words of the counts are cleared, by a fill sized on the
+// samples] and then, grouped: [repair lists (uint2 {begin, length} entries
+// with sub-bins)][group offsets][group order][workgroup slice bases]
+// [grouped pairs][grouped codes] and, with per-tile bin counts, [tile
+// segments][group info]; otherwise [entry ranks][repair lists] and, with
+// per-tile bin counts, [per-XCD counts][tile segments]. GLOBAL: [unsorted
+// keys][unsorted ids][sort scratch]. The zeroed region is cleared by one
+// fill at the start of each tgs_bin; with per-tile bin counts only the
+// first kCopies * S words of the counts are cleared, by a fill sized on the
 // device. K is the uniform bin count or the bound of the per-tile counts.
 // Sub-bins per bin of the grouped path: exact repair without records, and
 // bins of the depth itself (the sub-bin order is the depth order only when
@@ -192,12 +192,14 @@ Layout layout(int64_t n, int64_t capacity, int64_t T, int K, int order, bool var
     L.list_stride = nseg;
     if (grouped) {
         const size_t chunks = (size_t)((n + kGroupChunk - 1) / kGroupChunk);
+        size_t entry = sizeof(uint32_t);
         if (L.gm.SB > 1) {
-            // a queued sub-segment holds two or more of the at most capacity entries
+            // a queued sub-segment holds two or more of the at most capacity
+            // entries; it is queued as {begin, length}
             L.list_stride = std::min<int64_t>(nseg * L.gm.SB, capacity / 2 + 1);
-            L.sub_off = take(sizeof(uint32_t) * ((size_t)nseg * L.gm.SB + 1));
+            entry = sizeof(uint2);
         }
-        L.seg_lists = take(sizeof(uint32_t) * (size_t)kBuckets * (size_t)L.list_stride);
+        L.seg_lists = take(entry * (size_t)kBuckets * (size_t)L.list_stride);
         L.group_off = take(sizeof(uint32_t) * ((size_t)L.gm.G + 1));
         L.group_order = take(sizeof(uint32_t) * (size_t)L.gm.G);
         L.wgbase = take(sizeof(uint32_t) * (chunks > 0 ? chunks : 1) * (size_t)L.gm.G);
@@ -389,9 +391,8 @@ tgs_status tgs_bin(const tgs_projected* pr, const tgs_camera* cam, const tgs_par
         TGS_HIP(launch_group_scatter(pr->info_dev, n, emit_off, out->zrange_dev, nk, gm, tiles_x, tiles_y, group_off,
                                      wgbase, tmp_pair, tmp_code, cap, s),
                 "group scatter");
-        uint32_t* sub_off = gm.SB > 1 ? (uint32_t*)(w + L.sub_off) : nullptr;
         TGS_HIP(launch_group_sort(tmp_pair, tmp_code, group_off, group_order, gm, nseg, cap, out->pairs_dev,
-                                  out->offsets_dev, sub_off, seg_lists, L.list_stride, bucket_count, out->counters_dev,
+                                  out->offsets_dev, seg_lists, L.list_stride, bucket_count, out->counters_dev,
                                   params->repair == TGS_REPAIR_ALL, out->repaired_dev, rs, s),
                 "group sort");
         if (rules)
@@ -399,10 +400,10 @@ tgs_status tgs_bin(const tgs_projected* pr, const tgs_camera* cam, const tgs_par
                                          (uint64_t*)(zero + L.status_sel), zero + kSelCtl, seg_lists, bucket_count,
                                          out->counters_dev, out->repaired_dev, s),
                     "repair selection");
-        // with sub-bins the queues hold sub-segments, located by sub_off
+        // with sub-bins the queues hold sub-segment descriptors
         if (params->repair != TGS_REPAIR_NONE)
-            TGS_HIP(launch_repair(sub_off ? sub_off : out->offsets_dev, L.list_stride, out->pairs_dev, seg_lists,
-                                  bucket_count, rs, s),
+            TGS_HIP(launch_repair(out->offsets_dev, L.list_stride, out->pairs_dev, seg_lists, bucket_count, rs,
+                                  gm.SB > 1, s),
                     "repair");
         if (out->tile_order_dev)
             TGS_HIP(launch_tile_order(out->offsets_dev, sm, T, zero + kTileHist, out->tile_order_dev,
@@ -429,7 +430,7 @@ tgs_status tgs_bin(const tgs_projected* pr, const tgs_camera* cam, const tgs_par
                                count, nseg, entry_rank, out->pairs_dev, cap, rs, s),
             "bin scatter");
     if (params->repair != TGS_REPAIR_NONE)
-        TGS_HIP(launch_repair(out->offsets_dev, nseg, out->pairs_dev, seg_lists, bucket_count, rs, s), "repair");
+        TGS_HIP(launch_repair(out->offsets_dev, nseg, out->pairs_dev, seg_lists, bucket_count, rs, false, s), "repair");
     if (out->tile_order_dev)
         TGS_HIP(launch_tile_order(out->offsets_dev, sm, T, zero + kTileHist, out->tile_order_dev,
                                   params->split_entries, params->split_mean_factor, s),

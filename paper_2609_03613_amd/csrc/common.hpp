@@ -380,9 +380,8 @@ hipError_t launch_bin_scatter(const uint32_t* info, int64_t n, const uint32_t* e
 // group_sort: pairs in (tile, bin) order, bin_off
 // [S + 1] (S = T K), repair queues and repaired[] as launch_bin_offsets,
 // single-entry segments' records; bucket_count must be zero. With SB > 1
-// the repair queues hold sub-segments: sub_off [S SB + 1] gets their
-// offsets and lists their ids (list stride list_stride); repaired[] and
-// counters[3] stay per segment.
+// the repair queues hold sub-segments as uint2 {begin, length} (list stride
+// list_stride entries); repaired[] and counters[3] stay per segment.
 // The group count needs no bins; its first workgroup computes the depth
 // range (ra) meanwhile, which the group scatter then uses.
 hipError_t launch_group_count(const uint32_t* info, int64_t n, const uint32_t* emit_off, GroupMap gm, int tiles_x,
@@ -395,7 +394,7 @@ hipError_t launch_group_scatter(const uint32_t* info, int64_t n, const uint32_t*
                                 hipStream_t s);
 hipError_t launch_group_sort(const uint64_t* tmp_pair, const uint16_t* tmp_code, const uint32_t* group_off,
                              const uint32_t* order, GroupMap gm, int64_t nseg, int64_t capacity, uint64_t* pairs, uint32_t* bin_off,
-                             uint32_t* sub_off, uint32_t* lists, int64_t list_stride, uint32_t* bucket_count,
+                             uint32_t* lists, int64_t list_stride, uint32_t* bucket_count,
                              int64_t* counters, bool queue_all, uint8_t* repaired, RecordSink rs, hipStream_t s);
 
 // Per-tile bin counts: seg_base[t] = exclusive prefix sum of the bin counts
@@ -410,8 +409,10 @@ hipError_t launch_fill_u32_dyn(uint32_t* p, uint32_t v, const uint32_t* n_dev, i
                                hipStream_t s);
 
 // Sorts every queued segment by its 64-bit pairs and writes its records.
+// The lists hold segment ids located by bin_off (list stride nseg), or with
+// desc uint2 {begin, length} entries (sub-segments; no records).
 hipError_t launch_repair(const uint32_t* bin_off, int64_t nseg, uint64_t* pairs, const uint32_t* seg_lists,
-                         const uint32_t* bucket_count, RecordSink rs, hipStream_t s);
+                         const uint32_t* bucket_count, RecordSink rs, bool desc, hipStream_t s);
 
 // Tiles in descending order of their entry count (coarse: by bit length of
 // the count), so the heaviest tiles are dispatched first. order[T] = the

@@ -249,14 +249,14 @@ __host__ __device__ __forceinline__ int64_t blocks_for(int64_t n) {
     return b > 0 ? b : 1;
 }
 
-// Appends the segments with bk >= 0 (one per thread and round) to the
-// list of their repair bucket: aggregated per wavefront and per workgroup,
-// one global atomic per bucket and workgroup. lcount / lbase: LDS [kBuckets],
-// lcount zeroed before the first round.
-template <int R, int NT = kThreads>
-__device__ __forceinline__ void queue_segments(const int (&bk)[R], int64_t base, int64_t list_stride,
-                                               uint32_t* lcount, uint32_t* lbase, uint32_t* __restrict__ lists,
-                                               uint32_t* __restrict__ bucket_count) {
+// Appends value(r) of the items with bk[r] >= 0 (one per thread and round)
+// to the list of their repair bucket: aggregated per wavefront and per
+// workgroup, one global atomic per bucket and workgroup. lcount / lbase: LDS
+// [kBuckets], lcount zeroed before the first round.
+template <int R, int NT, class E, class V>
+__device__ __forceinline__ void queue_values(const int (&bk)[R], V&& value, int64_t list_stride, uint32_t* lcount,
+                                             uint32_t* lbase, E* __restrict__ lists,
+                                             uint32_t* __restrict__ bucket_count) {
     uint32_t slot[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -280,9 +280,18 @@ __device__ __forceinline__ void queue_segments(const int (&bk)[R], int64_t base,
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         if (bk[r] < 0) continue;
-        const int64_t sg = base + r * NT + threadIdx.x;
-        lists[(int64_t)bk[r] * list_stride + lbase[bk[r]] + slot[r]] = (uint32_t)sg;
+        lists[(int64_t)bk[r] * list_stride + lbase[bk[r]] + slot[r]] = value(r);
     }
+}
+
+// The same with the segment ids base + r NT + threadIdx.x as the values.
+template <int R, int NT = kThreads>
+__device__ __forceinline__ void queue_segments(const int (&bk)[R], int64_t base, int64_t list_stride,
+                                               uint32_t* lcount, uint32_t* lbase, uint32_t* __restrict__ lists,
+                                               uint32_t* __restrict__ bucket_count) {
+    queue_values<R, NT>(
+        bk, [&](int r) { return (uint32_t)(base + r * NT + threadIdx.x); }, list_stride, lcount, lbase, lists,
+        bucket_count);
 }
 
 // bin_off[s] = exclusive prefix of the summed copies (bin_off[nseg] = M);
@@ -662,13 +671,13 @@ constexpr int kSortBatch = 8192 / kSortThreads;  // entries per thread and sweep
 // (clipped to the capacity) are counted per code (segment, or sub-segment
 // when SB > 1) in LDS, the code offsets follow by a workgroup scan, and a
 // second sweep places every entry at its code offset + an LDS rank. Also
-// writes bin_off for the group's segments (and sub_off for its
-// sub-segments), queues the repair (sub-)segments (as bin_offsets_kernel),
+// writes bin_off for the group's segments, queues the repair segments (as
+// bin_offsets_kernel; sub-segments as {begin, length} when SB > 1),
 // and writes the records of single-entry segments.
 __global__ void __launch_bounds__(kSortThreads) group_sort_kernel(
     const uint64_t* __restrict__ tmp_pair, const uint16_t* __restrict__ tmp_code, const uint32_t* __restrict__ group_off,
     const uint32_t* __restrict__ order, GroupMap gm, int64_t nseg, int64_t capacity, uint64_t* __restrict__ pairs,
-    uint32_t* __restrict__ bin_off, uint32_t* __restrict__ sub_off, uint32_t* __restrict__ lists, int64_t list_stride,
+    uint32_t* __restrict__ bin_off, uint32_t* __restrict__ lists, int64_t list_stride,
     uint32_t* __restrict__ bucket_count, int64_t* __restrict__ counters, bool queue_all, uint8_t* __restrict__ repaired,
     RecordSink rs) {
     constexpr int NT = kSortThreads;
@@ -727,7 +736,7 @@ __global__ void __launch_bounds__(kSortThreads) group_sort_kernel(
         if (j < per) cur[threadIdx.x * per + j] = tex + ex[j];
     __syncthreads();
     const bool queue = queue_all && counters[2] == 0;
-    const int64_t cbase = sbase * gm.SB;  // id of the group's first code (ids of SB > 1 index sub_off)
+    const int64_t cbase = sbase * gm.SB;  // id of the group's first code
     // repair queues per code (segments when SB == 1, sub-segments otherwise)
     int bk[kMaxPer];
 #pragma unroll
@@ -735,13 +744,9 @@ __global__ void __launch_bounds__(kSortThreads) group_sort_kernel(
         const int c = r * NT + threadIdx.x;
         bk[r] = -1;
         if (r < per && c < codes) {
-            if (gm.SB > 1) sub_off[cbase + c] = lo + cur[c];
             if (queue) bk[r] = bucket_of(hist[c]);
         }
     }
-    // the end of the group's last code (the next group's first offset when
-    // its ids follow directly)
-    if (gm.SB > 1 && threadIdx.x == 0) sub_off[cbase + codes] = hi;
     // offsets, repair flags and repaired entries per segment
     uint32_t queued = 0;
     for (int c = threadIdx.x; c < segs; c += NT) {
@@ -754,7 +759,17 @@ __global__ void __launch_bounds__(kSortThreads) group_sort_kernel(
         if (rep) queued += len;
     }
     if (g == gm.G - 1 && threadIdx.x == 0) bin_off[nseg] = hi;
-    queue_segments<kMaxPer, NT>(bk, cbase, list_stride, lcount, lbase, lists, bucket_count);
+    if (gm.SB > 1)
+        // sub-segments are queued as {begin, length}: the repair needs no offset lookup
+        queue_values<kMaxPer, NT>(
+            bk,
+            [&](int r) {
+                const int c = r * NT + threadIdx.x;
+                return make_uint2(lo + cur[c], hist[c]);
+            },
+            list_stride, lcount, lbase, reinterpret_cast<uint2*>(lists), bucket_count);
+    else
+        queue_segments<kMaxPer, NT>(bk, cbase, list_stride, lcount, lbase, lists, bucket_count);
     if (queue) {
         const uint32_t qsum = block_sum_u32<NT>(queued, lds32);
         if (threadIdx.x == 0 && qsum)
@@ -836,10 +851,10 @@ hipError_t launch_group_scan(const uint32_t* gcount, GroupMap gm, uint32_t* grou
 
 hipError_t launch_group_sort(const uint64_t* tmp_pair, const uint16_t* tmp_code, const uint32_t* group_off,
                              const uint32_t* order, GroupMap gm, int64_t nseg, int64_t capacity, uint64_t* pairs, uint32_t* bin_off,
-                             uint32_t* sub_off, uint32_t* lists, int64_t list_stride, uint32_t* bucket_count,
+                             uint32_t* lists, int64_t list_stride, uint32_t* bucket_count,
                              int64_t* counters, bool queue_all, uint8_t* repaired, RecordSink rs, hipStream_t s) {
     hipLaunchKernelGGL(group_sort_kernel, dim3((unsigned)gm.G), dim3(kSortThreads), 0, s, tmp_pair, tmp_code, group_off, order, gm,
-                       nseg, capacity, pairs, bin_off, sub_off, lists, list_stride, bucket_count, counters, queue_all, repaired,
+                       nseg, capacity, pairs, bin_off, lists, list_stride, bucket_count, counters, queue_all, repaired,
                        rs);
     return hipGetLastError();
 }

@@ -56,7 +56,8 @@ __device__ __forceinline__ uint64_t group_bitonic(uint64_t v, int li) {
 // per lane in registers (key i = lane * E + k in register k, padded with
 // the maximum key): bitonic network whose comparators at distance j < E
 // stay inside a lane and at j >= E exchange register k with lane l ^ (j / E).
-template <int E>
+// REC: write the records of the sorted positions (rs.put).
+template <int E, bool REC>
 __device__ __forceinline__ void sort_wave_reg(uint64_t* __restrict__ seg, uint32_t s, uint32_t begin, uint32_t len,
                                               const RecordSink& rs) {
     const int l = lane();
@@ -97,7 +98,7 @@ __device__ __forceinline__ void sort_wave_reg(uint64_t* __restrict__ seg, uint32
         const uint32_t i = (uint32_t)(l * E + k);
         if (i < len) {
             seg[i] = v[k];
-            rs.put(s, begin + i, v[k]);
+            if (REC) rs.put(s, begin + i, v[k]);
         }
     }
 }
