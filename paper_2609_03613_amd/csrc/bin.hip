@@ -3,27 +3,30 @@
 // BINNED (the paper's tile-local path):
 //   depth_range  robust [zmin, zmax] from exact order statistics of the
 //                sampled depths (supplement, Algorithm "Robust depth-range
-//                estimation"), one workgroup, LDS radix select;
-//   grouped      (uniform K) the count / scan / scatter of Algorithm
-//                "Tile-local bin construction" in two levels: entries are
-//                counted and scattered per group of consecutive tiles with
-//                LDS counters and one global atomic per (workgroup, group),
-//                then each group is counting-sorted by (tile, bin) in LDS;
+//                estimation"): the samples are gathered by many workgroups,
+//                the LDS radix select runs in one workgroup (beside the
+//                group count when binning is grouped);
+//   grouped      the count / scan / scatter of Algorithm "Tile-local bin
+//                construction" in two levels: entries are counted and
+//                scattered per group of consecutive tiles with LDS counters
+//                and one global atomic per (workgroup, group), then each
+//                group is counting-sorted by (tile, bin[, sub-bin]) in LDS;
 //                per-entry global atomics on scattered counters run at
 //                ~25 G/s on this GPU and would dominate the stage;
-//   bin_count    (per-tile K, or group shapes out of range) log-depth bin of
-//                each Gaussian and an atomic count per (tile, bin); the
-//                returned old count is the entry's rank in its segment;
+//   bin_count    (group shapes beyond the LDS counters) log-depth bin of each
+//                Gaussian and an atomic count per (tile, bin) in the XCD's
+//                copy; the returned old count is the entry's rank;
 //   bin_scatter  pair = depth bits << 32 | id written at bin offset + rank;
 //   repair       every (tile, bin) segment with two or more entries is sorted
-//                by its unique 64-bit pair, routed by length to a wavefront
-//                register sort (<= 64), workgroup LDS sorts (<= 512, 2048,
-//                8192) or a global-memory tail sort (section "Repair for
+//                by its unique 64-bit pair (with sub-bins: every sub-segment),
+//                routed by length to wavefront register sorts (<= 64 in lane
+//                groups, <= 512 with 2-8 keys per lane), workgroup LDS sorts
+//                (<= 8192) or a global-memory tail sort (section "Repair for
 //                correctness": length buckets, local and broader exact
 //                paths);
 //   records      packed per-entry records written where each entry becomes
-//                final (the scatter for one-entry segments, the repair
-//                sorts for the others).
+//                final (the group sort or scatter for one-entry segments,
+//                the repair sorts for the others).
 // GLOBAL (the comparator): one (tile << 32 | depth bits, id) key-value pair
 // per entry, a device radix sort, and per-tile ranges by binary search.
 #include <algorithm>

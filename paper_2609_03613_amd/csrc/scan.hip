@@ -5,8 +5,10 @@
 // exchanged with agent-scope relaxed atomics), publishes its inclusive
 // prefix and writes its outputs. Items are read in coalesced rounds of 256.
 // Used for the per-Gaussian entry offsets (fused with the visible-Gaussian
-// list) and for the (tile, bin) counts -> bin offsets (fused with the
-// per-XCD bases and the repair-bucket classification).
+// list), the per-tile segment bases, the rule-based repair selection and, on
+// the per-entry atomic path, the (tile, bin) counts -> bin offsets (fused
+// with the per-XCD bases and the repair-bucket classification). Also here:
+// the group scan and the per-group counting sort of grouped binning.
 #include <algorithm>
 
 #include "common.hpp"
