@@ -213,8 +213,9 @@ typedef struct {
        tgs_bin writes the first segment of each tile, seg_base[T] = the
        number of segments S; offsets then holds S + 1 meaningful words (size
        it for T * num_bins + 1).
-   repaired [T * K] (optional, NULL = none; BINNED, uniform K): 1 for every
-       segment tgs_bin sorted, else 0. */
+   repaired [T * K] (optional, NULL = none; BINNED): 1 for every segment
+       tgs_bin sorted, else 0 (with per-tile bin counts the first S words,
+       in the segment numbering of seg_base). */
 typedef struct {
     int64_t capacity;
     uint64_t* keys_dev;
