@@ -160,18 +160,22 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Composites the cnt staged survivors of st[], two at a time (both read from
-// LDS before the first is evaluated).
+// Composites the cnt staged survivors of st[], four at a time (all four read
+// from LDS before the first is evaluated: more independent work per
+// wavefront hides the LDS latency better than more wavefronts would; eight
+// at a time costs too many registers).
 template <bool COUNT>
 __device__ __forceinline__ void composite_staged(Pix& p, float px, float py, const Staged* st, int cnt,
                                                  bool nostop = false) {
     int j = 0;
-    for (; j + 2 <= cnt; j += 2) {
-        const Staged s0 = st[j], s1 = st[j + 1];
+    for (; j + 4 <= cnt; j += 4) {
+        const Staged s0 = st[j], s1 = st[j + 1], s2 = st[j + 2], s3 = st[j + 3];
         blend<COUNT>(p, px, py, s0, nostop);
         blend<COUNT>(p, px, py, s1, nostop);
+        blend<COUNT>(p, px, py, s2, nostop);
+        blend<COUNT>(p, px, py, s3, nostop);
     }
-    if (j < cnt) blend<COUNT>(p, px, py, st[j], nostop);
+    for (; j < cnt; ++j) blend<COUNT>(p, px, py, st[j], nostop);
 }
 
 
