@@ -43,10 +43,12 @@ __device__ __forceinline__ uint64_t group_bitonic(uint64_t v, int li) {
     for (int k = 2; k <= G; k <<= 1) {
 #pragma unroll
         for (int j = k >> 1; j > 0; j >>= 1) {
+            // the lower lane of an ascending pair keeps the smaller key, the
+            // upper one the larger (descending: the reverse): keep the own
+            // key exactly when (own < other) says the same
             const uint64_t o = xor_lane_u64(v, j);
-            const bool up = (li & k) == 0, lower = (li & j) == 0;
-            const uint64_t mn = v < o ? v : o, mx = v < o ? o : v;
-            v = (lower == up) ? mn : mx;
+            const bool keep_min = ((li & k) == 0) == ((li & j) == 0);
+            v = ((v < o) == keep_min) ? v : o;
         }
     }
     return v;
@@ -86,9 +88,8 @@ __device__ __forceinline__ void sort_wave_reg(uint64_t* __restrict__ seg, uint32
 #pragma unroll
                 for (int k = 0; k < E; ++k) {
                     const uint64_t o = xor_lane_u64(v[k], m);
-                    const bool up = ((l * E + k) & kk) == 0, lower = (l & m) == 0;
-                    const uint64_t mn = v[k] < o ? v[k] : o, mx = v[k] < o ? o : v[k];
-                    v[k] = (lower == up) ? mn : mx;
+                    const bool keep_min = (((l * E + k) & kk) == 0) == ((l & m) == 0);
+                    v[k] = ((v[k] < o) == keep_min) ? v[k] : o;
                 }
             }
         }
