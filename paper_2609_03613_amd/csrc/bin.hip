@@ -166,28 +166,34 @@ __device__ __forceinline__ void depth_range_block(const uint4* __restrict__ info
             if (!same && (k & msk1) == pre1) atomicAdd(&R.hist[1][d], 1u);
         }
         __syncthreads();
-        // waves 0 and 1 each resolve one rank: lane l owns 32 consecutive bins
-        if (w < 2) {
-            const uint32_t* h = R.hist[same ? 0 : w];
-            const int l = lane();
-            constexpr int per = kBinsR / kWave;
-            uint32_t own = 0;
-            for (int j = 0; j < per; ++j) own += h[l * per + j];
-            const uint32_t inc = wave_inclusive_sum(own);
-            const uint32_t exc = inc - own;
-            const uint32_t r = R.sel[w][2];
-            if (exc <= r && r < inc) {
-                uint32_t rr = r - exc;
-                int d = l * per;
-                while (rr >= h[d]) {
-                    rr -= h[d];
-                    ++d;
-                }
-                R.sel[w][0] |= (uint32_t)d << shift;
-                R.sel[w][1] |= (uint32_t)(kBinsR - 1) << shift;
-                R.sel[w][2] = rr;
-            }
+        // both ranks are resolved by one workgroup scan over the bins:
+        // thread t owns bins 2t and 2t + 1 of each rank's histogram
+        static_assert(kBinsR == 2 * kRangeThreads, "two bins per thread");
+        const uint32_t* h0 = R.hist[0];
+        const uint32_t* h1 = R.hist[same ? 0 : 1];
+        const int t2 = 2 * (int)threadIdx.x;
+        const uint32_t a0 = h0[t2], a1 = h0[t2 + 1], b0 = h1[t2], b1 = h1[t2 + 1];
+        const uint32_t r0 = R.sel[0][2], r1 = R.sel[1][2];
+        const uint32_t ia = wave_inclusive_sum(a0 + a1), ib = wave_inclusive_sum(b0 + b1);
+        if (lane() == kWave - 1) {
+            R.red[0][w] = ia;
+            R.red[1][w] = ib;
         }
+        __syncthreads();
+        uint32_t ea = ia - (a0 + a1), eb = ib - (b0 + b1);
+        for (int i = 0; i < w; ++i) {
+            ea += R.red[0][i];
+            eb += R.red[1][i];
+        }
+        auto resolve = [&](int q, uint32_t e, uint32_t c0, uint32_t c1, uint32_t r) {
+            if (r < e || r >= e + c0 + c1) return;
+            const bool first = r < e + c0;
+            R.sel[q][0] |= (uint32_t)(first ? t2 : t2 + 1) << shift;
+            R.sel[q][1] |= (uint32_t)(kBinsR - 1) << shift;
+            R.sel[q][2] = first ? r - e : r - e - c0;
+        };
+        resolve(0, ea, a0, a1, r0);
+        resolve(1, eb, b0, b1, r1);
         __syncthreads();
     }
     if (threadIdx.x == 0) {
