@@ -663,11 +663,15 @@ __global__ void __launch_bounds__(256) sort_small_kernel(const uint32_t* __restr
 constexpr int kLargeThreads = 512;
 constexpr int kLargeCap = 8192;
 
+constexpr int kOrderBuckets = 33;  // tile order buckets: bit lengths 32 .. 0 of the entry count
+template <int NT>
+__device__ __forceinline__ void tile_place_chunk(const TileOrder& to, int64_t chunk, uint32_t* h, uint32_t* base);
+
 template <bool DESC>
 __global__ void __launch_bounds__(kLargeThreads) sort_large_kernel(const uint32_t* __restrict__ bin_off,
                                                                    const uint32_t* __restrict__ lists, int64_t nseg,
                                                                    const uint32_t* __restrict__ bucket_count,
-                                                                   uint64_t* pairs, RecordSink rs) {
+                                                                   uint64_t* pairs, RecordSink rs, TileOrder to) {
     __shared__ uint64_t buf[kLargeCap];
     auto entry = [&](int bucket, uint32_t i) {
         const int64_t at = (int64_t)bucket * nseg + i;
@@ -742,13 +746,19 @@ __global__ void __launch_bounds__(kLargeThreads) sort_large_kernel(const uint32_
             for (uint32_t e = threadIdx.x; e < len; e += kLargeThreads) rs.put(s, begin + e, a[e]);
         __syncthreads();
     }
+    // the tile order's placement, by the last workgroups (the first ones
+    // take the long segments)
+    if (to.order) {
+        __shared__ uint32_t oh[kOrderBuckets], ob[kOrderBuckets];
+        const int64_t chunks = (to.T + kLargeThreads - 1) / kLargeThreads;
+        for (int64_t c = (int64_t)gridDim.x - 1 - blockIdx.x; c < chunks; c += gridDim.x)
+            tile_place_chunk<kLargeThreads>(to, c, oh, ob);
+    }
 }
 
 // ---------------------------------------------------------------------------
 // heaviest-first tile order
 // ---------------------------------------------------------------------------
-
-constexpr int kOrderBuckets = 33;
 
 __device__ __forceinline__ int order_bucket(uint32_t c) { return c ? __builtin_clz(c) : 32; }
 
@@ -790,15 +800,18 @@ __global__ void __launch_bounds__(256) tile_hist_kernel(const uint32_t* __restri
     if (threadIdx.x < kOrderBuckets && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
 }
 
-__global__ void __launch_bounds__(256) tile_place_kernel(const uint32_t* __restrict__ offsets, SegMap sm, int64_t T,
-                                                         const uint32_t* __restrict__ hist, uint32_t* __restrict__ cursor,
-                                                         uint32_t* __restrict__ order, int split, int factor) {
-    __shared__ uint32_t h[kOrderBuckets], base[kOrderBuckets];
+// Placement of tiles [chunk NT, chunk NT + NT) by a workgroup of NT
+// threads; h, base: LDS [kOrderBuckets]. Ends with a barrier.
+template <int NT>
+__device__ __forceinline__ void tile_place_chunk(const TileOrder& to, int64_t chunk, uint32_t* h, uint32_t* base) {
+    const uint32_t* hist = to.hist;
+    uint32_t* cursor = to.hist + kOrderBuckets;
+    const int64_t T = to.T;
     if (threadIdx.x < kOrderBuckets) h[threadIdx.x] = 0;
     __syncthreads();
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = chunk * NT + threadIdx.x;
     const bool act = t < T;
-    const int b = act ? order_bucket(tile_count(offsets, sm, t)) : 0;
+    const int b = act ? order_bucket(tile_count(to.offsets, to.sm, t)) : 0;
     const uint32_t slot = wave_aggregated_add(h, b, act);
     __syncthreads();
     if (threadIdx.x < kOrderBuckets) {
@@ -807,8 +820,8 @@ __global__ void __launch_bounds__(256) tile_place_kernel(const uint32_t* __restr
         base[threadIdx.x] = h[threadIdx.x] ? start + atomicAdd(&cursor[threadIdx.x], h[threadIdx.x]) : 0u;
     }
     __syncthreads();
-    if (act) order[base[b] + slot] = (uint32_t)t;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (act) to.order[base[b] + slot] = (uint32_t)t;
+    if (chunk == 0 && threadIdx.x == 0) {
         // counts >= 2^h have a bit length > h: buckets 0 .. 31 - h. The
         // threshold is the smallest power of two >= split and >= `factor`
         // times the mean count of the non-empty tiles (only tiles far longer
@@ -818,14 +831,14 @@ __global__ void __launch_bounds__(256) tile_place_kernel(const uint32_t* __restr
         // the split set is a union of whole buckets (independent of the
         // order inside a bucket).
         uint32_t nh = 0, thr = 0;
-        if (split > 0) {
-            const uint64_t m = offsets[sm.first(T)];
+        if (to.split > 0) {
+            const uint64_t m = to.offsets[to.sm.first(T)];
             const uint64_t nonempty = (uint64_t)T - hist[32];
             // with fewer block wavefronts than the CUs hold (256 x 32), the
             // split parts run on otherwise idle SIMDs: no bound from the mean
             const bool filled = 4 * nonempty >= (uint64_t)kFillWaves;
-            const uint64_t rel = nonempty && filled ? (uint64_t)factor * m / nonempty : 0;
-            int h0 = 31 - __builtin_clz((uint32_t)split);
+            const uint64_t rel = nonempty && filled ? (uint64_t)to.factor * m / nonempty : 0;
+            int h0 = 31 - __builtin_clz((uint32_t)to.split);
             while (h0 < 31 && ((uint64_t)1 << h0) < rel) ++h0;
             for (int h = h0; h <= 31; ++h) {
                 uint32_t c = 0;
@@ -837,9 +850,15 @@ __global__ void __launch_bounds__(256) tile_place_kernel(const uint32_t* __restr
                 }
             }
         }
-        order[T] = nh;
-        order[T + 1] = thr;
+        to.order[T] = nh;
+        to.order[T + 1] = thr;
     }
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(256) tile_place_kernel(TileOrder to) {
+    __shared__ uint32_t h[kOrderBuckets], base[kOrderBuckets];
+    tile_place_chunk<256>(to, blockIdx.x, h, base);
 }
 
 // ---------------------------------------------------------------------------
@@ -925,19 +944,19 @@ hipError_t launch_bin_scatter(const uint32_t* info, int64_t n, const uint32_t* e
 }
 
 hipError_t launch_repair(const uint32_t* bin_off, int64_t nseg, uint64_t* pairs, const uint32_t* seg_lists,
-                         const uint32_t* bucket_count, RecordSink rs, bool desc, hipStream_t s) {
-    if (nseg == 0) return hipSuccess;
+                         const uint32_t* bucket_count, RecordSink rs, bool desc, const TileOrder& to, hipStream_t s) {
+    if (nseg == 0) return launch_tile_place(to, s);
     const unsigned small_blocks = (unsigned)std::min<int64_t>(std::max<int64_t>((nseg + 31) / 32, 1), 4096);
     if (desc) {
         hipLaunchKernelGGL(sort_small_kernel<true>, dim3(small_blocks), dim3(256), 0, s, bin_off, seg_lists, nseg,
                            bucket_count, pairs, rs);
         hipLaunchKernelGGL(sort_large_kernel<true>, dim3(512), dim3(kLargeThreads), 0, s, bin_off, seg_lists, nseg,
-                           bucket_count, pairs, rs);
+                           bucket_count, pairs, rs, to);
     } else {
         hipLaunchKernelGGL(sort_small_kernel<false>, dim3(small_blocks), dim3(256), 0, s, bin_off, seg_lists, nseg,
                            bucket_count, pairs, rs);
         hipLaunchKernelGGL(sort_large_kernel<false>, dim3(512), dim3(kLargeThreads), 0, s, bin_off, seg_lists, nseg,
-                           bucket_count, pairs, rs);
+                           bucket_count, pairs, rs, to);
     }
     return hipGetLastError();
 }
@@ -946,8 +965,14 @@ hipError_t launch_tile_order(const uint32_t* offsets, SegMap sm, int64_t T, uint
                              int factor, hipStream_t s) {
     if (T == 0) return hipSuccess;
     hipLaunchKernelGGL(tile_hist_kernel, dim3(grid_for(T, 256)), dim3(256), 0, s, offsets, sm, T, hist);
-    hipLaunchKernelGGL(tile_place_kernel, dim3(grid_for(T, 256)), dim3(256), 0, s, offsets, sm, T, hist,
-                       hist + kOrderBuckets, order, split, factor);
+    hipLaunchKernelGGL(tile_place_kernel, dim3(grid_for(T, 256)), dim3(256), 0, s,
+                       TileOrder{offsets, sm, T, hist, order, split, factor});
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_place(const TileOrder& to, hipStream_t s) {
+    if (to.T == 0 || !to.order) return hipSuccess;
+    hipLaunchKernelGGL(tile_place_kernel, dim3(grid_for(to.T, 256)), dim3(256), 0, s, to);
     return hipGetLastError();
 }
 

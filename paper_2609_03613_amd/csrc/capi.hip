@@ -391,9 +391,14 @@ tgs_status tgs_bin(const tgs_projected* pr, const tgs_camera* cam, const tgs_par
         TGS_HIP(launch_group_scatter(pr->info_dev, n, emit_off, out->zrange_dev, nk, gm, tiles_x, tiles_y, group_off,
                                      wgbase, tmp_pair, tmp_code, cap, s),
                 "group scatter");
+        // the group sort adds the tile-order histogram; the placement rides on
+        // the repair's long-segment launch
+        const TileOrder to{out->offsets_dev, sm, T, zero + kTileHist, out->tile_order_dev, params->split_entries,
+                           params->split_mean_factor};
         TGS_HIP(launch_group_sort(tmp_pair, tmp_code, group_off, group_order, gm, nseg, cap, out->pairs_dev,
                                   out->offsets_dev, seg_lists, L.list_stride, bucket_count, out->counters_dev,
-                                  params->repair == TGS_REPAIR_ALL, out->repaired_dev, rs, s),
+                                  params->repair == TGS_REPAIR_ALL, out->repaired_dev, rs,
+                                  to.order ? to.hist : nullptr, s),
                 "group sort");
         if (rules)
             TGS_HIP(launch_repair_select(out->offsets_dev, T, K, params->repair_budget, zero + kTicketSel,
@@ -403,12 +408,10 @@ tgs_status tgs_bin(const tgs_projected* pr, const tgs_camera* cam, const tgs_par
         // with sub-bins the queues hold sub-segment descriptors
         if (params->repair != TGS_REPAIR_NONE)
             TGS_HIP(launch_repair(out->offsets_dev, L.list_stride, out->pairs_dev, seg_lists, bucket_count, rs,
-                                  gm.SB > 1, s),
-                    "repair");
-        if (out->tile_order_dev)
-            TGS_HIP(launch_tile_order(out->offsets_dev, sm, T, zero + kTileHist, out->tile_order_dev,
-                                      params->split_entries, params->split_mean_factor, s),
-                    "tile order");
+                                  gm.SB > 1, to, s),
+                    "repair and tile order");
+        else
+            TGS_HIP(launch_tile_place(to, s), "tile order");
         return TGS_OK;
     }
     TGS_HIP(launch_depth_range(pr->info_dev, vis_ids, out->counters_dev, nk, S, params->p_lo, params->p_hi,
@@ -430,7 +433,9 @@ tgs_status tgs_bin(const tgs_projected* pr, const tgs_camera* cam, const tgs_par
                                count, nseg, entry_rank, out->pairs_dev, cap, rs, s),
             "bin scatter");
     if (params->repair != TGS_REPAIR_NONE)
-        TGS_HIP(launch_repair(out->offsets_dev, nseg, out->pairs_dev, seg_lists, bucket_count, rs, false, s), "repair");
+        TGS_HIP(launch_repair(out->offsets_dev, nseg, out->pairs_dev, seg_lists, bucket_count, rs, false, TileOrder{},
+                              s),
+                "repair");
     if (out->tile_order_dev)
         TGS_HIP(launch_tile_order(out->offsets_dev, sm, T, zero + kTileHist, out->tile_order_dev,
                                   params->split_entries, params->split_mean_factor, s),

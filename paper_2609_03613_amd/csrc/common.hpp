@@ -382,6 +382,9 @@ hipError_t launch_bin_scatter(const uint32_t* info, int64_t n, const uint32_t* e
 // single-entry segments' records; bucket_count must be zero. With SB > 1
 // the repair queues hold sub-segments as uint2 {begin, length} (list stride
 // list_stride entries); repaired[] and counters[3] stay per segment.
+// tile_hist != null: also adds each tile's bit-length bucket to the tile
+// order histogram tile_hist [33] (zero before), so that only the placement
+// half of the tile order is left (TileOrder).
 // The group count needs no bins; its first workgroup computes the depth
 // range (ra) meanwhile, which the group scatter then uses.
 hipError_t launch_group_count(const uint32_t* info, int64_t n, const uint32_t* emit_off, GroupMap gm, int tiles_x,
@@ -395,7 +398,8 @@ hipError_t launch_group_scatter(const uint32_t* info, int64_t n, const uint32_t*
 hipError_t launch_group_sort(const uint64_t* tmp_pair, const uint16_t* tmp_code, const uint32_t* group_off,
                              const uint32_t* order, GroupMap gm, int64_t nseg, int64_t capacity, uint64_t* pairs, uint32_t* bin_off,
                              uint32_t* lists, int64_t list_stride, uint32_t* bucket_count,
-                             int64_t* counters, bool queue_all, uint8_t* repaired, RecordSink rs, hipStream_t s);
+                             int64_t* counters, bool queue_all, uint8_t* repaired, RecordSink rs,
+                             uint32_t* tile_hist, hipStream_t s);
 
 // Per-tile bin counts: seg_base[t] = exclusive prefix sum of the bin counts
 // (each clamped to 1..kmax and rounded down to a power of two), seg_base[T]
@@ -408,11 +412,27 @@ hipError_t launch_seg_base(const int32_t* per_tile_bins, int64_t T, int kmax, ui
 hipError_t launch_fill_u32_dyn(uint32_t* p, uint32_t v, const uint32_t* n_dev, int mult, int64_t max_n,
                                hipStream_t s);
 
+// Placement half of the tile order (launch_tile_order below) over a
+// histogram that is already complete: hist [33] per bit-length bucket, then
+// the 33 placement cursors, zero. order == null: none.
+struct TileOrder {
+    const uint32_t* offsets;
+    SegMap sm;
+    int64_t T;
+    uint32_t* hist;
+    uint32_t* order;
+    int split, factor;
+};
+
 // Sorts every queued segment by its 64-bit pairs and writes its records.
 // The lists hold segment ids located by bin_off (list stride nseg), or with
-// desc uint2 {begin, length} entries (sub-segments; no records).
+// desc uint2 {begin, length} entries (sub-segments; no records). to.order !=
+// null: the last workgroups of the long-segment launch also place the tiles
+// (the sorts do not change the offsets).
 hipError_t launch_repair(const uint32_t* bin_off, int64_t nseg, uint64_t* pairs, const uint32_t* seg_lists,
-                         const uint32_t* bucket_count, RecordSink rs, bool desc, hipStream_t s);
+                         const uint32_t* bucket_count, RecordSink rs, bool desc, const TileOrder& to, hipStream_t s);
+// The placement half alone (tile order after a grouped sort without repair).
+hipError_t launch_tile_place(const TileOrder& to, hipStream_t s);
 
 // Tiles in descending order of their entry count (coarse: by bit length of
 // the count), so the heaviest tiles are dispatched first. order[T] = the

@@ -668,6 +668,7 @@ __global__ void __launch_bounds__(kTailThreads) group_scan_kernel(const uint32_t
 #endif
 constexpr int kSortThreads = TGS_SORT_THREADS;  // threads of a group-sort workgroup
 constexpr int kSortBatch = 8192 / kSortThreads;  // entries per thread and sweep step, loaded before any is used
+constexpr int kTileBuckets = 33;                  // tile order buckets: bit lengths 32 .. 0 of the entry count
 
 // One workgroup per group: its entries [group_off[g], group_off[g + 1])
 // (clipped to the capacity) are counted per code (segment, or sub-segment
@@ -681,7 +682,7 @@ __global__ void __launch_bounds__(kSortThreads) group_sort_kernel(
     const uint32_t* __restrict__ order, GroupMap gm, int64_t nseg, int64_t capacity, uint64_t* __restrict__ pairs,
     uint32_t* __restrict__ bin_off, uint32_t* __restrict__ lists, int64_t list_stride,
     uint32_t* __restrict__ bucket_count, int64_t* __restrict__ counters, bool queue_all, uint8_t* __restrict__ repaired,
-    RecordSink rs) {
+    RecordSink rs, uint32_t* __restrict__ tile_hist) {
     constexpr int NT = kSortThreads;
     constexpr int kMaxPer = kMaxGroupSegs / NT;
     constexpr uint32_t kNone = 0xFFFFFFFFu;
@@ -689,6 +690,7 @@ __global__ void __launch_bounds__(kSortThreads) group_sort_kernel(
     __shared__ uint32_t cur[kMaxGroupSegs];
     __shared__ uint32_t lds32[NT / kWave];
     __shared__ uint32_t lcount[kBuckets], lbase[kBuckets];
+    __shared__ uint32_t thist[kTileBuckets];
     const int g = (int)order[blockIdx.x];
     const int64_t cap = capacity;
     const uint32_t lo = (uint32_t)min((int64_t)group_off[g], cap);
@@ -711,6 +713,7 @@ __global__ void __launch_bounds__(kSortThreads) group_sort_kernel(
     const int per = (codes + NT - 1) / NT;  // codes per thread, <= kMaxPer
     for (int c = threadIdx.x; c < per * NT; c += NT) hist[c] = 0;
     if (threadIdx.x < kBuckets) lcount[threadIdx.x] = 0;
+    if (threadIdx.x < kTileBuckets) thist[threadIdx.x] = 0;
     __syncthreads();
     for (uint32_t base = lo; base < hi; base += NT * kSortBatch) {
         uint32_t c[kSortBatch];
@@ -737,6 +740,21 @@ __global__ void __launch_bounds__(kSortThreads) group_sort_kernel(
     for (int j = 0; j < kMaxPer; ++j)
         if (j < per) cur[threadIdx.x * per + j] = tex + ex[j];
     __syncthreads();
+    if (tile_hist) {
+        // entries per tile of the group (tiles g GT ..): difference of the
+        // exclusive prefixes at the tiles' first codes, as the bin offsets
+        // will give them; bucket = bit length of the count
+        const int64_t t0 = (int64_t)g * gm.GT, t1 = min(t0 + gm.GT, (int64_t)gm.T);
+        auto first_code = [&](int64_t t) -> uint32_t {
+            if (t >= t1) return hi - lo;
+            const int64_t c = gm.seg_base ? ((int64_t)gm.seg_base[t] - sbase) * SB : (t - t0) * gm.K * SB;
+            return c < codes ? cur[c] : hi - lo;
+        };
+        for (int64_t t = t0 + threadIdx.x; t < t1; t += NT) {
+            const uint32_t cnt = first_code(t + 1) - first_code(t);
+            atomicAdd(&thist[cnt ? __builtin_clz(cnt) : 32], 1u);
+        }
+    }
     const bool queue = queue_all && counters[2] == 0;
     const int64_t cbase = sbase * gm.SB;  // id of the group's first code
     // repair queues per code (segments when SB == 1, sub-segments otherwise)
@@ -799,6 +817,10 @@ __global__ void __launch_bounds__(kSortThreads) group_sort_kernel(
             if (rs.masks && hist[c[j]] == 1u) rs.put((uint32_t)(sbase + c[j]), p, pr[j]);
         }
     }
+    if (tile_hist) {
+        __syncthreads();
+        if (threadIdx.x < kTileBuckets && thist[threadIdx.x]) atomicAdd(&tile_hist[threadIdx.x], thist[threadIdx.x]);
+    }
 }
 
 __global__ void fill_u32_dyn_kernel(uint32_t* p, uint32_t v, const uint32_t* n_dev, int mult) {
@@ -854,10 +876,11 @@ hipError_t launch_group_scan(const uint32_t* gcount, GroupMap gm, uint32_t* grou
 hipError_t launch_group_sort(const uint64_t* tmp_pair, const uint16_t* tmp_code, const uint32_t* group_off,
                              const uint32_t* order, GroupMap gm, int64_t nseg, int64_t capacity, uint64_t* pairs, uint32_t* bin_off,
                              uint32_t* lists, int64_t list_stride, uint32_t* bucket_count,
-                             int64_t* counters, bool queue_all, uint8_t* repaired, RecordSink rs, hipStream_t s) {
+                             int64_t* counters, bool queue_all, uint8_t* repaired, RecordSink rs,
+                             uint32_t* tile_hist, hipStream_t s) {
     hipLaunchKernelGGL(group_sort_kernel, dim3((unsigned)gm.G), dim3(kSortThreads), 0, s, tmp_pair, tmp_code, group_off, order, gm,
                        nseg, capacity, pairs, bin_off, lists, list_stride, bucket_count, counters, queue_all, repaired,
-                       rs);
+                       rs, tile_hist);
     return hipGetLastError();
 }
 
