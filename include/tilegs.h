@@ -31,7 +31,8 @@
  *  - Pointers named *_dev are device pointers (hipMalloc'd or torch CUDA
  *    tensors); everything else is host memory. The caller owns every buffer,
  *    including the workspace; the library never allocates or frees device
- *    memory.
+ *    memory. Workspaces must be 256-byte aligned (hipMalloc and torch
+ *    allocations are); another start address fails with TGS_ERR_WORKSPACE.
  *  - Every call enqueues on `stream` (a hipStream_t, NULL = default stream)
  *    and returns without waiting, except tgs_bin with a non-NULL
  *    num_entries_host, which waits for the entry count.
@@ -62,7 +63,7 @@ typedef enum {
     TGS_ERR_CAPACITY = 2,    /* more entries than the binned buffers hold */
     TGS_ERR_HIP = 3,         /* a HIP runtime call or launch failed */
     TGS_ERR_UNSUPPORTED = 4, /* a valid but unimplemented option */
-    TGS_ERR_WORKSPACE = 5    /* workspace missing or smaller than required */
+    TGS_ERR_WORKSPACE = 5    /* workspace missing, smaller than required or misaligned */
 } tgs_status;
 
 /* Orders of the entry stream. */

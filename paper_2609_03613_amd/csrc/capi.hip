@@ -315,6 +315,7 @@ tgs_status tgs_bin(const tgs_projected* pr, const tgs_camera* cam, const tgs_par
     const Layout L = layout(n, cap, T, K, order, var, rules, sub_bins_for(params, order));
     if (!ws || ws_bytes < L.total)
         return fail(TGS_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
+    if (reinterpret_cast<uintptr_t>(ws) & 255) return fail(TGS_ERR_WORKSPACE, "workspace not 256-byte aligned");
     hipStream_t s = (hipStream_t)stream;
     char* w = (char*)ws;
     uint32_t* emit_off = (uint32_t*)(w + L.emit_off);
@@ -628,6 +629,7 @@ tgs_status tgs_rasterize_batch(int32_t num_views, const tgs_projected* pr, const
     a.tile_base[num_views] = (uint32_t)tiles;
     const size_t need = tgs_batch_workspace_size(num_views, cams, params);
     if (!ws || ws_bytes < need) return fail(TGS_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+    if (reinterpret_cast<uintptr_t>(ws) & 255) return fail(TGS_ERR_WORKSPACE, "workspace not 256-byte aligned");
     static int grid = 0;
     if (grid == 0) {
         int dev = 0, cus = 0, occ = 0;
@@ -689,6 +691,7 @@ tgs_status tgs_mlp_train_step(float* weights, float* velocity, const float* feat
     if (!isfinite(lr) || !isfinite(momentum)) return fail(TGS_ERR_INVALID_ARG, "lr and momentum must be finite");
     const size_t need = tgs_mlp_train_workspace_size(num_tiles);
     if (!ws || ws_bytes < need) return fail(TGS_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+    if (reinterpret_cast<uintptr_t>(ws) & 255) return fail(TGS_ERR_WORKSPACE, "workspace not 256-byte aligned");
     TGS_HIP(launch_mlp_train_step(weights, velocity, features, regret, num_tiles, lr, momentum, (float*)ws, loss,
                                   (hipStream_t)stream),
             "network training step");

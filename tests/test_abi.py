@@ -86,6 +86,10 @@ def test_bin_workspace_and_argument_errors():
     st, msg = status_of(lib.tgs_bin, ctypes.byref(pr), ctypes.byref(c), ctypes.byref(p), L.ORDER_BINNED, fake,
                         need - 1, ctypes.byref(b), None, None)
     assert st == L.TGS_ERR_WORKSPACE and "workspace" in msg
+    # a workspace that is large enough but not 256-byte aligned
+    st, msg = status_of(lib.tgs_bin, ctypes.byref(pr), ctypes.byref(c), ctypes.byref(p), L.ORDER_BINNED,
+                        ctypes.c_void_p(0x1010), need, ctypes.byref(b), None, None)
+    assert st == L.TGS_ERR_WORKSPACE and "aligned" in msg
     # the remaining cases pass no workspace, so that even a validation bug
     # stops at the workspace check instead of launching anything
     st, _ = status_of(lib.tgs_bin, ctypes.byref(pr), ctypes.byref(c), ctypes.byref(p), 7, None, 0,
