@@ -94,6 +94,13 @@ __device__ __forceinline__ void stage_sh_block(float4* sh_lds, const float* __re
     }
 }
 
+// SH3: each lane loads its Gaussian's 48 coefficients itself (twelve
+// 16-byte loads, no LDS). Without the 24 KB LDS block, which limited the
+// staged form to 3 wavefronts per SIMD, the registers allow 4, and the
+// extra wavefronts hide more of the load latency (68.8 -> 63.1 us for 1M
+// Gaussians). Other degrees (3, 12 or 27 floats per Gaussian, not 16-byte
+// multiples) use the staged form.
+template <bool DIRECT>
 __global__ void __launch_bounds__(kProjThreads) project_kernel(const float* __restrict__ means,
                                                       const float* __restrict__ log_scales,
                                                       const float* __restrict__ quats,
@@ -102,15 +109,24 @@ __global__ void __launch_bounds__(kProjThreads) project_kernel(const float* __re
                                                       Cam cam, float4* __restrict__ splats,
                                                       uint4* __restrict__ info) {
 #pragma clang fp contract(off)
-    // The SH coefficients of the workgroup's Gaussians are one contiguous
-    // block; stage it through LDS with coalesced 16-byte loads.
-    __shared__ float4 sh_lds[kShSink + 1];
+    // Staged form: the SH coefficients of the workgroup's Gaussians are one
+    // contiguous block, staged through LDS with coalesced 16-byte loads.
+    constexpr int kShVecs = kMaxShFloats / 4;
+    __shared__ float4 sh_lds[DIRECT ? 1 : kShSink + 1];
     const int nsh = (degree + 1) * (degree + 1);
     const int64_t g0 = (int64_t)blockIdx.x * kProjThreads;
     const int64_t g = g0 + threadIdx.x;
     // the Gaussian's own inputs, requested while the SH block is in flight
     float in_m[3] = {0.f, 0.f, 0.f}, in_q[4] = {0.f, 0.f, 0.f, 0.f}, in_s[3] = {0.f, 0.f, 0.f}, in_l = 0.f;
-    stage_sh_block(sh_lds, sh + g0 * nsh * 3, min((int64_t)kProjThreads, n - g0) * nsh * 3, [&]() {
+    float4 shv[DIRECT ? kShVecs : 1];
+    if constexpr (DIRECT) {
+        if (g < n) {
+            const float4* s4 = reinterpret_cast<const float4*>(sh + g * kMaxShFloats);
+#pragma unroll
+            for (int j = 0; j < kShVecs; ++j) shv[j] = s4[j];
+        }
+    }
+    auto own_inputs = [&]() {
         if (g >= n) return;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
@@ -120,8 +136,13 @@ __global__ void __launch_bounds__(kProjThreads) project_kernel(const float* __re
 #pragma unroll
         for (int k = 0; k < 4; ++k) in_q[k] = quats[4 * g + k];
         in_l = logits[g];
-    });
-    __syncthreads();
+    };
+    if constexpr (DIRECT) {
+        own_inputs();
+    } else {
+        stage_sh_block(sh_lds, sh + g0 * nsh * 3, min((int64_t)kProjThreads, n - g0) * nsh * 3, own_inputs);
+        __syncthreads();
+    }
     if (g >= n) return;
     float4* out = splats + kSplatVec * g;
     const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -208,11 +229,21 @@ __global__ void __launch_bounds__(kProjThreads) project_kernel(const float* __re
     double Y[16];
     sh_basis(dx, dy, dz, degree, Y);
     double col[3] = {0.0, 0.0, 0.0};
-    const float* shg = reinterpret_cast<const float*>(sh_lds) + threadIdx.x * nsh * 3;
-    for (int k = 0; k < nsh; ++k) {
-        col[0] += (double)shg[3 * k] * Y[k];
-        col[1] += (double)shg[3 * k + 1] * Y[k];
-        col[2] += (double)shg[3 * k + 2] * Y[k];
+    if constexpr (DIRECT) {
+        const float* shg = reinterpret_cast<const float*>(shv);
+#pragma unroll
+        for (int k = 0; k < kMaxShFloats / 3; ++k) {
+            col[0] += (double)shg[3 * k] * Y[k];
+            col[1] += (double)shg[3 * k + 1] * Y[k];
+            col[2] += (double)shg[3 * k + 2] * Y[k];
+        }
+    } else {
+        const float* shg = reinterpret_cast<const float*>(sh_lds) + threadIdx.x * nsh * 3;
+        for (int k = 0; k < nsh; ++k) {
+            col[0] += (double)shg[3 * k] * Y[k];
+            col[1] += (double)shg[3 * k + 1] * Y[k];
+            col[2] += (double)shg[3 * k + 2] * Y[k];
+        }
     }
     const float hx = (float)mxs, hy = (float)mys;
     out[0] = make_float4(hx, hy, (float)(mxs - (double)hx), (float)(mys - (double)hy));
@@ -522,9 +553,15 @@ hipError_t launch_project(const tgs_gaussians& g, const Cam& cam, float* splats,
     if (g.n == 0) return hipSuccess;
     const int block = kProjThreads;
     const int64_t grid = (g.n + block - 1) / block;
-    hipLaunchKernelGGL(project_kernel, dim3((unsigned)grid), dim3(block), 0, s, g.means_dev, g.log_scales_dev,
-                       g.quats_dev, g.logits_dev, g.sh_dev, g.n, g.sh_degree, cam,
-                       reinterpret_cast<float4*>(splats), reinterpret_cast<uint4*>(info));
+    const bool direct = g.sh_degree == 3 && (reinterpret_cast<uintptr_t>(g.sh_dev) & 15) == 0;
+    if (direct)
+        hipLaunchKernelGGL(project_kernel<true>, dim3((unsigned)grid), dim3(block), 0, s, g.means_dev,
+                           g.log_scales_dev, g.quats_dev, g.logits_dev, g.sh_dev, g.n, g.sh_degree, cam,
+                           reinterpret_cast<float4*>(splats), reinterpret_cast<uint4*>(info));
+    else
+        hipLaunchKernelGGL(project_kernel<false>, dim3((unsigned)grid), dim3(block), 0, s, g.means_dev,
+                           g.log_scales_dev, g.quats_dev, g.logits_dev, g.sh_dev, g.n, g.sh_degree, cam,
+                           reinterpret_cast<float4*>(splats), reinterpret_cast<uint4*>(info));
     return hipGetLastError();
 }
 
