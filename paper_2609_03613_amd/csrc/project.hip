@@ -328,30 +328,49 @@ __device__ __forceinline__ void sh_basis_vjp(double x, double y, double z, int d
 // Splitting keeps each kernel's binary64 register footprint small enough
 // for several wavefronts per SIMD. Gaussians whose gradient line is zero
 // (invisible or never composited) are skipped and get zero gradients.
+// DIRECT (SH3, 16-byte aligned coefficients and gradients): each lane loads
+// and stores its own 48 floats with 16-byte accesses, no LDS, as in the
+// forward.
+template <bool DIRECT>
 __global__ void __launch_bounds__(kProjThreads) sh_bwd_kernel(const float* __restrict__ means,
                                                              const float* __restrict__ sh, int64_t n, int degree,
                                                              Cam cam, const float4* __restrict__ dsp,
                                                              float* __restrict__ d_means, float* __restrict__ d_sh) {
 #pragma clang fp contract(off)
-    __shared__ float4 sh_lds[kShSink + 1];
-    const int nsh = (degree + 1) * (degree + 1);
+    constexpr int kShVecs = kMaxShFloats / 4;
+    __shared__ float4 sh_lds[DIRECT ? 1 : kShSink + 1];
+    const int nsh = DIRECT ? kMaxShFloats / 3 : (degree + 1) * (degree + 1);
     const int nf = nsh * 3;
     const int64_t g0 = (int64_t)blockIdx.x * kProjThreads;
     const int64_t cnt = min((int64_t)kProjThreads, n - g0) * nf;  // floats
-    float* f = reinterpret_cast<float*>(sh_lds);
     const int64_t g = g0 + threadIdx.x;
     float4 d1 = make_float4(0.f, 0.f, 0.f, 0.f), d2 = d1;
     float in_m[3] = {0.f, 0.f, 0.f};
-    stage_sh_block(sh_lds, sh + g0 * nf, cnt, [&]() {
+    float4 shv[DIRECT ? kShVecs : 1];
+    if constexpr (DIRECT) {
+        if (g < n) {
+            const float4* s4 = reinterpret_cast<const float4*>(sh + g * kMaxShFloats);
+#pragma unroll
+            for (int j = 0; j < kShVecs; ++j) shv[j] = s4[j];
+        }
+    }
+    auto own_inputs = [&]() {
         if (g >= n) return;
         d1 = dsp[kGradWords / 4 * g + 1];
         d2 = dsp[kGradWords / 4 * g + 2];
 #pragma unroll
         for (int k = 0; k < 3; ++k) in_m[k] = means[3 * g + k];
-    });
-    __syncthreads();
+    };
+    float* f = reinterpret_cast<float*>(sh_lds);
+    if constexpr (DIRECT) {
+        own_inputs();
+    } else {
+        stage_sh_block(sh_lds, sh + g0 * nf, cnt, own_inputs);
+        __syncthreads();
+    }
     if (g < n) {
-        float* shg = f + threadIdx.x * nf;  // coefficients in, gradients out (in place)
+        // coefficients in, gradients out (in place)
+        float* shg = DIRECT ? reinterpret_cast<float*>(shv) : f + threadIdx.x * nf;
         const double dcol[3] = {d1.z, d1.w, d2.x};
         double gm[3] = {0.0, 0.0, 0.0};
         if (dcol[0] != 0.0 || dcol[1] != 0.0 || dcol[2] != 0.0) {
@@ -391,9 +410,14 @@ __global__ void __launch_bounds__(kProjThreads) sh_bwd_kernel(const float* __res
         }
 #pragma unroll
         for (int k = 0; k < 3; ++k) d_means[3 * g + k] = (float)gm[k];
+        if constexpr (DIRECT) {
+            float4* d4 = reinterpret_cast<float4*>(d_sh + g * kMaxShFloats);
+#pragma unroll
+            for (int j = 0; j < kShVecs; ++j) d4[j] = shv[j];
+        }
     }
-    __syncthreads();
-    {
+    if constexpr (!DIRECT) {
+        __syncthreads();
         float* dst = d_sh + g0 * nf;
         if ((reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
             float4* d4 = reinterpret_cast<float4*>(dst);
@@ -570,8 +594,14 @@ hipError_t launch_project_backward(const tgs_gaussians& g, const Cam& cam, const
     if (g.n == 0) return hipSuccess;
     const int64_t grid = (g.n + kProjThreads - 1) / kProjThreads;
     const auto* dsp = reinterpret_cast<const float4*>(d_splats);
-    hipLaunchKernelGGL(sh_bwd_kernel, dim3((unsigned)grid), dim3(kProjThreads), 0, s, g.means_dev, g.sh_dev, g.n,
-                       g.sh_degree, cam, dsp, out.means_dev, out.sh_dev);
+    const bool direct = g.sh_degree == 3 && (reinterpret_cast<uintptr_t>(g.sh_dev) & 15) == 0 &&
+                        (reinterpret_cast<uintptr_t>(out.sh_dev) & 15) == 0;
+    if (direct)
+        hipLaunchKernelGGL(sh_bwd_kernel<true>, dim3((unsigned)grid), dim3(kProjThreads), 0, s, g.means_dev,
+                           g.sh_dev, g.n, g.sh_degree, cam, dsp, out.means_dev, out.sh_dev);
+    else
+        hipLaunchKernelGGL(sh_bwd_kernel<false>, dim3((unsigned)grid), dim3(kProjThreads), 0, s, g.means_dev,
+                           g.sh_dev, g.n, g.sh_degree, cam, dsp, out.means_dev, out.sh_dev);
     hipLaunchKernelGGL(geom_bwd_kernel, dim3((unsigned)((g.n + 255) / 256)), dim3(256), 0, s, g.means_dev,
                        g.log_scales_dev, g.quats_dev, g.logits_dev, g.n, cam, dsp, out.means_dev, out.log_scales_dev,
                        out.quats_dev, out.logits_dev);
