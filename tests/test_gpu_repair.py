@@ -161,6 +161,13 @@ def test_no_repair(case):
     assert not to_np(b.repaired)[:T * K].any()
     assert int(to_np(b.counters)[3]) == 0
     check_segments(to_np(b.pairs)[:ref["M"]].view(np.uint64), ref, np.zeros(T * K, np.uint8))
+    # without a repair launch the tile order is placed by its own launch: a
+    # permutation of the tiles in non-increasing bit length of their counts
+    order = to_np(b.tile_order).view(np.uint32)[:T]
+    assert np.array_equal(np.sort(order), np.arange(T))
+    cnt = np.diff(ref["bin_offsets"][::K].astype(np.int64))
+    blen = np.where(cnt[order] > 0, np.floor(np.log2(np.maximum(cnt[order], 1))) + 1, 0)
+    assert np.all(np.diff(blen) <= 0)
 
 
 def test_paper_mode_image():
