@@ -20,6 +20,11 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kRounds = 8;
 constexpr int kPerBlock = kThreads * kRounds;
+#ifndef TGS_EMIT_ROUNDS
+#define TGS_EMIT_ROUNDS 16
+#endif
+constexpr int kEmitRounds = TGS_EMIT_ROUNDS;  // items per thread of the emit scan
+constexpr int kEmitPerBlock = kThreads * kEmitRounds;
 constexpr uint64_t kFlagAgg = 1ull << 62;
 constexpr uint64_t kFlagInc = 2ull << 62;
 constexpr uint64_t kValMask = (1ull << 62) - 1;
@@ -164,8 +169,8 @@ __device__ __forceinline__ uint64_t block_excl_u64(uint64_t v, uint64_t* lds, ui
 // emit_off[g] (exclusive prefix of x), vis_ids[rank] = g for visible g, and
 // counters[0] = M, counters[1] = V, counters[2] = M > capacity.
 // Items are loaded and stored in coalesced rounds; in between they pass
-// through LDS so that each thread scans kRounds consecutive items and one
-// workgroup scan of the packed pair (x << 24 | y; y <= kPerBlock) serves
+// through LDS so that each thread scans kEmitRounds consecutive items and one
+// workgroup scan of the packed pair (x << 24 | y; y <= kEmitPerBlock) serves
 // both prefixes.
 
 __global__ void __launch_bounds__(kThreads) emit_scan_kernel(const uint4* __restrict__ info, int64_t n, int tiles_x,
@@ -173,32 +178,40 @@ __global__ void __launch_bounds__(kThreads) emit_scan_kernel(const uint4* __rest
                                                              uint32_t* __restrict__ vis_ids, uint32_t* ticket,
                                                              uint64_t* status_x, uint64_t* status_y,
                                                              int64_t* __restrict__ counters, int64_t capacity) {
-    static_assert(kRounds == 8 && kPerBlock < (1 << 24), "packed pair layout");
+    static_assert(kEmitRounds % 4 == 0 && kEmitPerBlock < (1 << 24), "packed pair layout");
     __shared__ uint32_t tk;
-    __shared__ __align__(16) uint32_t item_x[kPerBlock];  // tile counts, then exclusive x
-    __shared__ __align__(16) uint32_t item_y[kPerBlock];  // exclusive y | visible << 31
+    __shared__ __align__(16) uint32_t item_x[kEmitPerBlock];  // tile counts, then exclusive x
+    __shared__ __align__(16) uint32_t item_y[kEmitPerBlock];  // exclusive y | visible << 31
     __shared__ uint64_t lds64[kThreads / kWave];
     __shared__ uint64_t pre[2];
     if (threadIdx.x == 0) tk = atomicAdd(ticket, 1u);
     __syncthreads();
     const int64_t b = tk;
     const int64_t nb = gridDim.x;
-    const int64_t base = b * kPerBlock;
+    const int64_t base = b * kEmitPerBlock;
 #pragma unroll
-    for (int r = 0; r < kRounds; ++r) {
+    for (int r = 0; r < kEmitRounds; ++r) {
         const int64_t g = base + r * kThreads + threadIdx.x;
         int x0, y0, x1, y1;
         item_x[r * kThreads + threadIdx.x] = g < n ? (uint32_t)rect_of(info[g], tiles_x, tiles_y, x0, y0, x1, y1) : 0u;
     }
     __syncthreads();
-    const uint4* own = reinterpret_cast<const uint4*>(item_x) + 2 * threadIdx.x;
-    const uint4 c0 = own[0], c1 = own[1];
-    const uint32_t c[kRounds] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
-    uint32_t ex[kRounds], ey[kRounds];
+    constexpr int kVec = kEmitRounds / 4;
+    const uint4* own = reinterpret_cast<const uint4*>(item_x) + kVec * threadIdx.x;
+    uint32_t c[kEmitRounds];
+#pragma unroll
+    for (int q = 0; q < kVec; ++q) {
+        const uint4 cq = own[q];
+        c[4 * q] = cq.x;
+        c[4 * q + 1] = cq.y;
+        c[4 * q + 2] = cq.z;
+        c[4 * q + 3] = cq.w;
+    }
+    uint32_t ex[kEmitRounds], ey[kEmitRounds];
     uint64_t sx = 0;
     uint32_t sy = 0;
 #pragma unroll
-    for (int i = 0; i < kRounds; ++i) {
+    for (int i = 0; i < kEmitRounds; ++i) {
         ex[i] = (uint32_t)sx;
         ey[i] = sy;
         sx += c[i];
@@ -209,13 +222,14 @@ __global__ void __launch_bounds__(kThreads) emit_scan_kernel(const uint4* __rest
     const uint64_t ax = tot >> 24;
     const uint32_t ay = (uint32_t)(tot & 0xFFFFFFu);
     const uint32_t tx0 = (uint32_t)(tex >> 24), ty0 = (uint32_t)(tex & 0xFFFFFFu);
-    uint4* own_x = reinterpret_cast<uint4*>(item_x) + 2 * threadIdx.x;
-    uint4* own_y = reinterpret_cast<uint4*>(item_y) + 2 * threadIdx.x;
+    uint4* own_x = reinterpret_cast<uint4*>(item_x) + kVec * threadIdx.x;
+    uint4* own_y = reinterpret_cast<uint4*>(item_y) + kVec * threadIdx.x;
     auto vy = [&](int i) { return (ty0 + ey[i]) | (c[i] ? 0x80000000u : 0u); };
-    own_x[0] = make_uint4(tx0 + ex[0], tx0 + ex[1], tx0 + ex[2], tx0 + ex[3]);
-    own_x[1] = make_uint4(tx0 + ex[4], tx0 + ex[5], tx0 + ex[6], tx0 + ex[7]);
-    own_y[0] = make_uint4(vy(0), vy(1), vy(2), vy(3));
-    own_y[1] = make_uint4(vy(4), vy(5), vy(6), vy(7));
+#pragma unroll
+    for (int q = 0; q < kVec; ++q) {
+        own_x[q] = make_uint4(tx0 + ex[4 * q], tx0 + ex[4 * q + 1], tx0 + ex[4 * q + 2], tx0 + ex[4 * q + 3]);
+        own_y[q] = make_uint4(vy(4 * q), vy(4 * q + 1), vy(4 * q + 2), vy(4 * q + 3));
+    }
     if (threadIdx.x < kWave) {
         const uint64_t px = publish_and_look_back(status_x, b, ax);
         if (threadIdx.x == 0) pre[0] = px;
@@ -233,7 +247,7 @@ __global__ void __launch_bounds__(kThreads) emit_scan_kernel(const uint4* __rest
         counters[3] = 0;
     }
 #pragma unroll
-    for (int r = 0; r < kRounds; ++r) {
+    for (int r = 0; r < kEmitRounds; ++r) {
         const int64_t g = base + r * kThreads + threadIdx.x;
         if (g < n) {
             const int i = r * kThreads + threadIdx.x;
@@ -841,7 +855,8 @@ int64_t scan_blocks(int64_t n) { return n > 0 ? (n + kPerBlock - 1) / kPerBlock 
 hipError_t launch_emit_scan(const uint32_t* info, int64_t n, int tiles_x, int tiles_y, uint32_t* emit_off,
                             uint32_t* vis_ids, uint32_t* ticket, uint64_t* status_x, uint64_t* status_y,
                             int64_t* counters, int64_t capacity, hipStream_t s) {
-    hipLaunchKernelGGL(emit_scan_kernel, dim3((unsigned)scan_blocks(n)), dim3(kThreads), 0, s,
+    const int64_t blocks = n > 0 ? (n + kEmitPerBlock - 1) / kEmitPerBlock : 1;
+    hipLaunchKernelGGL(emit_scan_kernel, dim3((unsigned)blocks), dim3(kThreads), 0, s,
                        reinterpret_cast<const uint4*>(info), n, tiles_x, tiles_y, emit_off, vis_ids, ticket, status_x,
                        status_y, counters, capacity);
     return hipGetLastError();
