@@ -505,8 +505,13 @@ __global__ void __launch_bounds__(kCountThreads) group_count_kernel(const uint4*
     }
 }
 
+#ifndef TGS_SCATTER_THREADS
+#define TGS_SCATTER_THREADS 512
+#endif
+constexpr int kScatterThreads = TGS_SCATTER_THREADS;  // threads of a group-scatter workgroup
+
 template <bool VAR>
-__global__ void __launch_bounds__(256) group_scatter_kernel(const uint4* __restrict__ info, int64_t n,
+__global__ void __launch_bounds__(kScatterThreads) group_scatter_kernel(const uint4* __restrict__ info, int64_t n,
                                                             const uint32_t* __restrict__ emit_off,
                                                             const float* __restrict__ zrange, NearKey nk, GroupMap gm,
                                                             int tiles_x, int tiles_y,
@@ -514,18 +519,20 @@ __global__ void __launch_bounds__(256) group_scatter_kernel(const uint4* __restr
                                                             const uint32_t* __restrict__ wgbase,
                                                             uint64_t* __restrict__ tmp_pair,
                                                             uint16_t* __restrict__ tmp_code, int64_t capacity) {
-    __shared__ WaveGauss wg[4];
+    constexpr int NT = kScatterThreads, NW = NT / kWave;
+    static_assert(kGroupChunk % NT == 0, "whole wavefront slabs per chunk");
+    __shared__ WaveGauss wg[NW];
     __shared__ uint32_t cursor[kMaxGroups];
     const uint32_t* row = wgbase + (int64_t)blockIdx.x * gm.G;
     // slots of groups this workgroup does not touch hold stale values and
     // are never used
-    for (int g = threadIdx.x; g < gm.G; g += 256) cursor[g] = group_off[g] + row[g];
+    for (int g = threadIdx.x; g < gm.G; g += NT) cursor[g] = group_off[g] + row[g];
     __syncthreads();
     const int w = threadIdx.x / kWave;
     const int64_t first = (int64_t)blockIdx.x * kGroupChunk;
     constexpr int R = kExpandRounds;
-    for (int it = 0; it < kGroupChunk / 256; ++it) {
-        const int64_t g0 = first + (int64_t)(it * 4 + w) * kWave;
+    for (int it = 0; it < kGroupChunk / NT; ++it) {
+        const int64_t g0 = first + (int64_t)(it * NW + w) * kWave;
         for_wave_entries_at<R, true, VAR>(
             g0, info, n, emit_off, tiles_x, tiles_y, zrange, nk, gm.K * gm.SB, &wg[w], [&](const Ent (&en)[R]) {
 #pragma unroll
@@ -1021,11 +1028,11 @@ hipError_t launch_group_scatter(const uint32_t* info, int64_t n, const uint32_t*
     if (n == 0) return hipSuccess;
     const int64_t blocks = (n + kGroupChunk - 1) / kGroupChunk;
     if (gm.seg_base)
-        hipLaunchKernelGGL(group_scatter_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, s,
+        hipLaunchKernelGGL(group_scatter_kernel<true>, dim3((unsigned)blocks), dim3(kScatterThreads), 0, s,
                            reinterpret_cast<const uint4*>(info), n, emit_off, zrange, nk, gm, tiles_x, tiles_y,
                            group_off, wgbase, tmp_pair, tmp_code, capacity);
     else
-        hipLaunchKernelGGL(group_scatter_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, s,
+        hipLaunchKernelGGL(group_scatter_kernel<false>, dim3((unsigned)blocks), dim3(kScatterThreads), 0, s,
                            reinterpret_cast<const uint4*>(info), n, emit_off, zrange, nk, gm, tiles_x, tiles_y,
                            group_off, wgbase, tmp_pair, tmp_code, capacity);
     return hipGetLastError();
