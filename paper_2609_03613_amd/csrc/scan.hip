@@ -20,11 +20,15 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kRounds = 8;
 constexpr int kPerBlock = kThreads * kRounds;
-#ifndef TGS_EMIT_ROUNDS
-#define TGS_EMIT_ROUNDS 16
+#ifndef TGS_EMIT_THREADS
+#define TGS_EMIT_THREADS 1024
 #endif
-constexpr int kEmitRounds = TGS_EMIT_ROUNDS;  // items per thread of the emit scan
-constexpr int kEmitPerBlock = kThreads * kEmitRounds;
+#ifndef TGS_EMIT_ROUNDS
+#define TGS_EMIT_ROUNDS 4
+#endif
+constexpr int kEmitThreads = TGS_EMIT_THREADS;  // threads of an emit-scan workgroup
+constexpr int kEmitRounds = TGS_EMIT_ROUNDS;    // items per thread of the emit scan
+constexpr int kEmitPerBlock = kEmitThreads * kEmitRounds;
 constexpr uint64_t kFlagAgg = 1ull << 62;
 constexpr uint64_t kFlagInc = 2ull << 62;
 constexpr uint64_t kValMask = (1ull << 62) - 1;
@@ -141,8 +145,9 @@ __device__ __forceinline__ uint64_t publish_and_look_back(uint64_t* status, int6
 
 // Exclusive scan of one uint64 per thread across the workgroup; *total
 // receives the sum. Ends with a barrier, so lds is reusable.
+template <int NT = kThreads>
 __device__ __forceinline__ uint64_t block_excl_u64(uint64_t v, uint64_t* lds, uint64_t* total) {
-    constexpr int NW = kThreads / kWave;
+    constexpr int NW = NT / kWave;
     const int w = threadIdx.x / kWave, l = lane();
     uint64_t inc = v;
 #pragma unroll
@@ -173,7 +178,7 @@ __device__ __forceinline__ uint64_t block_excl_u64(uint64_t v, uint64_t* lds, ui
 // workgroup scan of the packed pair (x << 24 | y; y <= kEmitPerBlock) serves
 // both prefixes.
 
-__global__ void __launch_bounds__(kThreads) emit_scan_kernel(const uint4* __restrict__ info, int64_t n, int tiles_x,
+__global__ void __launch_bounds__(kEmitThreads) emit_scan_kernel(const uint4* __restrict__ info, int64_t n, int tiles_x,
                                                              int tiles_y, uint32_t* __restrict__ emit_off,
                                                              uint32_t* __restrict__ vis_ids, uint32_t* ticket,
                                                              uint64_t* status_x, uint64_t* status_y,
@@ -182,7 +187,7 @@ __global__ void __launch_bounds__(kThreads) emit_scan_kernel(const uint4* __rest
     __shared__ uint32_t tk;
     __shared__ __align__(16) uint32_t item_x[kEmitPerBlock];  // tile counts, then exclusive x
     __shared__ __align__(16) uint32_t item_y[kEmitPerBlock];  // exclusive y | visible << 31
-    __shared__ uint64_t lds64[kThreads / kWave];
+    __shared__ uint64_t lds64[kEmitThreads / kWave];
     __shared__ uint64_t pre[2];
     if (threadIdx.x == 0) tk = atomicAdd(ticket, 1u);
     __syncthreads();
@@ -191,9 +196,9 @@ __global__ void __launch_bounds__(kThreads) emit_scan_kernel(const uint4* __rest
     const int64_t base = b * kEmitPerBlock;
 #pragma unroll
     for (int r = 0; r < kEmitRounds; ++r) {
-        const int64_t g = base + r * kThreads + threadIdx.x;
+        const int64_t g = base + r * kEmitThreads + threadIdx.x;
         int x0, y0, x1, y1;
-        item_x[r * kThreads + threadIdx.x] = g < n ? (uint32_t)rect_of(info[g], tiles_x, tiles_y, x0, y0, x1, y1) : 0u;
+        item_x[r * kEmitThreads + threadIdx.x] = g < n ? (uint32_t)rect_of(info[g], tiles_x, tiles_y, x0, y0, x1, y1) : 0u;
     }
     __syncthreads();
     constexpr int kVec = kEmitRounds / 4;
@@ -218,7 +223,7 @@ __global__ void __launch_bounds__(kThreads) emit_scan_kernel(const uint4* __rest
         sy += c[i] ? 1u : 0u;
     }
     uint64_t tot;
-    const uint64_t tex = block_excl_u64((sx << 24) | sy, lds64, &tot);
+    const uint64_t tex = block_excl_u64<kEmitThreads>((sx << 24) | sy, lds64, &tot);
     const uint64_t ax = tot >> 24;
     const uint32_t ay = (uint32_t)(tot & 0xFFFFFFu);
     const uint32_t tx0 = (uint32_t)(tex >> 24), ty0 = (uint32_t)(tex & 0xFFFFFFu);
@@ -248,9 +253,9 @@ __global__ void __launch_bounds__(kThreads) emit_scan_kernel(const uint4* __rest
     }
 #pragma unroll
     for (int r = 0; r < kEmitRounds; ++r) {
-        const int64_t g = base + r * kThreads + threadIdx.x;
+        const int64_t g = base + r * kEmitThreads + threadIdx.x;
         if (g < n) {
-            const int i = r * kThreads + threadIdx.x;
+            const int i = r * kEmitThreads + threadIdx.x;
             emit_off[g] = (uint32_t)(cx + item_x[i]);
             const uint32_t y = item_y[i];
             if (y >> 31) vis_ids[cy + (y & 0x7FFFFFFFu)] = (uint32_t)g;
@@ -856,7 +861,7 @@ hipError_t launch_emit_scan(const uint32_t* info, int64_t n, int tiles_x, int ti
                             uint32_t* vis_ids, uint32_t* ticket, uint64_t* status_x, uint64_t* status_y,
                             int64_t* counters, int64_t capacity, hipStream_t s) {
     const int64_t blocks = n > 0 ? (n + kEmitPerBlock - 1) / kEmitPerBlock : 1;
-    hipLaunchKernelGGL(emit_scan_kernel, dim3((unsigned)blocks), dim3(kThreads), 0, s,
+    hipLaunchKernelGGL(emit_scan_kernel, dim3((unsigned)blocks), dim3(kEmitThreads), 0, s,
                        reinterpret_cast<const uint4*>(info), n, tiles_x, tiles_y, emit_off, vis_ids, ticket, status_x,
                        status_y, counters, capacity);
     return hipGetLastError();
