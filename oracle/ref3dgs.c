@@ -46,7 +46,7 @@ static const double ALPHA_MIN = 1.0 / 255.0;
 static const double ALPHA_MAX = 0.99;
 static const double T_MIN = 1e-4;
 static const double DILATION = 0.3;  /* px^2 added to the screen covariance */
-static const double GUARD = 0.3;     /* frustum guard: 30 % beyond the image */
+static const double GUARD = 0.3;     /* frustum guard: 0.3 tan(half FOV) beyond the image edge */
 
 /* Per-Gaussian flag bits written by orc_project. */
 enum {
@@ -211,8 +211,11 @@ ORC_EXPORT int orc_project(int64_t n, const float* means, const float* log_scale
                 Sc[3 * i + j] = acc;
             }
         /* Jacobian of the perspective map at the (guarded) centre */
-        double lim_xp = (W - cx) / fx + GUARD * W / fx, lim_xn = cx / fx + GUARD * W / fx;
-        double lim_yp = (H - cy) / fy + GUARD * H / fy, lim_yn = cy / fy + GUARD * H / fy;
+        /* x/z is clamped to the image edge plus 0.3 tan(half FOV), tan(half
+           FOV) = W / (2 fx): +-1.3 W / (2 fx) for a centred principal point */
+        double tanx = 0.5 * W / fx, tany = 0.5 * H / fy;
+        double lim_xp = (W - cx) / fx + GUARD * tanx, lim_xn = cx / fx + GUARD * tanx;
+        double lim_yp = (H - cy) / fy + GUARD * tany, lim_yn = cy / fy + GUARD * tany;
         double txz = pc[0] / z, tyz = pc[1] / z;
         double tx = z * fmin(lim_xp, fmax(-lim_xn, txz));
         double ty = z * fmin(lim_yp, fmax(-lim_yn, tyz));
@@ -839,8 +842,9 @@ static void adj_project_one(const double* means, const double* log_scales, const
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j)
             P->M[3 * i + j] = R[3 * i] * Rq[j] + R[3 * i + 1] * Rq[3 + j] + R[3 * i + 2] * Rq[6 + j];
-    const double lxp = (W - cx) / fx + GUARD * W / fx, lxn = cx / fx + GUARD * W / fx;
-    const double lyp = (H - cy) / fy + GUARD * H / fy, lyn = cy / fy + GUARD * H / fy;
+    const double tanx = 0.5 * W / fx, tany = 0.5 * H / fy;
+    const double lxp = (W - cx) / fx + GUARD * tanx, lxn = cx / fx + GUARD * tanx;
+    const double lyp = (H - cy) / fy + GUARD * tany, lyn = cy / fy + GUARD * tany;
     double tx = P->pc[0], ty = P->pc[1];
     if (P->pc[0] / z > lxp) { P->clx = 1; P->limx = lxp; tx = z * lxp; }
     else if (P->pc[0] / z < -lxn) { P->clx = 1; P->limx = -lxn; tx = -z * lxn; }

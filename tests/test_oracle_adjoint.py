@@ -134,7 +134,7 @@ def test_adjoint_frustum_guard():
     near = _one((0.1, 0.0, 3.0), (-2.0, -2.1, -2.2), 1.0, (0.1, 0.3, 0.5))
     g = _cat(far, near)
     cam_d = dict(cam)
-    lim = (32 - 16.0) / 30.0 + 0.3 * 32 / 30.0
+    lim = 1.3 * 32 / (2 * 30.0)  # the guard: 1.3 tan(half FOV), centred principal point
     assert 3.0 / 2.0 > lim
     target = np.full((32, 32, 3), 0.5)
     ga = as64(g)

@@ -236,3 +236,53 @@ def test_footprint_covers_alpha_support():
     assert len(xx) > 100
     assert (xx // 16).min() >= x0 and (xx // 16).max() < x1
     assert (yy // 16).min() >= y0 and (yy // 16).max() < y1
+
+
+@pytest.mark.parametrize("side", [1.0, -1.0])
+@pytest.mark.parametrize("axis", [0, 1])
+def test_frustum_guard_closed_form(side, axis):
+    # The 3DGS frustum guard clamps x/z (and y/z) of the Jacobian's centre to
+    # 1.3 tan(half FOV) = 1.3 W / (2 f) with a centred principal point. For
+    # an isotropic Gaussian (Sigma_cam = s^2 I) at (u z, 0, z):
+    #   Sigma'_00 = s^2 (f/z)^2 (1 + c^2) + 0.3,  Sigma'_01 = 0,
+    #   Sigma'_11 = s^2 (f/z)^2 + 0.3,
+    # with c = u inside the guard and c = +-1.3 W / (2 f) beyond it (swap the
+    # roles for the y axis). Gaussians 1.25x and 1.35x the half FOV off axis
+    # sit on the two sides of the limit; a guard of another width (such as
+    # the image edge plus 30 % of the whole width, 1.6 W / (2 f)) fails the
+    # second case.
+    f, W, H, z, s = 100.0, 64, 48, 3.0, 0.05
+    cam = scenes.camera(np.eye(3), np.zeros(3), f, f, W / 2.0, H / 2.0, W, H)
+    half = (W if axis == 0 else H) / (2.0 * f)
+    s32 = math.exp(float(np.float32(math.log(s))))
+    k = (f / z) ** 2 * s32 * s32
+    for frac, clamped in ((1.25, False), (1.35, True), (3.0, True)):
+        mean = [0.0, 0.0, z]
+        mean[axis] = side * frac * half * z
+        mu = np.array(mean, np.float32)
+        p = oracle.project(one_gaussian(mu, [math.log(s)] * 3), cam)
+        u = float(mu[axis]) / float(mu[2])
+        c = side * 1.3 * half if clamped else u
+        along, across = k * (1.0 + c * c) + 0.3, k + 0.3
+        want = [along, 0.0, across] if axis == 0 else [across, 0.0, along]
+        np.testing.assert_allclose(p["cov2d"][0], want, rtol=1e-12, atol=1e-12)
+        # the screen position is never clamped
+        np.testing.assert_allclose(p["mean2d"][0][axis], f * u + (W if axis == 0 else H) / 2.0, rtol=1e-12)
+
+
+def test_frustum_guard_off_centre_principal_point():
+    # With an off-centre principal point the guard is asymmetric: x/z is
+    # clamped to (W - cx)/fx + 0.3 W/(2 fx) on the right and to
+    # -(cx/fx + 0.3 W/(2 fx)) on the left (the gsplat form of the guard, equal
+    # to +-1.3 W/(2 fx) when cx = W/2).
+    fx, W, H, cx, z, s = 80.0, 64, 64, 20.0, 2.0, 0.04
+    cam = scenes.camera(np.eye(3), np.zeros(3), fx, fx, cx, 32.0, W, H)
+    s32 = math.exp(float(np.float32(math.log(s))))
+    k = (fx / z) ** 2 * s32 * s32
+    right = (W - cx) / fx + 0.3 * W / (2 * fx)   # 0.67
+    left = cx / fx + 0.3 * W / (2 * fx)          # 0.37
+    for u, clamped in ((0.6, False), (0.8, True), (-0.3, False), (-0.5, True)):
+        mu = np.array([u * z, 0.0, z], np.float32)
+        p = oracle.project(one_gaussian(mu, [math.log(s)] * 3), cam)
+        c = (right if u > 0 else -left) if clamped else float(mu[0]) / float(mu[2])
+        np.testing.assert_allclose(p["cov2d"][0], [k * (1 + c * c) + 0.3, 0.0, k + 0.3], rtol=1e-12, atol=1e-12)
