@@ -66,6 +66,7 @@ def lib():
                                         P, P, P, P, P, P, P, P]
         L.orc_adjoint.argtypes = [i64, P, P, P, P, P, i32, P, i32, P, P, P, P, P, P, P, P, P, P, P]
         L.orc_composite_adjoint.argtypes = [i64, P, P, P, P, P, P, P, i32, i32, i32, P, P, P, P, P, P]
+        L.orc_project_adjoint.argtypes = [i64, P, P, P, P, P, i32, P, i32, P, P, P, P, P, P]
         _lib = L
     return _lib
 
@@ -322,6 +323,25 @@ def adjoint(g, cam, tile_size=16, bg=(0.0, 0.0, 0.0), d_img=None, d_alpha=None):
     assert rc == 0, rc
     if grads is not None:
         out.update(grads)
+    return out
+
+
+def project_adjoint(g, cam, d_proj, tile_size=16):
+    """Parameter gradients (``means``, ``log_scales``, ``quats``, ``logits``,
+    ``sh`` in the input layouts) of the binary64 projection of ``g``, given
+    ``d_proj`` [n, 9] = dL/d(mean2d x, y, conic a, b, c, opacity, r, g, b)."""
+    n = g["means"].shape[0]
+    deg = int(g["sh_degree"])
+    nsh = (deg + 1) ** 2
+    ins = [_c(g[k], np.float64) for k in ("means", "log_scales", "quats", "logits", "sh")]
+    dp = _c(d_proj, np.float64)
+    assert dp.shape == (n, 9)
+    out = {"means": np.zeros((n, 3)), "log_scales": np.zeros((n, 3)), "quats": np.zeros((n, 4)),
+           "logits": np.zeros(n), "sh": np.zeros((n, nsh, 3))}
+    rc = lib().orc_project_adjoint(n, *[_p(a) for a in ins], deg, _p(cam_array(cam)), int(tile_size), _p(dp),
+                                   _p(out["means"]), _p(out["log_scales"]), _p(out["quats"]), _p(out["logits"]),
+                                   _p(out["sh"]))
+    assert rc == 0, rc
     return out
 
 

@@ -1190,3 +1190,31 @@ ORC_EXPORT int orc_composite_adjoint(int64_t n, const double* mean2d, const doub
     free(P);
     return err;
 }
+
+/*
+ * The projection adjoint alone: given d_proj [n][9] = dL/d(mean2d x, y,
+ * conic a, b, c, opacity, r, g, b) of the binary64 projection of the
+ * parameters, the parameter gradients in the input layouts (d_sh:
+ * [n][(D+1)^2][3]), as the last step of orc_adjoint. Gaussians the
+ * projection makes invisible get zero gradients.
+ */
+ORC_EXPORT int orc_project_adjoint(int64_t n, const double* means, const double* log_scales, const double* quats,
+                                   const double* logits, const double* sh, int sh_degree, const double* cam,
+                                   int tile_size, const double* d_proj, double* d_means, double* d_log_scales,
+                                   double* d_quats, double* d_logits, double* d_sh) {
+    if (n < 0 || sh_degree < 0 || sh_degree > 3 || tile_size <= 0) return 1;
+    const int nsh = (sh_degree + 1) * (sh_degree + 1);
+#pragma omp parallel for schedule(static)
+    for (int64_t g = 0; g < n; ++g) {
+        adj_g P;
+        adj_project_one(means, log_scales, quats, logits, sh, nsh, sh_degree, cam, tile_size, g, &P);
+        for (int k = 0; k < 3; ++k) d_means[3 * g + k] = d_log_scales[3 * g + k] = 0.0;
+        for (int k = 0; k < 4; ++k) d_quats[4 * g + k] = 0.0;
+        d_logits[g] = 0.0;
+        for (int k = 0; k < nsh * 3; ++k) d_sh[(int64_t)g * nsh * 3 + k] = 0.0;
+        if (P.vis)
+            adj_project_reverse(&P, d_proj + 9 * g, sh + (int64_t)g * nsh * 3, nsh, sh_degree, cam, d_means + 3 * g,
+                                d_log_scales + 3 * g, d_quats + 4 * g, d_logits + g, d_sh + (int64_t)g * nsh * 3);
+    }
+    return 0;
+}

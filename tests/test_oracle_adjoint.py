@@ -209,3 +209,71 @@ def test_composite_adjoint_on_records_matches_full_adjoint():
     np.testing.assert_allclose(rec["alpha"], full["alpha"], rtol=0, atol=1e-12)
     scale = np.abs(full["d_proj"]).max(axis=0)
     assert np.all(np.abs(rec["d_proj"] - full["d_proj"]) <= 1e-9 * scale + 1e-15)
+
+
+def test_project_adjoint_against_differences_of_the_projection():
+    # oracle.project_adjoint(d) is the gradient of the linear functional
+    # F = sum_g d[g] . (mean2d, conic, opacity, rgb)(theta) of the binary64
+    # projection. Central differences of oracle.project (which takes binary32
+    # parameters: the stencil points are binary32 values and the step is
+    # their exact difference) check it, with one Gaussian beyond the frustum
+    # guard and one with a colour channel clamped at zero.
+    cam = scenes.camera(np.eye(3), np.zeros(3), 90.0, 80.0, 33.0, 30.0, 64, 56)
+    rng = np.random.default_rng(5)
+    n = 6
+    g = {
+        "means": np.stack([rng.uniform(-0.4, 0.4, n), rng.uniform(-0.4, 0.4, n), rng.uniform(2, 4, n)], 1),
+        "log_scales": rng.normal(-2.5, 0.4, (n, 3)), "quats": rng.normal(0, 1, (n, 4)),
+        "logits": rng.normal(0.5, 1.0, n), "sh": rng.normal(0, 0.3, (n, 16, 3)), "sh_degree": 3,
+    }
+    g["means"][1] = (2.0, -0.1, 2.0)   # x/z = 1, beyond the guard (about 0.58 on the right)
+    g["log_scales"][1] = (-0.5, -0.6, -0.4)  # large enough to reach the image
+    g["sh"][2, 0, 0] = -3.0            # red channel clamped at zero
+    g = {k: (np.asarray(v, np.float32) if k != "sh_degree" else v) for k, v in g.items()}
+    d = rng.normal(0, 1, (n, 9))
+    # balance the conic terms against the others (conics of large splats are
+    # small), and let the guarded Gaussian's gradient come from its conic
+    # alone, so that the guard's part of the Jacobian derivative dominates it
+    d[:, 2:5] /= np.abs(oracle.project(g, cam)["conic"]).max(axis=1, keepdims=True)
+    d[1, [0, 1, 5, 6, 7, 8]] = 0.0
+    got = oracle.project_adjoint(g, cam, d)
+    assert got["sh"][2, :, 0].max() == 0.0 and np.abs(got["sh"][2, :, 1]).max() > 0
+
+    def F(gg):
+        p = oracle.project(gg, cam)
+        assert np.all(p["flags"] & oracle.VISIBLE)
+        v = np.concatenate([p["mean2d"], p["conic"], p["opacity"][:, None], p["rgb"]], 1)
+        return float(np.sum(d * v))
+
+    checked = 0
+    for key in KEYS:
+        arr = g[key]
+        for i in range(arr.size):
+            th = arr.reshape(-1)[i]
+            h = np.float32(2e-3 * max(0.05, abs(float(th))))
+            vals, pts = [], []
+            for s in (+1, -1):
+                gg = dict(g)
+                gg[key] = arr.copy()
+                gg[key].reshape(-1)[i] = np.float32(th + s * h)
+                pts.append(float(gg[key].reshape(-1)[i]))
+                vals.append(F(gg))
+            fd = (vals[0] - vals[1]) / (pts[0] - pts[1])
+            an = float(got[key].reshape(-1)[i])
+            scale = np.abs(got[key][i // (arr.size // n)]).max()
+            assert abs(fd - an) <= 2e-4 * (abs(an) + 1e-2 * scale), (key, i, fd, an)
+            checked += 1
+    assert checked == n * (3 + 3 + 4 + 1 + 48)
+
+
+def test_project_adjoint_is_the_last_step_of_the_full_adjoint():
+    # On the finite-difference sub-case the projection adjoint fed the full
+    # adjoint's d_proj returns the full adjoint's parameter gradients
+    g, cam = scenes.fd_subcase()
+    target = scenes.training_target(cam["width"], cam["height"])
+    ga = as64(g)
+    _, up = loss_fn(ga, cam, target)
+    a = oracle.adjoint(ga, cam, d_img=up)
+    p = oracle.project_adjoint(ga, cam, a["d_proj"])
+    for k in KEYS:
+        assert np.array_equal(p[k], a[k]), k
