@@ -1,6 +1,6 @@
 // Projection of 3D Gaussians to screen-space splats (EWA splatting with the
 // 3DGS conventions, which the paper keeps unchanged): camera transform,
-// covariance R S^2 R^T, perspective Jacobian with the 30 % frustum guard,
+// covariance R S^2 R^T, perspective Jacobian with the 3DGS frustum guard (1.3 x the half FOV),
 // 0.3 px^2 dilation, conic, sigmoid opacity, real spherical-harmonic colour
 // up to degree 3, and the opacity-aware tile rect.
 //
@@ -25,10 +25,14 @@ Cam make_cam(const tgs_camera& c, int tile) {
     k.tiles_x = div_up(c.width, tile);
     k.tiles_y = div_up(c.height, tile);
     for (int i = 0; i < 3; ++i) k.campos[i] = -(c.R[i] * c.t[0] + c.R[3 + i] * c.t[1] + c.R[6 + i] * c.t[2]);
-    k.lim_xp = (c.width - c.cx) / c.fx + 0.3 * c.width / c.fx;
-    k.lim_xn = c.cx / c.fx + 0.3 * c.width / c.fx;
-    k.lim_yp = (c.height - c.cy) / c.fy + 0.3 * c.height / c.fy;
-    k.lim_yn = c.cy / c.fy + 0.3 * c.height / c.fy;
+    // frustum guard: x/z is clamped to the image edge plus 0.3 tan(half
+    // FOV), tan(half FOV) = W / (2 fx), i.e. +-1.3 W / (2 fx) when the
+    // principal point is centred (and likewise for y)
+    const double tanx = 0.5 * c.width / c.fx, tany = 0.5 * c.height / c.fy;
+    k.lim_xp = (c.width - c.cx) / c.fx + 0.3 * tanx;
+    k.lim_xn = c.cx / c.fx + 0.3 * tanx;
+    k.lim_yp = (c.height - c.cy) / c.fy + 0.3 * tany;
+    k.lim_yn = c.cy / c.fy + 0.3 * tany;
     return k;
 }
 

@@ -278,6 +278,25 @@ def depth_stress_scene(kind, n=None, seed=0, width=1920, height=1080, focal=1100
     return g, cam
 
 
+def guard_scene(seed=0, n=4000, width=256, height=192, focal=200.0):
+    """Large Gaussians around and beyond the edges of the field of view, to
+    exercise the frustum guard: x/z and y/z uniform in +-2.2 x the half FOV,
+    z U[2, 6] (camera space, identity pose), log-scales N(-1.5, 0.3), logits
+    N(1, 1), SH degree 1 with coefficients N(0, 0.2)."""
+    rng = np.random.default_rng(seed)
+    z = rng.uniform(2.0, 6.0, size=n)
+    u = rng.uniform(-2.2, 2.2, size=n) * (0.5 * width / focal)
+    v = rng.uniform(-2.2, 2.2, size=n) * (0.5 * height / focal)
+    means = np.stack([u * z, v * z, z], 1)
+    log_scales = rng.normal(-1.5, 0.3, size=(n, 3))
+    quats = _unit_quats(rng, n)
+    logits = rng.normal(1.0, 1.0, size=n)
+    sh = rng.normal(0.0, 0.2, size=(n, 4, 3))
+    g = _pack(means, log_scales, quats, logits, sh, 1)
+    cam = camera(np.eye(3), np.zeros(3), focal, focal, width / 2.0, height / 2.0, width, height)
+    return g, cam
+
+
 def subset(g, idx):
     """Gaussians ``idx`` of scene ``g`` (keeps the degree)."""
     out = {k: np.ascontiguousarray(v[idx]) for k, v in g.items() if k != "sh_degree"}

@@ -42,9 +42,13 @@ def cam_for(W, H, f=100.0):
 # projection
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("case", ["small", "training_d3", "surface_d3"])
+@pytest.mark.parametrize("case", ["small", "training_d3", "surface_d3", "guard"])
 def test_project_matches_oracle(case):
-    if case == "small":
+    if case == "guard":
+        # large Gaussians up to 2.2x the half FOV off axis: many take the
+        # frustum guard and still reach the image
+        g, cam = scenes.guard_scene(seed=0)
+    elif case == "small":
         g, cam = scenes.small_forward(seed=0)
     elif case == "training_d3":
         g, cam = scenes.training_scene(seed=0, n=20000)
@@ -60,7 +64,7 @@ def test_project_matches_oracle(case):
     amb = (ref["flags"] & (oracle.AMBIG_RECT | oracle.AMBIG_VIS)) > 0
     assert np.array_equal(vis[~amb], vis_ref[~amb])
     v = vis & vis_ref
-    assert v.sum() > 0.5 * len(v)
+    assert v.sum() > (0.25 if case == "guard" else 0.5) * len(v)
     # depth key: bit-exact (same IEEE binary64 operations, one rounding)
     assert np.array_equal(depth[v].view(np.uint32), ref["depth_key"][v].view(np.uint32))
     ok = v & ~amb
