@@ -43,7 +43,8 @@
  *    outside (znear, zfar), a singular screen covariance, opacity < 1/255) is
  *    not an error: that Gaussian is invisible (empty rect).
  *  - Limits: 0 <= n < 2^31, sh_degree 0..3, width and height 1..16384,
- *    tile_size 16, 1 <= num_bins <= 1024, 0 < znear < zfar, entries < 2^32.
+ *    tile_size 8, 16 or 32 (8 and 32 with the WAVE raster and packed = 0),
+ *    1 <= num_bins <= 1024, 0 < znear < zfar, entries < 2^32.
  */
 #ifndef TILEGS_H
 #define TILEGS_H
