@@ -338,6 +338,27 @@ TGS_API tgs_status tgs_rasterize_batch(int32_t num_views, const tgs_projected* p
                                int32_t* const* last_dev, void* workspace_dev, size_t workspace_bytes,
                                void* stream);
 
+/* tgs_rasterize_batch for callers that cannot allocate device memory: code
+   under HIP graph capture, tight serving loops, harnesses that forbid
+   hipMalloc. Same arguments, outputs and errors as tgs_rasterize_batch
+   without the workspace: the batch's control words and work list live in a
+   fixed scratch array inside the library, 4 MiB on every device the library
+   runs on (held until the process ends), enough for about one million 8x8
+   pixel blocks over all views (e.g. 16 views of 3840x2160). Views needing
+   more (tgs_batch_workspace_size above 4 MiB) are rejected with
+   TGS_ERR_WORKSPACE before anything is enqueued. The call allocates
+   nothing; its first call on a device looks up that device's scratch
+   address (make that first call outside a graph capture). Every call on a
+   device shares that device's scratch: calls that overlap in time on one
+   device (two streams, two threads) race and must be serialised by the
+   caller; the control words are cleared by a fill kernel at the start of
+   every call. */
+TGS_API tgs_status tgs_rasterize_batch_noalloc(int32_t num_views, const tgs_projected* projected,
+                                       const tgs_binned* binned, const tgs_camera* cameras,
+                                       const tgs_params* params, const int32_t* orders, const float* bg,
+                                       float* const* rgb_dev, float* const* alpha_dev, int32_t* const* last_dev,
+                                       void* stream);
+
 /* Learned bin-count proposal. The paper fixes K = 64 bins per tile (section
    "Implementation details") and varies K per frame in its bin-count table;
    this addition picks K_t per tile with a small network from the previous

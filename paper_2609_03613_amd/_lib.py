@@ -19,6 +19,7 @@ REPAIR_ALL, REPAIR_RULES, REPAIR_NONE = 0, 1, 2
 
 EXPORTS = ("tgs_default_params", "tgs_project", "tgs_bin_workspace_size", "tgs_bin", "tgs_rasterize",
            "tgs_rasterize_backward", "tgs_project_backward", "tgs_batch_workspace_size", "tgs_rasterize_batch",
+           "tgs_rasterize_batch_noalloc",
            "tgs_tile_features", "tgs_propose_bins", "tgs_mlp_train_workspace_size", "tgs_mlp_train_step",
            "tgs_last_error")
 MLP_PARAMS = 5768
@@ -102,6 +103,9 @@ def lib():
         L.tgs_rasterize_batch.argtypes = [ctypes.c_int32, _c_p, _c_p, _c_p, _c_p, _c_p, P(ctypes.c_float), _c_p, _c_p,
                                           _c_p, _c_p, ctypes.c_size_t, _c_p]
         L.tgs_rasterize_batch.restype = ctypes.c_int
+        L.tgs_rasterize_batch_noalloc.argtypes = [ctypes.c_int32, _c_p, _c_p, _c_p, _c_p, _c_p, P(ctypes.c_float), _c_p,
+                                                  _c_p, _c_p, _c_p]
+        L.tgs_rasterize_batch_noalloc.restype = ctypes.c_int
         L.tgs_tile_features.argtypes = [P(Binned), P(Camera), P(Params), _c_p, _c_p]
         L.tgs_tile_features.restype = ctypes.c_int
         L.tgs_propose_bins.argtypes = [_c_p, _c_p, ctypes.c_int64, ctypes.c_int32, _c_p, _c_p, _c_p]

@@ -359,8 +359,10 @@ class BatchRenderer:
             self.proj = [(torch.empty((n, 16), dtype=torch.float32, device=self.device),
                           torch.empty((n, 4), dtype=torch.int32, device=self.device)) for _ in self.views]
 
-    def rasterize(self, projs, binned):
-        """tgs_rasterize_batch over (splats, info) and Binned per view."""
+    def rasterize(self, projs, binned, noalloc=False):
+        """tgs_rasterize_batch over (splats, info) and Binned per view (with
+        noalloc, tgs_rasterize_batch_noalloc: the library's fixed scratch
+        instead of the workspace)."""
         nv = len(self.views)
         prs = (L.Projected * nv)(*[L.Projected(_ptr(s).value, _ptr(i).value, int(s.shape[0])) for s, i in projs])
         bs = (L.Binned * nv)(*[b.c() for b in binned])
@@ -369,11 +371,13 @@ class BatchRenderer:
         bgc = (ctypes.c_float * 3)(*self.bg)
         ptrs = lambda k: (ctypes.c_void_p * nv)(*[o[k].data_ptr() for o in self.outs])
         self._keep = (prs, bs, orders, bgc)
-        L.check(L.lib().tgs_rasterize_batch(nv, ctypes.cast(prs, ctypes.c_void_p), ctypes.cast(bs, ctypes.c_void_p),
-                                            ctypes.cast(self._ccams, ctypes.c_void_p),
-                                            ctypes.cast(self._cparams, ctypes.c_void_p),
-                                            ctypes.cast(orders, ctypes.c_void_p), bgc, ptrs("rgb"), ptrs("alpha"),
-                                            ptrs("last"), _ptr(self.ws), self.ws.numel(), _stream()))
+        args = (nv, ctypes.cast(prs, ctypes.c_void_p), ctypes.cast(bs, ctypes.c_void_p),
+                ctypes.cast(self._ccams, ctypes.c_void_p), ctypes.cast(self._cparams, ctypes.c_void_p),
+                ctypes.cast(orders, ctypes.c_void_p), bgc, ptrs("rgb"), ptrs("alpha"), ptrs("last"))
+        if noalloc:
+            L.check(L.lib().tgs_rasterize_batch_noalloc(*args, _stream()))
+        else:
+            L.check(L.lib().tgs_rasterize_batch(*args, _ptr(self.ws), self.ws.numel(), _stream()))
         return self.outs
 
     def frame(self, g, sync=False):

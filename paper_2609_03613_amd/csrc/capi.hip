@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
 
 #include "common.hpp"
@@ -574,18 +575,75 @@ size_t tgs_batch_workspace_size(int32_t num_views, const tgs_camera* cams, const
     return sizeof(uint32_t) * (size_t)(256 + 8 * ((blocks + 7) / 8));
 }
 
-tgs_status tgs_rasterize_batch(int32_t num_views, const tgs_projected* pr, const tgs_binned* b,
-                               const tgs_camera* cams, const tgs_params* params, const int32_t* orders,
-                               const float* bg, float* const* rgb, float* const* alpha, int32_t* const* last,
-                               void* ws, size_t ws_bytes, void* stream) {
-    g_err.clear();
+}  // extern "C"
+
+// Fixed scratch of tgs_rasterize_batch_noalloc: the batch control words and
+// work list (tgs_batch_workspace_size bytes) of up to about one million 8x8
+// blocks, e.g. 16 views of 3840x2160 (2.1M pixels each). Every device the
+// library runs on holds its own copy until the process ends. In host code
+// `scratch` only names the symbol; its device address comes from
+// hipGetSymbolAddress, once per device (scratch_on_current_device).
+static constexpr size_t kScratchBytes = (size_t)4 << 20;
+static __device__ __align__(256) uint32_t scratch[kScratchBytes / sizeof(uint32_t)];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_dev_mu;
+void* g_scratch_dev[kMaxDevices] = {};  // device address of `scratch`, per device
+int g_batch_grid[kMaxDevices] = {};     // persistent-raster workgroups, per device
+
+tgs_status current_device(int* dev) {
+    TGS_HIP(hipGetDevice(dev), "current device");
+    if (*dev < 0 || *dev >= kMaxDevices) return fail(TGS_ERR_UNSUPPORTED, "device index %d >= %d", *dev, kMaxDevices);
+    return TGS_OK;
+}
+
+// Workgroups of the persistent raster on the current device: 8 per CU.
+tgs_status batch_grid(int* grid) {
+    int dev = 0;
+    tgs_status st = current_device(&dev);
+    if (st) return st;
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    if (g_batch_grid[dev] == 0) {
+        int cus = 0;
+        TGS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "device attributes");
+        g_batch_grid[dev] = (cus > 0 ? cus : 1) * 8;
+    }
+    *grid = g_batch_grid[dev];
+    return TGS_OK;
+}
+
+// Device address of the current device's copy of `scratch` (looked up on
+// the first call on each device, with that device current).
+tgs_status scratch_on_current_device(void** out) {
+    int dev = 0;
+    tgs_status st = current_device(&dev);
+    if (st) return st;
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        TGS_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "scratch address");
+        if (!p) return fail(TGS_ERR_HIP, "scratch address: null");
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return TGS_OK;
+}
+
+// Checks the views and fills the kernel arguments of a batched raster;
+// blocks = the 8x8 blocks of all views.
+tgs_status batch_args(int32_t num_views, const tgs_projected* pr, const tgs_binned* b, const tgs_camera* cams,
+                      const tgs_params* params, const int32_t* orders, const float* bg, float* const* rgb,
+                      float* const* alpha, int32_t* const* last, BatchArgs& a, int64_t& blocks) {
     if (num_views < 1 || num_views > kMaxViews) return fail(TGS_ERR_INVALID_ARG, "num_views %d outside 1..%d", num_views, kMaxViews);
     if (!pr || !b || !cams || !params || !orders || !bg || !rgb || !alpha || !last)
         return fail(TGS_ERR_INVALID_ARG, "an argument array is NULL");
-    BatchArgs a{};
+    a = BatchArgs{};
     a.nv = num_views;
     for (int i = 0; i < 3; ++i) a.bg[i] = bg[i];
-    int64_t tiles = 0, blocks = 0;
+    int64_t tiles = 0;
+    blocks = 0;
     for (int v = 0; v < num_views; ++v) {
         tgs_status st = check_projected(&pr[v]);
         if (st) return st;
@@ -627,17 +685,17 @@ tgs_status tgs_rasterize_batch(int32_t num_views, const tgs_projected* pr, const
     }
     if (tiles >= ((int64_t)1 << 31) || blocks >= ((int64_t)1 << 32)) return fail(TGS_ERR_INVALID_ARG, "too many tiles");
     a.tile_base[num_views] = (uint32_t)tiles;
-    const size_t need = tgs_batch_workspace_size(num_views, cams, params);
-    if (!ws || ws_bytes < need) return fail(TGS_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
-    if (reinterpret_cast<uintptr_t>(ws) & 255) return fail(TGS_ERR_WORKSPACE, "workspace not 256-byte aligned");
-    static int grid = 0;
-    if (grid == 0) {
-        int dev = 0, cus = 0, occ = 0;
-        TGS_HIP(hipGetDevice(&dev), "device");
-        TGS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "device attributes");
-        occ = 8;
-        grid = cus * occ;
-    }
+    return TGS_OK;
+}
+
+// Enqueues the batched raster with its control words and work list in ws
+// (at least tgs_batch_workspace_size bytes, 256-byte aligned): a fill kernel
+// clears the control words, then the two ordering launches and the
+// persistent launch.
+tgs_status batch_launch(const BatchArgs& a, int64_t blocks, void* ws, void* stream) {
+    int grid = 0;
+    tgs_status st = batch_grid(&grid);
+    if (st) return st;
     const int64_t want = (blocks + 3) / 4;
     const int g = (int)(want < grid ? want : grid);
     hipStream_t s = (hipStream_t)stream;
@@ -645,6 +703,45 @@ tgs_status tgs_rasterize_batch(int32_t num_views, const tgs_projected* pr, const
     TGS_HIP(launch_fill_u32(ctl, 0u, 256, s), "clear batch control words");
     TGS_HIP(launch_raster_batch(a, ctl, ctl + 256, blocks, g > 0 ? g : 1, s), "batched raster");
     return TGS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tgs_status tgs_rasterize_batch(int32_t num_views, const tgs_projected* pr, const tgs_binned* b,
+                               const tgs_camera* cams, const tgs_params* params, const int32_t* orders,
+                               const float* bg, float* const* rgb, float* const* alpha, int32_t* const* last,
+                               void* ws, size_t ws_bytes, void* stream) {
+    g_err.clear();
+    BatchArgs a{};
+    int64_t blocks = 0;
+    tgs_status st = batch_args(num_views, pr, b, cams, params, orders, bg, rgb, alpha, last, a, blocks);
+    if (st) return st;
+    const size_t need = tgs_batch_workspace_size(num_views, cams, params);
+    if (!ws || ws_bytes < need) return fail(TGS_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+    if (reinterpret_cast<uintptr_t>(ws) & 255) return fail(TGS_ERR_WORKSPACE, "workspace not 256-byte aligned");
+    return batch_launch(a, blocks, ws, stream);
+}
+
+tgs_status tgs_rasterize_batch_noalloc(int32_t num_views, const tgs_projected* pr, const tgs_binned* b,
+                                       const tgs_camera* cams, const tgs_params* params, const int32_t* orders,
+                                       const float* bg, float* const* rgb, float* const* alpha,
+                                       int32_t* const* last, void* stream) {
+    g_err.clear();
+    BatchArgs a{};
+    int64_t blocks = 0;
+    tgs_status st = batch_args(num_views, pr, b, cams, params, orders, bg, rgb, alpha, last, a, blocks);
+    if (st) return st;
+    const size_t need = tgs_batch_workspace_size(num_views, cams, params);
+    if (need > kScratchBytes)
+        return fail(TGS_ERR_WORKSPACE,
+                    "tgs_rasterize_batch_noalloc: these views need %zu bytes of scratch (%lld 8x8 blocks), the "
+                    "fixed scratch holds %zu; use tgs_rasterize_batch with a workspace",
+                    need, (long long)blocks, kScratchBytes);
+    void* ws = nullptr;
+    if ((st = scratch_on_current_device(&ws))) return st;
+    return batch_launch(a, blocks, ws, stream);
 }
 
 tgs_status tgs_tile_features(const tgs_binned* b, const tgs_camera* cam, const tgs_params* params, float* features,
