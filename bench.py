@@ -26,38 +26,53 @@ import numpy as np  # noqa: E402
 
 import scenes  # noqa: E402
 
-# MI355X fp32 vector peak 157.3 TFLOP/s = 256 CUs x 128 FMA lanes x 2 FLOP x
-# 2.4 GHz; counting one lane-op per VALU lane operation (an FMA is one),
-# 256 x 128 x 2.4e9 = 78.6e12 lane-op/s. (Measured wave64 VALU issue of the
-# rasters exceeds one instruction per CU per cycle, so 64 lanes per cycle is
-# not the bound.)
-PEAK_LANE_OPS = 256 * 128 * 2.4e9
-# algorithmic lane-op slots per alpha-supported pixel test: 2 sub (dx, dy),
-# 5 for q, 1 mul (opacity), 2 compares, 1 min, 2 for T (1 - alpha), 1 mul
-# (weight), 3 fma (colour); exp2 on the quarter-rate transcendental unit = 4
-OPS_PER_TEST = 17 + 4
+# Roofline of the raster (no dense contraction, so plain VALU): the published
+# MI355X fp32 vector peak, 157.3 TFLOP/s (256 CUs x 128 fp32 lanes x 2 FLOP x
+# 2.4 GHz, the lane count that packed fp32 reaches). The algorithmic work is
+# 15 fp32 operations per alpha-supported pixel test: 2 sub (dx, dy), 5 for q,
+# 1 exp, 1 mul (opacity), 1 min, 1 sub + 1 mul (T (1 - alpha)), 3 fma
+# (colour), counted once each.
+PEAK_FP32_FLOPS = 157.3e12
+FLOPS_PER_TEST = 15
+# the same work against one fp32 operation per lane per cycle on 64 lanes per
+# CU (the issue rate of unpacked wave64 VALU instructions): 3.93e13 op/s
+PEAK_LANE_OPS_64 = 256 * 64 * 2.4e9
 HBM_PEAK = 8.0e12
 
 
-def profiled_traffic():
-    """HBM bytes per launch of the product raster from the committed counter
-    summary (FETCH_SIZE / WRITE_SIZE scaled by a 256 MiB copy), or None when
-    the raster sources changed since the counters were taken."""
+def profiled_counters():
+    """Counter figures of the product raster from the committed summary
+    (profiles/raster_1080p.md): HBM bytes per launch (FETCH_SIZE and
+    WRITE_SIZE scaled by a 256 MiB copy) and the measured VALU issue, or
+    None for both when the raster sources changed since the counters were
+    taken."""
     import hashlib
     import re
     path = os.path.join(ROOT, "profiles", "raster_1080p.md")
     if not os.path.exists(path):
-        return None
+        return None, None
     h = hashlib.sha256()
     for f in ("raster.hip", "raster.hpp", "common.hpp"):
         with open(os.path.join(ROOT, "paper_2609_03613_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     text = open(path).read()
     m_hash = re.search(r"source_sha256: ([0-9a-f]+)", text)
+    if not m_hash or m_hash.group(1) != h.hexdigest():
+        return None, None
     m_traffic = re.search(r"traffic_bytes_per_launch: ([0-9.e+]+)", text)
-    if not m_hash or not m_traffic or m_hash.group(1) != h.hexdigest():
-        return None
-    return float(m_traffic.group(1))
+    m_valu = re.search(r"valu_insts_per_launch: ([0-9.e+]+)", text)
+    m_dur = re.search(r"valu_kernel_us: ([0-9.e+]+)", text)
+    traffic = float(m_traffic.group(1)) if m_traffic else None
+    issue = None
+    if m_valu and m_dur:
+        insts, us = float(m_valu.group(1)), float(m_dur.group(1))
+        # wave64 VALU instructions x 64 lanes against 64 lanes per CU per cycle
+        issue = {"valu_insts_per_launch": insts, "kernel_us": us,
+                 "achieved_lane_ops_per_s": insts * 64 / (us * 1e-6), "peak_lane_ops_per_s": PEAK_LANE_OPS_64,
+                 "frac": insts * 64 / (us * 1e-6) / PEAK_LANE_OPS_64,
+                 "note": "rocprofv3 SQ_INSTS_VALU of the product raster x 64 lanes per kernel second, against one "
+                         "wave64 VALU instruction per CU per cycle (256 CUs x 64 lanes x 2.4 GHz)"}
+    return traffic, issue
 
 
 def parse():
@@ -69,7 +84,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--mode", default="frame", choices=["frame", "kernels", "train", "batch", "learned", "repair",
-                                                      "scale", "stress"],
+                                                      "scale", "stress", "oracle-single"],
                     help="kernels: only launch the product and comparator raster kernels and a "
                          "256 MiB device copy (for profiler counter runs); train: only the training "
                          "step (forward + backward) on the 500k-Gaussian 1297x840 scene")
@@ -77,6 +92,7 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched multi-camera measurement")
     ap.add_argument("--no-repair", action="store_true", help="skip the repair-variant ablation")
     ap.add_argument("--no-ksweep", action="store_true", help="skip the bins-per-tile sweep")
+    ap.add_argument("--no-scale", action="store_true", help="skip the 10M-Gaussian scale-up point")
     ap.add_argument("--scale-sizes", default="5,10,15,20,25,30",
                     help="Gaussian counts (millions) of --mode scale, comma separated")
     return ap.parse_args()
@@ -561,28 +577,147 @@ def workload(name):
     return g, cam, desc
 
 
-def cpu_baseline(g, cam, budget_s):
-    """The FP64 oracle (project + schedule + tiled composite) on the host,
-    repeated whole frames until about budget_s seconds have passed."""
+def cpu_baseline(g, cam, budget_s, gpu_image=None):
+    """The FP64 oracle (project + tiled composite of every pixel) on the
+    host's cores, repeated whole frames for about budget_s seconds; one frame
+    on a single core in a child process; the oracle on the small forward
+    workload and on the 200-Gaussian adjoint sub-case of the training scene.
+    With gpu_image (rgb, alpha of the product frame), the largest difference
+    to the oracle's frame over the pixels it did not flag, and their count."""
+    import subprocess
     import oracle
     frames, M = 0, 0
     t0 = time.perf_counter()
     while True:
         p = oracle.project(g, cam)
         M = oracle.count_entries(p["rect"])
-        oracle.render(p, cam["width"], cam["height"])
+        ref = oracle.render(p, cam["width"], cam["height"])
         frames += 1
         el = time.perf_counter() - t0
         if el >= budget_s or frames >= 50:
             break
-    return {"value": M * frames / el, "unit": "Gaussian-tile pairs/s", "cores": oracle.num_threads(),
-            "kind": "oracle", "sample": f"{frames} whole frame(s) of the same workload in {el:.1f} s "
-                                       f"(FP64 projection + tiled compositing of all {cam['width']}x{cam['height']} px)",
-            "ms_per_frame": 1000.0 * el / frames}
+    out = {"value": M * frames / el, "unit": "Gaussian-tile pairs/s", "cores": oracle.num_threads(),
+           "kind": "oracle", "sample": f"{frames} whole frame(s) of the same workload in {el:.1f} s "
+                                      f"(FP64 projection + tiled compositing of all {cam['width']}x{cam['height']} px)",
+           "ms_per_frame": 1000.0 * el / frames}
+    if gpu_image is not None:
+        rgb, alpha = gpu_image
+        m = ref["flags"] == 0
+        out["max_abs_vs_oracle"] = {"rgb": float(np.abs(rgb.astype(np.float64) - ref["rgb"])[m].max()),
+                                    "alpha": float(np.abs(alpha.astype(np.float64) - ref["alpha"])[m].max())}
+        out["masked_pixels"] = int((~m).sum())
+        out["pixels"] = int(m.size)
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--mode", "oracle-single"], env=env,
+                       capture_output=True, text=True, timeout=600)
+    if r.returncode == 0 and r.stdout.strip():
+        out["single_core"] = json.loads(r.stdout.strip().splitlines()[-1])
+    else:
+        out["single_core"] = {"error": (r.stderr or "")[-300:]}
+    # the small forward workload and the adjoint sub-case, all host cores
+    gs, cs = scenes.small_forward(seed=0)
+    t0 = time.perf_counter()
+    k = 0
+    while k < 20 or time.perf_counter() - t0 < 0.5:
+        ps = oracle.project(gs, cs)
+        oracle.render(ps, cs["width"], cs["height"])
+        k += 1
+    out["small_forward_ms_per_frame"] = 1000.0 * (time.perf_counter() - t0) / k
+    gf, cf = scenes.fd_subcase()
+    tgt = scenes.training_target(cf["width"], cf["height"])
+    g64 = {kk: (np.asarray(v, np.float64) if kk != "sh_degree" else v) for kk, v in gf.items()}
+    t0 = time.perf_counter()
+    k = 0
+    while k < 10 or time.perf_counter() - t0 < 0.5:
+        a = oracle.adjoint(g64, cf)
+        _, up = oracle.mse_upstream(a["rgb"], tgt)
+        oracle.adjoint(g64, cf, d_img=up)
+        k += 1
+    out["adjoint_subcase_ms"] = 1000.0 * (time.perf_counter() - t0) / k
+    return out
+
+
+def oracle_single_core():
+    """One whole 1080p oracle frame on one core (run as a child process with
+    OMP_NUM_THREADS=1); prints one JSON line."""
+    import oracle
+    g, cam, _ = workload("1080p")
+    t0 = time.perf_counter()
+    p = oracle.project(g, cam)
+    M = oracle.count_entries(p["rect"])
+    oracle.render(p, cam["width"], cam["height"])
+    el = time.perf_counter() - t0
+    print(json.dumps({"cores": oracle.num_threads(), "ms_per_frame": 1000.0 * el, "value": M / el,
+                      "unit": "Gaussian-tile pairs/s", "sample": "1 whole frame"}), flush=True)
+
+
+def timed_frames(frame, steps, stream):
+    """Runs `steps` frames with 4 HIP events each on the launch stream;
+    returns (wall ms per frame, [steps, 3] stage ms, [steps] frame ms)."""
+    import torch
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        frame(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = np.array([[evs[k][j].elapsed_time(evs[k][j + 1]) for j in range(3)] for k in range(steps)])
+    tot = np.array([evs[k][0].elapsed_time(evs[k][3]) for k in range(steps)])
+    return 1000.0 * wall / steps, st, tot
+
+
+def scale_point(args, n_m=10):
+    """One point of the synthetic scale-up (the 1080p structure with n_m
+    million Gaussians): ordering stage, raster and whole frame, binned
+    against the globally sorted comparator (sync-free, capacity sized to the
+    entry count), medians of HIP-event-timed frames."""
+    import torch
+    import paper_2609_03613_amd as tg
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    steps = max(min(args.steps, 10), 5)
+    g, cam = scenes.scene_1080p(seed=0, n=n_m * 1_000_000)
+    gd = tg.to_device(g, dev)
+    del g
+    rb = tg.Renderer(cam, tg.Params(), device=dev)
+    rg = tg.Renderer(cam, tg.Params(raster="plain", tile_order=False), device=dev)
+    s, i = tg.project(gd, cam)
+    M = rb.bin(s, i, "binned", sync=True).num_entries
+    rg.bin(s, i, "global", capacity=int(M * 1.02) + 1024, sync=True)
+    H, W = cam["height"], cam["width"]
+    buf = {"rgb": torch.empty((H, W, 3), device=dev), "alpha": torch.empty((H, W), device=dev),
+           "last": torch.empty((H, W), dtype=torch.int32, device=dev)}
+
+    def run(r, order):
+        def frame(e=None):
+            if e: e[0].record(stream)
+            tg.project(gd, cam, r.params, out=(s, i))
+            if e: e[1].record(stream)
+            b = r.bin(s, i, order, sync=False)
+            if e: e[2].record(stream)
+            r.rasterize(s, i, b, out=buf)
+            if e: e[3].record(stream)
+        for _ in range(2):
+            frame()
+        _, st, tot = timed_frames(frame, steps, stream)
+        med = np.median(st, 0)
+        return {"order_ms": float(med[1]), "raster_ms": float(med[2]), "frame_ms": float(np.median(tot))}
+
+    b = run(rb, "binned")
+    gl = run(rg, "global")
+    del gd, rb, rg, s, i
+    torch.cuda.empty_cache()
+    return {"workload": f"1080p scene-shaped structure, {n_m}M Gaussians, SH3, 1920x1080, f=1100",
+            "gaussians": n_m * 1_000_000, "entries": M, "binned": b, "global": gl,
+            "order_x": gl["order_ms"] / b["order_ms"], "raster_x": gl["raster_ms"] / b["raster_ms"],
+            "frame_x": gl["frame_ms"] / b["frame_ms"], "pairs_per_s": M / (b["frame_ms"] * 1e-3)}
 
 
 def main():
     args = parse()
+    if args.mode == "oracle-single":
+        return oracle_single_core()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path shards by screen tiles "
               f"but multi-GPU runs are not part of this build", file=sys.stderr)
@@ -620,74 +755,65 @@ def main():
     g, cam, desc = workload(args.config)
     gd = tg.to_device(g, dev)
     stream = torch.cuda.current_stream()
+    H, W = cam["height"], cam["width"]
 
-    # the product: binned stream, wave raster gathering by id and culling
-    # per 8x8 block
+    # the product: binned stream, wave raster gathering by id and culling per
+    # 8x8 block, heaviest tiles first, the longest tiles split
     rb = tg.Renderer(cam, tg.Params(raster="wave", packed=0), device=dev)
     # the comparator: globally sorted stream, one workgroup per tile gathering
     # batches by id, tiles in raster order
     rg = tg.Renderer(cam, tg.Params(raster="plain", packed=0, tile_order=False), device=dev)
+    # the comparator's stream through the product raster (tile order + split):
+    # separates what binning earns from what the raster kernel earns
+    rgw = tg.Renderer(cam, tg.Params(raster="wave", packed=0), device=dev)
+    # the comparator as the library first shipped it: host read of the entry
+    # count before the sort
+    rgs = tg.Renderer(cam, tg.Params(raster="plain", packed=0, tile_order=False), device=dev)
 
-    # first frames: size the entry buffers (host reads the entry count once)
+    # first frames size the entry buffers; the sync-free global streams get a
+    # capacity of the entry count + 2 % (their sort runs over the capacity)
     splats, info = tg.project(gd, cam)
-    bb = rb.bin(splats, info, "binned", sync=True)
-    M = bb.num_entries
-    bgl = rg.bin(splats, info, "global", sync=True)
-    assert bgl.num_entries == M
+    M = rb.bin(splats, info, "binned", sync=True).num_entries
+    cap_g = int(M * 1.02) + 1024
+    for r in (rg, rgw, rgs):
+        assert r.bin(splats, info, "global", capacity=cap_g, sync=True).num_entries == M
     torch.cuda.synchronize()
 
-    def ev():
-        return torch.cuda.Event(enable_timing=True)
+    def mk():
+        return {"rgb": torch.empty((H, W, 3), dtype=torch.float32, device=dev),
+                "alpha": torch.empty((H, W), dtype=torch.float32, device=dev),
+                "last": torch.empty((H, W), dtype=torch.int32, device=dev)}
 
-    def binned_frame(evs=None):
-        if evs: evs[0].record(stream)
-        s, i = tg.project(gd, cam)
-        if evs: evs[1].record(stream)
-        b = rb.bin(s, i, "binned", sync=False)
-        if evs: evs[2].record(stream)
-        out = rb.rasterize(s, i, b, out=out_b)
-        if evs: evs[3].record(stream)
-        return out
+    bufs = {k: mk() for k in ("binned", "global", "global_product_raster", "global_host_sync")}
 
-    def global_frame(evs=None):
-        if evs: evs[0].record(stream)
-        s, i = tg.project(gd, cam)
-        if evs: evs[1].record(stream)
-        b = rg.bin(s, i, "global", sync=True)
-        if evs: evs[2].record(stream)
-        out = rg.rasterize(s, i, b, out=out_g)
-        if evs: evs[3].record(stream)
-        return out
+    def frame_fn(r, order, out, sync=False):
+        def frame(evs=None):
+            if evs: evs[0].record(stream)
+            s, i = tg.project(gd, cam, r.params, out=(splats, info))
+            if evs: evs[1].record(stream)
+            b = r.bin(s, i, order, sync=sync)
+            if evs: evs[2].record(stream)
+            r.rasterize(s, i, b, out=out)
+            if evs: evs[3].record(stream)
+        return frame
 
-    H, W = cam["height"], cam["width"]
-    mk = lambda: {"rgb": torch.empty((H, W, 3), dtype=torch.float32, device=dev),
-                  "alpha": torch.empty((H, W), dtype=torch.float32, device=dev),
-                  "last": torch.empty((H, W), dtype=torch.int32, device=dev)}
-    out_b, out_g = mk(), mk()
-
+    frames = {"binned": frame_fn(rb, "binned", bufs["binned"]),
+              "global": frame_fn(rg, "global", bufs["global"]),
+              "global_product_raster": frame_fn(rgw, "global", bufs["global_product_raster"]),
+              "global_host_sync": frame_fn(rgs, "global", bufs["global_host_sync"], sync=True)}
     for _ in range(args.warmup):
-        binned_frame()
-        global_frame()
+        for f in frames.values():
+            f()
     torch.cuda.synchronize()
+    timing = {k: timed_frames(f, args.steps, stream) for k, f in frames.items()}
+    frame_ms = {k: v[0] for k, v in timing.items()}
+    stage = {k: np.median(v[1], 0).tolist() for k, v in timing.items()}
 
-    def timed(frame):
-        evs = [[ev() for _ in range(4)] for _ in range(args.steps)]
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for k in range(args.steps):
-            frame(evs[k])
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        st = np.array([[evs[k][j].elapsed_time(evs[k][j + 1]) for j in range(3)] for k in range(args.steps)])
-        tot = np.array([evs[k][0].elapsed_time(evs[k][3]) for k in range(args.steps)])
-        return wall, st, tot
-
-    wall_b, st_b, tot_b = timed(binned_frame)
-    wall_g, st_g, tot_g = timed(global_frame)
-
-    # raster kernel alone, back to back on the prepared streams
+    # raster kernel alone, back to back on prepared streams (HIP events on the
+    # launch stream around every launch)
     def raster_only(r, b, out):
-        evs = [ev() for _ in range(args.steps + 1)]
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+        torch.cuda.synchronize()
         evs[0].record(stream)
         for k in range(args.steps):
             r.rasterize(splats, info, b, out=out)
@@ -695,11 +821,15 @@ def main():
         torch.cuda.synchronize()
         return np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)])
 
-    splats, info = tg.project(gd, cam)
+    tg.project(gd, cam, out=(splats, info))
     bb = rb.bin(splats, info, "binned", sync=False)
-    bgl = rg.bin(splats, info, "global", sync=True)
-    ras_b = raster_only(rb, bb, out_b)
-    ras_g = raster_only(rg, bgl, out_g)
+    bgl = rg.bin(splats, info, "global", sync=False)
+    bglw = rgw.bin(splats, info, "global", sync=False)
+    ras_b = raster_only(rb, bb, bufs["binned"])
+    ras_g = raster_only(rg, bgl, bufs["global"])
+    ras_gw = raster_only(rgw, bglw, bufs["global_product_raster"])
+    same_product = bool(torch.equal(bufs["binned"]["rgb"], bufs["global_product_raster"]["rgb"]) and
+                        torch.equal(bufs["binned"]["last"], bufs["global_product_raster"]["last"]))
 
     # ablation: the same streams through the other kernels and layouts; each
     # binned variant re-bins with its own options, timed separately
@@ -707,14 +837,16 @@ def main():
     bb_noorder = copy.copy(bb)
     bb_noorder.tile_order = None
     ablation = {"binned wave cull-in-raster (product)": float(np.median(ras_b)),
-                "binned wave cull-in-raster, raster-order tiles": float(np.median(raster_only(rb, bb_noorder, out_b)))}
+                "binned wave cull-in-raster, raster-order tiles": float(np.median(raster_only(rb, bb_noorder,
+                                                                                             bufs["binned"]))),
+                "global wave cull-in-raster, tile order + split (product raster)": float(np.median(ras_gw))}
     bin_ms = {}
     for name, prm in [("binned wave records+masks", tg.Params(raster="wave", packed=1)),
                       ("binned wave masks", tg.Params(raster="wave", packed=2)),
                       ("binned plain gather-by-id", tg.Params(raster="plain", packed=0))]:
         rv = tg.Renderer(cam, prm, device=dev)
         bv = rv.bin(splats, info, "binned", sync=True)
-        e0, e1 = ev(), ev()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         e0.record(stream)
         for _ in range(args.steps):
@@ -722,9 +854,8 @@ def main():
         e1.record(stream)
         torch.cuda.synchronize()
         bin_ms[name] = e0.elapsed_time(e1) / args.steps
-        ablation[name] = float(np.median(raster_only(rv, bv, out_b)))
-    r_wave_gather = tg.Renderer(cam, tg.Params(raster="wave", packed=0), device=dev)
-    ablation["global wave cull-in-raster"] = float(np.median(raster_only(r_wave_gather, bgl, out_g)))
+        ablation[name] = float(np.median(raster_only(rv, bv, bufs["binned"])))
+        del rv, bv
     ablation["global plain gather-by-id (comparator)"] = float(np.median(ras_g))
 
     # instrumented launches (outside the timed region): algorithmic work
@@ -743,21 +874,25 @@ def main():
     split_diff = float((cb["rgb"] - cu["rgb"]).abs().max().item())
     split_last_equal = bool(torch.equal(cb["last"], cu["last"]))
     n_split = [int(v) for v in bb.tile_order[-2:].tolist()]
+    gpu_image = (cb["rgb"].cpu().numpy(), cb["alpha"].cpu().numpy())
+    del cb, cg, cu, r_unsplit
 
     raster_ms_b = float(np.median(ras_b))
     raster_ms_g = float(np.median(ras_g))
-    frame_ms_b = 1000.0 * wall_b / args.steps
-    frame_ms_g = 1000.0 * wall_g / args.steps
-    ops = n_support * OPS_PER_TEST
-    achieved = ops / (float(np.mean(ras_b)) * 1e-3)
+    raster_ms_gw = float(np.median(ras_gw))
+    t_mean = float(np.mean(ras_b)) * 1e-3
+    flops = n_support * FLOPS_PER_TEST
+    achieved = flops / t_mean
+    traffic, issue = profiled_counters()
+    fb = frame_ms["binned"]
     result = {
         "metric": "raster-kernel ms/frame at 1080p, binned vs global-sort; Gaussian-tile pairs/s",
-        "value": M / (frame_ms_b * 1e-3),
+        "value": M / (fb * 1e-3),
         "unit": "Gaussian-tile pairs/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": frame_ms_b,
+        "ms_per_step": fb,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -767,13 +902,27 @@ def main():
                    "tile": 16, "bins": 64, "entries": M},
         "raster_ms": {"binned": raster_ms_b, "global": raster_ms_g, "speedup": raster_ms_g / raster_ms_b,
                       "binned_p10_p90": [float(np.percentile(ras_b, 10)), float(np.percentile(ras_b, 90))],
-                      "global_p10_p90": [float(np.percentile(ras_g, 10)), float(np.percentile(ras_g, 90))]},
+                      "global_p10_p90": [float(np.percentile(ras_g, 10)), float(np.percentile(ras_g, 90))],
+                      "global_product_raster": raster_ms_gw},
         "raster_pairs_per_s": {"binned": M / (raster_ms_b * 1e-3), "global": M / (raster_ms_g * 1e-3)},
-        "frame_ms": {"binned": frame_ms_b, "global": frame_ms_g, "speedup": frame_ms_g / frame_ms_b},
-        "fps": {"binned": 1000.0 / frame_ms_b, "global": 1000.0 / frame_ms_g},
+        "frame_ms": {"binned": fb, "global": frame_ms["global"], "speedup": frame_ms["global"] / fb,
+                     "global_product_raster": frame_ms["global_product_raster"],
+                     "global_host_sync": frame_ms["global_host_sync"]},
+        "fps": {"binned": 1000.0 / fb, "global": 1000.0 / frame_ms["global"]},
+        "binning_attributable": {
+            "note": "the same product raster (wave walk, heaviest tiles first, longest tiles split) on the binned "
+                    "and on the globally sorted stream: what the ordering stage itself earns",
+            "ordering_stage_x": stage["global_product_raster"][1] / stage["binned"][1],
+            "frame_same_raster_x": frame_ms["global_product_raster"] / fb,
+            "raster_same_kernel_x": raster_ms_gw / raster_ms_b,
+            "images_equal": same_product},
         "stage_ms_median": {
-            "binned": dict(zip(["project", "bin+repair+pack", "raster"], np.median(st_b, 0).tolist())),
-            "global": dict(zip(["project", "emit+sort+ranges", "raster"], np.median(st_g, 0).tolist())),
+            "binned": dict(zip(["project", "bin+repair", "raster"], stage["binned"])),
+            "global": dict(zip(["project", "emit+sort+ranges", "raster"], stage["global"])),
+            "global_product_raster": dict(zip(["project", "emit+sort+ranges+tile order", "raster"],
+                                              stage["global_product_raster"])),
+            "global_host_sync": dict(zip(["project", "emit+count read+sort+ranges", "raster"],
+                                         stage["global_host_sync"])),
         },
         "tests_per_pixel": {"support": n_support / (W * H), "visit_binned": n_visit_b / (W * H),
                             "visit_global": n_visit_g / (W * H)},
@@ -782,11 +931,18 @@ def main():
                              "max_abs_diff_vs_unsplit": split_diff, "last_equal": split_last_equal},
         "raster_ablation_ms": ablation,
         "bin_stage_ms_by_variant": bin_ms,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_LANE_OPS, "unit": "lane-op/s",
-                     "frac": achieved / PEAK_LANE_OPS, "traffic": profiled_traffic(),
-                     "kernel": "raster_split_kernel (binned, gather by id, per-block cull, longest tiles split)",
-                     "work": f"{n_support} alpha-supported pixel tests x {OPS_PER_TEST} lane-op slots"},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_FLOPS / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_FLOPS, "traffic": traffic,
+                     "kernel": "raster_split_kernel<1,false> (binned, gather by id, per-block cull, longest tiles "
+                               "split)",
+                     "work": f"{n_support} alpha-supported pixel tests x {FLOPS_PER_TEST} fp32 ops / mean launch "
+                             f"{t_mean * 1e6:.1f} us",
+                     "frac_vs_64_lanes_per_cu": flops / t_mean / PEAK_LANE_OPS_64,
+                     "frac_with_visits": n_visit_b * FLOPS_PER_TEST / t_mean / PEAK_FP32_FLOPS,
+                     "valu_issue": issue},
     }
+    if not args.no_scale:
+        result["scale_point"] = scale_point(args)
     if not args.no_repair:
         result["repair_ablation"] = repair_ablation(args, gd, cam)
     if not args.no_ksweep:
@@ -796,7 +952,7 @@ def main():
     if not args.no_batch:
         result["batched"] = batched(args)
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(g, cam, args.cpu_seconds)
+        result["cpu_baseline"] = cpu_baseline(g, cam, args.cpu_seconds, gpu_image)
     print(json.dumps(result), flush=True)
 
 

@@ -35,7 +35,7 @@
  *    allocations are); another start address fails with TGS_ERR_WORKSPACE.
  *  - Every call enqueues on `stream` (a hipStream_t, NULL = default stream)
  *    and returns without waiting, except tgs_bin with a non-NULL
- *    num_entries_host, which waits for the entry count.
+ *    num_entries_host, which waits for the entry count (both orders).
  *  - Arguments are validated on the host before anything is launched; on an
  *    error nothing is enqueued and outputs are untouched. tgs_last_error()
  *    returns a message for the last failing call on the calling thread.
@@ -256,7 +256,10 @@ TGS_API size_t tgs_bin_workspace_size(int64_t n, int64_t capacity, const tgs_cam
    synchronisation (an overflow is only reported through counters[2]);
    non-NULL = wait for the entry count, store it there, and return
    TGS_ERR_CAPACITY without building the stream when it exceeds capacity.
-   The GLOBAL order always synchronises (the radix sort needs the count). */
+   GLOBAL order without the host count: the radix sort runs over all
+   `capacity` slots, those past the entry count padded with keys past the
+   last tile (they stay out of the tile ranges), so its cost follows the
+   capacity; size it close to the expected entry count. */
 TGS_API tgs_status tgs_bin(const tgs_projected* projected, const tgs_camera* camera,
                    const tgs_params* params, int32_t order, void* workspace_dev,
                    size_t workspace_bytes, tgs_binned* out, int64_t* num_entries_host,

@@ -890,6 +890,21 @@ __global__ void __launch_bounds__(256) emit_keys_kernel(const uint4* __restrict_
                                       });
 }
 
+// Without a host-side entry count the sort runs over all `capacity` slots:
+// the slots past the device count M get keys of tile T (past the last
+// tile), which sort after every real entry and which tile_ranges_kernel
+// leaves out (tile_off[T] = M).
+__global__ void __launch_bounds__(256) pad_keys_kernel(uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                                                       const int64_t* __restrict__ counters, int64_t capacity,
+                                                       uint64_t pad) {
+    const int64_t m = counters[0];
+    for (int64_t i = (m > 0 ? m : 0) + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < capacity;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        keys[i] = pad;
+        vals[i] = 0u;
+    }
+}
+
 // tile_off[t] = first position whose tile is >= t (t = 0..T).
 __global__ void __launch_bounds__(256) tile_ranges_kernel(const uint64_t* __restrict__ keys, int64_t m, int64_t T,
                                                           uint32_t* __restrict__ tile_off) {
@@ -1043,6 +1058,15 @@ hipError_t launch_emit_keys(const uint32_t* info, int64_t n, const uint32_t* emi
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(emit_keys_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s,
                        reinterpret_cast<const uint4*>(info), n, emit_off, tiles_x, tiles_y, keys, vals, capacity);
+    return hipGetLastError();
+}
+
+hipError_t launch_pad_keys(uint64_t* keys, uint32_t* vals, const int64_t* counters, int64_t capacity, int64_t T,
+                           hipStream_t s) {
+    if (capacity <= 0) return hipSuccess;
+    const unsigned grid = (unsigned)std::min<int64_t>((capacity + 255) / 256, 2048);
+    hipLaunchKernelGGL(pad_keys_kernel, dim3(grid), dim3(256), 0, s, keys, vals, counters, capacity,
+                       (uint64_t)T << 32);
     return hipGetLastError();
 }
 

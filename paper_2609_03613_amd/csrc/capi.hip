@@ -220,7 +220,7 @@ Layout layout(int64_t n, int64_t capacity, int64_t T, int K, int order, bool var
     } else {
         L.keys_in = take(sizeof(uint64_t) * (size_t)capacity);
         L.vals_in = take(sizeof(uint32_t) * (size_t)capacity);
-        L.sort_tmp_bytes = global_sort_tmp_bytes(capacity, end_bit_for(T)) + 1024;
+        L.sort_tmp_bytes = global_sort_tmp_bytes(capacity, end_bit_for(T + 1)) + 1024;
         L.sort_tmp = take(L.sort_tmp_bytes);
     }
     L.total = off;
@@ -331,7 +331,7 @@ tgs_status tgs_bin(const tgs_projected* pr, const tgs_camera* cam, const tgs_par
                              out->counters_dev, cap, s),
             "emit scan");
     int64_t M = -1;
-    if (num_entries_host || order == TGS_ORDER_GLOBAL) {
+    if (num_entries_host) {
         TGS_HIP(hipMemcpyAsync(&M, out->counters_dev, sizeof(int64_t), hipMemcpyDeviceToHost, s), "read entry count");
         TGS_HIP(hipStreamSynchronize(s), "read entry count");
         if (num_entries_host) *num_entries_host = M;
@@ -341,10 +341,19 @@ tgs_status tgs_bin(const tgs_projected* pr, const tgs_camera* cam, const tgs_par
         uint64_t* keys_in = (uint64_t*)(w + L.keys_in);
         uint32_t* vals_in = (uint32_t*)(w + L.vals_in);
         TGS_HIP(launch_emit_keys(pr->info_dev, n, emit_off, tiles_x, tiles_y, keys_in, vals_in, cap, s), "emit keys");
-        TGS_HIP(launch_global_sort(w + L.sort_tmp, L.sort_tmp_bytes, keys_in, out->keys_dev, vals_in, out->vals_dev, M,
-                                   end_bit_for(T), s),
+        // without the host count: sort every slot, the unused ones padded
+        // with keys past the last tile
+        int64_t sort_n = M;
+        int end_bit = end_bit_for(T);
+        if (M < 0) {
+            TGS_HIP(launch_pad_keys(keys_in, vals_in, out->counters_dev, cap, T, s), "pad keys");
+            sort_n = cap;
+            end_bit = end_bit_for(T + 1);
+        }
+        TGS_HIP(launch_global_sort(w + L.sort_tmp, L.sort_tmp_bytes, keys_in, out->keys_dev, vals_in, out->vals_dev,
+                                   sort_n, end_bit, s),
                 "radix sort");
-        TGS_HIP(launch_tile_ranges(out->keys_dev, M, T, out->offsets_dev, s), "tile ranges");
+        TGS_HIP(launch_tile_ranges(out->keys_dev, sort_n, T, out->offsets_dev, s), "tile ranges");
         if (out->tile_order_dev)
             TGS_HIP(launch_tile_order(out->offsets_dev, SegMap{nullptr, 1, nullptr}, T, zero + kTileHist,
                                       out->tile_order_dev, params->split_entries, params->split_mean_factor, s),

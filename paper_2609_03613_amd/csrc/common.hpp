@@ -452,6 +452,8 @@ size_t global_sort_tmp_bytes(int64_t capacity, int end_bit);
 hipError_t launch_global_sort(void* tmp, size_t tmp_bytes, uint64_t* keys_in, uint64_t* keys_out,
                               uint32_t* vals_in, uint32_t* vals_out, int64_t m, int end_bit, hipStream_t s);
 hipError_t launch_tile_ranges(const uint64_t* keys, int64_t m, int64_t T, uint32_t* tile_off, hipStream_t s);
+hipError_t launch_pad_keys(uint64_t* keys, uint32_t* vals, const int64_t* counters, int64_t capacity, int64_t T,
+                           hipStream_t s);
 
 struct RasterArgs {
     const float* splats;    // [n][16]

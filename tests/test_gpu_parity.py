@@ -477,3 +477,47 @@ def test_per_tile_bins_bit_exact(ts):
     a1, a2 = to_np(g1).astype(np.float64), to_np(g2).astype(np.float64)
     scale = np.abs(a2).max(axis=0, keepdims=True) + 1e-30
     assert np.all(np.abs(a1 - a2) <= 1e-4 * (np.abs(a2) + 1e-3 * scale))
+
+
+@pytest.mark.parametrize("slack", [0, 1, 4000])
+def test_global_order_without_host_count(slack):
+    # GLOBAL without the host entry count sorts every slot of the capacity,
+    # the unused ones padded past the last tile: the stream, the ranges and
+    # the image equal the oracle's and the synchronised path's
+    n, W, H = 5000, 200, 120
+    splats, info = scenes.random_splats(n, W, H, seed=9, tie_fraction=0.2, hidden_fraction=0.1)
+    cam = cam_for(W, H)
+    depth, rect = scenes.info_depth(info), scenes.info_rects(info)
+    ref = oracle.schedule(depth, rect, 13, 8, znear=cam["znear"], zfar=cam["zfar"])
+    M = ref["M"]
+    r = tg.Renderer(cam, tg.Params(), device=dev())
+    s = torch.as_tensor(splats).to(dev())
+    i = torch.as_tensor(info.view(np.int32)).to(dev())
+    r._binned[0] = tg.Binned("global", M + slack, r.tiles, 64, 0, dev())
+    b = r.bin(s, i, "global", sync=False)
+    out = r.rasterize(s, i, b)
+    torch.cuda.synchronize()
+    assert int(to_np(b.counters)[0]) == M and int(to_np(b.counters)[2]) == 0
+    assert np.array_equal(to_np(b.keys)[:M].view(np.uint64), ref["keys"])
+    assert np.array_equal(to_np(b.vals)[:M].view(np.uint32), ref["vals"])
+    assert np.array_equal(to_np(b.offsets).view(np.uint32), ref["tile_offsets"])
+    rs = tg.Renderer(cam, tg.Params(), device=dev())
+    want = rs.rasterize(s, i, rs.bin(s, i, "global", sync=True))
+    torch.cuda.synchronize()
+    assert torch.equal(out["rgb"], want["rgb"]) and torch.equal(out["last"], want["last"])
+
+
+def test_global_order_without_host_count_overflow():
+    splats, info = scenes.random_splats(2000, 128, 128, seed=5)
+    cam = cam_for(128, 128)
+    M = oracle.count_entries(scenes.info_rects(info))
+    r = tg.Renderer(cam, tg.Params(), device=dev())
+    s = torch.as_tensor(splats).to(dev())
+    i = torch.as_tensor(info.view(np.int32)).to(dev())
+    r._binned[0] = tg.Binned("global", M // 2, r.tiles, 64, 0, dev())
+    b = r.bin(s, i, "global", sync=False)
+    out = r.rasterize(s, i, b)
+    torch.cuda.synchronize()
+    c = to_np(b.counters)
+    assert c[0] == M and c[2] == 1
+    assert np.all(np.isnan(to_np(out["rgb"])))
