@@ -48,7 +48,7 @@ def lib():
         i64, i32, dbl, flt = ctypes.c_int64, ctypes.c_int, ctypes.c_double, ctypes.c_float
         L.orc_num_threads.restype = i32
         L.orc_sh_basis.argtypes = [P, i32, P]
-        L.orc_project.argtypes = [i64, P, P, P, P, P, i32, P, i32, P, P, P, P, P, P, P, P, P]
+        L.orc_project.argtypes = [i64, P, P, P, P, P, i32, P, i32, i32, P, P, P, P, P, P, P, P, P]
         L.orc_render.argtypes = [i64, P, P, P, P, P, P, P, i32, i32, i32, P, i64, P,
                                  P, P, P, P, P, P, P, P]
         L.orc_count_entries.argtypes = [i64, P]
@@ -97,8 +97,13 @@ def sh_basis(direction, degree=3):
     return out[: (degree + 1) ** 2]
 
 
-def project(g, cam, tile_size=16):
-    """FP64 projection of Gaussians ``g`` (scenes.py layout) through ``cam``."""
+FOOTPRINTS = {"opacity": 0, "three_sigma": 1}
+
+
+def project(g, cam, tile_size=16, footprint="opacity"):
+    """FP64 projection of Gaussians ``g`` (scenes.py layout) through ``cam``;
+    ``footprint`` "opacity" (the alpha-support box, the default) or
+    "three_sigma" (the baseline's 3-sigma square, cut at tiles)."""
     n = g["means"].shape[0]
     means = _c(g["means"], np.float32)
     ls = _c(g["log_scales"], np.float32)
@@ -112,7 +117,8 @@ def project(g, cam, tile_size=16):
         "flags": np.zeros(n, np.uint8),
     }
     rc = lib().orc_project(n, _p(means), _p(ls), _p(qs), _p(lg), _p(sh), int(g["sh_degree"]),
-                           _p(cam_array(cam)), int(tile_size), _p(out["mean2d"]), _p(out["cov2d"]),
+                           _p(cam_array(cam)), int(tile_size), FOOTPRINTS[footprint], _p(out["mean2d"]),
+                           _p(out["cov2d"]),
                            _p(out["conic"]), _p(out["depth"]), _p(out["opacity"]), _p(out["rgb"]),
                            _p(out["rect"]), _p(out["depth_key"]), _p(out["flags"]))
     assert rc == 0, rc

@@ -131,13 +131,29 @@ static int near_integer(double v, double tol) {
     return fabs(v - floor(v + 0.5)) < tol;
 }
 
+/*
+ * Footprint (tile rect) rules of orc_project:
+ *  OPACITY_AWARE: the tiles meeting the bounding box of the ellipse where
+ *    o exp(-q/2) >= 1/255, i.e. q <= 2 ln(255 o) (a superset of the alpha
+ *    support, so the image does not depend on tiles); Gaussians with
+ *    o < 1/255 are invisible.
+ *  THREE_SIGMA: the rule of the baseline rasterizer the paper compares
+ *    against: the tiles meeting the square of half side r = ceil(3
+ *    sqrt(lambda_max)) pixels around the mean, lambda_max = mid + sqrt(max(
+ *    0.1, mid^2 - det)) the larger eigenvalue of the screen covariance (mid
+ *    its mean diagonal); the alpha support is cut at those tiles, so the
+ *    image depends on the tile size; no opacity cut.
+ */
+enum { FOOT_OPACITY_AWARE = 0, FOOT_THREE_SIGMA = 1 };
+
 ORC_EXPORT int orc_project(int64_t n, const float* means, const float* log_scales,
                            const float* quats, const float* logits, const float* sh,
-                           int sh_degree, const double* cam, int tile_size,
+                           int sh_degree, const double* cam, int tile_size, int footprint,
                            double* mean2d, double* cov2d, double* conic, double* depth,
                            double* opacity, double* rgb, int32_t* rect, float* depth_key,
                            uint8_t* flags) {
     if (n < 0 || sh_degree < 0 || sh_degree > 3 || tile_size <= 0) return 1;
+    if (footprint != FOOT_OPACITY_AWARE && footprint != FOOT_THREE_SIGMA) return 1;
     const double* R = cam;
     const double* t = cam + 9;
     const double fx = cam[12], fy = cam[13], cx = cam[14], cy = cam[15];
@@ -258,12 +274,22 @@ ORC_EXPORT int orc_project(int64_t n, const float* means, const float* log_scale
             rgb[3 * g + ch] = fmax(0.0, 0.5 + acc);
         }
 
-        /* opacity-aware footprint: alpha >= 1/255 needs q <= 2 ln(255 o) */
-        if (fabs(o * 255.0 - 1.0) < 1e-12) fl |= ORC_AMBIG_VIS;
-        if (!(o >= ALPHA_MIN)) { flags[g] = fl; continue; }
-        double tau = 2.0 * log(255.0 * o);
-        double hx = sqrt(tau * c00), hy = sqrt(tau * c11);
-        double ex = hx * (1.0 + 1e-4) + 1e-3, ey = hy * (1.0 + 1e-4) + 1e-3;
+        double ex, ey;
+        if (footprint == FOOT_OPACITY_AWARE) {
+            /* alpha >= 1/255 needs q <= 2 ln(255 o) */
+            if (fabs(o * 255.0 - 1.0) < 1e-12) fl |= ORC_AMBIG_VIS;
+            if (!(o >= ALPHA_MIN)) { flags[g] = fl; continue; }
+            double tau = 2.0 * log(255.0 * o);
+            double hx = sqrt(tau * c00), hy = sqrt(tau * c11);
+            ex = hx * (1.0 + 1e-4) + 1e-3;
+            ey = hy * (1.0 + 1e-4) + 1e-3;
+        } else {
+            double mid = 0.5 * (c00 + c11);
+            double lam = mid + sqrt(fmax(0.1, mid * mid - det));
+            double r3 = 3.0 * sqrt(lam);
+            if (near_integer(r3, 1e-9)) fl |= ORC_AMBIG_RECT;
+            ex = ey = ceil(r3);
+        }
         double fx0 = (mx - ex) / tile_size, fx1 = (mx + ex) / tile_size;
         double fy0 = (my - ey) / tile_size, fy1 = (my + ey) / tile_size;
         if (near_integer(fx0, 1e-9) || near_integer(fx1, 1e-9) || near_integer(fy0, 1e-9) || near_integer(fy1, 1e-9))

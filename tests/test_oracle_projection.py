@@ -286,3 +286,56 @@ def test_frustum_guard_off_centre_principal_point():
         p = oracle.project(one_gaussian(mu, [math.log(s)] * 3), cam)
         c = (right if u > 0 else -left) if clamped else float(mu[0]) / float(mu[2])
         np.testing.assert_allclose(p["cov2d"][0], [k * (1 + c * c) + 0.3, 0.0, k + 0.3], rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("ts", [8, 16, 32])
+def test_three_sigma_footprint_closed_form(ts):
+    # THREE_SIGMA: the tiles meeting the square of half side
+    # r = ceil(3 sqrt(lambda_max)) around the mean. For an on-axis isotropic
+    # Gaussian Sigma' = (f sigma / z)^2 I + 0.3 I, so lambda_max = the
+    # diagonal value v when v^2 - det = 0 < 0.1, i.e. lambda_max = v +
+    # sqrt(0.1): the 0.1 floor of the baseline's eigenvalue formula.
+    f, W, H, z = 100.0, 96, 64, 3.0
+    cam = ident_cam(f, W, H)
+    for s in (0.02, 0.05, 0.2):
+        g = one_gaussian((0.0, 0.0, z), [math.log(s)] * 3)
+        p = oracle.project(g, cam, tile_size=ts, footprint="three_sigma")
+        s32 = math.exp(float(np.float32(math.log(s))))
+        v = (f * s32 / z) ** 2 + 0.3
+        r = math.ceil(3.0 * math.sqrt(v + math.sqrt(0.1)))
+        cx, cy = W / 2.0, H / 2.0
+        tx, ty = (W + ts - 1) // ts, (H + ts - 1) // ts
+        want = [max(0, math.floor((cx - r) / ts)), max(0, math.floor((cy - r) / ts)),
+                min(tx, math.floor((cx + r) / ts) + 1), min(ty, math.floor((cy + r) / ts) + 1)]
+        assert list(p["rect"][0]) == want, (s, r)
+        assert p["flags"][0] & oracle.VISIBLE
+
+
+def test_three_sigma_footprint_no_opacity_cut_and_truncation():
+    # no opacity cut: o < 1/255 still gets its 3-sigma tiles (and never
+    # passes the alpha test); an opaque Gaussian (o = 0.99: alpha support
+    # out to sqrt(2 ln(255 o)) = 3.3 sigma) is cut at its 3-sigma tiles,
+    # while the opacity-aware rect reaches every pixel of its support
+    f, W, H, z, s = 100.0, 128, 128, 3.0, 0.2
+    cam = ident_cam(f, W, H)
+    faint = one_gaussian((0.0, 0.0, z), [math.log(s)] * 3, logit=-7.0)
+    pf = oracle.project(faint, cam, footprint="three_sigma")
+    assert pf["flags"][0] & oracle.VISIBLE and pf["opacity"][0] < 1 / 255
+    assert not (oracle.project(faint, cam)["flags"][0] & oracle.VISIBLE)
+    img = oracle.render(pf, W, H)
+    assert img["alpha"].max() == 0.0 and img["nvisit"].max() == 1
+    # mean at pixel (69.5, 69.5): the 3-sigma square (half side 21) starts
+    # just inside tile 3, the alpha support (3.3 sigma = 22.2 px) in tile 2
+    off = (69.5 - 64.0) * z / f
+    opaque = one_gaussian((off, off, z), [math.log(s)] * 3, logit=math.log(0.99 / 0.01))
+    p3 = oracle.project(opaque, cam, tile_size=16, footprint="three_sigma")
+    po = oracle.project(opaque, cam, tile_size=16)
+    x0, y0, x1, y1 = p3["rect"][0]
+    ox0, oy0, ox1, oy1 = po["rect"][0]
+    assert ox0 < x0 and oy0 < y0 and ox1 == x1  # the alpha support reaches tiles the square does not
+    a3 = oracle.render(p3, W, H)["alpha"]
+    ao = oracle.render(po, W, H)["alpha"]
+    inside = np.zeros((H, W), bool)
+    inside[y0 * 16:y1 * 16, x0 * 16:x1 * 16] = True
+    assert np.array_equal(a3[inside], ao[inside])
+    assert a3[~inside].max() == 0.0 and ao[~inside].max() > 1 / 255
