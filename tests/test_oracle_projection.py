@@ -295,15 +295,18 @@ def test_three_sigma_footprint_closed_form(ts):
     # Gaussian Sigma' = (f sigma / z)^2 I + 0.3 I, so lambda_max = the
     # diagonal value v when v^2 - det = 0 < 0.1, i.e. lambda_max = v +
     # sqrt(0.1): the 0.1 floor of the baseline's eigenvalue formula.
+    # The principal point puts the mean half a pixel right of a tile
+    # boundary plus r, so a radius one pixel smaller (no 0.1 floor, or a
+    # 2.9-sigma rule) moves the rect's first column.
     f, W, H, z = 100.0, 96, 64, 3.0
-    cam = ident_cam(f, W, H)
     for s in (0.02, 0.05, 0.2):
-        g = one_gaussian((0.0, 0.0, z), [math.log(s)] * 3)
-        p = oracle.project(g, cam, tile_size=ts, footprint="three_sigma")
         s32 = math.exp(float(np.float32(math.log(s))))
         v = (f * s32 / z) ** 2 + 0.3
         r = math.ceil(3.0 * math.sqrt(v + math.sqrt(0.1)))
-        cx, cy = W / 2.0, H / 2.0
+        cx, cy = 32.0 + r - 0.5, H / 2.0
+        cam = scenes.camera(np.eye(3), np.zeros(3), f, f, cx, cy, W, H)
+        g = one_gaussian((0.0, 0.0, z), [math.log(s)] * 3)
+        p = oracle.project(g, cam, tile_size=ts, footprint="three_sigma")
         tx, ty = (W + ts - 1) // ts, (H + ts - 1) // ts
         want = [max(0, math.floor((cx - r) / ts)), max(0, math.floor((cy - r) / ts)),
                 min(tx, math.floor((cx + r) / ts) + 1), min(ty, math.floor((cy + r) / ts) + 1)]
