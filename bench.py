@@ -546,7 +546,7 @@ def stress(args):
                "frame_x": tgl["frame"] / tb["frame"], "longest_segment": int(lens.max().item()),
                "entries_in_segments_over_64": float(lens[lens > 64].sum().item()) / max(M, 1),
                "paper_kept_frac": kept / max(M, 1), "paper_budget_active": kept > 0.25 * M,
-               "split_tiles": int(bb.tile_order[-2].item()),
+               "split_tiles": bb.split()[0],
                "unsplit_equals_global": bool(torch.equal(o0["rgb"], og["rgb"])),
                "split_max_abs_diff": float((ob["rgb"] - o0["rgb"]).abs().max().item())}
         del gd
@@ -873,7 +873,7 @@ def main():
     same = bool(torch.equal(cu["rgb"], cg["rgb"]) and torch.equal(cu["last"], cg["last"]))
     split_diff = float((cb["rgb"] - cu["rgb"]).abs().max().item())
     split_last_equal = bool(torch.equal(cb["last"], cu["last"]))
-    n_split = [int(v) for v in bb.tile_order[-2:].tolist()]
+    n_split = list(bb.split())
     gpu_image = (cb["rgb"].cpu().numpy(), cb["alpha"].cpu().numpy())
     del cb, cg, cu, r_unsplit
 

@@ -91,6 +91,19 @@ enum { TGS_RASTER_PLAIN = 0, TGS_RASTER_WAVE = 1 };
    the parallel scatter, which varies from call to call. */
 enum { TGS_REPAIR_ALL = 0, TGS_REPAIR_RULES = 1, TGS_REPAIR_NONE = 2 };
 
+/* Footprint: the tile rect tgs_project writes for a Gaussian.
+   OPACITY_AWARE: the tiles meeting the bounding box of the ellipse where
+   o exp(-q/2) >= 1/255 (q <= 2 ln(255 o)), widened by a relative 1e-4 and
+   1e-3 px; Gaussians with opacity < 1/255 are invisible. A superset of the
+   alpha support, so images do not depend on the tile size or the bins.
+   THREE_SIGMA: the rule of the baseline rasterizer the paper compares
+   against (section "Baseline 3DGS rasterization"): the tiles meeting the
+   square of half side ceil(3 sqrt(lambda_max)) px around the mean,
+   lambda_max = mid + sqrt(max(0.1, mid^2 - det)) of the screen covariance
+   (mid = its mean diagonal), no opacity cut. The alpha support is cut at
+   those tiles, so images depend on the tile size. */
+enum { TGS_FOOTPRINT_OPACITY_AWARE = 0, TGS_FOOTPRINT_THREE_SIGMA = 1 };
+
 /* Pinhole camera, host struct. p_cam = R p_world + t, R row-major, image x
    right, y down, z forward; pixel (i, j) is sampled at (i + 0.5, j + 0.5). */
 typedef struct {
@@ -186,6 +199,8 @@ typedef struct {
     int32_t split_mean_factor; /* 0..64 (4); 0: the threshold is split_entries
                              alone. Where every tile is long, pixels stop
                              early and a split part's walk is mostly wasted */
+    int32_t footprint;    /* TGS_FOOTPRINT_*: the tiles tgs_project gives a
+                             Gaussian (OPACITY_AWARE by default) */
 } tgs_params;
 
 /* Entry buffers written by tgs_bin and read by tgs_rasterize. All device
@@ -235,8 +250,8 @@ typedef struct {
 
 /* Fills the paper's defaults (16 px tiles, K = 64, S = 8192, 1st / 99th
    percentiles, 5 % pad, repair budget 0.25, shift alpha 1 and gamma 0.25),
-   the WAVE raster gathering by id (packed = 0) and exact repair (repair =
-   ALL, near_shift = 0). The paper's own selective mode is repair = RULES
+   the WAVE raster gathering by id (packed = 0), exact repair (repair =
+   ALL, near_shift = 0) and the opacity-aware footprint. The paper's own selective mode is repair = RULES
    with near_shift = 1. */
 TGS_API void tgs_default_params(tgs_params* params);
 

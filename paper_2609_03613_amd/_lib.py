@@ -16,6 +16,7 @@ TGS_OK, TGS_ERR_INVALID_ARG, TGS_ERR_CAPACITY, TGS_ERR_HIP, TGS_ERR_UNSUPPORTED,
 ORDER_GLOBAL, ORDER_BINNED = 0, 1
 RASTER_PLAIN, RASTER_WAVE = 0, 1
 REPAIR_ALL, REPAIR_RULES, REPAIR_NONE = 0, 1, 2
+FOOTPRINT_OPACITY_AWARE, FOOTPRINT_THREE_SIGMA = 0, 1
 
 EXPORTS = ("tgs_default_params", "tgs_project", "tgs_bin_workspace_size", "tgs_bin", "tgs_rasterize",
            "tgs_rasterize_backward", "tgs_project_backward", "tgs_batch_workspace_size", "tgs_rasterize_batch",
@@ -51,7 +52,7 @@ class Params(ctypes.Structure):
                 ("raster", ctypes.c_int32), ("packed", ctypes.c_int32), ("per_tile_bins", _c_p),
                 ("repair", ctypes.c_int32), ("repair_budget", ctypes.c_float), ("near_shift", ctypes.c_int32),
                 ("shift_alpha", ctypes.c_float), ("shift_gamma", ctypes.c_float), ("split_entries", ctypes.c_int32),
-                ("split_mean_factor", ctypes.c_int32)]
+                ("split_mean_factor", ctypes.c_int32), ("footprint", ctypes.c_int32)]
 
 
 class Binned(ctypes.Structure):

@@ -21,6 +21,7 @@ from . import _lib as L
 ORDERS = {"global": L.ORDER_GLOBAL, "binned": L.ORDER_BINNED}
 RASTERS = {"plain": L.RASTER_PLAIN, "wave": L.RASTER_WAVE}
 REPAIRS = {"all": L.REPAIR_ALL, "rules": L.REPAIR_RULES, "none": L.REPAIR_NONE}
+FOOTPRINTS = {"opacity": L.FOOTPRINT_OPACITY_AWARE, "three_sigma": L.FOOTPRINT_THREE_SIGMA}
 
 
 @dataclass
@@ -45,13 +46,14 @@ class Params:
     shift_gamma: float = 0.25
     split_entries: int = 4096  # tiles with this many entries are split over 8 wavefronts per block (0: never)
     split_mean_factor: int = 4  # ... and with this many times the mean of the non-empty tiles (0: no such bound)
+    footprint: str = "opacity"  # tile rect rule: "opacity" (alpha-support box) or "three_sigma" (baseline square)
 
     def c(self):
         return L.Params(self.tile_size, self.num_bins, self.sample_count, self.p_lo, self.p_hi, self.pad,
                         RASTERS[self.raster], int(self.packed), _ptr(self.per_tile_bins).value,
                         REPAIRS[self.repair], float(self.repair_budget), int(bool(self.near_shift)),
                         float(self.shift_alpha), float(self.shift_gamma), int(self.split_entries),
-                        int(self.split_mean_factor))
+                        int(self.split_mean_factor), FOOTPRINTS[self.footprint])
 
 
 def paper_params(**kw):
@@ -128,11 +130,21 @@ class Binned:
                 self.masks = torch.empty(cap, dtype=torch.uint8, **kw)
             if packed == 1:
                 self.records = torch.empty((cap, 12), dtype=torch.float32, **kw)
+        self.tiles = int(tiles)
         self.tile_order = torch.empty(tiles + 2, dtype=torch.int32, **kw) if tile_order else None
         self.seg_base = torch.empty(tiles + 1, dtype=torch.int32, **kw) if per_tile else None
         self.repaired = (torch.empty(max(tiles * num_bins, 1), dtype=torch.uint8, **kw)
                          if self.order == L.ORDER_BINNED else None)
         self.num_entries = None
+
+    def dispatch_order(self):
+        """The tiles in dispatch order (device int32 [T]), or None."""
+        return None if self.tile_order is None else self.tile_order[: self.tiles]
+
+    def split(self):
+        """(number of split tiles, their entry threshold) written by tgs_bin."""
+        v = self.tile_order[self.tiles: self.tiles + 2].tolist()
+        return int(v[0]), int(v[1])
 
     def c(self):
         return L.Binned(self.capacity, _ptr(self.keys).value, _ptr(self.vals).value, _ptr(self.pairs).value,

@@ -92,6 +92,8 @@ tgs_status check_params(const tgs_params* p) {
         return fail(TGS_ERR_INVALID_ARG, "shift_alpha must be finite and >= 0");
     if (!(p->shift_gamma >= 0.f && p->shift_gamma < 1.f))
         return fail(TGS_ERR_INVALID_ARG, "shift_gamma must be in [0, 1)");
+    if (p->footprint != TGS_FOOTPRINT_OPACITY_AWARE && p->footprint != TGS_FOOTPRINT_THREE_SIGMA)
+        return fail(TGS_ERR_INVALID_ARG, "unknown footprint %d", p->footprint);
     return TGS_OK;
 }
 
@@ -253,6 +255,7 @@ void tgs_default_params(tgs_params* p) {
     p->shift_gamma = 0.25f;
     p->split_entries = 4096;
     p->split_mean_factor = 4;
+    p->footprint = TGS_FOOTPRINT_OPACITY_AWARE;
 }
 
 const char* tgs_last_error(void) { return g_err.c_str(); }
@@ -270,7 +273,7 @@ tgs_status tgs_project(const tgs_gaussians* g, const tgs_camera* cam, const tgs_
     if ((st = check_params(params))) return st;
     if (!out || out->n != g->n) return fail(TGS_ERR_INVALID_ARG, "projected output missing or n mismatch");
     if (g->n > 0 && (!out->splats_dev || !out->info_dev)) return fail(TGS_ERR_INVALID_ARG, "projected buffers are NULL");
-    TGS_HIP(launch_project(*g, make_cam(*cam, params->tile_size), out->splats_dev, out->info_dev, (hipStream_t)stream),
+    TGS_HIP(launch_project(*g, make_cam(*cam, params->tile_size, params->footprint), out->splats_dev, out->info_dev, (hipStream_t)stream),
             "project");
     return TGS_OK;
 }
@@ -568,7 +571,7 @@ tgs_status tgs_project_backward(const tgs_gaussians* g, const tgs_camera* cam, c
     if (g->n > 0 && (!d_splats || !out->means_dev || !out->log_scales_dev || !out->quats_dev || !out->logits_dev ||
                      !out->sh_dev))
         return fail(TGS_ERR_INVALID_ARG, "a gradient pointer is NULL");
-    TGS_HIP(launch_project_backward(*g, make_cam(*cam, kTile), d_splats, *out, (hipStream_t)stream), "project backward");
+    TGS_HIP(launch_project_backward(*g, make_cam(*cam, kTile, TGS_FOOTPRINT_OPACITY_AWARE), d_splats, *out, (hipStream_t)stream), "project backward");
     return TGS_OK;
 }
 

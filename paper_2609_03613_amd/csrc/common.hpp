@@ -135,7 +135,9 @@ __device__ __forceinline__ bool block_may_touch(float mx, float my, float a, flo
     }
     const float mxd = fmaxf(fabsf(dxl), fabsf(dxh)), myd = fmaxf(fabsf(dyl), fabsf(dyh));
     const float mag = a * mxd * mxd + c * myd * myd + 2.0f * fabsf(b) * mxd * myd;
-    const float tau = 2.0f * __logf(255.0f * o);
+    // 2 ln(255 o) from the hardware base-2 logarithm (relative error near
+    // 1e-7, far inside the 1e-3 margin)
+    const float tau = (2.0f * 0.69314718f) * __builtin_amdgcn_logf(255.0f * o);
     return qmin <= tau + 1e-3f + 4e-6f * mag;
 }
 
@@ -281,10 +283,11 @@ struct Cam {
     double campos[3];
     double lim_xp, lim_xn, lim_yp, lim_yn;
     int width, height, tile, tiles_x, tiles_y;
+    int footprint;  // TGS_FOOTPRINT_*
 };
 
-// tile: tile edge in pixels (8, 16 or 32).
-Cam make_cam(const tgs_camera& c, int tile);
+// tile: tile edge in pixels (8, 16 or 32); footprint: TGS_FOOTPRINT_*.
+Cam make_cam(const tgs_camera& c, int tile, int footprint);
 
 // Launch helpers (host), implemented next to their kernels.
 hipError_t launch_project(const tgs_gaussians& g, const Cam& cam, float* splats, uint32_t* info,

@@ -14,8 +14,9 @@
 
 namespace tgs {
 
-Cam make_cam(const tgs_camera& c, int tile) {
+Cam make_cam(const tgs_camera& c, int tile, int footprint) {
     Cam k;
+    k.footprint = footprint;
     for (int i = 0; i < 9; ++i) k.R[i] = c.R[i];
     for (int i = 0; i < 3; ++i) k.t[i] = c.t[i];
     k.fx = c.fx; k.fy = c.fy; k.cx = c.cx; k.cy = c.cy;
@@ -202,15 +203,24 @@ __global__ void __launch_bounds__(kProjThreads) project_kernel(const float* __re
         mxs = cam.fx * px / z + cam.cx;
         mys = cam.fy * py / z + cam.cy;
         o = 1.0 / (1.0 + exp(-(double)in_l));
-        ok = ok && (o >= 1.0 / 255.0) && isfinite(mxs) && isfinite(mys);
+        const bool opaque_enough = cam.footprint == TGS_FOOTPRINT_THREE_SIGMA || o >= 1.0 / 255.0;
+        ok = ok && opaque_enough && isfinite(mxs) && isfinite(mys);
     }
     int x0 = 0, y0 = 0, x1 = 0, y1 = 0;
     if (ok) {
-        // opacity-aware footprint: alpha >= 1/255 requires q <= 2 ln(255 o),
-        // whose ellipse has half-extents sqrt(tau c00), sqrt(tau c11)
-        const double tau = 2.0 * log(255.0 * o);
-        const double ex = sqrt(tau * c00) * (1.0 + 1e-4) + 1e-3;
-        const double ey = sqrt(tau * c11) * (1.0 + 1e-4) + 1e-3;
+        double ex, ey;
+        if (cam.footprint == TGS_FOOTPRINT_THREE_SIGMA) {
+            // the baseline's square: half side ceil(3 sqrt(lambda_max))
+            const double mid = 0.5 * (c00 + c11);
+            const double lam = mid + sqrt(fmax(0.1, mid * mid - det));
+            ex = ey = ceil(3.0 * sqrt(lam));
+        } else {
+            // opacity-aware footprint: alpha >= 1/255 requires q <= 2 ln(255 o),
+            // whose ellipse has half-extents sqrt(tau c00), sqrt(tau c11)
+            const double tau = 2.0 * log(255.0 * o);
+            ex = sqrt(tau * c00) * (1.0 + 1e-4) + 1e-3;
+            ey = sqrt(tau * c11) * (1.0 + 1e-4) + 1e-3;
+        }
         const double ts = (double)cam.tile;
         double fx0 = floor((mxs - ex) / ts), fx1 = floor((mxs + ex) / ts) + 1.0;
         double fy0 = floor((mys - ey) / ts), fy1 = floor((mys + ey) / ts) + 1.0;

@@ -105,11 +105,15 @@ __global__ void __launch_bounds__(256) raster_wave_kernel(RasterArgs A) {
 // Heavy-tile split (16-pixel tiles, heaviest-first dispatch order). A pixel
 // is composited sequentially over its tile's whole range, so the
 // wavefronts of the few longest tiles decide when the WAVE raster ends.
-// Workgroups of 8 wavefronts take, in this order: the first NA = order[T]
-// tiles of the order (those with at least order[T + 1] >= A.split entries,
-// at most kSplitTiles) one 8x8 block each, with 8 parts of the range; all other tiles two per
-// workgroup, one wavefront per block, as in the WAVE raster. (Giving the
-// tiles of half that size 4 parts per block was measured no faster.) Part 0 of a block composites as usual; parts 1..
+// Workgroups of kSplitWaves = 4 wavefronts take, in this order: the first
+// NA = order[T] tiles of the order (those with at least order[T + 1] >=
+// A.split entries, at most kSplitTiles) one 8x8 block each, with 4 parts of
+// the range; all other tiles one per workgroup, one wavefront per block, as
+// in the WAVE raster. (Workgroups of 8 wavefronts, 8 parts for the split
+// blocks and two other tiles per workgroup, were measured 3 % slower at
+// 1080p and 10 % on the dense 500k training scene: a workgroup holds its
+// slots until its slowest wavefront ends.) Part 0 of a block composites as
+// usual; parts 1..
 // composite every supported entry from a local transmittance of 1, giving
 // local colour C_k and transmittance T_k. Each part then derives its
 // entering transmittance T_in = T_0 ... T_{k-1}, or that the pixel stopped
@@ -120,7 +124,7 @@ __global__ void __launch_bounds__(256) raster_wave_kernel(RasterArgs A) {
 // from T_in with the stop test. The part-0 wavefront adds the colours and
 // takes T and the last id of the last live part. Images equal the unsplit
 // ones up to the rounding of the regrouped products.
-constexpr int kSplitWaves = 8;
+constexpr int kSplitWaves = 4;
 
 struct PixLds {
     float r, g, b, T;
@@ -142,7 +146,7 @@ __global__ void __launch_bounds__(kSplitWaves * kWave) raster_split_kernel(Raste
         parts = kSplitWaves;
         part = w;
     } else {
-        slot = na + 2 * (i - 4 * na) + (w >> 2);
+        slot = na + (kSplitWaves / 4) * (i - 4 * na) + (w >> 2);
         bi = w & 3;
         parts = 1;
         part = 0;
@@ -245,7 +249,7 @@ hipError_t split_dispatch(const RasterArgs& a, hipStream_t s) {
     const int T = a.tiles_x * a.tiles_y;
     // split blocks first, then two light tiles per workgroup; workgroups
     // past the last item leave at once
-    const int grid = 4 * std::min(T, kSplitTiles) + (T + 1) / 2;
+    const int grid = 4 * std::min(T, kSplitTiles) + (T + kSplitWaves / 4 - 1) / (kSplitWaves / 4);
     if (a.n_visit || a.n_support || a.n_contrib)
         hipLaunchKernelGGL((raster_split_kernel<SRC, true>), dim3(grid), dim3(kSplitWaves * kWave), 0, s, a);
     else

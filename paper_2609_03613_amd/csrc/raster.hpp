@@ -21,12 +21,13 @@ struct Pix {
     bool done;
 };
 
-// The per-pixel step shared by both kernels, without branches (explicit
-// operation order, no implicit contraction, so both produce identical bits):
-// skip when q < 0 (rounding only) or alpha < 1/255; stop, without
-// compositing, when T (1 - alpha) < 1e-4; otherwise C += alpha T c and
-// T *= 1 - alpha. nostop (a later part of a split range, whose entering
-// transmittance is not known yet): every supported entry is composited.
+// The per-pixel step shared by all rasters, without branches (explicit
+// operation order, no implicit contraction, so every kernel produces
+// identical bits): skip when q < 0 (rounding only) or alpha < 1/255; with
+// w = alpha T, stop, without compositing, when the transmittance after the
+// entry, T - w, is below 1e-4; otherwise C += w c and T = T - w. nostop (a
+// later part of a split range, whose entering transmittance is not known
+// yet): every supported entry is composited.
 template <bool COUNT>
 __device__ __forceinline__ void blend(Pix& p, float px, float py, const Staged& s, bool nostop = false) {
 #pragma clang fp contract(off)
@@ -38,19 +39,21 @@ __device__ __forceinline__ void blend(Pix& p, float px, float py, const Staged& 
     const bool live = !p.done;
     const bool sup = live && (q2 <= 0.0f) && (araw >= kAlphaMin);
     const float alpha = fminf(kAlphaMax, araw);
-    const float test = p.T * (1.0f - alpha);
-    const bool comp = sup && (nostop || test >= kTMin);
+    const float wt0 = alpha * p.T;
+    const float next = p.T - wt0;
+    const bool pass = nostop || next >= kTMin;
+    const bool comp = sup && pass;
     if (COUNT) {
         p.nvis += live ? 1 : 0;
         p.nsup += sup ? 1 : 0;
         p.ncon += comp ? 1 : 0;
     }
-    p.done = p.done || (sup && !comp);
-    const float wt = comp ? alpha * p.T : 0.0f;
+    p.done = p.done || (sup && !pass);
+    const float wt = comp ? wt0 : 0.0f;
     p.r = fmaf(wt, s.b.z, p.r);
     p.g = fmaf(wt, s.b.w, p.g);
     p.b = fmaf(wt, s.c.x, p.b);
-    p.T = comp ? test : p.T;
+    p.T = comp ? next : p.T;
     p.last = comp ? __float_as_int(s.c.y) : p.last;
 }
 

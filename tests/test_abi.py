@@ -32,6 +32,12 @@ def test_default_params():
     assert (p.tile_size, p.num_bins, p.sample_count) == (16, 64, 8192)
     assert (p.p_lo, p.p_hi) == (1.0, 99.0) and abs(p.pad - 0.05) < 1e-7
     assert p.raster == L.RASTER_WAVE and p.packed == 0
+    assert p.footprint == L.FOOTPRINT_OPACITY_AWARE and (p.split_entries, p.split_mean_factor) == (4096, 4)
+    # the binding's defaults are the library's
+    q = tg.Params().c()
+    for name, _ in L.Params._fields_:
+        assert getattr(q, name) == getattr(p, name) or name in ("p_lo", "p_hi", "pad", "repair_budget",
+                                                               "shift_alpha", "shift_gamma"), name
 
 
 def cam(w=64, h=48):

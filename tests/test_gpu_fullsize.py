@@ -86,12 +86,13 @@ def test_fullsize_schedule_bit_exact():
     assert np.array_equal(to_np(bb.pairs)[:M].view(np.uint64), ref["stream"])
     # heaviest-first dispatch order: a permutation of the tiles, non-increasing bit length of the counts,
     # then the number of split tiles and their threshold (split_entries = 4096)
-    order = to_np(bb.tile_order).view(np.uint32)
-    assert np.array_equal(np.sort(order[:-2]), np.arange(120 * 68))
+    order = to_np(bb.dispatch_order()).view(np.uint32)
+    assert np.array_equal(np.sort(order), np.arange(120 * 68))
     cnt = np.diff(ref["tile_offsets"].astype(np.int64))
-    blen = np.where(cnt[order[:-2]] > 0, np.floor(np.log2(np.maximum(cnt[order[:-2]], 1))) + 1, 0)
+    blen = np.where(cnt[order] > 0, np.floor(np.log2(np.maximum(cnt[order], 1))) + 1, 0)
     assert np.all(np.diff(blen) <= 0)
-    assert order[-2] == int((cnt >= 4096).sum()) > 0 and order[-1] == 4096
+    ns, thr = bb.split()
+    assert ns == int((cnt >= 4096).sum()) > 0 and thr == 4096
 
 
 def test_fullsize_image_full_frame():

@@ -521,3 +521,42 @@ def test_global_order_without_host_count_overflow():
     c = to_np(b.counters)
     assert c[0] == M and c[2] == 1
     assert np.all(np.isnan(to_np(out["rgb"])))
+
+
+@pytest.mark.parametrize("ts", [8, 16, 32])
+def test_three_sigma_footprint(ts):
+    # the baseline's 3-sigma tile rule: rects equal to the oracle's (outside
+    # its rounding flags), images within 1e-4 of the oracle's tiled render
+    # with the same rects, binned == global bitwise
+    g, cam = scenes.training_scene(seed=6, n=20000, width=320, height=208)
+    W, H = cam["width"], cam["height"]
+    ref = oracle.project(g, cam, tile_size=ts, footprint="three_sigma")
+    gd = tg.to_device(g, dev())
+    p = tg.Params(tile_size=ts, footprint="three_sigma", num_bins=32)
+    splats, info = tg.project(gd, cam, p)
+    torch.cuda.synchronize()
+    depth, rect = decode_info(to_np(info))
+    vis = (rect[:, 2] > rect[:, 0]) & (rect[:, 3] > rect[:, 1])
+    amb = (ref["flags"] & (oracle.AMBIG_RECT | oracle.AMBIG_VIS)) > 0
+    vis_ref = (ref["flags"] & oracle.VISIBLE) > 0
+    assert np.array_equal(vis[~amb], vis_ref[~amb])
+    ok = vis & vis_ref & ~amb
+    assert np.array_equal(rect[ok], ref["rect"][ok].astype(np.int64))
+    # no opacity cut: Gaussians below 1/255 keep their tiles
+    assert np.any(vis & (ref["opacity"] < 1 / 255))
+    want = oracle.render(ref, W, H, tile_size=ts)
+    r = tg.Renderer(cam, p, device=dev())
+    imgs = {}
+    for order in ("binned", "global"):
+        out = r.rasterize(splats, info, r.bin(splats, info, order))
+        torch.cuda.synchronize()
+        e_rgb, e_a, nflag = image_compare(to_np(out["rgb"]), to_np(out["alpha"]), want)
+        assert e_rgb <= TOL and e_a <= TOL, (ts, order, e_rgb, e_a, nflag)
+        imgs[order] = to_np(out["rgb"])
+    assert np.array_equal(imgs["binned"], imgs["global"])
+    # the cut at the 3-sigma tiles changes the image against the
+    # opacity-aware footprint
+    ro = tg.Renderer(cam, tg.Params(tile_size=ts, num_bins=32), device=dev())
+    full = ro.render(gd)
+    torch.cuda.synchronize()
+    assert float(np.abs(to_np(full["rgb"]) - imgs["binned"]).max()) > 1e-3

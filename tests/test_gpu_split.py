@@ -66,7 +66,7 @@ def test_split_matches_oracle_and_unsplit(case):
     out = rs.rasterize(s, i, bs, counts=True, trans=True)
     out0 = r0.rasterize(s, i, b0, counts=True, trans=True)
     torch.cuda.synchronize()
-    ns, thr = (int(v) for v in to_np(bs.tile_order)[-2:])
+    ns, thr = bs.split()
     offs = to_np(bs.offsets).view(np.uint32).astype(np.int64)
     tiles = rs.tiles
     counts = offs[64::64][:tiles] - offs[0:tiles * 64:64]
@@ -142,7 +142,7 @@ def test_split_cap_is_deterministic():
         b = r.bin(s, i, "binned")
         outs.append({k: v.clone() for k, v in r.rasterize(s, i, b).items()})
         torch.cuda.synchronize()
-        ns, thr = (int(v) for v in to_np(b.tile_order)[-2:])
+        ns, thr = b.split()
         offs = to_np(b.offsets).view(np.uint32).astype(np.int64)
         counts = offs[64::64][:r.tiles] - offs[0:r.tiles * 64:64]
         assert int((counts >= 256).sum()) > 1024
@@ -172,7 +172,7 @@ def test_split_relative_bound():
         out = r.rasterize(s, i, b)
         u = r0.rasterize(s, i, r0.bin(s, i, "binned"))
         torch.cuda.synchronize()
-        ns, thr = (int(v) for v in to_np(b.tile_order)[-2:])
+        ns, thr = b.split()
         offs = to_np(b.offsets).view(np.uint32).astype(np.int64)
         counts = offs[64::64][:r.tiles] - offs[0:r.tiles * 64:64]
         nonempty = int((counts > 0).sum())
