@@ -271,7 +271,7 @@ def learned_bins(args):
     fixed = tg.Renderer(cam, tg.Params(), device=dev)
     s, i = tg.project(gd, cam, fixed.params)
     bf = fixed.bin(s, i, "binned", sync=True)
-    lb = bins.LearnedBins(cam, weights=w, device=dev)
+    lb = bins.LearnedBins(cam, weights=w, device=dev, judge=False)
     for _ in range(3):
         lb.bin(s, i, sync=True)  # frame 1 fixed K, then learned; sizes the buffers
 
@@ -301,6 +301,12 @@ def learned_bins(args):
     fixed_ms = timed(lambda: fixed.bin(s, i, "binned", sync=False), steps)
     learned_ms = timed(lambda: lb.bin(s, i, sync=False), steps)
     fixed_ms2 = timed(lambda: fixed.bin(s, i, "binned", sync=False), steps)
+    # the product configuration: the network judged against the fixed K at
+    # run time (probes included in the mean)
+    lj = bins.LearnedBins(cam, weights=w, device=dev, judge=True, warm=4, probe_every=32)
+    for _ in range(8):
+        lj.bin(s, i, sync=True)
+    judged_ms = timed(lambda: lj.bin(s, i, sync=False), max(steps, 32))
     r, b = lb.bin(s, i, sync=True)
     out_l = r.rasterize(s, i, b)
     out_f = fixed.rasterize(s, i, fixed.bin(s, i, "binned", sync=True))
@@ -312,6 +318,7 @@ def learned_bins(args):
     return {"workload": "6M Gaussians on 64 surfaces (SH3), 3840x2160, f=2200", "entries": bf.num_entries,
             "weights": "trained" if w is not None else "missing (fixed K fallback)",
             "fixed64_bin_ms": fixed_ms, "learned_bin_ms": learned_ms, "gain": fixed_ms / learned_ms,
+            "judged_bin_ms": judged_ms, "judged_gain": fixed_ms / judged_ms, "judge_choice": lj.choice(),
             "per_tile_machinery_all64_ms": var64_ms, "uniform_k_sweep_ms": sweep,
             "images_equal": same, "per_tile_bins": {int(k): int(c) for k, c in zip(ks, counts)}}
 

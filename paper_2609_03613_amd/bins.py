@@ -98,12 +98,24 @@ def init_weights(seed=0):
 
 
 class LearnedBins:
-    """Frame loop with learned bin counts for one camera: frame 1 uses the
-    fixed K; every later frame bins with the counts the network proposed
-    from the previous frame's stream. Without valid weights every frame
-    uses the fixed K."""
+    """Frame loop with learned bin counts for one camera, judged against
+    the fixed K at run time.
 
-    def __init__(self, cam, weights=None, device="cuda", tile_size=16):
+    Frame 1 uses the fixed K; a learned frame bins with the counts the
+    network proposed from the previous frame's stream (features and
+    proposal included in its cost). The judge times bin stages with HIP
+    events on the launch stream, read back without waiting once they have
+    completed. It alternates the two modes until each has `warm` timings
+    (waiting for them once if the host has run ahead of the GPU) and keeps
+    the faster by median; from then on every `probe_every`-th frame bins
+    with the other mode and the frame after it with the kept one, both
+    timed (the others are not), and the choice is revisited with each new
+    pair, so a scene change can flip it. Without valid weights every frame
+    uses the fixed K; with judge=False and weights, every frame after the
+    first is learned. Exact repair keeps every image identical whichever
+    mode bins it."""
+
+    def __init__(self, cam, weights=None, device="cuda", tile_size=16, judge=True, warm=4, probe_every=64):
         self.weights = None if weights is None else torch.as_tensor(np.asarray(weights, np.float32)).to(device)
         self.fixed = Renderer(cam, Params(tile_size=tile_size, num_bins=FALLBACK_BINS), device=device)
         self.learned = Renderer(cam, Params(tile_size=tile_size, num_bins=MAX_BINS), device=device)
@@ -111,19 +123,78 @@ class LearnedBins:
         self.learned.set_per_tile_bins(self.kt)
         self.feat = torch.empty((self.fixed.tiles, 16), dtype=torch.float32, device=device)
         self.prev = None  # (renderer, binned) of the previous frame
+        self.judge = judge
+        self.warm = int(warm)
+        self.probe_every = max(2, int(probe_every))
+        self.times = {"learned": [], "fixed": []}
+        self.modes = []  # the mode of every frame
+        self._pending = []
+        self._best = None
+        self._since = 0  # frames since the decision
+
+    def _collect(self):
+        keep, new = [], False
+        for mode, e0, e1 in self._pending:
+            if e1.query():
+                self.times[mode].append(e0.elapsed_time(e1))
+                new = True
+            else:
+                keep.append((mode, e0, e1))
+        self._pending = keep
+        if new:
+            tl, tf = self.times["learned"], self.times["fixed"]
+            if len(tl) >= self.warm and len(tf) >= self.warm:
+                self._best = "learned" if np.median(tl[-self.warm:]) < np.median(tf[-self.warm:]) else "fixed"
+
+    def choice(self):
+        """The mode the judge currently prefers ("learned" or "fixed"), or
+        None while it has fewer than `warm` timings of either."""
+        return self._best
+
+    def _mode(self):
+        """(mode, timed) of the next frame."""
+        if self.weights is None or self.prev is None:
+            return "fixed", False
+        if not self.judge:
+            return "learned", False
+        if self._pending:
+            self._collect()
+        if self._best is None:
+            n_l = len(self.times["learned"]) + sum(m == "learned" for m, _, _ in self._pending)
+            n_f = len(self.times["fixed"]) + sum(m == "fixed" for m, _, _ in self._pending)
+            if min(n_l, n_f) >= self.warm:
+                # both modes probed, timings still in flight (the host runs
+                # ahead of the GPU): wait for them once, to decide
+                for _, _, e1 in self._pending:
+                    e1.synchronize()
+                self._collect()
+            if self._best is None:  # still probing: the mode with fewer timings
+                return ("learned" if n_l <= n_f else "fixed"), True
+        self._since += 1
+        k = self._since % self.probe_every
+        if k == 0:
+            return ("fixed" if self._best == "learned" else "learned"), True
+        return self._best, k == 1
 
     def bin(self, splats, info, sync=False):
-        """Bins with the counts proposed from the previous frame's stream
-        (or the fixed K) and proposes the next frame's counts."""
-        if self.weights is None:
-            return self.fixed, self.fixed.bin(splats, info, "binned", sync=sync)
-        if self.prev is not None:
+        """Bins one frame (learned counts or the fixed K, as the judge
+        decides); returns (renderer, binned)."""
+        mode, timed = self._mode()
+        if timed:
+            stream = torch.cuda.current_stream()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+        if mode == "learned":
             r0, b0 = self.prev
             tile_features(r0, b0, out=self.feat)
             propose_bins(self.weights, self.feat, out=self.kt)
             r, b = self.learned, self.learned.bin(splats, info, "binned", sync=sync)
         else:
             r, b = self.fixed, self.fixed.bin(splats, info, "binned", sync=sync)
+        if timed:
+            e1.record(stream)
+            self._pending.append((mode, e0, e1))
+        self.modes.append(mode)
         self.prev = (r, b)
         return r, b
 
