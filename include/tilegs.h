@@ -58,6 +58,9 @@ extern "C" {
 
 #define TGS_API __attribute__((visibility("default")))
 
+/* Most cameras (views) of one batched call. */
+#define TGS_MAX_VIEWS 16
+
 typedef enum {
     TGS_OK = 0,
     TGS_ERR_INVALID_ARG = 1,
@@ -262,6 +265,14 @@ TGS_API void tgs_default_params(tgs_params* params);
 TGS_API tgs_status tgs_project(const tgs_gaussians* gaussians, const tgs_camera* camera,
                        const tgs_params* params, tgs_projected* out, void* stream);
 
+/* tgs_project for num_views (1..TGS_MAX_VIEWS) cameras of the same
+   Gaussians: cameras, params and out are host arrays of num_views
+   elements, out[v] receives exactly what tgs_project(gaussians, &cameras[v],
+   &params[v], &out[v]) writes (bitwise). Each launch reads every
+   Gaussian's parameters once and writes up to 4 views. */
+TGS_API tgs_status tgs_project_views(const tgs_gaussians* gaussians, int32_t num_views, const tgs_camera* cameras,
+                             const tgs_params* params, tgs_projected* out, void* stream);
+
 /* Workspace bytes tgs_bin needs for n Gaussians, `capacity` entries, this
    camera, params and order. */
 TGS_API size_t tgs_bin_workspace_size(int64_t n, int64_t capacity, const tgs_camera* camera,
@@ -348,7 +359,6 @@ TGS_API tgs_status tgs_project_backward(const tgs_gaussians* gaussians, const tg
    and the persistent launch on `stream` and never synchronises, so it can
    be captured in a HIP graph (the view descriptors travel in the kernel
    arguments). Workspace: tgs_batch_workspace_size bytes, caller-owned. */
-#define TGS_MAX_VIEWS 16
 TGS_API size_t tgs_batch_workspace_size(int32_t num_views, const tgs_camera* cameras, const tgs_params* params);
 TGS_API tgs_status tgs_rasterize_batch(int32_t num_views, const tgs_projected* projected, const tgs_binned* binned,
                                const tgs_camera* cameras, const tgs_params* params, const int32_t* orders,

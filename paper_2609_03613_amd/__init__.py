@@ -6,4 +6,4 @@ The compute path is the HIP library ``libtilegs.so`` behind the C ABI in
 from ._lib import (ORDER_BINNED, ORDER_GLOBAL, RASTER_PLAIN, RASTER_WAVE, REPAIR_ALL, REPAIR_NONE,  # noqa: F401
                    REPAIR_RULES, TileGSError, LIB_PATH, EXPORTS, lib)
 from .api import (BatchRenderer, Binned, Params, Renderer, camera_struct, paper_params, project,  # noqa: F401
-                  project_backward, render, render_differentiable, to_device)
+                  project_backward, project_views, render, render_differentiable, to_device)

@@ -18,7 +18,7 @@ RASTER_PLAIN, RASTER_WAVE = 0, 1
 REPAIR_ALL, REPAIR_RULES, REPAIR_NONE = 0, 1, 2
 FOOTPRINT_OPACITY_AWARE, FOOTPRINT_THREE_SIGMA = 0, 1
 
-EXPORTS = ("tgs_default_params", "tgs_project", "tgs_bin_workspace_size", "tgs_bin", "tgs_rasterize",
+EXPORTS = ("tgs_default_params", "tgs_project", "tgs_project_views", "tgs_bin_workspace_size", "tgs_bin", "tgs_rasterize",
            "tgs_rasterize_backward", "tgs_project_backward", "tgs_batch_workspace_size", "tgs_rasterize_batch",
            "tgs_rasterize_batch_noalloc",
            "tgs_tile_features", "tgs_propose_bins", "tgs_mlp_train_workspace_size", "tgs_mlp_train_step",
@@ -86,6 +86,8 @@ def lib():
         L.tgs_default_params.restype = None
         L.tgs_project.argtypes = [P(Gaussians), P(Camera), P(Params), P(Projected), _c_p]
         L.tgs_project.restype = ctypes.c_int
+        L.tgs_project_views.argtypes = [P(Gaussians), ctypes.c_int32, _c_p, _c_p, _c_p, _c_p]
+        L.tgs_project_views.restype = ctypes.c_int
         L.tgs_bin_workspace_size.argtypes = [ctypes.c_int64, ctypes.c_int64, P(Camera), P(Params), ctypes.c_int32]
         L.tgs_bin_workspace_size.restype = ctypes.c_size_t
         L.tgs_bin.argtypes = [P(Projected), P(Camera), P(Params), ctypes.c_int32, _c_p, ctypes.c_size_t, P(Binned),

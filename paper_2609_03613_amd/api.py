@@ -108,6 +108,22 @@ def project(g, cam, params=None, out=None):
     return splats, info
 
 
+def project_views(g, cams, params, outs):
+    """tgs_project_views: the projections of g through every camera of cams
+    (with params[v]) into outs[v] = (splats, info), each launch reading the
+    Gaussians once for up to four cameras."""
+    nv = len(cams)
+    n = int(g["means"].shape[0])
+    gs = L.Gaussians(_ptr(g["means"]).value, _ptr(g["log_scales"]).value, _ptr(g["quats"]).value,
+                     _ptr(g["logits"]).value, _ptr(g["sh"]).value, n, int(g["sh_degree"]))
+    cc = (L.Camera * nv)(*[camera_struct(c) for c in cams])
+    pp = (L.Params * nv)(*[p.c() for p in params])
+    pr = (L.Projected * nv)(*[L.Projected(_ptr(s).value, _ptr(i).value, n) for s, i in outs])
+    L.check(L.lib().tgs_project_views(ctypes.byref(gs), nv, ctypes.cast(cc, ctypes.c_void_p),
+                                      ctypes.cast(pp, ctypes.c_void_p), ctypes.cast(pr, ctypes.c_void_p), _stream()))
+    return outs
+
+
 class Binned:
     """Device buffers of one entry stream (see tgs_binned)."""
 
@@ -334,9 +350,10 @@ def render_differentiable(renderer, g, order="binned", bg=(0.0, 0.0, 0.0)):
 
 
 class BatchRenderer:
-    """Several cameras per frame: per-view tgs_project and tgs_bin (BINNED,
-    each view with its own params: tile size, bins), then one
-    tgs_rasterize_batch persistent launch for all views. ``capture`` records
+    """Several cameras per frame: tgs_project_views for all views (the
+    Gaussians read once per four views), per-view tgs_bin (BINNED, each view
+    with its own params: tile size, bins), then one tgs_rasterize_batch
+    persistent launch for all views. ``capture`` records
     the whole frame in a HIP graph (torch.cuda.CUDAGraph) after an eager
     frame has sized every buffer; ``replay`` launches it."""
 
@@ -397,10 +414,8 @@ class BatchRenderer:
         With sync, entry counts are read back and buffers grown as needed
         (do this once before capture)."""
         self._alloc_proj(int(g["means"].shape[0]))
-        binned = []
-        for r, (s, i) in zip(self.views, self.proj):
-            project(g, r.cam, r.params, out=(s, i))
-            binned.append(r.bin(s, i, "binned", sync=sync))
+        project_views(g, [r.cam for r in self.views], [r.params for r in self.views], self.proj)
+        binned = [r.bin(s, i, "binned", sync=sync) for r, (s, i) in zip(self.views, self.proj)]
         self.binned = binned
         if sync:
             self.entries = [b.num_entries for b in binned]

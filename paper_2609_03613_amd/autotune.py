@@ -1,9 +1,10 @@
 """Per-camera tile-size / bin-count autotuner.
 
-For one camera and scene size it times the whole per-view frame (projection,
-binning with exact repair, WAVE raster) for every candidate (tile size in
-{8, 16, 32}) x (bins K in {16, 32, 64, 128}) with HIP events on the launch
-stream and keeps the fastest. The choice never changes the image beyond
+For one camera and scene size it times the whole per-view frame as the
+batched renderer runs it (projection, binning with exact repair, the
+persistent multi-view raster on this one view) for every candidate (tile
+size in {8, 16, 32}) x (bins K in {16, 32, 64, 128}) with HIP events on the
+launch stream and keeps the fastest. The choice never changes the image beyond
 rounding (exact repair keeps the global order; the tile size only moves the
 tile-relative origin of the staged means), so only time is compared.
 
@@ -20,7 +21,7 @@ import os
 import numpy as np
 import torch
 
-from .api import Params, Renderer, project
+from .api import BatchRenderer, Params, project
 
 TILE_SIZES = (8, 16, 32)
 BIN_COUNTS = (16, 32, 64, 128)
@@ -35,23 +36,19 @@ def cache_key(cam, n):
 
 
 def measure(g, cam, tile_size, num_bins, reps=5, warmup=2):
-    """Median ms of one view's frame (project + bin + raster) with these
-    options, inputs resident."""
+    """Median ms of one view's frame (project + bin + the persistent batched
+    raster on this view alone) with these options, inputs resident."""
     p = Params(tile_size=tile_size, num_bins=num_bins)
-    r = Renderer(cam, p, device=g["means"].device)
+    br = BatchRenderer([cam], [p], device=g["means"].device)
+    r = br.views[0]
     s, i = project(g, cam, p)
     b = r.bin(s, i, "binned", sync=True)  # sizes the buffers
-    H, W = int(cam["height"]), int(cam["width"])
-    dev = g["means"].device
-    out = {"rgb": torch.empty((H, W, 3), dtype=torch.float32, device=dev),
-           "alpha": torch.empty((H, W), dtype=torch.float32, device=dev),
-           "last": torch.empty((H, W), dtype=torch.int32, device=dev)}
     stream = torch.cuda.current_stream()
 
     def once():
         project(g, cam, p, out=(s, i))
         bb = r.bin(s, i, "binned", sync=False)
-        r.rasterize(s, i, bb, out=out)
+        br.rasterize([(s, i)], [bb])
 
     for _ in range(warmup):
         once()

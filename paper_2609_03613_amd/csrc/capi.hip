@@ -278,6 +278,38 @@ tgs_status tgs_project(const tgs_gaussians* g, const tgs_camera* cam, const tgs_
     return TGS_OK;
 }
 
+tgs_status tgs_project_views(const tgs_gaussians* g, int32_t num_views, const tgs_camera* cams,
+                             const tgs_params* params, tgs_projected* out, void* stream) {
+    g_err.clear();
+    if (!g) return fail(TGS_ERR_INVALID_ARG, "gaussians is NULL");
+    if (g->n < 0 || g->n >= (int64_t)1 << 31) return fail(TGS_ERR_INVALID_ARG, "n = %lld outside 0..2^31-1", (long long)g->n);
+    if (g->sh_degree < 0 || g->sh_degree > 3) return fail(TGS_ERR_INVALID_ARG, "sh_degree %d outside 0..3", g->sh_degree);
+    if (g->n > 0 && (!g->means_dev || !g->log_scales_dev || !g->quats_dev || !g->logits_dev || !g->sh_dev))
+        return fail(TGS_ERR_INVALID_ARG, "a Gaussian attribute pointer is NULL");
+    if (num_views < 1 || num_views > TGS_MAX_VIEWS)
+        return fail(TGS_ERR_INVALID_ARG, "num_views %d outside 1..%d", num_views, TGS_MAX_VIEWS);
+    if (!cams || !params || !out) return fail(TGS_ERR_INVALID_ARG, "an argument array is NULL");
+    for (int v = 0; v < num_views; ++v) {
+        tgs_status st = check_camera(&cams[v]);
+        if (st) return st;
+        if ((st = check_params(&params[v]))) return st;
+        if (out[v].n != g->n) return fail(TGS_ERR_INVALID_ARG, "view %d: projected n mismatch", v);
+        if (g->n > 0 && (!out[v].splats_dev || !out[v].info_dev))
+            return fail(TGS_ERR_INVALID_ARG, "view %d: projected buffers are NULL", v);
+    }
+    for (int v0 = 0; v0 < num_views; v0 += kProjViews) {
+        ProjViews pv{};
+        pv.nv = std::min(kProjViews, num_views - v0);
+        for (int k = 0; k < pv.nv; ++k) {
+            pv.cam[k] = make_cam(cams[v0 + k], params[v0 + k].tile_size, params[v0 + k].footprint);
+            pv.splats[k] = reinterpret_cast<float4*>(out[v0 + k].splats_dev);
+            pv.info[k] = reinterpret_cast<uint4*>(out[v0 + k].info_dev);
+        }
+        TGS_HIP(launch_project_views(*g, pv, (hipStream_t)stream), "project views");
+    }
+    return TGS_OK;
+}
+
 size_t tgs_bin_workspace_size(int64_t n, int64_t capacity, const tgs_camera* cam, const tgs_params* params,
                               int32_t order) {
     if (!cam || !params || n < 0 || capacity < 0) return 0;

@@ -289,6 +289,17 @@ struct Cam {
 // tile: tile edge in pixels (8, 16 or 32); footprint: TGS_FOOTPRINT_*.
 Cam make_cam(const tgs_camera& c, int tile, int footprint);
 
+// Cameras of one projection launch: each lane reads its Gaussian once and
+// writes its splat and info lines for every camera.
+constexpr int kProjViews = 4;
+struct ProjViews {
+    Cam cam[kProjViews];
+    float4* splats[kProjViews];
+    uint4* info[kProjViews];
+    int nv;
+};
+hipError_t launch_project_views(const tgs_gaussians& g, const ProjViews& views, hipStream_t s);
+
 // Launch helpers (host), implemented next to their kernels.
 hipError_t launch_project(const tgs_gaussians& g, const Cam& cam, float* splats, uint32_t* info,
                           hipStream_t s);

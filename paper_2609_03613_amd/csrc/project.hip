@@ -99,6 +99,9 @@ __device__ __forceinline__ void stage_sh_block(float4* sh_lds, const float* __re
     }
 }
 
+// Every lane reads its Gaussian's parameters once and writes the splat and
+// info lines of up to kProjViews cameras (views.nv of them).
+//
 // SH3: each lane loads its Gaussian's 48 coefficients itself (twelve
 // 16-byte loads, no LDS). Without the 24 KB LDS block, which limited the
 // staged form to 3 wavefronts per SIMD, the registers allow 4, and the
@@ -111,8 +114,7 @@ __global__ void __launch_bounds__(kProjThreads) project_kernel(const float* __re
                                                       const float* __restrict__ quats,
                                                       const float* __restrict__ logits,
                                                       const float* __restrict__ sh, int64_t n, int degree,
-                                                      Cam cam, float4* __restrict__ splats,
-                                                      uint4* __restrict__ info) {
+                                                      ProjViews views) {
 #pragma clang fp contract(off)
     // Staged form: the SH coefficients of the workgroup's Gaussians are one
     // contiguous block, staged through LDS with coalesced 16-byte loads.
@@ -149,128 +151,133 @@ __global__ void __launch_bounds__(kProjThreads) project_kernel(const float* __re
         __syncthreads();
     }
     if (g >= n) return;
-    float4* out = splats + kSplatVec * g;
-    const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
-    uint4 inf = make_uint4(0u, 0u, 0u, 0u);
+    // one camera: its splat and info line of this Gaussian
+    auto one = [&](const Cam& cam, float4* __restrict__ splats, uint4* __restrict__ info) {
+        float4* out = splats + kSplatVec * g;
+        const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+        uint4 inf = make_uint4(0u, 0u, 0u, 0u);
 
-    const double mx3 = in_m[0], my3 = in_m[1], mz3 = in_m[2];
-    const double* R = cam.R;
-    // camera-space point; the z expression is the ordering key's definition
-    const double px = R[0] * mx3 + R[1] * my3 + R[2] * mz3 + cam.t[0];
-    const double py = R[3] * mx3 + R[4] * my3 + R[5] * mz3 + cam.t[1];
-    const double z = R[6] * mx3 + R[7] * my3 + R[8] * mz3 + cam.t[2];
+        const double mx3 = in_m[0], my3 = in_m[1], mz3 = in_m[2];
+        const double* R = cam.R;
+        // camera-space point; the z expression is the ordering key's definition
+        const double px = R[0] * mx3 + R[1] * my3 + R[2] * mz3 + cam.t[0];
+        const double py = R[3] * mx3 + R[4] * my3 + R[5] * mz3 + cam.t[1];
+        const double z = R[6] * mx3 + R[7] * my3 + R[8] * mz3 + cam.t[2];
 
-    bool ok = (z > cam.znear) && (z < cam.zfar);
-    double qw = in_q[0], qx = in_q[1], qy = in_q[2], qz = in_q[3];
-    const double qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
-    ok = ok && (qn > 0.0) && isfinite(qn);
-    double c00 = 0, c01 = 0, c11 = 0, det = 0, mxs = 0, mys = 0, o = 0, smax = 0;
-    if (ok) {
-        qw /= qn; qx /= qn; qy /= qn; qz /= qn;
-        const double Rq[9] = {1.0 - 2.0 * (qy * qy + qz * qz), 2.0 * (qx * qy - qw * qz), 2.0 * (qx * qz + qw * qy),
-                              2.0 * (qx * qy + qw * qz), 1.0 - 2.0 * (qx * qx + qz * qz), 2.0 * (qy * qz - qw * qx),
-                              2.0 * (qx * qz - qw * qy), 2.0 * (qy * qz + qw * qx), 1.0 - 2.0 * (qx * qx + qy * qy)};
-        double s2[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const double s = exp((double)in_s[k]);
-            s2[k] = s * s;
-            smax = fmax(smax, s);
+        bool ok = (z > cam.znear) && (z < cam.zfar);
+        double qw = in_q[0], qx = in_q[1], qy = in_q[2], qz = in_q[3];
+        const double qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+        ok = ok && (qn > 0.0) && isfinite(qn);
+        double c00 = 0, c01 = 0, c11 = 0, det = 0, mxs = 0, mys = 0, o = 0, smax = 0;
+        if (ok) {
+            qw /= qn; qx /= qn; qy /= qn; qz /= qn;
+            const double Rq[9] = {1.0 - 2.0 * (qy * qy + qz * qz), 2.0 * (qx * qy - qw * qz), 2.0 * (qx * qz + qw * qy),
+                                  2.0 * (qx * qy + qw * qz), 1.0 - 2.0 * (qx * qx + qz * qz), 2.0 * (qy * qz - qw * qx),
+                                  2.0 * (qx * qz - qw * qy), 2.0 * (qy * qz + qw * qx), 1.0 - 2.0 * (qx * qx + qy * qy)};
+            double s2[3];
+    #pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const double s = exp((double)in_s[k]);
+                s2[k] = s * s;
+                smax = fmax(smax, s);
+            }
+            // M = R_cam Rq: camera covariance = M diag(s^2) M^T
+            double M[9];
+    #pragma unroll
+            for (int i = 0; i < 3; ++i)
+    #pragma unroll
+                for (int j = 0; j < 3; ++j) M[3 * i + j] = R[3 * i] * Rq[j] + R[3 * i + 1] * Rq[3 + j] + R[3 * i + 2] * Rq[6 + j];
+            const double txz = px / z, tyz = py / z;
+            const double tx = z * fmin(cam.lim_xp, fmax(-cam.lim_xn, txz));
+            const double ty = z * fmin(cam.lim_yp, fmax(-cam.lim_yn, tyz));
+            // rows of J M, J = [[fx/z, 0, -fx tx/z^2], [0, fy/z, -fy ty/z^2]]
+            const double j00 = cam.fx / z, j02 = -cam.fx * tx / (z * z);
+            const double j11 = cam.fy / z, j12 = -cam.fy * ty / (z * z);
+            double A[3], B[3];
+    #pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                A[k] = j00 * M[k] + j02 * M[6 + k];
+                B[k] = j11 * M[3 + k] + j12 * M[6 + k];
+            }
+            c00 = A[0] * A[0] * s2[0] + A[1] * A[1] * s2[1] + A[2] * A[2] * s2[2] + 0.3;
+            c01 = A[0] * B[0] * s2[0] + A[1] * B[1] * s2[1] + A[2] * B[2] * s2[2];
+            c11 = B[0] * B[0] * s2[0] + B[1] * B[1] * s2[1] + B[2] * B[2] * s2[2] + 0.3;
+            det = c00 * c11 - c01 * c01;
+            ok = (det > 0.0) && isfinite(det);
+            mxs = cam.fx * px / z + cam.cx;
+            mys = cam.fy * py / z + cam.cy;
+            o = 1.0 / (1.0 + exp(-(double)in_l));
+            const bool opaque_enough = cam.footprint == TGS_FOOTPRINT_THREE_SIGMA || o >= 1.0 / 255.0;
+            ok = ok && opaque_enough && isfinite(mxs) && isfinite(mys);
         }
-        // M = R_cam Rq: camera covariance = M diag(s^2) M^T
-        double M[9];
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) M[3 * i + j] = R[3 * i] * Rq[j] + R[3 * i + 1] * Rq[3 + j] + R[3 * i + 2] * Rq[6 + j];
-        const double txz = px / z, tyz = py / z;
-        const double tx = z * fmin(cam.lim_xp, fmax(-cam.lim_xn, txz));
-        const double ty = z * fmin(cam.lim_yp, fmax(-cam.lim_yn, tyz));
-        // rows of J M, J = [[fx/z, 0, -fx tx/z^2], [0, fy/z, -fy ty/z^2]]
-        const double j00 = cam.fx / z, j02 = -cam.fx * tx / (z * z);
-        const double j11 = cam.fy / z, j12 = -cam.fy * ty / (z * z);
-        double A[3], B[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            A[k] = j00 * M[k] + j02 * M[6 + k];
-            B[k] = j11 * M[3 + k] + j12 * M[6 + k];
+        int x0 = 0, y0 = 0, x1 = 0, y1 = 0;
+        if (ok) {
+            double ex, ey;
+            if (cam.footprint == TGS_FOOTPRINT_THREE_SIGMA) {
+                // the baseline's square: half side ceil(3 sqrt(lambda_max))
+                const double mid = 0.5 * (c00 + c11);
+                const double lam = mid + sqrt(fmax(0.1, mid * mid - det));
+                ex = ey = ceil(3.0 * sqrt(lam));
+            } else {
+                // opacity-aware footprint: alpha >= 1/255 requires q <= 2 ln(255 o),
+                // whose ellipse has half-extents sqrt(tau c00), sqrt(tau c11)
+                const double tau = 2.0 * log(255.0 * o);
+                ex = sqrt(tau * c00) * (1.0 + 1e-4) + 1e-3;
+                ey = sqrt(tau * c11) * (1.0 + 1e-4) + 1e-3;
+            }
+            const double ts = (double)cam.tile;
+            double fx0 = floor((mxs - ex) / ts), fx1 = floor((mxs + ex) / ts) + 1.0;
+            double fy0 = floor((mys - ey) / ts), fy1 = floor((mys + ey) / ts) + 1.0;
+            fx0 = fmin(fmax(fx0, 0.0), (double)cam.tiles_x);
+            fx1 = fmin(fmax(fx1, 0.0), (double)cam.tiles_x);
+            fy0 = fmin(fmax(fy0, 0.0), (double)cam.tiles_y);
+            fy1 = fmin(fmax(fy1, 0.0), (double)cam.tiles_y);
+            x0 = (int)fx0; x1 = (int)fx1; y0 = (int)fy0; y1 = (int)fy1;
+            ok = (x1 > x0) && (y1 > y0);
         }
-        c00 = A[0] * A[0] * s2[0] + A[1] * A[1] * s2[1] + A[2] * A[2] * s2[2] + 0.3;
-        c01 = A[0] * B[0] * s2[0] + A[1] * B[1] * s2[1] + A[2] * B[2] * s2[2];
-        c11 = B[0] * B[0] * s2[0] + B[1] * B[1] * s2[1] + B[2] * B[2] * s2[2] + 0.3;
-        det = c00 * c11 - c01 * c01;
-        ok = (det > 0.0) && isfinite(det);
-        mxs = cam.fx * px / z + cam.cx;
-        mys = cam.fy * py / z + cam.cy;
-        o = 1.0 / (1.0 + exp(-(double)in_l));
-        const bool opaque_enough = cam.footprint == TGS_FOOTPRINT_THREE_SIGMA || o >= 1.0 / 255.0;
-        ok = ok && opaque_enough && isfinite(mxs) && isfinite(mys);
-    }
-    int x0 = 0, y0 = 0, x1 = 0, y1 = 0;
-    if (ok) {
-        double ex, ey;
-        if (cam.footprint == TGS_FOOTPRINT_THREE_SIGMA) {
-            // the baseline's square: half side ceil(3 sqrt(lambda_max))
-            const double mid = 0.5 * (c00 + c11);
-            const double lam = mid + sqrt(fmax(0.1, mid * mid - det));
-            ex = ey = ceil(3.0 * sqrt(lam));
+        if (!ok) {
+            out[0] = zero4; out[1] = zero4; out[2] = zero4; out[3] = zero4;
+            info[g] = inf;
+            return;
+        }
+        // colour: 0.5 + sum sh_lm Y_lm(dir), dir from the camera centre, >= 0
+        double dx = mx3 - cam.campos[0], dy = my3 - cam.campos[1], dz = mz3 - cam.campos[2];
+        const double dn = sqrt(dx * dx + dy * dy + dz * dz);
+        dx /= dn; dy /= dn; dz /= dn;
+        double Y[16];
+        sh_basis(dx, dy, dz, degree, Y);
+        double col[3] = {0.0, 0.0, 0.0};
+        if constexpr (DIRECT) {
+            const float* shg = reinterpret_cast<const float*>(shv);
+    #pragma unroll
+            for (int k = 0; k < kMaxShFloats / 3; ++k) {
+                col[0] += (double)shg[3 * k] * Y[k];
+                col[1] += (double)shg[3 * k + 1] * Y[k];
+                col[2] += (double)shg[3 * k + 2] * Y[k];
+            }
         } else {
-            // opacity-aware footprint: alpha >= 1/255 requires q <= 2 ln(255 o),
-            // whose ellipse has half-extents sqrt(tau c00), sqrt(tau c11)
-            const double tau = 2.0 * log(255.0 * o);
-            ex = sqrt(tau * c00) * (1.0 + 1e-4) + 1e-3;
-            ey = sqrt(tau * c11) * (1.0 + 1e-4) + 1e-3;
+            const float* shg = reinterpret_cast<const float*>(sh_lds) + threadIdx.x * nsh * 3;
+            for (int k = 0; k < nsh; ++k) {
+                col[0] += (double)shg[3 * k] * Y[k];
+                col[1] += (double)shg[3 * k + 1] * Y[k];
+                col[2] += (double)shg[3 * k + 2] * Y[k];
+            }
         }
-        const double ts = (double)cam.tile;
-        double fx0 = floor((mxs - ex) / ts), fx1 = floor((mxs + ex) / ts) + 1.0;
-        double fy0 = floor((mys - ey) / ts), fy1 = floor((mys + ey) / ts) + 1.0;
-        fx0 = fmin(fmax(fx0, 0.0), (double)cam.tiles_x);
-        fx1 = fmin(fmax(fx1, 0.0), (double)cam.tiles_x);
-        fy0 = fmin(fmax(fy0, 0.0), (double)cam.tiles_y);
-        fy1 = fmin(fmax(fy1, 0.0), (double)cam.tiles_y);
-        x0 = (int)fx0; x1 = (int)fx1; y0 = (int)fy0; y1 = (int)fy1;
-        ok = (x1 > x0) && (y1 > y0);
-    }
-    if (!ok) {
-        out[0] = zero4; out[1] = zero4; out[2] = zero4; out[3] = zero4;
+        const float hx = (float)mxs, hy = (float)mys;
+        out[0] = make_float4(hx, hy, (float)(mxs - (double)hx), (float)(mys - (double)hy));
+        out[1] = make_float4((float)(c11 / det), (float)(-c01 / det), (float)(c00 / det), (float)o);
+        out[2] = make_float4((float)fmax(0.0, 0.5 + col[0]), (float)fmax(0.0, 0.5 + col[1]),
+                             (float)fmax(0.0, 0.5 + col[2]), (float)smax);
+        out[3] = zero4;
+        const float zf = (float)z;
+        inf.x = __float_as_uint(zf);
+        inf.y = (uint32_t)x0 | ((uint32_t)y0 << 16);
+        inf.z = (uint32_t)x1 | ((uint32_t)y1 << 16);
+        inf.w = (uint32_t)((x1 - x0) * (y1 - y0));
         info[g] = inf;
-        return;
-    }
-    // colour: 0.5 + sum sh_lm Y_lm(dir), dir from the camera centre, >= 0
-    double dx = mx3 - cam.campos[0], dy = my3 - cam.campos[1], dz = mz3 - cam.campos[2];
-    const double dn = sqrt(dx * dx + dy * dy + dz * dz);
-    dx /= dn; dy /= dn; dz /= dn;
-    double Y[16];
-    sh_basis(dx, dy, dz, degree, Y);
-    double col[3] = {0.0, 0.0, 0.0};
-    if constexpr (DIRECT) {
-        const float* shg = reinterpret_cast<const float*>(shv);
-#pragma unroll
-        for (int k = 0; k < kMaxShFloats / 3; ++k) {
-            col[0] += (double)shg[3 * k] * Y[k];
-            col[1] += (double)shg[3 * k + 1] * Y[k];
-            col[2] += (double)shg[3 * k + 2] * Y[k];
-        }
-    } else {
-        const float* shg = reinterpret_cast<const float*>(sh_lds) + threadIdx.x * nsh * 3;
-        for (int k = 0; k < nsh; ++k) {
-            col[0] += (double)shg[3 * k] * Y[k];
-            col[1] += (double)shg[3 * k + 1] * Y[k];
-            col[2] += (double)shg[3 * k + 2] * Y[k];
-        }
-    }
-    const float hx = (float)mxs, hy = (float)mys;
-    out[0] = make_float4(hx, hy, (float)(mxs - (double)hx), (float)(mys - (double)hy));
-    out[1] = make_float4((float)(c11 / det), (float)(-c01 / det), (float)(c00 / det), (float)o);
-    out[2] = make_float4((float)fmax(0.0, 0.5 + col[0]), (float)fmax(0.0, 0.5 + col[1]),
-                         (float)fmax(0.0, 0.5 + col[2]), (float)smax);
-    out[3] = zero4;
-    const float zf = (float)z;
-    inf.x = __float_as_uint(zf);
-    inf.y = (uint32_t)x0 | ((uint32_t)y0 << 16);
-    inf.z = (uint32_t)x1 | ((uint32_t)y1 << 16);
-    inf.w = (uint32_t)((x1 - x0) * (y1 - y0));
-    info[g] = inf;
+    };
+#pragma unroll 1
+    for (int v = 0; v < views.nv; ++v) one(views.cam[v], views.splats[v], views.info[v]);
 }
 
 // sum_k gY[k] grad Y_k at the unit direction (x, y, z): the derivatives of
@@ -587,20 +594,27 @@ __global__ void __launch_bounds__(256) geom_bwd_kernel(const float* __restrict__
     d_logits[g] = (float)glogit;
 }
 
-hipError_t launch_project(const tgs_gaussians& g, const Cam& cam, float* splats, uint32_t* info, hipStream_t s) {
-    if (g.n == 0) return hipSuccess;
+hipError_t launch_project_views(const tgs_gaussians& g, const ProjViews& views, hipStream_t s) {
+    if (g.n == 0 || views.nv == 0) return hipSuccess;
     const int block = kProjThreads;
     const int64_t grid = (g.n + block - 1) / block;
     const bool direct = g.sh_degree == 3 && (reinterpret_cast<uintptr_t>(g.sh_dev) & 15) == 0;
     if (direct)
         hipLaunchKernelGGL(project_kernel<true>, dim3((unsigned)grid), dim3(block), 0, s, g.means_dev,
-                           g.log_scales_dev, g.quats_dev, g.logits_dev, g.sh_dev, g.n, g.sh_degree, cam,
-                           reinterpret_cast<float4*>(splats), reinterpret_cast<uint4*>(info));
+                           g.log_scales_dev, g.quats_dev, g.logits_dev, g.sh_dev, g.n, g.sh_degree, views);
     else
         hipLaunchKernelGGL(project_kernel<false>, dim3((unsigned)grid), dim3(block), 0, s, g.means_dev,
-                           g.log_scales_dev, g.quats_dev, g.logits_dev, g.sh_dev, g.n, g.sh_degree, cam,
-                           reinterpret_cast<float4*>(splats), reinterpret_cast<uint4*>(info));
+                           g.log_scales_dev, g.quats_dev, g.logits_dev, g.sh_dev, g.n, g.sh_degree, views);
     return hipGetLastError();
+}
+
+hipError_t launch_project(const tgs_gaussians& g, const Cam& cam, float* splats, uint32_t* info, hipStream_t s) {
+    ProjViews v{};
+    v.nv = 1;
+    v.cam[0] = cam;
+    v.splats[0] = reinterpret_cast<float4*>(splats);
+    v.info[0] = reinterpret_cast<uint4*>(info);
+    return launch_project_views(g, v, s);
 }
 
 hipError_t launch_project_backward(const tgs_gaussians& g, const Cam& cam, const float* d_splats,

@@ -134,3 +134,29 @@ def test_autotuner_picks_valid_schedule_and_caches(tmp_path):
     b = tg.render(g, cam)
     torch.cuda.synchronize()
     assert (a["rgb"] - b["rgb"]).abs().max().item() <= 1e-5
+
+
+@pytest.mark.parametrize("degree", [0, 3])
+def test_project_views_equals_per_view_projection(degree):
+    # one launch per four cameras, each lane reading its Gaussian once: the
+    # splat and info lines of every view equal tgs_project's bit for bit
+    # (mixed tile sizes and footprints; 6 views = a full and a partial launch)
+    gnp, _ = scenes.batched_scene(seed=7, n=50000)
+    if degree == 3:
+        rng = np.random.default_rng(7)
+        gnp = dict(gnp, sh=rng.normal(0, 0.2, size=(50000, 16, 3)).astype(np.float32), sh_degree=3)
+    cams = small_views(6, scale=0.5, seed=7)
+    params = [tg.Params(tile_size=ts, footprint=fp) for ts, fp in
+              ((16, "opacity"), (8, "opacity"), (32, "three_sigma"), (16, "three_sigma"), (32, "opacity"),
+               (8, "three_sigma"))]
+    g = tg.to_device(gnp, dev())
+    n = 50000
+    outs = [(torch.full((n, 16), -1.0, device=dev()), torch.full((n, 4), -1, dtype=torch.int32, device=dev()))
+            for _ in cams]
+    tg.project_views(g, cams, params, outs)
+    torch.cuda.synchronize()
+    for v, (c, p) in enumerate(zip(cams, params)):
+        s, i = tg.project(g, c, p)
+        torch.cuda.synchronize()
+        assert torch.equal(outs[v][0], s) and torch.equal(outs[v][1], i), v
+        assert int((i[:, 3] > 0).sum()) > 1000, v
