@@ -84,7 +84,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--mode", default="frame", choices=["frame", "kernels", "train", "batch", "learned", "repair",
-                                                      "scale", "stress", "oracle-single"],
+                                                      "scale", "stress", "layout", "oracle-single"],
                     help="kernels: only launch the product and comparator raster kernels and a "
                          "256 MiB device copy (for profiler counter runs); train: only the training "
                          "step (forward + backward) on the 500k-Gaussian 1297x840 scene")
@@ -591,6 +591,37 @@ def stress(args):
     return out
 
 
+def layout(args):
+    """Storage layout of the Gaussians (the paper's raster-order-aware
+    storage direction): the 1080p workload and the 500k training scene with
+    the Gaussians in generation order (points drawn surface by surface, in
+    random order on each) against Z-order of their means; per-stage median
+    ms of the binned frame, and the largest image difference (the order of
+    equal depths follows the Gaussian id, so only exact depth ties can move)."""
+    import torch
+    import paper_2609_03613_amd as tg
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    steps = max(args.steps, 10)
+    out = {}
+    for name, (g, cam) in (("1080p scene-shaped, 1M", scenes.scene_1080p(seed=0)),
+                           ("training scene, 500k", scenes.training_scene(seed=0))):
+        row, imgs = {}, {}
+        for order, gg in (("generation", g), ("morton", scenes.morton_sorted(g))):
+            gd = tg.to_device(gg, dev)
+            r = tg.Renderer(cam, tg.Params(), device=dev)
+            st, _, img = _stage_times(tg, r, gd, cam, "binned", steps, stream)
+            row[order] = st
+            imgs[order] = img["rgb"].clone()
+            del gd
+        row["raster_x"] = row["generation"]["raster"] / row["morton"]["raster"]
+        row["frame_x"] = row["generation"]["frame"] / row["morton"]["frame"]
+        row["max_abs_image_diff"] = float((imgs["generation"] - imgs["morton"]).abs().max().item())
+        out[name] = row
+        torch.cuda.empty_cache()
+    return out
+
+
 def workload(name):
     if name == "1080p":
         g, cam = scenes.scene_1080p(seed=0)
@@ -762,6 +793,9 @@ def main():
         return
     if args.mode == "scale":
         print(json.dumps({"mode": "scale", **scale_up(args)}), flush=True)
+        return
+    if args.mode == "layout":
+        print(json.dumps({"mode": "layout", **layout(args)}), flush=True)
         return
     if args.mode == "repair":
         import torch

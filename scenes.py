@@ -297,6 +297,21 @@ def guard_scene(seed=0, n=4000, width=256, height=192, focal=200.0):
     return g, cam
 
 
+def morton_sorted(g, bits=10):
+    """The same Gaussians stored in the Z-order (Morton order) of their
+    means over the scene's bounding box, quantised to 2^bits cells per
+    axis: a storage layout in which Gaussians that are near in space, and so
+    in the same screen tiles, are near in memory."""
+    m = np.asarray(g["means"], np.float64)
+    lo, hi = m.min(0), m.max(0)
+    q = ((m - lo) / np.maximum(hi - lo, 1e-12) * ((1 << bits) - 1)).astype(np.uint64)
+    code = np.zeros(len(m), np.uint64)
+    for b in range(bits):
+        for a in range(3):
+            code |= ((q[:, a] >> np.uint64(b)) & np.uint64(1)) << np.uint64(3 * b + a)
+    return subset(g, np.argsort(code, kind="stable"))
+
+
 def subset(g, idx):
     """Gaussians ``idx`` of scene ``g`` (keeps the degree)."""
     out = {k: np.ascontiguousarray(v[idx]) for k, v in g.items() if k != "sh_degree"}
