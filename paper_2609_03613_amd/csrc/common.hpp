@@ -398,7 +398,9 @@ hipError_t launch_bin_scatter(const uint32_t* info, int64_t n, const uint32_t* e
 // list_stride entries); repaired[] and counters[3] stay per segment.
 // tile_hist != null: also adds each tile's bit-length bucket to the tile
 // order histogram tile_hist [33] (zero before), so that only the placement
-// half of the tile order is left (TileOrder).
+// half of the tile order is left (TileOrder). With SB > 1, a group of at
+// most 4096 entries is staged through LDS and its sub-segments of up to 128
+// entries come out in pair order (they are not queued).
 // The group count needs no bins; its first workgroup computes the depth
 // range (ra) meanwhile, which the group scatter then uses.
 hipError_t launch_group_count(const uint32_t* info, int64_t n, const uint32_t* emit_off, GroupMap gm, int tiles_x,

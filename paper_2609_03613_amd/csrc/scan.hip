@@ -685,18 +685,47 @@ __global__ void __launch_bounds__(kTailThreads) group_scan_kernel(const uint32_t
 #ifndef TGS_SORT_THREADS
 #define TGS_SORT_THREADS 512
 #endif
+#ifndef TGS_SORT_BATCH
+#define TGS_SORT_BATCH (8192 / TGS_SORT_THREADS)
+#endif
+#ifndef TGS_SORT_WAVES_PER_EU
+#define TGS_SORT_WAVES_PER_EU 0
+#endif
+#if TGS_SORT_WAVES_PER_EU > 0
+#define TGS_SORT_ATTR __attribute__((amdgpu_waves_per_eu(TGS_SORT_WAVES_PER_EU, TGS_SORT_WAVES_PER_EU)))
+#else
+#define TGS_SORT_ATTR
+#endif
 constexpr int kSortThreads = TGS_SORT_THREADS;  // threads of a group-sort workgroup
-constexpr int kSortBatch = 8192 / kSortThreads;  // entries per thread and sweep step, loaded before any is used
+constexpr int kSortBatch = TGS_SORT_BATCH;      // entries per thread and sweep step, loaded before any is used
 constexpr int kTileBuckets = 33;                  // tile order buckets: bit lengths 32 .. 0 of the entry count
+
+// Staging of the group sort's output when the lists hold sub-segment
+// descriptors (SB > 1: exact repair, no records) and the group has at most
+// kStage entries: they are placed at their code offsets in LDS, each
+// sub-segment of 2..kRankMax entries is put in pair order there (an entry's
+// rank among its sub-segment's pairs, ties by slot), and the group is
+// written out in order: the output is written in runs instead of one
+// scattered 8-byte store per entry, and the short sub-segments need no
+// repair pass.
+#ifndef TGS_RANK_MAX
+#define TGS_RANK_MAX 128
+#endif
+#ifndef TGS_STAGE
+#define TGS_STAGE 4096
+#endif
+constexpr int kStage = TGS_STAGE;
+constexpr int kRankMax = TGS_RANK_MAX;
 
 // One workgroup per group: its entries [group_off[g], group_off[g + 1])
 // (clipped to the capacity) are counted per code (segment, or sub-segment
 // when SB > 1) in LDS, the code offsets follow by a workgroup scan, and a
-// second sweep places every entry at its code offset + an LDS rank. Also
-// writes bin_off for the group's segments, queues the repair segments (as
-// bin_offsets_kernel; sub-segments as {begin, length} when SB > 1),
-// and writes the records of single-entry segments.
-__global__ void __launch_bounds__(kSortThreads) group_sort_kernel(
+// second sweep places every entry at its code offset + an LDS rank (staged
+// as above when SB > 1). Also writes bin_off for the group's segments,
+// queues the repair segments (as bin_offsets_kernel; sub-segments as
+// {begin, length} when SB > 1, without those the staging ordered), and
+// writes the records of single-entry segments.
+__global__ void __launch_bounds__(kSortThreads) TGS_SORT_ATTR group_sort_kernel(
     const uint64_t* __restrict__ tmp_pair, const uint16_t* __restrict__ tmp_code, const uint32_t* __restrict__ group_off,
     const uint32_t* __restrict__ order, GroupMap gm, int64_t nseg, int64_t capacity, uint64_t* __restrict__ pairs,
     uint32_t* __restrict__ bin_off, uint32_t* __restrict__ lists, int64_t list_stride,
@@ -710,6 +739,8 @@ __global__ void __launch_bounds__(kSortThreads) group_sort_kernel(
     __shared__ uint32_t lds32[NT / kWave];
     __shared__ uint32_t lcount[kBuckets], lbase[kBuckets];
     __shared__ uint32_t thist[kTileBuckets];
+    __shared__ uint64_t stage[kStage];
+    __shared__ uint16_t scode[kStage];
     const int g = (int)order[blockIdx.x];
     const int64_t cap = capacity;
     const uint32_t lo = (uint32_t)min((int64_t)group_off[g], cap);
@@ -776,6 +807,10 @@ __global__ void __launch_bounds__(kSortThreads) group_sort_kernel(
     }
     const bool queue = queue_all && counters[2] == 0;
     const int64_t cbase = sbase * gm.SB;  // id of the group's first code
+    const uint32_t n = hi - lo;
+    const bool staged = gm.SB > 1 && n <= (uint32_t)kStage;
+    // sub-segments the staging puts in order (none with an overflow)
+    const uint32_t local_max = staged && queue ? (uint32_t)kRankMax : 1u;
     // repair queues per code (segments when SB == 1, sub-segments otherwise)
     int bk[kMaxPer];
 #pragma unroll
@@ -783,7 +818,7 @@ __global__ void __launch_bounds__(kSortThreads) group_sort_kernel(
         const int c = r * NT + threadIdx.x;
         bk[r] = -1;
         if (r < per && c < codes) {
-            if (queue) bk[r] = bucket_of(hist[c]);
+            if (queue && hist[c] > local_max) bk[r] = bucket_of(hist[c]);
         }
     }
     // offsets, repair flags and repaired entries per segment
@@ -814,26 +849,70 @@ __global__ void __launch_bounds__(kSortThreads) group_sort_kernel(
         if (threadIdx.x == 0 && qsum)
             atomicAdd(reinterpret_cast<unsigned long long*>(&counters[3]), (unsigned long long)qsum);
     }
-    for (uint32_t base = lo; base < hi; base += NT * kSortBatch) {
-        uint32_t c[kSortBatch];
-        uint64_t pr[kSortBatch];
+    if (staged) {
+        // place at the code offsets in LDS ...
+        for (uint32_t base = lo; base < hi; base += NT * kSortBatch) {
+            uint32_t c[kSortBatch];
+            uint64_t pr[kSortBatch];
 #pragma unroll
-        for (int j = 0; j < kSortBatch; ++j) {
-            const uint32_t e = base + (uint32_t)(j * NT) + threadIdx.x;
-            c[j] = kNone;
-            pr[j] = 0;
-            if (e < hi) {
-                c[j] = tmp_code[e];
-                pr[j] = tmp_pair[e];
+            for (int j = 0; j < kSortBatch; ++j) {
+                const uint32_t e = base + (uint32_t)(j * NT) + threadIdx.x;
+                c[j] = kNone;
+                pr[j] = 0;
+                if (e < hi) {
+                    c[j] = tmp_code[e];
+                    pr[j] = tmp_pair[e];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < kSortBatch; ++j) {
+                if (c[j] == kNone) continue;
+                const uint32_t q = atomicAdd(&cur[c[j]], 1u);
+                stage[q] = pr[j];
+                scode[q] = (uint16_t)c[j];
             }
         }
+        __syncthreads();
+        // ... and write the group out in order, short sub-segments by rank
+        for (uint32_t q = threadIdx.x; q < n; q += NT) {
+            const uint32_t c = scode[q];
+            const uint64_t v = stage[q];
+            uint32_t out = q;
+            const uint32_t len = hist[c];
+            if (len >= 2 && len <= local_max) {
+                // the code's slots are [cur - len, cur) once placed
+                const uint32_t b = cur[c] - len;
+                uint32_t rank = 0;
+                for (uint32_t k = 0; k < len; ++k) {
+                    const uint64_t x = stage[b + k];
+                    rank += (x < v || (x == v && b + k < q)) ? 1u : 0u;
+                }
+                out = b + rank;
+            }
+            pairs[lo + out] = v;
+        }
+    } else {
+        for (uint32_t base = lo; base < hi; base += NT * kSortBatch) {
+            uint32_t c[kSortBatch];
+            uint64_t pr[kSortBatch];
 #pragma unroll
-        for (int j = 0; j < kSortBatch; ++j) {
-            if (c[j] == kNone) continue;
-            const uint32_t p = lo + atomicAdd(&cur[c[j]], 1u);
-            pairs[p] = pr[j];
-            // records exist only with SB == 1, where a code is a segment
-            if (rs.masks && hist[c[j]] == 1u) rs.put((uint32_t)(sbase + c[j]), p, pr[j]);
+            for (int j = 0; j < kSortBatch; ++j) {
+                const uint32_t e = base + (uint32_t)(j * NT) + threadIdx.x;
+                c[j] = kNone;
+                pr[j] = 0;
+                if (e < hi) {
+                    c[j] = tmp_code[e];
+                    pr[j] = tmp_pair[e];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < kSortBatch; ++j) {
+                if (c[j] == kNone) continue;
+                const uint32_t p = lo + atomicAdd(&cur[c[j]], 1u);
+                pairs[p] = pr[j];
+                // records exist only with SB == 1, where a code is a segment
+                if (rs.masks && hist[c[j]] == 1u) rs.put((uint32_t)(sbase + c[j]), p, pr[j]);
+            }
         }
     }
     if (tile_hist) {

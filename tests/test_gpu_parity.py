@@ -143,6 +143,59 @@ def test_tail_segments_bit_exact():
     del rng
 
 
+# The staged group sort (exact repair, sub-bins): 8 tiles in one row make
+# one group of 8 x 64 segments. A group of at most 4096 entries is staged in
+# LDS, where sub-segments of 2..128 entries are put in order; longer ones
+# (depth clusters: one shared depth on one tile) are staged and then queued
+# for the repair sorts; a larger group takes the unstaged path.
+STAGE_CASES = [
+    # (n, widest rect in tiles, tie fraction, cluster sizes)
+    (1200, 3, 0.2, ()),
+    (1500, 2, 0.0, (700,)),
+    (3000, 1, 0.1, (2100, 300, 129, 128)),
+    (4096, 1, 0.0, (64,)),
+    (12000, 8, 0.3, (3000, 1000, 200)),
+]
+
+
+@pytest.mark.parametrize("case", STAGE_CASES)
+def test_staged_group_sort(case):
+    n, widest, ties, clusters = case
+    W, H = 128, 16
+    splats, info = scenes.random_splats(n, W, H, seed=n, tie_fraction=ties, max_sigma_px=2.0)
+    rng = np.random.default_rng(n)
+    rect = np.zeros((n, 4), np.int64)
+    x0 = rng.integers(0, 8, n)
+    rect[:, 0] = x0
+    rect[:, 2] = np.minimum(x0 + rng.integers(1, widest + 1, n), 8)
+    rect[:, 3] = 1
+    depth = scenes.info_depth(info).copy()
+    at = 0
+    for k, size in enumerate(clusters):
+        # one shared depth per cluster, all on tile k: one sub-segment of that size
+        depth[at:at + size] = depth[at]
+        rect[at:at + size, 0] = k
+        rect[at:at + size, 2] = k + 1
+        at += size
+    info = scenes.make_info(depth, rect)
+    cam = cam_for(W, H)
+    ref = oracle.schedule(depth, rect, 8, 1, K=64, znear=cam["znear"], zfar=cam["zfar"])
+    M = ref["M"]
+    _, _, _, bb = run_bin(splats, info, cam, "binned", tg.Params(num_bins=64))
+    assert bb.num_entries == M
+    assert np.array_equal(to_np(bb.offsets).view(np.uint32), ref["bin_offsets"])
+    assert np.array_equal(to_np(bb.pairs)[:M].view(np.uint64), ref["stream"])
+    c = to_np(bb.counters)
+    assert c[2] == 0
+    # the path this case is meant to take, and its sub-segments (the bins at
+    # 8 K): each cluster is one sub-segment of at least its size
+    assert (M <= 4096) == (n <= 4096)
+    sub = np.diff(oracle.schedule(depth, rect, 8, 1, K=512, znear=cam["znear"], zfar=cam["zfar"])["bin_offsets"]
+                  .astype(np.int64))
+    for size in clusters:
+        assert (sub >= size).sum() >= sum(1 for s2 in clusters if s2 >= size)
+
+
 @pytest.mark.parametrize("per_tile", [False, True])
 def test_per_entry_atomic_path_bit_exact(per_tile):
     # 8-pixel tiles at 2560x1440 (57,600 tiles) with K = 1024: a group of
