@@ -20,9 +20,9 @@
 // and, when alpha is not capped at 0.99, through alpha = o exp2(q'):
 // dL/do = dL/dalpha exp2(q'), dL/dq' = dL/dalpha alpha ln 2, with q' the
 // scaled quadratic form of the staged conic. The 9 per-lane gradients of an
-// entry are summed over the wavefront (DPP within rows of 16 for each, then
-// one select and two lane swaps for all nine) and lanes 0..8 add the 9 sums
-// to the Gaussian's gradient line with one float atomic each.
+// entry are summed over the wavefront (recursive halving with DPP within the
+// rows of 16 lanes, then two lane swaps) and nine lanes of row 0 add the 9
+// sums to the Gaussian's gradient line with one float atomic each.
 #include <math.h>
 
 #include "raster.hpp"
@@ -33,27 +33,47 @@ namespace {
 
 using namespace raster;
 
-// Sum over the 16 lanes of each row, result in every lane of the row.
-__device__ __forceinline__ float row_sum(float v) {
-    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));   // quad [1,0,3,2]
-    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));   // quad [2,3,0,1]
-    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, false));  // row half-mirror
-    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, false));  // row mirror
-    return v;
+// v + the value of the DPP partner (control CTRL) of the lane.
+template <int CTRL>
+__device__ __forceinline__ float dpp_add(float v, float send) {
+    return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(send), CTRL, 0xF, 0xF, false));
 }
 
-// Wavefront sums of 9 values: d[k] summed over the 64 lanes ends in lane k
-// (k < 9). Every value is first summed within each row of 16 lanes (DPP,
-// result in every lane of the row); lane c of each row then keeps the row
-// sum of value c, and two lane swaps add the four rows.
+// One halving step of the row reduction: the lane keeps the slots of its
+// side (hi: the upper set) and adds its partner's copy of them, which the
+// partner, on the other side, sends.
+template <int CTRL>
+__device__ __forceinline__ float halve(bool hi, float lower, float upper) {
+    return dpp_add<CTRL>(hi ? upper : lower, hi ? lower : upper);
+}
+
+// Word of the gradient line whose wavefront sum wave_sums9 leaves in lane
+// i (0..15) of a row, 0xF for none: lanes 0, 1, 2, 4, 5 hold words 0..4,
+// lanes 8, 9, 10, 12 words 5..8.
+constexpr uint64_t kSumWord = 0xFFF8F765FF43F210ull;
+
+// Wavefront sums of 9 values by recursive halving within the rows of 16
+// lanes: each step pairs every lane with a partner on the other side of a
+// split (row mirror: i and 15 - i; half-row mirror: i and 7 - i within each
+// half; then lane ^ 2 and lane ^ 1), the lane keeps half of its value slots
+// and adds the partner's copy of them (9 -> 5 -> 3 -> 2 -> 1 slots), so that
+// after four steps every lane holds one value summed over its row; the four
+// rows are then added by two lane swaps. The sum of word w ends in the row-0
+// lane whose kSumWord nibble is w.
 __device__ __forceinline__ float wave_sums9(const float* d) {
-    const int c = lane() & 15;
-    float mine = 0.f;
+    const int i = lane() & 15;
+    const bool ha = i >= 8, hb = (i & 4) != 0, hc = (i & 2) != 0, hd = (i & 1) != 0;
+    float a[5];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
-        const float r = row_sum(d[k]);
-        mine = c == k ? r : mine;
-    }
+    for (int s = 0; s < 4; ++s) a[s] = halve<0x140>(ha, d[s], d[5 + s]);
+    a[4] = halve<0x140>(ha, d[4], 0.f);
+    float b[3];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) b[t] = halve<0x141>(hb, a[t], a[3 + t]);
+    b[2] = halve<0x141>(hb, a[2], 0.f);
+    const float c0 = halve<0x4E>(hc, b[0], b[2]);
+    const float c1 = halve<0x4E>(hc, b[1], 0.f);
+    float mine = halve<0xB1>(hd, c0, c1);
     mine += __shfl_xor(mine, 16, kWave);
     mine += __shfl_xor(mine, 32, kWave);
     return mine;
@@ -118,6 +138,8 @@ __global__ void __launch_bounds__(256) raster_bwd_kernel(RasterArgs A, const flo
     }
     const float Tf = p.T;
     const float gaT = ga * Tf;
+    // the gradient word this lane adds (row 0 only)
+    const int sum_word = l < 16 ? (int)((kSumWord >> (4 * l)) & 0xF) : 0xF;
     float T = Tf;
     float Sr = Tf * A.bg[0], Sg = Tf * A.bg[1], Sb = Tf * A.bg[2];
     // Chunks of 64 entries downwards from hi; lane l holds entry top - l. The
@@ -200,7 +222,7 @@ __global__ void __launch_bounds__(256) raster_bwd_kernel(RasterArgs A, const flo
                 }
             }
             const float mine = wave_sums9(d);
-            if (l < 9) unsafeAtomicAdd(d_splats + kGradWords * (int64_t)idw[j] + l, mine);
+            if (sum_word != 0xF) unsafeAtomicAdd(d_splats + kGradWords * (int64_t)idw[j] + sum_word, mine);
         }
         wave_sync();
     };
