@@ -192,6 +192,9 @@ __global__ void __launch_bounds__(256) raster_bwd_kernel(RasterArgs A, const flo
             if (ballot(comp) == 0) continue;
             float d[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
             if (comp) {
+                // the gradient arithmetic may fuse (the bars are not bitwise);
+                // the compositing decision above repeats the forward exactly
+#pragma clang fp contract(fast)
                 const float alpha = fminf(kAlphaMax, araw);
                 const float om = 1.0f - alpha;
                 // 1 / (1 - alpha) to within an ulp (hardware reciprocal);
