@@ -985,7 +985,7 @@ def main():
         "tests_per_pixel": {"support": n_support / (W * H), "visit_binned": n_visit_b / (W * H),
                             "visit_global": n_visit_g / (W * H)},
         "images_bitwise_equal": same,
-        "heavy_tile_split": {"tiles": n_split[0], "min_entries": n_split[1], "waves_per_block": 8,
+        "heavy_tile_split": {"tiles": n_split[0], "min_entries": n_split[1], "waves_per_block": 4,
                              "max_abs_diff_vs_unsplit": split_diff, "last_equal": split_last_equal},
         "raster_ablation_ms": ablation,
         "bin_stage_ms_by_variant": bin_ms,

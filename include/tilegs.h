@@ -192,8 +192,8 @@ typedef struct {
                              a tile order, the tiles with at least this many
                              entries and split_mean_factor x the mean of the
                              non-empty tiles (the threshold raised by powers
-                             of two to at most 1024 tiles) get 8 wavefronts
-                             per 8x8 block, each over an eighth of the range
+                             of two to at most 1024 tiles) get 4 wavefronts
+                             per 8x8 block, each over a quarter of the range
                              (merged in order, parts where a pixel stops
                              walked again from their entering transmittance);
                              images equal the unsplit ones up to rounding
