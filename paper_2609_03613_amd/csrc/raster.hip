@@ -247,8 +247,8 @@ __global__ void __launch_bounds__(kSplitWaves * kWave) raster_split_kernel(Raste
 template <int SRC>
 hipError_t split_dispatch(const RasterArgs& a, hipStream_t s) {
     const int T = a.tiles_x * a.tiles_y;
-    // split blocks first, then two light tiles per workgroup; workgroups
-    // past the last item leave at once
+    // split blocks first (one workgroup per 8x8 block), then one light tile
+    // per workgroup; workgroups past the last item leave at once
     const int grid = 4 * std::min(T, kSplitTiles) + (T + kSplitWaves / 4 - 1) / (kSplitWaves / 4);
     if (a.n_visit || a.n_support || a.n_contrib)
         hipLaunchKernelGGL((raster_split_kernel<SRC, true>), dim3(grid), dim3(kSplitWaves * kWave), 0, s, a);
