@@ -674,12 +674,38 @@ constexpr int kOrderBuckets = 33;  // tile order buckets: bit lengths 32 .. 0 of
 template <int NT>
 __device__ __forceinline__ void tile_place_chunk(const TileOrder& to, int64_t chunk, uint32_t* h, uint32_t* base);
 
+// One segment of 513..8192 keys by the workgroup: coalesced load into LDS
+// (padded slots), E keys per thread into registers, the register / lane /
+// LDS bitonic network of sort_block_reg, and a coalesced store (with the
+// records when !DESC).
+template <int E, bool DESC>
+__device__ __forceinline__ void sort_large_block(uint64_t* pairs, uint32_t s, uint32_t begin, uint32_t len,
+                                                 const RecordSink& rs, uint64_t* buf) {
+    constexpr uint32_t P = (uint32_t)kLargeThreads * E;
+    for (uint32_t e = threadIdx.x; e < P; e += kLargeThreads) buf[block_slot<E>(e)] = e < len ? pairs[begin + e] : ~0ull;
+    __syncthreads();
+    uint64_t v[E];
+#pragma unroll
+    for (int k = 0; k < E; ++k) v[k] = buf[block_slot<E>((uint32_t)(threadIdx.x * E + k))];
+    __syncthreads();
+    sort_block_reg<E, kLargeThreads>(v, buf);
+#pragma unroll
+    for (int k = 0; k < E; ++k) buf[block_slot<E>((uint32_t)(threadIdx.x * E + k))] = v[k];
+    __syncthreads();
+    for (uint32_t e = threadIdx.x; e < len; e += kLargeThreads) {
+        const uint64_t x = buf[block_slot<E>(e)];
+        pairs[begin + e] = x;
+        if (!DESC) rs.put(s, begin + e, x);
+    }
+    __syncthreads();
+}
+
 template <bool DESC>
 __global__ void __launch_bounds__(kLargeThreads) sort_large_kernel(const uint32_t* __restrict__ bin_off,
                                                                    const uint32_t* __restrict__ lists, int64_t nseg,
                                                                    const uint32_t* __restrict__ bucket_count,
                                                                    uint64_t* pairs, RecordSink rs, TileOrder to) {
-    __shared__ uint64_t buf[kLargeCap];
+    __shared__ uint64_t buf[kLargeCap + kLargeThreads];  // block_slot<E> of P = 512 E keys: at most 8192 + 512
     auto entry = [&](int bucket, uint32_t i) {
         const int64_t at = (int64_t)bucket * nseg + i;
         return DESC ? reinterpret_cast<const uint2*>(lists)[at] : make_uint2(lists[at], 0u);
@@ -691,27 +717,15 @@ __global__ void __launch_bounds__(kLargeThreads) sort_large_kernel(const uint32_
             locate<DESC>(bin_off, entry(bucket, i), s, begin, len);
             uint32_t P = 1;
             while (P < len) P <<= 1;
-            for (uint32_t e = threadIdx.x; e < P; e += kLargeThreads) buf[e] = e < len ? pairs[begin + e] : ~0ull;
-            __syncthreads();
-            for (uint32_t k = 2; k <= P; k <<= 1) {
-                for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-                    for (uint32_t t = threadIdx.x; t < P / 2; t += kLargeThreads) {
-                        const uint32_t lo = (t / j) * 2 * j + (t % j), hi = lo + j;
-                        const uint64_t a = buf[lo], b = buf[hi];
-                        const bool up = (lo & k) == 0;
-                        if ((a > b) == up) {
-                            buf[lo] = b;
-                            buf[hi] = a;
-                        }
-                    }
-                    __syncthreads();
-                }
-            }
-            for (uint32_t e = threadIdx.x; e < len; e += kLargeThreads) {
-                pairs[begin + e] = buf[e];
-                if (!DESC) rs.put(s, begin + e, buf[e]);
-            }
-            __syncthreads();
+            // E = P / kLargeThreads keys per thread (P = 1024 .. 8192)
+            if (P <= 1024)
+                sort_large_block<2, DESC>(pairs, s, begin, len, rs, buf);
+            else if (P <= 2048)
+                sort_large_block<4, DESC>(pairs, s, begin, len, rs, buf);
+            else if (P <= 4096)
+                sort_large_block<8, DESC>(pairs, s, begin, len, rs, buf);
+            else
+                sort_large_block<16, DESC>(pairs, s, begin, len, rs, buf);
         }
     }
     const uint32_t cnt = bucket_count[7];

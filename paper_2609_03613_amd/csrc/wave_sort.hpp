@@ -104,4 +104,63 @@ __device__ __forceinline__ void sort_wave_reg(uint64_t* __restrict__ seg, uint32
     }
 }
 
+// LDS slot of key i in the workgroup networks below: one pad slot after
+// every E keys, so that the E-key runs of consecutive threads start in
+// different banks.
+template <int E>
+__device__ __forceinline__ uint32_t block_slot(uint32_t i) {
+    return i + i / E;
+}
+
+// Segments of 513..8192 keys: one workgroup of NT threads, E consecutive
+// keys per thread in registers (key i = t E + k in register k of thread t,
+// padded with the maximum key; P = NT E keys): the bitonic network with the
+// comparators at distance j < E inside a thread, E <= j < 64 E between the
+// lanes of a wavefront (lane l ^ j / E), and j >= 64 E between wavefronts
+// through LDS (lds: block_slot<E>(P) slots). Only the last log2(NT / 64)
+// merge levels cross wavefronts, so the network takes 2 barriers per
+// cross-wavefront step instead of one per step.
+template <int E, int NT>
+__device__ __forceinline__ void sort_block_reg(uint64_t (&v)[E], uint64_t* lds) {
+    const int t = (int)threadIdx.x, l = lane();
+    constexpr int P = NT * E;
+#pragma unroll
+    for (int kk = 2; kk <= P; kk <<= 1) {
+#pragma unroll
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+            if (j < E) {
+#pragma unroll
+                for (int k = 0; k < E; ++k) {
+                    if (k & j) continue;
+                    const bool up = (((uint32_t)(t * E + k)) & (uint32_t)kk) == 0;
+                    const uint64_t a = v[k], b = v[k | j];
+                    const bool sw = (a > b) == up;
+                    v[k] = sw ? b : a;
+                    v[k | j] = sw ? a : b;
+                }
+            } else if (j < kWave * E) {
+                const int m = j / E;
+#pragma unroll
+                for (int k = 0; k < E; ++k) {
+                    const uint64_t o = xor_lane_u64(v[k], m);
+                    const bool keep_min = ((((uint32_t)(t * E + k)) & (uint32_t)kk) == 0) == ((l & m) == 0);
+                    v[k] = ((v[k] < o) == keep_min) ? v[k] : o;
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < E; ++k) lds[block_slot<E>((uint32_t)(t * E + k))] = v[k];
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < E; ++k) {
+                    const uint32_t i = (uint32_t)(t * E + k);
+                    const uint64_t o = lds[block_slot<E>(i ^ (uint32_t)j)];
+                    const bool keep_min = ((i & (uint32_t)kk) == 0) == ((i & (uint32_t)j) == 0);
+                    v[k] = ((v[k] < o) == keep_min) ? v[k] : o;
+                }
+                __syncthreads();
+            }
+        }
+    }
+}
+
 }  // namespace tgs

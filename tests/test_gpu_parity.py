@@ -359,7 +359,8 @@ def test_invalid_arguments_raise():
             torch.as_tensor(splats).to(dev()), torch.as_tensor(info.view(np.int32)).to(dev()))
 
 
-BUCKET_EDGES = [2, 3, 63, 64, 65, 127, 128, 129, 255, 256, 257, 511, 512, 513, 4096, 4097, 8192, 8193]
+BUCKET_EDGES = [2, 3, 63, 64, 65, 127, 128, 129, 255, 256, 257, 511, 512, 513, 1024, 1025, 2048, 2049, 4096, 4097,
+                8192, 8193]
 
 
 def test_repair_bucket_edges_and_records():
