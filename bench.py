@@ -194,10 +194,11 @@ def train_step(args):
 def batched(args):
     """16 cameras of uneven resolution on a ring around 3M Gaussians (SH0):
     per-view tile size and bins from the autotuner, the whole multi-view
-    frame (16 projections, 16 binnings, one persistent raster launch)
-    captured in a HIP graph and replayed. Beside it: the same frame launched
-    eagerly, and the per-view default path (16 px tiles, K = 64, one raster
-    launch per view)."""
+    frame (projection in launches of four views, 16 binnings on four
+    streams, one persistent raster launch) captured in a HIP graph and
+    replayed. Beside it: the same frame launched eagerly, eagerly with the
+    binnings on one stream, and the per-view default path (16 px tiles,
+    K = 64, one raster launch per view)."""
     import torch
     import paper_2609_03613_amd as tg
     from paper_2609_03613_amd import autotune
@@ -231,6 +232,14 @@ def batched(args):
     graph_ms = timed(br.replay, args.steps)
     assert not br.overflowed()
     eager_ms = timed(lambda: br.frame(gd), args.steps)
+    # the same frame with the per-view binnings one after another on one
+    # stream, eager and captured
+    lanes = br.lanes
+    br.lanes = 1
+    one_lane_ms = timed(lambda: br.frame(gd), args.steps)
+    br.capture(gd)
+    graph_one_lane_ms = timed(br.replay, args.steps)
+    br.lanes = lanes
     # per-view default path, one raster launch per view
     views = [tg.Renderer(c, tg.Params(), device=dev) for c in cams]
     prep = []
@@ -265,8 +274,11 @@ def batched(args):
     return {"workload": "batched: 3M Gaussians (SH0) on 16 ring cameras, 640x360 .. 2560x1440",
             "views": len(cams), "pixels": pixels, "entries": entries,
             "graph_ms_per_batch": graph_ms, "eager_batched_ms_per_batch": eager_ms,
+            "binning_lanes": lanes, "eager_one_lane_ms_per_batch": one_lane_ms,
+            "graph_one_lane_ms_per_batch": graph_one_lane_ms,
             "per_view_default_ms_per_batch": default_ms, "per_view_tuned_ms_per_batch": tuned_ms,
-            "tuning_gain": default_ms / tuned_ms, "persistent_launch_gain": tuned_ms / eager_ms,
+            "tuning_gain": default_ms / tuned_ms, "persistent_launch_gain": tuned_ms / one_lane_ms,
+            "binning_overlap_gain": graph_one_lane_ms / graph_ms,
             "views_per_s": len(cams) / (graph_ms * 1e-3), "pairs_per_s": entries / (graph_ms * 1e-3),
             "speedup_vs_per_view_default": default_ms / graph_ms, "tuned": tune_recs}
 

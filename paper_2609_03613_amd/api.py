@@ -352,14 +352,19 @@ def render_differentiable(renderer, g, order="binned", bg=(0.0, 0.0, 0.0)):
 class BatchRenderer:
     """Several cameras per frame: tgs_project_views for all views (the
     Gaussians read once per four views), per-view tgs_bin (BINNED, each view
-    with its own params: tile size, bins), then one tgs_rasterize_batch
-    persistent launch for all views. ``capture`` records
+    with its own params: tile size, bins; up to ``lanes`` views at once on
+    side streams), then one tgs_rasterize_batch persistent launch for all
+    views. ``capture`` records
     the whole frame in a HIP graph (torch.cuda.CUDAGraph) after an eager
     frame has sized every buffer; ``replay`` launches it."""
 
-    def __init__(self, cams, params=None, device="cuda", bg=(0.0, 0.0, 0.0)):
+    def __init__(self, cams, params=None, device="cuda", bg=(0.0, 0.0, 0.0), lanes=4):
         if len(cams) > L.MAX_VIEWS:
             raise ValueError(f"at most {L.MAX_VIEWS} views per batch")
+        # per-view binnings run on this many streams at once (default
+        # priority), forked from and joined back into the caller's stream
+        self.lanes = max(1, int(lanes))
+        self._side = None
         params = params or [Params() for _ in cams]
         self.views = [Renderer(c, p, device=device) for c, p in zip(cams, params)]
         self.device = device
@@ -415,7 +420,22 @@ class BatchRenderer:
         (do this once before capture)."""
         self._alloc_proj(int(g["means"].shape[0]))
         project_views(g, [r.cam for r in self.views], [r.params for r in self.views], self.proj)
-        binned = [r.bin(s, i, "binned", sync=sync) for r, (s, i) in zip(self.views, self.proj)]
+        if sync or self.lanes == 1 or len(self.views) == 1:
+            binned = [r.bin(s, i, "binned", sync=sync) for r, (s, i) in zip(self.views, self.proj)]
+        else:
+            # every view has its own buffers (sized by a sync frame), so the
+            # binnings of different views may overlap
+            main = torch.cuda.current_stream()
+            if self._side is None:
+                self._side = [torch.cuda.Stream(device=self.device) for _ in range(self.lanes)]
+            for st in self._side:
+                st.wait_stream(main)
+            binned = []
+            for v, (r, (sp, ip)) in enumerate(zip(self.views, self.proj)):
+                with torch.cuda.stream(self._side[v % self.lanes]):
+                    binned.append(r.bin(sp, ip, "binned", sync=False))
+            for st in self._side:
+                main.wait_stream(st)
         self.binned = binned
         if sync:
             self.entries = [b.num_entries for b in binned]
