@@ -430,16 +430,29 @@ class BatchRenderer:
                 self._side = [torch.cuda.Stream(device=self.device) for _ in range(self.lanes)]
             for st in self._side:
                 st.wait_stream(main)
-            binned = []
-            for v, (r, (sp, ip)) in enumerate(zip(self.views, self.proj)):
-                with torch.cuda.stream(self._side[v % self.lanes]):
-                    binned.append(r.bin(sp, ip, "binned", sync=False))
+            binned = [None] * len(self.views)
+            for v, lane in self._lane_of():
+                r, (sp, ip) = self.views[v], self.proj[v]
+                with torch.cuda.stream(self._side[lane]):
+                    binned[v] = r.bin(sp, ip, "binned", sync=False)
             for st in self._side:
                 main.wait_stream(st)
         self.binned = binned
         if sync:
             self.entries = [b.num_entries for b in binned]
         return self.rasterize(self.proj, binned)
+
+    def _lane_of(self):
+        """(view, stream) pairs: the views by decreasing entry count (pixels
+        before the first sized frame), each to the least loaded stream."""
+        load = [0] * self.lanes
+        sizes = self.entries or [int(r.cam["width"]) * int(r.cam["height"]) for r in self.views]
+        out = []
+        for v in sorted(range(len(self.views)), key=lambda k: -sizes[k]):
+            lane = min(range(self.lanes), key=lambda k: load[k])
+            load[lane] += sizes[v]
+            out.append((v, lane))
+        return out
 
     def overflowed(self):
         return any(int(b.counters[2].item()) != 0 for b in self.binned)
