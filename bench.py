@@ -93,6 +93,7 @@ def parse():
     ap.add_argument("--no-repair", action="store_true", help="skip the repair-variant ablation")
     ap.add_argument("--no-ksweep", action="store_true", help="skip the bins-per-tile sweep")
     ap.add_argument("--no-scale", action="store_true", help="skip the 10M-Gaussian scale-up point")
+    ap.add_argument("--no-tune", action="store_true", help="training step: skip the autotuned configuration")
     ap.add_argument("--scale-sizes", default="5,10,15,20,25,30",
                     help="Gaussian counts (millions) of --mode scale, comma separated")
     return ap.parse_args()
@@ -133,63 +134,77 @@ def train_step(args):
     small-forward structure, SH degree 3, 1297x840), binned order, inputs
     resident: project, bin, raster, the loss gradient of mean((rgb -
     target)^2), raster backward, projection backward. Returns per-stage
-    median ms (HIP events on the launch stream) and the whole-step rate."""
+    median ms (HIP events on the launch stream) and the whole-step rate,
+    with the paper's tile size and bins (16 px, K = 64) and with the ones
+    the autotuner picks for this camera."""
     import torch
     import paper_2609_03613_amd as tg
+    from paper_2609_03613_amd import autotune
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     g, cam = scenes.training_scene(seed=0)
     gd = tg.to_device(g, dev)
     target = torch.as_tensor(scenes.training_target(cam["width"], cam["height"])).to(dev)
-    r = tg.Renderer(cam, tg.Params(raster="wave", packed=0), device=dev)
-    splats, info = tg.project(gd, cam)
-    b = r.bin(splats, info, "binned", sync=True)
-    M = b.num_entries
     H, W = cam["height"], cam["width"]
-    out = {"rgb": torch.empty((H, W, 3), dtype=torch.float32, device=dev),
-           "alpha": torch.empty((H, W), dtype=torch.float32, device=dev),
-           "last": torch.empty((H, W), dtype=torch.int32, device=dev),
-           "trans": torch.empty((H, W), dtype=torch.float32, device=dev)}
     n = int(g["means"].shape[0])
-    d_splats = torch.empty((n, 12), dtype=torch.float32, device=dev)
-    d_rgb = torch.empty((H, W, 3), dtype=torch.float32, device=dev)
-    scale = 2.0 / (3 * W * H)
-
-    def step(evs=None):
-        if evs: evs[0].record(stream)
-        s, i = tg.project(gd, cam)
-        if evs: evs[1].record(stream)
-        bb = r.bin(s, i, "binned", sync=False)
-        if evs: evs[2].record(stream)
-        o = r.rasterize(s, i, bb, out=out)
-        if evs: evs[3].record(stream)
-        torch.sub(o["rgb"], target, out=d_rgb)
-        d_rgb.mul_(scale)
-        if evs: evs[4].record(stream)
-        r.rasterize_backward(s, i, bb, d_rgb, None, out=d_splats, saved=o)
-        if evs: evs[5].record(stream)
-        grads = tg.project_backward(gd, cam, d_splats)
-        if evs: evs[6].record(stream)
-        return grads
-
-    for _ in range(args.warmup):
-        step()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(7)] for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        step(evs[k])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
     names = ["project", "bin+repair", "raster", "loss grad", "raster backward", "project backward"]
-    st = np.array([[evs[k][j].elapsed_time(evs[k][j + 1]) for j in range(6)] for k in range(args.steps)])
-    med = dict(zip(names, np.median(st, 0).tolist()))
-    return {"workload": "training scene: 500k Gaussians, SH3, 1297x840, f=1297, binned order",
+
+    def measure(p):
+        r = tg.Renderer(cam, p, device=dev)
+        splats, info = tg.project(gd, cam, p)
+        b = r.bin(splats, info, "binned", sync=True)
+        M = b.num_entries
+        out = {"rgb": torch.empty((H, W, 3), dtype=torch.float32, device=dev),
+               "alpha": torch.empty((H, W), dtype=torch.float32, device=dev),
+               "last": torch.empty((H, W), dtype=torch.int32, device=dev),
+               "trans": torch.empty((H, W), dtype=torch.float32, device=dev)}
+        d_splats = torch.empty((n, 12), dtype=torch.float32, device=dev)
+        d_rgb = torch.empty((H, W, 3), dtype=torch.float32, device=dev)
+        scale = 2.0 / (3 * W * H)
+
+        def step(evs=None):
+            if evs: evs[0].record(stream)
+            s, i = tg.project(gd, cam, p)
+            if evs: evs[1].record(stream)
+            bb = r.bin(s, i, "binned", sync=False)
+            if evs: evs[2].record(stream)
+            o = r.rasterize(s, i, bb, out=out)
+            if evs: evs[3].record(stream)
+            torch.sub(o["rgb"], target, out=d_rgb)
+            d_rgb.mul_(scale)
+            if evs: evs[4].record(stream)
+            r.rasterize_backward(s, i, bb, d_rgb, None, out=d_splats, saved=o)
+            if evs: evs[5].record(stream)
+            grads = tg.project_backward(gd, cam, d_splats)
+            if evs: evs[6].record(stream)
+            return grads
+
+        for _ in range(args.warmup):
+            step()
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(7)] for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            step(evs[k])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        st = np.array([[evs[k][j].elapsed_time(evs[k][j + 1]) for j in range(6)] for k in range(args.steps)])
+        med = dict(zip(names, np.median(st, 0).tolist()))
+        return M, wall, med
+
+    M, wall, med = measure(tg.Params(raster="wave", packed=0))
+    res = {"workload": "training scene: 500k Gaussians, SH3, 1297x840, f=1297, binned order",
             "gaussians": n, "entries": M, "ms_per_step": 1000.0 * wall / args.steps,
             "steps_per_s": args.steps / wall, "stage_ms_median": med,
             "backward_ms": med["raster backward"] + med["project backward"],
             "forward_ms": med["project"] + med["bin+repair"] + med["raster"]}
-
+    if not args.no_tune:
+        tp, _ = autotune.tune(gd, cam, cache_path=None, reps=3)
+        tM, twall, tmed = measure(tp)
+        res["tuned"] = {"tile_size": tp.tile_size, "num_bins": tp.num_bins, "entries": tM,
+                        "ms_per_step": 1000.0 * twall / args.steps, "steps_per_s": args.steps / twall,
+                        "stage_ms_median": tmed}
+    return res
 
 def batched(args):
     """16 cameras of uneven resolution on a ring around 3M Gaussians (SH0):

@@ -1,10 +1,11 @@
 """Oracle parity at the stated sizes of the remaining workloads, in the
 launch configurations the benchmark times:
 
-- the training step: 500k Gaussians (SH3) at 1297x840, every Gaussian's
-  gradient line against the oracle's compositing adjoint of the same splats,
-  and every Gaussian's parameter gradients against the oracle's projection
-  adjoint;
+- the training step: 500k Gaussians (SH3) at 1297x840, with 16-pixel tiles
+  and K = 64 and with the autotuned 32-pixel tiles and K = 128, every
+  Gaussian's gradient line against the oracle's compositing adjoint of the
+  same splats, and every Gaussian's parameter gradients against the oracle's
+  projection adjoint;
 - the 4K evaluation scene of the learned bins: 6M Gaussians (SH3) at
   3840x2160, the global and binned streams (22M entries) bit for bit and
   65,536 random pixels end to end;
@@ -59,20 +60,23 @@ def grad_err(gpu, ref):
 # training step: 500k Gaussians, SH3, 1297x840
 # ---------------------------------------------------------------------------
 
-def test_training_step_gradients_full_size():
+# the paper's tile size and bins, and the ones the autotuner picks for this camera
+@pytest.mark.parametrize("ts,K", [(16, 64), (32, 128)])
+def test_training_step_gradients_full_size(ts, K):
     g, cam = scenes.training_scene(seed=0)
     W, H = cam["width"], cam["height"]
     n = len(g["logits"])
     target = scenes.training_target(W, H)
     gd = tg.to_device(g, dev())
-    r = tg.Renderer(cam, tg.Params(), device=dev())
-    splats, info = tg.project(gd, cam)
+    p = tg.Params(tile_size=ts, num_bins=K)
+    r = tg.Renderer(cam, p, device=dev())
+    splats, info = tg.project(gd, cam, p)
     b = r.bin(splats, info, "binned", fresh=True)
     fwd = r.rasterize(splats, info, b, trans=True)
     torch.cuda.synchronize()
-    assert b.num_entries > 7_000_000
+    assert b.num_entries > (7_000_000 if ts == 16 else 2_500_000)
     proj = oracle.splats_to_proj(to_np(splats), to_np(info).view(np.uint32))
-    ref_fwd = oracle.render(proj, W, H)
+    ref_fwd = oracle.render(proj, W, H, tile_size=ts)
     e_rgb, e_a, _ = image_compare(to_np(fwd["rgb"]), to_np(fwd["alpha"]), ref_fwd)
     assert e_rgb <= TOL and e_a <= TOL, (e_rgb, e_a)
     mask = (ref_fwd["flags"] & AMBIG) == 0
@@ -80,7 +84,7 @@ def test_training_step_gradients_full_size():
     # the loss gradient of mean((rgb - target)^2) at the oracle's image, in
     # binary32 so that both sides see the same upstream values
     up = (2.0 * (ref_fwd["rgb"] - target) / ref_fwd["rgb"].size * mask[..., None]).astype(np.float32)
-    ref = oracle.composite_adjoint(proj, W, H, d_img=up)
+    ref = oracle.composite_adjoint(proj, W, H, tile_size=ts, d_img=up)
     up_d = torch.as_tensor(up).to(dev())
     # the benchmark's step (forward state saved), and the recomputed walk
     d_saved = to_np(r.rasterize_backward(splats, info, b, up_d, saved=fwd))
@@ -95,7 +99,7 @@ def test_training_step_gradients_full_size():
     # same lines, and end to end (the GPU's own lines). Gaussians whose
     # visibility or rect the oracle finds within rounding of an edge are left
     # out on both sides.
-    pflags = oracle.project(g, cam)["flags"]
+    pflags = oracle.project(g, cam, tile_size=ts)["flags"]
     keep = (pflags & (oracle.AMBIG_RECT | oracle.AMBIG_VIS)) == 0
     d32 = np.zeros((n, 12), np.float32)
     d32[:, :9] = ref["d_proj"]
