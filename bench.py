@@ -950,14 +950,17 @@ def main():
     n_support = int(cb["n_support"].sum().item())
     n_visit_b = int(cb["n_visit"].sum().item())
     n_visit_g = int(cg["n_visit"].sum().item())
-    # the product without the heavy-tile split equals the comparator bit for
-    # bit; the split regroups the products of the longest tiles
+    # the product equals the comparator bit for bit, with and without the
+    # heavy-tile quad walk (the same per-pixel chain)
     r_unsplit = tg.Renderer(cam, tg.Params(raster="wave", packed=0, split_entries=0), device=dev)
     cu = r_unsplit.rasterize(splats, info, r_unsplit.bin(splats, info, "binned", sync=True), counts=True)
     torch.cuda.synchronize()
     same = bool(torch.equal(cu["rgb"], cg["rgb"]) and torch.equal(cu["last"], cg["last"]))
     split_diff = float((cb["rgb"] - cu["rgb"]).abs().max().item())
     split_last_equal = bool(torch.equal(cb["last"], cu["last"]))
+    split_bitwise = bool(torch.equal(cb["rgb"], cu["rgb"]) and torch.equal(cb["alpha"], cu["alpha"])
+                         and split_last_equal)
+    product_same = bool(torch.equal(cb["rgb"], cg["rgb"]) and torch.equal(cb["last"], cg["last"]))
     n_split = list(bb.split())
     gpu_image = (cb["rgb"].cpu().numpy(), cb["alpha"].cpu().numpy())
     del cb, cg, cu, r_unsplit
@@ -1012,14 +1015,17 @@ def main():
         "tests_per_pixel": {"support": n_support / (W * H), "visit_binned": n_visit_b / (W * H),
                             "visit_global": n_visit_g / (W * H)},
         "images_bitwise_equal": same,
+        "product_equals_comparator": product_same,
         "heavy_tile_split": {"tiles": n_split[0], "min_entries": n_split[1], "waves_per_block": 4,
+                             "walk": "quad: a 4x4 quarter per wavefront, 4 lanes per pixel, 4 entries per step",
+                             "bitwise_equal_to_unsplit": split_bitwise,
                              "max_abs_diff_vs_unsplit": split_diff, "last_equal": split_last_equal},
         "raster_ablation_ms": ablation,
         "bin_stage_ms_by_variant": bin_ms,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_FLOPS / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_FLOPS, "traffic": traffic,
-                     "kernel": "raster_split_kernel<1,false> (binned, gather by id, per-block cull, longest tiles "
-                               "split)",
+                     "kernel": "raster_split_kernel<1,false> (binned, gather by id, per-block cull, long-tail "
+                               "tiles in the quad walk)",
                      "work": f"{n_support} alpha-supported pixel tests x {FLOPS_PER_TEST} fp32 ops / mean launch "
                              f"{t_mean * 1e6:.1f} us",
                      "frac_vs_64_lanes_per_cu": flops / t_mean / PEAK_LANE_OPS_64,

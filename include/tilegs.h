@@ -187,21 +187,25 @@ typedef struct {
                              pairs keep the depth bits */
     float shift_alpha;    /* alpha >= 0, 1.0 */
     float shift_gamma;    /* gamma in [0, 1), 0.25 */
-    int32_t split_entries; /* 0, or a power of two in 256..2^24 (4096): with
+    int32_t split_entries; /* 0, or a power of two in 256..2^24 (2048): with
                              the WAVE raster, 16-pixel tiles, packed = 0 and
                              a tile order, the tiles with at least this many
                              entries and split_mean_factor x the mean of the
                              non-empty tiles (the threshold raised by powers
                              of two to at most 1024 tiles) get 4 wavefronts
-                             per 8x8 block, each over a quarter of the range
-                             (merged in order, parts where a pixel stops
-                             walked again from their entering transmittance);
-                             images equal the unsplit ones up to rounding
-                             (<= 1e-6), last ids and counts except at that
-                             rounding */
-    int32_t split_mean_factor; /* 0..64 (4); 0: the threshold is split_entries
-                             alone. Where every tile is long, pixels stop
-                             early and a split part's walk is mostly wasted */
+                             per 8x8 block, one per 4x4 quarter, with four
+                             lanes per pixel taking four entries per step
+                             through the same per-pixel arithmetic: images,
+                             last ids and counts other than n_visit (the
+                             finer quarter cull visits fewer entries) are
+                             bitwise those of the unsplit raster */
+    int32_t split_mean_factor; /* 0..64 (2); 0: the threshold is split_entries
+                             alone. Otherwise no tile is split unless the
+                             longest tiles reach twice factor x the mean (a
+                             long tail): where every tile is long, no tile
+                             is on the critical path alone, and the quad
+                             walk's extra instructions per entry cost more
+                             than its shorter walks gain */
     int32_t footprint;    /* TGS_FOOTPRINT_*: the tiles tgs_project gives a
                              Gaussian (OPACITY_AWARE by default) */
 } tgs_params;
@@ -228,7 +232,9 @@ typedef struct {
        params.split_entries and >= params.split_mean_factor x the mean
        entries of the non-empty tiles (this bound only when the non-empty
        tiles have at least 8192 blocks, enough wavefronts to fill the GPU)
-       that leaves at most 1024 of them (0 and 0 when split_entries is 0).
+       that leaves at most 1024 of them; 0 and 0 when split_entries is 0,
+       or when the bound from the mean applies and the longest tiles' bit
+       length puts them below twice it.
    seg_base [T + 1] (required with params.per_tile_bins_dev, else unused):
        tgs_bin writes the first segment of each tile, seg_base[T] = the
        number of segments S; offsets then holds S + 1 meaningful words (size

@@ -44,8 +44,8 @@ class Params:
     near_shift: bool = False  # bin on z - min(alpha s_max, gamma z) instead of z
     shift_alpha: float = 1.0
     shift_gamma: float = 0.25
-    split_entries: int = 4096  # tiles with this many entries are split over 4 wavefronts per block (0: never)
-    split_mean_factor: int = 4  # ... and with this many times the mean of the non-empty tiles (0: no such bound)
+    split_entries: int = 2048  # tiles with this many entries take the quad walk, 16 wavefronts per tile (0: never)
+    split_mean_factor: int = 2  # ... and this many times the mean of the non-empty tiles, when the longest reach twice that (0: no such bound)
     footprint: str = "opacity"  # tile rect rule: "opacity" (alpha-support box) or "three_sigma" (baseline square)
 
     def c(self):

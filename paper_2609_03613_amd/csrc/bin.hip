@@ -845,21 +845,25 @@ __device__ __forceinline__ void tile_place_chunk(const TileOrder& to, int64_t ch
     if (chunk == 0 && threadIdx.x == 0) {
         // counts >= 2^h have a bit length > h: buckets 0 .. 31 - h. The
         // threshold is the smallest power of two >= split and >= `factor`
-        // times the mean count of the non-empty tiles (only tiles far longer
-        // than the typical walk are on the critical path; where all tiles
-        // are long, pixels tend to stop early and a split part's walk is
-        // mostly wasted) that leaves at most kSplitTiles tiles above it, so
-        // the split set is a union of whole buckets (independent of the
-        // order inside a bucket).
+        // times the mean count of the non-empty tiles that leaves at most
+        // kSplitTiles tiles above it, so the split set is a union of whole
+        // buckets (independent of the order inside a bucket). Only tiles
+        // far longer than the typical walk are on the critical path, and
+        // only when the longest reach at least twice that bound (a long
+        // tail): where every tile is long the quad walk's extra
+        // instructions per entry cost more than its shorter walks gain.
         uint32_t nh = 0, thr = 0;
         if (to.split > 0) {
             const uint64_t m = to.offsets[to.sm.first(T)];
             const uint64_t nonempty = (uint64_t)T - hist[32];
             // with fewer block wavefronts than the CUs hold (256 x 32), the
-            // split parts run on otherwise idle SIMDs: no bound from the mean
+            // quad walks run on otherwise idle SIMDs: no bound from the mean
             const bool filled = 4 * nonempty >= (uint64_t)kFillWaves;
             const uint64_t rel = nonempty && filled ? (uint64_t)to.factor * m / nonempty : 0;
-            int h0 = 31 - __builtin_clz((uint32_t)to.split);
+            int top = 0;  // bucket of the longest tiles
+            while (top < 32 && hist[top] == 0) ++top;
+            const uint64_t longest = top < 32 ? (uint64_t)1 << (31 - top) : 0;  // their lower bound
+            int h0 = rel == 0 || longest >= 2 * rel ? 31 - __builtin_clz((uint32_t)to.split) : 32;
             while (h0 < 31 && ((uint64_t)1 << h0) < rel) ++h0;
             for (int h = h0; h <= 31; ++h) {
                 uint32_t c = 0;

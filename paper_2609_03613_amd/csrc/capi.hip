@@ -253,8 +253,8 @@ void tgs_default_params(tgs_params* p) {
     p->near_shift = 0;
     p->shift_alpha = 1.0f;
     p->shift_gamma = 0.25f;
-    p->split_entries = 4096;
-    p->split_mean_factor = 4;
+    p->split_entries = 2048;
+    p->split_mean_factor = 2;
     p->footprint = TGS_FOOTPRINT_OPACITY_AWARE;
 }
 

@@ -28,17 +28,27 @@ struct Pix {
 // entry, T - w, is below 1e-4; otherwise C += w c and T = T - w. nostop (a
 // later part of a split range, whose entering transmittance is not known
 // yet): every supported entry is composited.
-template <bool COUNT>
-__device__ __forceinline__ void blend(Pix& p, float px, float py, const Staged& s, bool nostop = false) {
+// The entry's alpha at the pixel (px, py) and whether it passes the support
+// test (q <= 0 and alpha >= 1/255), in the one operation order every
+// raster uses.
+__device__ __forceinline__ float entry_alpha(float px, float py, const Staged& s, bool& sup) {
 #pragma clang fp contract(off)
     const float dx = s.a.x - px;
     const float dy = s.a.y - py;
     const float w = fmaf(s.a.z, dx, s.a.w * dy);
     const float q2 = fmaf(dx, w, (s.b.x * dy) * dy);  // = -q / (2 ln 2)
     const float araw = s.b.y * __builtin_amdgcn_exp2f(q2);
+    sup = (q2 <= 0.0f) && (araw >= kAlphaMin);
+    return fminf(kAlphaMax, araw);
+}
+
+template <bool COUNT>
+__device__ __forceinline__ void blend(Pix& p, float px, float py, const Staged& s, bool nostop = false) {
+#pragma clang fp contract(off)
+    bool in_support;
+    const float alpha = entry_alpha(px, py, s, in_support);
     const bool live = !p.done;
-    const bool sup = live && (q2 <= 0.0f) && (araw >= kAlphaMin);
-    const float alpha = fminf(kAlphaMax, araw);
+    const bool sup = live && in_support;
     const float wt0 = alpha * p.T;
     const float next = p.T - wt0;
     const bool pass = nostop || next >= kTMin;
@@ -270,6 +280,240 @@ __device__ __forceinline__ void wave_forward(const RasterArgs& A, Staged* st, in
         chunk(base, b0, b1, b2, ga, a0, a1, a2, gb);
         base += kWave;
     }
+}
+
+// ---------------------------------------------------------------------------
+// Quad walk (the heavy tiles of the split raster). A wavefront owns a 4x4
+// quarter of an 8x8 block with four lanes per pixel: lane 4 i + k serves
+// pixel i of the quarter in role k. Survivors are taken four at a time:
+// lane k evaluates the alpha of survivor 4 s + k at its pixel, then each of
+// the pixel's four lanes runs the pixel's transmittance chain over the four
+// entries in stream order, on alphas broadcast within the lane quad, with
+// blend's binary32 operations (w = alpha T, T' = T - w, stop when T' <
+// 1e-4), and lane k < 3 adds w times colour channel k. The chain therefore
+// gives, per pixel, exactly blend's values: images, last ids and counts are
+// bitwise those of the one-lane-per-pixel walk, while a heavy tile's walk is
+// spread over 16 wavefronts that each take four entries per step.
+struct QuadPix {
+    float T;       // transmittance before the next entry; 0 once the pixel has stopped (and
+                   // for pixels outside the image), otherwise at least 1e-4
+    float Tend;    // transmittance at the stop
+    float acc;     // colour channel k (roles 0..2)
+    int32_t last;  // position of this lane's last composited entry (the quad's largest is the pixel's)
+    int32_t ncon, nvis, nsup;  // this lane's entries (summed over the quad at the end)
+};
+
+// Lane 4 (lane / 4) + J's value, for every lane of the quad.
+template <int J>
+__device__ __forceinline__ int quad_bcast(int v) {
+    return __builtin_amdgcn_mov_dpp(v, J * 0x55, 0xF, 0xF, true);
+}
+template <int J>
+__device__ __forceinline__ float quad_bcast(float v) {
+    return __int_as_float(quad_bcast<J>(__float_as_int(v)));
+}
+// Sum / maximum over the lane quad, in every lane of it.
+__device__ __forceinline__ int quad_sum(int v) {
+    v += __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true);  // lanes (1, 0, 3, 2)
+    return v + __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true);  // lanes (2, 3, 0, 1)
+}
+__device__ __forceinline__ int quad_max(int v) {
+    v = max(v, __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true));
+    return max(v, __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true));
+}
+
+// Entry J of a step in which some pixel of the wavefront stops: blend's
+// chain for one entry, with the stop (aj = entry J's alpha or 0, c its
+// colour channel k; own = this lane holds entry J, real = it exists).
+template <bool COUNT, int J>
+__device__ __forceinline__ void quad_entry(QuadPix& p, int k, float aj, int32_t pos, float c, bool real) {
+#pragma clang fp contract(off)
+    const bool own = k == J;
+    const bool live = p.T > 0.0f;
+    float wt = aj * p.T;
+    float next = p.T - wt;
+    const bool stop = live && next < kTMin;
+    if (COUNT && own && real) {
+        p.nvis += live ? 1 : 0;
+        p.nsup += (live && aj > 0.0f) ? 1 : 0;
+    }
+    p.Tend = stop ? p.T : p.Tend;
+    wt = stop ? 0.0f : wt;
+    next = stop ? 0.0f : next;
+    const bool comp = own && wt > 0.0f;
+    if (COUNT) p.ncon += comp ? 1 : 0;
+    p.last = comp ? pos : p.last;
+    p.acc = fmaf(wt, c, p.acc);
+    p.T = next;
+}
+
+// Four entries (this lane's: alpha a, or 0 when unsupported or padding;
+// own = a > 0; real = the entry exists; c = colour channel k of the four).
+// The transmittance only decreases along the chain, so when the fourth
+// value is at least 1e-4 for every live pixel no pixel stops inside the
+// step: then every supported entry is composited, which is blend's result
+// for all four, and the lane's own entry decides its last position.
+// Otherwise the step is redone entry by entry from its saved state.
+template <bool COUNT>
+__device__ __forceinline__ void quad_step(QuadPix& p, int k, float a, bool own, bool real, int32_t pos,
+                                          const float4& c) {
+#pragma clang fp contract(off)
+    const QuadPix p0 = p;
+    const float a0 = quad_bcast<0>(a), a1 = quad_bcast<1>(a), a2 = quad_bcast<2>(a), a3 = quad_bcast<3>(a);
+    const bool live = p.T > 0.0f;
+    const float w0 = a0 * p.T;
+    const float t1 = p.T - w0;
+    const float w1 = a1 * t1;
+    const float t2 = t1 - w1;
+    const float w2 = a2 * t2;
+    const float t3 = t2 - w2;
+    const float w3 = a3 * t3;
+    const float t4 = t3 - w3;
+    p.acc = fmaf(w0, c.x, p.acc);
+    p.acc = fmaf(w1, c.y, p.acc);
+    p.acc = fmaf(w2, c.z, p.acc);
+    p.acc = fmaf(w3, c.w, p.acc);
+    p.T = t4;
+    const bool comp = own && live;
+    p.last = comp ? pos : p.last;
+    if (COUNT) {
+        p.nvis += (real && live) ? 1 : 0;
+        p.nsup += comp ? 1 : 0;
+        p.ncon += comp ? 1 : 0;
+    }
+    if ((ballot(t4 < kTMin) & ballot(live)) != 0) {
+        p = p0;
+        quad_entry<COUNT, 0>(p, k, a0, pos, c.x, real);
+        quad_entry<COUNT, 1>(p, k, a1, pos, c.y, real);
+        quad_entry<COUNT, 2>(p, k, a2, pos, c.z, real);
+        quad_entry<COUNT, 3>(p, k, a3, pos, c.w, real);
+    }
+}
+
+// The cnt staged survivors st[] (colour channel ch of survivor i at
+// col[ch kWave + i]; slots cnt .. cnt rounded up to 4 hold 0).
+template <bool COUNT>
+__device__ __forceinline__ void composite_quad(QuadPix& p, int k, float px, float py, const Staged* st,
+                                               const float* col, int cnt) {
+    const Staged* sk = st + k;
+    const float* ck = col + (k < 3 ? k : 2) * kWave;
+    for (int s4 = 0; s4 < cnt; s4 += 4) {
+        // slots past cnt (at most the last three of the step) hold stale
+        // entries: their alpha is replaced by 0 and their colours are 0
+        const Staged s = sk[s4];
+        const float4 c4 = *reinterpret_cast<const float4*>(ck + s4);
+        const bool real = s4 + k < cnt;
+        bool sup;
+        const float alpha = entry_alpha(px, py, s, sup);
+        const bool own = sup && real;
+        const float a = own ? alpha : 0.0f;
+        quad_step<COUNT>(p, k, a, own, real, __float_as_int(s.c.y), c4);
+    }
+}
+
+// The quad walk of one 4x4 quarter (box [xa, xb] x [ya, yb]) over the tile
+// range [begin, end): wave_forward's pipelined gathers and cull, survivors
+// staged with their colours split by channel, composited by composite_quad.
+template <int SRC, bool COUNT>
+__device__ __forceinline__ void quad_forward(const RasterArgs& A, Staged* st, float* col, uint32_t begin,
+                                             uint32_t end, float ox, float oy, float px, float py, float xa,
+                                             float xb, float ya, float yb, QuadPix& p) {
+    if (begin >= end) return;
+    const int l = lane(), k = l & 3;
+    const float4* sp = reinterpret_cast<const float4*>(A.splats);
+    auto id_clamped = [&](uint32_t e) { return id_at<SRC>(A, e < end ? e : end - 1); };
+    auto gather = [&](uint32_t g, float4& r0, float4& r1, float4& r2) {
+        const float4* q = sp + kSplatVec * (int64_t)g;
+        r0 = q[0];
+        r1 = q[1];
+        r2 = q[2];
+    };
+    auto chunk = [&](uint32_t base, const float4& c0, const float4& c1, const float4& c2, uint32_t g_next,
+                     float4& n0, float4& n1, float4& n2, uint32_t& g_after) {
+        const uint32_t e = base + l;
+        bool keep = e < end;
+        gather(g_next, n0, n1, n2);
+        g_after = id_clamped(e + 2 * kWave);
+        Staged s;
+        if (keep) {
+            float s2;
+            stage_splat(c0, c1, c2, ox, oy, s.a, s.b, s2);
+            s.c = make_float2(s2, __int_as_float((int32_t)e));
+            keep = block_may_touch(s.a.x, s.a.y, c1.x, c1.y, c1.z, c1.w, xa, xb, ya, yb);
+        }
+        const uint64_t m = ballot(keep);
+        if (m != 0) {
+            const int cnt = __builtin_popcountll(m);
+            if (keep) {
+                const uint32_t r = rank_in(m);
+                st[r] = s;
+                col[r] = s.b.z;
+                col[kWave + r] = s.b.w;
+                col[2 * kWave + r] = s.c.x;
+            }
+            if (l >= cnt && l < ((cnt + 3) & ~3)) {
+                col[l] = 0.0f;
+                col[kWave + l] = 0.0f;
+                col[2 * kWave + l] = 0.0f;
+            }
+            wave_sync();
+            composite_quad<COUNT>(p, k, px, py, st, col, cnt);
+            wave_sync();
+        }
+    };
+    float4 a0, a1, a2, b0, b1, b2;
+    uint32_t ga = id_clamped(begin + l), gb;
+    gather(ga, a0, a1, a2);
+    gb = id_clamped(begin + kWave + l);
+    for (uint32_t base = begin;;) {
+        if (base >= end || ballot(p.T > 0.0f) == 0) break;
+        chunk(base, a0, a1, a2, gb, b0, b1, b2, ga);
+        base += kWave;
+        if (base >= end || ballot(p.T > 0.0f) == 0) break;
+        chunk(base, b0, b1, b2, ga, a0, a1, a2, gb);
+        base += kWave;
+    }
+}
+
+// write_pixel for the quad walk (called by all four lanes of the quad):
+// role k < 3 writes colour channel k, role 3 the alpha, last id and the
+// optional planes (the same expressions).
+template <bool COUNT>
+__device__ __forceinline__ void write_quad(const RasterArgs& A, int x, int y, int k, bool inside, QuadPix p,
+                                           bool bad) {
+    p.last = quad_max(p.last);
+    if (COUNT) {
+        p.ncon = quad_sum(p.ncon);
+        p.nvis = quad_sum(p.nvis);
+        p.nsup = quad_sum(p.nsup);
+    }
+    if (!inside) return;
+    const int64_t i = (int64_t)y * A.width + x;
+    const float T = p.T > 0.0f ? p.T : p.Tend;
+    if (bad) {
+        const float nan = __builtin_nanf("");
+        if (k < 3) {
+            A.rgb[3 * i + k] = nan;
+            return;
+        }
+        A.alpha[i] = nan;
+        A.last[i] = -1;
+        if (A.trans) A.trans[i] = nan;
+        if (A.n_contrib) A.n_contrib[i] = 0;
+        if (A.n_visit) A.n_visit[i] = 0;
+        if (A.n_support) A.n_support[i] = 0;
+        return;
+    }
+    if (k == 0) A.rgb[3 * i] = p.acc + T * A.bg[0];
+    if (k == 1) A.rgb[3 * i + 1] = p.acc + T * A.bg[1];
+    if (k == 2) A.rgb[3 * i + 2] = p.acc + T * A.bg[2];
+    if (k < 3) return;
+    A.alpha[i] = 1.0f - T;
+    A.last[i] = p.last;
+    if (A.trans) A.trans[i] = T;
+    if (A.n_contrib) A.n_contrib[i] = p.ncon;
+    if (A.n_visit) A.n_visit[i] = p.nvis;
+    if (A.n_support) A.n_support[i] = p.nsup;
 }
 
 }  // namespace raster

@@ -32,7 +32,7 @@ def test_default_params():
     assert (p.tile_size, p.num_bins, p.sample_count) == (16, 64, 8192)
     assert (p.p_lo, p.p_hi) == (1.0, 99.0) and abs(p.pad - 0.05) < 1e-7
     assert p.raster == L.RASTER_WAVE and p.packed == 0
-    assert p.footprint == L.FOOTPRINT_OPACITY_AWARE and (p.split_entries, p.split_mean_factor) == (4096, 4)
+    assert p.footprint == L.FOOTPRINT_OPACITY_AWARE and (p.split_entries, p.split_mean_factor) == (2048, 2)
     # the binding's defaults are the library's
     q = tg.Params().c()
     for name, _ in L.Params._fields_:
@@ -195,7 +195,7 @@ def test_repair_mode_argument_errors():
     lib.tgs_default_params(ctypes.byref(p))
     assert (p.repair, p.near_shift) == (L.REPAIR_ALL, 0)
     assert abs(p.repair_budget - 0.25) < 1e-7 and p.shift_alpha == 1.0 and p.shift_gamma == 0.25
-    assert p.split_entries == 4096 and p.split_mean_factor == 4
+    assert p.split_entries == 2048 and p.split_mean_factor == 2
     cases = [(tg.Params(repair="rules", packed=1), L.TGS_ERR_UNSUPPORTED, "packed"),
              (tg.Params(repair="none", packed=2), L.TGS_ERR_UNSUPPORTED, "packed"),
              (tg.Params(repair="rules", repair_budget=1.5), L.TGS_ERR_INVALID_ARG, "repair_budget"),
