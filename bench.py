@@ -998,7 +998,7 @@ def main():
                      "global_host_sync": frame_ms["global_host_sync"]},
         "fps": {"binned": 1000.0 / fb, "global": 1000.0 / frame_ms["global"]},
         "binning_attributable": {
-            "note": "the same product raster (wave walk, heaviest tiles first, longest tiles split) on the binned "
+            "note": "the same product raster (wave walk, heaviest tiles first, long-tail tiles in the quad walk) on the binned "
                     "and on the globally sorted stream: what the ordering stage itself earns",
             "ordering_stage_x": stage["global_product_raster"][1] / stage["binned"][1],
             "frame_same_raster_x": frame_ms["global_product_raster"] / fb,
