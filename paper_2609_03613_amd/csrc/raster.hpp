@@ -25,9 +25,7 @@ struct Pix {
 // operation order, no implicit contraction, so every kernel produces
 // identical bits): skip when q < 0 (rounding only) or alpha < 1/255; with
 // w = alpha T, stop, without compositing, when the transmittance after the
-// entry, T - w, is below 1e-4; otherwise C += w c and T = T - w. nostop (a
-// later part of a split range, whose entering transmittance is not known
-// yet): every supported entry is composited.
+// entry, T - w, is below 1e-4; otherwise C += w c and T = T - w.
 // The entry's alpha at the pixel (px, py) and whether it passes the support
 // test (q <= 0 and alpha >= 1/255), in the one operation order every
 // raster uses.
@@ -43,7 +41,7 @@ __device__ __forceinline__ float entry_alpha(float px, float py, const Staged& s
 }
 
 template <bool COUNT>
-__device__ __forceinline__ void blend(Pix& p, float px, float py, const Staged& s, bool nostop = false) {
+__device__ __forceinline__ void blend(Pix& p, float px, float py, const Staged& s) {
 #pragma clang fp contract(off)
     bool in_support;
     const float alpha = entry_alpha(px, py, s, in_support);
@@ -51,7 +49,7 @@ __device__ __forceinline__ void blend(Pix& p, float px, float py, const Staged& 
     const bool sup = live && in_support;
     const float wt0 = alpha * p.T;
     const float next = p.T - wt0;
-    const bool pass = nostop || next >= kTMin;
+    const bool pass = next >= kTMin;
     const bool comp = sup && pass;
     if (COUNT) {
         p.nvis += live ? 1 : 0;
@@ -173,22 +171,64 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// One entry of a group in which no pixel stops: blend's arithmetic without
+// the stop test (comp = supported and the pixel live; a = its alpha, 0
+// otherwise).
+__device__ __forceinline__ void blend_pass(Pix& p, float alpha, bool comp, const Staged& s) {
+#pragma clang fp contract(off)
+    const float a = comp ? alpha : 0.0f;
+    const float wt = a * p.T;
+    p.T = p.T - wt;
+    p.r = fmaf(wt, s.b.z, p.r);
+    p.g = fmaf(wt, s.b.w, p.g);
+    p.b = fmaf(wt, s.c.x, p.b);
+    p.last = comp ? __float_as_int(s.c.y) : p.last;
+}
+
+// Four entries. The transmittance only decreases, and a stopped pixel keeps
+// one of at least 1e-4, so when every lane's transmittance after the four
+// is at least 1e-4 no pixel stopped inside them: each supported entry was
+// composited, with exactly blend's operations, and the per-entry stop tests
+// and selects are skipped. Otherwise the four are redone by blend.
+template <bool COUNT>
+__device__ __forceinline__ void blend4(Pix& p, float px, float py, const Staged& s0, const Staged& s1,
+                                       const Staged& s2, const Staged& s3) {
+    const Pix p0 = p;
+    const bool live = !p.done;
+    bool u0, u1, u2, u3;
+    const float a0 = entry_alpha(px, py, s0, u0), a1 = entry_alpha(px, py, s1, u1);
+    const float a2 = entry_alpha(px, py, s2, u2), a3 = entry_alpha(px, py, s3, u3);
+    blend_pass(p, a0, live && u0, s0);
+    blend_pass(p, a1, live && u1, s1);
+    blend_pass(p, a2, live && u2, s2);
+    blend_pass(p, a3, live && u3, s3);
+    if (COUNT) {
+        p.nvis += live ? 4 : 0;
+        const int su = (u0 ? 1 : 0) + (u1 ? 1 : 0) + (u2 ? 1 : 0) + (u3 ? 1 : 0);
+        p.nsup += live ? su : 0;
+        p.ncon += live ? su : 0;
+    }
+    if (ballot(p.T < kTMin) != 0) {
+        p = p0;
+        blend<COUNT>(p, px, py, s0);
+        blend<COUNT>(p, px, py, s1);
+        blend<COUNT>(p, px, py, s2);
+        blend<COUNT>(p, px, py, s3);
+    }
+}
+
 // Composites the cnt staged survivors of st[], four at a time (all four read
 // from LDS before the first is evaluated: more independent work per
 // wavefront hides the LDS latency better than more wavefronts would; eight
 // at a time costs too many registers).
 template <bool COUNT>
-__device__ __forceinline__ void composite_staged(Pix& p, float px, float py, const Staged* st, int cnt,
-                                                 bool nostop = false) {
+__device__ __forceinline__ void composite_staged(Pix& p, float px, float py, const Staged* st, int cnt) {
     int j = 0;
     for (; j + 4 <= cnt; j += 4) {
         const Staged s0 = st[j], s1 = st[j + 1], s2 = st[j + 2], s3 = st[j + 3];
-        blend<COUNT>(p, px, py, s0, nostop);
-        blend<COUNT>(p, px, py, s1, nostop);
-        blend<COUNT>(p, px, py, s2, nostop);
-        blend<COUNT>(p, px, py, s3, nostop);
+        blend4<COUNT>(p, px, py, s0, s1, s2, s3);
     }
-    for (; j < cnt; ++j) blend<COUNT>(p, px, py, st[j], nostop);
+    for (; j < cnt; ++j) blend<COUNT>(p, px, py, st[j]);
 }
 
 
@@ -199,16 +239,10 @@ __device__ __forceinline__ void composite_staged(Pix& p, float px, float py, con
 // slots st[] and composited by every lane. Without masks the gathers are
 // software-pipelined: while chunk i is culled and composited, the splats of
 // chunk i + 1 and the ids of chunk i + 2 are in flight.
-struct NoHook {
-    __device__ __forceinline__ void operator()(Pix&) const {}
-};
-
-// hook(p) runs after every chunk (a split part publishes its progress and
-// drops pixels that stopped in an earlier part).
-template <int SRC, bool COUNT, class Hook = NoHook>
+template <int SRC, bool COUNT>
 __device__ __forceinline__ void wave_forward(const RasterArgs& A, Staged* st, int bi, uint32_t begin, uint32_t end,
                                              float ox, float oy, float px, float py, float xa, float xb, float ya,
-                                             float yb, Pix& p, bool nostop = false, Hook hook = Hook()) {
+                                             float yb, Pix& p) {
     const int l = lane();
     if (A.masks) {
         const uint32_t bit = 1u << bi;  // block masks exist for 16-pixel tiles only (bi < 4)
@@ -224,10 +258,9 @@ __device__ __forceinline__ void wave_forward(const RasterArgs& A, Staged* st, in
             if (m != 0) {
                 if (keep) st[rank_in(m)] = s;
                 wave_sync();
-                composite_staged<COUNT>(p, px, py, st, __builtin_popcountll(m), nostop);
+                composite_staged<COUNT>(p, px, py, st, __builtin_popcountll(m));
                 wave_sync();
             }
-            hook(p);
         }
         return;
     }
@@ -263,10 +296,9 @@ __device__ __forceinline__ void wave_forward(const RasterArgs& A, Staged* st, in
         if (m != 0) {
             if (keep) st[rank_in(m)] = s;
             wave_sync();
-            composite_staged<COUNT>(p, px, py, st, __builtin_popcountll(m), nostop);
+            composite_staged<COUNT>(p, px, py, st, __builtin_popcountll(m));
             wave_sync();
         }
-        hook(p);
     };
     float4 a0, a1, a2, b0, b1, b2;
     uint32_t ga = id_clamped(begin + l), gb;
