@@ -147,7 +147,8 @@ def test_tail_segments_bit_exact():
 # one group of 8 x 64 segments. A group of at most 4096 entries is staged in
 # LDS, where sub-segments of 2..128 entries are put in order; longer ones
 # (depth clusters: one shared depth on one tile) are staged and then queued
-# for the repair sorts; a larger group takes the unstaged path.
+# for the repair sorts; a larger group takes the unstaged path (up to 70,000
+# entries here, several sweeps of the group sort's 8192-entry batches).
 STAGE_CASES = [
     # (n, widest rect in tiles, tie fraction, cluster sizes)
     (1200, 3, 0.2, ()),
@@ -155,6 +156,10 @@ STAGE_CASES = [
     (3000, 1, 0.1, (2100, 300, 129, 128)),
     (4096, 1, 0.0, (64,)),
     (12000, 8, 0.3, (3000, 1000, 200)),
+    (16384, 1, 0.0, ()),
+    (16385, 1, 0.1, (5000,)),
+    (40000, 2, 0.2, (20000, 3000, 129)),
+    (70000, 1, 0.1, ()),
 ]
 
 
