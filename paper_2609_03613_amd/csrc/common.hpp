@@ -103,36 +103,32 @@ __device__ __forceinline__ void stage_splat(const float4& a, const float4& b, co
 // Conservative block test: can q = a dx^2 + 2 b dx dy + c dy^2 (unscaled
 // conic, mean mx, my) reach 2 ln(255 o) at some pixel centre of the box
 // [xa, xb] x [ya, yb]? The minimum of the convex q over the box is 0 when
-// the mean is inside, otherwise the smallest of the four edge minima. The
-// margin exceeds the binary32 error of both this bound and the per-pixel
-// evaluation, so a block that fails the test fails the alpha >= 1/255 test
-// at every one of its pixels. The edge minimisers use the hardware
-// reciprocal: an edge point that misses the exact minimiser by a relative
-// 1e-7 raises q only by c (1e-7 e)^2, far inside the margin.
+// the mean is inside. Otherwise it lies on an edge facing the mean: from a
+// point of any other edge, q decreases toward the mean (where q = 0) and
+// that direction enters the box. So the bound is the smaller of two edge
+// minima: the vertical edge on the mean's side and the horizontal edge on
+// the mean's side (either one of a pair when the mean lies between them,
+// whose minimum is then at least the true one). The margin exceeds the
+// binary32 error of both this bound and the per-pixel evaluation, so a
+// block that fails the test fails the alpha >= 1/255 test at every one of
+// its pixels. The edge minimisers use the hardware reciprocal: an edge
+// point that misses the exact minimiser by a relative 1e-7 raises q only by
+// c (1e-7 e)^2, far inside the margin.
 __device__ __forceinline__ bool block_may_touch(float mx, float my, float a, float b, float c, float o, float xa,
                                                 float xb, float ya, float yb) {
     const float dxl = mx - xb, dxh = mx - xa, dyl = my - yb, dyh = my - ya;
-    float qmin = 0.0f;
-    if (!(dxl <= 0.0f && dxh >= 0.0f && dyl <= 0.0f && dyh >= 0.0f)) {
-        const float ic = __builtin_amdgcn_rcpf(c), ia = __builtin_amdgcn_rcpf(a);
-        qmin = INFINITY;
-        {
-            const float d = dxl, e = fminf(fmaxf(-b * d * ic, dyl), dyh);
-            qmin = fminf(qmin, a * d * d + 2.0f * b * d * e + c * e * e);
-        }
-        {
-            const float d = dxh, e = fminf(fmaxf(-b * d * ic, dyl), dyh);
-            qmin = fminf(qmin, a * d * d + 2.0f * b * d * e + c * e * e);
-        }
-        {
-            const float e = dyl, d = fminf(fmaxf(-b * e * ia, dxl), dxh);
-            qmin = fminf(qmin, a * d * d + 2.0f * b * d * e + c * e * e);
-        }
-        {
-            const float e = dyh, d = fminf(fmaxf(-b * e * ia, dxl), dxh);
-            qmin = fminf(qmin, a * d * d + 2.0f * b * d * e + c * e * e);
-        }
+    const float ic = __builtin_amdgcn_rcpf(c), ia = __builtin_amdgcn_rcpf(a);
+    float qx, qy;
+    {
+        const float d = dxh < 0.0f ? dxh : dxl, e = fminf(fmaxf(-b * d * ic, dyl), dyh);
+        qx = a * d * d + 2.0f * b * d * e + c * e * e;
     }
+    {
+        const float e = dyh < 0.0f ? dyh : dyl, d = fminf(fmaxf(-b * e * ia, dxl), dxh);
+        qy = a * d * d + 2.0f * b * d * e + c * e * e;
+    }
+    const bool inside = dxl <= 0.0f && dxh >= 0.0f && dyl <= 0.0f && dyh >= 0.0f;
+    const float qmin = inside ? 0.0f : fminf(qx, qy);
     const float mxd = fmaxf(fabsf(dxl), fabsf(dxh)), myd = fmaxf(fabsf(dyl), fabsf(dyh));
     const float mag = a * mxd * mxd + c * myd * myd + 2.0f * fabsf(b) * mxd * myd;
     // 2 ln(255 o) from the hardware base-2 logarithm (relative error near
