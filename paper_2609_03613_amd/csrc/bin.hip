@@ -588,77 +588,74 @@ __device__ __forceinline__ void locate(const uint32_t* __restrict__ bin_off, uin
 // one list, longest first (bucket 4: one 65..512 segment per wavefront job,
 // 2, 4 or 8 keys per lane; buckets 3..0: 1, 2, 4, 8 segments of 64 / G
 // lanes each), which every wavefront strides through, so that no wavefront
-// gets a job of every bucket.
+// gets a job of every bucket. Each bucket's stretch of the list is its own
+// loop with the group size fixed at compile time.
+struct SmallSort {
+    const uint32_t* bin_off;
+    const uint32_t* lists;
+    int64_t nseg;
+    uint64_t* pairs;
+    uint32_t waves, wid;
+};
+
+// The first job >= a of wavefront wid (jobs wid, wid + waves, ...).
+__device__ __forceinline__ uint32_t first_job(const SmallSort& S, uint32_t a) {
+    return a + (S.wid + S.waves - a % S.waves) % S.waves;
+}
+
+// Jobs [j_begin, j_end) of bucket b (list entries from (j - j_begin) (64 /
+// G)): 64 / G segments of at most G keys per job, G lanes each.
+template <int G, bool DESC>
+__device__ __forceinline__ void sort_groups(const SmallSort& S, int b, uint32_t j_begin, uint32_t j_end, uint32_t cnt,
+                                            const RecordSink& rs) {
+    const int l = lane(), li = l & (G - 1);
+    const uint32_t sub = (uint32_t)(l / G);
+    for (uint32_t j = first_job(S, j_begin); j < j_end; j += S.waves) {
+        const uint32_t i = (j - j_begin) * (uint32_t)(kWave / G) + sub;
+        uint32_t sg = 0, begin = 0, len = 0;
+        if (i < cnt) {
+            const int64_t at = (int64_t)b * S.nseg + i;
+            locate<DESC>(S.bin_off, DESC ? reinterpret_cast<const uint2*>(S.lists)[at] : make_uint2(S.lists[at], 0u),
+                         sg, begin, len);
+        }
+        uint64_t* seg = S.pairs + begin;
+        uint64_t v = (uint32_t)li < len ? seg[li] : ~0ull;
+        v = group_bitonic<G>(v, li);
+        if ((uint32_t)li < len) {
+            seg[li] = v;
+            if (!DESC) rs.put(sg, begin + li, v);
+        }
+    }
+}
+
 template <bool DESC>
 __global__ void __launch_bounds__(256) sort_small_kernel(const uint32_t* __restrict__ bin_off,
                                                          const uint32_t* __restrict__ lists, int64_t nseg,
                                                          const uint32_t* __restrict__ bucket_count,
                                                          uint64_t* __restrict__ pairs, RecordSink rs) {
-    const uint32_t waves = gridDim.x * (blockDim.x / kWave);
-    const uint32_t wid = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    const SmallSort S{bin_off, lists, nseg, pairs, gridDim.x * (blockDim.x / kWave),
+                      blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave};
     const uint32_t c0 = bucket_count[0], c1 = bucket_count[1], c2 = bucket_count[2], c3 = bucket_count[3],
                    c4 = bucket_count[4];
     // job counts and their running sums, bucket 4 first
     const uint32_t j4 = c4, j3 = j4 + c3, j2 = j3 + (c2 + 1) / 2, j1 = j2 + (c1 + 3) / 4, j0 = j1 + (c0 + 7) / 8;
-    if (wid >= j0) return;
-    const int l = lane();
-    // bucket and list index of this lane's segment in job j
-    auto ref = [&](uint32_t j, int& b, uint32_t& i, bool& ok) {
-        uint32_t cnt;
-        if (j < j4) {
-            b = 4; i = j; cnt = c4;
-        } else if (j < j3) {
-            b = 3; i = j - j4; cnt = c3;
-        } else if (j < j2) {
-            b = 2; i = (j - j3) * 2 + (uint32_t)(l >> 5); cnt = c2;
-        } else if (j < j1) {
-            b = 1; i = (j - j2) * 4 + (uint32_t)(l >> 4); cnt = c1;
-        } else {
-            b = 0; i = (j - j1) * 8 + (uint32_t)(l >> 3); cnt = c0;
-        }
-        ok = i < cnt;
-    };
-    auto fetch = [&](uint32_t j) {
-        int b;
-        uint32_t i;
-        bool ok;
-        ref(j, b, i, ok);
-        if (!ok) return make_uint2(0u, 0u);
-        const int64_t at = (int64_t)b * nseg + i;
-        return DESC ? reinterpret_cast<const uint2*>(lists)[at] : make_uint2(lists[at], 0u);
-    };
-    for (uint32_t j = wid; j < j0; j += waves) {
-        int b;
-        uint32_t i;
-        bool ok;
-        ref(j, b, i, ok);
+    if (S.wid >= j0) return;
+    for (uint32_t j = first_job(S, 0); j < j4; j += S.waves) {
         uint32_t sg = 0, begin = 0, len = 0;
-        if (ok) locate<DESC>(bin_off, fetch(j), sg, begin, len);
-        if (b == 4) {
-            if (len <= 2 * kWave)
-                sort_wave_reg<2, !DESC>(pairs + begin, sg, begin, len, rs);
-            else if (len <= 4 * kWave)
-                sort_wave_reg<4, !DESC>(pairs + begin, sg, begin, len, rs);
-            else
-                sort_wave_reg<8, !DESC>(pairs + begin, sg, begin, len, rs);
-        } else {
-            const int G = b == 3 ? 64 : b == 2 ? 32 : b == 1 ? 16 : 8;
-            const int li = l & (G - 1);
-            uint64_t v = (uint32_t)li < len ? pairs[begin + li] : ~0ull;
-            if (b == 3)
-                v = group_bitonic<64>(v, li);
-            else if (b == 2)
-                v = group_bitonic<32>(v, li);
-            else if (b == 1)
-                v = group_bitonic<16>(v, li);
-            else
-                v = group_bitonic<8>(v, li);
-            if ((uint32_t)li < len) {
-                pairs[begin + li] = v;
-                if (!DESC) rs.put(sg, begin + li, v);
-            }
-        }
+        const int64_t at = (int64_t)4 * nseg + j;
+        locate<DESC>(bin_off, DESC ? reinterpret_cast<const uint2*>(lists)[at] : make_uint2(lists[at], 0u), sg,
+                     begin, len);
+        if (len <= 2 * kWave)
+            sort_wave_reg<2, !DESC>(pairs + begin, sg, begin, len, rs);
+        else if (len <= 4 * kWave)
+            sort_wave_reg<4, !DESC>(pairs + begin, sg, begin, len, rs);
+        else
+            sort_wave_reg<8, !DESC>(pairs + begin, sg, begin, len, rs);
     }
+    sort_groups<64, DESC>(S, 3, j4, j3, c3, rs);
+    sort_groups<32, DESC>(S, 2, j3, j2, c2, rs);
+    sort_groups<16, DESC>(S, 1, j2, j1, c1, rs);
+    sort_groups<8, DESC>(S, 0, j1, j0, c0, rs);
 }
 
 // Buckets 5..7: one workgroup per segment. 513..8192 keys: bitonic network

@@ -15,16 +15,16 @@ __device__ __forceinline__ uint32_t xor_lane_u32(uint32_t v, int m) {
     const int x = (int)v;
     switch (m) {
         case 1:
-            return (uint32_t)__builtin_amdgcn_update_dpp(x, x, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+            return (uint32_t)__builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, true);  // quad_perm [1,0,3,2]
         case 2:
-            return (uint32_t)__builtin_amdgcn_update_dpp(x, x, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+            return (uint32_t)__builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, true);  // quad_perm [2,3,0,1]
         case 4: {
-            const int r4 = __builtin_amdgcn_update_dpp(x, x, 0x124, 0xF, 0xF, false);   // row_ror:4
-            const int r12 = __builtin_amdgcn_update_dpp(x, x, 0x12C, 0xF, 0xF, false);  // row_ror:12
+            const int r4 = __builtin_amdgcn_mov_dpp(x, 0x124, 0xF, 0xF, true);   // row_ror:4
+            const int r12 = __builtin_amdgcn_mov_dpp(x, 0x12C, 0xF, 0xF, true);  // row_ror:12
             return (uint32_t)((lane() & 4) ? r4 : r12);
         }
         case 8:
-            return (uint32_t)__builtin_amdgcn_update_dpp(x, x, 0x128, 0xF, 0xF, false);  // row_ror:8
+            return (uint32_t)__builtin_amdgcn_mov_dpp(x, 0x128, 0xF, 0xF, true);  // row_ror:8
         default:
             return shfl_xor_u32(v, m);
     }
