@@ -211,3 +211,34 @@ def test_split_relative_bound():
         else:
             assert 4 * nonempty < 8192 and thr == 256 and ns > 0
         assert torch.equal(out["rgb"], u["rgb"]) and torch.equal(out["last"], u["last"])
+
+
+@pytest.mark.parametrize("W,H", [(203, 77), (134, 42), (18, 9)])
+def test_split_ragged_image(W, H):
+    # image sizes that cut tiles, 8x8 blocks and 4x4 quarters (quarters
+    # partly or wholly outside the image, whose lanes composite nothing and
+    # write nothing): the quad walk on every non-empty tile equals the
+    # unsplit raster bit for bit (the visit count bounded by it: the quarter
+    # cull visits fewer entries), and the oracle within 1e-4
+    g, _ = dense(11, 2500, 1.5)
+    cam = scenes.camera(np.eye(3), np.zeros(3), 0.5 * W, 0.5 * W, W / 2.0, H / 2.0, W, H)
+    proj = oracle.project(g, cam)
+    ref = oracle.render(proj, W, H)
+    gd = tg.to_device(g, dev())
+    rs = tg.Renderer(cam, tg.Params(split_entries=256, split_mean_factor=0), device=dev())
+    r0 = tg.Renderer(cam, tg.Params(split_entries=0), device=dev())
+    s, i = tg.project(gd, cam)
+    bs = rs.bin(s, i, "binned")
+    out = rs.rasterize(s, i, bs, counts=True, trans=True)
+    out0 = r0.rasterize(s, i, r0.bin(s, i, "binned"), counts=True, trans=True)
+    torch.cuda.synchronize()
+    ns, thr = bs.split()
+    offs = to_np(bs.offsets).view(np.uint32).astype(np.int64)
+    counts = offs[64::64][:rs.tiles] - offs[0:rs.tiles * 64:64]
+    assert ns == int((counts >= 256).sum()) > 0 and thr == 256
+    for key in ("rgb", "alpha", "trans", "last", "n_contrib", "n_support"):
+        assert torch.equal(out[key], out0[key]), key
+    nv, nv0 = to_np(out["n_visit"]), to_np(out0["n_visit"])
+    assert np.all(nv <= nv0) and np.all(nv >= to_np(out["n_support"]))
+    e_rgb, e_a, nflag = image_compare(to_np(out["rgb"]), to_np(out["alpha"]), ref)
+    assert e_rgb <= TOL and e_a <= TOL, (e_rgb, e_a, nflag)
