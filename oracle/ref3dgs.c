@@ -371,6 +371,28 @@ static void composite_pixel(const ord_t* list, int64_t len, int64_t pos_base, do
 }
 
 /*
+ * Input check of the tiled entry points: every non-empty rect of a Gaussian
+ * that counts (gflags NULL, or ORC_VISIBLE set) lies inside the tiles_x x
+ * tiles_y grid, and every listed pixel inside the image. A rect in another
+ * tile size's units would otherwise index past the tile lists.
+ */
+static int rects_in_grid(int64_t n, const int32_t* rect, const uint8_t* gflags, int tiles_x, int tiles_y) {
+    for (int64_t g = 0; g < n; ++g) {
+        if (gflags && !(gflags[g] & ORC_VISIBLE)) continue;
+        const int32_t* r = rect + 4 * g;
+        if (r[2] <= r[0] || r[3] <= r[1]) continue;
+        if (r[0] < 0 || r[1] < 0 || r[2] > tiles_x || r[3] > tiles_y) return 0;
+    }
+    return 1;
+}
+
+static int pixels_in_image(int64_t npix, const int32_t* pix, int width, int height) {
+    for (int64_t p = 0; pix && p < npix; ++p)
+        if (pix[2 * p] < 0 || pix[2 * p] >= width || pix[2 * p + 1] < 0 || pix[2 * p + 1] >= height) return 0;
+    return 1;
+}
+
+/*
  * Render the pixels listed in pix ([npix][2] as x, y; NULL = every pixel,
  * row-major). With rect != NULL ("tiled"), each pixel walks the ordered list
  * of its tile (Gaussians whose half-open tile rect contains the tile), and
@@ -391,8 +413,10 @@ ORC_EXPORT int orc_render(int64_t n, const double* mean2d, const double* conic, 
     const int tiles_x = (width + tile_size - 1) / tile_size;
     const int tiles_y = (height + tile_size - 1) / tile_size;
     const int64_t T = (int64_t)tiles_x * tiles_y;
+    if (!pixels_in_image(npix, pix, width, height)) return 1;
 
     if (rect) {
+        if (!rects_in_grid(n, rect, gflags, tiles_x, tiles_y)) return 1;
         /* tile lists in CSR form */
         int64_t* off = (int64_t*)calloc((size_t)T + 1, sizeof(int64_t));
         if (!off) return 2;
@@ -494,6 +518,7 @@ ORC_EXPORT int orc_render_stream(int64_t n, const double* mean2d, const double* 
     const int tiles_y = (height + tile_size - 1) / tile_size;
     const int64_t T = (int64_t)tiles_x * tiles_y;
     const int64_t M = tile_offsets[T];
+    if (!pixels_in_image(npix, pix, width, height)) return 1;
     ord_t* lists = (ord_t*)malloc((size_t)(M > 0 ? M : 1) * sizeof(ord_t));
     if (!lists) return 2;
     for (int64_t i = 0; i < M; ++i) {
@@ -640,6 +665,7 @@ static int schedule_impl(int64_t n, const float* depth, const float* bin_depth, 
                          float zfar, uint64_t* keys, uint32_t* vals, uint32_t* tile_offsets, float* zrange,
                          uint32_t* seg_base_out, uint32_t* bin_offsets, uint64_t* stream) {
     const int64_t T = (int64_t)tiles_x * tiles_y;
+    if (tiles_x <= 0 || tiles_y <= 0 || !rects_in_grid(n, rect, NULL, tiles_x, tiles_y)) return 1;
     const int64_t M = orc_count_entries(n, rect);
     kv_t* e = (kv_t*)malloc((size_t)(M > 0 ? M : 1) * sizeof(kv_t));
     int64_t* sb = (int64_t*)malloc(((size_t)T + 1) * sizeof(int64_t));
@@ -1200,6 +1226,8 @@ ORC_EXPORT int orc_composite_adjoint(int64_t n, const double* mean2d, const doub
                                      const double* d_img, const double* d_alpha, double* out_rgb, double* out_alpha,
                                      double* d_proj) {
     if (n < 0 || width <= 0 || height <= 0 || tile_size <= 0) return 1;
+    if (!rects_in_grid(n, rect, gflags, (width + tile_size - 1) / tile_size, (height + tile_size - 1) / tile_size))
+        return 1;
     adj_g* P = (adj_g*)calloc((size_t)(n > 0 ? n : 1), sizeof(adj_g));
     if (!P) return 2;
     for (int64_t g = 0; g < n; ++g) {

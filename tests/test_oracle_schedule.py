@@ -210,3 +210,27 @@ def test_per_tile_bins_special_cases():
     var = oracle.schedule_tiles(p["depth_key"], p["rect"], 8, 8, kt)
     np.testing.assert_array_equal(var["stream"], uni["stream"])
     np.testing.assert_array_equal(var["bin_offsets"][var["seg_base"]], uni["tile_offsets"])
+
+
+def test_rects_outside_the_grid_are_rejected():
+    # a rect in another tile size's units (8-pixel tiles handed to a 16-pixel
+    # grid) reaches past the tile lists: the tiled render, the schedule and
+    # the compositing adjoint refuse it instead of indexing past their arrays;
+    # so does a pixel outside the image
+    W, H = 160, 40
+    splats, info = scenes.random_splats(300, W, H, tile_size=8, seed=3)
+    proj = oracle.splats_to_proj(splats, info)
+    assert proj["rect"][:, 2].max() > (W + 15) // 16
+    oracle.render(proj, W, H, tile_size=8)
+    with pytest.raises(AssertionError):
+        oracle.render(proj, W, H, tile_size=16)
+    depth, rect = scenes.info_depth(info), scenes.info_rects(info)
+    oracle.schedule(depth, rect, (W + 7) // 8, (H + 7) // 8, K=8)
+    with pytest.raises(AssertionError):
+        oracle.schedule(depth, rect, (W + 15) // 16, (H + 15) // 16, K=8)
+    d_img = np.zeros((H, W, 3))
+    oracle.composite_adjoint(proj, W, H, tile_size=8, d_img=d_img)
+    with pytest.raises(AssertionError):
+        oracle.composite_adjoint(proj, W, H, tile_size=16, d_img=d_img)
+    with pytest.raises(AssertionError):
+        oracle.render(proj, W, H, tile_size=8, pix=np.array([[W, 0]], np.int32))
