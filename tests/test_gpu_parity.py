@@ -477,6 +477,50 @@ def test_tile_sizes(ts):
     assert np.abs(outs["binned"]["rgb"] - to_np(base["rgb"])).max() <= 1e-5
 
 
+@pytest.mark.parametrize("W,H,ts", [(16384, 24, 8), (24, 16384, 16), (16384, 40, 32)])
+def test_maximum_image_extent(W, H, ts):
+    # the largest accepted width or height (16384 px): 2048 tile columns of
+    # 8 px, 1024 tile rows of 16 px, 512 columns of 32 px, with a ragged
+    # last tile row or column. Schedule bit-exact against the oracle on the
+    # same tile grid; the product image (binned, wave raster, tile order and
+    # split), the globally sorted stream through the same raster and, with
+    # 16-pixel tiles, the comparator (one workgroup per tile) within 1e-4 of
+    # the oracle and bitwise equal to each other
+    n = 6000
+    splats, info = scenes.random_splats(n, W, H, tile_size=ts, seed=W + H + ts, tie_fraction=0.05,
+                                        hidden_fraction=0.05, max_sigma_px=6.0)
+    cam = cam_for(W, H)
+    depth, rect = decode_info(info.view(np.int32))
+    tx, ty = (W + ts - 1) // ts, (H + ts - 1) // ts
+    ref_s = oracle.schedule(depth, rect, tx, ty, K=32, znear=cam["znear"], zfar=cam["zfar"])
+    ref = oracle.render(oracle.splats_to_proj(splats, info), W, H, tile_size=ts, bg=(0.1, 0.2, 0.3))
+    s = torch.as_tensor(splats).to(dev())
+    i = torch.as_tensor(info.view(np.int32)).to(dev())
+    outs = {}
+    legs = [("binned", "wave"), ("global", "wave")] + ([("global", "plain")] if ts == 16 else [])
+    for order, raster in legs:
+        r = tg.Renderer(cam, tg.Params(tile_size=ts, num_bins=32, raster=raster), device=dev())
+        b = r.bin(s, i, order)
+        M = ref_s["M"]
+        assert b.num_entries == M
+        if order == "binned":
+            assert np.array_equal(to_np(b.offsets).view(np.uint32), ref_s["bin_offsets"])
+            assert np.array_equal(to_np(b.pairs)[:M].view(np.uint64), ref_s["stream"])
+        else:
+            assert np.array_equal(to_np(b.offsets).view(np.uint32), ref_s["tile_offsets"])
+        out = r.rasterize(s, i, b, bg=(0.1, 0.2, 0.3), counts=True)
+        torch.cuda.synchronize()
+        o = outs[(order, raster)] = {k: to_np(v) for k, v in out.items()}
+        e_rgb, e_a, nflag = image_compare(o["rgb"], o["alpha"], ref)
+        assert e_rgb <= TOL and e_a <= TOL, (order, raster, e_rgb, e_a, nflag)
+        mask = ref["flags"] == 0
+        assert np.array_equal(o["n_contrib"][mask], ref["ncontrib"][mask])
+        assert np.array_equal(o["n_support"][mask], ref["nsupport"][mask])
+    for leg, o in outs.items():
+        for key in ("rgb", "alpha", "last", "n_contrib"):
+            assert np.array_equal(o[key], outs[legs[0]][key]), (leg, key)
+
+
 def effective_bins(kt, kmax):
     """Per-tile bin counts as the library applies them: clamped to
     1..kmax and rounded down to a power of two."""
