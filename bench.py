@@ -204,7 +204,8 @@ def train_step(args):
     if not args.no_tune:
         tp, _ = autotune.tune(gd, cam, cache_path=None, reps=3)
         tM, twall, tmed = measure(tp)
-        res["tuned"] = {"tile_size": tp.tile_size, "num_bins": tp.num_bins, "entries": tM,
+        res["tuned"] = {"tile_size": tp.tile_size, "num_bins": tp.num_bins, "sub_bins": tp.sub_bins or 8,
+                        "entries": tM,
                         "ms_per_step": 1000.0 * twall / args.steps, "steps_per_s": args.steps / twall,
                         "stage_ms_median": tmed}
     return res
@@ -258,7 +259,8 @@ def batched(args):
     for c in cams:
         p, rec = autotune.tune(gd, c, cache_path=None, reps=3)
         tuned.append(p)
-        tune_recs.append({"tile_size": p.tile_size, "num_bins": p.num_bins, "ms": rec["ms"]})
+        tune_recs.append({"tile_size": p.tile_size, "num_bins": p.num_bins, "sub_bins": p.sub_bins or 8,
+                          "ms": rec["ms"]})
     br = tg.BatchRenderer(cams, tuned, device=dev)
     br.capture(gd)
     torch.cuda.synchronize()

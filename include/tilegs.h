@@ -208,6 +208,15 @@ typedef struct {
                              than its shorter walks gain */
     int32_t footprint;    /* TGS_FOOTPRINT_*: the tiles tgs_project gives a
                              Gaussian (OPACITY_AWARE by default) */
+    int32_t sub_bins;     /* BINNED with exact repair (repair = ALL, packed =
+                             0, near_shift = 0): the binning first orders each
+                             (tile, bin) segment by this many sub-bins of the
+                             same log-depth map, and the repair sorts the
+                             sub-segments. 1, 2, 4 or 8; 0 = the default 8.
+                             The stream is the same for every value: only the
+                             split of the work between the binning and the
+                             repair changes (fewer sub-bins: fewer, longer
+                             sub-segments) */
 } tgs_params;
 
 /* Entry buffers written by tgs_bin and read by tgs_rasterize. All device

@@ -52,7 +52,7 @@ class Params(ctypes.Structure):
                 ("raster", ctypes.c_int32), ("packed", ctypes.c_int32), ("per_tile_bins", _c_p),
                 ("repair", ctypes.c_int32), ("repair_budget", ctypes.c_float), ("near_shift", ctypes.c_int32),
                 ("shift_alpha", ctypes.c_float), ("shift_gamma", ctypes.c_float), ("split_entries", ctypes.c_int32),
-                ("split_mean_factor", ctypes.c_int32), ("footprint", ctypes.c_int32)]
+                ("split_mean_factor", ctypes.c_int32), ("footprint", ctypes.c_int32), ("sub_bins", ctypes.c_int32)]
 
 
 class Binned(ctypes.Structure):

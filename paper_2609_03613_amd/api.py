@@ -47,13 +47,14 @@ class Params:
     split_entries: int = 2048  # tiles with this many entries take the quad walk, 16 wavefronts per tile (0: never)
     split_mean_factor: int = 2  # ... and this many times the mean of the non-empty tiles, when the longest reach twice that (0: no such bound)
     footprint: str = "opacity"  # tile rect rule: "opacity" (alpha-support box) or "three_sigma" (baseline square)
+    sub_bins: int = 0  # exact repair: log-depth sub-bins per bin ordered by the binning (1, 2, 4, 8; 0: 8)
 
     def c(self):
         return L.Params(self.tile_size, self.num_bins, self.sample_count, self.p_lo, self.p_hi, self.pad,
                         RASTERS[self.raster], int(self.packed), _ptr(self.per_tile_bins).value,
                         REPAIRS[self.repair], float(self.repair_budget), int(bool(self.near_shift)),
                         float(self.shift_alpha), float(self.shift_gamma), int(self.split_entries),
-                        int(self.split_mean_factor), FOOTPRINTS[self.footprint])
+                        int(self.split_mean_factor), FOOTPRINTS[self.footprint], int(self.sub_bins))
 
 
 def paper_params(**kw):

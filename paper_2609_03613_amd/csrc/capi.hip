@@ -94,6 +94,8 @@ tgs_status check_params(const tgs_params* p) {
         return fail(TGS_ERR_INVALID_ARG, "shift_gamma must be in [0, 1)");
     if (p->footprint != TGS_FOOTPRINT_OPACITY_AWARE && p->footprint != TGS_FOOTPRINT_THREE_SIGMA)
         return fail(TGS_ERR_INVALID_ARG, "unknown footprint %d", p->footprint);
+    if (p->sub_bins != 0 && p->sub_bins != 1 && p->sub_bins != 2 && p->sub_bins != 4 && p->sub_bins != 8)
+        return fail(TGS_ERR_INVALID_ARG, "sub_bins %d (0, 1, 2, 4 or 8)", p->sub_bins);
     return TGS_OK;
 }
 
@@ -149,7 +151,7 @@ int end_bit_for(int64_t T) {
 // the binning key is the sort key; the near-depth key is not).
 int sub_bins_for(const tgs_params* p, int order) {
     const bool ok = order == TGS_ORDER_BINNED && p->repair == TGS_REPAIR_ALL && !p->packed && !p->near_shift;
-    return ok ? kSubBins : 1;
+    return ok ? (p->sub_bins > 0 ? p->sub_bins : kSubBins) : 1;
 }
 
 Layout layout(int64_t n, int64_t capacity, int64_t T, int K, int order, bool var, bool rules, int sub) {
@@ -256,6 +258,7 @@ void tgs_default_params(tgs_params* p) {
     p->split_entries = 2048;
     p->split_mean_factor = 2;
     p->footprint = TGS_FOOTPRINT_OPACITY_AWARE;
+    p->sub_bins = 0;
 }
 
 const char* tgs_last_error(void) { return g_err.c_str(); }

@@ -33,6 +33,7 @@ def test_default_params():
     assert (p.p_lo, p.p_hi) == (1.0, 99.0) and abs(p.pad - 0.05) < 1e-7
     assert p.raster == L.RASTER_WAVE and p.packed == 0
     assert p.footprint == L.FOOTPRINT_OPACITY_AWARE and (p.split_entries, p.split_mean_factor) == (2048, 2)
+    assert p.sub_bins == 0
     # the binding's defaults are the library's
     q = tg.Params().c()
     for name, _ in L.Params._fields_:
@@ -205,7 +206,9 @@ def test_repair_mode_argument_errors():
              (tg.Params(near_shift=True, shift_alpha=float("inf")), L.TGS_ERR_INVALID_ARG, "shift_alpha"),
              (tg.Params(split_entries=1000), L.TGS_ERR_INVALID_ARG, "split_entries"),
              (tg.Params(split_entries=128), L.TGS_ERR_INVALID_ARG, "split_entries"),
-             (tg.Params(split_mean_factor=-1), L.TGS_ERR_INVALID_ARG, "split_mean_factor")]
+             (tg.Params(split_mean_factor=-1), L.TGS_ERR_INVALID_ARG, "split_mean_factor"),
+             (tg.Params(sub_bins=3), L.TGS_ERR_INVALID_ARG, "sub_bins"),
+             (tg.Params(sub_bins=16), L.TGS_ERR_INVALID_ARG, "sub_bins")]
     for bad, code, word in cases:
         st, msg = status_of(lib.tgs_project, ctypes.byref(g), ctypes.byref(cam()), ctypes.byref(bad.c()),
                             ctypes.byref(out), None)

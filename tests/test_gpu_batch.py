@@ -127,8 +127,9 @@ def test_autotuner_picks_valid_schedule_and_caches(tmp_path):
     assert not rec["cached"]
     assert (p.tile_size, p.num_bins) in cands
     assert rec["ms"] == min(v["ms"] for v in rec["table"].values())
+    assert p.sub_bins in autotune.SUB_BINS and len(rec["table"]) == len(cands) * len(autotune.SUB_BINS)
     p2, rec2 = autotune.tune(g, cam, cache_path=path, candidates=cands, reps=2)
-    assert rec2["cached"] and (p2.tile_size, p2.num_bins) == (p.tile_size, p.num_bins)
+    assert rec2["cached"] and (p2.tile_size, p2.num_bins, p2.sub_bins) == (p.tile_size, p.num_bins, p.sub_bins)
     # the tuned schedule renders the same image up to rounding
     a = tg.render(g, cam, p)
     b = tg.render(g, cam)

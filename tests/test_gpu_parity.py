@@ -201,6 +201,38 @@ def test_staged_group_sort(case):
         assert (sub >= size).sum() >= sum(1 for s2 in clusters if s2 >= size)
 
 
+@pytest.mark.parametrize("sub_bins", [1, 2, 4, 8])
+@pytest.mark.parametrize("case", [STAGE_CASES[2], STAGE_CASES[7], STAGE_CASES[8]])
+def test_sub_bin_counts_bit_exact(case, sub_bins):
+    # any number of sub-bins gives the same stream (the sub-bins only split
+    # the work between the group sort and the repair): staged and unstaged
+    # groups, whole segments queued at one sub-bin
+    n, widest, ties, clusters = case
+    W, H = 128, 16
+    splats, info = scenes.random_splats(n, W, H, seed=n + sub_bins, tie_fraction=ties, max_sigma_px=2.0)
+    rng = np.random.default_rng(n + sub_bins)
+    rect = np.zeros((n, 4), np.int64)
+    x0 = rng.integers(0, 8, n)
+    rect[:, 0] = x0
+    rect[:, 2] = np.minimum(x0 + rng.integers(1, widest + 1, n), 8)
+    rect[:, 3] = 1
+    depth = scenes.info_depth(info).copy()
+    at = 0
+    for k, size in enumerate(clusters):
+        depth[at:at + size] = depth[at]
+        rect[at:at + size, 0] = k
+        rect[at:at + size, 2] = k + 1
+        at += size
+    info = scenes.make_info(depth, rect)
+    cam = cam_for(W, H)
+    ref = oracle.schedule(depth, rect, 8, 1, K=64, znear=cam["znear"], zfar=cam["zfar"])
+    M = ref["M"]
+    _, _, _, bb = run_bin(splats, info, cam, "binned", tg.Params(num_bins=64, sub_bins=sub_bins))
+    assert bb.num_entries == M and to_np(bb.counters)[2] == 0
+    assert np.array_equal(to_np(bb.offsets).view(np.uint32), ref["bin_offsets"])
+    assert np.array_equal(to_np(bb.pairs)[:M].view(np.uint64), ref["stream"])
+
+
 @pytest.mark.parametrize("per_tile", [False, True])
 def test_per_entry_atomic_path_bit_exact(per_tile):
     # 8-pixel tiles at 2560x1440 (57,600 tiles) with K = 1024: a group of
