@@ -212,7 +212,10 @@ typedef struct {
                              0, near_shift = 0): the binning first orders each
                              (tile, bin) segment by this many sub-bins of the
                              same log-depth map, and the repair sorts the
-                             sub-segments. 1, 2, 4 or 8; 0 = the default 8.
+                             sub-segments. 1, 2, 4 or 8; 0 = the default 8
+                             (1 where a group's segments times the sub-bins
+                             exceed the group sort's 4096 counters, e.g. 8-
+                             pixel tiles at K = 256, or without groups).
                              The stream is the same for every value: only the
                              split of the work between the binning and the
                              repair changes (fewer sub-bins: fewer, longer
