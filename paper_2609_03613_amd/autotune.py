@@ -4,7 +4,7 @@ For one camera and scene size it times the whole per-view frame as the
 batched renderer runs it (projection, binning with exact repair, the
 persistent multi-view raster on this one view) for every candidate (tile
 size in {8, 16, 32}) x (bins K in {16, 32, 64, 128, 256}) x (sub-bins per bin in
-{8, 4}) with HIP events on the launch stream and keeps the fastest. The
+{8, 4, 2}) with HIP events on the launch stream and keeps the fastest. The
 choice never changes the image beyond rounding (exact repair keeps the
 global order, whatever the bins and sub-bins; the tile size only moves the
 tile-relative origin of the staged means), so only time is compared.
@@ -27,7 +27,7 @@ from .api import BatchRenderer, Params, project
 TILE_SIZES = (8, 16, 32)
 BIN_COUNTS = (16, 32, 64, 128, 256)
 CANDIDATES = tuple((ts, k) for ts in TILE_SIZES for k in BIN_COUNTS)
-SUB_BINS = (8, 4)  # sub-bins per bin of the exact repair: more split the long segments finer
+SUB_BINS = (8, 4, 2)  # sub-bins per bin of the exact repair: more split the long segments finer
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "tilegs", "autotune.json")
 
 
