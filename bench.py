@@ -90,7 +90,7 @@ def parse():
                          "256 MiB device copy (for profiler counter runs); train: only the training "
                          "step (forward + backward) on the 500k-Gaussian 1297x840 scene; batch-replay: "
                          "only replays of the captured 16-view frame (32-pixel tiles, K = 128, "
-                         "4 sub-bins, binnings on one stream), for a kernel trace of the replay alone")
+                         "2 sub-bins, binnings on one stream), for a kernel trace of the replay alone")
     ap.add_argument("--no-train", action="store_true", help="skip the training-step measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched multi-camera measurement")
     ap.add_argument("--no-repair", action="store_true", help="skip the repair-variant ablation")
@@ -212,7 +212,7 @@ def train_step(args):
 
 def batch_replay(args):
     """The 16-view batched frame with fixed per-view parameters (32-pixel
-    tiles, K = 128, 4 sub-bins: the autotuner's usual choice on this
+    tiles, K = 128, 2 sub-bins: the autotuner's usual choice on this
     workload) and the binnings on one stream, captured once and replayed:
     warmup replays, then `steps` timed ones. No autotuning, eager or
     per-view legs, so that a kernel trace holds the replays alone."""
@@ -222,7 +222,7 @@ def batch_replay(args):
     stream = torch.cuda.current_stream()
     g, cams = scenes.batched_scene(seed=0)
     gd = tg.to_device(g, dev)
-    br = tg.BatchRenderer(cams, [tg.Params(tile_size=32, num_bins=128, sub_bins=4) for _ in cams], device=dev,
+    br = tg.BatchRenderer(cams, [tg.Params(tile_size=32, num_bins=128, sub_bins=2) for _ in cams], device=dev,
                           lanes=1)
     br.capture(gd)
     for _ in range(args.warmup):
@@ -236,7 +236,7 @@ def batch_replay(args):
     torch.cuda.synchronize()
     assert not br.overflowed()
     return {"workload": "batched: 3M Gaussians (SH0) on 16 ring cameras, 640x360 .. 2560x1440; "
-                        "32-pixel tiles, K = 128, 4 sub-bins, binnings on one stream",
+                        "32-pixel tiles, K = 128, 2 sub-bins, binnings on one stream",
             "views": len(cams), "entries": int(sum(br.entries)), "entries_per_view": [int(e) for e in br.entries],
             "replays": args.steps, "ms_per_replay": e0.elapsed_time(e1) / args.steps}
 
