@@ -244,7 +244,7 @@ def batch_replay(args):
 def batched(args):
     """16 cameras of uneven resolution on a ring around 3M Gaussians (SH0):
     per-view tile size and bins from the autotuner, the whole multi-view
-    frame (projection in launches of four views, 16 binnings on four
+    frame (projection in launches of eight views, 16 binnings on four
     streams, one persistent raster launch) captured in a HIP graph and
     replayed. Beside it: the same frame launched eagerly, eagerly with the
     binnings on one stream, and the per-view default path (16 px tiles,

@@ -287,7 +287,7 @@ TGS_API tgs_status tgs_project(const tgs_gaussians* gaussians, const tgs_camera*
    Gaussians: cameras, params and out are host arrays of num_views
    elements, out[v] receives exactly what tgs_project(gaussians, &cameras[v],
    &params[v], &out[v]) writes (bitwise). Each launch reads every
-   Gaussian's parameters once and writes up to 4 views. */
+   Gaussian's parameters once and writes up to 8 views. */
 TGS_API tgs_status tgs_project_views(const tgs_gaussians* gaussians, int32_t num_views, const tgs_camera* cameras,
                              const tgs_params* params, tgs_projected* out, void* stream);
 

@@ -112,7 +112,7 @@ def project(g, cam, params=None, out=None):
 def project_views(g, cams, params, outs):
     """tgs_project_views: the projections of g through every camera of cams
     (with params[v]) into outs[v] = (splats, info), each launch reading the
-    Gaussians once for up to four cameras."""
+    Gaussians once for up to eight cameras."""
     nv = len(cams)
     n = int(g["means"].shape[0])
     gs = L.Gaussians(_ptr(g["means"]).value, _ptr(g["log_scales"]).value, _ptr(g["quats"]).value,
@@ -352,7 +352,7 @@ def render_differentiable(renderer, g, order="binned", bg=(0.0, 0.0, 0.0)):
 
 class BatchRenderer:
     """Several cameras per frame: tgs_project_views for all views (the
-    Gaussians read once per four views), per-view tgs_bin (BINNED, each view
+    Gaussians read once per eight views), per-view tgs_bin (BINNED, each view
     with its own params: tile size, bins; up to ``lanes`` views at once on
     side streams), then one tgs_rasterize_batch persistent launch for all
     views. ``capture`` records

@@ -287,7 +287,7 @@ Cam make_cam(const tgs_camera& c, int tile, int footprint);
 
 // Cameras of one projection launch: each lane reads its Gaussian once and
 // writes its splat and info lines for every camera.
-constexpr int kProjViews = 4;
+constexpr int kProjViews = 8;
 struct ProjViews {
     Cam cam[kProjViews];
     float4* splats[kProjViews];

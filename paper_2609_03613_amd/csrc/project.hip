@@ -103,10 +103,9 @@ __device__ __forceinline__ void stage_sh_block(float4* sh_lds, const float* __re
 // info lines of up to kProjViews cameras (views.nv of them).
 //
 // SH3: each lane loads its Gaussian's 48 coefficients itself (twelve
-// 16-byte loads, no LDS). Without the 24 KB LDS block, which limited the
-// staged form to 3 wavefronts per SIMD, the registers allow 4, and the
-// extra wavefronts hide more of the load latency (68.8 -> 63.1 us for 1M
-// Gaussians). Other degrees (3, 12 or 27 floats per Gaussian, not 16-byte
+// 16-byte loads, no LDS), all issued before the first wait, which keeps the
+// kernel at the copy rate of its bytes without the 24 KB LDS block of the
+// staged form. Other degrees (3, 12 or 27 floats per Gaussian, not 16-byte
 // multiples) use the staged form.
 template <bool DIRECT>
 __global__ void __launch_bounds__(kProjThreads) project_kernel(const float* __restrict__ means,
